@@ -1,0 +1,60 @@
+"""FP64 CPU oracle for the spectral Poisson solve -- TEST INFRASTRUCTURE ONLY.
+
+This package is the plain, slow reference that the GPU library is checked
+against.  It follows the paper (SailFFish, Section 2): forward transform,
+pointwise spectral multiply, optional spectral derivative, backward
+transform, for periodic, Dirichlet and Neumann boundaries (Table 1) and for
+free space by domain doubling (Section 2.5).  Every transform is either its
+textbook definition written out (the sine / cosine transforms) or a library
+DFT (numpy.fft), in float64.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  The GPU library never imports, links or
+calls it, and it shares no code with the GPU library.
+
+Parity status of each function is recorded next to its pins in tests/.
+"""
+import numpy as np
+
+from . import bounded, grid, transforms, unbounded
+
+__all__ = ["bounded", "grid", "transforms", "unbounded", "solve"]
+
+
+def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
+          faces=None, sigma_cells=2.0):
+    """One solve described like the library's plan descriptor.
+
+    bc: "periodic" | "dirichlet" | "neumann" | "unbounded"
+    grid_type: "regular" | "staggered"
+    nc, lo, hi: per-axis cell count and domain bounds (length = ndim)
+    f: source on the unknown points (scalar), or (3, ...) for a 3D vector
+    operator: "ps" | "fd2" for bounded BCs (ignored for unbounded: G2)
+    diff: "none" | "grad" | "curl"
+    faces: {(axis, side): g} boundary values (FD2 Dirichlet / Neumann)
+    Returns (psi, derivs) on the output points.
+    """
+    nd = len(nc)
+    hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
+    lengths = [float(hi[a]) - float(lo[a]) for a in range(nd)]
+    f = np.asarray(f, dtype=np.float64)
+    if bc == "unbounded":
+        sigma = float(sigma_cells) * max(hs)
+        return unbounded.solve_unbounded(f, hs, sigma, diff)
+    vector = f.ndim == nd + 1
+    comps = [f[c] for c in range(f.shape[0])] if vector else [f]
+    psi = [bounded.solve_bounded(c, bc, grid_type, operator, lengths, hs, faces if not vector else (faces[i] if faces else None))
+           for i, c in enumerate(comps)]
+    derivs = []
+    if diff == "grad":
+        if bc != "periodic" or vector:
+            raise NotImplementedError("bounded gradient: periodic scalar only")
+        derivs = bounded.periodic_gradient(psi[0], lengths)
+    elif diff == "curl":
+        if bc != "periodic" or not vector or nd != 3:
+            raise NotImplementedError("bounded curl: periodic 3D vector only")
+        g = [bounded.periodic_gradient(p, lengths) for p in psi]
+        derivs = [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+    elif diff != "none":
+        raise ValueError(diff)
+    return (np.stack(psi) if vector else psi[0]), derivs

@@ -1,0 +1,192 @@
+"""Bounded solves (periodic, Dirichlet, Neumann) of the oracle.
+
+The solve follows the four steps of Section 2.2: forward transform, pointwise
+multiply by the spectral multiplier, (optional spectral operation), backward
+transform.  Table 1 (tab:Bounded) names the transform pair and the 1D
+eigenvalue for every BC / grid / operator combination; eq. (pois_spec) sums
+the per-axis eigenvalues in 2D and 3D.  The zero wavenumber, where the
+eigenvalue vanishes (periodic and Neumann), is set to zero (the remark after
+eq. (spect_sol)).
+
+Inhomogeneous Dirichlet / Neumann values (Section 2.4.2 and Section 4.2) are
+only available with the FD2 eigenvalues.  The paper names the technique
+("simple weighting of the boundary source terms") without writing it out; the
+reading used here moves each boundary value into the right-hand side of the
+layer of unknowns next to the face, through the ghost-point rule of each
+grid (g is the boundary value for Dirichlet and d(psi)/dx_a, not the outward
+normal derivative, for Neumann, as in eq. (tfih1Dgrad)):
+
+  Dirichlet REGULAR    psi at the boundary node is g:   f_first -= g / H^2
+  Dirichlet STAGGERED  ghost = 2 g - psi_0:             f_first -= 2 g / H^2
+  Neumann  REGULAR     ghost = psi_1 -+ 2 H g:          f_first += 2 g / H,
+                                                        f_last  -= 2 g / H
+  Neumann  STAGGERED   face difference (psi_0 - ghost) / H = g:
+                                                        f_first += g / H,
+                                                        f_last  -= g / H
+
+In several dimensions every face adds to its own adjacent layer, so edges and
+corners collect the terms of every face that touches them.
+"""
+import numpy as np
+
+from . import grid as _grid
+from . import transforms as _tr
+
+# Table 1: forward transform, backward transform, and the factor c(n) with
+# backward(forward(x)) = c(n) x for the unnormalised definitions.
+TRANSFORM_PAIRS = {
+    ("dirichlet", "regular"): ("dst1", "dst1", lambda n: 2.0 * (n + 1)),
+    ("dirichlet", "staggered"): ("dst2", "dst3", lambda n: 2.0 * n),
+    ("neumann", "regular"): ("dct1", "dct1", lambda n: 2.0 * (n - 1)),
+    # Table 1 prints "DST-III" as the backward transform here; the inverse of
+    # DCT-II is DCT-III, which is what is used.
+    ("neumann", "staggered"): ("dct2", "dct3", lambda n: 2.0 * n),
+}
+
+
+def eigenvalues(bc, grid, operator, n, length, h):
+    """1D eigenvalues of Table 1 for k = 0 .. n-1 (N of the table is n).
+
+    operator is "ps" (pseudo-spectral) or "fd2" (second-order finite
+    difference).  length is L = X_u - X_l, h the cell size H.
+    """
+    k = np.arange(n, dtype=np.float64)
+    L = float(length)
+    if operator == "ps":
+        if bc == "dirichlet":
+            return -((np.pi * (k + 1.0) / L) ** 2)
+        if bc == "neumann":
+            return -((np.pi * k / L) ** 2)
+        if bc == "periodic":
+            kk = np.where(k < n / 2.0, k, n - k)
+            return -((2.0 * np.pi * kk / L) ** 2)
+    elif operator == "fd2":
+        s = -4.0 / (h * h)
+        if bc == "dirichlet" and grid == "regular":
+            return s * np.sin(np.pi * (k + 1.0) / (2.0 * (n + 1))) ** 2
+        if bc == "dirichlet" and grid == "staggered":
+            return s * np.sin(np.pi * (k + 1.0) / (2.0 * n)) ** 2
+        if bc == "neumann" and grid == "regular":
+            return s * np.sin(np.pi * k / (2.0 * (n - 1))) ** 2
+        if bc == "neumann" and grid == "staggered":
+            return s * np.sin(np.pi * k / (2.0 * n)) ** 2
+        if bc == "periodic":
+            return s * np.sin(np.pi * k / n) ** 2
+    raise ValueError((bc, grid, operator))
+
+
+def multiplier(bc, grid, operator, shape, lengths, hs):
+    """Sum of the per-axis eigenvalues on the spectral grid (eq. pois_spec)."""
+    lam = np.zeros(shape)
+    for a, n in enumerate(shape):
+        la = eigenvalues(bc, grid, operator, n, lengths[a], hs[a])
+        view = [1] * len(shape)
+        view[a] = n
+        lam = lam + la.reshape(view)
+    return lam
+
+
+def _divide(fhat, lam):
+    """psi_hat = f_hat / lambda, with the zero eigenvalue mapped to zero."""
+    out = np.zeros_like(fhat)
+    nz = lam != 0.0
+    out[nz] = fhat[nz] / lam[nz]
+    return out
+
+
+def apply_boundary_values(f, bc, grid, hs, faces):
+    """Move boundary values into the right-hand side (FD2 only).
+
+    f has the unknown shape.  faces maps (axis, side) with side 0 = lower,
+    1 = upper to an array with the output shape of the other axes.  For
+    REGULAR Dirichlet only the entries at interior nodes of the other axes
+    enter the right-hand side.
+    """
+    f = np.array(f, dtype=np.float64, copy=True)
+    nd = f.ndim
+    for (axis, side), g in faces.items():
+        g = np.asarray(g, dtype=np.float64)
+        if bc == "dirichlet" and grid == "regular":
+            g = g[tuple(slice(1, -1) for _ in range(nd - 1))]
+        h = hs[axis]
+        if bc == "dirichlet" and grid == "regular":
+            term = -g / h**2
+        elif bc == "dirichlet" and grid == "staggered":
+            term = -2.0 * g / h**2
+        elif bc == "neumann" and grid == "regular":
+            term = (2.0 * g / h) if side == 0 else (-2.0 * g / h)
+        elif bc == "neumann" and grid == "staggered":
+            term = (g / h) if side == 0 else (-g / h)
+        else:
+            raise ValueError("boundary values need a Dirichlet or Neumann BC")
+        idx = [slice(None)] * nd
+        idx[axis] = 0 if side == 0 else f.shape[axis] - 1
+        f[tuple(idx)] += term
+    return f
+
+
+def dirichlet_regular_output(psi_inner, faces):
+    """Embed interior nodes into the node grid and write the boundary nodes.
+
+    Boundary nodes take the value of their face; a node on several faces takes
+    the value of the face with the highest axis index.  Missing faces are 0.
+    """
+    nd = psi_inner.ndim
+    out = np.zeros(tuple(n + 2 for n in psi_inner.shape))
+    out[tuple(slice(1, -1) for _ in range(nd))] = psi_inner
+    for axis in range(nd):
+        for side in (0, 1):
+            g = faces.get((axis, side)) if faces else None
+            idx = [slice(None)] * nd
+            idx[axis] = 0 if side == 0 else out.shape[axis] - 1
+            out[tuple(idx)] = 0.0 if g is None else np.asarray(g, dtype=np.float64)
+    return out
+
+
+def solve_bounded(f, bc, grid, operator, lengths, hs, faces=None):
+    """Solve lap(psi) = f on a bounded grid.
+
+    f has the unknown shape (grid.unknowns per axis).  Returns psi on the
+    output points (grid.output_points per axis).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    if faces:
+        if operator != "fd2":
+            raise ValueError("inhomogeneous boundary values need the FD2 operator")
+        f = apply_boundary_values(f, bc, grid, hs, faces)
+    lam = multiplier(bc, grid, operator, f.shape, lengths, hs)
+    if bc == "periodic":
+        psi = np.fft.ifftn(_divide(np.fft.fftn(f), lam)).real
+        return psi
+    fwd, bwd, norm = TRANSFORM_PAIRS[(bc, grid)]
+    fhat = f
+    for a in range(f.ndim):
+        fhat = _tr.apply(fwd, fhat, a)
+    psihat = _divide(fhat, lam)
+    psi = psihat
+    for a in reversed(range(f.ndim)):
+        psi = _tr.apply(bwd, psi, a) / norm(f.shape[a])
+    if bc == "dirichlet" and grid == "regular":
+        psi = dirichlet_regular_output(psi, faces or {})
+    return psi
+
+
+def periodic_gradient(psi, lengths):
+    """Spectral gradient of a periodic field (Section 2.3.3, eq. ft_sd).
+
+    Multiplies the DFT by i k_a, k_a = 2 pi m / L_a with m taken in
+    (-n/2, n/2); the Nyquist mode m = n/2 has no real derivative and is set to
+    zero (the paper does not say what it does with it).
+    """
+    psi = np.asarray(psi, dtype=np.float64)
+    ph = np.fft.fftn(psi)
+    out = []
+    for a, n in enumerate(psi.shape):
+        m = np.fft.fftfreq(n, d=1.0 / n)
+        if n % 2 == 0:
+            m[n // 2] = 0.0
+        k = 2.0 * np.pi * m / float(lengths[a])
+        view = [1] * psi.ndim
+        view[a] = n
+        out.append(np.fft.ifftn(1j * k.reshape(view) * ph).real)
+    return out

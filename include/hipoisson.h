@@ -1,0 +1,177 @@
+/*
+ * hipoisson -- spectral Poisson solver for AMD Instinct MI355X (gfx950).
+ *
+ * Solves lap(psi) = f on 1D/2D/3D rectangular grids by the four steps of the
+ * SailFFish method (Section 2.2): forward transform, pointwise multiply by a
+ * spectral multiplier, optional spectral derivative, backward transform.
+ *
+ *   periodic    DFT, PS or FD2 eigenvalues             (Table 1, last row)
+ *   Dirichlet   DST-I / DST-II+III, PS or FD2          (Table 1)
+ *   Neumann     DCT-I / DCT-II+III, PS or FD2          (Table 1; the printed
+ *               "DST-III" backward transform for the staggered grid is read
+ *               as DCT-III, the inverse of DCT-II)
+ *   unbounded   Hockney-Eastwood domain doubling with a precomputed spectral
+ *               Green's function (Section 2.5), R2C / C2R for real data
+ *
+ * Grids (Section 2.3.2, eq. gridpos): REGULAR solves on cell boundaries,
+ * STAGGERED on cell centres.  Unknown counts per axis for N_c cells:
+ *   Dirichlet REGULAR N_c - 1 (output N_c + 1 nodes incl. boundary nodes),
+ *   Neumann REGULAR N_c + 1, unbounded REGULAR N_c + 1, all others N_c.
+ *
+ * Memory layout: every field is a C-contiguous array [n_0][n_1][n_2] (last
+ * axis contiguous) of float (HP_F32) or double (HP_F64); a 3-component field
+ * is three separate arrays, one per component.
+ *
+ * Ownership: the plan owns its workspaces and tables.  The caller owns every
+ * input, boundary and output buffer.  Device pointers passed with
+ * on_device = 1 are bound, not copied: they are read or written by the solve
+ * when it runs on the plan's stream and must stay valid until it completes.
+ * Host pointers (on_device = 0) are copied with stream-ordered copies.
+ *
+ * Errors: every call returns hp_status; no C++ exception crosses this
+ * interface.  hp_last_error() gives a message for the last failure of a plan.
+ * A plan is not re-entrant: use one plan per stream.  Descriptor validation
+ * happens before any GPU call, so invalid descriptors are reported on
+ * machines without a GPU.
+ */
+#ifndef HIPOISSON_H
+#define HIPOISSON_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define HP_API __attribute__((visibility("default")))
+#else
+#define HP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp_plan_s* hp_plan; /* opaque, library-owned */
+typedef void* hp_stream;           /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  HP_OK = 0,
+  HP_E_ARG = -1,         /* invalid argument or descriptor */
+  HP_E_UNSUPPORTED = -2, /* valid, but not provided by this library */
+  HP_E_NOMEM = -3,       /* device or host allocation failed */
+  HP_E_DEVICE = -4,      /* a HIP runtime call failed */
+  HP_E_STATE = -5        /* call out of order (e.g. output before a solve) */
+} hp_status;
+
+typedef enum { HP_PERIODIC = 0, HP_DIRICHLET = 1, HP_NEUMANN = 2, HP_UNBOUNDED = 3 } hp_bc;
+typedef enum { HP_REGULAR = 0, HP_STAGGERED = 1 } hp_grid;
+/* Spectral multiplier: PS / FD2 eigenvalues (Table 1) for bounded BCs, the
+ * Gaussian-regularised 3D kernel G2 (Section 2.5.2) for unbounded ones. */
+typedef enum { HP_OP_PS = 0, HP_OP_FD2 = 1, HP_G_GAUSS2 = 2 } hp_kernel;
+/* Spectral derivative applied after the convolution (Section 2.3.3):
+ * GRAD of a scalar (ndim extra outputs), CURL of a 3D vector (3 outputs). */
+typedef enum { HP_D_NONE = 0, HP_D_GRAD = 1, HP_D_CURL = 2 } hp_diff;
+typedef enum { HP_F32 = 0, HP_F64 = 1 } hp_prec;
+
+typedef struct {
+  int ndim;             /* 1, 2 or 3 */
+  int ncomp;            /* 1 (scalar) or 3 (3D vector, component-wise) */
+  int64_t nc[3];        /* cells per axis N_c (entries >= ndim ignored) */
+  double lo[3], hi[3];  /* domain bounds X_l < X_u per axis */
+  int bc;               /* hp_bc, the same on every face */
+  int grid;             /* hp_grid */
+  int kernel;           /* hp_kernel */
+  int diff;             /* hp_diff */
+  int prec;             /* hp_prec: data and FFT precision; tables are FP64-built */
+  int inhomogeneous;    /* 1: boundary values from hp_set_boundary (FD2 only) */
+  double reg_sigma_cells; /* G2 width sigma in units of max_a H_a; 0 -> 2.0 */
+} hp_desc;
+
+/* Query keys for hp_query. */
+enum {
+  HP_Q_MODEL_BYTES = 1,     /* algorithmic HBM bytes of one hp_solve */
+  HP_Q_WORKSPACE_BYTES = 2, /* device workspace held by the plan */
+  HP_Q_NUM_PASSES = 3,      /* kernel launches of one hp_solve */
+  HP_Q_NUM_OUTPUTS = 4,     /* psi components + derivative components */
+  HP_Q_NUM_DERIVS = 5       /* derivative components (gradient or curl) */
+};
+
+/* Create a plan for one problem (the initialisation of Section 3.2.1): grid
+ * geometry, eigenvalue tables or the Green's spectrum (computed in FP64 on
+ * the GPU for unbounded problems), twiddle tables, workspaces.  Returns
+ * HP_E_ARG / HP_E_UNSUPPORTED for descriptors it cannot serve.  Blocking. */
+HP_API hp_status hp_plan_create(const hp_desc* desc, hp_stream stream, hp_plan* out);
+
+/* A plan over `count` independent problems (descs[0..count-1]); they must
+ * share bc, grid, kernel, diff, prec and ndim and may differ in size.  One
+ * hp_solve launches a single persistent kernel that runs every pass of every
+ * problem.  Supported for bounded, non-periodic, homogeneous problems. */
+HP_API hp_status hp_plan_create_batched(const hp_desc* descs, int count, hp_stream stream, hp_plan* out);
+
+/* Unknown (input) and output point counts per axis of problem `problem`;
+ * shape[a] = 1 for a >= ndim. */
+HP_API hp_status hp_input_shape(hp_plan plan, int problem, int64_t shape[3]);
+HP_API hp_status hp_output_shape(hp_plan plan, int problem, int64_t shape[3]);
+
+/* Source f of component `comp` (Section 3.2.2, Set_Input): an array with the
+ * input shape.  on_device = 1 binds a device pointer; 0 copies from host. */
+HP_API hp_status hp_set_input(hp_plan plan, int problem, int comp, const void* f, int on_device);
+
+/* Boundary values of face (axis, side) (side 0 = lower, 1 = upper) for
+ * inhomogeneous FD2 Dirichlet / Neumann plans (Section 2.4.2): an array with
+ * the output shape of the other axes (ascending axis order).  Dirichlet: psi
+ * on the face; Neumann: d(psi)/dx_axis on the face.  NULL = homogeneous. */
+HP_API hp_status hp_set_boundary(hp_plan plan, int problem, int axis, int side, int comp,
+                          const void* g, int on_device);
+
+/* Bind caller-owned device buffers that the solve writes directly: psi of
+ * component `comp` (output shape), and derivative component `comp`
+ * (gradient d/dx_comp or curl component comp, output shape).  Without a
+ * binding the plan writes into buffers it owns. */
+HP_API hp_status hp_bind_output(hp_plan plan, int problem, int comp, void* psi);
+HP_API hp_status hp_bind_gradient(hp_plan plan, int problem, int comp, void* out);
+
+/* Run the solve (Section 3.2.2 steps 2-4) on the plan's stream, without host
+ * synchronisation.  Returns HP_E_STATE if an input is missing. */
+HP_API hp_status hp_solve(hp_plan plan);
+
+/* Transpose of the solve map f -> (psi, derivatives), for back-propagation.
+ * Reads the upstream gradients from the buffers bound with hp_bind_output /
+ * hp_bind_gradient (a NULL binding is a zero gradient) and writes the
+ * gradient with respect to f into the buffers bound with hp_set_input
+ * (on_device = 1 required).  Unbounded plans: the Green's operator is
+ * symmetric, the curl symmetric and the gradient's transpose is minus the
+ * divergence.  Other plans: HP_E_UNSUPPORTED. */
+HP_API hp_status hp_solve_adjoint(hp_plan plan);
+
+/* Copy psi / a derivative component to `dst` (Get_Output).  Stream-ordered;
+ * a device-to-host copy synchronises the stream.  HP_E_STATE before the
+ * first solve. */
+HP_API hp_status hp_get_output(hp_plan plan, int problem, int comp, void* dst, int on_device);
+HP_API hp_status hp_get_gradient(hp_plan plan, int problem, int comp, void* dst, int on_device);
+
+/* Per-pass instrumentation for benchmarks.  While enabled, hp_solve records a
+ * HIP event pair around every kernel it launches on the plan's stream.
+ * hp_pass_stats synchronises the stream and returns, for each of the `*npass`
+ * passes of a solve (at most `max`), the mean elapsed milliseconds over the
+ * solves recorded since the last call (ms), the algorithmic HBM bytes of the
+ * pass (bytes: stored input read once plus stored output written once, plus
+ * the Green's octant) and a static name (names); any output may be NULL. */
+HP_API hp_status hp_set_timing(hp_plan plan, int enable);
+HP_API hp_status hp_pass_stats(hp_plan plan, int max, int* npass, double* ms, double* bytes,
+                               const char** names);
+
+/* Numeric plan properties (HP_Q_* keys). */
+HP_API hp_status hp_query(hp_plan plan, int what, double* value);
+
+/* Release the plan and everything it owns (synchronises its stream). */
+HP_API hp_status hp_plan_destroy(hp_plan plan);
+
+/* Static text for a status code; message of the last failure on `plan`
+ * (or of the last failed plan creation when plan is NULL). */
+HP_API const char* hp_status_string(hp_status status);
+HP_API const char* hp_last_error(hp_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPOISSON_H */

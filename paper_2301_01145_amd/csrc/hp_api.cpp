@@ -1,0 +1,1373 @@
+// C-ABI of the spectral Poisson solver: descriptor validation, plans, passes.
+//
+// A plan follows the initialisation steps of Section 3.2.1 (grid setup, data
+// setup, Green's function / eigenvalues, derivative operators) and a solve the
+// execution steps of Section 3.2.2 (set input, forward transform, convolution
+// with spectral derivative, backward transform, get output).  Every transform
+// is a sequence of pencil passes (hp_kernels.hip); the multiply and derivative
+// are fused into the pass of the last forward axis.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hp_plan.hpp"
+
+using namespace hp;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+namespace {
+
+const char* kStatusText[] = {"ok", "invalid argument", "unsupported", "out of memory",
+                             "device error", "bad call order"};
+
+hp_status fail(hp_plan p, hp_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+hp_status dev_alloc(hp_plan p, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (p->fail_alloc_at >= 0 && p->alloc_count++ == p->fail_alloc_at)
+    return fail(p, HP_E_NOMEM, "injected allocation failure");
+  if (hipMalloc(out, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(p, HP_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  p->allocs.push_back(*out);
+  p->ws_bytes += bytes;
+  return HP_OK;
+}
+
+#define HP_TRY(expr)                      \
+  do {                                    \
+    hp_status _s = (expr);                \
+    if (_s != HP_OK) return _s;           \
+  } while (0)
+#define HP_HIP(p, expr)                                                          \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess)                                                        \
+      return fail((p), HP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// ------------------------------------------------------------ geometry
+int unknowns(int bc, int grid, int nc) {
+  switch (bc) {
+    case HP_DIRICHLET: return grid == HP_REGULAR ? nc - 1 : nc;
+    case HP_NEUMANN: return grid == HP_REGULAR ? nc + 1 : nc;
+    case HP_UNBOUNDED: return grid == HP_REGULAR ? nc + 1 : nc;
+    default: return nc;
+  }
+}
+
+int outputs(int bc, int grid, int nc) {
+  if (bc == HP_DIRICHLET && grid == HP_REGULAR) return nc + 1;
+  return unknowns(bc, grid, nc);
+}
+
+// Forward / backward transform of Table 1 and the FFT length they need.
+void r2r_ops(int bc, int grid, int n, int* xf, int* xb, int* L, double* c) {
+  if (bc == HP_DIRICHLET && grid == HP_REGULAR) { *xf = X_DST1; *xb = X_DST1; *L = 2 * (n + 1); *c = 2.0 * (n + 1); }
+  else if (bc == HP_DIRICHLET) { *xf = X_DST2; *xb = X_DST3; *L = 2 * n; *c = 2.0 * n; }
+  else if (grid == HP_REGULAR) { *xf = X_DCT1; *xb = X_DCT1; *L = 2 * (n - 1); *c = 2.0 * (n - 1); }
+  else { *xf = X_DCT2; *xb = X_DCT3; *L = 2 * n; *c = 2.0 * n; }
+}
+
+bool factorize(int L, int* radix, int* nstage) {
+  if (L < 1) return false;
+  int s = 0, r = L;
+  while (r > 1) {
+    int f = 0;
+    if (r % 8 == 0) f = 8;
+    else if (r % 4 == 0) f = 4;
+    else if (r % 2 == 0) f = 2;
+    else if (r % 3 == 0) f = 3;
+    else if (r % 5 == 0) f = 5;
+    else return false;
+    if (s >= kMaxStages) return false;
+    radix[s++] = f;
+    r /= f;
+  }
+  *nstage = s;
+  return true;
+}
+
+int maxe(int prec) { return prec == 0 ? 32 : 16; }
+
+// Pick the tile width P (power of two) for a pass; returns 0 if nothing fits.
+// lds(P) gives the LDS bytes, nfft(P) the transforms per FFT call.
+template <class F1, class F2>
+int choose_P(int want, int minP, int Np, int L, int prec, F1 lds, F2 nfft, int* lds_out) {
+  int cap = 1;
+  while (cap < Np) cap <<= 1;
+  int P = want;
+  if (P > cap) P = cap < minP ? minP : cap;
+  const int budgets[2] = {64 * 1024, 160 * 1024};
+  for (int b = 0; b < 2; ++b) {
+    for (int q = P; q >= minP; q >>= 1) {
+      if ((long long)nfft(q) * L <= (long long)maxe(prec) * kThreads && lds(q) <= budgets[b]) {
+        *lds_out = (int)lds(q);
+        return q;
+      }
+    }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------- validation
+hp_status validate(const hp_desc* d) {
+  if (!d) return fail(nullptr, HP_E_ARG, "null descriptor");
+  if (d->ndim < 1 || d->ndim > 3) return fail(nullptr, HP_E_ARG, "ndim must be 1, 2 or 3");
+  if (d->ncomp != 1 && d->ncomp != 3) return fail(nullptr, HP_E_ARG, "ncomp must be 1 or 3");
+  if (d->ncomp == 3 && d->ndim != 3) return fail(nullptr, HP_E_ARG, "vector fields need ndim 3");
+  if (d->bc < 0 || d->bc > 3) return fail(nullptr, HP_E_ARG, "bad bc");
+  if (d->grid < 0 || d->grid > 1) return fail(nullptr, HP_E_ARG, "bad grid");
+  if (d->kernel < 0 || d->kernel > 2) return fail(nullptr, HP_E_ARG, "bad kernel");
+  if (d->diff < 0 || d->diff > 2) return fail(nullptr, HP_E_ARG, "bad diff");
+  if (d->prec < 0 || d->prec > 1) return fail(nullptr, HP_E_ARG, "bad prec");
+  if (d->reg_sigma_cells < 0.0 || !std::isfinite(d->reg_sigma_cells))
+    return fail(nullptr, HP_E_ARG, "bad reg_sigma_cells");
+  for (int a = 0; a < d->ndim; ++a) {
+    if (d->nc[a] < 1 || d->nc[a] > (1 << 20)) return fail(nullptr, HP_E_ARG, "nc out of range");
+    if (!(d->hi[a] > d->lo[a]) || !std::isfinite(d->lo[a]) || !std::isfinite(d->hi[a]))
+      return fail(nullptr, HP_E_ARG, "need lo < hi on every axis");
+    const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);
+    if (n < 1) return fail(nullptr, HP_E_ARG, "too few cells for this BC and grid");
+    if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && n < 2)
+      return fail(nullptr, HP_E_ARG, "too few cells for this BC and grid");
+  }
+  const bool unb = d->bc == HP_UNBOUNDED;
+  if (unb && d->kernel != HP_G_GAUSS2)
+    return fail(nullptr, HP_E_ARG, "unbounded plans take a Green's kernel (HP_G_GAUSS2)");
+  if (!unb && d->kernel == HP_G_GAUSS2)
+    return fail(nullptr, HP_E_ARG, "bounded plans take PS or FD2 eigenvalues");
+  if (d->inhomogeneous) {
+    if (d->bc != HP_DIRICHLET && d->bc != HP_NEUMANN)
+      return fail(nullptr, HP_E_ARG, "boundary values need a Dirichlet or Neumann BC");
+    if (d->kernel != HP_OP_FD2)
+      return fail(nullptr, HP_E_UNSUPPORTED, "inhomogeneous BCs need FD2 eigenvalues");
+  }
+  if (d->diff == HP_D_CURL && (d->ncomp != 3 || d->ndim != 3))
+    return fail(nullptr, HP_E_ARG, "curl needs a 3-component 3D field");
+  if (d->diff == HP_D_GRAD && d->ncomp != 1)
+    return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
+  if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN))
+    return fail(nullptr, HP_E_UNSUPPORTED, "spectral derivatives on Dirichlet/Neumann grids");
+  if (unb && d->ndim != 3)
+    return fail(nullptr, HP_E_UNSUPPORTED, "unbounded solves are 3D (G2 is the 3D kernel)");
+  // transform lengths must be 2^a 3^b 5^c
+  for (int a = 0; a < d->ndim; ++a) {
+    const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);
+    int L = n, xf, xb, rad[kMaxStages], ns;
+    double c;
+    if (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN) r2r_ops(d->bc, d->grid, n, &xf, &xb, &L, &c);
+    if (unb) L = 2 * n;
+    if (!factorize(L, rad, &ns))
+      return fail(nullptr, HP_E_UNSUPPORTED,
+                  "transform length " + std::to_string(L) + " is not a product of 2, 3 and 5");
+    if ((long long)L > (long long)maxe(d->prec) * kThreads / (d->prec == 0 ? 1 : 1))
+      return fail(nullptr, HP_E_UNSUPPORTED, "transform length too large");
+  }
+  return HP_OK;
+}
+
+// ----------------------------------------------------------- tables
+hp_status twiddles(hp_plan p, int L, const void** out) {
+  auto it = p->tw.find(L);
+  if (it != p->tw.end()) { *out = it->second; return HP_OK; }
+  std::vector<double> w(2 * (size_t)L);
+  for (int m = 0; m < L; ++m) {
+    const double ang = 2.0 * M_PI * (double)m / (double)L;
+    w[2 * m] = std::cos(ang);
+    w[2 * m + 1] = -std::sin(ang);
+  }
+  void* d;
+  HP_TRY(dev_alloc(p, (size_t)L * 2 * p->es, &d));
+  if (p->prec == 0) {
+    std::vector<float> f(w.begin(), w.end());
+    HP_HIP(p, hipMemcpy(d, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    HP_HIP(p, hipMemcpy(d, w.data(), w.size() * 8, hipMemcpyHostToDevice));
+  }
+  p->tw[L] = d;
+  *out = d;
+  return HP_OK;
+}
+
+hp_status quarter(hp_plan p, int n, const void** out) {
+  auto it = p->qtw.find(n);
+  if (it != p->qtw.end()) { *out = it->second; return HP_OK; }
+  std::vector<double> w(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    const double ang = M_PI * (double)j / (2.0 * n);
+    w[2 * j] = std::cos(ang);
+    w[2 * j + 1] = -std::sin(ang);
+  }
+  void* d;
+  HP_TRY(dev_alloc(p, (size_t)n * 2 * p->es, &d));
+  if (p->prec == 0) {
+    std::vector<float> f(w.begin(), w.end());
+    HP_HIP(p, hipMemcpy(d, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    HP_HIP(p, hipMemcpy(d, w.data(), w.size() * 8, hipMemcpyHostToDevice));
+  }
+  p->qtw[n] = d;
+  *out = d;
+  return HP_OK;
+}
+
+hp_status upload(hp_plan p, const std::vector<double>& v, bool as_T, void** out) {
+  const size_t es = as_T ? p->es : 8;
+  HP_TRY(dev_alloc(p, v.size() * es, out));
+  if (!as_T || p->prec == 1) {
+    HP_HIP(p, hipMemcpy(*out, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(v.begin(), v.end());
+    HP_HIP(p, hipMemcpy(*out, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  return HP_OK;
+}
+
+// Table 1 eigenvalues, k = 0 .. n-1 (N of the table is n).
+std::vector<double> eigen(int bc, int grid, int op, int n, double L, double h) {
+  std::vector<double> v(n);
+  for (int k = 0; k < n; ++k) {
+    double e = 0.0;
+    if (op == HP_OP_PS) {
+      if (bc == HP_DIRICHLET) e = -std::pow(M_PI * (k + 1.0) / L, 2);
+      else if (bc == HP_NEUMANN) e = -std::pow(M_PI * k / L, 2);
+      else {
+        const double kk = (k < n / 2.0) ? k : n - k;
+        e = -std::pow(2.0 * M_PI * kk / L, 2);
+      }
+    } else {
+      double s;
+      if (bc == HP_DIRICHLET && grid == HP_REGULAR) s = std::sin(M_PI * (k + 1.0) / (2.0 * (n + 1)));
+      else if (bc == HP_DIRICHLET) s = std::sin(M_PI * (k + 1.0) / (2.0 * n));
+      else if (bc == HP_NEUMANN && grid == HP_REGULAR) s = std::sin(M_PI * k / (2.0 * (n - 1)));
+      else if (bc == HP_NEUMANN) s = std::sin(M_PI * k / (2.0 * n));
+      else s = std::sin(M_PI * k / n);
+      e = -4.0 / (h * h) * s * s;
+    }
+    v[k] = e;
+  }
+  return v;
+}
+
+// Angular wavenumbers 2 pi m~ / (N h) over N points (m~ in (-N/2, N/2)),
+// zero at the Nyquist index N/2.
+std::vector<double> wavenumbers(int N, double h, int count) {
+  std::vector<double> k(count);
+  for (int m = 0; m < count; ++m) {
+    double mm = (2 * m < N) ? m : m - N;
+    if (2 * m == N) mm = 0.0;
+    k[m] = 2.0 * M_PI * mm / (N * h);
+  }
+  return k;
+}
+
+// ----------------------------------------------------------- Green's spectrum
+hp_status green_spectrum(hp_plan p, Problem& P) {
+  const int M[3] = {P.M[0], P.M[1], P.M[2]};
+  const int K2 = M[2] / 2 + 1;
+  const double hmax = std::max(P.h[0], std::max(P.h[1], P.h[2]));
+  const double sigma = (P.d.reg_sigma_cells > 0 ? P.d.reg_sigma_cells : 2.0) * hmax;
+  const size_t nreal = (size_t)M[0] * M[1] * M[2];
+  const size_t ncplx = (size_t)M[0] * M[1] * K2;
+  void *g = nullptr, *spec = nullptr;
+  if (hipMalloc(&g, nreal * 8) != hipSuccess) { (void)hipGetLastError(); return fail(p, HP_E_NOMEM, "Green's grid allocation failed"); }
+  if (hipMalloc(&spec, ncplx * 16) != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(g);
+    return fail(p, HP_E_NOMEM, "Green's spectrum allocation failed");
+  }
+  hp_status st = HP_OK;
+  auto run = [&]() -> hp_status {
+    HP_HIP(p, launch_green_eval((double*)g, M, P.h, sigma, P.h[0] * P.h[1] * P.h[2], p->stream));
+    // FP64 forward transform with the general passes (a temporary FP64 view)
+    const int saved_prec = p->prec;
+    const size_t saved_es = p->es;
+    std::map<int, void*> saved_tw;
+    saved_tw.swap(p->tw);
+    p->prec = 1;
+    p->es = 8;
+    auto restore = [&]() {
+      p->prec = saved_prec;
+      p->es = saved_es;
+      p->tw.swap(saved_tw);
+      for (auto& kv : saved_tw) (void)kv;  // FP64 tables stay owned by the plan
+    };
+    for (int axis = 2; axis >= 0; --axis) {
+      PassArgs a{};
+      a.kind = PK_ONEWAY;
+      a.xf = axis == 2 ? X_R2C : X_C2C_F;
+      a.L = M[axis];
+      a.n = M[axis];
+      a.nin = M[axis];
+      a.nout = axis == 2 ? K2 : M[axis];
+      if (!factorize(a.L, a.radix, &a.nstage)) { restore(); return fail(p, HP_E_UNSUPPORTED, "Green's length"); }
+      const void* tw;
+      hp_status s = twiddles(p, a.L, &tw);
+      if (s != HP_OK) { restore(); return s; }
+      a.tw = tw;
+      a.ax_j = a.ax_p = a.ax_o = -1;
+      a.n_in = a.n_out = 1;
+      if (axis == 2) {
+        a.in[0] = g;
+        a.out[0] = spec;
+        a.in_sj = 1; a.in_sp = M[2]; a.in_so = (long long)M[1] * M[2];
+        a.out_sj = 1; a.out_sp = K2; a.out_so = (long long)M[1] * K2;
+        a.Np = M[1]; a.No = M[0];
+        a.in_jfast = a.out_jfast = 1;
+        int lds;
+        a.P = choose_P(16, 2, a.Np, a.L, 1,
+                       [&](int q) { return (long long)(q / 2) * a.L * 16 + (long long)q * a.nin * 8; },
+                       [&](int q) { return q / 2; }, &lds);
+        a.lds_bytes = lds;
+      } else {
+        a.in[0] = spec;
+        a.out[0] = spec;
+        a.in_sj = a.out_sj = axis == 1 ? K2 : (long long)M[1] * K2;
+        a.in_sp = a.out_sp = 1;
+        a.in_so = a.out_so = axis == 1 ? (long long)M[1] * K2 : K2;
+        a.Np = K2; a.No = axis == 1 ? M[0] : M[1];
+        a.in_jfast = a.out_jfast = 0;
+        int lds;
+        a.P = choose_P(8, 1, a.Np, a.L, 1, [&](int q) { return (long long)q * a.L * 16; },
+                       [&](int q) { return q; }, &lds);
+        a.lds_bytes = lds;
+      }
+      if (a.P == 0) { restore(); return fail(p, HP_E_UNSUPPORTED, "Green's transform does not fit"); }
+      hipError_t e = launch_pass(a, 1, 1, p->stream);
+      if (e != hipSuccess) { restore(); return fail(p, HP_E_DEVICE, std::string("Green's pass: ") + hipGetErrorString(e)); }
+    }
+    restore();
+    const size_t oct = (size_t)(M[0] / 2 + 1) * (M[1] / 2 + 1) * K2;
+    HP_TRY(dev_alloc(p, oct * p->es, &P.green));
+    HP_HIP(p, launch_octant((const double*)spec, M, 1.0 / ((double)M[0] * M[1] * M[2]), P.green,
+                            p->prec, p->stream));
+    P.g_s[0] = 1;
+    P.g_s[1] = M[0] / 2 + 1;
+    P.g_s[2] = (long long)(M[0] / 2 + 1) * (M[1] / 2 + 1);
+    HP_HIP(p, hipStreamSynchronize(p->stream));
+    return HP_OK;
+  };
+  st = run();
+  (void)hipStreamSynchronize(p->stream);
+  hipFree(g);
+  hipFree(spec);
+  return st;
+}
+
+// ----------------------------------------------------------- plan setup
+hp_status setup_problem(hp_plan p, Problem& P) {
+  const hp_desc& d = P.d;
+  P.nd = d.ndim;
+  P.ncomp = d.ncomp;
+  P.nder = d.diff == HP_D_GRAD ? d.ndim : (d.diff == HP_D_CURL ? 3 : 0);
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = P.nout[a] = P.M[a] = 1;
+    P.h[a] = P.len[a] = 1.0;
+  }
+  for (int a = 0; a < P.nd; ++a) {
+    P.len[a] = d.hi[a] - d.lo[a];
+    P.h[a] = P.len[a] / (double)d.nc[a];
+    P.n[a] = unknowns(d.bc, d.grid, (int)d.nc[a]);
+    P.nout[a] = outputs(d.bc, d.grid, (int)d.nc[a]);
+    P.M[a] = 2 * P.n[a];
+  }
+  const size_t es = p->es;
+  if (d.bc == HP_DIRICHLET || d.bc == HP_NEUMANN) {
+    P.norm = 1.0;
+    for (int a = 0; a < P.nd; ++a) {
+      int xf, xb, L;
+      double c;
+      r2r_ops(d.bc, d.grid, P.n[a], &xf, &xb, &L, &c);
+      P.norm /= c;
+      HP_TRY(upload(p, eigen(d.bc, d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false, (void**)&P.lam[a]));
+    }
+  } else if (d.bc == HP_PERIODIC) {
+    P.norm = 1.0;
+    for (int a = 0; a < P.nd; ++a) {
+      P.norm /= P.n[a];
+      HP_TRY(upload(p, eigen(d.bc, d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false, (void**)&P.lam[a]));
+      if (P.nder) HP_TRY(upload(p, wavenumbers(P.n[a], P.h[a], P.n[a]), true, &P.kvec[a]));
+    }
+    const int nf = P.ncomp + P.nder;
+    if (P.nd >= 2) {
+      const size_t K = (size_t)P.n[P.nd - 1] / 2 + 1;
+      size_t sz = K;
+      for (int a = 0; a < P.nd - 1; ++a) sz *= P.n[a];
+      for (int f = 0; f < nf; ++f) {
+        void* b;
+        HP_TRY(dev_alloc(p, sz * 2 * es, &b));
+        P.b2.push_back(b);
+      }
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      const int cnt = a == 2 ? P.M[2] / 2 + 1 : P.M[a];
+      HP_TRY(upload(p, wavenumbers(P.M[a], P.h[a], cnt), true, &P.kvec[a]));
+    }
+    HP_TRY(green_spectrum(p, P));
+    const int nf = P.ncomp + P.nder;
+    const size_t K2 = (size_t)P.M[2] / 2 + 1;
+    for (int f = 0; f < nf; ++f) {
+      void* b;
+      HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2 * P.n[1] * 2 * es, &b));
+      P.a1.push_back(b);
+      HP_TRY(dev_alloc(p, K2 * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
+      P.b2.push_back(b);
+    }
+  }
+  return HP_OK;
+}
+
+size_t count_elems(const int* dims, int nd) {
+  size_t s = 1;
+  for (int a = 0; a < nd; ++a) s *= (size_t)dims[a];
+  return s;
+}
+
+// Output buffers: bound pointers or plan-owned ones.
+hp_status ensure_outputs(hp_plan p, Problem& P) {
+  const size_t cnt = count_elems(P.nout, P.nd);
+  for (int c = 0; c < P.ncomp; ++c)
+    if (!P.out[c]) {
+      if (!P.own_out[c]) HP_TRY(dev_alloc(p, cnt * p->es, &P.own_out[c]));
+      P.out[c] = P.own_out[c];
+    }
+  for (int c = 0; c < P.nder; ++c)
+    if (!P.der[c]) {
+      if (!P.own_der[c]) HP_TRY(dev_alloc(p, cnt * p->es, &P.own_der[c]));
+      P.der[c] = P.own_der[c];
+    }
+  return HP_OK;
+}
+
+void strides_of(const int* dims, long long* s) {
+  s[2] = 1;
+  s[1] = dims[2];
+  s[0] = (long long)dims[1] * dims[2];
+}
+
+// Fill the FFT fields of a pass for length L; P from the LDS model.
+hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_per_P_fixed,
+                      int lds_kind) {
+  if (!factorize(a.L, a.radix, &a.nstage)) return fail(p, HP_E_UNSUPPORTED, "length");
+  const void* tw;
+  HP_TRY(twiddles(p, a.L, &tw));
+  a.tw = tw;
+  (void)lds_per_P_fixed;
+  const long long cs = 2 * (long long)p->es, es = p->es;
+  int lds = 0;
+  auto nfft_pair = [](int q) { return q / 2; };
+  auto nfft_one = [](int q) { return q; };
+  switch (lds_kind) {
+    case 0:  // one-way complex
+      a.P = choose_P(want, minP, a.Np, a.L, p->prec, [&](int q) { return (long long)q * a.L * cs; }, nfft_one, &lds);
+      break;
+    case 1:  // one-way real input (pairs)
+      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
+                     [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
+      break;
+    case 2:  // one-way C2R (pairs, complex staging)
+      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
+                     [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * cs; }, nfft_pair, &lds);
+      break;
+    case 3:  // r2r sandwich
+      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
+                     [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
+      break;
+    case 4: {  // c2c sandwich: (nS + 1) complex tiles
+      const int nS = (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) ? a.n_out : a.n_in;
+      a.P = choose_P(want, minP, a.Np, a.L, p->prec,
+                     [&](int q) { return (long long)(nS + 1) * q * a.L * cs; }, nfft_one, &lds);
+    } break;
+    case 5: {  // paired c2c sandwich (1D periodic)
+      const int nS = a.n_in;
+      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
+                     [&](int q) { return (long long)(nS + 1) * (q / 2) * a.L * cs + (long long)q * a.nin * es; },
+                     nfft_pair, &lds);
+    } break;
+  }
+  if (a.P == 0) return fail(p, HP_E_UNSUPPORTED, "pass of length " + std::to_string(a.L) + " does not fit in LDS");
+  a.lds_bytes = lds;
+  return HP_OK;
+}
+
+// --------------------------------------------------------- pass lists
+hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
+  const hp_desc& d = P.d;
+  const int nd = P.nd;
+  int xf[3], xb[3], L[3];
+  double c[3];
+  for (int a = 0; a < nd; ++a) r2r_ops(d.bc, d.grid, P.n[a], &xf[a], &xb[a], &L[a], &c[a]);
+  // work view = the output array (interior for REGULAR Dirichlet)
+  int od[3] = {1, 1, 1}, idims[3] = {1, 1, 1};
+  for (int a = 0; a < nd; ++a) { od[a] = P.nout[a]; idims[a] = P.n[a]; }
+  // logical axis a of an nd-D array maps to storage dim (3 - nd + a)
+  int sod[3] = {1, 1, 1}, sid[3] = {1, 1, 1};
+  for (int a = 0; a < nd; ++a) { sod[3 - nd + a] = od[a]; sid[3 - nd + a] = idims[a]; }
+  long long os3[3], is3[3];
+  strides_of(sod, os3);
+  strides_of(sid, is3);
+  long long ws[3], fs[3];
+  for (int a = 0; a < 3; ++a) ws[a] = fs[a] = 0;
+  for (int a = 0; a < nd; ++a) { ws[a] = os3[3 - nd + a]; fs[a] = is3[3 - nd + a]; }
+  const bool dreg = d.bc == HP_DIRICHLET && d.grid == HP_REGULAR;
+  long long woff = 0;
+  if (dreg)
+    for (int a = 0; a < nd; ++a) woff += ws[a];
+  const size_t es = p->es;
+  auto work = [&](int comp) { return (void*)((char*)P.out[comp] + woff * es); };
+
+  auto base = [&]() {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.No = 1;
+    a.Np = 1;
+    a.n_in = a.n_out = 1;
+    for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? P.n[b] : 0;
+    return a;
+  };
+  auto set_faces = [&](PassArgs& a, int comp) {
+    if (!d.inhomogeneous) return;
+    a.face_off = dreg ? 1 : 0;
+    for (int ax = 0; ax < nd; ++ax) {
+      // strides of the face array over the remaining axes (output layout)
+      int rem[2], nr = 0;
+      for (int b = 0; b < nd; ++b)
+        if (b != ax) rem[nr++] = b;
+      long long s1 = 1;
+      a.face_s[ax][0] = a.face_s[ax][1] = 0;
+      if (nr == 2) { a.face_s[ax][1] = 1; a.face_s[ax][0] = P.nout[rem[1]]; }
+      else if (nr == 1) { a.face_s[ax][0] = 1; }
+      (void)s1;
+      const double h = P.h[ax];
+      for (int side = 0; side < 2; ++side) {
+        a.face[ax][side] = P.face[ax][side][comp];
+        double w;
+        if (d.bc == HP_DIRICHLET) w = (d.grid == HP_REGULAR ? -1.0 : -2.0) / (h * h);
+        else if (d.grid == HP_REGULAR) w = (side == 0 ? 2.0 : -2.0) / h;
+        else w = (side == 0 ? 1.0 : -1.0) / h;
+        a.face_w[ax][side] = w;
+      }
+    }
+  };
+  // one pass per component (faces differ per component)
+  for (int comp = 0; comp < P.ncomp; ++comp) {
+    if (nd == 1) {
+      PassArgs a = base();
+      a.kind = PK_SANDWICH;
+      a.xf = xf[0]; a.xb = xb[0];
+      a.L = L[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
+      a.in[0] = P.in[comp]; a.out[0] = work(comp);
+      a.in_sj = 1; a.out_sj = 1; a.in_jfast = a.out_jfast = 1;
+      a.ax_j = 0;
+      a.mult = M_EIGEN; a.lam[0] = P.lam[0]; a.norm = P.norm;
+      set_faces(a, comp);
+      HP_TRY(finish_pass(p, a, 2, 2, 0, 3));
+      const void* q;
+      HP_TRY(quarter(p, a.n, &q));
+      a.qtw = q;
+      out.push_back({a, 1});
+      continue;
+    }
+    const int last = nd - 1;
+    // P1: forward along the last (contiguous) axis, source + boundary terms
+    {
+      PassArgs a = base();
+      a.kind = PK_ONEWAY;
+      a.xf = xf[last];
+      a.L = L[last]; a.n = P.n[last]; a.nin = a.nout = P.n[last];
+      a.in[0] = P.in[comp]; a.out[0] = work(comp);
+      a.in_sj = fs[last]; a.out_sj = ws[last];
+      a.in_sp = fs[last - 1]; a.out_sp = ws[last - 1];
+      a.Np = P.n[last - 1];
+      a.ax_j = last; a.ax_p = last - 1;
+      if (nd == 3) { a.in_so = fs[0]; a.out_so = ws[0]; a.No = P.n[0]; a.ax_o = 0; }
+      a.in_jfast = a.out_jfast = 1;
+      set_faces(a, comp);
+      HP_TRY(finish_pass(p, a, 16, 2, 0, 1));
+      const void* q;
+      HP_TRY(quarter(p, a.n, &q));
+      a.qtw = q;
+      out.push_back({a, 1});
+    }
+    // P2 (3D): forward along axis 1, in place, tile across the last axis
+    if (nd == 3) {
+      PassArgs a = base();
+      a.kind = PK_ONEWAY;
+      a.xf = xf[1];
+      a.L = L[1]; a.n = P.n[1]; a.nin = a.nout = P.n[1];
+      a.in[0] = work(comp); a.out[0] = work(comp);
+      a.in_sj = a.out_sj = ws[1];
+      a.in_sp = a.out_sp = ws[2];
+      a.in_so = a.out_so = ws[0];
+      a.Np = P.n[2]; a.No = P.n[0];
+      a.ax_j = 1; a.ax_p = 2; a.ax_o = 0;
+      HP_TRY(finish_pass(p, a, 32, 2, 0, 1));
+      const void* q;
+      HP_TRY(quarter(p, a.n, &q));
+      a.qtw = q;
+      out.push_back({a, 1});
+    }
+    // P3: sandwich along axis 0
+    {
+      PassArgs a = base();
+      a.kind = PK_SANDWICH;
+      a.xf = xf[0]; a.xb = xb[0];
+      a.L = L[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
+      a.in[0] = work(comp); a.out[0] = work(comp);
+      a.in_sj = a.out_sj = ws[0];
+      a.in_sp = a.out_sp = ws[last];
+      a.Np = P.n[last];
+      a.ax_j = 0; a.ax_p = last;
+      if (nd == 3) { a.in_so = a.out_so = ws[1]; a.No = P.n[1]; a.ax_o = 1; }
+      a.mult = M_EIGEN;
+      for (int b = 0; b < nd; ++b) a.lam[b] = P.lam[b];
+      a.norm = P.norm;
+      HP_TRY(finish_pass(p, a, 32, 2, 0, 3));
+      const void* q;
+      HP_TRY(quarter(p, a.n, &q));
+      a.qtw = q;
+      out.push_back({a, 1});
+    }
+    // P4 (3D): backward along axis 1
+    if (nd == 3) {
+      PassArgs a = out[out.size() - 2].a;  // same geometry as P2
+      a.xf = xb[1];
+      out.push_back({a, 1});
+    }
+    // P5: backward along the last axis, in place
+    {
+      PassArgs a = base();
+      a.kind = PK_ONEWAY;
+      a.xf = xb[last];
+      a.L = L[last]; a.n = P.n[last]; a.nin = a.nout = P.n[last];
+      a.in[0] = work(comp); a.out[0] = work(comp);
+      a.in_sj = a.out_sj = ws[last];
+      a.in_sp = a.out_sp = ws[last - 1];
+      a.Np = P.n[last - 1];
+      a.ax_j = last; a.ax_p = last - 1;
+      if (nd == 3) { a.in_so = a.out_so = ws[0]; a.No = P.n[0]; a.ax_o = 0; }
+      a.in_jfast = a.out_jfast = 1;
+      HP_TRY(finish_pass(p, a, 16, 2, 0, 1));
+      const void* q;
+      HP_TRY(quarter(p, a.n, &q));
+      a.qtw = q;
+      out.push_back({a, 1});
+    }
+  }
+  return HP_OK;
+}
+
+hp_status passes_periodic(hp_plan p, Problem& P, std::vector<PassRec>& out) {
+  const int nd = P.nd;
+  const bool coupled = P.nder > 0;
+  const int nin = P.ncomp, nfo = P.ncomp + P.nder;
+  auto base = [&]() {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.No = 1;
+    a.Np = 1;
+    a.n_in = a.n_out = 1;
+    return a;
+  };
+  auto outptr = [&](int f) -> void* { return f < P.ncomp ? P.out[f] : P.der[f - P.ncomp]; };
+  auto sandwich_common = [&](PassArgs& a) {
+    a.kind = PK_SANDWICH;
+    a.mult = M_EIGEN;
+    for (int b = 0; b < nd; ++b) { a.lam[b] = P.lam[b]; a.kvec[b] = P.kvec[b]; }
+    a.norm = P.norm;
+    a.diff = P.d.diff == HP_D_GRAD ? D_GRAD : (P.d.diff == HP_D_CURL ? D_CURL : D_NONE);
+    a.n_in = coupled ? nin : 1;
+    a.n_out = coupled ? nfo : 1;
+  };
+  if (nd == 1) {
+    PassArgs a = base();
+    sandwich_common(a);
+    a.xf = X_PAIR_F; a.xb = X_PAIR_B;
+    a.L = P.n[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
+    for (int f = 0; f < nin; ++f) a.in[f] = P.in[f];
+    for (int f = 0; f < nfo; ++f) a.out[f] = outptr(f);
+    a.in_sj = a.out_sj = 1;
+    a.in_jfast = a.out_jfast = 1;
+    a.ax_j = 0;
+    HP_TRY(finish_pass(p, a, 2, 2, 0, 5));
+    out.push_back({a, coupled ? 1 : nin});
+    return HP_OK;
+  }
+  const int last = nd - 1;
+  const int n_last = P.n[last];
+  const int K = n_last / 2 + 1;
+  // spectral buffer dims (storage): [n0][n1][K] (3D) or [n0][K] (2D)
+  long long ss[3] = {0, 0, 0};  // strides per logical axis
+  if (nd == 3) { ss[2] = 1; ss[1] = K; ss[0] = (long long)P.n[1] * K; }
+  else { ss[1] = 1; ss[0] = K; }
+  long long fs[3] = {0, 0, 0};
+  if (nd == 3) { fs[2] = 1; fs[1] = P.n[2]; fs[0] = (long long)P.n[1] * P.n[2]; }
+  else { fs[1] = 1; fs[0] = P.n[1]; }
+  // P1: R2C along the last axis, per input component
+  {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_R2C;
+    a.L = n_last; a.n = n_last; a.nin = n_last; a.nout = K;
+    for (int f = 0; f < nin; ++f) { a.in[f] = P.in[f]; a.out[f] = P.b2[f]; }
+    a.in_sj = fs[last]; a.in_sp = fs[last - 1];
+    a.out_sj = ss[last]; a.out_sp = ss[last - 1];
+    a.Np = P.n[last - 1];
+    if (nd == 3) { a.in_so = fs[0]; a.out_so = ss[0]; a.No = P.n[0]; }
+    a.in_jfast = a.out_jfast = 1;
+    HP_TRY(finish_pass(p, a, 16, 2, 0, 1));
+    out.push_back({a, nin});
+  }
+  // P2 (3D): forward C2C along axis 1, in place
+  PassArgs p2{};
+  if (nd == 3) {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_C2C_F;
+    a.L = P.n[1]; a.n = P.n[1]; a.nin = a.nout = P.n[1];
+    for (int f = 0; f < nin; ++f) { a.in[f] = P.b2[f]; a.out[f] = P.b2[f]; }
+    a.in_sj = a.out_sj = ss[1];
+    a.in_sp = a.out_sp = ss[2];
+    a.in_so = a.out_so = ss[0];
+    a.Np = K; a.No = P.n[0];
+    HP_TRY(finish_pass(p, a, 16, 1, 0, 0));
+    p2 = a;
+    out.push_back({a, nin});
+  }
+  // P3: sandwich along axis 0
+  {
+    PassArgs a = base();
+    sandwich_common(a);
+    a.xf = X_C2C_F; a.xb = X_C2C_B;
+    a.L = P.n[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
+    for (int f = 0; f < nin; ++f) a.in[f] = P.b2[f];
+    for (int f = 0; f < nfo; ++f) a.out[f] = P.b2[f];
+    a.in_sj = a.out_sj = ss[0];
+    a.in_sp = a.out_sp = ss[last];
+    a.Np = K;
+    a.ax_j = 0; a.ax_p = last;
+    if (nd == 3) { a.in_so = a.out_so = ss[1]; a.No = P.n[1]; a.ax_o = 1; }
+    HP_TRY(finish_pass(p, a, 16, 1, 0, 4));
+    out.push_back({a, coupled ? 1 : nin});
+  }
+  // P4 (3D): backward C2C along axis 1 on every output field
+  if (nd == 3) {
+    PassArgs a = p2;
+    a.xf = X_C2C_B;
+    for (int f = 0; f < nfo; ++f) { a.in[f] = P.b2[f]; a.out[f] = P.b2[f]; }
+    out.push_back({a, nfo});
+  }
+  // P5: C2R along the last axis into the outputs
+  {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_C2R;
+    a.L = n_last; a.n = n_last; a.nin = K; a.nout = n_last;
+    for (int f = 0; f < nfo; ++f) { a.in[f] = P.b2[f]; a.out[f] = outptr(f); }
+    a.in_sj = ss[last]; a.in_sp = ss[last - 1];
+    a.out_sj = fs[last]; a.out_sp = fs[last - 1];
+    a.Np = P.n[last - 1];
+    if (nd == 3) { a.in_so = ss[0]; a.out_so = fs[0]; a.No = P.n[0]; }
+    a.in_jfast = a.out_jfast = 1;
+    HP_TRY(finish_pass(p, a, 16, 2, 0, 2));
+    out.push_back({a, nfo});
+  }
+  return HP_OK;
+}
+
+// Unbounded (3D): pruned doubled-domain transform with transposing layouts
+//   f [x][y][z] -R2C z-> A1 [x][kz][y] -C2C y-> B2 [kz][ky][x]
+//   -sandwich x (Ghat, derivative)-> B2 -C2C^-1 y-> [kz][y][x] -C2R z-> out [x][y][z]
+// Only the physical half of every doubled axis is ever loaded or stored.
+hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2];
+  const int K2 = M2 / 2 + 1;
+  const int nc = P.ncomp, nder = P.nder;
+  const int nslot = nc + nder;
+  // input / output fields of this direction
+  const void* src[kMaxFields] = {};
+  void* dst[kMaxFields] = {};
+  int n_src, n_dst;
+  if (!adjoint) {
+    n_src = nc;
+    n_dst = nslot;
+    for (int c = 0; c < nc; ++c) src[c] = P.in[c];
+    for (int f = 0; f < nslot; ++f) dst[f] = f < nc ? P.out[f] : P.der[f - nc];
+  } else {
+    n_src = nslot;
+    n_dst = nc;
+    for (int f = 0; f < nslot; ++f) src[f] = f < nc ? P.out[f] : P.der[f - nc];
+    for (int c = 0; c < nc; ++c) dst[c] = (void*)P.in[c];
+  }
+  auto base = [&]() {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.n_in = a.n_out = 1;
+    return a;
+  };
+  // P1: R2C along z (pruned input: z < n2 of M2)
+  {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_R2C;
+    a.L = M2; a.n = M2; a.nin = n2; a.nout = K2;
+    for (int f = 0; f < n_src; ++f) { a.in[f] = src[f]; a.out[f] = P.a1[f]; }
+    a.in_sj = 1; a.in_sp = n2; a.in_so = (long long)n1 * n2;
+    a.out_sj = n1; a.out_sp = 1; a.out_so = (long long)K2 * n1;
+    a.Np = n1; a.No = n0;
+    a.in_jfast = 1; a.out_jfast = 0;
+    HP_TRY(finish_pass(p, a, p->prec == 0 ? 32 : 16, 2, 0, 1));
+    out.push_back({a, n_src});
+  }
+  // P2: C2C along y (pruned input y < n1 of M1), transposing to [kz][ky][x]
+  {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_C2C_F;
+    a.L = M1; a.n = M1; a.nin = n1; a.nout = M1;
+    for (int f = 0; f < n_src; ++f) { a.in[f] = src[f] ? P.a1[f] : nullptr; a.out[f] = P.b2[f]; }
+    a.in_sj = 1; a.in_sp = (long long)K2 * n1; a.in_so = n1;
+    a.out_sj = n0; a.out_sp = 1; a.out_so = (long long)M1 * n0;
+    a.Np = n0; a.No = K2;
+    a.in_jfast = 1; a.out_jfast = 0;
+    HP_TRY(finish_pass(p, a, p->prec == 0 ? 32 : 16, 1, 0, 0));
+    out.push_back({a, n_src});
+  }
+  // P3: sandwich along x: forward (x < n0 of M0), Ghat, derivative, backward (x < n0)
+  {
+    PassArgs a = base();
+    a.kind = PK_SANDWICH;
+    a.xf = X_C2C_F; a.xb = X_C2C_B;
+    a.L = M0; a.n = M0; a.nin = n0; a.nout = n0;
+    for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
+    for (int f = 0; f < n_dst; ++f) a.out[f] = P.b2[f];
+    a.in_sj = a.out_sj = 1;
+    a.in_sp = a.out_sp = n0;
+    a.in_so = a.out_so = (long long)M1 * n0;
+    a.Np = M1; a.No = K2;
+    a.in_jfast = a.out_jfast = 1;
+    a.ax_j = 0; a.ax_p = 1; a.ax_o = 2;
+    a.mult = M_GREEN;
+    a.green = P.green;
+    for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+    a.gM[0] = M0; a.gM[1] = M1; a.gM[2] = M2;
+    for (int b = 0; b < 3; ++b) a.kvec[b] = P.kvec[b];
+    const int dk = P.d.diff;
+    if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
+    else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
+    const bool coupled = a.diff != D_NONE;
+    a.n_in = coupled ? n_src : 1;
+    a.n_out = coupled ? n_dst : 1;
+    HP_TRY(finish_pass(p, a, 16, 1, 0, 4));
+    out.push_back({a, coupled ? 1 : nc});
+  }
+  // P4: backward C2C along y, keep y < n1, in place in B2
+  {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_C2C_B;
+    a.L = M1; a.n = M1; a.nin = M1; a.nout = n1;
+    for (int f = 0; f < n_dst; ++f) { a.in[f] = P.b2[f]; a.out[f] = P.b2[f]; }
+    a.in_sj = a.out_sj = n0;
+    a.in_sp = a.out_sp = 1;
+    a.in_so = a.out_so = (long long)M1 * n0;
+    a.Np = n0; a.No = K2;
+    a.in_jfast = a.out_jfast = 0;
+    HP_TRY(finish_pass(p, a, p->prec == 0 ? 32 : 16, 1, 0, 0));
+    out.push_back({a, n_dst});
+  }
+  // P5: C2R along z, keep z < n2, into the destination arrays [x][y][z]
+  {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = X_C2R;
+    a.L = M2; a.n = M2; a.nin = K2; a.nout = n2;
+    for (int f = 0; f < n_dst; ++f) { a.in[f] = P.b2[f]; a.out[f] = dst[f]; }
+    a.in_sj = (long long)M1 * n0; a.in_sp = 1; a.in_so = n0;
+    a.out_sj = 1; a.out_sp = (long long)n1 * n2; a.out_so = n2;
+    a.Np = n0; a.No = n1;
+    a.in_jfast = 0; a.out_jfast = 1;
+    HP_TRY(finish_pass(p, a, p->prec == 0 ? 32 : 16, 2, 0, 2));
+    out.push_back({a, n_dst});
+  }
+  return HP_OK;
+}
+
+// Upgrade the general free-space passes to the wavefront-FFT kernels when every
+// doubled length is a power of two in [64, 1024] and the tiles fit in LDS.
+hp_status use_fast_unbounded(hp_plan p, Problem& P, std::vector<PassRec>& ps, size_t first) {
+  if (std::getenv("HP_GENERIC")) return HP_OK;
+  auto pow2 = [](int v) { return v >= 64 && v <= 1024 && (v & (v - 1)) == 0; };
+  for (int a = 0; a < 3; ++a)
+    if (!pow2(P.M[a])) return HP_OK;
+  const int Pw = p->prec == 0 ? 16 : 8;
+  const int kinds[5] = {FAST_R2C, FAST_FWD_Y, FAST_SANDWICH, FAST_INV_Y, FAST_C2R};
+  const int axisL[5] = {P.M[2], P.M[1], P.M[0], P.M[1], P.M[2]};
+  const int K2 = P.M[2] / 2 + 1;
+  for (int i = 0; i < 5; ++i)
+    if (fast_lds_bytes(kinds[i], axisL[i], Pw, K2, p->prec) > 160 * 1024) return HP_OK;
+  for (int i = 0; i < 5; ++i) {
+    PassArgs& a = ps[first + i].a;
+    a.fast = kinds[i];
+    a.P = Pw;
+    a.L = axisL[i];
+    const void* tw;
+    HP_TRY(twiddles(p, a.L, &tw));
+    a.tw = tw;
+    a.lds_bytes = fast_lds_bytes(kinds[i], a.L, Pw, K2, p->prec);
+    for (int b = 0; b < 3; ++b) {
+      a.un[b] = P.n[b];
+      a.gM[b] = P.M[b];
+      a.kc[b] = 2.0 * M_PI / (P.M[b] * P.h[b]);
+    }
+  }
+  return HP_OK;
+}
+
+hp_status build_passes(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
+  if (P.d.bc == HP_UNBOUNDED) {
+    const size_t first = out.size();
+    HP_TRY(passes_unbounded(p, P, adjoint, out));
+    return use_fast_unbounded(p, P, out, first);
+  }
+  if (adjoint) return fail(p, HP_E_UNSUPPORTED, "adjoint solve is provided for unbounded plans");
+  if (P.d.bc == HP_PERIODIC) return passes_periodic(p, P, out);
+  return passes_bounded(p, P, out);
+}
+
+// Algorithmic bytes: every pass reads its stored input and writes its stored
+// output once; the Green's octant is read once.
+double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
+  double b = 0.0;
+  const double es = (double)p->es;
+  for (auto& r : ps) {
+    const PassArgs& a = r.a;
+    const double pencils = (double)a.Np * a.No;
+    auto elem_in = [&](int x) {
+      return (x == X_C2C_F || x == X_C2C_B || x == X_C2R) ? 2 * es : es;
+    };
+    auto elem_out = [&](int x) {
+      return (x == X_C2C_F || x == X_C2C_B || x == X_R2C) ? 2 * es : es;
+    };
+    int nin_f, nout_f;
+    if (a.kind == PK_SANDWICH && a.diff != D_NONE) {
+      nin_f = 0;
+      for (int f = 0; f < a.n_in; ++f) nin_f += a.in[f] ? 1 : 0;
+      nout_f = a.n_out;
+    } else {
+      nin_f = 0;
+      for (int f = 0; f < r.grid_y; ++f) nin_f += a.in[f] ? 1 : 0;
+      nout_f = nin_f;
+    }
+    const int xb = a.kind == PK_SANDWICH ? a.xb : a.xf;
+    b += pencils * a.nin * elem_in(a.xf) * nin_f + pencils * a.nout * elem_out(xb) * nout_f;
+    if (a.mult == M_GREEN)
+      b += (double)(a.gM[0] / 2 + 1) * (a.gM[1] / 2 + 1) * (a.gM[2] / 2 + 1) * es;
+  }
+  return b;
+}
+
+const char* pass_name(const PassArgs& a) {
+  static const char* fast_names[] = {"", "r2c_z", "fwd_y", "sandwich_x", "inv_y", "c2r_z"};
+  if (a.fast) return fast_names[a.fast];
+  if (a.kind == PK_SANDWICH) return "sandwich";
+  switch (a.xf) {
+    case X_C2C_F: return "c2c_fwd";
+    case X_C2C_B: return "c2c_inv";
+    case X_R2C: return "r2c";
+    case X_C2R: return "c2r";
+    default: return "r2r";
+  }
+}
+
+hp_status next_event(hp_plan p, hipEvent_t* e) {
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t n;
+    HP_HIP(p, hipEventCreate(&n));
+    p->ev_pool.push_back(n);
+  }
+  *e = p->ev_pool[p->ev_used++];
+  return HP_OK;
+}
+
+hp_status run_passes(hp_plan p, const std::vector<PassRec>& ps) {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  if (p->timing) {
+    p->pass_bytes.clear();
+    p->pass_names.clear();
+  }
+  for (auto& r : ps) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p->timing) {
+      HP_TRY(next_event(p, &e0));
+      HP_TRY(next_event(p, &e1));
+      HP_HIP(p, hipEventRecord(e0, p->stream));
+    }
+    hipError_t e = r.a.fast ? launch_fast(r.a, p->prec, r.grid_y, p->stream)
+                            : launch_pass(r.a, p->prec, r.grid_y, p->stream);
+    if (e != hipSuccess) return fail(p, HP_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
+    if (p->timing) {
+      HP_HIP(p, hipEventRecord(e1, p->stream));
+      evs.push_back({e0, e1});
+      p->pass_bytes.push_back(model_bytes(p, std::vector<PassRec>{r}));
+      p->pass_names.push_back(pass_name(r.a));
+    }
+  }
+  if (p->timing) p->ev_solves.push_back(evs);
+  return HP_OK;
+}
+
+Problem* get_problem(hp_plan p, int problem) {
+  if (!p || problem < 0 || problem >= (int)p->probs.size()) return nullptr;
+  return &p->probs[problem];
+}
+
+hp_status copy_in(hp_plan p, const void* src, size_t bytes, int on_device, void** own,
+                  const void** slot) {
+  if (on_device) {
+    *slot = src;
+    return HP_OK;
+  }
+  if (!*own) HP_TRY(dev_alloc(p, bytes, own));
+  HP_HIP(p, hipMemcpyAsync(*own, src, bytes, hipMemcpyHostToDevice, p->stream));
+  HP_HIP(p, hipStreamSynchronize(p->stream));
+  *slot = *own;
+  return HP_OK;
+}
+
+hp_status create(const hp_desc* descs, int count, hp_stream stream, hp_plan* out, bool batched) {
+  if (!out) return fail(nullptr, HP_E_ARG, "null plan pointer");
+  *out = nullptr;
+  if (count < 1) return fail(nullptr, HP_E_ARG, "count must be >= 1");
+  if (!descs) return fail(nullptr, HP_E_ARG, "null descriptor");
+  for (int i = 0; i < count; ++i) HP_TRY(validate(&descs[i]));
+  if (batched) {
+    const hp_desc& d0 = descs[0];
+    for (int i = 1; i < count; ++i) {
+      const hp_desc& d = descs[i];
+      if (d.bc != d0.bc || d.grid != d0.grid || d.kernel != d0.kernel || d.diff != d0.diff ||
+          d.prec != d0.prec || d.ndim != d0.ndim || d.ncomp != d0.ncomp)
+        return fail(nullptr, HP_E_ARG, "batched problems must share bc/grid/kernel/diff/prec/ndim/ncomp");
+    }
+    if (d0.bc != HP_DIRICHLET && d0.bc != HP_NEUMANN)
+      return fail(nullptr, HP_E_UNSUPPORTED, "batched plans take Dirichlet or Neumann problems");
+    if (d0.inhomogeneous)
+      return fail(nullptr, HP_E_UNSUPPORTED, "batched plans take homogeneous problems");
+    if (d0.ndim != 3)
+      return fail(nullptr, HP_E_UNSUPPORTED, "batched plans take 3D problems");
+  }
+  hp_plan p = new (std::nothrow) hp_plan_s();
+  if (!p) return fail(nullptr, HP_E_NOMEM, "host allocation failed");
+  p->stream = (hipStream_t)stream;
+  p->prec = descs[0].prec;
+  p->es = p->prec == 0 ? 4 : 8;
+  p->batched = batched;
+  if (const char* f = std::getenv("HP_FAULT_ALLOC")) p->fail_alloc_at = std::atoi(f);
+  p->probs.resize(count);
+  hp_status st = HP_OK;
+  for (int i = 0; i < count && st == HP_OK; ++i) {
+    p->probs[i].d = descs[i];
+    st = setup_problem(p, p->probs[i]);
+  }
+  if (st == HP_OK && !batched) {
+    // dry build: every pass must fit (strides / LDS), with placeholder bindings
+    std::vector<PassRec> dry;
+    st = build_passes(p, p->probs[0], false, dry);
+  }
+  if (st != HP_OK) {
+    g_create_error = p->err;
+    for (void* a : p->allocs) hipFree(a);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return HP_OK;
+}
+
+}  // namespace
+
+namespace hp {
+hp_status plan_fail(hp_plan p, hp_status s, const std::string& msg) { return fail(p, s, msg); }
+hp_status plan_alloc(hp_plan p, size_t bytes, void** out) { return dev_alloc(p, bytes, out); }
+hp_status passes_for(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
+  return build_passes(p, P, adjoint, out);
+}
+double passes_model_bytes(hp_plan p, const std::vector<PassRec>& ps) { return model_bytes(p, ps); }
+}  // namespace hp
+
+extern "C" {
+
+const char* hp_status_string(hp_status s) {
+  const int i = -(int)s;
+  if (i < 0 || i > 5) return "unknown status";
+  return kStatusText[i];
+}
+
+const char* hp_last_error(hp_plan plan) {
+  if (!plan) return g_create_error.c_str();
+  return plan->err.c_str();
+}
+
+hp_status hp_plan_create(const hp_desc* desc, hp_stream stream, hp_plan* out) {
+  return create(desc, 1, stream, out, false);
+}
+
+hp_status hp_input_shape(hp_plan plan, int problem, int64_t shape[3]) {
+  Problem* P = get_problem(plan, problem);
+  if (!P || !shape) return fail(plan, HP_E_ARG, "bad problem index or shape pointer");
+  for (int a = 0; a < 3; ++a) shape[a] = P->n[a];
+  return HP_OK;
+}
+
+hp_status hp_output_shape(hp_plan plan, int problem, int64_t shape[3]) {
+  Problem* P = get_problem(plan, problem);
+  if (!P || !shape) return fail(plan, HP_E_ARG, "bad problem index or shape pointer");
+  for (int a = 0; a < 3; ++a) shape[a] = P->nout[a];
+  return HP_OK;
+}
+
+hp_status hp_set_input(hp_plan plan, int problem, int comp, const void* f, int on_device) {
+  Problem* P = get_problem(plan, problem);
+  if (!P) return fail(plan, HP_E_ARG, "bad plan or problem index");
+  if (comp < 0 || comp >= P->ncomp) return fail(plan, HP_E_ARG, "bad component");
+  if (!f) {
+    P->in[comp] = nullptr;
+    return HP_OK;
+  }
+  const size_t bytes = count_elems(P->n, P->nd) * plan->es;
+  return copy_in(plan, f, bytes, on_device, &P->own_in[comp], &P->in[comp]);
+}
+
+hp_status hp_set_boundary(hp_plan plan, int problem, int axis, int side, int comp, const void* g,
+                          int on_device) {
+  Problem* P = get_problem(plan, problem);
+  if (!P) return fail(plan, HP_E_ARG, "bad plan or problem index");
+  if (!P->d.inhomogeneous) return fail(plan, HP_E_STATE, "plan was created homogeneous");
+  if (axis < 0 || axis >= P->nd || side < 0 || side > 1 || comp < 0 || comp >= P->ncomp)
+    return fail(plan, HP_E_ARG, "bad axis, side or component");
+  if (!g) {
+    P->face[axis][side][comp] = nullptr;
+    return HP_OK;
+  }
+  size_t cnt = 1;
+  for (int b = 0; b < P->nd; ++b)
+    if (b != axis) cnt *= (size_t)P->nout[b];
+  return copy_in(plan, g, cnt * plan->es, on_device, &P->own_face[axis][side][comp],
+                 &P->face[axis][side][comp]);
+}
+
+hp_status hp_bind_output(hp_plan plan, int problem, int comp, void* psi) {
+  Problem* P = get_problem(plan, problem);
+  if (!P) return fail(plan, HP_E_ARG, "bad plan or problem index");
+  if (comp < 0 || comp >= P->ncomp) return fail(plan, HP_E_ARG, "bad component");
+  P->out[comp] = psi ? psi : P->own_out[comp];
+  return HP_OK;
+}
+
+hp_status hp_bind_gradient(hp_plan plan, int problem, int comp, void* out) {
+  Problem* P = get_problem(plan, problem);
+  if (!P) return fail(plan, HP_E_ARG, "bad plan or problem index");
+  if (comp < 0 || comp >= P->nder) return fail(plan, HP_E_ARG, "bad derivative component");
+  P->der[comp] = out ? out : P->own_der[comp];
+  return HP_OK;
+}
+
+hp_status hp_solve(hp_plan plan) {
+  if (!plan) return HP_E_ARG;
+  if (plan->batched) return hp::batched_solve(plan);
+  Problem& P = plan->probs[0];
+  for (int c = 0; c < P.ncomp; ++c)
+    if (!P.in[c]) return fail(plan, HP_E_STATE, "input component " + std::to_string(c) + " not set");
+  HP_TRY(ensure_outputs(plan, P));
+  std::vector<PassRec> ps;
+  HP_TRY(build_passes(plan, P, false, ps));
+  HP_TRY(run_passes(plan, ps));
+  if (P.d.bc == HP_DIRICHLET && P.d.grid == HP_REGULAR) {
+    for (int c = 0; c < P.ncomp; ++c) {
+      const void* faces[3][2] = {};
+      for (int a = 0; a < P.nd; ++a)
+        for (int s = 0; s < 2; ++s) faces[a][s] = P.d.inhomogeneous ? P.face[a][s][c] : nullptr;
+      int N[3] = {1, 1, 1};
+      for (int a = 0; a < P.nd; ++a) N[3 - P.nd + a] = P.nout[a];
+      // the fill kernel indexes logical axes; pass dims in logical order
+      int Nl[3] = {P.nout[0], P.nd > 1 ? P.nout[1] : 1, P.nd > 2 ? P.nout[2] : 1};
+      (void)N;
+      HP_HIP(plan, launch_dirichlet_fill(P.out[c], Nl, P.nd, faces, plan->prec, plan->stream));
+    }
+  }
+  plan->solved = true;
+  return HP_OK;
+}
+
+hp_status hp_solve_adjoint(hp_plan plan) {
+  if (!plan) return HP_E_ARG;
+  if (plan->batched) return fail(plan, HP_E_UNSUPPORTED, "adjoint of a batched plan");
+  Problem& P = plan->probs[0];
+  if (P.d.bc != HP_UNBOUNDED) return fail(plan, HP_E_UNSUPPORTED, "adjoint solve is provided for unbounded plans");
+  for (int c = 0; c < P.ncomp; ++c) {
+    if (!P.in[c] || P.in[c] == P.own_in[c])
+      return fail(plan, HP_E_STATE, "adjoint needs device buffers bound with hp_set_input");
+  }
+  // unbound upstream gradients are zero: use null sources
+  Problem Q = P;
+  for (int c = 0; c < P.ncomp; ++c)
+    if (Q.out[c] == P.own_out[c]) Q.out[c] = nullptr;
+  for (int c = 0; c < P.nder; ++c)
+    if (Q.der[c] == P.own_der[c]) Q.der[c] = nullptr;
+  bool any = false;
+  for (int c = 0; c < P.ncomp; ++c) any |= Q.out[c] != nullptr;
+  for (int c = 0; c < P.nder; ++c) any |= Q.der[c] != nullptr;
+  if (!any) return fail(plan, HP_E_STATE, "adjoint needs at least one bound upstream gradient");
+  std::vector<PassRec> ps;
+  HP_TRY(build_passes(plan, Q, true, ps));
+  HP_TRY(run_passes(plan, ps));
+  return HP_OK;
+}
+
+static hp_status get_field(hp_plan plan, int problem, int comp, void* dst, int on_device, bool der) {
+  Problem* P = get_problem(plan, problem);
+  if (!P) return fail(plan, HP_E_ARG, "bad plan or problem index");
+  if (!plan->solved) return fail(plan, HP_E_STATE, "no solve has run");
+  if (!dst) return fail(plan, HP_E_ARG, "null destination");
+  void* srcp;
+  if (der) {
+    if (comp < 0 || comp >= P->nder) return fail(plan, HP_E_ARG, "bad derivative component");
+    srcp = P->der[comp];
+  } else {
+    if (comp < 0 || comp >= P->ncomp) return fail(plan, HP_E_ARG, "bad component");
+    srcp = P->out[comp];
+  }
+  if (!srcp) return fail(plan, HP_E_STATE, "output not available");
+  const size_t bytes = count_elems(P->nout, P->nd) * plan->es;
+  if (on_device) {
+    if (dst == srcp) return HP_OK;
+    HP_HIP(plan, hipMemcpyAsync(dst, srcp, bytes, hipMemcpyDeviceToDevice, plan->stream));
+  } else {
+    HP_HIP(plan, hipMemcpyAsync(dst, srcp, bytes, hipMemcpyDeviceToHost, plan->stream));
+    HP_HIP(plan, hipStreamSynchronize(plan->stream));
+  }
+  return HP_OK;
+}
+
+hp_status hp_get_output(hp_plan plan, int problem, int comp, void* dst, int on_device) {
+  return get_field(plan, problem, comp, dst, on_device, false);
+}
+
+hp_status hp_get_gradient(hp_plan plan, int problem, int comp, void* dst, int on_device) {
+  return get_field(plan, problem, comp, dst, on_device, true);
+}
+
+hp_status hp_set_timing(hp_plan plan, int enable) {
+  if (!plan) return HP_E_ARG;
+  plan->timing = enable != 0;
+  return HP_OK;
+}
+
+hp_status hp_pass_stats(hp_plan plan, int max, int* npass, double* ms, double* bytes,
+                        const char** names) {
+  if (!plan || max < 0) return HP_E_ARG;
+  HP_HIP(plan, hipStreamSynchronize(plan->stream));
+  const size_t np = plan->pass_names.size();
+  if (npass) *npass = (int)np;
+  std::vector<double> acc(np, 0.0);
+  size_t nsolve = 0;
+  for (auto& evs : plan->ev_solves) {
+    if (evs.size() != np) continue;
+    for (size_t i = 0; i < np; ++i) {
+      float t = 0.f;
+      HP_HIP(plan, hipEventElapsedTime(&t, evs[i].first, evs[i].second));
+      acc[i] += t;
+    }
+    ++nsolve;
+  }
+  for (size_t i = 0; i < np && (int)i < max; ++i) {
+    if (ms) ms[i] = nsolve ? acc[i] / nsolve : 0.0;
+    if (bytes) bytes[i] = plan->pass_bytes[i];
+    if (names) names[i] = plan->pass_names[i];
+  }
+  plan->ev_solves.clear();
+  plan->ev_used = 0;
+  return HP_OK;
+}
+
+hp_status hp_query(hp_plan plan, int what, double* value) {
+  if (!plan || !value) return HP_E_ARG;
+  Problem& P = plan->probs[0];
+  switch (what) {
+    case HP_Q_WORKSPACE_BYTES:
+      *value = (double)plan->ws_bytes;
+      return HP_OK;
+    case HP_Q_NUM_OUTPUTS:
+      *value = P.ncomp + P.nder;
+      return HP_OK;
+    case HP_Q_NUM_DERIVS:
+      *value = P.nder;
+      return HP_OK;
+    case HP_Q_MODEL_BYTES:
+    case HP_Q_NUM_PASSES: {
+      if (plan->batched) {
+        *value = what == HP_Q_MODEL_BYTES ? model_bytes(plan, plan->batch_passes)
+                                          : (double)plan->batch_passes.size();
+        return HP_OK;
+      }
+      // model with placeholder (non-null) bindings
+      Problem Q = P;
+      static char dummy;
+      for (int c = 0; c < Q.ncomp; ++c) if (!Q.in[c]) Q.in[c] = &dummy;
+      for (int c = 0; c < Q.ncomp; ++c) if (!Q.out[c]) Q.out[c] = &dummy;
+      for (int c = 0; c < Q.nder; ++c) if (!Q.der[c]) Q.der[c] = &dummy;
+      std::vector<PassRec> ps;
+      HP_TRY(build_passes(plan, Q, false, ps));
+      *value = what == HP_Q_MODEL_BYTES ? model_bytes(plan, ps) : (double)ps.size();
+      return HP_OK;
+    }
+    default:
+      return fail(plan, HP_E_ARG, "unknown query");
+  }
+}
+
+hp_status hp_plan_destroy(hp_plan plan) {
+  if (!plan) return HP_E_ARG;
+  (void)hipStreamSynchronize(plan->stream);
+  for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+  for (void* a : plan->allocs) (void)hipFree(a);
+  delete plan;
+  return HP_OK;
+}
+
+}  // extern "C"
+
+extern "C" hp_status hp_plan_create_batched(const hp_desc* descs, int count, hp_stream stream,
+                                            hp_plan* out) {
+  hp_status s = create(descs, count, stream, out, true);
+  if (s != HP_OK) return s;
+  s = hp::batched_setup(*out);
+  if (s != HP_OK) {
+    g_create_error = (*out)->err;
+    hp_plan_destroy(*out);
+    *out = nullptr;
+  }
+  return s;
+}

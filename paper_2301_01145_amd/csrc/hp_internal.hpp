@@ -1,0 +1,103 @@
+// Internal types shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hp {
+
+// Transform applied along the pencil axis of a pass.  Real-to-real and
+// real/complex conversions are computed with one complex FFT of length L on a
+// pair of real pencils (a + i b) and an extension or twiddle around it.
+enum Xform : int {
+  X_C2C_F = 0,  // complex DFT, exponent sign -1 (eq. dft, forward)
+  X_C2C_B = 1,  // complex DFT, exponent sign +1, unscaled
+  X_R2C = 2,    // real -> half spectrum (L/2 + 1), L = FFT length
+  X_C2R = 3,    // half spectrum -> real, unscaled
+  X_PAIR_F = 4, // two real pencils as one complex pencil, forward DFT
+  X_PAIR_B = 5, // inverse of X_PAIR_F (real part -> first, imag -> second)
+  X_DST1 = 6,   // L = 2 (n + 1), odd extension
+  X_DST2 = 7,   // via DCT-II of (-1)^j x_j, reversed output
+  X_DST3 = 8,   // via DCT-III of the reversed input, (-1)^k output
+  X_DCT1 = 9,   // L = 2 (n - 1), even extension
+  X_DCT2 = 10,  // L = 2 n, symmetric extension and e^{-i pi k / 2n}
+  X_DCT3 = 11   // L = 2 n, e^{+i pi j / 2n} Hermitian input, inverse DFT
+};
+
+enum PassKind : int { PK_ONEWAY = 0, PK_SANDWICH = 1 };
+enum MultKind : int { M_NONE = 0, M_EIGEN = 1, M_GREEN = 2 };
+// Derivative coupling inside the sandwich pass.
+enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_CURL = 4 };
+
+constexpr int kThreads = 256;
+constexpr int kMaxStages = 8;
+constexpr int kMaxFields = 6;
+
+struct PassArgs {
+  int kind;          // PassKind
+  int xf, xb;        // forward transform (and backward for the sandwich)
+  int L;             // FFT length
+  int n;             // transform length n of the real-to-real family
+  int nin, nout;     // stored elements along the pencil on input / output
+  int P;             // pencils per tile
+  int Np, No;        // pencils along the tile axis / outer axis
+  int in_jfast, out_jfast;  // 1: pencil axis has unit stride on that side
+  int nstage;
+  int radix[kMaxStages];
+  long long in_sj, in_sp, in_so;    // strides (elements) of the input side
+  long long out_sj, out_sp, out_so; // strides (elements) of the output side
+  int n_in, n_out;   // field counts (sandwich: coupled; one-way: per blockIdx.y)
+  const void* in[kMaxFields];
+  void* out[kMaxFields];
+  const void* tw;    // complex T, W_L^m = exp(-2 pi i m / L), m < L
+  const void* qtw;   // complex T, exp(-i pi j / (2 n)), j < n (DCT-II/III family)
+  int ax_j, ax_p, ax_o;  // logical axis of the pencil / tile / outer index (-1: none)
+  // multiplier of the sandwich
+  int mult;
+  const double* lam[3];  // per-axis eigenvalues (FP64)
+  double norm;           // product of the backward normalisations
+  const void* green;     // Ghat octant (T), norm folded in, layout [k2][i1][i0]
+  long long g_s[3];      // octant strides of i0, i1, k2
+  int gM[3];             // doubled sizes M_a
+  int diff;
+  const void* kvec[3];   // T, angular wavenumber per index (Nyquist 0)
+  // boundary terms added while loading the first pass (FD2 inhomogeneous)
+  const void* face[3][2];
+  long long face_s[3][2];  // strides of the two remaining axes (ascending)
+  int face_off;            // 1 when faces include boundary nodes (REGULAR Dirichlet)
+  double face_w[3][2];     // weight applied to g
+  int nunk[3];             // unknown counts per logical axis
+  int lds_bytes;
+  // wavefront-FFT kernels of the free-space path (0: general pass)
+  int fast;                // FAST_* below
+  int un[3];               // physical (undoubled) sizes n_a
+  double kc[3];            // 2 pi / (M_a H_a): angular wavenumber per index
+};
+
+enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
+                      FAST_INV_Y = 4, FAST_C2R = 5 };
+
+// Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
+hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
+// Dynamic LDS bytes of a wavefront-FFT pass.
+int fast_lds_bytes(int fast, int L, int P, int K2, int prec);
+
+// Launch one pass over `grid_y` independent field groups.
+hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s);
+// Evaluate prod(H) * G2 on the doubled grid (FP64, real, [M0][M1][M2]).
+hipError_t launch_green_eval(double* g, const int M[3], const double h[3], double sigma,
+                             double scale, hipStream_t s);
+// Keep the real part of an FP64 half spectrum [M0][M1][M2/2+1] (complex) on the
+// octant, scaled, as T, stored [M2/2+1][M1/2+1][M0/2+1] (axis 0 contiguous).
+hipError_t launch_octant(const double* spec, const int M[3], double scale, void* out,
+                         int prec, hipStream_t s);
+// Write the boundary nodes of a REGULAR Dirichlet output [N0][N1][N2] from
+// face arrays (node with several faces: highest axis wins).
+hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, const void* face[3][2],
+                                 int prec, hipStream_t s);
+// Persistent batched solve (bounded R2R problems).
+struct BatchItem;
+hipError_t launch_batched(const void* problems, int nprob, const void* items, int nitems,
+                          unsigned* counters, int ncounters, int grid, int lds, int prec,
+                          hipStream_t s);
+}  // namespace hp

@@ -1,0 +1,716 @@
+// General pencil-pass kernels of the spectral Poisson solve (gfx950).
+//
+// One launch transforms every pencil (1D line) of a field along one axis.  A
+// workgroup of 256 threads takes a tile of P pencils: it loads the tile from
+// HBM with unit-stride runs (along the pencil when the pencil is contiguous,
+// across pencils otherwise), builds the complex FFT input in LDS, runs a
+// mixed-radix (2/3/4/5/8) Stockham FFT in LDS and writes the result with
+// unit-stride runs again.  The strides of the input and output sides are
+// independent, so a pass can also transpose.
+//
+// The sandwich pass (last axis of the forward transform) loads, transforms,
+// multiplies by the spectral multiplier (Table 1 eigenvalues or the Green's
+// spectrum, Section 2.2 step 2), applies the spectral derivative (step 3,
+// eq. ft_sd), transforms back and stores, so the spectrum of that axis never
+// leaves LDS.
+#include "hp_device.hpp"
+#include "hp_internal.hpp"
+
+namespace hp {
+
+// ------------------------------------------------------------- Stockham FFT
+// One radix-R stage over `nfft` transforms of length L stored contiguously in
+// LDS.  Butterfly j of a transform reads x[j + t L/R] (t < R), twiddles input
+// t by W_{Ns R}^{t k} (k = j mod Ns), and writes output t' to
+// (j / Ns) Ns R + k + t' Ns.  All reads finish (barrier) before any write, so
+// the stage is in place.
+template <typename T, int R, int MAXE, bool INV>
+__device__ __attribute__((noinline)) void fft_stage(C2<T>* Z, int L, int nfft, int Ns, int twstep,
+                                          const C2<T>* __restrict__ tw) {
+  constexpr int MB = (MAXE + R - 1) / R;
+  const int nbl = L / R;
+  const int total = nfft * nbl;
+  C2<T> v[MB][R];
+  int ob[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int idx = threadIdx.x + b * kThreads;
+    ob[b] = -1;
+    if (idx < total) {
+      const int f = idx / nbl;
+      const int j = idx - f * nbl;
+      const int k = j % Ns;
+      const C2<T>* src = Z + f * L + j;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        C2<T> x = src[t * nbl];
+        if (t > 0 && k > 0) {
+          C2<T> w = tw[t * k * twstep];
+          if (INV) w.im = -w.im;
+          x = cmul(x, w);
+        }
+        v[b][t] = x;
+      }
+      ob[b] = f * L + (j - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    if (ob[b] >= 0) {
+      dftR<T, R, INV>(v[b]);
+#pragma unroll
+      for (int t = 0; t < R; ++t) Z[ob[b] + t * Ns] = v[b][t];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+struct Maxe {
+  static constexpr int v = 32;
+};
+template <>
+struct Maxe<double> {
+  static constexpr int v = 16;
+};
+
+// Full FFT of nfft transforms in LDS (caller has synchronised the input).
+template <typename T, bool INV>
+__device__ void fft_lds(C2<T>* Z, int nfft, const PassArgs& a) {
+  constexpr int ME = Maxe<T>::v;
+  const C2<T>* tw = (const C2<T>*)a.tw;
+  const int L = a.L;
+  int Ns = 1;
+  for (int s = 0; s < a.nstage; ++s) {
+    const int R = a.radix[s];
+    const int twstep = L / (Ns * R);
+    switch (R) {
+      case 8: fft_stage<T, 8, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+      case 4: fft_stage<T, 4, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+      case 2: fft_stage<T, 2, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+      case 3: fft_stage<T, 3, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+      default: fft_stage<T, 5, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+    }
+    Ns *= R;
+  }
+}
+
+__device__ __forceinline__ bool xform_inverse_fft(int x) {
+  return x == X_C2C_B || x == X_C2R || x == X_PAIR_B || x == X_DCT3 || x == X_DST3;
+}
+__device__ __forceinline__ bool xform_real_in(int x) {
+  return x == X_R2C || x == X_PAIR_F || x == X_DST1 || x == X_DST2 || x == X_DST3 ||
+         x == X_DCT1 || x == X_DCT2 || x == X_DCT3;
+}
+__device__ __forceinline__ bool xform_real_out(int x) {
+  return x == X_C2R || x == X_PAIR_B || x == X_DST1 || x == X_DST2 || x == X_DST3 ||
+         x == X_DCT1 || x == X_DCT2 || x == X_DCT3;
+}
+
+// ----------------------------------------------------------- tile addressing
+struct Tile {
+  int o, p0, np;
+};
+
+__device__ __forceinline__ Tile tile_of(const PassArgs& a) {
+  const int tiles_p = (a.Np + a.P - 1) / a.P;
+  Tile t;
+  t.o = blockIdx.x / tiles_p;
+  t.p0 = (blockIdx.x - t.o * tiles_p) * a.P;
+  t.np = min(a.P, a.Np - t.p0);
+  return t;
+}
+
+// Element e of a P x cnt tile -> (p, j), unit stride runs on the memory side.
+__device__ __forceinline__ void tile_pj(int e, int P, int cnt, int jfast, int& p, int& j) {
+  if (jfast) {
+    p = e / cnt;
+    j = e - p * cnt;
+  } else {
+    j = e / P;
+    p = e - j * P;
+  }
+}
+
+// Boundary terms of inhomogeneous FD2 problems (added to the source value of
+// an unknown next to a face).
+template <typename T>
+__device__ __forceinline__ double face_terms(const PassArgs& a, int j, int p, int o) {
+  int c[3] = {0, 0, 0};
+  if (a.ax_j >= 0) c[a.ax_j] = j;
+  if (a.ax_p >= 0) c[a.ax_p] = p;
+  if (a.ax_o >= 0) c[a.ax_o] = o;
+  double add = 0.0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const T* g = (const T*)a.face[ax][side];
+      if (!g) continue;
+      const int edge = side == 0 ? 0 : a.nunk[ax] - 1;
+      if (c[ax] != edge) continue;
+      long long off = 0;
+      int r = 0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (b == ax || a.nunk[b] <= 0) continue;
+        if (r < 2) off += (long long)(c[b] + a.face_off) * a.face_s[ax][r];
+        ++r;
+      }
+      add += a.face_w[ax][side] * (double)g[off];
+    }
+  }
+  return add;
+}
+
+// ---------------------------------------------------------------- loading
+// Complex pencils straight into Z[p][m], zero beyond nin.
+template <typename T>
+__device__ void load_c2c(C2<T>* Z, const void* src, const PassArgs& a, const Tile& t) {
+  const C2<T>* in = (const C2<T>*)src;
+  const int cnt = a.nin;
+  const int total = a.P * cnt;
+  const long long obase = (long long)t.o * a.in_so + (long long)t.p0 * a.in_sp;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int p, j;
+    tile_pj(e, a.P, cnt, a.in_jfast, p, j);
+    C2<T> v = {(T)0, (T)0};
+    if (p < t.np) v = in[obase + (long long)p * a.in_sp + (long long)j * a.in_sj];
+    Z[p * a.L + j] = v;
+  }
+  for (int e = threadIdx.x; e < a.P * (a.L - cnt); e += kThreads) {
+    const int p = e / (a.L - cnt);
+    const int m = cnt + (e - p * (a.L - cnt));
+    Z[p * a.L + m] = {(T)0, (T)0};
+  }
+}
+
+// Real pencils into R[p][j] (j < nin), with boundary terms when present.
+template <typename T>
+__device__ void load_real(T* R, const void* src, const PassArgs& a, const Tile& t, bool faces) {
+  const T* in = (const T*)src;
+  const int cnt = a.nin;
+  const int total = a.P * cnt;
+  const long long obase = (long long)t.o * a.in_so + (long long)t.p0 * a.in_sp;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int p, j;
+    tile_pj(e, a.P, cnt, a.in_jfast, p, j);
+    T v = (T)0;
+    if (p < t.np) {
+      v = in[obase + (long long)p * a.in_sp + (long long)j * a.in_sj];
+      if (faces) v = (T)((double)v + face_terms<T>(a, j, t.p0 + p, t.o));
+    }
+    R[p * cnt + j] = v;
+  }
+}
+
+// Half spectra (complex, nin = L/2 + 1) into R[p][k].
+template <typename T>
+__device__ void load_half(C2<T>* R, const void* src, const PassArgs& a, const Tile& t) {
+  const C2<T>* in = (const C2<T>*)src;
+  const int cnt = a.nin;
+  const int total = a.P * cnt;
+  const long long obase = (long long)t.o * a.in_so + (long long)t.p0 * a.in_sp;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int p, j;
+    tile_pj(e, a.P, cnt, a.in_jfast, p, j);
+    C2<T> v = {(T)0, (T)0};
+    if (p < t.np) v = in[obase + (long long)p * a.in_sp + (long long)j * a.in_sj];
+    R[p * cnt + j] = v;
+  }
+}
+
+// Build the complex FFT input Z[f][m] (f = pencil pair) from real pencils R.
+template <typename T>
+__device__ void build_from_real(C2<T>* Z, const T* R, int x, const PassArgs& a, int nfft) {
+  const int L = a.L, n = a.n, cnt = a.nin;
+  const C2<T>* q = (const C2<T>*)a.qtw;
+  for (int e = threadIdx.x; e < nfft * L; e += kThreads) {
+    const int f = e / L;
+    const int m = e - f * L;
+    const T* ra = R + (2 * f) * cnt;
+    const T* rb = ra + cnt;
+    C2<T> z = {(T)0, (T)0};
+    switch (x) {
+      case X_R2C:
+      case X_PAIR_F:
+        if (m < cnt) z = {ra[m], rb[m]};
+        break;
+      case X_DST1:  // [0, x_0..x_{n-1}, 0, -x_{n-1}..-x_0]
+        if (m >= 1 && m <= n) z = {ra[m - 1], rb[m - 1]};
+        else if (m > n + 1) z = {-ra[L - m - 1], -rb[L - m - 1]};
+        break;
+      case X_DCT1: {  // [x_0..x_{n-1}, x_{n-2}..x_1]
+        const int s = m < n ? m : L - m;
+        z = {ra[s], rb[s]};
+      } break;
+      case X_DCT2:
+      case X_DST2: {  // [x_0..x_{n-1}, x_{n-1}..x_0], DST-II with (-1)^j
+        const int s = m < n ? m : L - 1 - m;
+        z = {ra[s], rb[s]};
+        if (x == X_DST2 && (s & 1)) z = {-z.re, -z.im};
+      } break;
+      case X_DCT3:
+      case X_DST3: {  // e^{+i pi j/2n} (a_j + i b_j), j < n; 0 at n; conjugate twist above
+        if (m == n) break;
+        const int s = m < n ? m : L - m;
+        const int src = (x == X_DST3) ? n - 1 - s : s;
+        C2<T> v = {ra[src], rb[src]};
+        C2<T> w = q[s];  // e^{-i pi s / 2n}
+        if (m < n) w.im = -w.im;
+        z = cmul(v, w);
+      } break;
+      default:
+        break;
+    }
+    Z[e] = z;
+  }
+}
+
+// Build Z[f][m] from two half spectra R[2f], R[2f+1] (Hermitian completion).
+template <typename T>
+__device__ void build_from_half(C2<T>* Z, const C2<T>* R, const PassArgs& a, int nfft) {
+  const int L = a.L, cnt = a.nin, half = L / 2;
+  for (int e = threadIdx.x; e < nfft * L; e += kThreads) {
+    const int f = e / L;
+    const int m = e - f * L;
+    const C2<T>* ra = R + (2 * f) * cnt;
+    const C2<T>* rb = ra + cnt;
+    C2<T> A, B;
+    if (m <= half) {
+      A = ra[m];
+      B = rb[m];
+      if (m == 0 || 2 * m == L) {
+        A.im = (T)0;
+        B.im = (T)0;
+      }
+    } else {
+      A = cconj(ra[L - m]);
+      B = cconj(rb[L - m]);
+    }
+    Z[e] = {A.re - B.im, A.im + B.re};
+  }
+}
+
+// ---------------------------------------------------------------- storing
+// Value of output element (pencil p, index k) computed from the transformed Z.
+template <typename T>
+__device__ __forceinline__ T real_out(const C2<T>* Z, int x, const PassArgs& a, int p, int k) {
+  const int f = p >> 1;
+  const bool second = p & 1;
+  const C2<T>* z = Z + f * a.L;
+  switch (x) {
+    case X_DST1: {
+      C2<T> v = z[k + 1];
+      return second ? v.re : -v.im;
+    }
+    case X_DCT1:
+    case X_DCT3:
+    case X_C2R:
+    case X_PAIR_B: {
+      C2<T> v = z[k];
+      return second ? v.im : v.re;
+    }
+    case X_DST3: {
+      C2<T> v = z[k];
+      T r = second ? v.im : v.re;
+      return (k & 1) ? -r : r;
+    }
+    case X_DCT2:
+    case X_DST2: {
+      const int kk = (x == X_DST2) ? a.n - 1 - k : k;
+      C2<T> v = cmul(z[kk], ((const C2<T>*)a.qtw)[kk]);
+      return second ? v.im : v.re;
+    }
+    default:
+      return (T)0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T> half_out(const C2<T>* Z, const PassArgs& a, int p, int k) {
+  const int f = p >> 1;
+  const C2<T>* z = Z + f * a.L;
+  C2<T> zk = z[k];
+  C2<T> zc = cconj(z[k == 0 ? 0 : a.L - k]);
+  if (p & 1) {  // (zk - zc) / (2 i)
+    C2<T> d = csub(zk, zc);
+    return {d.im * (T)0.5, -d.re * (T)0.5};
+  }
+  C2<T> s = cadd(zk, zc);
+  return {s.re * (T)0.5, s.im * (T)0.5};
+}
+
+template <typename T>
+__device__ void store_out(const C2<T>* Z, int x, void* dst, const PassArgs& a, const Tile& t) {
+  const int cnt = a.nout;
+  const int total = a.P * cnt;
+  const long long obase = (long long)t.o * a.out_so + (long long)t.p0 * a.out_sp;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int p, k;
+    tile_pj(e, a.P, cnt, a.out_jfast, p, k);
+    if (p >= t.np) continue;
+    const long long off = obase + (long long)p * a.out_sp + (long long)k * a.out_sj;
+    if (x == X_C2C_F || x == X_C2C_B) {
+      ((C2<T>*)dst)[off] = Z[p * a.L + k];
+    } else if (x == X_R2C) {
+      ((C2<T>*)dst)[off] = half_out(Z, a, p, k);
+    } else {
+      ((T*)dst)[off] = real_out(Z, x, a, p, k);
+    }
+  }
+}
+
+// -------------------------------------------------------- spectral multiply
+template <typename T>
+__device__ __forceinline__ T multiplier(const PassArgs& a, const int k[3]) {
+  if (a.mult == M_EIGEN) {
+    double lam = a.lam[0][k[0]];
+    if (a.lam[1]) lam += a.lam[1][k[1]];
+    if (a.lam[2]) lam += a.lam[2][k[2]];
+    return lam == 0.0 ? (T)0 : (T)(a.norm / lam);
+  }
+  if (a.mult == M_GREEN) {
+    const int i0 = min(k[0], a.gM[0] - k[0]);
+    const int i1 = min(k[1], a.gM[1] - k[1]);
+    return ((const T*)a.green)[(long long)i0 * a.g_s[0] + (long long)i1 * a.g_s[1] +
+                               (long long)k[2] * a.g_s[2]];
+  }
+  return (T)1;
+}
+
+// Spectral indices of element m of pencil p (tile-relative pencils beyond the
+// last one are clamped: their values are never stored).
+__device__ __forceinline__ void spectral_index(const PassArgs& a, int m, int p, int o, int k[3]) {
+  p = min(p, a.Np - 1);
+  k[0] = k[1] = k[2] = 0;
+  if (a.ax_j >= 0) k[a.ax_j] = m;
+  if (a.ax_p >= 0) k[a.ax_p] = p;
+  if (a.ax_o >= 0) k[a.ax_o] = o;
+}
+
+template <typename T>
+__device__ __forceinline__ T kval(const PassArgs& a, int axis, const int k[3]) {
+  return ((const T*)a.kvec[axis])[k[axis]];
+}
+
+// ------------------------------------------------------------ pass bodies
+template <typename T>
+__device__ void oneway(const PassArgs& a, unsigned char* smem, const Tile& t, int field) {
+  if (!a.in[field]) return;  // absent field (zero upstream gradient): uniform per block
+  C2<T>* Z = (C2<T>*)smem;
+  const int x = a.xf;
+  const bool pair = xform_real_in(x) || x == X_C2R;
+  const int nfft = pair ? a.P / 2 : a.P;
+  const bool faces = a.face[0][0] || a.face[0][1] || a.face[1][0] || a.face[1][1] ||
+                     a.face[2][0] || a.face[2][1];
+  unsigned char* rbuf = smem + (size_t)nfft * a.L * sizeof(C2<T>);
+  if (x == X_C2C_F || x == X_C2C_B) {
+    load_c2c<T>(Z, a.in[field], a, t);
+  } else if (x == X_C2R) {
+    load_half<T>((C2<T>*)rbuf, a.in[field], a, t);
+    __syncthreads();
+    build_from_half<T>(Z, (const C2<T>*)rbuf, a, nfft);
+  } else {
+    load_real<T>((T*)rbuf, a.in[field], a, t, faces);
+    __syncthreads();
+    build_from_real<T>(Z, (const T*)rbuf, x, a, nfft);
+  }
+  __syncthreads();
+  if (xform_inverse_fft(x)) fft_lds<T, true>(Z, nfft, a);
+  else fft_lds<T, false>(Z, nfft, a);
+  store_out<T>(Z, x, a.out[field], a, t);
+}
+
+// Real-to-real sandwich (Dirichlet / Neumann): forward R2R, multiply by the
+// FD2 / PS multiplier, backward R2R, along the same axis.
+template <typename T>
+__device__ void sandwich_r2r(const PassArgs& a, unsigned char* smem, const Tile& t, int field) {
+  const int nfft = a.P / 2;
+  C2<T>* Z = (C2<T>*)smem;
+  T* R = (T*)(smem + (size_t)nfft * a.L * sizeof(C2<T>));
+  const bool faces = a.face[0][0] || a.face[0][1] || a.face[1][0] || a.face[1][1] ||
+                     a.face[2][0] || a.face[2][1];
+  load_real<T>(R, a.in[field], a, t, faces);
+  __syncthreads();
+  build_from_real<T>(Z, R, a.xf, a, nfft);
+  __syncthreads();
+  if (xform_inverse_fft(a.xf)) fft_lds<T, true>(Z, nfft, a);
+  else fft_lds<T, false>(Z, nfft, a);
+  // spectral values times the multiplier, back into R (same [p][k] layout)
+  for (int e = threadIdx.x; e < a.P * a.n; e += kThreads) {
+    const int p = e / a.n;
+    const int m = e - p * a.n;
+    int k[3];
+    spectral_index(a, m, t.p0 + p, t.o, k);
+    R[e] = real_out<T>(Z, a.xf, a, p, m) * multiplier<T>(a, k);
+  }
+  __syncthreads();
+  build_from_real<T>(Z, R, a.xb, a, nfft);
+  __syncthreads();
+  if (xform_inverse_fft(a.xb)) fft_lds<T, true>(Z, nfft, a);
+  else fft_lds<T, false>(Z, nfft, a);
+  store_out<T>(Z, a.xb, a.out[field], a, t);
+}
+
+// Complex sandwich (periodic after R2C, unbounded, 1D periodic pairs):
+// every coupled field of the tile is resident: S_c (P x L each) plus a work
+// buffer W for derivative outputs.
+template <typename T>
+__device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile& t) {
+  const bool pair = a.xf == X_PAIR_F;
+  const int nfft = pair ? a.P / 2 : a.P;
+  const int L = a.L;
+  const int tileC = nfft * L;
+  const bool adj = a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD;
+  const int nS = adj ? a.n_out : a.n_in;
+  // independent fields (no derivative coupling) take their field from blockIdx.y
+  const int fb = (a.diff == D_NONE) ? (int)blockIdx.y : 0;
+  C2<T>* S = (C2<T>*)smem;
+  C2<T>* W = S + (size_t)nS * tileC;
+  T* R = (T*)(W + tileC);  // raw real pencils (pair mode)
+
+  auto load_into = [&](C2<T>* dst, const void* src) {
+    if (pair) {
+      load_real<T>(R, src, a, t, false);
+      __syncthreads();
+      build_from_real<T>(dst, R, X_PAIR_F, a, nfft);
+    } else {
+      load_c2c<T>(dst, src, a, t);
+    }
+    __syncthreads();
+    fft_lds<T, false>(dst, nfft, a);
+  };
+
+  for (int c = 0; c < nS; ++c) {
+    if (a.in[fb + c]) {
+      load_into(S + (size_t)c * tileC, a.in[fb + c]);
+    } else {
+      for (int e = threadIdx.x; e < tileC; e += kThreads) S[(size_t)c * tileC + e] = {(T)0, (T)0};
+      __syncthreads();
+    }
+  }
+  // Transposed derivative inputs: curl (symmetric) or minus the divergence.
+  if (adj) {
+    const int nextra = a.n_in - nS;
+    for (int i = 0; i < nextra; ++i) {
+      const void* src = a.in[nS + i];
+      if (!src) continue;
+      load_into(W, src);
+      for (int e = threadIdx.x; e < tileC; e += kThreads) {
+        const int f = e / L;
+        const int m = e - f * L;
+        int k[3];
+        spectral_index(a, m, t.p0 + f, t.o, k);
+        const C2<T> g = W[e];
+        if (a.diff == D_ADJ_CURL) {
+          // (C g)_c = i(k_{c+1} g_{c+2} - k_{c+2} g_{c+1}): g_i enters
+          // component i+1 with +i k_{i+2} and component i+2 with -i k_{i+1}
+          const int c1 = (i + 1) % 3, c2 = (i + 2) % 3;
+          const T kc1 = kval<T>(a, c1, k), kc2 = kval<T>(a, c2, k);
+          C2<T> ig = cmuli(g);
+          S[(size_t)c1 * tileC + e] = cadd(S[(size_t)c1 * tileC + e], cscale(ig, kc2));
+          S[(size_t)c2 * tileC + e] = csub(S[(size_t)c2 * tileC + e], cscale(ig, kc1));
+        } else {
+          const T ka = kval<T>(a, i, k);
+          S[e] = csub(S[e], cscale(cmuli(g), ka));
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // multiply by the spectral multiplier
+  for (int e = threadIdx.x; e < tileC; e += kThreads) {
+    const int f = e / L;
+    const int m = e - f * L;
+    int k[3];
+    spectral_index(a, m, t.p0 + f, t.o, k);
+    const T mu = multiplier<T>(a, k);
+    for (int c = 0; c < nS; ++c) S[(size_t)c * tileC + e] = cscale(S[(size_t)c * tileC + e], mu);
+  }
+  __syncthreads();
+  const int xb = pair ? X_PAIR_B : X_C2C_B;
+  // derivative outputs (forward GRAD / CURL) through W, then psi in place
+  if (a.diff == D_GRAD || a.diff == D_CURL) {
+    const int nd = a.n_out - a.n_in;
+    for (int d = 0; d < nd; ++d) {
+      for (int e = threadIdx.x; e < tileC; e += kThreads) {
+        const int f = e / L;
+        const int m = e - f * L;
+        int k[3];
+        spectral_index(a, m, t.p0 + f, t.o, k);
+        C2<T> v;
+        if (a.diff == D_GRAD) {
+          v = cscale(cmuli(S[e]), kval<T>(a, d, k));
+        } else {
+          const int c1 = (d + 1) % 3, c2 = (d + 2) % 3;
+          v = cmuli(csub(cscale(S[(size_t)c2 * tileC + e], kval<T>(a, c1, k)),
+                         cscale(S[(size_t)c1 * tileC + e], kval<T>(a, c2, k))));
+        }
+        W[e] = v;
+      }
+      __syncthreads();
+      fft_lds<T, true>(W, nfft, a);
+      store_out<T>(W, xb, a.out[a.n_in + d], a, t);
+      __syncthreads();
+    }
+  }
+  for (int c = 0; c < nS; ++c) {
+    fft_lds<T, true>(S + (size_t)c * tileC, nfft, a);
+    store_out<T>(S + (size_t)c * tileC, xb, a.out[fb + c], a, t);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_oneway(const PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  oneway<T>(a, smem, tile_of(a), blockIdx.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_sandwich_c2c(const PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sandwich_c2c<T>(a, smem, tile_of(a));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_sandwich_r2r(const PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sandwich_r2r<T>(a, smem, tile_of(a), blockIdx.y);
+}
+
+template <auto K>
+static void allow_lds() {
+  static bool done = false;  // one flag per kernel instantiation
+  if (!done) {
+    (void)hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    done = true;
+  }
+}
+
+template <typename T>
+static void launch_t(const PassArgs& a, dim3 grid, hipStream_t s) {
+  allow_lds<k_oneway<T>>();
+  allow_lds<k_sandwich_c2c<T>>();
+  allow_lds<k_sandwich_r2r<T>>();
+  if (a.kind == PK_ONEWAY)
+    hipLaunchKernelGGL(k_oneway<T>, grid, dim3(kThreads), a.lds_bytes, s, a);
+  else if (a.xf == X_C2C_F || a.xf == X_PAIR_F)
+    hipLaunchKernelGGL(k_sandwich_c2c<T>, grid, dim3(kThreads), a.lds_bytes, s, a);
+  else
+    hipLaunchKernelGGL(k_sandwich_r2r<T>, grid, dim3(kThreads), a.lds_bytes, s, a);
+}
+
+hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s) {
+  const int tiles = ((a.Np + a.P - 1) / a.P) * a.No;
+  dim3 grid(tiles, grid_y);
+  if (prec == 0) launch_t<float>(a, grid, s);
+  else launch_t<double>(a, grid, s);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ plan-time kernels
+__global__ void k_green_eval(double* g, int M0, int M1, int M2, double h0, double h1,
+                             double h2, double sigma, double scale) {
+  const long long total = (long long)M0 * M1 * M2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(i % M2);
+    const int y = (int)((i / M2) % M1);
+    const int x = (int)(i / ((long long)M1 * M2));
+    const double dx = min(x, M0 - x) * h0, dy = min(y, M1 - y) * h1, dz = min(z, M2 - z) * h2;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double v;
+    if (r == 0.0) {
+      v = -1.0 / (pow(2.0 * M_PI, 1.5) * sigma);
+    } else {
+      v = -erf(r / (M_SQRT2 * sigma)) / (4.0 * M_PI * r);
+    }
+    g[i] = v * scale;
+  }
+}
+
+hipError_t launch_green_eval(double* g, const int M[3], const double h[3], double sigma,
+                             double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_green_eval, dim3(4096), dim3(256), 0, s, g, M[0], M[1], M[2], h[0], h[1],
+                     h[2], sigma, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_octant(const double* spec, int M0, int M1, int K2, double scale, T* out) {
+  const int O0 = M0 / 2 + 1, O1 = M1 / 2 + 1;
+  const long long total = (long long)O0 * O1 * K2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % O0);
+    const int y = (int)((i / O0) % O1);
+    const int z = (int)(i / ((long long)O0 * O1));
+    const long long src = ((long long)x * M1 + y) * K2 + z;
+    out[i] = (T)(spec[2 * src] * scale);
+  }
+}
+
+hipError_t launch_octant(const double* spec, const int M[3], double scale, void* out, int prec,
+                         hipStream_t s) {
+  const int K2 = M[2] / 2 + 1;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_octant<float>, dim3(2048), dim3(256), 0, s, spec, M[0], M[1], K2, scale,
+                       (float*)out);
+  else
+    hipLaunchKernelGGL(k_octant<double>, dim3(2048), dim3(256), 0, s, spec, M[0], M[1], K2, scale,
+                       (double*)out);
+  return hipGetLastError();
+}
+
+struct FacePtrs {
+  const void* f[3][2];
+};
+
+template <typename T>
+__global__ void k_dirichlet_fill(T* out, int N0, int N1, int N2, int ndim, FacePtrs fp) {
+  const int N[3] = {N0, N1, N2};
+  const long long total = (long long)N0 * N1 * N2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int c[3];
+    c[2] = (int)(i % N2);
+    c[1] = (int)((i / N2) % N1);
+    c[0] = (int)(i / ((long long)N1 * N2));
+    int axis = -1, side = 0;
+    for (int a = 0; a < ndim; ++a) {
+      if (c[a] == 0) { axis = a; side = 0; }
+      else if (c[a] == N[a] - 1) { axis = a; side = 1; }
+    }
+    if (axis < 0) continue;
+    const T* g = (const T*)fp.f[axis][side];
+    T v = (T)0;
+    if (g) {
+      long long off = 0;
+      for (int b = 0; b < ndim; ++b) {
+        if (b == axis) continue;
+        off = off * N[b] + c[b];
+      }
+      v = g[off];
+    }
+    out[i] = v;
+  }
+}
+
+hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, const void* face[3][2],
+                                 int prec, hipStream_t s) {
+  FacePtrs fp;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 2; ++b) fp.f[a][b] = face[a][b];
+  if (prec == 0)
+    hipLaunchKernelGGL(k_dirichlet_fill<float>, dim3(1024), dim3(256), 0, s, (float*)out, N[0],
+                       N[1], N[2], ndim, fp);
+  else
+    hipLaunchKernelGGL(k_dirichlet_fill<double>, dim3(1024), dim3(256), 0, s, (double*)out, N[0],
+                       N[1], N[2], ndim, fp);
+  return hipGetLastError();
+}
+
+}  // namespace hp

@@ -1,0 +1,83 @@
+// Host-side plan state shared by the C-ABI and the batched solver.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hipoisson.h"
+#include "hp_internal.hpp"
+
+namespace hp {
+
+struct PassRec {
+  PassArgs a;
+  int grid_y;
+};
+
+struct Problem {
+  hp_desc d{};
+  int nd = 0, ncomp = 1, nder = 0;
+  int n[3] = {1, 1, 1};     // unknowns
+  int nout[3] = {1, 1, 1};  // output points
+  int M[3] = {1, 1, 1};     // doubled sizes (unbounded)
+  double h[3] = {1, 1, 1}, len[3] = {1, 1, 1};
+  // bindings (device pointers); slot c < ncomp for f / psi, derivative d
+  const void* in[kMaxFields] = {};
+  void* out[3] = {};
+  void* der[3] = {};
+  const void* face[3][2][3] = {};
+  // plan-owned device memory backing unbound slots
+  void* own_in[kMaxFields] = {};
+  void* own_out[3] = {};
+  void* own_der[3] = {};
+  void* own_face[3][2][3] = {};
+  std::vector<void*> a1, b2;  // unbounded / periodic workspaces
+  double* lam[3] = {};        // eigenvalue tables (bounded)
+  void* kvec[3] = {};         // wavenumber tables
+  void* green = nullptr;      // Ghat octant
+  long long g_s[3] = {0, 0, 0};  // octant strides of i0, i1, k2
+  double norm = 1.0;
+};
+
+}  // namespace hp
+
+struct hp_plan_s {
+  hipStream_t stream = nullptr;
+  int prec = 0;
+  size_t es = 4;  // real element size
+  bool batched = false;
+  bool solved = false;
+  std::vector<hp::Problem> probs;
+  std::vector<void*> allocs;
+  std::map<int, void*> tw;   // L -> W_L table
+  std::map<int, void*> qtw;  // n -> exp(-i pi j / 2n)
+  std::string err;
+  size_t ws_bytes = 0;
+  int alloc_count = 0;
+  int fail_alloc_at = -1;
+  // batched persistent-kernel state
+  void* batch_probs = nullptr;
+  void* batch_items = nullptr;
+  unsigned* batch_counters = nullptr;
+  int batch_nitems = 0, batch_ncounters = 0, batch_grid = 0, batch_lds = 0;
+  std::vector<hp::PassRec> batch_passes;
+  // per-pass timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> ev_solves;
+  size_t ev_used = 0;
+  std::vector<double> pass_bytes;
+  std::vector<const char*> pass_names;
+};
+
+namespace hp {
+// implemented in hp_api.cpp
+hp_status plan_fail(hp_plan p, hp_status s, const std::string& msg);
+hp_status plan_alloc(hp_plan p, size_t bytes, void** out);
+hp_status passes_for(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out);
+double passes_model_bytes(hp_plan p, const std::vector<PassRec>& ps);
+// implemented in hp_batched.cpp
+hp_status batched_setup(hp_plan p);
+hp_status batched_solve(hp_plan p);
+}  // namespace hp

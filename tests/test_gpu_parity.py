@@ -1,0 +1,149 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle, small grids.
+
+Each case draws a seeded source (and boundary values), rounds it to the solve
+precision, runs libhipoisson.so and the oracle on the same values and
+compares every output element: rel-L2 <= 1e-12 / rel-max <= 1e-11 in FP64,
+rel-L2 <= 1e-5 / rel-max <= 1e-4 in FP32.  Sizes span several tiles, odd and
+mixed-radix lengths and ragged last tiles.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from gpu_util import TOL, case_input, gpu_solve, oracle_solve, rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+LO = [0.0, -0.5, 1.0]
+HI = [1.0, 1.3, 2.5]
+
+
+def check(got, ref, prec, what=""):
+    l2, mx = TOL[prec]
+    e2, em = rel_l2(got, ref), rel_max(got, ref)
+    assert e2 <= l2 and em <= mx, f"{what}: rel-L2 {e2:.3e} rel-max {em:.3e}"
+
+
+BOUNDED = []
+for bc, grid, kernel, nd, prec in itertools.product(
+        ["dirichlet", "neumann"], ["regular", "staggered"], ["ps", "fd2"], [1, 2, 3], ["f64", "f32"]):
+    BOUNDED.append((bc, grid, kernel, nd, prec, False))
+    if kernel == "fd2":
+        BOUNDED.append((bc, grid, kernel, nd, prec, True))
+
+
+@pytest.mark.parametrize("bc,grid,kernel,nd,prec,inhom", BOUNDED)
+def test_bounded_small(bc, grid, kernel, nd, prec, inhom):
+    nc = [12, 10, 9][:nd]
+    f, faces = case_input(bc, grid, nc, 1, inhom, prec, seed=nd * 7 + inhom)
+    got, _ = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", prec, 1, faces)
+    ref, _ = oracle_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", faces)
+    check(got, ref, prec, "psi")
+
+
+@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("dirichlet", "staggered"),
+                                     ("neumann", "regular"), ("neumann", "staggered")])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bounded_tiles(bc, grid, prec):
+    nc = [40, 36, 48]
+    f, faces = case_input(bc, grid, nc, 1, True, prec, seed=3)
+    got, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", prec, 1, faces)
+    ref, _ = oracle_solve(bc, grid, nc, LO, HI, f, "fd2", "none", faces)
+    check(got, ref, prec, "psi")
+
+
+@pytest.mark.parametrize("nd,nc", [(1, [12]), (1, [9]), (2, [12, 10]), (2, [9, 15]), (3, [12, 10, 9]),
+                                   (3, [20, 24, 30])])
+@pytest.mark.parametrize("kernel", ["ps", "fd2"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("diff", ["none", "grad"])
+def test_periodic(nd, nc, kernel, prec, diff):
+    f, _ = case_input("periodic", "staggered", nc, 1, False, prec, seed=nd)
+    got, gd = gpu_solve("periodic", "staggered", nc, LO[:nd], HI[:nd], f, kernel, diff, prec, 1, None)
+    ref, rd = oracle_solve("periodic", "staggered", nc, LO[:nd], HI[:nd], f, kernel, diff, None)
+    check(got, ref, prec, "psi")
+    assert len(gd) == len(rd)
+    for a in range(len(rd)):
+        check(gd[a], rd[a], prec, f"grad {a}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nc", [[12, 10, 9], [16, 20, 24]])
+def test_periodic_curl(prec, nc):
+    f, _ = case_input("periodic", "staggered", nc, 3, False, prec, seed=5)
+    got, gd = gpu_solve("periodic", "staggered", nc, LO, HI, f, "ps", "curl", prec, 3, None)
+    ref, rd = oracle_solve("periodic", "staggered", nc, LO, HI, f, "ps", "curl", None)
+    check(got, ref, prec, "psi")
+    for a in range(3):
+        check(gd[a], rd[a], prec, f"curl {a}")
+
+
+UNB = [([8, 10, 12], 1, "none"), ([8, 10, 12], 1, "grad"), ([8, 10, 12], 3, "curl"),
+       ([20, 18, 24], 3, "curl"), ([20, 18, 24], 3, "none"), ([30, 16, 15], 1, "grad"),
+       # power-of-two doubled lengths: wavefront-FFT kernels
+       ([32, 32, 32], 3, "curl"), ([64, 32, 128], 3, "curl"), ([32, 128, 64], 1, "grad"),
+       ([64, 64, 32], 1, "none"), ([512, 32, 32], 1, "none")]
+
+
+@pytest.mark.parametrize("nc,ncomp,diff", UNB)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("grid", ["staggered", "regular"])
+def test_unbounded(nc, ncomp, diff, prec, grid):
+    if prec == "f64" and nc[0] == 512:
+        pytest.skip("one long-axis case")
+    if grid == "regular" and nc[0] != 8:
+        pytest.skip("regular grid: one size")
+    if grid == "regular":
+        nc = [9, 14, 11]  # N_c + 1 nodes -> doubled 20, 30, 24
+    f, _ = case_input("unbounded", grid, nc, ncomp, False, prec, seed=11)
+    got, gd = gpu_solve("unbounded", grid, nc, LO, HI, f, "g2", diff, prec, ncomp, None)
+    ref, rd = oracle_solve("unbounded", grid, nc, LO, HI, f, "g2", diff, None)
+    check(got, ref, prec, "psi")
+    for a in range(len(rd)):
+        check(gd[a], rd[a], prec, f"deriv {a}")
+
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_unbounded_generic_matches_fast(generic, monkeypatch):
+    """The same power-of-two problem through the general passes and the wavefront kernels."""
+    if generic:
+        monkeypatch.setenv("HP_GENERIC", "1")
+    nc = [32, 64, 32]
+    f, _ = case_input("unbounded", "staggered", nc, 3, False, "f32", seed=2)
+    got, gd = gpu_solve("unbounded", "staggered", nc, LO, HI, f, "g2", "curl", "f32", 3, None)
+    ref, rd = oracle_solve("unbounded", "staggered", nc, LO, HI, f, "g2", "curl", None)
+    check(got, ref, "f32", "psi")
+    for a in range(3):
+        check(gd[a], rd[a], "f32", f"curl {a}")
+
+
+@pytest.mark.parametrize("diff,ncomp", [("none", 1), ("grad", 1), ("curl", 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("with_psi", [True, False])
+@pytest.mark.parametrize("nc", [[10, 12, 8], [32, 64, 32]])
+def test_unbounded_adjoint(diff, ncomp, prec, with_psi, nc):
+    import torch
+    from oracle import grid as og
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd import Solver
+    if diff == "none" and not with_psi:
+        pytest.skip("no upstream gradient")
+    rng = np.random.default_rng(21)
+    shape = tuple(nc)
+    rnd = np.float32 if prec == "f32" else np.float64
+    gpsi = rng.normal(size=((ncomp,) + shape) if ncomp == 3 else shape).astype(rnd).astype(np.float64)
+    nder = 3 if diff != "none" else 0
+    gder = [rng.normal(size=shape).astype(rnd).astype(np.float64) for _ in range(nder)]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver("unbounded", "staggered", nc, LO, HI, diff=diff, dtype=dtype, ncomp=ncomp)
+    dev = lambda x: torch.as_tensor(x, dtype=dtype, device="cuda")
+    gp = ([dev(gpsi[c]) for c in range(3)] if ncomp == 3 else [dev(gpsi)]) if with_psi else None
+    gd = [dev(g) for g in gder] if nder else None
+    out = s.adjoint(gp, gd)
+    torch.cuda.synchronize()
+    got = np.stack([o.double().cpu().numpy() for o in out]) if ncomp == 3 else out[0].double().cpu().numpy()
+    hs = [(HI[a] - LO[a]) / nc[a] for a in range(3)]
+    ref = ub.adjoint_unbounded(gpsi if with_psi else None, gder, hs, 2.0 * max(hs), diff)
+    s.close()
+    check(got, ref, prec, "adjoint")

@@ -91,7 +91,9 @@ enum {
   HP_Q_WORKSPACE_BYTES = 2, /* device workspace held by the plan */
   HP_Q_NUM_PASSES = 3,      /* kernel launches of one hp_solve */
   HP_Q_NUM_OUTPUTS = 4,     /* psi components + derivative components */
-  HP_Q_NUM_DERIVS = 5       /* derivative components (gradient or curl) */
+  HP_Q_NUM_DERIVS = 5,      /* derivative components (gradient or curl) */
+  HP_Q_BATCH_ERROR = 6      /* batched plans: 1 if the last solve hit a dependency-wait
+                               limit (results invalid), else 0; synchronises */
 };
 
 /* Create a plan for one problem (the initialisation of Section 3.2.1): grid

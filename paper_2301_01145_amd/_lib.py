@@ -17,6 +17,7 @@ HP_OP_PS, HP_OP_FD2, HP_G_GAUSS2 = 0, 1, 2
 HP_D_NONE, HP_D_GRAD, HP_D_CURL = 0, 1, 2
 HP_F32, HP_F64 = 0, 1
 HP_Q_MODEL_BYTES, HP_Q_WORKSPACE_BYTES, HP_Q_NUM_PASSES, HP_Q_NUM_OUTPUTS, HP_Q_NUM_DERIVS = 1, 2, 3, 4, 5
+HP_Q_BATCH_ERROR = 6
 
 # Every exported function of include/hipoisson.h (checked by the ABI tests).
 EXPORTS = (

@@ -8,6 +8,7 @@
 // are fused into the pass of the last forward axis.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -293,7 +294,7 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
   if (hipMalloc(&g, nreal * 8) != hipSuccess) { (void)hipGetLastError(); return fail(p, HP_E_NOMEM, "Green's grid allocation failed"); }
   if (hipMalloc(&spec, ncplx * 16) != hipSuccess) {
     (void)hipGetLastError();
-    hipFree(g);
+    (void)hipFree(g);
     return fail(p, HP_E_NOMEM, "Green's spectrum allocation failed");
   }
   hp_status st = HP_OK;
@@ -369,12 +370,14 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
   };
   st = run();
   (void)hipStreamSynchronize(p->stream);
-  hipFree(g);
-  hipFree(spec);
+  (void)hipFree(g);
+  (void)hipFree(spec);
   return st;
 }
 
 // ----------------------------------------------------------- plan setup
+bool fast_unbounded_ok(hp_plan p, const Problem& P);
+
 hp_status setup_problem(hp_plan p, Problem& P) {
   const hp_desc& d = P.d;
   P.nd = d.ndim;
@@ -427,12 +430,17 @@ hp_status setup_problem(hp_plan p, Problem& P) {
     HP_TRY(green_spectrum(p, P));
     const int nf = P.ncomp + P.nder;
     const size_t K2 = (size_t)P.M[2] / 2 + 1;
+    const bool fast = fast_unbounded_ok(p, P);
     for (int f = 0; f < nf; ++f) {
       void* b;
       HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2 * P.n[1] * 2 * es, &b));
       P.a1.push_back(b);
       HP_TRY(dev_alloc(p, K2 * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
       P.b2.push_back(b);
+      if (fast) {
+        HP_TRY(dev_alloc(p, K2 * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
+        P.c2.push_back(b);
+      }
     }
   }
   return HP_OK;
@@ -502,7 +510,10 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
     case 5: {  // paired c2c sandwich (1D periodic)
       const int nS = a.n_in;
       a.P = choose_P(want, 2, a.Np, a.L, p->prec,
-                     [&](int q) { return (long long)(nS + 1) * (q / 2) * a.L * cs + (long long)q * a.nin * es; },
+                     [&](int q) {
+                       return (long long)nS * (q / 2) * a.L * cs +
+                              std::max((long long)(q / 2) * a.L * cs, (long long)q * a.nin * es);
+                     },
                      nfft_pair, &lds);
     } break;
   }
@@ -915,42 +926,128 @@ hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<Pass
   return HP_OK;
 }
 
-// Upgrade the general free-space passes to the wavefront-FFT kernels when every
-// doubled length is a power of two in [64, 1024] and the tiles fit in LDS.
-hp_status use_fast_unbounded(hp_plan p, Problem& P, std::vector<PassRec>& ps, size_t first) {
-  if (std::getenv("HP_GENERIC")) return HP_OK;
+// Wavefront-FFT free-space passes (every doubled length a power of two in
+// [64, 1024]).  Layouts (complex): A1 [x][kz][y], B2 [kz][ky][x],
+// C2 [kz][x][ky], C1 [y][x][kz] (C1 reuses the A1 buffers).  Every pass reads
+// contiguous pencils; strided sides are written through LDS tiles.
+bool fast_unbounded_ok(hp_plan p, const Problem& P) {
+  if (std::getenv("HP_GENERIC")) return false;
   auto pow2 = [](int v) { return v >= 64 && v <= 1024 && (v & (v - 1)) == 0; };
   for (int a = 0; a < 3; ++a)
-    if (!pow2(P.M[a])) return HP_OK;
-  const int Pw = p->prec == 0 ? 16 : 8;
+    if (!pow2(P.M[a])) return false;
   const int kinds[5] = {FAST_R2C, FAST_FWD_Y, FAST_SANDWICH, FAST_INV_Y, FAST_C2R};
   const int axisL[5] = {P.M[2], P.M[1], P.M[0], P.M[1], P.M[2]};
   const int K2 = P.M[2] / 2 + 1;
-  for (int i = 0; i < 5; ++i)
-    if (fast_lds_bytes(kinds[i], axisL[i], Pw, K2, p->prec) > 160 * 1024) return HP_OK;
   for (int i = 0; i < 5; ++i) {
-    PassArgs& a = ps[first + i].a;
-    a.fast = kinds[i];
-    a.P = Pw;
-    a.L = axisL[i];
-    const void* tw;
-    HP_TRY(twiddles(p, a.L, &tw));
-    a.tw = tw;
-    a.lds_bytes = fast_lds_bytes(kinds[i], a.L, Pw, K2, p->prec);
+    const int Pt = fast_tile(kinds[i], axisL[i], p->prec);
+    if (fast_lds_bytes(kinds[i], axisL[i], Pt, K2, p->prec) > 160 * 1024) return false;
+  }
+  return true;
+}
+
+hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
+  const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+  const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2];
+  const int K2 = M2 / 2 + 1;
+  const int nc = P.ncomp, nder = P.nder;
+  const double es = (double)p->es, cs = 2.0 * p->es;
+  const void* src[kMaxFields] = {};
+  void* dst[kMaxFields] = {};
+  int n_src, n_dst, n_mid, iy_mode;
+  const int dk = P.d.diff;
+  if (!adjoint) {
+    n_src = nc;
+    n_dst = nc + nder;
+    for (int c = 0; c < nc; ++c) src[c] = P.in[c];
+    for (int f = 0; f < n_dst; ++f) dst[f] = f < nc ? P.out[f] : P.der[f - nc];
+    n_mid = dk == HP_D_CURL ? 5 : (dk == HP_D_GRAD ? 2 : nc);
+    iy_mode = dk == HP_D_CURL ? IY_CURL5 : (dk == HP_D_GRAD ? IY_GRAD2 : IY_PLAIN);
+  } else {
+    n_src = nc + nder;
+    n_dst = nc;
+    for (int f = 0; f < n_src; ++f) src[f] = f < nc ? P.out[f] : P.der[f - nc];
+    for (int c = 0; c < nc; ++c) dst[c] = (void*)P.in[c];
+    n_mid = nc;
+    iy_mode = IY_PLAIN;
+  }
+  int n_live = 0;
+  for (int f = 0; f < n_src; ++f) n_live += src[f] ? 1 : 0;
+  auto base = [&](int kind, int L) -> hp_status {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.n_in = a.n_out = 1;
+    a.fast = kind;
+    a.L = a.n = L;
+    a.P = fast_tile(kind, L, p->prec);
     for (int b = 0; b < 3; ++b) {
       a.un[b] = P.n[b];
       a.gM[b] = P.M[b];
       a.kc[b] = 2.0 * M_PI / (P.M[b] * P.h[b]);
     }
+    const void* tw;
+    HP_TRY(twiddles(p, L, &tw));
+    a.tw = tw;
+    a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec);
+    out.push_back({a, 1});
+    return HP_OK;
+  };
+  // P1: R2C along z into A1
+  HP_TRY(base(FAST_R2C, M2));
+  {
+    PassRec& r = out.back();
+    for (int f = 0; f < n_src; ++f) { r.a.in[f] = src[f]; r.a.out[f] = P.a1[f]; }
+    r.grid_y = n_src;
+    r.bytes = n_live * ((double)n0 * n1 * n2 * es + (double)n0 * K2 * n1 * cs);
+  }
+  // P2: forward C2C along y into B2
+  HP_TRY(base(FAST_FWD_Y, M1));
+  {
+    PassRec& r = out.back();
+    for (int f = 0; f < n_src; ++f) { r.a.in[f] = src[f] ? P.a1[f] : nullptr; r.a.out[f] = P.b2[f]; }
+    r.grid_y = n_src;
+    r.bytes = n_live * ((double)n0 * K2 * n1 * cs + (double)K2 * M1 * n0 * cs);
+  }
+  // P3: sandwich along x into C2
+  HP_TRY(base(FAST_SANDWICH, M0));
+  {
+    PassRec& r = out.back();
+    PassArgs& a = r.a;
+    a.mult = M_GREEN;
+    a.green = P.green;
+    for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+    if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
+    else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
+    for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
+    for (int f = 0; f < n_mid; ++f) a.out[f] = P.c2[f];
+    r.grid_y = a.diff == D_NONE ? nc : 1;
+    const double oct = (double)(M0 / 2 + 1) * (M1 / 2 + 1) * K2 * es;
+    r.bytes = (n_live + n_mid) * (double)K2 * M1 * n0 * cs + oct;
+  }
+  // P4: backward C2C along y (with derivative completion) into C1 (= A1 buffers)
+  HP_TRY(base(FAST_INV_Y, M1));
+  {
+    PassRec& r = out.back();
+    r.a.iy_mode = iy_mode;
+    for (int f = 0; f < n_mid; ++f) r.a.in[f] = P.c2[f];
+    for (int f = 0; f < n_dst; ++f) r.a.out[f] = P.a1[f];
+    r.grid_y = iy_mode == IY_PLAIN ? n_mid : 1;
+    r.bytes = n_mid * (double)K2 * n0 * M1 * cs + n_dst * (double)n1 * n0 * K2 * cs;
+  }
+  // P5: C2R along z into the destination arrays
+  HP_TRY(base(FAST_C2R, M2));
+  {
+    PassRec& r = out.back();
+    for (int f = 0; f < n_dst; ++f) { r.a.in[f] = P.a1[f]; r.a.out[f] = dst[f]; }
+    r.grid_y = n_dst;
+    r.bytes = n_dst * ((double)n1 * n0 * K2 * cs + (double)n0 * n1 * n2 * es);
   }
   return HP_OK;
 }
 
 hp_status build_passes(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
   if (P.d.bc == HP_UNBOUNDED) {
-    const size_t first = out.size();
-    HP_TRY(passes_unbounded(p, P, adjoint, out));
-    return use_fast_unbounded(p, P, out, first);
+    if (fast_unbounded_ok(p, P)) return passes_unbounded_fast(p, P, adjoint, out);
+    return passes_unbounded(p, P, adjoint, out);
   }
   if (adjoint) return fail(p, HP_E_UNSUPPORTED, "adjoint solve is provided for unbounded plans");
   if (P.d.bc == HP_PERIODIC) return passes_periodic(p, P, out);
@@ -963,6 +1060,10 @@ double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
   double b = 0.0;
   const double es = (double)p->es;
   for (auto& r : ps) {
+    if (r.bytes >= 0.0) {
+      b += r.bytes;
+      continue;
+    }
     const PassArgs& a = r.a;
     const double pencils = (double)a.Np * a.No;
     auto elem_in = [&](int x) {
@@ -1098,7 +1199,7 @@ hp_status create(const hp_desc* descs, int count, hp_stream stream, hp_plan* out
   }
   if (st != HP_OK) {
     g_create_error = p->err;
-    for (void* a : p->allocs) hipFree(a);
+    for (void* a : p->allocs) (void)hipFree(a);
     delete p;
     return st;
   }
@@ -1325,6 +1426,15 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
     case HP_Q_NUM_DERIVS:
       *value = P.nder;
       return HP_OK;
+    case HP_Q_BATCH_ERROR: {
+      if (!plan->batched) return fail(plan, HP_E_ARG, "not a batched plan");
+      int err = 0;
+      HP_HIP(plan, hipStreamSynchronize(plan->stream));
+      HP_HIP(plan, hipMemcpy(&err, plan->batch_counters + plan->batch_ncounters, sizeof(int),
+                             hipMemcpyDeviceToHost));
+      *value = err;
+      return HP_OK;
+    }
     case HP_Q_MODEL_BYTES:
     case HP_Q_NUM_PASSES: {
       if (plan->batched) {

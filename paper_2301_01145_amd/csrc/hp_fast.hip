@@ -17,6 +17,8 @@
 // Layouts (complex elements):  A1 [x][kz][y],  B2 [kz][ky][x];  user fields
 // [x][y][z] real.  Passes whose pencil is strided in memory stage a tile of P
 // pencils through LDS so that global accesses are runs of P elements.
+#include <cstdlib>
+
 #include "hp_device.hpp"
 #include "hp_internal.hpp"
 
@@ -100,26 +102,33 @@ __device__ __forceinline__ int signed_index(int m, int M) {
 // Rows (x, y) of the real source, z < n2 of L = M2; pairs of rows (y, y+1)
 // form one complex FFT; the half spectrum is untangled and written to
 // A1[x][kz][y] through a [K2][P] tile.
+template <int L, int P>
+struct R2CShape {
+  static constexpr int NW = (P / 2 + WF<L>::PPW - 1) / WF<L>::PPW;  // wavefronts
+  static constexpr int NT = 64 * NW;
+};
+
 template <typename T, int L, int P>
-__global__ void __launch_bounds__(kThreads) kf_r2c(const PassArgs a) {
+__global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   constexpr int K2 = L / 2 + 1, TS = P + 1;
+  constexpr int NW = R2CShape<L, P>::NW, NT = R2CShape<L, P>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
-  C2<T>* tile = exch + 4 * PPW * L;
+  C2<T>* tile = exch + NW * PPW * L;
   const T* in = (const T*)a.in[blockIdx.y];
   C2<T>* out = (C2<T>*)a.out[blockIdx.y];
   if (!in) return;
   const int n0 = a.un[0], n1 = a.un[1], n2 = a.un[2];
   const int ytiles = (n1 + P - 1) / P;
   const int x = blockIdx.x / ytiles, y0 = (blockIdx.x % ytiles) * P;
-  load_tw<T, L>(tw, a.tw);
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   C2<T>* buf = exch + (wave * PPW + q) * L;
-  for (int pr0 = wave * PPW; pr0 < P / 2; pr0 += 4 * PPW) {
+  for (int pr0 = wave * PPW; pr0 < P / 2; pr0 += NW * PPW) {
     const int pr = pr0 + q;
     const int ya = y0 + 2 * pr, yb = ya + 1;
     const bool va = pr < P / 2 && ya < n1, vb = pr < P / 2 && yb < n1;
@@ -155,7 +164,7 @@ __global__ void __launch_bounds__(kThreads) kf_r2c(const PassArgs a) {
   }
   __syncthreads();
   const long long obase = (long long)x * K2 * n1 + y0;
-  for (int e = threadIdx.x; e < K2 * P; e += kThreads) {
+  for (int e = threadIdx.x; e < K2 * P; e += NT) {
     const int k = e / P, c = e - (e / P) * P;
     if (y0 + c < n1) out[obase + (long long)k * n1 + c] = tile[k * TS + c];
   }
@@ -166,9 +175,9 @@ __global__ void __launch_bounds__(kThreads) kf_r2c(const PassArgs a) {
 // Pencils (x, kz) of A1, y < n1 of L = M1, written to B2[kz][ky][x] through a
 // [L][P] tile whose columns double as the FFT exchange slots.
 template <typename T, int L, int P>
-__global__ void __launch_bounds__(kThreads) kf_fwd_y(const PassArgs a) {
+__global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
-  constexpr int TS = P + 1;
+  constexpr int TS = P + 1, NT = 64 * (P / PPW);
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* tile = tw + L;
@@ -179,11 +188,12 @@ __global__ void __launch_bounds__(kThreads) kf_fwd_y(const PassArgs a) {
   const int K2 = a.gM[2] / 2 + 1;
   const int xtiles = (n0 + P - 1) / P;
   const int kz = blockIdx.x / xtiles, x0 = (blockIdx.x % xtiles) * P;
-  load_tw<T, L>(tw, a.tw);
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  for (int pp = wave * PPW; pp < P; pp += 4 * PPW) {
+  {
+    const int pp = wave * PPW;
     const int p = pp + q;
     const bool valid = p < P && x0 + p < n0;
     const C2<T>* src = in + ((long long)(x0 + p) * K2 + kz) * n1;
@@ -203,292 +213,341 @@ __global__ void __launch_bounds__(kThreads) kf_fwd_y(const PassArgs a) {
   }
   __syncthreads();
   const long long obase = (long long)kz * L * n0 + x0;
-  for (int e = threadIdx.x; e < L * P; e += kThreads) {
+  for (int e = threadIdx.x; e < L * P; e += NT) {
     const int ky = e / P, c = e - (e / P) * P;
     if (x0 + c < n0) out[obase + (long long)ky * n0 + c] = tile[ky * TS + c];
   }
 }
 
 // --------------------------------------------------------- P3: sandwich (x)
-// Pencils (ky, kz) of B2, x < n0 of L = M0: forward FFT, Ghat multiply,
-// spectral derivative, backward FFT, x < n0 stored, all in registers.
-template <typename T, int L>
-__global__ void __launch_bounds__(kThreads) kf_sandwich(const PassArgs a) {
+// A workgroup takes P consecutive pencils (ky0 .. ky0+P-1, kz) of
+// B2[kz][ky][x], one (or PPW) per wavefront.  Each wavefront does the forward
+// FFT (x < n0 of L = M0 nonzero), the Green's multiply and the x-derivative in
+// registers; every output field is transformed back and written, x < n0, to an
+// [L][P] LDS tile whose columns are also the FFT exchange slots, then stored as
+// runs of P along ky into C2[kz][x][ky] (the next pass reads its y-pencils
+// contiguously).  Outputs: psi and, for the curl, A = -d_x psi_z and
+// B = d_x psi_y (the y and z derivatives are applied by the y pass); for the
+// gradient, psi and d_x psi.
+template <typename T, int L, int P, bool ADJ>
+__global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
+  constexpr int NT = 64 * (P / PPW), TS = P + 1, NX = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
-  C2<T>* exch = tw + L;
-  const int n0 = a.un[0];
-  const int M1 = a.gM[1], M2 = a.gM[2], K2 = M2 / 2 + 1;
-  load_tw<T, L>(tw, a.tw);
+  C2<T>* tile = tw + L;
+  const int M1 = a.gM[1], M2 = a.gM[2];
+  const int ytiles = M1 / P;
+  const int kz = blockIdx.x / ytiles, ky0 = (blockIdx.x % ytiles) * P;
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  C2<T>* buf = exch + (wave * PPW + q) * L;
-  const long long total = (long long)M1 * K2;
+  const int p = wave * PPW + q;
+  const int ky = ky0 + p;
+  C2<T>* col = tile + p;
+  const long long ibase = ((long long)kz * M1 + ky) * NX;
+  const long long obase = (long long)kz * NX * M1 + ky0;
   const int fb = a.diff == D_NONE ? (int)blockIdx.y : 0;
-  const T* gtab = (const T*)a.green;
-
-  auto load = [&](C2<T> (&v)[R0], const void* src, long long base, bool valid) {
-    const C2<T>* s = (const C2<T>*)src;
-#pragma unroll
-    for (int i = 0; i < R0; ++i) {
-      v[i] = {(T)0, (T)0};
-      if (i < R0 / 2 && valid) v[i] = s[base + g + G * i];
-    }
-  };
-  auto store = [&](const C2<T> (&v)[R0], void* dst, long long base, bool valid) {
-    C2<T>* d = (C2<T>*)dst;
-    if (!valid) return;
-#pragma unroll
-    for (int i = 0; i < R0 / 2; ++i) d[base + g + G * i] = v[i];
-  };
-
-  for (long long grp = (long long)blockIdx.x * 4 + wave; grp * PPW < total;
-       grp += (long long)gridDim.x * 4) {
-    const long long pen = grp * PPW + q;
-    const bool valid = pen < total;
-    const int ky = valid ? (int)(pen % M1) : 0;
-    const int kz = valid ? (int)(pen / M1) : 0;
-    const long long base = ((long long)kz * M1 + ky) * n0;
-    // Green's spectrum along the pencil and the wavenumbers
-    const int i1 = min(ky, M1 - ky);
-    const T* grow = gtab + (long long)kz * a.g_s[2] + (long long)i1 * a.g_s[1];
-    T gv[R0], kx[R0];
+  const T* grow = (const T*)a.green + (long long)kz * a.g_s[2] +
+                  (long long)min(ky, M1 - ky) * a.g_s[1];
+  const T kyv = (T)(a.kc[1] * signed_index(ky, M1));
+  const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
+  auto kx = [&](int i) -> T { return (T)(a.kc[0] * signed_index(g + G * i, L)); };
+  auto kcomp = [&](int c, int i) -> T { return c == 0 ? kx(i) : (c == 1 ? kyv : kzv); };
+  auto green = [&](C2<T> (&v)[R0]) {
 #pragma unroll
     for (int i = 0; i < R0; ++i) {
       const int k0 = g + G * i;
-      gv[i] = grow[min(k0, L - k0)];
-      kx[i] = (T)(a.kc[0] * signed_index(k0, L));
+      v[i] = cscale(v[i], grow[min(k0, L - k0)]);
     }
-    const T kyv = (T)(a.kc[1] * signed_index(ky, M1));
-    const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
-    auto kcomp = [&](int c, int i) -> T { return c == 0 ? kx[i] : (c == 1 ? kyv : kzv); };
+  };
+  // forward FFT of the pencil of field `src` (x < n0 nonzero)
+  auto load = [&](C2<T> (&v)[R0], const void* src) {
+    const C2<T>* sp = (const C2<T>*)src + ibase;
+#pragma unroll
+    for (int i = 0; i < R0; ++i) v[i] = i < R0 / 2 ? sp[g + G * i] : C2<T>{(T)0, (T)0};
+    wave_fft<T, L, false>(v, col, TS, g, tw);
+  };
+  // backward FFT, x < n0 of every pencil to the tile, stored along ky
+  auto emit = [&](C2<T> (&v)[R0], void* dst) {
+    wave_fft<T, L, true>(v, col, TS, g, tw);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < R0 / 2; ++i) col[(g + G * i) * TS] = v[i];
+    __syncthreads();
+    C2<T>* d = (C2<T>*)dst + obase;
+    for (int e = threadIdx.x; e < NX * P; e += NT) {
+      const int x = e / P, c = e - (e / P) * P;
+      d[(long long)x * M1 + c] = tile[x * TS + c];
+    }
+    __syncthreads();
+  };
 
-    if (a.diff == D_NONE) {
+  if (a.diff == D_NONE) {
+    C2<T> v[R0];
+    load(v, a.in[fb]);
+    green(v);
+    emit(v, a.out[fb]);
+  } else if (!ADJ && a.diff == D_CURL) {
+    // component by component: psi_c, plus B = d_x psi_y and A = -d_x psi_z
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
       C2<T> v[R0];
-      load(v, a.in[fb], base, valid);
-      wave_fft<T, L, false>(v, buf, 1, g, tw);
+      load(v, a.in[c]);
+      green(v);
+      if (c > 0) {
+        C2<T> u[R0];
+        const T sgn = c == 1 ? (T)1 : (T)-1;
 #pragma unroll
-      for (int i = 0; i < R0; ++i) v[i] = cscale(v[i], gv[i]);
-      wave_fft<T, L, true>(v, buf, 1, g, tw);
-      store(v, a.out[fb], base, valid);
-    } else if (a.diff == D_CURL || a.diff == D_ADJ_CURL) {
-      C2<T> S[3][R0];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (a.in[c]) {
-          load(S[c], a.in[c], base, valid);
-          wave_fft<T, L, false>(S[c], buf, 1, g, tw);
-        } else {
-#pragma unroll
-          for (int i = 0; i < R0; ++i) S[c][i] = {(T)0, (T)0};
-        }
+        for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
+        emit(u, a.out[c == 1 ? 4 : 3]);
       }
-      if (a.diff == D_ADJ_CURL) {
-        // the curl is symmetric: g_i enters S_{i+1} with +i k_{i+2}, S_{i+2} with -i k_{i+1}
+      emit(v, a.out[c]);
+    }
+  } else if (ADJ && a.diff == D_ADJ_CURL) {
+    C2<T> S[3][R0];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (!a.in[3 + c]) continue;
-          C2<T> w[R0];
-          load(w, a.in[3 + c], base, valid);
-          wave_fft<T, L, false>(w, buf, 1, g, tw);
-          const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-#pragma unroll
-          for (int i = 0; i < R0; ++i) {
-            const C2<T> iw = cmuli(w[i]);
-            S[c1][i] = cadd(S[c1][i], cscale(iw, kcomp(c2, i)));
-            S[c2][i] = csub(S[c2][i], cscale(iw, kcomp(c1, i)));
-          }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < R0; ++i) S[c][i] = cscale(S[c][i], gv[i]);
-      if (a.diff == D_CURL) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const int c1 = (d + 1) % 3, c2 = (d + 2) % 3;
-          C2<T> u[R0];
-#pragma unroll
-          for (int i = 0; i < R0; ++i)
-            u[i] = cmuli(csub(cscale(S[c2][i], kcomp(c1, i)), cscale(S[c1][i], kcomp(c2, i))));
-          wave_fft<T, L, true>(u, buf, 1, g, tw);
-          store(u, a.out[3 + d], base, valid);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        wave_fft<T, L, true>(S[c], buf, 1, g, tw);
-        store(S[c], a.out[c], base, valid);
-      }
-    } else {  // D_GRAD / D_ADJ_GRAD on a scalar
-      C2<T> S[R0];
-      if (a.in[0]) {
-        load(S, a.in[0], base, valid);
-        wave_fft<T, L, false>(S, buf, 1, g, tw);
+    for (int c = 0; c < 3; ++c) {
+      if (a.in[c]) {
+        load(S[c], a.in[c]);
       } else {
 #pragma unroll
-        for (int i = 0; i < R0; ++i) S[i] = {(T)0, (T)0};
+        for (int i = 0; i < R0; ++i) S[c][i] = {(T)0, (T)0};
       }
-      if (a.diff == D_ADJ_GRAD) {
-        // transpose of the gradient: minus the divergence
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (!a.in[1 + c]) continue;
-          C2<T> w[R0];
-          load(w, a.in[1 + c], base, valid);
-          wave_fft<T, L, false>(w, buf, 1, g, tw);
-#pragma unroll
-          for (int i = 0; i < R0; ++i) S[i] = csub(S[i], cscale(cmuli(w[i]), kcomp(c, i)));
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < R0; ++i) S[i] = cscale(S[i], gv[i]);
-      if (a.diff == D_GRAD) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          C2<T> u[R0];
-#pragma unroll
-          for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(S[i]), kcomp(c, i));
-          wave_fft<T, L, true>(u, buf, 1, g, tw);
-          store(u, a.out[1 + c], base, valid);
-        }
-      }
-      wave_fft<T, L, true>(S, buf, 1, g, tw);
-      store(S, a.out[0], base, valid);
     }
+    // the curl is symmetric: g_i enters S_{i+1} with +i k_{i+2}, S_{i+2} with -i k_{i+1}
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (!a.in[3 + c]) continue;
+      C2<T> w[R0];
+      load(w, a.in[3 + c]);
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+#pragma unroll
+      for (int i = 0; i < R0; ++i) {
+        const C2<T> iw = cmuli(w[i]);
+        S[c1][i] = cadd(S[c1][i], cscale(iw, kcomp(c2, i)));
+        S[c2][i] = csub(S[c2][i], cscale(iw, kcomp(c1, i)));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      green(S[c]);
+      emit(S[c], a.out[c]);
+    }
+  } else {  // scalar gradient and its transpose
+    C2<T> S[R0];
+    if (a.in[0]) {
+      load(S, a.in[0]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < R0; ++i) S[i] = {(T)0, (T)0};
+    }
+    if (ADJ) {
+      // transpose of the gradient: minus the divergence
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (!a.in[1 + c]) continue;
+        C2<T> w[R0];
+        load(w, a.in[1 + c]);
+#pragma unroll
+        for (int i = 0; i < R0; ++i) S[i] = csub(S[i], cscale(cmuli(w[i]), kcomp(c, i)));
+      }
+    }
+    green(S);
+    if (!ADJ) {
+      C2<T> u[R0];
+#pragma unroll
+      for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(S[i]), kx(i));
+      emit(u, a.out[1]);
+    }
+    emit(S, a.out[0]);
   }
 }
 
 // ------------------------------------------------------- P4: backward C2C (y)
-// B2[kz][ky][x] -> B2[kz][y][x] (y < n1), in place, through a [L][P] tile.
+// A workgroup takes P consecutive pencils (x, kz0 .. kz0+P-1) of C2[kz][x][ky]
+// (each contiguous, all M1 wavenumbers), transforms them back along y and keeps
+// y < n1, written through an [L][P] tile (columns = FFT exchange slots) as runs
+// of P along kz into C1[y][x][kz].  In curl mode the five inputs psi_x, psi_y,
+// psi_z, A, B give psi and u = curl psi (u_x = d_y psi_z - d_z psi_y,
+// u_y = d_z psi_x + A, u_z = B - d_y psi_x); in gradient mode psi, d_x psi give
+// psi and grad psi.  At most two spectra are live per lane.
 template <typename T, int L, int P>
-__global__ void __launch_bounds__(kThreads) kf_inv_y(const PassArgs a) {
+__global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
-  constexpr int TS = P + 1;
+  constexpr int NT = 64 * (P / PPW), TS = P + 1, NY = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* tile = tw + L;
-  const C2<T>* in = (const C2<T>*)a.in[blockIdx.y];
-  C2<T>* out = (C2<T>*)a.out[blockIdx.y];
-  if (!in) return;
-  const int n0 = a.un[0], n1 = a.un[1];
-  const int xtiles = (n0 + P - 1) / P;
-  const int kz = blockIdx.x / xtiles, x0 = (blockIdx.x % xtiles) * P;
-  load_tw<T, L>(tw, a.tw);
-  const long long base = (long long)kz * L * n0 + x0;
-  for (int e = threadIdx.x; e < L * P; e += kThreads) {
-    const int ky = e / P, c = e - (e / P) * P;
-    C2<T> v = {(T)0, (T)0};
-    if (x0 + c < n0) v = in[base + (long long)ky * n0 + c];
-    tile[ky * TS + c] = v;
-  }
+  const int n0 = a.un[0];
+  const int M2 = a.gM[2], K2 = M2 / 2 + 1;
+  const int ztiles = (K2 + P - 1) / P;
+  const int x = blockIdx.x / ztiles, kz0 = (blockIdx.x % ztiles) * P;
+  for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  for (int pp = wave * PPW; pp < P; pp += 4 * PPW) {
-    const int p = pp + q;
-    C2<T>* col = tile + (p < P ? p : 0);
-    C2<T> v[R0];
+  const int p = wave * PPW + q;
+  const int kz = kz0 + p;
+  const bool valid = kz < K2;
+  C2<T>* col = tile + p;
+  const long long ibase = ((long long)(valid ? kz : 0) * n0 + x) * L;
+  const long long obase = (long long)x * K2 + kz0;
+  const int nvalid = min(P, K2 - kz0);
+  auto kyv = [&](int i) -> T { return (T)(a.kc[1] * signed_index(g + G * i, L)); };
+  const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
+
+  auto load = [&](C2<T> (&v)[R0], const void* src) {
+    const C2<T>* sp = (const C2<T>*)src + ibase;
 #pragma unroll
-    for (int i = 0; i < R0; ++i) v[i] = col[(g + G * i) * TS];
+    for (int i = 0; i < R0; ++i) v[i] = valid ? sp[g + G * i] : C2<T>{(T)0, (T)0};
+  };
+  auto emit = [&](C2<T> (&v)[R0], void* dst) {
     wave_fft<T, L, true>(v, col, TS, g, tw);
-    if (p < P) {
-#pragma unroll
-      for (int i = 0; i < R0 / 2; ++i) col[(g + G * i) * TS] = v[i];
-    }
     wave_sync();
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < n1 * P; e += kThreads) {
-    const int y = e / P, c = e - (e / P) * P;
-    if (x0 + c < n0) out[base + (long long)y * n0 + c] = tile[y * TS + c];
+#pragma unroll
+    for (int i = 0; i < R0 / 2; ++i) col[(g + G * i) * TS] = v[i];
+    __syncthreads();
+    C2<T>* d = (C2<T>*)dst + obase;
+    for (int e = threadIdx.x; e < NY * P; e += NT) {
+      const int y = e / P, c = e - (e / P) * P;
+      if (c < nvalid) d[(long long)y * n0 * K2 + c] = tile[y * TS + c];
+    }
+    __syncthreads();
+  };
+
+  if (a.iy_mode == IY_PLAIN) {
+    C2<T> v[R0];
+    load(v, a.in[blockIdx.y]);
+    emit(v, a.out[blockIdx.y]);
+  } else if (a.iy_mode == IY_CURL5) {
+    C2<T> s[R0], w[R0];
+    load(s, a.in[2]);  // psi_z
+#pragma unroll
+    for (int i = 0; i < R0; ++i) w[i] = cscale(cmuli(s[i]), kyv(i));  // d_y psi_z
+    emit(s, a.out[2]);
+    load(s, a.in[1]);  // psi_y
+#pragma unroll
+    for (int i = 0; i < R0; ++i) w[i] = csub(w[i], cscale(cmuli(s[i]), kzv));  // - d_z psi_y
+    emit(w, a.out[3]);
+    emit(s, a.out[1]);
+    load(s, a.in[0]);  // psi_x
+    load(w, a.in[3]);  // A
+#pragma unroll
+    for (int i = 0; i < R0; ++i) w[i] = cadd(w[i], cscale(cmuli(s[i]), kzv));  // d_z psi_x + A
+    emit(w, a.out[4]);
+    load(w, a.in[4]);  // B
+#pragma unroll
+    for (int i = 0; i < R0; ++i) w[i] = csub(w[i], cscale(cmuli(s[i]), kyv(i)));  // B - d_y psi_x
+    emit(w, a.out[5]);
+    emit(s, a.out[0]);
+  } else {  // IY_GRAD2
+    C2<T> s[R0], w[R0];
+    load(s, a.in[0]);
+#pragma unroll
+    for (int i = 0; i < R0; ++i) w[i] = cscale(cmuli(s[i]), kyv(i));
+    emit(w, a.out[2]);
+#pragma unroll
+    for (int i = 0; i < R0; ++i) w[i] = cscale(cmuli(s[i]), kzv);
+    emit(w, a.out[3]);
+    emit(s, a.out[0]);
+    load(w, a.in[1]);
+    emit(w, a.out[1]);
   }
 }
 
 // --------------------------------------------------------------- P5: C2R (z)
-// Half spectra B2[kz][y][x] (kz < K2) of pencils (x, y) through a [K2][P]
-// tile; pairs of pencils form one complex inverse FFT; z < n2 stored into the
-// real output [x][y][z].
-template <typename T, int L, int P>
+// Half spectra C1[y][x][kz] (kz < K2, contiguous) of pencils (x, y) and
+// (x + 1, y) form one complex inverse FFT (Hermitian completion); z < n2 of
+// both rows is stored into the real output [x][y][z].
+template <typename T, int L>
 __global__ void __launch_bounds__(kThreads) kf_c2r(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
-  constexpr int K2 = L / 2 + 1, TS = P + 1;
+  constexpr int K2 = L / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
-  C2<T>* tile = exch + 4 * PPW * L;
   const C2<T>* in = (const C2<T>*)a.in[blockIdx.y];
   T* out = (T*)a.out[blockIdx.y];
   if (!in) return;
   const int n0 = a.un[0], n1 = a.un[1], n2 = a.un[2];
-  const int M1 = a.gM[1];
-  const int xtiles = (n0 + P - 1) / P;
-  const int y = blockIdx.x / xtiles, x0 = (blockIdx.x % xtiles) * P;
   load_tw<T, L>(tw, a.tw);
-  const long long ibase = (long long)y * n0 + x0;
-  for (int e = threadIdx.x; e < K2 * P; e += kThreads) {
-    const int k = e / P, c = e - (e / P) * P;
-    C2<T> v = {(T)0, (T)0};
-    if (x0 + c < n0) v = in[ibase + (long long)k * M1 * n0 + c];
-    tile[k * TS + c] = v;
-  }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   C2<T>* buf = exch + (wave * PPW + q) * L;
-  for (int pr0 = wave * PPW; pr0 < P / 2; pr0 += 4 * PPW) {
-    const int pr = pr0 + q;
-    const int ca = 2 * (pr < P / 2 ? pr : 0), cb = ca + 1;
+  const int xpairs = (n0 + 1) / 2;
+  const long long total = (long long)n1 * xpairs;
+  for (long long grp = (long long)blockIdx.x * 4 + wave; grp * PPW < total;
+       grp += (long long)gridDim.x * 4) {
+    const long long pr = grp * PPW + q;
+    const bool valid = pr < total;
+    const int y = valid ? (int)(pr / xpairs) : 0;
+    const int xa = valid ? 2 * (int)(pr % xpairs) : 0, xb = xa + 1;
+    const bool vb = valid && xb < n0;
+    const C2<T>* pa = in + ((long long)y * n0 + xa) * K2;
+    const C2<T>* pb = pa + K2;
     C2<T> v[R0];
 #pragma unroll
     for (int i = 0; i < R0; ++i) {
       const int m = g + G * i;
-      C2<T> A, B;
-      if (m <= L / 2) {
-        A = tile[m * TS + ca];
-        B = tile[m * TS + cb];
-        if (m == 0 || m == L / 2) {
-          A.im = (T)0;
-          B.im = (T)0;
-        }
-      } else {
-        A = cconj(tile[(L - m) * TS + ca]);
-        B = cconj(tile[(L - m) * TS + cb]);
+      const int mm = m <= L / 2 ? m : L - m;
+      C2<T> A = {(T)0, (T)0}, B = {(T)0, (T)0};
+      if (valid) A = pa[mm];
+      if (vb) B = pb[mm];
+      if (m == 0 || m == L / 2) {
+        A.im = (T)0;
+        B.im = (T)0;
+      } else if (m > L / 2) {
+        A = cconj(A);
+        B = cconj(B);
       }
       v[i] = {A.re - B.im, A.im + B.re};
     }
     wave_fft<T, L, true>(v, buf, 1, g, tw);
-    const int xa = x0 + ca, xb = xa + 1;
-    const bool va = pr < P / 2 && xa < n0, vb = pr < P / 2 && xb < n0;
     T* oa = out + ((long long)xa * n1 + y) * n2;
     T* ob = out + ((long long)xb * n1 + y) * n2;
 #pragma unroll
     for (int i = 0; i < R0 / 2; ++i) {
-      if (va) oa[g + G * i] = v[i].re;
+      if (valid) oa[g + G * i] = v[i].re;
       if (vb) ob[g + G * i] = v[i].im;
     }
   }
 }
 
 // ---------------------------------------------------------------- launch
+// Pencils per workgroup (runs of P elements on the strided side of a pass):
+// FP32 8 or 16 per pass, FP64 8.  One-pencil kernels (C2R) take no tile.
+int fast_tile(int fast, int L, int prec) {
+  if (fast == FAST_C2R) return 2;
+  if (prec != 0) return 8;
+  if ((fast == FAST_SANDWICH || fast == FAST_INV_Y) && L >= 1024) return 8;
+  static const char* env[] = {"", "HP_TILE_R2C", "HP_TILE_FWDY", "HP_TILE_SAND", "HP_TILE_INVY"};
+  if (const char* t = std::getenv(env[fast])) {
+    const int v = std::atoi(t);
+    if (v == 8 || v == 16) return v;
+  }
+  // measured on MI355X at 256^3 (doubled 512^3): narrower tiles (more
+  // workgroups per CU) win except in the backward y pass
+  return fast == FAST_SANDWICH ? 8 : 16;
+}
+
 int fast_lds_bytes(int fast, int L, int P, int K2, int prec) {
   const int cs = prec == 0 ? 8 : 16;
   const int R0 = L >= 1024 ? 16 : 8;
-  const int exch = 4 * (64 / (L / R0)) * L;
+  const int ppw = 64 / (L / R0);
+  const int exch4 = 4 * ppw * L;
   switch (fast) {
-    case FAST_R2C:
-    case FAST_C2R: return (L + exch + K2 * (P + 1)) * cs;
+    case FAST_R2C: return (L + ((P / 2 + ppw - 1) / ppw) * ppw * L + K2 * (P + 1)) * cs;
     case FAST_FWD_Y:
+    case FAST_SANDWICH:
     case FAST_INV_Y: return (L + L * (P + 1)) * cs;
-    case FAST_SANDWICH: return (L + exch) * cs;
+    case FAST_C2R: return (L + exch4) * cs;
     default: return 0;
   }
 }
 
-// Allow up to the full 160 KB of LDS for a kernel (once per instantiation).
 template <auto K>
 static void allow_lds() {
   static bool done = false;  // one flag per kernel instantiation
@@ -500,36 +559,37 @@ static void allow_lds() {
 }
 
 template <typename T, int L, int P>
-static hipError_t launch_L(const PassArgs& a, int grid_y, hipStream_t s) {
+static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
   const int n0 = a.un[0], n1 = a.un[1];
+  const int K2 = a.gM[2] / 2 + 1;
   const int lds = a.lds_bytes;
   switch (a.fast) {
     case FAST_R2C: {
       dim3 grid(((n1 + P - 1) / P) * n0, grid_y);
       allow_lds<kf_r2c<T, L, P>>();
-      hipLaunchKernelGGL((kf_r2c<T, L, P>), grid, dim3(kThreads), lds, s, a);
+      hipLaunchKernelGGL((kf_r2c<T, L, P>), grid, dim3(R2CShape<L, P>::NT), lds, s, a);
     } break;
     case FAST_FWD_Y: {
-      dim3 grid(((n0 + P - 1) / P) * (a.gM[2] / 2 + 1), grid_y);
+      dim3 grid(((n0 + P - 1) / P) * K2, grid_y);
       allow_lds<kf_fwd_y<T, L, P>>();
-      hipLaunchKernelGGL((kf_fwd_y<T, L, P>), grid, dim3(kThreads), lds, s, a);
+      hipLaunchKernelGGL((kf_fwd_y<T, L, P>), grid, dim3(64 * (P / WF<L>::PPW)), lds, s, a);
     } break;
     case FAST_SANDWICH: {
-      const long long total = (long long)a.gM[1] * (a.gM[2] / 2 + 1);
-      const long long groups = (total + WF<L>::PPW - 1) / WF<L>::PPW;
-      dim3 grid((unsigned)((groups + 3) / 4), grid_y);
-      allow_lds<kf_sandwich<T, L>>();
-      hipLaunchKernelGGL((kf_sandwich<T, L>), grid, dim3(kThreads), lds, s, a);
+      constexpr int NT = 64 * (P / WF<L>::PPW);
+      dim3 grid((a.gM[1] / P) * K2, grid_y);
+      if (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) {
+        allow_lds<kf_sandwich<T, L, P, true>>();
+        hipLaunchKernelGGL((kf_sandwich<T, L, P, true>), grid, dim3(NT), lds, s, a);
+      } else {
+        allow_lds<kf_sandwich<T, L, P, false>>();
+        hipLaunchKernelGGL((kf_sandwich<T, L, P, false>), grid, dim3(NT), lds, s, a);
+      }
     } break;
     case FAST_INV_Y: {
-      dim3 grid(((n0 + P - 1) / P) * (a.gM[2] / 2 + 1), grid_y);
+      constexpr int NT = 64 * (P / WF<L>::PPW);
+      dim3 grid(((K2 + P - 1) / P) * n0, grid_y);
       allow_lds<kf_inv_y<T, L, P>>();
-      hipLaunchKernelGGL((kf_inv_y<T, L, P>), grid, dim3(kThreads), lds, s, a);
-    } break;
-    case FAST_C2R: {
-      dim3 grid(((n0 + P - 1) / P) * n1, grid_y);
-      allow_lds<kf_c2r<T, L, P>>();
-      hipLaunchKernelGGL((kf_c2r<T, L, P>), grid, dim3(kThreads), lds, s, a);
+      hipLaunchKernelGGL((kf_inv_y<T, L, P>), grid, dim3(NT), lds, s, a);
     } break;
     default:
       return hipErrorInvalidValue;
@@ -537,25 +597,39 @@ static hipError_t launch_L(const PassArgs& a, int grid_y, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int P>
+template <typename T, int L>
+static hipError_t launch_L(const PassArgs& a, int grid_y, hipStream_t s) {
+  if (a.fast == FAST_C2R) {
+    const int n0 = a.un[0], n1 = a.un[1];
+    const long long pairs = (long long)n1 * ((n0 + 1) / 2);
+    const long long groups = (pairs + WF<L>::PPW - 1) / WF<L>::PPW;
+    dim3 grid((unsigned)((groups + 3) / 4), grid_y);
+    allow_lds<kf_c2r<T, L>>();
+    hipLaunchKernelGGL((kf_c2r<T, L>), grid, dim3(kThreads), a.lds_bytes, s, a);
+    return hipGetLastError();
+  }
+  if (a.P == 8) return launch_LP<T, L, 8>(a, grid_y, s);
+  if constexpr (sizeof(T) == 4 && L < 1024) {
+    if (a.P == 16) return launch_LP<T, L, 16>(a, grid_y, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
 static hipError_t launch_T(const PassArgs& a, int grid_y, hipStream_t s) {
   switch (a.L) {
-    case 64: return launch_L<T, 64, P>(a, grid_y, s);
-    case 128: return launch_L<T, 128, P>(a, grid_y, s);
-    case 256: return launch_L<T, 256, P>(a, grid_y, s);
-    case 512: return launch_L<T, 512, P>(a, grid_y, s);
-    case 1024: return launch_L<T, 1024, P>(a, grid_y, s);
+    case 64: return launch_L<T, 64>(a, grid_y, s);
+    case 128: return launch_L<T, 128>(a, grid_y, s);
+    case 256: return launch_L<T, 256>(a, grid_y, s);
+    case 512: return launch_L<T, 512>(a, grid_y, s);
+    case 1024: return launch_L<T, 1024>(a, grid_y, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s) {
-  if (prec == 0) {
-    if (a.P != 16) return hipErrorInvalidValue;
-    return launch_T<float, 16>(a, grid_y, s);
-  }
-  if (a.P != 8) return hipErrorInvalidValue;
-  return launch_T<double, 8>(a, grid_y, s);
+  if (prec == 0) return launch_T<float>(a, grid_y, s);
+  return launch_T<double>(a, grid_y, s);
 }
 
 }  // namespace hp

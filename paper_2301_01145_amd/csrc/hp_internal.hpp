@@ -72,15 +72,20 @@ struct PassArgs {
   int fast;                // FAST_* below
   int un[3];               // physical (undoubled) sizes n_a
   double kc[3];            // 2 pi / (M_a H_a): angular wavenumber per index
+  int iy_mode;             // InvYMode of the backward y pass
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
                       FAST_INV_Y = 4, FAST_C2R = 5 };
+// Derivative completion in the backward y pass of the free-space path.
+enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
-// Dynamic LDS bytes of a wavefront-FFT pass.
+// Dynamic LDS bytes of a wavefront-FFT pass; 0 if the pass is not available.
 int fast_lds_bytes(int fast, int L, int P, int K2, int prec);
+// Pencils per workgroup of the wavefront-FFT passes.
+int fast_tile(int fast, int L, int prec);
 
 // Launch one pass over `grid_y` independent field groups.
 hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s);
@@ -95,9 +100,22 @@ hipError_t launch_octant(const double* spec, const int M[3], double scale, void*
 // face arrays (node with several faces: highest axis wins).
 hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, const void* face[3][2],
                                  int prec, hipStream_t s);
-// Persistent batched solve (bounded R2R problems).
-struct BatchItem;
-hipError_t launch_batched(const void* problems, int nprob, const void* items, int nitems,
-                          unsigned* counters, int ncounters, int grid, int lds, int prec,
-                          hipStream_t s);
+// One tile of one pass of the batched persistent solve.  `dep` is the global
+// index of the pass that must be complete first (-1: none) and `need` its tile
+// count; items are ordered so that every dependency has lower item indices.
+struct BatchItem {
+  int pass;
+  int tile;
+  int dep;
+  int need;
+};
+
+// Persistent batched solve: counters[0] is the work-queue head, counters[1 + i]
+// the completed tiles of pass i (zeroed by the launch itself); err[0] is set
+// to 1 if a dependency wait exceeds its spin limit (the item is then skipped).
+hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int nitems,
+                          unsigned* counters, int ncounters, int* err, int grid, int lds,
+                          int prec, hipStream_t s);
+// Resident workgroups per CU of the persistent kernel with `lds` bytes of LDS.
+int batched_blocks_per_cu(int lds, int prec);
 }  // namespace hp

@@ -469,7 +469,7 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
   const int fb = (a.diff == D_NONE) ? (int)blockIdx.y : 0;
   C2<T>* S = (C2<T>*)smem;
   C2<T>* W = S + (size_t)nS * tileC;
-  T* R = (T*)(W + tileC);  // raw real pencils (pair mode)
+  T* R = (T*)W;  // raw real pencils (pair mode; W is free while loading)
 
   auto load_into = [&](C2<T>* dst, const void* src) {
     if (pair) {
@@ -608,6 +608,92 @@ hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s) {
   dim3 grid(tiles, grid_y);
   if (prec == 0) launch_t<float>(a, grid, s);
   else launch_t<double>(a, grid, s);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched persistent
+// Every workgroup pulls items (one tile of one pass of one problem) from a
+// global queue in order, waits until the pass it depends on is complete,
+// runs the tile with the same device code as the one-launch-per-pass path and
+// publishes its completion.  Items are ordered pass by pass, so a workgroup
+// only ever waits for items that running workgroups took earlier.
+__global__ void k_zero_counters(unsigned* c, int n, int* err) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) err[0] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, const BatchItem* items,
+                                                      int nitems, unsigned* counters, int* err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item, s_ok;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= nitems) break;  // uniform: every wave leaves the loop
+    const BatchItem bi = items[it];
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      if (bi.dep >= 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(&counters[1 + bi.dep], __ATOMIC_ACQUIRE,
+                                 __HIP_MEMORY_SCOPE_AGENT) < (unsigned)bi.need) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > (1u << 24)) {  // bounded wait: report and skip
+            ok = 0;
+            atomicExch(err, 1);
+            break;
+          }
+        }
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    if (s_ok) {
+      const PassArgs& a = passes[bi.pass];
+      const int tiles_p = (a.Np + a.P - 1) / a.P;
+      Tile t;
+      t.o = bi.tile / tiles_p;
+      t.p0 = (bi.tile - t.o * tiles_p) * a.P;
+      t.np = min(a.P, a.Np - t.p0);
+      if (a.kind == PK_ONEWAY) oneway<T>(a, smem, t, 0);
+      else sandwich_r2r<T>(a, smem, t, 0);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(&counters[1 + bi.pass], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+int batched_blocks_per_cu(int lds, int prec) {
+  int n = 0;
+  hipError_t e = prec == 0
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<float>, kThreads, lds)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<double>, kThreads, lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int nitems,
+                          unsigned* counters, int ncounters, int* err, int grid, int lds,
+                          int prec, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1 + ncounters / 256), dim3(256), 0, s, counters,
+                     ncounters, err);
+  if (prec == 0) {
+    allow_lds<k_batched<float>>();
+    hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kThreads), lds, s, passes, items, nitems,
+                       counters, err);
+  } else {
+    allow_lds<k_batched<double>>();
+    hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kThreads), lds, s, passes, items, nitems,
+                       counters, err);
+  }
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ namespace hp {
 struct PassRec {
   PassArgs a;
   int grid_y;
+  double bytes = -1.0;  // algorithmic bytes when set by the planner
 };
 
 struct Problem {
@@ -32,7 +33,7 @@ struct Problem {
   void* own_out[3] = {};
   void* own_der[3] = {};
   void* own_face[3][2][3] = {};
-  std::vector<void*> a1, b2;  // unbounded / periodic workspaces
+  std::vector<void*> a1, b2, c2;  // unbounded / periodic workspaces
   double* lam[3] = {};        // eigenvalue tables (bounded)
   void* kvec[3] = {};         // wavenumber tables
   void* green = nullptr;      // Ghat octant
@@ -62,6 +63,7 @@ struct hp_plan_s {
   unsigned* batch_counters = nullptr;
   int batch_nitems = 0, batch_ncounters = 0, batch_grid = 0, batch_lds = 0;
   std::vector<hp::PassRec> batch_passes;
+  std::vector<unsigned char> batch_uploaded;  // pass table last copied to the device
   // per-pass timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;

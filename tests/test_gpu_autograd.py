@@ -1,0 +1,80 @@
+"""Differentiable free-space curl solve (torch.autograd.Function over the
+library's transposed solve).
+
+L(f) = sum |curl psi(f) - u_t|^2 is quadratic in f, so the central difference
+(L(f + v) - L(f - v)) / 2 equals <grad L, v> exactly in exact arithmetic; it is
+evaluated with the FP64 solve.  Pass: |<g, v> - FD64(v)| <= 1e-5 |g| |v|
+(FP32 gradient) and <= 1e-10 |g| |v| (FP64 gradient).  The gradient itself is
+also compared with the oracle's transposed map.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n, prec, seed_f, seed_t, rings):
+    import torch
+    from paper_2301_01145_amd import Solver
+    from workloads import vortex_rings
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    f = vortex_rings(n, seed=seed_f, count=rings, r_range=(0.08, 0.16), core_ratio=0.25)
+    ft = vortex_rings(n, seed=seed_t, count=rings, r_range=(0.08, 0.16), core_ratio=0.25)
+    s = Solver("unbounded", "staggered", [n] * 3, diff="curl", dtype=dtype, ncomp=3)
+    return s, f, ft, dtype
+
+
+def _loss64(s64, f, ut):
+    import torch
+    fin = [torch.as_tensor(f[c], dtype=torch.float64, device="cuda") for c in range(3)]
+    _, u = s64.solve(fin)
+    return sum(float(torch.sum((u[c] - ut[c]) ** 2)) for c in range(3))
+
+
+@pytest.mark.parametrize("n,ndir", [(32, 8), (128, 64)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_gradient_vs_fd(n, ndir, prec):
+    import torch
+    from paper_2301_01145_amd import Solver
+    from paper_2301_01145_amd.autograd import poisson_solve
+    from workloads import random_directions
+    s, f, ft, dtype = _setup(n, prec, 6, 7, 16)
+    s64 = Solver("unbounded", "staggered", [n] * 3, diff="curl", dtype=torch.float64, ncomp=3)
+    rnd = np.float32 if prec == "f32" else np.float64
+    f = f.astype(rnd).astype(np.float64)
+    # target u_t from the FP64 solve of the target source
+    _, ut = s64.solve([torch.as_tensor(ft[c], dtype=torch.float64, device="cuda") for c in range(3)])
+    ut = [u.clone() for u in ut]
+    fin = [torch.as_tensor(f[c], dtype=dtype, device="cuda").requires_grad_(True) for c in range(3)]
+    _, u = poisson_solve(s, fin)
+    loss = sum(torch.sum((u[c] - ut[c].to(dtype)) ** 2) for c in range(3))
+    loss.backward()
+    g = np.stack([x.grad.double().cpu().numpy() for x in fin])
+    gnorm = np.linalg.norm(g)
+    tol = 1e-5 if prec == "f32" else 1e-10
+    dirs = random_directions((3, n, n, n), seeds=range(1000, 1000 + ndir))
+    for v in dirs:
+        fd = (_loss64(s64, f + v, ut) - _loss64(s64, f - v, ut)) / 2.0
+        lhs = float(np.sum(g * v))
+        assert abs(lhs - fd) <= tol * gnorm * np.linalg.norm(v), (lhs, fd)
+    s.close()
+    s64.close()
+
+
+def test_gradient_vs_oracle_transpose():
+    import torch
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd.autograd import poisson_solve
+    n = 32
+    s, f, ft, dtype = _setup(n, "f32", 6, 7, 6)
+    f = f.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(3)
+    gu = rng.normal(size=(3, n, n, n)).astype(np.float32).astype(np.float64)
+    fin = [torch.as_tensor(f[c], dtype=dtype, device="cuda").requires_grad_(True) for c in range(3)]
+    _, u = poisson_solve(s, fin)
+    torch.autograd.backward(u, [torch.as_tensor(gu[c], dtype=dtype, device="cuda") for c in range(3)])
+    g = np.stack([x.grad.double().cpu().numpy() for x in fin])
+    h = 1.0 / n
+    ref = ub.adjoint_unbounded(None, list(gu), [h] * 3, 2 * h, "curl")
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-5
+    s.close()

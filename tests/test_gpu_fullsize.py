@@ -1,0 +1,169 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+* 2D periodic 64^2 FP64 PS: every element against the closed form and oracle.
+* 3D Dirichlet 128^3 REGULAR FD2 with inhomogeneous boundary values, FP32
+  (and FP64): every element against the oracle.
+* 3D free-space 256^3 (doubled 512^3) curl of 32 vortex rings: psi and curl at
+  512 seeded sample points against stored oracle values
+  (tests/golden/unbounded256_curl_samples.npz, written by
+  tests/golden/make_unbounded_samples.py from oracle/), full-field L2 norms,
+  and psi at 8 points by the oracle's direct sum (independent of the file).
+* The Gaussian-blob twin at 256^3: psi and curl against the closed form.
+* 3D free-space 128^3 (doubled 256^3) curl: every element against the oracle.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+from gpu_util import TOL, rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "unbounded256_curl_samples.npz")
+
+
+def test_periodic_64_fp64():
+    import torch
+    import oracle
+    from paper_2301_01145_amd import Solver
+    from workloads import periodic_modes_2d
+    f, modes = periodic_modes_2d(64, seed=1)
+    s = Solver("periodic", "staggered", [64, 64], kernel="ps", dtype=torch.float64)
+    psi, _ = s.solve(torch.as_tensor(f, device="cuda"))
+    got = psi[0].cpu().numpy()
+    x = (np.arange(64) + 0.5) / 64
+    X, Y = x[:, None], x[None, :]
+    ref = np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y) / (-8 * np.pi ** 2)
+    for p, q, a, b in modes:
+        ph = 2 * np.pi * (p * X + q * Y)
+        ref = ref + (a * np.cos(ph) + b * np.sin(ph)) / (-4 * np.pi ** 2 * (p * p + q * q))
+    assert rel_l2(got, ref) <= 1e-12
+    ora, _ = oracle.solve("periodic", "staggered", [64, 64], [0, 0], [1, 1], f)
+    assert rel_l2(got, ora) <= 1e-12 and rel_max(got, ora) <= 1e-11
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_dirichlet_128_inhomogeneous(prec):
+    import torch
+    import oracle
+    from paper_2301_01145_amd import Solver
+    from workloads import dirichlet_3d
+    f, faces = dirichlet_3d(128)
+    rnd = np.float32 if prec == "f32" else np.float64
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    f = f.astype(rnd).astype(np.float64)
+    faces = {k: v.astype(rnd).astype(np.float64) for k, v in faces.items()}
+    s = Solver("dirichlet", "regular", [128] * 3, kernel="fd2", dtype=dtype, inhomogeneous=True)
+    fd = {k: torch.as_tensor(v, dtype=dtype, device="cuda") for k, v in faces.items()}
+    psi, _ = s.solve(torch.as_tensor(f, dtype=dtype, device="cuda"), fd)
+    got = psi[0].double().cpu().numpy()
+    ref, _ = oracle.solve("dirichlet", "regular", [128] * 3, [0, 0, 0], [1, 1, 1], f,
+                          operator="fd2", faces=faces)
+    l2, mx = TOL[prec]
+    assert got.shape == (129, 129, 129)
+    assert rel_l2(got, ref) <= l2 and rel_max(got, ref) <= mx
+    s.close()
+
+
+def _unbounded256(prec):
+    import torch
+    from paper_2301_01145_amd import Solver
+    from workloads import vortex_rings
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    f = vortex_rings(256, seed=4, count=32).astype(np.float32)
+    s = Solver("unbounded", "staggered", [256] * 3, diff="curl", dtype=dtype, ncomp=3)
+    psi, u = s.solve([torch.as_tensor(f[c], device="cuda").to(dtype) for c in range(3)])
+    torch.cuda.synchronize()
+    s.close()
+    return f, psi, u
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_unbounded_256_curl_samples(prec):
+    import oracle.unbounded as ub
+    g = np.load(GOLDEN)
+    f, psi, u = _unbounded256(prec)
+    idx = g["idx"]
+    sl = (idx[:, 0], idx[:, 1], idx[:, 2])
+    gp = np.stack([psi[c].double().cpu().numpy()[sl] for c in range(3)])
+    gu = np.stack([u[c].double().cpu().numpy()[sl] for c in range(3)])
+    l2, _ = TOL[prec]
+    for c in range(3):
+        assert rel_l2(gp[c], g["psi"][c]) <= l2, ("psi", c)
+        assert rel_l2(gu[c], g["curl"][c]) <= l2, ("curl", c)
+        assert abs(float(psi[c].double().norm()) / g["psi_norm"][c] - 1) <= l2
+        assert abs(float(u[c].double().norm()) / g["curl_norm"][c] - 1) <= l2
+    # direct sums of the discrete convolution at a few points (no stored values)
+    h = 1.0 / 256
+    pts = [tuple(p) for p in idx[:4]] + [(0, 0, 0), (255, 255, 255), (128, 0, 255), (17, 200, 3)]
+    for c in range(3):
+        ref = ub.psi_at(pts, f[c].astype(np.float64), [h] * 3, 2 * h)
+        got = np.array([float(psi[c][p]) for p in pts])
+        assert np.max(np.abs(got - ref)) <= l2 * 10 * g["psi_absmax"][c], c
+
+
+def _blob_fields(n, s_blob, sigma, params, x):
+    X, Y, Z = x[:, None, None], x[None, :, None], x[None, None, :]
+    se = math.sqrt(s_blob ** 2 + sigma ** 2)
+    psi = []
+    dpsi = []  # gradient of each component's potential
+    for centres, amps in params:
+        p = np.zeros((n, n, n))
+        gr = [np.zeros((n, n, n)) for _ in range(3)]
+        for cc, A in zip(centres, amps):
+            Q = A * (2 * np.pi * s_blob * s_blob) ** 1.5
+            dx, dy, dz = X - cc[0], Y - cc[1], Z - cc[2]
+            r = np.sqrt(dx * dx + dy * dy + dz * dz)
+            rs = np.where(r > 0, r, 1.0)
+            p += np.where(r > 0, -Q * erf(rs / (math.sqrt(2) * se)) / (4 * np.pi * rs),
+                          -Q * math.sqrt(2 / np.pi) / (4 * np.pi * se))
+            dp = np.where(r > 0, Q * erf(rs / (math.sqrt(2) * se)) / (4 * np.pi * rs ** 2)
+                          - Q * math.sqrt(2 / np.pi) / se * np.exp(-rs ** 2 / (2 * se * se)) / (4 * np.pi * rs), 0.0)
+            for a, d in enumerate((dx, dy, dz)):
+                gr[a] += dp * d / rs
+        psi.append(p)
+        dpsi.append(gr)
+    curl = [dpsi[2][1] - dpsi[1][2], dpsi[0][2] - dpsi[2][0], dpsi[1][0] - dpsi[0][1]]
+    return psi, curl
+
+
+def test_unbounded_256_gaussian_closed_form():
+    import torch
+    from paper_2301_01145_amd import Solver
+    from workloads import gaussian_blobs_vector, staggered_axis
+    n = 256
+    f, params = gaussian_blobs_vector(n, seed=8)
+    s = Solver("unbounded", "staggered", [n] * 3, diff="curl", dtype=torch.float32, ncomp=3)
+    psi, u = s.solve([torch.as_tensor(f[c].astype(np.float32), device="cuda") for c in range(3)])
+    torch.cuda.synchronize()
+    ref_psi, ref_u = _blob_fields(n, 0.03, 2.0 / n, params, staggered_axis(n))
+    for c in range(3):
+        assert rel_l2(psi[c].double().cpu().numpy(), ref_psi[c]) <= 1e-5, ("psi", c)
+        assert rel_l2(u[c].double().cpu().numpy(), ref_u[c]) <= 1e-5, ("curl", c)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_unbounded_128_curl_full(prec):
+    import torch
+    import oracle
+    from paper_2301_01145_amd import Solver
+    from workloads import vortex_rings
+    n = 128
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    rnd = np.float32 if prec == "f32" else np.float64
+    f = vortex_rings(n, seed=6, count=16, r_range=(0.08, 0.16), core_ratio=0.25).astype(rnd).astype(np.float64)
+    s = Solver("unbounded", "staggered", [n] * 3, diff="curl", dtype=dtype, ncomp=3)
+    psi, u = s.solve([torch.as_tensor(f[c], dtype=dtype, device="cuda") for c in range(3)])
+    torch.cuda.synchronize()
+    ref_psi, ref_u = oracle.solve("unbounded", "staggered", [n] * 3, [0, 0, 0], [1, 1, 1], f, diff="curl")
+    l2, mx = TOL[prec]
+    for c in range(3):
+        assert rel_l2(psi[c].double().cpu().numpy(), ref_psi[c]) <= l2
+        assert rel_l2(u[c].double().cpu().numpy(), ref_u[c]) <= l2
+        assert rel_max(u[c].double().cpu().numpy(), ref_u[c]) <= mx
+    s.close()

@@ -147,3 +147,27 @@ def test_unbounded_adjoint(diff, ncomp, prec, with_psi, nc):
     ref = ub.adjoint_unbounded(gpsi if with_psi else None, gder, hs, 2.0 * max(hs), diff)
     s.close()
     check(got, ref, prec, "adjoint")
+
+
+@pytest.mark.parametrize("bc,grid,nc", [("periodic", "staggered", [1, 8]), ("neumann", "regular", [1]),
+                                        ("dirichlet", "staggered", [1]), ("dirichlet", "regular", [2, 3]),
+                                        ("periodic", "regular", [4096]), ("dirichlet", "regular", [2048]),
+                                        ("neumann", "staggered", [2, 1, 3])])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_degenerate_and_long(bc, grid, nc, prec):
+    """Axes of one or two cells, and the longest single-axis transforms."""
+    nd = len(nc)
+    kernel = "fd2"
+    f, _ = case_input(bc, grid, nc, 1, False, prec, seed=13)
+    got, _ = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", prec, 1, None)
+    ref, _ = oracle_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", None)
+    check(got, ref, prec, "psi")
+
+
+@pytest.mark.parametrize("bc", ["periodic", "neumann", "dirichlet", "unbounded"])
+def test_zero_source(bc):
+    nc = [8, 8, 8]
+    f = np.zeros(tuple(nc) if bc != "neumann" else (8, 8, 8))
+    kernel = "g2" if bc == "unbounded" else "ps"
+    got, _ = gpu_solve(bc, "staggered", nc, LO, HI, f, kernel, "none", "f32", 1, None)
+    assert np.all(got == 0.0)

@@ -32,7 +32,98 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128, help="grid of the oracle sample")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the secondary workloads (2D periodic, 3D Dirichlet, batched Neumann, "
+                         "differentiable 128^3)")
     return ap.parse_args()
+
+
+def _time(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def other_workloads(steps, warmup):
+    """Secondary workloads: solves/s and model GB/s each (same timing method)."""
+    import numpy as np
+    import torch
+
+    from paper_2301_01145_amd import Solver
+    from paper_2301_01145_amd.autograd import poisson_solve
+    from paper_2301_01145_amd.batched import BatchedSolver
+    from workloads import dirichlet_3d, neumann_batch, periodic_modes_2d, vortex_rings
+    res = {}
+    # 2D periodic 64^2 FP64 PS
+    f, _ = periodic_modes_2d(64, seed=1)
+    s = Solver("periodic", "staggered", [64, 64], kernel="ps", dtype=torch.float64)
+    s.bind(torch.as_tensor(f, device="cuda"))
+    ms = _time(s.run, steps, warmup, s.stream)
+    res["periodic2d_64_fp64"] = {"solves_per_s": 1000 / ms, "ms": ms,
+                                 "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+    s.close()
+    # 3D Dirichlet 128^3 regular FD2 inhomogeneous FP32
+    f, faces = dirichlet_3d(128)
+    s = Solver("dirichlet", "regular", [128] * 3, kernel="fd2", dtype=torch.float32, inhomogeneous=True)
+    fd = {k: torch.as_tensor(v.astype(np.float32), device="cuda") for k, v in faces.items()}
+    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"), fd)
+    ms = _time(s.run, steps, warmup, s.stream)
+    res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+                                       "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+    s.close()
+    # 64 batched Neumann problems, one persistent launch, FP32
+    probs = neumann_batch(64, seed=5)
+    bs = BatchedSolver("neumann", "staggered", [{"nc": list(p["shape"])} for p in probs], kernel="ps")
+    bs.bind([torch.as_tensor(p["f"].astype(np.float32), device="cuda") for p in probs])
+    ms = _time(bs.run, steps, warmup, bs.stream)
+    res["neumann_batch64_fp32"] = {"batches_per_s": 1000 / ms, "problems_per_s": 64000 / ms, "ms": ms,
+                                   "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
+                                   "error_flag": bs.error_flag()}
+    bs.close()
+    # differentiable 128^3 curl solve: forward + backward of sum |u - u_t|^2, FP32
+    n = 128
+    fr = vortex_rings(n, seed=6, count=16, r_range=(0.08, 0.16), core_ratio=0.25).astype(np.float32)
+    ft = vortex_rings(n, seed=7, count=16, r_range=(0.08, 0.16), core_ratio=0.25).astype(np.float32)
+    s = Solver("unbounded", "staggered", [n] * 3, diff="curl", dtype=torch.float32, ncomp=3)
+    _, ut = s.solve([torch.as_tensor(ft[c], device="cuda") for c in range(3)])
+    ut = [u.clone() for u in ut]
+    fin = [torch.as_tensor(fr[c], device="cuda").requires_grad_(True) for c in range(3)]
+
+    def step():
+        for x in fin:
+            x.grad = None
+        _, u = poisson_solve(s, fin)
+        loss = sum(torch.sum((u[c] - ut[c]) ** 2) for c in range(3))
+        loss.backward()
+
+    ms = _time(step, steps, warmup, s.stream)
+    res["autograd_unbounded128_curl_fp32"] = {"steps_per_s": 1000 / ms, "ms_fwd_bwd": ms}
+    s.close()
+    return res
+
+
+def copy_reference():
+    """A plain device-to-device copy of known size, to calibrate FETCH_SIZE /
+    WRITE_SIZE counters against bytes actually moved."""
+    import torch
+    n = 1 << 28  # 2^28 floats = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 3}), flush=True)
 
 
 def timed_solves(solver, steps, warmup):
@@ -85,6 +176,9 @@ def cpu_baseline(n_sample, n_full):
 
 def main():
     args = parse()
+    if args.copy_ref:
+        copy_reference()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
@@ -152,6 +246,8 @@ def main():
         out["fp64"] = {"value": 1000.0 / r64["ms"], "ms_per_step": r64["ms"],
                        "model_gbs": r64["model_bytes"] / (r64["ms"] * 1e-3) / 1e9}
         out["fp32_error_vs_fp64"] = {"rel_l2": (num / den) ** 0.5, "rel_max": mx / mref}
+    if not args.no_others:
+        out["other_workloads"] = other_workloads(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
     print(json.dumps(out), flush=True)

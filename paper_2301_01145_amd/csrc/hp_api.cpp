@@ -431,14 +431,31 @@ hp_status setup_problem(hp_plan p, Problem& P) {
     const int nf = P.ncomp + P.nder;
     const size_t K2 = (size_t)P.M[2] / 2 + 1;
     const bool fast = fast_unbounded_ok(p, P);
+    // kz slabs of the y / x passes (fast path): B2 and C2 then hold one slab
+    P.slabs.clear();
+    int sl = 0;
+    if (fast) {
+      if (const char* e = std::getenv("HP_SLAB")) sl = std::atoi(e);
+    }
+    if (sl > 0 && sl < (int)K2) {
+      for (int k = 0; k < (int)K2; k += sl) P.slabs.push_back({k, std::min(sl, (int)K2 - k)});
+      if (P.slabs.size() > 1 && P.slabs.back().second < sl / 2) {
+        P.slabs[P.slabs.size() - 2].second += P.slabs.back().second;
+        P.slabs.pop_back();
+      }
+    } else {
+      P.slabs.push_back({0, (int)K2});
+    }
+    size_t kzmax = 0;
+    for (auto& s : P.slabs) kzmax = std::max(kzmax, (size_t)s.second);
     for (int f = 0; f < nf; ++f) {
       void* b;
       HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2 * P.n[1] * 2 * es, &b));
       P.a1.push_back(b);
-      HP_TRY(dev_alloc(p, K2 * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
+      HP_TRY(dev_alloc(p, (fast ? kzmax : K2) * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
       P.b2.push_back(b);
       if (fast) {
-        HP_TRY(dev_alloc(p, K2 * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
+        HP_TRY(dev_alloc(p, kzmax * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
         P.c2.push_back(b);
       }
     }
@@ -999,39 +1016,49 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     r.grid_y = n_src;
     r.bytes = n_live * ((double)n0 * n1 * n2 * es + (double)n0 * K2 * n1 * cs);
   }
-  // P2: forward C2C along y into B2
-  HP_TRY(base(FAST_FWD_Y, M1));
-  {
-    PassRec& r = out.back();
-    for (int f = 0; f < n_src; ++f) { r.a.in[f] = src[f] ? P.a1[f] : nullptr; r.a.out[f] = P.b2[f]; }
-    r.grid_y = n_src;
-    r.bytes = n_live * ((double)n0 * K2 * n1 * cs + (double)K2 * M1 * n0 * cs);
-  }
-  // P3: sandwich along x into C2
-  HP_TRY(base(FAST_SANDWICH, M0));
-  {
-    PassRec& r = out.back();
-    PassArgs& a = r.a;
-    a.mult = M_GREEN;
-    a.green = P.green;
-    for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
-    if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
-    else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
-    for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
-    for (int f = 0; f < n_mid; ++f) a.out[f] = P.c2[f];
-    r.grid_y = a.diff == D_NONE ? nc : 1;
-    const double oct = (double)(M0 / 2 + 1) * (M1 / 2 + 1) * K2 * es;
-    r.bytes = (n_live + n_mid) * (double)K2 * M1 * n0 * cs + oct;
-  }
-  // P4: backward C2C along y (with derivative completion) into C1 (= A1 buffers)
-  HP_TRY(base(FAST_INV_Y, M1));
-  {
-    PassRec& r = out.back();
-    r.a.iy_mode = iy_mode;
-    for (int f = 0; f < n_mid; ++f) r.a.in[f] = P.c2[f];
-    for (int f = 0; f < n_dst; ++f) r.a.out[f] = P.a1[f];
-    r.grid_y = iy_mode == IY_PLAIN ? n_mid : 1;
-    r.bytes = n_mid * (double)K2 * n0 * M1 * cs + n_dst * (double)n1 * n0 * K2 * cs;
+  // P2 - P4 per kz slab (one slab covering all K2 planes unless HP_SLAB set)
+  for (const auto& slab : P.slabs) {
+    const int kb = slab.first, kc = slab.second;
+    // P2: forward C2C along y into B2
+    HP_TRY(base(FAST_FWD_Y, M1));
+    {
+      PassRec& r = out.back();
+      r.a.kz_base = kb;
+      r.a.kz_count = kc;
+      for (int f = 0; f < n_src; ++f) { r.a.in[f] = src[f] ? P.a1[f] : nullptr; r.a.out[f] = P.b2[f]; }
+      r.grid_y = n_src;
+      r.bytes = n_live * ((double)n0 * kc * n1 * cs + (double)kc * M1 * n0 * cs);
+    }
+    // P3: sandwich along x into C2
+    HP_TRY(base(FAST_SANDWICH, M0));
+    {
+      PassRec& r = out.back();
+      PassArgs& a = r.a;
+      a.kz_base = kb;
+      a.kz_count = kc;
+      a.mult = M_GREEN;
+      a.green = P.green;
+      for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+      if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
+      else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
+      for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
+      for (int f = 0; f < n_mid; ++f) a.out[f] = P.c2[f];
+      r.grid_y = (a.diff == D_NONE || a.diff == D_CURL) ? nc : 1;
+      const double oct = (double)(M0 / 2 + 1) * (M1 / 2 + 1) * kc * es;
+      r.bytes = (n_live + n_mid) * (double)kc * M1 * n0 * cs + oct;
+    }
+    // P4: backward C2C along y (with derivative completion) into C1 (= A1 buffers)
+    HP_TRY(base(FAST_INV_Y, M1));
+    {
+      PassRec& r = out.back();
+      r.a.kz_base = kb;
+      r.a.kz_count = kc;
+      r.a.iy_mode = iy_mode;
+      for (int f = 0; f < n_mid; ++f) r.a.in[f] = P.c2[f];
+      for (int f = 0; f < n_dst; ++f) r.a.out[f] = P.a1[f];
+      r.grid_y = iy_mode == IY_PLAIN ? n_mid : (iy_mode == IY_CURL5 ? 2 : 1);
+      r.bytes = n_mid * (double)kc * n0 * M1 * cs + n_dst * (double)n1 * n0 * kc * cs;
+    }
   }
   // P5: C2R along z into the destination arrays
   HP_TRY(base(FAST_C2R, M2));

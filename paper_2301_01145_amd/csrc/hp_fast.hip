@@ -187,7 +187,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
   const int n0 = a.un[0], n1 = a.un[1];
   const int K2 = a.gM[2] / 2 + 1;
   const int xtiles = (n0 + P - 1) / P;
-  const int kz = blockIdx.x / xtiles, x0 = (blockIdx.x % xtiles) * P;
+  const int kzl = blockIdx.x / xtiles, x0 = (blockIdx.x % xtiles) * P;
+  const int kz = a.kz_base + kzl;  // global kz (A1); kzl indexes the B2 slab
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -212,7 +213,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
     wave_sync();
   }
   __syncthreads();
-  const long long obase = (long long)kz * L * n0 + x0;
+  const long long obase = (long long)kzl * L * n0 + x0;
   for (int e = threadIdx.x; e < L * P; e += NT) {
     const int ky = e / P, c = e - (e / P) * P;
     if (x0 + c < n0) out[obase + (long long)ky * n0 + c] = tile[ky * TS + c];
@@ -238,7 +239,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassA
   C2<T>* tile = tw + L;
   const int M1 = a.gM[1], M2 = a.gM[2];
   const int ytiles = M1 / P;
-  const int kz = blockIdx.x / ytiles, ky0 = (blockIdx.x % ytiles) * P;
+  const int kzl = blockIdx.x / ytiles, ky0 = (blockIdx.x % ytiles) * P;
+  const int kz = a.kz_base + kzl;  // global kz (Ghat, k_z); kzl indexes the B2 / C2 slabs
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -246,8 +248,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassA
   const int p = wave * PPW + q;
   const int ky = ky0 + p;
   C2<T>* col = tile + p;
-  const long long ibase = ((long long)kz * M1 + ky) * NX;
-  const long long obase = (long long)kz * NX * M1 + ky0;
+  const long long ibase = ((long long)kzl * M1 + ky) * NX;
+  const long long obase = (long long)kzl * NX * M1 + ky0;
   const int fb = a.diff == D_NONE ? (int)blockIdx.y : 0;
   const T* grow = (const T*)a.green + (long long)kz * a.g_s[2] +
                   (long long)min(ky, M1 - ky) * a.g_s[1];
@@ -290,21 +292,20 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassA
     green(v);
     emit(v, a.out[fb]);
   } else if (!ADJ && a.diff == D_CURL) {
-    // component by component: psi_c, plus B = d_x psi_y and A = -d_x psi_z
-#pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-      C2<T> v[R0];
-      load(v, a.in[c]);
-      green(v);
-      if (c > 0) {
-        C2<T> u[R0];
-        const T sgn = c == 1 ? (T)1 : (T)-1;
+    // one component per blockIdx.y: psi_c, plus B = d_x psi_y (c = 1) or
+    // A = -d_x psi_z (c = 2)
+    const int c = blockIdx.y;
+    C2<T> v[R0];
+    load(v, a.in[c]);
+    green(v);
+    if (c > 0) {
+      C2<T> u[R0];
+      const T sgn = c == 1 ? (T)1 : (T)-1;
 #pragma unroll
-        for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
-        emit(u, a.out[c == 1 ? 4 : 3]);
-      }
-      emit(v, a.out[c]);
+      for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
+      emit(u, a.out[c == 1 ? 4 : 3]);
     }
+    emit(v, a.out[c]);
   } else if (ADJ && a.diff == D_ADJ_CURL) {
     C2<T> S[3][R0];
 #pragma unroll
@@ -382,19 +383,20 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   C2<T>* tile = tw + L;
   const int n0 = a.un[0];
   const int M2 = a.gM[2], K2 = M2 / 2 + 1;
-  const int ztiles = (K2 + P - 1) / P;
-  const int x = blockIdx.x / ztiles, kz0 = (blockIdx.x % ztiles) * P;
+  const int ztiles = (a.kz_count + P - 1) / P;
+  const int x = blockIdx.x / ztiles, kzl0 = (blockIdx.x % ztiles) * P;
+  const int kz0 = a.kz_base + kzl0;  // global kz (C1, k_z); kzl indexes the C2 slab
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   const int p = wave * PPW + q;
   const int kz = kz0 + p;
-  const bool valid = kz < K2;
+  const bool valid = kzl0 + p < a.kz_count;
   C2<T>* col = tile + p;
-  const long long ibase = ((long long)(valid ? kz : 0) * n0 + x) * L;
+  const long long ibase = ((long long)(valid ? kzl0 + p : 0) * n0 + x) * L;
   const long long obase = (long long)x * K2 + kz0;
-  const int nvalid = min(P, K2 - kz0);
+  const int nvalid = min(P, a.kz_count - kzl0);
   auto kyv = [&](int i) -> T { return (T)(a.kc[1] * signed_index(g + G * i, L)); };
   const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
 
@@ -422,26 +424,31 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
     load(v, a.in[blockIdx.y]);
     emit(v, a.out[blockIdx.y]);
   } else if (a.iy_mode == IY_CURL5) {
+    // two independent output groups (blockIdx.y), no input read twice:
+    // {psi_z, u_x, psi_y} from psi_y, psi_z; {u_y, u_z, psi_x} from psi_x, A, B
     C2<T> s[R0], w[R0];
-    load(s, a.in[2]);  // psi_z
+    if (blockIdx.y == 0) {
+      load(s, a.in[2]);  // psi_z
 #pragma unroll
-    for (int i = 0; i < R0; ++i) w[i] = cscale(cmuli(s[i]), kyv(i));  // d_y psi_z
-    emit(s, a.out[2]);
-    load(s, a.in[1]);  // psi_y
+      for (int i = 0; i < R0; ++i) w[i] = cscale(cmuli(s[i]), kyv(i));  // d_y psi_z
+      emit(s, a.out[2]);
+      load(s, a.in[1]);  // psi_y
 #pragma unroll
-    for (int i = 0; i < R0; ++i) w[i] = csub(w[i], cscale(cmuli(s[i]), kzv));  // - d_z psi_y
-    emit(w, a.out[3]);
-    emit(s, a.out[1]);
-    load(s, a.in[0]);  // psi_x
-    load(w, a.in[3]);  // A
+      for (int i = 0; i < R0; ++i) w[i] = csub(w[i], cscale(cmuli(s[i]), kzv));  // - d_z psi_y
+      emit(w, a.out[3]);
+      emit(s, a.out[1]);
+    } else {
+      load(s, a.in[0]);  // psi_x
+      load(w, a.in[3]);  // A
 #pragma unroll
-    for (int i = 0; i < R0; ++i) w[i] = cadd(w[i], cscale(cmuli(s[i]), kzv));  // d_z psi_x + A
-    emit(w, a.out[4]);
-    load(w, a.in[4]);  // B
+      for (int i = 0; i < R0; ++i) w[i] = cadd(w[i], cscale(cmuli(s[i]), kzv));  // d_z psi_x + A
+      emit(w, a.out[4]);
+      load(w, a.in[4]);  // B
 #pragma unroll
-    for (int i = 0; i < R0; ++i) w[i] = csub(w[i], cscale(cmuli(s[i]), kyv(i)));  // B - d_y psi_x
-    emit(w, a.out[5]);
-    emit(s, a.out[0]);
+      for (int i = 0; i < R0; ++i) w[i] = csub(w[i], cscale(cmuli(s[i]), kyv(i)));  // B - d_y psi_x
+      emit(w, a.out[5]);
+      emit(s, a.out[0]);
+    }
   } else {  // IY_GRAD2
     C2<T> s[R0], w[R0];
     load(s, a.in[0]);
@@ -561,7 +568,6 @@ static void allow_lds() {
 template <typename T, int L, int P>
 static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
   const int n0 = a.un[0], n1 = a.un[1];
-  const int K2 = a.gM[2] / 2 + 1;
   const int lds = a.lds_bytes;
   switch (a.fast) {
     case FAST_R2C: {
@@ -570,13 +576,13 @@ static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
       hipLaunchKernelGGL((kf_r2c<T, L, P>), grid, dim3(R2CShape<L, P>::NT), lds, s, a);
     } break;
     case FAST_FWD_Y: {
-      dim3 grid(((n0 + P - 1) / P) * K2, grid_y);
+      dim3 grid(((n0 + P - 1) / P) * a.kz_count, grid_y);
       allow_lds<kf_fwd_y<T, L, P>>();
       hipLaunchKernelGGL((kf_fwd_y<T, L, P>), grid, dim3(64 * (P / WF<L>::PPW)), lds, s, a);
     } break;
     case FAST_SANDWICH: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
-      dim3 grid((a.gM[1] / P) * K2, grid_y);
+      dim3 grid((a.gM[1] / P) * a.kz_count, grid_y);
       if (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) {
         allow_lds<kf_sandwich<T, L, P, true>>();
         hipLaunchKernelGGL((kf_sandwich<T, L, P, true>), grid, dim3(NT), lds, s, a);
@@ -587,7 +593,7 @@ static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
     } break;
     case FAST_INV_Y: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
-      dim3 grid(((K2 + P - 1) / P) * n0, grid_y);
+      dim3 grid(((a.kz_count + P - 1) / P) * n0, grid_y);
       allow_lds<kf_inv_y<T, L, P>>();
       hipLaunchKernelGGL((kf_inv_y<T, L, P>), grid, dim3(NT), lds, s, a);
     } break;

@@ -73,6 +73,7 @@ struct PassArgs {
   int un[3];               // physical (undoubled) sizes n_a
   double kc[3];            // 2 pi / (M_a H_a): angular wavenumber per index
   int iy_mode;             // InvYMode of the backward y pass
+  int kz_base, kz_count;   // kz slab of the y and x passes (B2 / C2 hold kz_count planes)
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,

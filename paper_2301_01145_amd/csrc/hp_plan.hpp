@@ -39,6 +39,7 @@ struct Problem {
   void* green = nullptr;      // Ghat octant
   long long g_s[3] = {0, 0, 0};  // octant strides of i0, i1, k2
   double norm = 1.0;
+  std::vector<std::pair<int, int>> slabs;  // kz (first, count) of the free-space y / x passes
 };
 
 }  // namespace hp

@@ -171,3 +171,17 @@ def test_zero_source(bc):
     kernel = "g2" if bc == "unbounded" else "ps"
     got, _ = gpu_solve(bc, "staggered", nc, LO, HI, f, kernel, "none", "f32", 1, None)
     assert np.all(got == 0.0)
+
+
+@pytest.mark.parametrize("slab", ["8", "16"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_unbounded_kz_slabs(slab, prec, monkeypatch):
+    """The y / x passes run slab by slab along kz (uneven last slab)."""
+    monkeypatch.setenv("HP_SLAB", slab)
+    nc = [64, 32, 128]
+    f, _ = case_input("unbounded", "staggered", nc, 3, False, prec, seed=4)
+    got, gd = gpu_solve("unbounded", "staggered", nc, LO, HI, f, "g2", "curl", prec, 3, None)
+    ref, rd = oracle_solve("unbounded", "staggered", nc, LO, HI, f, "g2", "curl", None)
+    check(got, ref, prec, "psi")
+    for a in range(3):
+        check(gd[a], rd[a], prec, f"curl {a}")

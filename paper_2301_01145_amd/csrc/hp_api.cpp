@@ -457,6 +457,12 @@ hp_status setup_problem(hp_plan p, Problem& P) {
       if (fast) {
         HP_TRY(dev_alloc(p, kzmax * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
         P.c2.push_back(b);
+        // with several kz slabs the backward y pass must not write over A1,
+        // which later slabs still read: C1 gets its own buffers
+        if (P.slabs.size() > 1) {
+          HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2 * P.n[1] * 2 * es, &b));
+          P.c1.push_back(b);
+        }
       }
     }
   }
@@ -957,7 +963,7 @@ bool fast_unbounded_ok(hp_plan p, const Problem& P) {
   const int K2 = P.M[2] / 2 + 1;
   for (int i = 0; i < 5; ++i) {
     const int Pt = fast_tile(kinds[i], axisL[i], p->prec);
-    if (fast_lds_bytes(kinds[i], axisL[i], Pt, K2, p->prec) > 160 * 1024) return false;
+    if (fast_lds_bytes(kinds[i], axisL[i], Pt, K2, p->prec, 0) > 160 * 1024) return false;
   }
   return true;
 }
@@ -1004,7 +1010,9 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     const void* tw;
     HP_TRY(twiddles(p, L, &tw));
     a.tw = tw;
-    a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec);
+    a.emit_dbl = fast_emit_dbl();
+    if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl) > 160 * 1024) a.emit_dbl = 0;
+    a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl);
     out.push_back({a, 1});
     return HP_OK;
   };
@@ -1055,7 +1063,7 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
       r.a.kz_count = kc;
       r.a.iy_mode = iy_mode;
       for (int f = 0; f < n_mid; ++f) r.a.in[f] = P.c2[f];
-      for (int f = 0; f < n_dst; ++f) r.a.out[f] = P.a1[f];
+      for (int f = 0; f < n_dst; ++f) r.a.out[f] = P.c1.empty() ? P.a1[f] : P.c1[f];
       r.grid_y = iy_mode == IY_PLAIN ? n_mid : (iy_mode == IY_CURL5 ? 2 : 1);
       r.bytes = n_mid * (double)kc * n0 * M1 * cs + n_dst * (double)n1 * n0 * kc * cs;
     }
@@ -1064,7 +1072,7 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
   HP_TRY(base(FAST_C2R, M2));
   {
     PassRec& r = out.back();
-    for (int f = 0; f < n_dst; ++f) { r.a.in[f] = P.a1[f]; r.a.out[f] = dst[f]; }
+    for (int f = 0; f < n_dst; ++f) { r.a.in[f] = P.c1.empty() ? P.a1[f] : P.c1[f]; r.a.out[f] = dst[f]; }
     r.grid_y = n_dst;
     r.bytes = n_dst * ((double)n1 * n0 * K2 * cs + (double)n0 * n1 * n2 * es);
   }

@@ -33,6 +33,12 @@ struct WF {
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// LDS row of FFT element m: one pad row every 16 keeps the strided Stockham
+// writes (stride R0 or R NS elements across lanes) within 1.5x of the
+// conflict-free rate on the 64 LDS banks.
+__host__ __device__ constexpr int padrow(int m) { return m + (m >> 4); }
+__host__ __device__ constexpr int padded(int L) { return L + L / 16; }
+
 // One Stockham stage (radix R, NS = product of earlier radices) over the
 // wavefront slot `buf` (element m at buf[m * bs]).
 template <typename T, int L, int R, int NS, bool LAST, bool INV>
@@ -44,7 +50,7 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
 #pragma unroll
-    for (int t = 0; t < R; ++t) v[b * R + t] = buf[(j + t * (L / R)) * bs];
+    for (int t = 0; t < R; ++t) v[b * R + t] = buf[padrow(j + t * (L / R)) * bs];
   }
   wave_sync();
 #pragma unroll
@@ -63,7 +69,7 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
       for (int t = 0; t < R; ++t) x[b + t * NB] = v[b * R + t];
     } else {
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[((j - k) * R + k + t * NS) * bs] = v[b * R + t];
+      for (int t = 0; t < R; ++t) buf[padrow((j - k) * R + k + t * NS) * bs] = v[b * R + t];
     }
   }
   if constexpr (!LAST) wave_sync();
@@ -77,7 +83,7 @@ __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int 
   dftN<T, R0, INV>(x);
   wave_sync();
 #pragma unroll
-  for (int t = 0; t < R0; ++t) buf[(g * R0 + t) * bs] = x[t];
+  for (int t = 0; t < R0; ++t) buf[padrow(g * R0 + t) * bs] = x[t];
   wave_sync();
   if constexpr (G == 8) {
     wstage<T, L, 8, R0, true, INV>(x, buf, bs, g, tw);
@@ -116,7 +122,7 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
-  C2<T>* tile = exch + NW * PPW * L;
+  C2<T>* tile = exch + NW * PPW * padded(L);
   const T* in = (const T*)a.in[blockIdx.y];
   C2<T>* out = (C2<T>*)a.out[blockIdx.y];
   if (!in) return;
@@ -125,9 +131,9 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
   const int x = blockIdx.x / ytiles, y0 = (blockIdx.x % ytiles) * P;
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  C2<T>* buf = exch + (wave * PPW + q) * L;
+  C2<T>* buf = exch + (wave * PPW + q) * padded(L);
   for (int pr0 = wave * PPW; pr0 < P / 2; pr0 += NW * PPW) {
     const int pr = pr0 + q;
     const int ya = y0 + 2 * pr, yb = ya + 1;
@@ -146,15 +152,15 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
     wave_fft<T, L, false>(v, buf, 1, g, tw);
     wave_sync();
 #pragma unroll
-    for (int i = 0; i < R0; ++i) buf[g + G * i] = v[i];
+    for (int i = 0; i < R0; ++i) buf[padrow(g + G * i)] = v[i];
     wave_sync();
     if (pr < P / 2) {
 #pragma unroll
       for (int i = 0; i <= R0 / 2; ++i) {
         const int k = g + G * i;
         if (k > L / 2) break;
-        const C2<T> zk = buf[k];
-        const C2<T> zc = cconj(buf[(L - k) & (L - 1)]);
+        const C2<T> zk = buf[padrow(k)];
+        const C2<T> zc = cconj(buf[padrow((L - k) & (L - 1))]);
         const C2<T> s = cadd(zk, zc), d = csub(zk, zc);
         tile[k * TS + 2 * pr] = {s.re * (T)0.5, s.im * (T)0.5};
         tile[k * TS + 2 * pr + 1] = {d.im * (T)0.5, -d.re * (T)0.5};
@@ -191,7 +197,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
   const int kz = a.kz_base + kzl;  // global kz (A1); kzl indexes the B2 slab
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   {
     const int pp = wave * PPW;
@@ -206,9 +212,10 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
     }
     C2<T>* col = tile + (p < P ? p : 0);
     wave_fft<T, L, false>(v, col, TS, g, tw);
+    wave_sync();
     if (p < P) {
 #pragma unroll
-      for (int i = 0; i < R0; ++i) col[(g + G * i) * TS] = v[i];
+      for (int i = 0; i < R0; ++i) col[padrow(g + G * i) * TS] = v[i];
     }
     wave_sync();
   }
@@ -216,7 +223,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
   const long long obase = (long long)kzl * L * n0 + x0;
   for (int e = threadIdx.x; e < L * P; e += NT) {
     const int ky = e / P, c = e - (e / P) * P;
-    if (x0 + c < n0) out[obase + (long long)ky * n0 + c] = tile[ky * TS + c];
+    if (x0 + c < n0) out[obase + (long long)ky * n0 + c] = tile[padrow(ky) * TS + c];
   }
 }
 
@@ -230,24 +237,29 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
 // contiguously).  Outputs: psi and, for the curl, A = -d_x psi_z and
 // B = d_x psi_y (the y and z derivatives are applied by the y pass); for the
 // gradient, psi and d_x psi.
-template <typename T, int L, int P, bool ADJ>
+template <typename T, int L, int P, bool ADJ, bool DBL>
 __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   constexpr int NT = 64 * (P / PPW), TS = P + 1, NX = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
+  // DBL: per-pencil exchange slots and two alternating [NX][P] output tiles
+  // (one barrier per output field); otherwise one [padded(L)][P] tile whose
+  // columns are the exchange slots (two barriers per output field).
   C2<T>* tw = (C2<T>*)smem;
-  C2<T>* tile = tw + L;
+  C2<T>* exch = tw + L;
+  C2<T>* tiles = DBL ? exch + P * padded(L) : exch;
   const int M1 = a.gM[1], M2 = a.gM[2];
   const int ytiles = M1 / P;
   const int kzl = blockIdx.x / ytiles, ky0 = (blockIdx.x % ytiles) * P;
   const int kz = a.kz_base + kzl;  // global kz (Ghat, k_z); kzl indexes the B2 / C2 slabs
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   const int p = wave * PPW + q;
   const int ky = ky0 + p;
-  C2<T>* col = tile + p;
+  C2<T>* col = DBL ? exch + p * padded(L) : tiles + p;
+  constexpr int bs = DBL ? 1 : TS;
   const long long ibase = ((long long)kzl * M1 + ky) * NX;
   const long long obase = (long long)kzl * NX * M1 + ky0;
   const int fb = a.diff == D_NONE ? (int)blockIdx.y : 0;
@@ -269,21 +281,25 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassA
     const C2<T>* sp = (const C2<T>*)src + ibase;
 #pragma unroll
     for (int i = 0; i < R0; ++i) v[i] = i < R0 / 2 ? sp[g + G * i] : C2<T>{(T)0, (T)0};
-    wave_fft<T, L, false>(v, col, TS, g, tw);
+    wave_fft<T, L, false>(v, col, bs, g, tw);
   };
   // backward FFT, x < n0 of every pencil to the tile, stored along ky
+  int tb = 0;
   auto emit = [&](C2<T> (&v)[R0], void* dst) {
-    wave_fft<T, L, true>(v, col, TS, g, tw);
+    wave_fft<T, L, true>(v, col, bs, g, tw);
     wave_sync();
+    C2<T>* tile = DBL ? tiles + tb * NX * TS : tiles;
+    auto row = [](int x) { return DBL ? x : padrow(x); };
 #pragma unroll
-    for (int i = 0; i < R0 / 2; ++i) col[(g + G * i) * TS] = v[i];
+    for (int i = 0; i < R0 / 2; ++i) tile[row(g + G * i) * TS + p] = v[i];
     __syncthreads();
     C2<T>* d = (C2<T>*)dst + obase;
     for (int e = threadIdx.x; e < NX * P; e += NT) {
       const int x = e / P, c = e - (e / P) * P;
-      d[(long long)x * M1 + c] = tile[x * TS + c];
+      d[(long long)x * M1 + c] = tile[row(x) * TS + c];
     }
-    __syncthreads();
+    if (DBL) tb ^= 1;
+    else __syncthreads();
   };
 
   if (a.diff == D_NONE) {
@@ -374,13 +390,14 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassA
 // psi_z, A, B give psi and u = curl psi (u_x = d_y psi_z - d_z psi_y,
 // u_y = d_z psi_x + A, u_z = B - d_y psi_x); in gradient mode psi, d_x psi give
 // psi and grad psi.  At most two spectra are live per lane.
-template <typename T, int L, int P>
+template <typename T, int L, int P, bool DBL>
 __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   constexpr int NT = 64 * (P / PPW), TS = P + 1, NY = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
-  C2<T>* tile = tw + L;
+  C2<T>* exch = tw + L;
+  C2<T>* tiles = DBL ? exch + P * padded(L) : exch;
   const int n0 = a.un[0];
   const int M2 = a.gM[2], K2 = M2 / 2 + 1;
   const int ztiles = (a.kz_count + P - 1) / P;
@@ -388,12 +405,13 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   const int kz0 = a.kz_base + kzl0;  // global kz (C1, k_z); kzl indexes the C2 slab
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   const int p = wave * PPW + q;
   const int kz = kz0 + p;
   const bool valid = kzl0 + p < a.kz_count;
-  C2<T>* col = tile + p;
+  C2<T>* col = DBL ? exch + p * padded(L) : tiles + p;
+  constexpr int bs = DBL ? 1 : TS;
   const long long ibase = ((long long)(valid ? kzl0 + p : 0) * n0 + x) * L;
   const long long obase = (long long)x * K2 + kz0;
   const int nvalid = min(P, a.kz_count - kzl0);
@@ -405,18 +423,22 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
 #pragma unroll
     for (int i = 0; i < R0; ++i) v[i] = valid ? sp[g + G * i] : C2<T>{(T)0, (T)0};
   };
+  int tb = 0;
   auto emit = [&](C2<T> (&v)[R0], void* dst) {
-    wave_fft<T, L, true>(v, col, TS, g, tw);
+    wave_fft<T, L, true>(v, col, bs, g, tw);
     wave_sync();
+    C2<T>* tile = DBL ? tiles + tb * NY * TS : tiles;
+    auto row = [](int y) { return DBL ? y : padrow(y); };
 #pragma unroll
-    for (int i = 0; i < R0 / 2; ++i) col[(g + G * i) * TS] = v[i];
+    for (int i = 0; i < R0 / 2; ++i) tile[row(g + G * i) * TS + p] = v[i];
     __syncthreads();
     C2<T>* d = (C2<T>*)dst + obase;
     for (int e = threadIdx.x; e < NY * P; e += NT) {
       const int y = e / P, c = e - (e / P) * P;
-      if (c < nvalid) d[(long long)y * n0 * K2 + c] = tile[y * TS + c];
+      if (c < nvalid) d[(long long)y * n0 * K2 + c] = tile[row(y) * TS + c];
     }
-    __syncthreads();
+    if (DBL) tb ^= 1;
+    else __syncthreads();
   };
 
   if (a.iy_mode == IY_PLAIN) {
@@ -481,9 +503,9 @@ __global__ void __launch_bounds__(kThreads) kf_c2r(const PassArgs a) {
   const int n0 = a.un[0], n1 = a.un[1], n2 = a.un[2];
   load_tw<T, L>(tw, a.tw);
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  C2<T>* buf = exch + (wave * PPW + q) * L;
+  C2<T>* buf = exch + (wave * PPW + q) * padded(L);
   const int xpairs = (n0 + 1) / 2;
   const long long total = (long long)n1 * xpairs;
   for (long long grp = (long long)blockIdx.x * 4 + wave; grp * PPW < total;
@@ -540,17 +562,27 @@ int fast_tile(int fast, int L, int prec) {
   return fast == FAST_SANDWICH ? 8 : 16;
 }
 
-int fast_lds_bytes(int fast, int L, int P, int K2, int prec) {
+// Output-tile scheme of the x and backward-y passes: 1 = double-buffered
+// tiles with separate exchange slots, 0 = one tile whose columns are the
+// exchange slots (less LDS, two barriers per output field).
+int fast_emit_dbl() {
+  if (const char* e = std::getenv("HP_EMIT")) return std::atoi(e) == 1 ? 1 : 0;
+  return 1;
+}
+
+int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl) {
   const int cs = prec == 0 ? 8 : 16;
   const int R0 = L >= 1024 ? 16 : 8;
   const int ppw = 64 / (L / R0);
-  const int exch4 = 4 * ppw * L;
+  const int SL = padded(L);
   switch (fast) {
-    case FAST_R2C: return (L + ((P / 2 + ppw - 1) / ppw) * ppw * L + K2 * (P + 1)) * cs;
-    case FAST_FWD_Y:
+    case FAST_R2C: return (L + ((P / 2 + ppw - 1) / ppw) * ppw * SL + K2 * (P + 1)) * cs;
+    case FAST_FWD_Y: return (L + SL * (P + 1)) * cs;
     case FAST_SANDWICH:
-    case FAST_INV_Y: return (L + L * (P + 1)) * cs;
-    case FAST_C2R: return (L + exch4) * cs;
+    case FAST_INV_Y:
+      if (dbl) return (L + P * SL + 2 * (L / 2) * (P + 1)) * cs;
+      return (L + SL * (P + 1)) * cs;
+    case FAST_C2R: return (L + 4 * ppw * SL) * cs;
     default: return 0;
   }
 }
@@ -559,8 +591,16 @@ template <auto K>
 static void allow_lds() {
   static bool done = false;  // one flag per kernel instantiation
   if (!done) {
-    (void)hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    // ask for the whole 160 KB minus the kernel's static LDS; a refusal is
+    // not an error here (the launch itself reports a size that does not fit),
+    // so clear it instead of leaving it for the next hipGetLastError
+    hipFuncAttributes fa{};
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&fa, (const void*)K) == hipSuccess) stat = fa.sharedSizeBytes;
+    else (void)hipGetLastError();
+    if (hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(160 * 1024 - stat)) != hipSuccess)
+      (void)hipGetLastError();
     done = true;
   }
 }
@@ -583,19 +623,36 @@ static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
     case FAST_SANDWICH: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
       dim3 grid((a.gM[1] / P) * a.kz_count, grid_y);
-      if (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) {
-        allow_lds<kf_sandwich<T, L, P, true>>();
-        hipLaunchKernelGGL((kf_sandwich<T, L, P, true>), grid, dim3(NT), lds, s, a);
+      const bool adj = a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD;
+      if (a.emit_dbl) {  // double-buffered output tiles
+        if (adj) {
+          allow_lds<kf_sandwich<T, L, P, true, true>>();
+          hipLaunchKernelGGL((kf_sandwich<T, L, P, true, true>), grid, dim3(NT), lds, s, a);
+        } else {
+          allow_lds<kf_sandwich<T, L, P, false, true>>();
+          hipLaunchKernelGGL((kf_sandwich<T, L, P, false, true>), grid, dim3(NT), lds, s, a);
+        }
       } else {
-        allow_lds<kf_sandwich<T, L, P, false>>();
-        hipLaunchKernelGGL((kf_sandwich<T, L, P, false>), grid, dim3(NT), lds, s, a);
+        if (adj) {
+          allow_lds<kf_sandwich<T, L, P, true, false>>();
+          hipLaunchKernelGGL((kf_sandwich<T, L, P, true, false>), grid, dim3(NT), lds, s, a);
+        } else {
+          allow_lds<kf_sandwich<T, L, P, false, false>>();
+          hipLaunchKernelGGL((kf_sandwich<T, L, P, false, false>), grid, dim3(NT), lds, s, a);
+        }
       }
     } break;
     case FAST_INV_Y: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
       dim3 grid(((a.kz_count + P - 1) / P) * n0, grid_y);
-      allow_lds<kf_inv_y<T, L, P>>();
-      hipLaunchKernelGGL((kf_inv_y<T, L, P>), grid, dim3(NT), lds, s, a);
+      if (a.P > 64) return hipErrorInvalidValue;
+      if (a.emit_dbl) {  // double-buffered output tiles
+        allow_lds<kf_inv_y<T, L, P, true>>();
+        hipLaunchKernelGGL((kf_inv_y<T, L, P, true>), grid, dim3(NT), lds, s, a);
+      } else {
+        allow_lds<kf_inv_y<T, L, P, false>>();
+        hipLaunchKernelGGL((kf_inv_y<T, L, P, false>), grid, dim3(NT), lds, s, a);
+      }
     } break;
     default:
       return hipErrorInvalidValue;

@@ -74,6 +74,7 @@ struct PassArgs {
   double kc[3];            // 2 pi / (M_a H_a): angular wavenumber per index
   int iy_mode;             // InvYMode of the backward y pass
   int kz_base, kz_count;   // kz slab of the y and x passes (B2 / C2 hold kz_count planes)
+  int emit_dbl;            // x / backward-y passes: double-buffered output tiles
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
@@ -84,7 +85,8 @@ enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
 // Dynamic LDS bytes of a wavefront-FFT pass; 0 if the pass is not available.
-int fast_lds_bytes(int fast, int L, int P, int K2, int prec);
+int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl);
+int fast_emit_dbl();
 // Pencils per workgroup of the wavefront-FFT passes.
 int fast_tile(int fast, int L, int prec);
 

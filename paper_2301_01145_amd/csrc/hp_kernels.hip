@@ -584,8 +584,16 @@ template <auto K>
 static void allow_lds() {
   static bool done = false;  // one flag per kernel instantiation
   if (!done) {
-    (void)hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    // ask for the whole 160 KB minus the kernel's static LDS; a refusal is
+    // not an error here (the launch itself reports a size that does not fit),
+    // so clear it instead of leaving it for the next hipGetLastError
+    hipFuncAttributes fa{};
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&fa, (const void*)K) == hipSuccess) stat = fa.sharedSizeBytes;
+    else (void)hipGetLastError();
+    if (hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(160 * 1024 - stat)) != hipSuccess)
+      (void)hipGetLastError();
     done = true;
   }
 }
@@ -627,11 +635,14 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
                                                       int nitems, unsigned* counters, int* err) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_item, s_ok;
+  // The item index and the wait result are read back with readfirstlane so
+  // that the compiler sees them as uniform: the loop then has one uniform
+  // exit and every barrier is reached by all threads in every iteration.
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[0], 1u);
     __syncthreads();
-    const int it = s_item;
-    if (it >= nitems) break;  // uniform: every wave leaves the loop
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= nitems) break;
     const BatchItem bi = items[it];
     if (threadIdx.x == 0) {
       int ok = 1;
@@ -640,7 +651,9 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
         while (__hip_atomic_load(&counters[1 + bi.dep], __ATOMIC_ACQUIRE,
                                  __HIP_MEMORY_SCOPE_AGENT) < (unsigned)bi.need) {
           __builtin_amdgcn_s_sleep(2);
-          if (++spins > (1u << 24)) {  // bounded wait: report and skip
+          // bounded wait: report and skip (also stop at once if another wait failed)
+          if (++spins > (1u << 22) ||
+              __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             ok = 0;
             atomicExch(err, 1);
             break;
@@ -650,8 +663,9 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
       s_ok = ok;
     }
     __syncthreads();
+    const int ok = __builtin_amdgcn_readfirstlane(s_ok);
     __threadfence();
-    if (s_ok) {
+    if (ok) {
       const PassArgs& a = passes[bi.pass];
       const int tiles_p = (a.Np + a.P - 1) / a.P;
       Tile t;
@@ -665,6 +679,7 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
     __syncthreads();
     if (threadIdx.x == 0)
       __hip_atomic_fetch_add(&counters[1 + bi.pass], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
   }
 }
 

@@ -33,7 +33,7 @@ struct Problem {
   void* own_out[3] = {};
   void* own_der[3] = {};
   void* own_face[3][2][3] = {};
-  std::vector<void*> a1, b2, c2;  // unbounded / periodic workspaces
+  std::vector<void*> a1, b2, c2, c1;  // unbounded / periodic workspaces
   double* lam[3] = {};        // eigenvalue tables (bounded)
   void* kvec[3] = {};         // wavenumber tables
   void* green = nullptr;      // Ghat octant

@@ -448,9 +448,12 @@ hp_status setup_problem(hp_plan p, Problem& P) {
     }
     size_t kzmax = 0;
     for (auto& s : P.slabs) kzmax = std::max(kzmax, (size_t)s.second);
+    // C1[y][x][kz] rows (fast path) are padded to a multiple of 16 elements,
+    // so that the backward y pass writes whole 128-byte lines
+    const size_t K2c = fast ? (K2 + 15) / 16 * 16 : K2;
     for (int f = 0; f < nf; ++f) {
       void* b;
-      HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2 * P.n[1] * 2 * es, &b));
+      HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2c * P.n[1] * 2 * es, &b));
       P.a1.push_back(b);
       HP_TRY(dev_alloc(p, (fast ? kzmax : K2) * P.M[1] * (size_t)P.n[0] * 2 * es, &b));
       P.b2.push_back(b);
@@ -460,7 +463,7 @@ hp_status setup_problem(hp_plan p, Problem& P) {
         // with several kz slabs the backward y pass must not write over A1,
         // which later slabs still read: C1 gets its own buffers
         if (P.slabs.size() > 1) {
-          HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2 * P.n[1] * 2 * es, &b));
+          HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2c * P.n[1] * 2 * es, &b));
           P.c1.push_back(b);
         }
       }
@@ -1010,6 +1013,7 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     const void* tw;
     HP_TRY(twiddles(p, L, &tw));
     a.tw = tw;
+    a.c1_ld = (K2 + 15) / 16 * 16;
     a.emit_dbl = fast_emit_dbl();
     if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl) > 160 * 1024) a.emit_dbl = 0;
     a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl);

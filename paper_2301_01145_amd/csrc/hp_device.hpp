@@ -55,11 +55,18 @@ __device__ __forceinline__ void dft4v(C2<T>* v) {
   v[0] = a; v[1] = b; v[2] = c; v[3] = d;
 }
 
-template <typename T, bool INV>
+// HALF: v[4..7] are known to be zero (zero-padded input), the first
+// butterfly layer reduces to copies.
+template <typename T, bool INV, bool HALF = false>
 __device__ __forceinline__ void dft8(C2<T>* v) {
   const T r = (T)0.70710678118654752440084436210485;
-  C2<T> a0 = cadd(v[0], v[4]), a1 = cadd(v[1], v[5]), a2 = cadd(v[2], v[6]), a3 = cadd(v[3], v[7]);
-  C2<T> b0 = csub(v[0], v[4]), b1 = csub(v[1], v[5]), b2 = csub(v[2], v[6]), b3 = csub(v[3], v[7]);
+  C2<T> a0, a1, a2, a3, b0, b1, b2, b3;
+  if constexpr (HALF) {
+    a0 = b0 = v[0]; a1 = b1 = v[1]; a2 = b2 = v[2]; a3 = b3 = v[3];
+  } else {
+    a0 = cadd(v[0], v[4]); a1 = cadd(v[1], v[5]); a2 = cadd(v[2], v[6]); a3 = cadd(v[3], v[7]);
+    b0 = csub(v[0], v[4]); b1 = csub(v[1], v[5]); b2 = csub(v[2], v[6]); b3 = csub(v[3], v[7]);
+  }
   // b_t *= W8^t (forward W8 = (1 - i)/sqrt2, backward its conjugate)
   if (INV) {
     b1 = {(b1.re - b1.im) * r, (b1.re + b1.im) * r};
@@ -115,15 +122,23 @@ __device__ __forceinline__ void dftR(C2<T>* v) {
 }
 
 // 16-point DFT as 4 x 4 with W16 twiddles between the two radix-4 layers.
-template <typename T, bool INV>
+// HALF: v[8..15] are known to be zero.
+template <typename T, bool INV, bool HALF = false>
 __device__ __forceinline__ void dft16(C2<T>* v) {
   // columns: a_n1[n2] = v[n1 + 4 n2]; DFT4 over n2 for each n1
   C2<T> a[4][4];
 #pragma unroll
   for (int n1 = 0; n1 < 4; ++n1) {
-    C2<T> x0 = v[n1], x1 = v[n1 + 4], x2 = v[n1 + 8], x3 = v[n1 + 12];
-    dft4<T, INV>(x0, x1, x2, x3);
-    a[n1][0] = x0; a[n1][1] = x1; a[n1][2] = x2; a[n1][3] = x3;
+    C2<T> x0 = v[n1], x1 = v[n1 + 4];
+    if constexpr (HALF) {
+      const C2<T> r1 = rot<T, INV>(x1);
+      a[n1][0] = cadd(x0, x1); a[n1][1] = cadd(x0, r1);
+      a[n1][2] = csub(x0, x1); a[n1][3] = csub(x0, r1);
+    } else {
+      C2<T> x2 = v[n1 + 8], x3 = v[n1 + 12];
+      dft4<T, INV>(x0, x1, x2, x3);
+      a[n1][0] = x0; a[n1][1] = x1; a[n1][2] = x2; a[n1][3] = x3;
+    }
   }
   // twiddle W16^(n1 k2)
   const T c1 = (T)0.92387953251128675612818318939679;  // cos(pi/8)
@@ -159,6 +174,14 @@ template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftN(C2<T>* v) {
   if constexpr (R == 16) dft16<T, INV>(v);
   else dftR<T, R, INV>(v);
+}
+
+// First-stage DFT of a zero-padded pencil: the upper half of v is zero.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftN_half(C2<T>* v) {
+  static_assert(R == 8 || R == 16, "half-input DFT for radix 8 and 16");
+  if constexpr (R == 16) dft16<T, INV, true>(v);
+  else dft8<T, INV, true>(v);
 }
 
 }  // namespace hp

@@ -17,7 +17,9 @@
 // Layouts (complex elements):  A1 [x][kz][y],  B2 [kz][ky][x];  user fields
 // [x][y][z] real.  Passes whose pencil is strided in memory stage a tile of P
 // pencils through LDS so that global accesses are runs of P elements.
+#include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "hp_device.hpp"
 #include "hp_internal.hpp"
@@ -34,13 +36,22 @@ struct WF {
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // LDS row of FFT element m: one pad row every 16 keeps the strided Stockham
-// writes (stride R0 or R NS elements across lanes) within 1.5x of the
-// conflict-free rate on the 64 LDS banks.
+// writes (stride R0 or R NS elements across lanes) within 2x of the
+// conflict-free rate on the LDS banks.
 __host__ __device__ constexpr int padrow(int m) { return m + (m >> 4); }
 __host__ __device__ constexpr int padded(int L) { return L + L / 16; }
 
+// Rows of the elements a + t S (t = 0, 1, ...) as padrow(a) + t * step:
+// exact when S is a multiple of 16, so every access of a pattern shares one
+// base address and differs by an immediate offset.
+template <int S>
+__device__ __forceinline__ int padrun(int a, int t) {
+  if constexpr (S % 16 == 0) return padrow(a) + t * padded(S);
+  else return padrow(a + t * S);
+}
+
 // One Stockham stage (radix R, NS = product of earlier radices) over the
-// wavefront slot `buf` (element m at buf[m * bs]).
+// wavefront slot `buf` (element m at buf[padrow(m) * bs]).
 template <typename T, int L, int R, int NS, bool LAST, bool INV>
 __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs, int g,
                                        const C2<T>* tw) {
@@ -50,16 +61,17 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
 #pragma unroll
-    for (int t = 0; t < R; ++t) v[b * R + t] = buf[padrow(j + t * (L / R)) * bs];
+    for (int t = 0; t < R; ++t) v[b * R + t] = buf[padrun<L / R>(j, t) * bs];
   }
   wave_sync();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
     const int k = j % NS;
+    const int ks = k * (L / (NS * R));
 #pragma unroll
     for (int t = 1; t < R; ++t) {
-      C2<T> w = tw[t * k * (L / (NS * R))];
+      C2<T> w = tw[t * ks];
       if (INV) w.im = -w.im;
       v[b * R + t] = cmul(v[b * R + t], w);
     }
@@ -68,22 +80,34 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
 #pragma unroll
       for (int t = 0; t < R; ++t) x[b + t * NB] = v[b * R + t];
     } else {
+      // element (j - k) R + k + t NS; (j - k) R is a multiple of NS R >= 64
+      const int m0 = (j - k) * R;
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[padrow((j - k) * R + k + t * NS) * bs] = v[b * R + t];
+      for (int t = 0; t < R; ++t) {
+        int row;
+        if constexpr (NS % 16 == 0) row = padrow(m0 + k) + t * padded(NS);
+        else if constexpr (NS == 8) row = padrow(m0) + k + 8 * t + (t >> 1);  // k < 8
+        else row = padrow(m0 + k + t * NS);
+        buf[row * bs] = v[b * R + t];
+      }
     }
   }
   if constexpr (!LAST) wave_sync();
 }
 
 // In-place FFT of the pencil held as x[i] = x[g + G i]; on return x[i] = X[g + G i].
-template <typename T, int L, bool INV>
+// HALF: x[i] is zero for i >= R0 / 2 (zero-padded input).
+template <typename T, int L, bool INV, bool HALF = false>
 __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs, int g,
                                          const C2<T>* tw) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G;
-  dftN<T, R0, INV>(x);
+  if constexpr (HALF) dftN_half<T, R0, INV>(x);
+  else dftN<T, R0, INV>(x);
   wave_sync();
+  // element g R0 + t, t < R0 in {8, 16}: never crosses a multiple of 16
+  const int r0 = padrow(g * R0);
 #pragma unroll
-  for (int t = 0; t < R0; ++t) buf[padrow(g * R0 + t) * bs] = x[t];
+  for (int t = 0; t < R0; ++t) buf[(r0 + t) * bs] = x[t];
   wave_sync();
   if constexpr (G == 8) {
     wstage<T, L, 8, R0, true, INV>(x, buf, bs, g, tw);
@@ -97,6 +121,16 @@ template <typename T, int L>
 __device__ __forceinline__ void load_tw(C2<T>* tw_s, const void* tw) {
   const C2<T>* src = (const C2<T>*)tw;
   for (int m = threadIdx.x; m < L; m += kThreads) tw_s[m] = src[m];
+}
+
+// Logical block index with the blocks of one XCD contiguous: workgroups are
+// dealt to the 8 XCDs in turn, so workgroup b runs on XCD b % 8; numbering
+// them XCD by XCD puts blocks with neighbouring logical indices (which read
+// the same Green's function rows) behind one L2.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+  const int xcd = bid & 7, local = bid >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return xcd * per + min(xcd, rem) + local;
 }
 
 // signed index m~ of m on an M-point grid, 0 at the Nyquist index
@@ -149,10 +183,10 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
         if (vb) v[i].im = rb[g + G * i];
       }
     }
-    wave_fft<T, L, false>(v, buf, 1, g, tw);
+    wave_fft<T, L, false, true>(v, buf, 1, g, tw);
     wave_sync();
 #pragma unroll
-    for (int i = 0; i < R0; ++i) buf[padrow(g + G * i)] = v[i];
+    for (int i = 0; i < R0; ++i) buf[padrun<G>(g, i)] = v[i];
     wave_sync();
     if (pr < P / 2) {
 #pragma unroll
@@ -211,11 +245,11 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
       if (i < R0 / 2 && valid) v[i] = src[g + G * i];
     }
     C2<T>* col = tile + (p < P ? p : 0);
-    wave_fft<T, L, false>(v, col, TS, g, tw);
+    wave_fft<T, L, false, true>(v, col, TS, g, tw);
     wave_sync();
     if (p < P) {
 #pragma unroll
-      for (int i = 0; i < R0; ++i) col[padrow(g + G * i) * TS] = v[i];
+      for (int i = 0; i < R0; ++i) col[padrun<G>(g, i) * TS] = v[i];
     }
     wave_sync();
   }
@@ -228,17 +262,25 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
 }
 
 // --------------------------------------------------------- P3: sandwich (x)
-// A workgroup takes P consecutive pencils (ky0 .. ky0+P-1, kz) of
-// B2[kz][ky][x], one (or PPW) per wavefront.  Each wavefront does the forward
-// FFT (x < n0 of L = M0 nonzero), the Green's multiply and the x-derivative in
-// registers; every output field is transformed back and written, x < n0, to an
-// [L][P] LDS tile whose columns are also the FFT exchange slots, then stored as
-// runs of P along ky into C2[kz][x][ky] (the next pass reads its y-pencils
-// contiguously).  Outputs: psi and, for the curl, A = -d_x psi_z and
-// B = d_x psi_y (the y and z derivatives are applied by the y pass); for the
-// gradient, psi and d_x psi.
+// A tile is P consecutive pencils (ky0 .. ky0+P-1, kz) of B2[kz][ky][x], one
+// (or PPW) per wavefront, and one output group.  Each wavefront does the
+// forward FFT (x < n0 nonzero of L = M0), the Green's multiply and the
+// x-derivative in registers; every output field is transformed back and
+// written, x < n0, to an LDS tile, then stored as runs of P along ky into
+// C2[kz][x][ky] (the next pass reads its y-pencils contiguously).  Outputs:
+// psi and, for the curl, A = -d_x psi_z and B = d_x psi_y (the y and z
+// derivatives are applied by the y pass); for the gradient, psi and d_x psi.
+//
+// Persistent: a workgroup loads the twiddles once and walks tiles
+// blockIdx-strided; the input pencil and Green's values of its next tile are
+// loaded before the current one is processed, so their latency overlaps the
+// FFTs and stores.  Tile order: kz slowest, then pairs of ky tiles
+// (t, ytiles-1-t) whose wavenumbers +-ky share Green's function rows, then the
+// output groups; the XCD-contiguous numbering keeps such tiles behind one L2.
 template <typename T, int L, int P, bool ADJ, bool DBL>
-__global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassArgs a) {
+__global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
+                                  (sizeof(T) == 4 && P == 8 && L == 512 && !ADJ) ? 4 : 1)
+    kf_sandwich(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   constexpr int NT = 64 * (P / PPW), TS = P + 1, NX = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -249,136 +291,200 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_sandwich(const PassA
   C2<T>* exch = tw + L;
   C2<T>* tiles = DBL ? exch + P * padded(L) : exch;
   const int M1 = a.gM[1], M2 = a.gM[2];
-  const int ytiles = M1 / P;
-  const int kzl = blockIdx.x / ytiles, ky0 = (blockIdx.x % ytiles) * P;
-  const int kz = a.kz_base + kzl;  // global kz (Ghat, k_z); kzl indexes the B2 / C2 slabs
+  const int ytiles = M1 / P;  // even: M1 is a power of two >= 64, P <= 16
+  const int ngrp = a.ngrp;
+  const int ntiles = ytiles * a.kz_count * ngrp;
+  int lt = xcd_block(blockIdx.x, gridDim.x);
+  if (lt >= ntiles) return;  // whole workgroup
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
-  __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   const int p = wave * PPW + q;
-  const int ky = ky0 + p;
   C2<T>* col = DBL ? exch + p * padded(L) : tiles + p;
   constexpr int bs = DBL ? 1 : TS;
-  const long long ibase = ((long long)kzl * M1 + ky) * NX;
-  const long long obase = (long long)kzl * NX * M1 + ky0;
-  const int fb = a.diff == D_NONE ? (int)blockIdx.y : 0;
-  const T* grow = (const T*)a.green + (long long)kz * a.g_s[2] +
-                  (long long)min(ky, M1 - ky) * a.g_s[1];
-  const T kyv = (T)(a.kc[1] * signed_index(ky, M1));
-  const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
   auto kx = [&](int i) -> T { return (T)(a.kc[0] * signed_index(g + G * i, L)); };
-  auto kcomp = [&](int c, int i) -> T { return c == 0 ? kx(i) : (c == 1 ? kyv : kzv); };
-  auto green = [&](C2<T> (&v)[R0]) {
-#pragma unroll
-    for (int i = 0; i < R0; ++i) {
-      const int k0 = g + G * i;
-      v[i] = cscale(v[i], grow[min(k0, L - k0)]);
-    }
-  };
-  // forward FFT of the pencil of field `src` (x < n0 nonzero)
-  auto load = [&](C2<T> (&v)[R0], const void* src) {
-    const C2<T>* sp = (const C2<T>*)src + ibase;
-#pragma unroll
-    for (int i = 0; i < R0; ++i) v[i] = i < R0 / 2 ? sp[g + G * i] : C2<T>{(T)0, (T)0};
-    wave_fft<T, L, false>(v, col, bs, g, tw);
-  };
-  // backward FFT, x < n0 of every pencil to the tile, stored along ky
-  int tb = 0;
-  auto emit = [&](C2<T> (&v)[R0], void* dst) {
-    wave_fft<T, L, true>(v, col, bs, g, tw);
-    wave_sync();
-    C2<T>* tile = DBL ? tiles + tb * NX * TS : tiles;
-    auto row = [](int x) { return DBL ? x : padrow(x); };
-#pragma unroll
-    for (int i = 0; i < R0 / 2; ++i) tile[row(g + G * i) * TS + p] = v[i];
-    __syncthreads();
-    C2<T>* d = (C2<T>*)dst + obase;
-    for (int e = threadIdx.x; e < NX * P; e += NT) {
-      const int x = e / P, c = e - (e / P) * P;
-      d[(long long)x * M1 + c] = tile[row(x) * TS + c];
-    }
-    if (DBL) tb ^= 1;
-    else __syncthreads();
-  };
 
-  if (a.diff == D_NONE) {
-    C2<T> v[R0];
-    load(v, a.in[fb]);
-    green(v);
-    emit(v, a.out[fb]);
-  } else if (!ADJ && a.diff == D_CURL) {
-    // one component per blockIdx.y: psi_c, plus B = d_x psi_y (c = 1) or
-    // A = -d_x psi_z (c = 2)
-    const int c = blockIdx.y;
-    C2<T> v[R0];
-    load(v, a.in[c]);
-    green(v);
-    if (c > 0) {
-      C2<T> u[R0];
-      const T sgn = c == 1 ? (T)1 : (T)-1;
+  struct TileIdx {
+    int grp, kzl, ky0;
+  };
+  auto decode = [&](int l) {
+    TileIdx t;
+    t.grp = l % ngrp;
+    l /= ngrp;
+    const int mirror = l & 1;
+    l >>= 1;
+    const int tj = l % (ytiles / 2);
+    t.kzl = l / (ytiles / 2);
+    t.ky0 = (mirror ? ytiles - 1 - tj : tj) * P;
+    return t;
+  };
+  auto in_ptr = [&](const TileIdx& t, const void* src) {
+    return (const C2<T>*)src + ((long long)t.kzl * M1 + t.ky0 + p) * NX;
+  };
+  auto green_ptr = [&](const TileIdx& t) {
+    const int ky = t.ky0 + p;
+    return (const T*)a.green + (long long)(a.kz_base + t.kzl) * a.g_s[2] +
+           (long long)min(ky, M1 - ky) * a.g_s[1];
+  };
+  // single-input groups (D_NONE, forward curl): prefetched input and Green's values
+  const bool pref = a.diff == D_NONE || (!ADJ && a.diff == D_CURL);
+  auto src_of = [&](const TileIdx& t) { return a.in[a.diff == D_NONE || a.diff == D_CURL ? t.grp : 0]; };
+  C2<T> pf[R0 / 2];
+  T pg[R0];
+  auto prefetch = [&](const TileIdx& t) {
+    // an unbound field (adjoint with a zero upstream gradient) reads as zero
+    const void* src = src_of(t);
+    const T* gr = green_ptr(t);
+    if (src) {
+      const C2<T>* sp = in_ptr(t, src);
 #pragma unroll
-      for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
-      emit(u, a.out[c == 1 ? 4 : 3]);
-    }
-    emit(v, a.out[c]);
-  } else if (ADJ && a.diff == D_ADJ_CURL) {
-    C2<T> S[3][R0];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (a.in[c]) {
-        load(S[c], a.in[c]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < R0; ++i) S[c][i] = {(T)0, (T)0};
-      }
-    }
-    // the curl is symmetric: g_i enters S_{i+1} with +i k_{i+2}, S_{i+2} with -i k_{i+1}
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (!a.in[3 + c]) continue;
-      C2<T> w[R0];
-      load(w, a.in[3 + c]);
-      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-#pragma unroll
-      for (int i = 0; i < R0; ++i) {
-        const C2<T> iw = cmuli(w[i]);
-        S[c1][i] = cadd(S[c1][i], cscale(iw, kcomp(c2, i)));
-        S[c2][i] = csub(S[c2][i], cscale(iw, kcomp(c1, i)));
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      green(S[c]);
-      emit(S[c], a.out[c]);
-    }
-  } else {  // scalar gradient and its transpose
-    C2<T> S[R0];
-    if (a.in[0]) {
-      load(S, a.in[0]);
+      for (int i = 0; i < R0 / 2; ++i) pf[i] = sp[g + G * i];
     } else {
 #pragma unroll
-      for (int i = 0; i < R0; ++i) S[i] = {(T)0, (T)0};
+      for (int i = 0; i < R0 / 2; ++i) pf[i] = {(T)0, (T)0};
     }
-    if (ADJ) {
-      // transpose of the gradient: minus the divergence
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (!a.in[1 + c]) continue;
-        C2<T> w[R0];
-        load(w, a.in[1 + c]);
+    for (int i = 0; i < R0; ++i) pg[i] = gr[min(g + G * i, L - g - G * i)];
+  };
+  TileIdx cur = decode(lt);
+  if (pref) prefetch(cur);
+  __syncthreads();  // twiddles
+  int tb = 0;
+  for (;;) {
+    const TileIdx t = cur;
+    const int ky = t.ky0 + p;
+    const int kz = a.kz_base + t.kzl;  // global kz (Ghat, k_z); t.kzl indexes the B2 / C2 slabs
+    const T kyv = (T)(a.kc[1] * signed_index(ky, M1));
+    const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
+    auto kcomp = [&](int c, int i) -> T { return c == 0 ? kx(i) : (c == 1 ? kyv : kzv); };
+    const long long obase = (long long)t.kzl * NX * M1 + t.ky0;
+    C2<T> v[R0];
+    T gv[R0];
+    if (pref) {
 #pragma unroll
-        for (int i = 0; i < R0; ++i) S[i] = csub(S[i], cscale(cmuli(w[i]), kcomp(c, i)));
+      for (int i = 0; i < R0; ++i) {
+        v[i] = i < R0 / 2 ? pf[i] : C2<T>{(T)0, (T)0};
+        gv[i] = pg[i];
       }
     }
-    green(S);
-    if (!ADJ) {
-      C2<T> u[R0];
-#pragma unroll
-      for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(S[i]), kx(i));
-      emit(u, a.out[1]);
+    const int nxt = lt + (int)gridDim.x;
+    if (nxt < ntiles) {
+      cur = decode(nxt);
+      if (pref) prefetch(cur);
     }
-    emit(S, a.out[0]);
+    auto green = [&](C2<T> (&w)[R0]) {
+      if (pref) {
+#pragma unroll
+        for (int i = 0; i < R0; ++i) w[i] = cscale(w[i], gv[i]);
+      } else {
+        const T* gr = green_ptr(t);
+#pragma unroll
+        for (int i = 0; i < R0; ++i) w[i] = cscale(w[i], gr[min(g + G * i, L - g - G * i)]);
+      }
+    };
+    // forward FFT of the pencil of field `src` (x < n0 nonzero)
+    auto load = [&](C2<T> (&w)[R0], const void* src) {
+      const C2<T>* sp = in_ptr(t, src);
+#pragma unroll
+      for (int i = 0; i < R0; ++i) w[i] = i < R0 / 2 ? sp[g + G * i] : C2<T>{(T)0, (T)0};
+      wave_fft<T, L, false, true>(w, col, bs, g, tw);
+    };
+    // backward FFT, x < n0 of every pencil to the tile, stored along ky
+    auto emit = [&](C2<T> (&w)[R0], void* dst) {
+      wave_fft<T, L, true>(w, col, bs, g, tw);
+      wave_sync();
+      C2<T>* tile = DBL ? tiles + tb * NX * TS : tiles;
+      auto row = [](int x) { return DBL ? x : padrow(x); };
+#pragma unroll
+      for (int i = 0; i < R0 / 2; ++i) tile[row(g + G * i) * TS + p] = w[i];
+      __syncthreads();
+      C2<T>* d = (C2<T>*)dst + obase;
+      for (int e = threadIdx.x; e < NX * P; e += NT) {
+        const int x = e / P, c = e - (e / P) * P;
+        d[(long long)x * M1 + c] = tile[row(x) * TS + c];
+      }
+      if (DBL) tb ^= 1;
+      else __syncthreads();
+    };
+
+    if (a.diff == D_NONE) {
+      wave_fft<T, L, false, true>(v, col, bs, g, tw);
+      green(v);
+      emit(v, a.out[t.grp]);
+    } else if (!ADJ && a.diff == D_CURL) {
+      // one component per output group: psi_c, plus B = d_x psi_y (c = 1) or
+      // A = -d_x psi_z (c = 2)
+      const int c = t.grp;
+      wave_fft<T, L, false, true>(v, col, bs, g, tw);
+      green(v);
+      if (c > 0) {
+        C2<T> u[R0];
+        const T sgn = c == 1 ? (T)1 : (T)-1;
+#pragma unroll
+        for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
+        emit(u, a.out[c == 1 ? 4 : 3]);
+      }
+      emit(v, a.out[c]);
+    } else if (ADJ && a.diff == D_ADJ_CURL) {
+      C2<T> S[3][R0];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (a.in[c]) {
+          load(S[c], a.in[c]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < R0; ++i) S[c][i] = {(T)0, (T)0};
+        }
+      }
+      // the curl is symmetric: g_i enters S_{i+1} with +i k_{i+2}, S_{i+2} with -i k_{i+1}
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (!a.in[3 + c]) continue;
+        C2<T> w[R0];
+        load(w, a.in[3 + c]);
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+#pragma unroll
+        for (int i = 0; i < R0; ++i) {
+          const C2<T> iw = cmuli(w[i]);
+          S[c1][i] = cadd(S[c1][i], cscale(iw, kcomp(c2, i)));
+          S[c2][i] = csub(S[c2][i], cscale(iw, kcomp(c1, i)));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        green(S[c]);
+        emit(S[c], a.out[c]);
+      }
+    } else {  // scalar gradient and its transpose
+      C2<T> S[R0];
+      if (a.in[0]) {
+        load(S, a.in[0]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < R0; ++i) S[i] = {(T)0, (T)0};
+      }
+      if (ADJ) {
+        // transpose of the gradient: minus the divergence
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (!a.in[1 + c]) continue;
+          C2<T> w[R0];
+          load(w, a.in[1 + c]);
+#pragma unroll
+          for (int i = 0; i < R0; ++i) S[i] = csub(S[i], cscale(cmuli(w[i]), kcomp(c, i)));
+        }
+      }
+      green(S);
+      if (!ADJ) {
+        C2<T> u[R0];
+#pragma unroll
+        for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(S[i]), kx(i));
+        emit(u, a.out[1]);
+      }
+      emit(S, a.out[0]);
+    }
+    lt = nxt;
+    if (lt >= ntiles) break;
   }
 }
 
@@ -413,7 +519,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   C2<T>* col = DBL ? exch + p * padded(L) : tiles + p;
   constexpr int bs = DBL ? 1 : TS;
   const long long ibase = ((long long)(valid ? kzl0 + p : 0) * n0 + x) * L;
-  const long long obase = (long long)x * K2 + kz0;
+  const long long obase = (long long)x * a.c1_ld + kz0;
   const int nvalid = min(P, a.kz_count - kzl0);
   auto kyv = [&](int i) -> T { return (T)(a.kc[1] * signed_index(g + G * i, L)); };
   const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
@@ -435,7 +541,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
     C2<T>* d = (C2<T>*)dst + obase;
     for (int e = threadIdx.x; e < NY * P; e += NT) {
       const int y = e / P, c = e - (e / P) * P;
-      if (c < nvalid) d[(long long)y * n0 * K2 + c] = tile[row(y) * TS + c];
+      if (c < nvalid) d[(long long)y * n0 * a.c1_ld + c] = tile[row(y) * TS + c];
     }
     if (DBL) tb ^= 1;
     else __syncthreads();
@@ -515,8 +621,8 @@ __global__ void __launch_bounds__(kThreads) kf_c2r(const PassArgs a) {
     const int y = valid ? (int)(pr / xpairs) : 0;
     const int xa = valid ? 2 * (int)(pr % xpairs) : 0, xb = xa + 1;
     const bool vb = valid && xb < n0;
-    const C2<T>* pa = in + ((long long)y * n0 + xa) * K2;
-    const C2<T>* pb = pa + K2;
+    const C2<T>* pa = in + ((long long)y * n0 + xa) * a.c1_ld;
+    const C2<T>* pb = pa + a.c1_ld;
     C2<T> v[R0];
 #pragma unroll
     for (int i = 0; i < R0; ++i) {
@@ -605,8 +711,44 @@ static void allow_lds() {
   }
 }
 
+// Workgroups that fit on the device at once (persistent launches), or the
+// tile count when HP_PERSIST=0.
+template <auto K>
+static int persistent_grid(int nt, int lds, int ntiles) {
+  static int cached_lds = -1, per_cu = 1;  // one cache per kernel instantiation
+  if (cached_lds != lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, nt, lds) != hipSuccess || n < 1) {
+      (void)hipGetLastError();
+      n = 1;
+    }
+    per_cu = n;
+    cached_lds = lds;
+  }
+  static int cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  if (!cus[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) {
+      (void)hipGetLastError();
+      c = 1;
+    }
+    cus[dev] = c;
+  }
+  const char* e = std::getenv("HP_PERSIST");
+  if (e && std::atoi(e) == 0) return ntiles;
+  const long long g = (long long)per_cu * cus[dev];
+  return (int)std::max(1LL, std::min<long long>(g, ntiles));
+}
+
 template <typename T, int L, int P>
-static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
+static hipError_t launch_LP(const PassArgs& a0, int grid_y, hipStream_t s) {
+  PassArgs a = a0;
+  a.ngrp = grid_y;
   const int n0 = a.un[0], n1 = a.un[1];
   const int lds = a.lds_bytes;
   switch (a.fast) {
@@ -622,24 +764,19 @@ static hipError_t launch_LP(const PassArgs& a, int grid_y, hipStream_t s) {
     } break;
     case FAST_SANDWICH: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
-      dim3 grid((a.gM[1] / P) * a.kz_count, grid_y);
+      const int ntiles = (a.gM[1] / P) * a.kz_count * grid_y;
       const bool adj = a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD;
+      auto go = [&](auto kern) {
+        allow_lds<decltype(kern)::value>();
+        const int nb = persistent_grid<decltype(kern)::value>(NT, lds, ntiles);
+        hipLaunchKernelGGL(decltype(kern)::value, dim3(nb), dim3(NT), lds, s, a);
+      };
       if (a.emit_dbl) {  // double-buffered output tiles
-        if (adj) {
-          allow_lds<kf_sandwich<T, L, P, true, true>>();
-          hipLaunchKernelGGL((kf_sandwich<T, L, P, true, true>), grid, dim3(NT), lds, s, a);
-        } else {
-          allow_lds<kf_sandwich<T, L, P, false, true>>();
-          hipLaunchKernelGGL((kf_sandwich<T, L, P, false, true>), grid, dim3(NT), lds, s, a);
-        }
+        if (adj) go(std::integral_constant<decltype(&kf_sandwich<T, L, P, true, true>), &kf_sandwich<T, L, P, true, true>>{});
+        else go(std::integral_constant<decltype(&kf_sandwich<T, L, P, false, true>), &kf_sandwich<T, L, P, false, true>>{});
       } else {
-        if (adj) {
-          allow_lds<kf_sandwich<T, L, P, true, false>>();
-          hipLaunchKernelGGL((kf_sandwich<T, L, P, true, false>), grid, dim3(NT), lds, s, a);
-        } else {
-          allow_lds<kf_sandwich<T, L, P, false, false>>();
-          hipLaunchKernelGGL((kf_sandwich<T, L, P, false, false>), grid, dim3(NT), lds, s, a);
-        }
+        if (adj) go(std::integral_constant<decltype(&kf_sandwich<T, L, P, true, false>), &kf_sandwich<T, L, P, true, false>>{});
+        else go(std::integral_constant<decltype(&kf_sandwich<T, L, P, false, false>), &kf_sandwich<T, L, P, false, false>>{});
       }
     } break;
     case FAST_INV_Y: {

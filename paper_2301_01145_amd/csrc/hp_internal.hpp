@@ -75,6 +75,8 @@ struct PassArgs {
   int iy_mode;             // InvYMode of the backward y pass
   int kz_base, kz_count;   // kz slab of the y and x passes (B2 / C2 hold kz_count planes)
   int emit_dbl;            // x / backward-y passes: double-buffered output tiles
+  int c1_ld;               // row length (kz) of C1[y][x][kz]: K2 rounded up to 16
+  int ngrp;                // x pass: output groups per tile (set at launch)
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,

@@ -149,6 +149,35 @@ def test_unbounded_adjoint(diff, ncomp, prec, with_psi, nc):
     check(got, ref, prec, "adjoint")
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nc", [[10, 12, 8], [32, 64, 32]])
+def test_unbounded_adjoint_partial_gradients(prec, nc):
+    """Plain vector adjoint with only one upstream gradient bound: the other
+    components of grad_f are the transpose applied to zero, i.e. zero."""
+    import torch
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd import Solver
+    rng = np.random.default_rng(23)
+    shape = tuple(nc)
+    rnd = np.float32 if prec == "f32" else np.float64
+    g1 = rng.normal(size=shape).astype(rnd).astype(np.float64)
+    gpsi = np.zeros((3,) + shape)
+    gpsi[1] = g1
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver("unbounded", "staggered", nc, LO, HI, diff="none", dtype=dtype, ncomp=3)
+    gp = [None, torch.as_tensor(g1, dtype=dtype, device="cuda"), None]
+    # poison the outputs: every component must be written
+    gf = [torch.full(shape, float("nan"), dtype=dtype, device="cuda") for _ in range(3)]
+    out = s.adjoint(gp, None, gf)
+    torch.cuda.synchronize()
+    got = np.stack([o.double().cpu().numpy() for o in out])
+    hs = [(HI[a] - LO[a]) / nc[a] for a in range(3)]
+    ref = ub.adjoint_unbounded(gpsi, None, hs, 2.0 * max(hs), "none")
+    s.close()
+    assert np.all(got[0] == 0) and np.all(got[2] == 0)
+    check(got[1], ref[1], prec, "adjoint component 1")
+
+
 @pytest.mark.parametrize("bc,grid,nc", [("periodic", "staggered", [1, 8]), ("neumann", "regular", [1]),
                                         ("dirichlet", "staggered", [1]), ("dirichlet", "regular", [2, 3]),
                                         ("periodic", "regular", [4096]), ("dirichlet", "regular", [2048]),

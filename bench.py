@@ -11,6 +11,7 @@ same way and reported beside it, with the FP32 error against it.
 Prints one JSON line (rank 0).  Usage: python bench.py [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +22,40 @@ sys.path.insert(0, ROOT)
 
 METRIC = "3D Poisson solves/s + HBM GB/s at 256^3 unbounded, FP32 vs FP64 at stated err"
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_digest():
+    """sha256 over the library sources (name + bytes, sorted): HBM counters
+    recorded for one digest do not describe kernels built from another."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2301_01145_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(pass_name, n):
+    """HBM bytes per launch of `pass_name` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy-kernel
+    factors), or None when there is none for these sources."""
+    path = os.path.join(PROFILES, f"unbounded{n}_curl_fp32_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    digest, traffic = None, {}
+    with open(path) as fh:
+        for line in fh:
+            t = line.strip().strip("`").split()
+            if len(t) == 2 and t[0] == "source_sha256:":
+                digest = t[1]
+            elif len(t) == 4 and t[0] == "traffic_bytes:":
+                traffic[t[1]] = float(t[2]) + float(t[3])
+    if digest != kernel_source_digest():
+        return None
+    return traffic.get(pass_name)
 
 
 def parse():
@@ -232,8 +267,8 @@ def main():
         "model_gbs": r32["model_bytes"] / (r32["ms"] * 1e-3) / 1e9,
         "model_bytes_per_solve": r32["model_bytes"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": name,
-                     "kernel_ms": pms, "kernel_bytes": pbytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n),
+                     "kernel": name, "kernel_ms": pms, "kernel_bytes": pbytes},
         "passes": [{"name": a, "ms": b, "model_gbs": c / (b * 1e-3) / 1e9 if b > 0 else None}
                    for a, b, c in r32["passes"]],
     })

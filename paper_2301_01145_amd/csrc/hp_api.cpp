@@ -210,6 +210,43 @@ hp_status twiddles(hp_plan p, int L, const void** out) {
   return HP_OK;
 }
 
+// Twiddles of the wavefront FFT of length L (power of two, 64..1024), per
+// stage after the first: stage 1 (radix 8 after R0) then stage 2 (radix
+// G/8 after 8 R0), each stored [t - 1][k] = W_{NS R}^{t k}, so that the lanes
+// of a wavefront read consecutive entries.  L entries are allocated (the
+// kernels copy L entries to LDS); unused ones are zero.
+hp_status fast_twiddles(hp_plan p, int L, const void** out) {
+  auto it = p->ftw.find(L);
+  if (it != p->ftw.end()) { *out = it->second; return HP_OK; }
+  const int R0 = L >= 1024 ? 16 : 8, G = L / R0;
+  std::vector<double> w(2 * (size_t)L, 0.0);
+  size_t off = 0;
+  auto stage = [&](int NS, int R) {
+    const long long N = (long long)NS * R;
+    for (int t = 1; t < R; ++t)
+      for (int k = 0; k < NS; ++k) {
+        const double ang = 2.0 * M_PI * (double)(((long long)t * k) % N) / (double)N;
+        w[2 * (off + (size_t)(t - 1) * NS + k)] = std::cos(ang);
+        w[2 * (off + (size_t)(t - 1) * NS + k) + 1] = -std::sin(ang);
+      }
+    off += (size_t)(R - 1) * NS;
+  };
+  stage(R0, 8);
+  if (G > 8) stage(8 * R0, G / 8);
+  if (off > (size_t)L) return fail(p, HP_E_UNSUPPORTED, "wavefront FFT twiddle table overflow");
+  void* d;
+  HP_TRY(dev_alloc(p, (size_t)L * 2 * p->es, &d));
+  if (p->prec == 0) {
+    std::vector<float> f(w.begin(), w.end());
+    HP_HIP(p, hipMemcpy(d, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    HP_HIP(p, hipMemcpy(d, w.data(), w.size() * 8, hipMemcpyHostToDevice));
+  }
+  p->ftw[L] = d;
+  *out = d;
+  return HP_OK;
+}
+
 hp_status quarter(hp_plan p, int n, const void** out) {
   auto it = p->qtw.find(n);
   if (it != p->qtw.end()) { *out = it->second; return HP_OK; }
@@ -1011,7 +1048,7 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
       a.kc[b] = 2.0 * M_PI / (P.M[b] * P.h[b]);
     }
     const void* tw;
-    HP_TRY(twiddles(p, L, &tw));
+    HP_TRY(fast_twiddles(p, L, &tw));
     a.tw = tw;
     a.c1_ld = (K2 + 15) / 16 * 16;
     a.emit_dbl = fast_emit_dbl();

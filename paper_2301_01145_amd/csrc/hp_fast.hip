@@ -35,43 +35,61 @@ struct WF {
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
-// LDS row of FFT element m: one pad row every 16 keeps the strided Stockham
-// writes (stride R0 or R NS elements across lanes) within 2x of the
-// conflict-free rate on the LDS banks.
-__host__ __device__ constexpr int padrow(int m) { return m + (m >> 4); }
-__host__ __device__ constexpr int padded(int L) { return L + L / 16; }
+// LDS layouts of the FFT exchange.  Element m of a pencil sits at row
+// m + (m >> S) K of its slot.  The first exchange (stage-0 write, stride R0
+// across lanes; stage-1 read, stride L/8) uses S = 4, K = 1; the second
+// (stage-1 write, runs of 8 at stride 64; stage-2 read) uses S = 5, K = 4
+// (S = 4, K = 2 for L = 128).  In a model of the LDS as 32 banks served 16
+// lanes at a time every access of both exchanges is conflict-free (the first
+// exchange's is within 2x in a 64-bank model).
+template <int S, int K>
+struct Pad {
+  static constexpr int S_ = S, K_ = K;
+  __host__ __device__ static constexpr int row(int m) { return m + (m >> S) * K; }
+};
+using PadA = Pad<4, 1>;
+template <int L>
+using PadB = typename std::conditional<(L >= 256), Pad<5, 4>, Pad<4, 2>>::type;
 
-// Rows of the elements a + t S (t = 0, 1, ...) as padrow(a) + t * step:
-// exact when S is a multiple of 16, so every access of a pattern shares one
-// base address and differs by an immediate offset.
-template <int S>
+__host__ __device__ constexpr int padrow(int m) { return PadA::row(m); }
+// rows of one exchange slot (both layouts)
+__host__ __device__ constexpr int slot_len(int L) {
+  const int a = PadA::row(L - 1) + 1;
+  const int b = (L >= 256 ? Pad<5, 4>::row(L - 1) : Pad<4, 2>::row(L - 1)) + 1;
+  return a > b ? a : b;
+}
+
+// Rows of the elements a + t S' (t = 0, 1, ...) in layout PD: one base row
+// plus a constant step when S' is a multiple of 2^S, so every access of a
+// pattern shares one address and differs by an immediate offset.
+template <typename PD, int SP>
 __device__ __forceinline__ int padrun(int a, int t) {
-  if constexpr (S % 16 == 0) return padrow(a) + t * padded(S);
-  else return padrow(a + t * S);
+  if constexpr (SP % (1 << PD::S_) == 0) return PD::row(a) + t * PD::row(SP);
+  else return PD::row(a + t * SP);
 }
 
 // One Stockham stage (radix R, NS = product of earlier radices) over the
-// wavefront slot `buf` (element m at buf[padrow(m) * bs]).
-template <typename T, int L, int R, int NS, bool LAST, bool INV>
+// wavefront slot `buf`: reads in layout PR, writes (unless LAST) in layout PW.
+// twS holds this stage's twiddles as twS[(t - 1) NS + k] = W_{NS R}^{t k}.
+template <typename T, int L, int R, int NS, bool LAST, bool INV, typename PR, typename PW>
 __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs, int g,
-                                       const C2<T>* tw) {
+                                       const C2<T>* twS) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, NB = R0 / R;
   C2<T> v[R0];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
 #pragma unroll
-    for (int t = 0; t < R; ++t) v[b * R + t] = buf[padrun<L / R>(j, t) * bs];
+    for (int t = 0; t < R; ++t) v[b * R + t] = buf[padrun<PR, L / R>(j, t) * bs];
   }
   wave_sync();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = g + G * b;
     const int k = j % NS;
-    const int ks = k * (L / (NS * R));
 #pragma unroll
     for (int t = 1; t < R; ++t) {
-      C2<T> w = tw[t * ks];
+      C2<T> w = twS[(t - 1) * NS + k];
       if (INV) w.im = -w.im;
       v[b * R + t] = cmul(v[b * R + t], w);
     }
@@ -85,9 +103,11 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         int row;
-        if constexpr (NS % 16 == 0) row = padrow(m0 + k) + t * padded(NS);
-        else if constexpr (NS == 8) row = padrow(m0) + k + 8 * t + (t >> 1);  // k < 8
-        else row = padrow(m0 + k + t * NS);
+        // NS and 2^S are powers of two and m0 is a multiple of 2^S: for
+        // NS >= 2^S the step is constant; for NS < 2^S, k < NS keeps
+        // k + NS t within the same 2^S block as NS t
+        if constexpr (NS % (1 << PW::S_) == 0) row = PW::row(m0 + k) + t * PW::row(NS);
+        else row = PW::row(m0) + k + NS * t + ((NS * t) >> PW::S_) * PW::K_;
         buf[row * bs] = v[b * R + t];
       }
     }
@@ -96,7 +116,8 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
 }
 
 // In-place FFT of the pencil held as x[i] = x[g + G i]; on return x[i] = X[g + G i].
-// HALF: x[i] is zero for i >= R0 / 2 (zero-padded input).
+// HALF: x[i] is zero for i >= R0 / 2 (zero-padded input).  tw is the
+// per-stage twiddle table (stage 1 at 0, stage 2 at 7 R0).
 template <typename T, int L, bool INV, bool HALF = false>
 __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs, int g,
                                          const C2<T>* tw) {
@@ -105,15 +126,15 @@ __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int 
   else dftN<T, R0, INV>(x);
   wave_sync();
   // element g R0 + t, t < R0 in {8, 16}: never crosses a multiple of 16
-  const int r0 = padrow(g * R0);
+  const int r0 = PadA::row(g * R0);
 #pragma unroll
   for (int t = 0; t < R0; ++t) buf[(r0 + t) * bs] = x[t];
   wave_sync();
   if constexpr (G == 8) {
-    wstage<T, L, 8, R0, true, INV>(x, buf, bs, g, tw);
+    wstage<T, L, 8, R0, true, INV, PadA, PadA>(x, buf, bs, g, tw);
   } else {
-    wstage<T, L, 8, R0, false, INV>(x, buf, bs, g, tw);
-    wstage<T, L, G / 8, 8 * R0, true, INV>(x, buf, bs, g, tw);
+    wstage<T, L, 8, R0, false, INV, PadA, PadB<L>>(x, buf, bs, g, tw);
+    wstage<T, L, G / 8, 8 * R0, true, INV, PadB<L>, PadB<L>>(x, buf, bs, g, tw + 7 * R0);
   }
 }
 
@@ -156,7 +177,7 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
-  C2<T>* tile = exch + NW * PPW * padded(L);
+  C2<T>* tile = exch + NW * PPW * slot_len(L);
   const T* in = (const T*)a.in[blockIdx.y];
   C2<T>* out = (C2<T>*)a.out[blockIdx.y];
   if (!in) return;
@@ -167,7 +188,7 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  C2<T>* buf = exch + (wave * PPW + q) * padded(L);
+  C2<T>* buf = exch + (wave * PPW + q) * slot_len(L);
   for (int pr0 = wave * PPW; pr0 < P / 2; pr0 += NW * PPW) {
     const int pr = pr0 + q;
     const int ya = y0 + 2 * pr, yb = ya + 1;
@@ -186,7 +207,7 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
     wave_fft<T, L, false, true>(v, buf, 1, g, tw);
     wave_sync();
 #pragma unroll
-    for (int i = 0; i < R0; ++i) buf[padrun<G>(g, i)] = v[i];
+    for (int i = 0; i < R0; ++i) buf[padrun<PadA, G>(g, i)] = v[i];
     wave_sync();
     if (pr < P / 2) {
 #pragma unroll
@@ -249,7 +270,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
     wave_sync();
     if (p < P) {
 #pragma unroll
-      for (int i = 0; i < R0; ++i) col[padrun<G>(g, i) * TS] = v[i];
+      for (int i = 0; i < R0; ++i) col[padrun<PadA, G>(g, i) * TS] = v[i];
     }
     wave_sync();
   }
@@ -285,11 +306,11 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
   constexpr int NT = 64 * (P / PPW), TS = P + 1, NX = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   // DBL: per-pencil exchange slots and two alternating [NX][P] output tiles
-  // (one barrier per output field); otherwise one [padded(L)][P] tile whose
+  // (one barrier per output field); otherwise one [slot_len(L)][P] tile whose
   // columns are the exchange slots (two barriers per output field).
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
-  C2<T>* tiles = DBL ? exch + P * padded(L) : exch;
+  C2<T>* tiles = DBL ? exch + P * slot_len(L) : exch;
   const int M1 = a.gM[1], M2 = a.gM[2];
   const int ytiles = M1 / P;  // even: M1 is a power of two >= 64, P <= 16
   const int ngrp = a.ngrp;
@@ -300,7 +321,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   const int p = wave * PPW + q;
-  C2<T>* col = DBL ? exch + p * padded(L) : tiles + p;
+  C2<T>* col = DBL ? exch + p * slot_len(L) : tiles + p;
   constexpr int bs = DBL ? 1 : TS;
   auto kx = [&](int i) -> T { return (T)(a.kc[0] * signed_index(g + G * i, L)); };
 
@@ -503,7 +524,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
-  C2<T>* tiles = DBL ? exch + P * padded(L) : exch;
+  C2<T>* tiles = DBL ? exch + P * slot_len(L) : exch;
   const int n0 = a.un[0];
   const int M2 = a.gM[2], K2 = M2 / 2 + 1;
   const int ztiles = (a.kz_count + P - 1) / P;
@@ -516,7 +537,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   const int p = wave * PPW + q;
   const int kz = kz0 + p;
   const bool valid = kzl0 + p < a.kz_count;
-  C2<T>* col = DBL ? exch + p * padded(L) : tiles + p;
+  C2<T>* col = DBL ? exch + p * slot_len(L) : tiles + p;
   constexpr int bs = DBL ? 1 : TS;
   const long long ibase = ((long long)(valid ? kzl0 + p : 0) * n0 + x) * L;
   const long long obase = (long long)x * a.c1_ld + kz0;
@@ -611,7 +632,7 @@ __global__ void __launch_bounds__(kThreads) kf_c2r(const PassArgs a) {
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
-  C2<T>* buf = exch + (wave * PPW + q) * padded(L);
+  C2<T>* buf = exch + (wave * PPW + q) * slot_len(L);
   const int xpairs = (n0 + 1) / 2;
   const long long total = (long long)n1 * xpairs;
   for (long long grp = (long long)blockIdx.x * 4 + wave; grp * PPW < total;
@@ -680,7 +701,7 @@ int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl) {
   const int cs = prec == 0 ? 8 : 16;
   const int R0 = L >= 1024 ? 16 : 8;
   const int ppw = 64 / (L / R0);
-  const int SL = padded(L);
+  const int SL = slot_len(L);
   switch (fast) {
     case FAST_R2C: return (L + ((P / 2 + ppw - 1) / ppw) * ppw * SL + K2 * (P + 1)) * cs;
     case FAST_FWD_Y: return (L + SL * (P + 1)) * cs;

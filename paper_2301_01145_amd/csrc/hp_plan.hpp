@@ -54,6 +54,7 @@ struct hp_plan_s {
   std::vector<void*> allocs;
   std::map<int, void*> tw;   // L -> W_L table
   std::map<int, void*> qtw;  // n -> exp(-i pi j / 2n)
+  std::map<int, void*> ftw;  // L -> per-stage wavefront-FFT twiddles
   std::string err;
   size_t ws_bytes = 0;
   int alloc_count = 0;

@@ -108,7 +108,7 @@ bool factorize(int L, int* radix, int* nstage) {
   return true;
 }
 
-int maxe(int prec) { return prec == 0 ? 32 : 16; }
+int maxe(int prec) { return prec == 0 ? kMaxeF32 : kMaxeF32 / 2; }
 
 // Pick the tile width P (power of two) for a pass; returns 0 if nothing fits.
 // lds(P) gives the LDS bytes, nfft(P) the transforms per FFT call.
@@ -181,7 +181,7 @@ hp_status validate(const hp_desc* d) {
     if (!factorize(L, rad, &ns))
       return fail(nullptr, HP_E_UNSUPPORTED,
                   "transform length " + std::to_string(L) + " is not a product of 2, 3 and 5");
-    if ((long long)L > (long long)maxe(d->prec) * kThreads / (d->prec == 0 ? 1 : 1))
+    if ((long long)L > (long long)(d->prec == 0 ? 32 : 16) * kMaxLenThreads)
       return fail(nullptr, HP_E_UNSUPPORTED, "transform length too large");
   }
   return HP_OK;
@@ -586,12 +586,37 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
 }
 
 // --------------------------------------------------------- pass lists
+// Wavefront-FFT kernels for the bounded passes (hp_bounded.hip): 2D / 3D
+// single plans whose every transform length is a power of two in [64, 512].
+bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
+  if (std::getenv("HP_GENERIC") || p->batched || P.nd < 2) return false;
+  for (int a = 0; a < P.nd; ++a) {
+    if (L[a] < 64 || L[a] > 512 || (L[a] & (L[a] - 1))) return false;
+    for (int k = FAST_R2R_C; k <= FAST_R2R_SW; ++k)
+      if (r2r_lds_bytes(k, L[a], P.n[a], p->prec) > 160 * 1024) return false;
+  }
+  return true;
+}
+
+// Switch a general bounded pass (same descriptor) to its wavefront kernel.
+hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
+  const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
+  a.fast = a.kind == PK_SANDWICH ? FAST_R2R_SW : (contig ? FAST_R2R_C : FAST_R2R_S);
+  const void* tw;
+  HP_TRY(fast_twiddles(p, a.L, &tw));
+  a.tw = tw;
+  a.P = r2r_tile(p->prec);
+  a.lds_bytes = r2r_lds_bytes(a.fast, a.L, a.n, p->prec);
+  return HP_OK;
+}
+
 hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   const hp_desc& d = P.d;
   const int nd = P.nd;
   int xf[3], xb[3], L[3];
   double c[3];
   for (int a = 0; a < nd; ++a) r2r_ops(d.bc, d.grid, P.n[a], &xf[a], &xb[a], &L[a], &c[a]);
+  const size_t first_pass = out.size();
   // work view = the output array (interior for REGULAR Dirichlet)
   int od[3] = {1, 1, 1}, idims[3] = {1, 1, 1};
   for (int a = 0; a < nd; ++a) { od[a] = P.nout[a]; idims[a] = P.n[a]; }
@@ -749,6 +774,8 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
     }
   }
+  if (bounded_fast_ok(p, P, L))
+    for (size_t i = first_pass; i < out.size(); ++i) HP_TRY(to_fast_r2r(p, out[i].a));
   return HP_OK;
 }
 
@@ -1051,7 +1078,7 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     HP_TRY(fast_twiddles(p, L, &tw));
     a.tw = tw;
     a.c1_ld = (K2 + 15) / 16 * 16;
-    a.emit_dbl = fast_emit_dbl();
+    a.emit_dbl = fast_emit_dbl(kind);
     if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl) > 160 * 1024) a.emit_dbl = 0;
     a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl);
     out.push_back({a, 1});
@@ -1167,7 +1194,8 @@ double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
 }
 
 const char* pass_name(const PassArgs& a) {
-  static const char* fast_names[] = {"", "r2c_z", "fwd_y", "sandwich_x", "inv_y", "c2r_z"};
+  static const char* fast_names[] = {"",       "r2c_z",      "fwd_y",       "sandwich_x", "inv_y",
+                                     "c2r_z",  "r2r_contig", "r2r_strided", "r2r_sandwich"};
   if (a.fast) return fast_names[a.fast];
   if (a.kind == PK_SANDWICH) return "sandwich";
   switch (a.xf) {
@@ -1202,8 +1230,9 @@ hp_status run_passes(hp_plan p, const std::vector<PassRec>& ps) {
       HP_TRY(next_event(p, &e1));
       HP_HIP(p, hipEventRecord(e0, p->stream));
     }
-    hipError_t e = r.a.fast ? launch_fast(r.a, p->prec, r.grid_y, p->stream)
-                            : launch_pass(r.a, p->prec, r.grid_y, p->stream);
+    hipError_t e = r.a.fast >= FAST_R2R_C ? launch_bounded(r.a, p->prec, p->stream)
+                   : r.a.fast               ? launch_fast(r.a, p->prec, r.grid_y, p->stream)
+                                            : launch_pass(r.a, p->prec, r.grid_y, p->stream);
     if (e != hipSuccess) return fail(p, HP_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
     if (p->timing) {
       HP_HIP(p, hipEventRecord(e1, p->stream));

@@ -29,7 +29,21 @@ enum MultKind : int { M_NONE = 0, M_EIGEN = 1, M_GREEN = 2 };
 // Derivative coupling inside the sandwich pass.
 enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_CURL = 4 };
 
-constexpr int kThreads = 256;
+// Threads per workgroup of the general pencil kernels (and the persistent
+// batched kernel); the wavefront-FFT kernels size their own workgroups.
+#ifndef HP_GEN_THREADS
+#define HP_GEN_THREADS 256
+#endif
+constexpr int kThreads = HP_GEN_THREADS;
+// Complex elements per thread held in registers by one FFT stage of the
+// general kernels (FP32; FP64 holds half as many).
+#ifndef HP_GEN_MAXE
+#define HP_GEN_MAXE 32
+#endif
+constexpr int kMaxeF32 = HP_GEN_MAXE;
+// Longest transform of the general path: 32 (FP32) or 16 (FP64) elements per
+// thread of a 256-thread workgroup.
+constexpr int kMaxLenThreads = 256;
 constexpr int kMaxStages = 8;
 constexpr int kMaxFields = 6;
 
@@ -80,15 +94,20 @@ struct PassArgs {
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
-                      FAST_INV_Y = 4, FAST_C2R = 5 };
+                      FAST_INV_Y = 4, FAST_C2R = 5,
+                      // bounded real-to-real passes (hp_bounded.hip)
+                      FAST_R2R_C = 6, FAST_R2R_S = 7, FAST_R2R_SW = 8 };
 // Derivative completion in the backward y pass of the free-space path.
 enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
+hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s);
+int r2r_tile(int prec);
+int r2r_lds_bytes(int fast, int L, int n, int prec);
 // Dynamic LDS bytes of a wavefront-FFT pass; 0 if the pass is not available.
 int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl);
-int fast_emit_dbl();
+int fast_emit_dbl(int fast);
 // Pencils per workgroup of the wavefront-FFT passes.
 int fast_tile(int fast, int L, int prec);
 

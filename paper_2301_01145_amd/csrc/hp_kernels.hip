@@ -14,6 +14,7 @@
 // eq. ft_sd), transforms back and stores, so the spectrum of that axis never
 // leaves LDS.
 #include "hp_device.hpp"
+#include "hp_faces.hpp"
 #include "hp_internal.hpp"
 
 namespace hp {
@@ -68,11 +69,11 @@ __device__ __attribute__((noinline)) void fft_stage(C2<T>* Z, int L, int nfft, i
 
 template <typename T>
 struct Maxe {
-  static constexpr int v = 32;
+  static constexpr int v = kMaxeF32;
 };
 template <>
 struct Maxe<double> {
-  static constexpr int v = 16;
+  static constexpr int v = kMaxeF32 / 2;
 };
 
 // Full FFT of nfft transforms in LDS (caller has synchronised the input).
@@ -131,37 +132,6 @@ __device__ __forceinline__ void tile_pj(int e, int P, int cnt, int jfast, int& p
     j = e / P;
     p = e - j * P;
   }
-}
-
-// Boundary terms of inhomogeneous FD2 problems (added to the source value of
-// an unknown next to a face).
-template <typename T>
-__device__ __forceinline__ double face_terms(const PassArgs& a, int j, int p, int o) {
-  int c[3] = {0, 0, 0};
-  if (a.ax_j >= 0) c[a.ax_j] = j;
-  if (a.ax_p >= 0) c[a.ax_p] = p;
-  if (a.ax_o >= 0) c[a.ax_o] = o;
-  double add = 0.0;
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const T* g = (const T*)a.face[ax][side];
-      if (!g) continue;
-      const int edge = side == 0 ? 0 : a.nunk[ax] - 1;
-      if (c[ax] != edge) continue;
-      long long off = 0;
-      int r = 0;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        if (b == ax || a.nunk[b] <= 0) continue;
-        if (r < 2) off += (long long)(c[b] + a.face_off) * a.face_s[ax][r];
-        ++r;
-      }
-      add += a.face_w[ax][side] * (double)g[off];
-    }
-  }
-  return add;
 }
 
 // ---------------------------------------------------------------- loading

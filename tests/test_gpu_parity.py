@@ -53,6 +53,36 @@ def test_bounded_tiles(bc, grid, prec):
     check(got, ref, prec, "psi")
 
 
+# Power-of-two transform lengths in [64, 512] on every axis: the wavefront-FFT
+# bounded kernels (ragged 32-pencil tiles where an axis has N_c - 1 or
+# N_c + 1 unknowns).
+FASTB = [([64, 32, 128], "fd2", True), ([32, 64, 32], "ps", False), ([64, 128], "fd2", True),
+         ([128, 32], "ps", False), ([256, 32, 32], "fd2", True), ([32, 32, 256], "ps", False)]
+
+
+@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("dirichlet", "staggered"),
+                                     ("neumann", "regular"), ("neumann", "staggered")])
+@pytest.mark.parametrize("nc,kernel,inhom", FASTB)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bounded_fast(bc, grid, nc, kernel, inhom, prec):
+    nd = len(nc)
+    f, faces = case_input(bc, grid, nc, 1, inhom, prec, seed=17 + nd)
+    got, _ = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", prec, 1, faces)
+    ref, _ = oracle_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", faces)
+    check(got, ref, prec, "psi")
+
+
+@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("neumann", "staggered")])
+def test_bounded_fast_matches_general(bc, grid, monkeypatch):
+    """The same power-of-two problem through the wavefront and the general kernels."""
+    nc = [64, 32, 128]
+    f, faces = case_input(bc, grid, nc, 1, True, "f64", seed=29)
+    fast, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", "f64", 1, faces)
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", "f64", 1, faces)
+    check(fast, gen, "f64", "fast vs general")
+
+
 @pytest.mark.parametrize("nd,nc", [(1, [12]), (1, [9]), (2, [12, 10]), (2, [9, 15]), (3, [12, 10, 9]),
                                    (3, [20, 24, 30])])
 @pytest.mark.parametrize("kernel", ["ps", "fd2"])

@@ -601,6 +601,9 @@ bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
 // Switch a general bounded pass (same descriptor) to its wavefront kernel.
 hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
   const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
+  bool faces = false;
+  for (int ax = 0; ax < 3; ++ax) faces |= a.face[ax][0] != nullptr || a.face[ax][1] != nullptr;
+  if (faces && !contig) return HP_OK;  // boundary terms: contiguous passes only
   a.fast = a.kind == PK_SANDWICH ? FAST_R2R_SW : (contig ? FAST_R2R_C : FAST_R2R_S);
   const void* tw;
   HP_TRY(fast_twiddles(p, a.L, &tw));

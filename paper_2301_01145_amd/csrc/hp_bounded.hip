@@ -123,10 +123,12 @@ __device__ __forceinline__ void r2r_fft(C2<T> (&v)[WF<L>::R0], int x, int n, C2<
 
 // Multiplier norm / (sum of the eigenvalues) at spectral index k along the
 // pencil axis, given the eigenvalue sum `rest` of the other axes.
+// (the eigenvalue sum is formed in FP64; an FP32 plan divides in FP32)
 template <typename T>
 __device__ __forceinline__ T eigen_mult(const PassArgs& a, int k, double rest) {
   const double lam = a.lam[a.ax_j][k] + rest;
-  return lam == 0.0 ? (T)0 : (T)(a.norm / lam);
+  if (lam == 0.0) return (T)0;
+  return (T)a.norm / (T)lam;
 }
 
 __device__ __forceinline__ double eigen_rest(const PassArgs& a, int p, int o) {
@@ -202,77 +204,124 @@ __global__ void __launch_bounds__(64 * kR2RContigWaves) kb_contig(const PassArgs
 // contiguous axis is p.  The tile [n][P] (reals) is loaded as runs of P,
 // wavefront pairs transform columns (2f, 2f+1) in place in it, and it is
 // stored as runs of P.  SW: sandwich (forward, multiplier, backward).
-template <typename T, int L, int P, bool SW>
-__global__ void __launch_bounds__(64 * (P / 2 / WF<L>::PPW)) kb_strided(const PassArgs a) {
+//
+// PERS (persistent): a workgroup walks tiles blockIdx-strided; every thread
+// loads its share of the next tile into registers before the current tile's
+// FFTs and writes it to LDS after the current tile has been stored.  Chosen
+// when there are many more tiles than resident workgroups.
+// (Boundary terms enter in the contiguous first pass only.)
+template <typename T, int L, int P, int W, bool SW, bool PERS>
+__global__ void __launch_bounds__(64 * W) kb_strided(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
-  constexpr int NT = 64 * (P / 2 / PPW), TS = P + 1;
+  constexpr int NT = 64 * W, TS = P + 1;
+  constexpr int MAXN = L / 2 + 1;             // rows of a tile (n <= L/2 + 1)
+  constexpr int PER = (MAXN * P + NT - 1) / NT;  // tile elements per thread
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = a.n;
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* q = tw + L;
   C2<T>* slots = q + n;
-  T* tile = (T*)(slots + (P / 2) * slot_len(L));
+  T* tile = (T*)(slots + W * PPW * slot_len(L));
   const int tiles_p = (a.Np + P - 1) / P;
-  const int o = blockIdx.x / tiles_p, p0 = (blockIdx.x % tiles_p) * P;
-  const int np = min(P, a.Np - p0);
+  const int ntiles = tiles_p * a.No;
+  int t = blockIdx.x;
+  if (t >= ntiles) return;  // whole workgroup
   for (int m = threadIdx.x; m < L; m += NT) tw[m] = ((const C2<T>*)a.tw)[m];
   if (a.qtw)
     for (int m = threadIdx.x; m < n; m += NT) q[m] = ((const C2<T>*)a.qtw)[m];
-  const bool faces = has_faces(a);
-  {
-    const T* in = (const T*)a.in[0];
+  const T* in = (const T*)a.in[0];
+  T* out = (T*)a.out[0];
+  T pre[PER];
+  auto fetch = [&](int tt) {
+    const int o = tt / tiles_p, p0 = (tt % tiles_p) * P;
+    const int np = min(P, a.Np - p0);
+    const long long ib = (long long)o * a.in_so + (long long)p0 * a.in_sp;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * NT;
+      const int j = e / P, c = e - (e / P) * P;
+      pre[r] = (j < n && c < np) ? in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = threadIdx.x + r * NT;
+      const int j = e / P, c = e - (e / P) * P;
+      if (j < n) tile[j * TS + c] = pre[r];
+    }
+  };
+  if constexpr (PERS) {
+    fetch(t);
+    put();
+  } else {
+    const int o = t / tiles_p, p0 = (t % tiles_p) * P;
+    const int np = min(P, a.Np - p0);
     const long long ib = (long long)o * a.in_so + (long long)p0 * a.in_sp;
     for (int e = threadIdx.x; e < n * P; e += NT) {
       const int j = e / P, c = e - (e / P) * P;
-      T v = (T)0;
-      if (c < np) {
-        v = in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp];
-        if (faces) v = (T)((double)v + face_terms<T>(a, j, p0 + c, o));
-      }
-      tile[j * TS + c] = v;
+      tile[j * TS + c] = c < np ? in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
     }
   }
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int qq = lane / G, g = lane % G;
-  const int f = wave * PPW + qq;  // pair: columns 2f, 2f + 1
-  C2<T>* slot = slots + f * slot_len(L);
-  T* ca = tile + 2 * f;
-  auto get = [&](int s, int w) { return ca[s * TS + w]; };
-  C2<T> v[R0];
-  r2r_fft<T, L>(v, a.xf, n, slot, g, tw, q, get);
-  int x_out = a.xf;
-  if (SW) {
-    // spectra times the multiplier, back into the pair's columns
-    const int pa = min(p0 + 2 * f, a.Np - 1), pb = min(p0 + 2 * f + 1, a.Np - 1);
-    const double ra = eigen_rest(a, pa, o), rb = eigen_rest(a, pb, o);
+  const int qq = lane / G, g_lane = lane % G;
+  C2<T>* slot = slots + (wave * PPW + qq) * slot_len(L);
+  for (;;) {
+    const int o = t / tiles_p, p0 = (t % tiles_p) * P;
+    const int np = min(P, a.Np - p0);
+    const int nxt = PERS ? t + (int)gridDim.x : ntiles;
+    if (PERS && nxt < ntiles) fetch(nxt);
+    // the FFT's LDS addresses depend only on the lane: keep the compiler from
+    // holding them in registers across the tile loop
+    int g = g_lane;
+    if constexpr (PERS) asm volatile("" : "+v"(g));
+    static_assert(P / 2 == W * PPW, "one pair per wavefront lane group");
+    {
+      const int f = wave * PPW + qq;  // pair: columns 2f, 2f + 1
+      T* ca = tile + 2 * f;
+      auto get = [&](int s, int w) { return ca[s * TS + w]; };
+      C2<T> v[R0];
+      r2r_fft<T, L>(v, a.xf, n, slot, g, tw, q, get);
+      int x_out = a.xf;
+      if (SW) {
+        // spectra times the multiplier, back into the pair's columns
+        const int pa = min(p0 + 2 * f, a.Np - 1), pb = min(p0 + 2 * f + 1, a.Np - 1);
+        const double ra = eigen_rest(a, pa, o), rb = eigen_rest(a, pb, o);
 #pragma unroll
-    for (int i = 0; i < R0; ++i) {
-      T sa, sb;
-      const int k = r2r_extract<T>(a.xf, g + G * i, n, v[i], q, sa, sb);
-      if (k < 0) continue;
-      ca[k * TS] = sa * eigen_mult<T>(a, k, ra);
-      ca[k * TS + 1] = sb * eigen_mult<T>(a, k, rb);
+        for (int i = 0; i < R0; ++i) {
+          T sa, sb;
+          const int k = r2r_extract<T>(a.xf, g + G * i, n, v[i], q, sa, sb);
+          if (k < 0) continue;
+          ca[k * TS] = sa * eigen_mult<T>(a, k, ra);
+          ca[k * TS + 1] = sb * eigen_mult<T>(a, k, rb);
+        }
+        wave_sync();
+        r2r_fft<T, L>(v, a.xb, n, slot, g, tw, q, get);
+        x_out = a.xb;
+      }
+      // outputs into the pair's columns (the inputs were consumed above)
+#pragma unroll
+      for (int i = 0; i < R0; ++i) {
+        T oa, obv;
+        const int k = r2r_extract<T>(x_out, g + G * i, n, v[i], q, oa, obv);
+        if (k < 0) continue;
+        ca[k * TS] = oa;
+        ca[k * TS + 1] = obv;
+      }
+      wave_sync();  // the slot is reused by the next pair
     }
-    wave_sync();
-    r2r_fft<T, L>(v, a.xb, n, slot, g, tw, q, get);
-    x_out = a.xb;
-  }
-  // outputs into the pair's columns (the inputs were consumed above)
-#pragma unroll
-  for (int i = 0; i < R0; ++i) {
-    T oa, obv;
-    const int k = r2r_extract<T>(x_out, g + G * i, n, v[i], q, oa, obv);
-    if (k < 0) continue;
-    ca[k * TS] = oa;
-    ca[k * TS + 1] = obv;
-  }
-  __syncthreads();
-  T* out = (T*)a.out[0];
-  const long long ob = (long long)o * a.out_so + (long long)p0 * a.out_sp;
-  for (int e = threadIdx.x; e < n * P; e += NT) {
-    const int j = e / P, c = e - (e / P) * P;
-    if (c < np) out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp] = tile[j * TS + c];
+    __syncthreads();
+    const long long ob = (long long)o * a.out_so + (long long)p0 * a.out_sp;
+    for (int e = threadIdx.x; e < n * P; e += NT) {
+      const int j = e / P, c = e - (e / P) * P;
+      if (c < np) out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp] = tile[j * TS + c];
+    }
+    t = nxt;
+    if (!PERS || t >= ntiles) break;
+    __syncthreads();  // the tile has been read out
+    put();
+    __syncthreads();
   }
 }
 
@@ -280,13 +329,17 @@ __global__ void __launch_bounds__(64 * (P / 2 / WF<L>::PPW)) kb_strided(const Pa
 // Pencils per tile of the strided passes: runs of 128 bytes.
 int r2r_tile(int prec) { return prec == 0 ? 32 : 16; }
 
+// Wavefronts per strided workgroup: one per pair (PPW pairs per wavefront
+// for short transforms).
+constexpr int r2r_waves(int P, int ppw) { return (P / 2) / ppw; }
+
 int r2r_lds_bytes(int fast, int L, int n, int prec) {
   const int cs = prec == 0 ? 8 : 16, es = cs / 2;
   const int R0 = L >= 1024 ? 16 : 8, ppw = 64 / (L / R0);
   const int SL = slot_len(L);
   if (fast == FAST_R2R_C) return (L + n + kR2RContigWaves * ppw * SL) * cs;
   const int P = r2r_tile(prec);
-  return (L + n + (P / 2) * SL) * cs + n * (P + 1) * es;
+  return (L + n + r2r_waves(P, ppw) * ppw * SL) * cs + n * (P + 1) * es;
 }
 
 namespace {
@@ -304,15 +357,28 @@ hipError_t launch_bounded_L(const PassArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   constexpr int P = sizeof(T) == 4 ? 32 : 16;
-  constexpr int NT = 64 * (P / 2 / PPW);
+  constexpr int W = r2r_waves(P, PPW);
   if (a.P != P) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(((a.Np + P - 1) / P) * a.No));
+  const int ntiles = (int)grid.x;
   if (a.fast == FAST_R2R_SW) {
-    allow_lds<kb_strided<T, L, P, true>>();
-    hipLaunchKernelGGL((kb_strided<T, L, P, true>), grid, dim3(NT), lds, s, a);
+    allow_lds<kb_strided<T, L, P, W, true, true>>();
+    const int nb = persistent_grid<kb_strided<T, L, P, W, true, true>>(64 * W, lds, ntiles);
+    if (ntiles > 4 * nb && !std::getenv("HP_R2R_NOPERS")) {
+      hipLaunchKernelGGL((kb_strided<T, L, P, W, true, true>), dim3(nb), dim3(64 * W), lds, s, a);
+    } else {
+      allow_lds<kb_strided<T, L, P, W, true, false>>();
+      hipLaunchKernelGGL((kb_strided<T, L, P, W, true, false>), grid, dim3(64 * W), lds, s, a);
+    }
   } else {
-    allow_lds<kb_strided<T, L, P, false>>();
-    hipLaunchKernelGGL((kb_strided<T, L, P, false>), grid, dim3(NT), lds, s, a);
+    allow_lds<kb_strided<T, L, P, W, false, true>>();
+    const int nb = persistent_grid<kb_strided<T, L, P, W, false, true>>(64 * W, lds, ntiles);
+    if (ntiles > 4 * nb) {
+      hipLaunchKernelGGL((kb_strided<T, L, P, W, false, true>), dim3(nb), dim3(64 * W), lds, s, a);
+    } else {
+      allow_lds<kb_strided<T, L, P, W, false, false>>();
+      hipLaunchKernelGGL((kb_strided<T, L, P, W, false, false>), grid, dim3(64 * W), lds, s, a);
+    }
   }
   return hipGetLastError();
 }

@@ -5,6 +5,7 @@
 // ordered pass level by pass level, with per-pass completion counters as the
 // only dependencies between workgroups.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "hp_plan.hpp"
@@ -34,6 +35,15 @@ hp_status build_all(hp_plan p, bool placeholders, std::vector<std::vector<PassRe
 
 int tiles_of(const PassArgs& a) { return ((a.Np + a.P - 1) / a.P) * a.No; }
 
+int batch_tiles_per_item() {
+  if (const char* e = std::getenv("HP_BATCH_TILES")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 64) return v;
+  }
+  return 4;
+}
+const int kBatchTilesPerItem = batch_tiles_per_item();
+
 }  // namespace
 
 hp_status batched_setup(hp_plan p) {
@@ -61,8 +71,11 @@ hp_status batched_setup(hp_plan p) {
       const int gp = first[q] + lev;
       const int dep = lev > 0 ? gp - 1 : -1;
       const int need = lev > 0 ? tiles_of(lists[q][lev - 1].a) : 0;
+      // consecutive tiles of a pass share one item (one queue step, one
+      // dependency check and one release per item)
       const int nt = tiles_of(lists[q][lev].a);
-      for (int t = 0; t < nt; ++t) items.push_back({gp, t, dep, need});
+      for (int t = 0; t < nt; t += kBatchTilesPerItem)
+        items.push_back({gp, t, std::min(kBatchTilesPerItem, nt - t), dep, need});
     }
   }
   p->batch_nitems = (int)items.size();

@@ -124,14 +124,15 @@ hipError_t launch_octant(const double* spec, const int M[3], double scale, void*
 // face arrays (node with several faces: highest axis wins).
 hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, const void* face[3][2],
                                  int prec, hipStream_t s);
-// One tile of one pass of the batched persistent solve.  `dep` is the global
+// Consecutive tiles of one pass of the batched persistent solve.  `dep` is the global
 // index of the pass that must be complete first (-1: none) and `need` its tile
 // count; items are ordered so that every dependency has lower item indices.
 struct BatchItem {
   int pass;
-  int tile;
-  int dep;
-  int need;
+  int tile;   // first tile of the item
+  int ntile;  // consecutive tiles of the pass in the item
+  int dep;    // pass whose tiles must all be done first (-1: none)
+  int need;   // tile count of that pass
 };
 
 // Persistent batched solve: counters[0] is the work-queue head, counters[1 + i]

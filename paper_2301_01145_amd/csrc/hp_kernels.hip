@@ -634,21 +634,28 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
     }
     __syncthreads();
     const int ok = __builtin_amdgcn_readfirstlane(s_ok);
-    __threadfence();
+    // acquire: the tiles written by the workgroups that completed the pass
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (ok) {
       const PassArgs& a = passes[bi.pass];
       const int tiles_p = (a.Np + a.P - 1) / a.P;
-      Tile t;
-      t.o = bi.tile / tiles_p;
-      t.p0 = (bi.tile - t.o * tiles_p) * a.P;
-      t.np = min(a.P, a.Np - t.p0);
-      if (a.kind == PK_ONEWAY) oneway<T>(a, smem, t, 0);
-      else sandwich_r2r<T>(a, smem, t, 0);
+      for (int k = 0; k < bi.ntile; ++k) {
+        const int tile = bi.tile + k;
+        Tile t;
+        t.o = tile / tiles_p;
+        t.p0 = (tile - t.o * tiles_p) * a.P;
+        t.np = min(a.P, a.Np - t.p0);
+        if (a.kind == PK_ONEWAY) oneway<T>(a, smem, t, 0);
+        else sandwich_r2r<T>(a, smem, t, 0);
+        __syncthreads();  // LDS reuse by the next tile
+      }
     }
-    __threadfence();
+    // release: this item's stores before its tiles are counted
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(&counters[1 + bi.pass], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&counters[1 + bi.pass], (unsigned)bi.ntile, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
 }

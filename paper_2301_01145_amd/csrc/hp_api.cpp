@@ -485,7 +485,7 @@ hp_status setup_problem(hp_plan p, Problem& P) {
     }
     size_t kzmax = 0;
     for (auto& s : P.slabs) kzmax = std::max(kzmax, (size_t)s.second);
-    // C1[y][x][kz] rows (fast path) are padded to a multiple of 16 elements,
+    // C1 [x][y][kz] rows (fast path) are padded to a multiple of 16 elements,
     // so that the backward y pass writes whole 128-byte lines
     const size_t K2c = fast ? (K2 + 15) / 16 * 16 : K2;
     for (int f = 0; f < nf; ++f) {
@@ -1021,7 +1021,7 @@ hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<Pass
 
 // Wavefront-FFT free-space passes (every doubled length a power of two in
 // [64, 1024]).  Layouts (complex): A1 [x][kz][y], B2 [kz][ky][x],
-// C2 [kz][x][ky], C1 [y][x][kz] (C1 reuses the A1 buffers).  Every pass reads
+// C2 [kz][x][ky], C1 [x][y][kz] (C1 reuses the A1 buffers).  Every pass reads
 // contiguous pencils; strided sides are written through LDS tiles.
 bool fast_unbounded_ok(hp_plan p, const Problem& P) {
   if (std::getenv("HP_GENERIC")) return false;
@@ -1081,6 +1081,9 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     HP_TRY(fast_twiddles(p, L, &tw));
     a.tw = tw;
     a.c1_ld = (K2 + 15) / 16 * 16;
+    // C1 [x][y][kz]: the backward y pass writes rows y of one x close together
+    a.c1_sx = (long long)P.n[1] * a.c1_ld;
+    a.c1_sy = a.c1_ld;
     a.emit_dbl = fast_emit_dbl(kind);
     if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl) > 160 * 1024) a.emit_dbl = 0;
     a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl);

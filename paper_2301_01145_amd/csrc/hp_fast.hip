@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
 // A workgroup takes P consecutive pencils (x, kz0 .. kz0+P-1) of C2[kz][x][ky]
 // (each contiguous, all M1 wavenumbers), transforms them back along y and keeps
 // y < n1, written through an [L][P] tile (columns = FFT exchange slots) as runs
-// of P along kz into C1[y][x][kz].  In curl mode the five inputs psi_x, psi_y,
+// of P along kz into C1 ([x][y][kz]).  In curl mode the five inputs psi_x, psi_y,
 // psi_z, A, B give psi and u = curl psi (u_x = d_y psi_z - d_z psi_y,
 // u_y = d_z psi_x + A, u_z = B - d_y psi_x); in gradient mode psi, d_x psi give
 // psi and grad psi.  At most two spectra are live per lane.
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   C2<T>* col = DBL ? exch + p * slot_len(L) : tiles + p;
   constexpr int bs = DBL ? 1 : TS;
   const long long ibase = ((long long)(valid ? kzl0 + p : 0) * n0 + x) * L;
-  const long long obase = (long long)x * a.c1_ld + kz0;
+  const long long obase = (long long)x * a.c1_sx + kz0;
   const int nvalid = min(P, a.kz_count - kzl0);
   auto kyv = [&](int i) -> T { return (T)(a.kc[1] * signed_index(g + G * i, L)); };
   const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
     C2<T>* d = (C2<T>*)dst + obase;
     for (int e = threadIdx.x; e < NY * P; e += NT) {
       const int y = e / P, c = e - (e / P) * P;
-      if (c < nvalid) d[(long long)y * n0 * a.c1_ld + c] = tile[row(y) * TS + c];
+      if (c < nvalid) d[(long long)y * a.c1_sy + c] = tile[row(y) * TS + c];
     }
     if (DBL) tb ^= 1;
     else __syncthreads();
@@ -487,8 +487,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
 }
 
 // --------------------------------------------------------------- P5: C2R (z)
-// Half spectra C1[y][x][kz] (kz < K2, contiguous) of pencils (x, y) and
-// (x + 1, y) form one complex inverse FFT (Hermitian completion); z < n2 of
+// Half spectra C1 (kz < K2 contiguous; [x][y][kz]) of pencils (x, y) and
+// (x, y + 1) form one complex inverse FFT (Hermitian completion); z < n2 of
 // both rows is stored into the real output [x][y][z].
 template <typename T, int L>
 __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
@@ -506,17 +506,17 @@ __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int q = lane / G, g = lane % G;
   C2<T>* buf = exch + (wave * PPW + q) * slot_len(L);
-  const int xpairs = (n0 + 1) / 2;
-  const long long total = (long long)n1 * xpairs;
+  const int ypairs = (n1 + 1) / 2;
+  const long long total = (long long)n0 * ypairs;
   for (long long grp = (long long)blockIdx.x * 4 + wave; grp * PPW < total;
        grp += (long long)gridDim.x * 4) {
     const long long pr = grp * PPW + q;
     const bool valid = pr < total;
-    const int y = valid ? (int)(pr / xpairs) : 0;
-    const int xa = valid ? 2 * (int)(pr % xpairs) : 0, xb = xa + 1;
-    const bool vb = valid && xb < n0;
-    const C2<T>* pa = in + ((long long)y * n0 + xa) * a.c1_ld;
-    const C2<T>* pb = pa + a.c1_ld;
+    const int x = valid ? (int)(pr / ypairs) : 0;
+    const int ya = valid ? 2 * (int)(pr % ypairs) : 0, yb = ya + 1;
+    const bool vb = valid && yb < n1;
+    const C2<T>* pa = in + (long long)ya * a.c1_sy + (long long)x * a.c1_sx;
+    const C2<T>* pb = pa + a.c1_sy;
     C2<T> v[R0];
 #pragma unroll
     for (int i = 0; i < R0; ++i) {
@@ -535,8 +535,8 @@ __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
       v[i] = {A.re - B.im, A.im + B.re};
     }
     wave_fft<T, L, true>(v, buf, 1, g, tw);
-    T* oa = out + ((long long)xa * n1 + y) * n2;
-    T* ob = out + ((long long)xb * n1 + y) * n2;
+    T* oa = out + ((long long)x * n1 + ya) * n2;
+    T* ob = oa + n2;
 #pragma unroll
     for (int i = 0; i < R0 / 2; ++i) {
       if (valid) oa[g + G * i] = v[i].re;
@@ -646,7 +646,7 @@ template <typename T, int L>
 static hipError_t launch_L(const PassArgs& a, int grid_y, hipStream_t s) {
   if (a.fast == FAST_C2R) {
     const int n0 = a.un[0], n1 = a.un[1];
-    const long long pairs = (long long)n1 * ((n0 + 1) / 2);
+    const long long pairs = (long long)n0 * ((n1 + 1) / 2);
     const long long groups = (pairs + WF<L>::PPW - 1) / WF<L>::PPW;
     dim3 grid((unsigned)((groups + 3) / 4), grid_y);
     allow_lds<kf_c2r<T, L>>();

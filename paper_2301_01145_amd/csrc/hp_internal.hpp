@@ -89,7 +89,8 @@ struct PassArgs {
   int iy_mode;             // InvYMode of the backward y pass
   int kz_base, kz_count;   // kz slab of the y and x passes (B2 / C2 hold kz_count planes)
   int emit_dbl;            // x / backward-y passes: double-buffered output tiles
-  int c1_ld;               // row length (kz) of C1[y][x][kz]: K2 rounded up to 16
+  int c1_ld;               // row length (kz) of C1: K2 rounded up to 16
+  long long c1_sx, c1_sy;  // C1 strides (elements) of x and y
   int ngrp;                // x pass: output groups per tile (set at launch)
 };
 

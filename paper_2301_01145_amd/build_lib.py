@@ -18,21 +18,27 @@ FLAGS = [
 
 
 def build(verbose=False):
+    """Compile every source (in parallel) and link libhipoisson.so."""
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    objs = []
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = ["hipcc"] + FLAGS[:-0 or None] + ["-c"] + lang + [os.path.join(CSRC, src), "-o", obj,
+        cmd = ["hipcc"] + FLAGS + ["-c"] + lang + [os.path.join(CSRC, src), "-o", obj,
                "-I", os.path.join(ROOT, "include"), "-I", CSRC]
         cmd = [c for c in cmd if c != "-shared"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError("hipcc failed on " + src)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
         objs.append(obj)
+    failed = []
+    for src, pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out + err)
+            failed.append(src)
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -108,12 +108,13 @@ bool factorize(int L, int* radix, int* nstage) {
   return true;
 }
 
-int maxe(int prec) { return prec == 0 ? kMaxeF32 : kMaxeF32 / 2; }
+// Complex elements per thread of a general-kernel FFT stage (PassArgs.big).
+int maxe(int prec, int big) { return (big ? 32 : 16) / (prec == 0 ? 1 : 2); }
 
 // Pick the tile width P (power of two) for a pass; returns 0 if nothing fits.
 // lds(P) gives the LDS bytes, nfft(P) the transforms per FFT call.
 template <class F1, class F2>
-int choose_P(int want, int minP, int Np, int L, int prec, F1 lds, F2 nfft, int* lds_out) {
+int choose_P(int want, int minP, int Np, int L, int prec, int big, F1 lds, F2 nfft, int* lds_out) {
   int cap = 1;
   while (cap < Np) cap <<= 1;
   int P = want;
@@ -121,7 +122,7 @@ int choose_P(int want, int minP, int Np, int L, int prec, F1 lds, F2 nfft, int* 
   const int budgets[2] = {64 * 1024, 160 * 1024};
   for (int b = 0; b < 2; ++b) {
     for (int q = P; q >= minP; q >>= 1) {
-      if ((long long)nfft(q) * L <= (long long)maxe(prec) * kThreads && lds(q) <= budgets[b]) {
+      if ((long long)nfft(q) * L <= (long long)maxe(prec, big) * kThreads && lds(q) <= budgets[b]) {
         *lds_out = (int)lds(q);
         return q;
       }
@@ -373,7 +374,8 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
         a.Np = M[1]; a.No = M[0];
         a.in_jfast = a.out_jfast = 1;
         int lds;
-        a.P = choose_P(16, 2, a.Np, a.L, 1,
+        a.big = 1;
+        a.P = choose_P(16, 2, a.Np, a.L, 1, 1,
                        [&](int q) { return (long long)(q / 2) * a.L * 16 + (long long)q * a.nin * 8; },
                        [&](int q) { return q / 2; }, &lds);
         a.lds_bytes = lds;
@@ -386,7 +388,8 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
         a.Np = K2; a.No = axis == 1 ? M[0] : M[1];
         a.in_jfast = a.out_jfast = 0;
         int lds;
-        a.P = choose_P(8, 1, a.Np, a.L, 1, [&](int q) { return (long long)q * a.L * 16; },
+        a.big = 1;
+        a.P = choose_P(8, 1, a.Np, a.L, 1, 1, [&](int q) { return (long long)q * a.L * 16; },
                        [&](int q) { return q; }, &lds);
         a.lds_bytes = lds;
       }
@@ -549,36 +552,42 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
   int lds = 0;
   auto nfft_pair = [](int q) { return q / 2; };
   auto nfft_one = [](int q) { return q; };
-  switch (lds_kind) {
-    case 0:  // one-way complex
-      a.P = choose_P(want, minP, a.Np, a.L, p->prec, [&](int q) { return (long long)q * a.L * cs; }, nfft_one, &lds);
-      break;
-    case 1:  // one-way real input (pairs)
-      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
-                     [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
-      break;
-    case 2:  // one-way C2R (pairs, complex staging)
-      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
-                     [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * cs; }, nfft_pair, &lds);
-      break;
-    case 3:  // r2r sandwich
-      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
-                     [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
-      break;
-    case 4: {  // c2c sandwich: (nS + 1) complex tiles
-      const int nS = (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) ? a.n_out : a.n_in;
-      a.P = choose_P(want, minP, a.Np, a.L, p->prec,
-                     [&](int q) { return (long long)(nS + 1) * q * a.L * cs; }, nfft_one, &lds);
-    } break;
-    case 5: {  // paired c2c sandwich (1D periodic)
-      const int nS = a.n_in;
-      a.P = choose_P(want, 2, a.Np, a.L, p->prec,
-                     [&](int q) {
-                       return (long long)nS * (q / 2) * a.L * cs +
-                              std::max((long long)(q / 2) * a.L * cs, (long long)q * a.nin * es);
-                     },
-                     nfft_pair, &lds);
-    } break;
+  // the smaller register budget first (more resident waves), the larger one
+  // when a tile of this length does not fit it
+  for (int big = 0; big < 2; ++big) {
+    a.big = big;
+    switch (lds_kind) {
+      case 0:  // one-way complex
+        a.P = choose_P(want, minP, a.Np, a.L, p->prec, big, [&](int q) { return (long long)q * a.L * cs; }, nfft_one, &lds);
+        break;
+      case 1:  // one-way real input (pairs)
+        a.P = choose_P(want, 2, a.Np, a.L, p->prec, big,
+                       [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
+        break;
+      case 2:  // one-way C2R (pairs, complex staging)
+        a.P = choose_P(want, 2, a.Np, a.L, p->prec, big,
+                       [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * cs; }, nfft_pair, &lds);
+        break;
+      case 3:  // r2r sandwich
+        a.P = choose_P(want, 2, a.Np, a.L, p->prec, big,
+                       [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
+        break;
+      case 4: {  // c2c sandwich: (nS + 1) complex tiles
+        const int nS = (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) ? a.n_out : a.n_in;
+        a.P = choose_P(want, minP, a.Np, a.L, p->prec, big,
+                       [&](int q) { return (long long)(nS + 1) * q * a.L * cs; }, nfft_one, &lds);
+      } break;
+      case 5: {  // paired c2c sandwich (1D periodic)
+        const int nS = a.n_in;
+        a.P = choose_P(want, 2, a.Np, a.L, p->prec, big,
+                       [&](int q) {
+                         return (long long)nS * (q / 2) * a.L * cs +
+                                std::max((long long)(q / 2) * a.L * cs, (long long)q * a.nin * es);
+                       },
+                       nfft_pair, &lds);
+      } break;
+    }
+    if (a.P > 0) break;
   }
   if (a.P == 0) return fail(p, HP_E_UNSUPPORTED, "pass of length " + std::to_string(a.L) + " does not fit in LDS");
   a.lds_bytes = lds;

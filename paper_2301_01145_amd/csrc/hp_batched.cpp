@@ -57,13 +57,17 @@ hp_status batched_setup(hp_plan p) {
   if (s != HP_OK) return s;
   // items: pass level by pass level, problems in order, tiles in order
   std::vector<int> first(lists.size(), 0);
-  int npass = 0, maxlev = 0, lds = 0;
+  int npass = 0, maxlev = 0, lds = 0, big = 0;
   for (size_t q = 0; q < lists.size(); ++q) {
     first[q] = npass;
     npass += (int)lists[q].size();
     maxlev = std::max(maxlev, (int)lists[q].size());
-    for (auto& r : lists[q]) lds = std::max(lds, r.a.lds_bytes);
+    for (auto& r : lists[q]) {
+      lds = std::max(lds, r.a.lds_bytes);
+      big = std::max(big, r.a.big);
+    }
   }
+  p->batch_big = big;
   std::vector<BatchItem> items;
   for (int lev = 0; lev < maxlev; ++lev) {
     for (size_t q = 0; q < lists.size(); ++q) {
@@ -97,7 +101,7 @@ hp_status batched_setup(hp_plan p) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return plan_fail(p, HP_E_DEVICE, "device query failed");
-  const int per_cu = batched_blocks_per_cu(lds, p->prec);
+  const int per_cu = batched_blocks_per_cu(lds, p->prec, big);
   p->batch_grid = std::max(1, std::min(p->batch_nitems, per_cu * cus));
   // keep the pass list (placeholder pointers) for the byte model
   p->batch_passes.clear();
@@ -143,7 +147,7 @@ hp_status batched_solve(hp_plan p) {
   hipError_t e = launch_batched((const PassArgs*)p->batch_probs, (const BatchItem*)p->batch_items,
                                 p->batch_nitems, p->batch_counters, p->batch_ncounters,
                                 (int*)(p->batch_counters + p->batch_ncounters), p->batch_grid,
-                                p->batch_lds, p->prec, p->stream);
+                                p->batch_lds, p->prec, p->batch_big, p->stream);
   if (e != hipSuccess)
     return plan_fail(p, HP_E_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
   p->solved = true;

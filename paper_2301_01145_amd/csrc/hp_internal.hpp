@@ -35,12 +35,6 @@ enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_
 #define HP_GEN_THREADS 256
 #endif
 constexpr int kThreads = HP_GEN_THREADS;
-// Complex elements per thread held in registers by one FFT stage of the
-// general kernels (FP32; FP64 holds half as many).
-#ifndef HP_GEN_MAXE
-#define HP_GEN_MAXE 32
-#endif
-constexpr int kMaxeF32 = HP_GEN_MAXE;
 // Longest transform of the general path: 32 (FP32) or 16 (FP64) elements per
 // thread of a 256-thread workgroup.
 constexpr int kMaxLenThreads = 256;
@@ -82,6 +76,7 @@ struct PassArgs {
   double face_w[3][2];     // weight applied to g
   int nunk[3];             // unknown counts per logical axis
   int lds_bytes;
+  int big;                 // general kernels: 1 = the larger per-thread register budget
   // wavefront-FFT kernels of the free-space path (0: general pass)
   int fast;                // FAST_* below
   int un[3];               // physical (undoubled) sizes n_a
@@ -141,7 +136,7 @@ struct BatchItem {
 // to 1 if a dependency wait exceeds its spin limit (the item is then skipped).
 hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int nitems,
                           unsigned* counters, int ncounters, int* err, int grid, int lds,
-                          int prec, hipStream_t s);
+                          int prec, int big, hipStream_t s);
 // Resident workgroups per CU of the persistent kernel with `lds` bytes of LDS.
-int batched_blocks_per_cu(int lds, int prec);
+int batched_blocks_per_cu(int lds, int prec, int big);
 }  // namespace hp

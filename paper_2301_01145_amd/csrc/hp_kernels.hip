@@ -67,19 +67,18 @@ __device__ __attribute__((noinline)) void fft_stage(C2<T>* Z, int L, int nfft, i
   __syncthreads();
 }
 
-template <typename T>
+// Complex elements per thread of one stage: BIG = 0 holds 16 (FP32) / 8
+// (FP64), fewer registers and more resident waves; BIG = 1 holds 32 / 16 for
+// tiles of long transforms.
+template <typename T, int BIG>
 struct Maxe {
-  static constexpr int v = kMaxeF32;
-};
-template <>
-struct Maxe<double> {
-  static constexpr int v = kMaxeF32 / 2;
+  static constexpr int v = (BIG ? 32 : 16) / (sizeof(T) == 8 ? 2 : 1);
 };
 
 // Full FFT of nfft transforms in LDS (caller has synchronised the input).
-template <typename T, bool INV>
+template <typename T, int BIG, bool INV>
 __device__ void fft_lds(C2<T>* Z, int nfft, const PassArgs& a) {
-  constexpr int ME = Maxe<T>::v;
+  constexpr int ME = Maxe<T, BIG>::v;
   const C2<T>* tw = (const C2<T>*)a.tw;
   const int L = a.L;
   int Ns = 1;
@@ -366,7 +365,7 @@ __device__ __forceinline__ T kval(const PassArgs& a, int axis, const int k[3]) {
 }
 
 // ------------------------------------------------------------ pass bodies
-template <typename T>
+template <typename T, int BIG>
 __device__ void oneway(const PassArgs& a, unsigned char* smem, const Tile& t, int field) {
   if (!a.in[field]) return;  // absent field (zero upstream gradient): uniform per block
   C2<T>* Z = (C2<T>*)smem;
@@ -388,14 +387,14 @@ __device__ void oneway(const PassArgs& a, unsigned char* smem, const Tile& t, in
     build_from_real<T>(Z, (const T*)rbuf, x, a, nfft);
   }
   __syncthreads();
-  if (xform_inverse_fft(x)) fft_lds<T, true>(Z, nfft, a);
-  else fft_lds<T, false>(Z, nfft, a);
+  if (xform_inverse_fft(x)) fft_lds<T, BIG, true>(Z, nfft, a);
+  else fft_lds<T, BIG, false>(Z, nfft, a);
   store_out<T>(Z, x, a.out[field], a, t);
 }
 
 // Real-to-real sandwich (Dirichlet / Neumann): forward R2R, multiply by the
 // FD2 / PS multiplier, backward R2R, along the same axis.
-template <typename T>
+template <typename T, int BIG>
 __device__ void sandwich_r2r(const PassArgs& a, unsigned char* smem, const Tile& t, int field) {
   const int nfft = a.P / 2;
   C2<T>* Z = (C2<T>*)smem;
@@ -406,8 +405,8 @@ __device__ void sandwich_r2r(const PassArgs& a, unsigned char* smem, const Tile&
   __syncthreads();
   build_from_real<T>(Z, R, a.xf, a, nfft);
   __syncthreads();
-  if (xform_inverse_fft(a.xf)) fft_lds<T, true>(Z, nfft, a);
-  else fft_lds<T, false>(Z, nfft, a);
+  if (xform_inverse_fft(a.xf)) fft_lds<T, BIG, true>(Z, nfft, a);
+  else fft_lds<T, BIG, false>(Z, nfft, a);
   // spectral values times the multiplier, back into R (same [p][k] layout)
   for (int e = threadIdx.x; e < a.P * a.n; e += kThreads) {
     const int p = e / a.n;
@@ -419,15 +418,15 @@ __device__ void sandwich_r2r(const PassArgs& a, unsigned char* smem, const Tile&
   __syncthreads();
   build_from_real<T>(Z, R, a.xb, a, nfft);
   __syncthreads();
-  if (xform_inverse_fft(a.xb)) fft_lds<T, true>(Z, nfft, a);
-  else fft_lds<T, false>(Z, nfft, a);
+  if (xform_inverse_fft(a.xb)) fft_lds<T, BIG, true>(Z, nfft, a);
+  else fft_lds<T, BIG, false>(Z, nfft, a);
   store_out<T>(Z, a.xb, a.out[field], a, t);
 }
 
 // Complex sandwich (periodic after R2C, unbounded, 1D periodic pairs):
 // every coupled field of the tile is resident: S_c (P x L each) plus a work
 // buffer W for derivative outputs.
-template <typename T>
+template <typename T, int BIG>
 __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile& t) {
   const bool pair = a.xf == X_PAIR_F;
   const int nfft = pair ? a.P / 2 : a.P;
@@ -450,7 +449,7 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
       load_c2c<T>(dst, src, a, t);
     }
     __syncthreads();
-    fft_lds<T, false>(dst, nfft, a);
+    fft_lds<T, BIG, false>(dst, nfft, a);
   };
 
   for (int c = 0; c < nS; ++c) {
@@ -521,33 +520,33 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
         W[e] = v;
       }
       __syncthreads();
-      fft_lds<T, true>(W, nfft, a);
+      fft_lds<T, BIG, true>(W, nfft, a);
       store_out<T>(W, xb, a.out[a.n_in + d], a, t);
       __syncthreads();
     }
   }
   for (int c = 0; c < nS; ++c) {
-    fft_lds<T, true>(S + (size_t)c * tileC, nfft, a);
+    fft_lds<T, BIG, true>(S + (size_t)c * tileC, nfft, a);
     store_out<T>(S + (size_t)c * tileC, xb, a.out[fb + c], a, t);
   }
 }
 
-template <typename T>
+template <typename T, int BIG>
 __global__ void __launch_bounds__(kThreads) k_oneway(const PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  oneway<T>(a, smem, tile_of(a), blockIdx.y);
+  oneway<T, BIG>(a, smem, tile_of(a), blockIdx.y);
 }
 
-template <typename T>
+template <typename T, int BIG>
 __global__ void __launch_bounds__(kThreads) k_sandwich_c2c(const PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sandwich_c2c<T>(a, smem, tile_of(a));
+  sandwich_c2c<T, BIG>(a, smem, tile_of(a));
 }
 
-template <typename T>
+template <typename T, int BIG>
 __global__ void __launch_bounds__(kThreads) k_sandwich_r2r(const PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sandwich_r2r<T>(a, smem, tile_of(a), blockIdx.y);
+  sandwich_r2r<T, BIG>(a, smem, tile_of(a), blockIdx.y);
 }
 
 template <auto K>
@@ -568,24 +567,29 @@ static void allow_lds() {
   }
 }
 
-template <typename T>
+template <typename T, int BIG>
 static void launch_t(const PassArgs& a, dim3 grid, hipStream_t s) {
-  allow_lds<k_oneway<T>>();
-  allow_lds<k_sandwich_c2c<T>>();
-  allow_lds<k_sandwich_r2r<T>>();
+  allow_lds<k_oneway<T, BIG>>();
+  allow_lds<k_sandwich_c2c<T, BIG>>();
+  allow_lds<k_sandwich_r2r<T, BIG>>();
   if (a.kind == PK_ONEWAY)
-    hipLaunchKernelGGL(k_oneway<T>, grid, dim3(kThreads), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((k_oneway<T, BIG>), grid, dim3(kThreads), a.lds_bytes, s, a);
   else if (a.xf == X_C2C_F || a.xf == X_PAIR_F)
-    hipLaunchKernelGGL(k_sandwich_c2c<T>, grid, dim3(kThreads), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((k_sandwich_c2c<T, BIG>), grid, dim3(kThreads), a.lds_bytes, s, a);
   else
-    hipLaunchKernelGGL(k_sandwich_r2r<T>, grid, dim3(kThreads), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((k_sandwich_r2r<T, BIG>), grid, dim3(kThreads), a.lds_bytes, s, a);
 }
 
 hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s) {
   const int tiles = ((a.Np + a.P - 1) / a.P) * a.No;
   dim3 grid(tiles, grid_y);
-  if (prec == 0) launch_t<float>(a, grid, s);
-  else launch_t<double>(a, grid, s);
+  if (prec == 0) {
+    if (a.big) launch_t<float, 1>(a, grid, s);
+    else launch_t<float, 0>(a, grid, s);
+  } else {
+    if (a.big) launch_t<double, 1>(a, grid, s);
+    else launch_t<double, 0>(a, grid, s);
+  }
   return hipGetLastError();
 }
 
@@ -600,7 +604,7 @@ __global__ void k_zero_counters(unsigned* c, int n, int* err) {
   if (blockIdx.x == 0 && threadIdx.x == 0) err[0] = 0;
 }
 
-template <typename T>
+template <typename T, int BIG>
 __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, const BatchItem* items,
                                                       int nitems, unsigned* counters, int* err) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -645,8 +649,8 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
         t.o = tile / tiles_p;
         t.p0 = (tile - t.o * tiles_p) * a.P;
         t.np = min(a.P, a.Np - t.p0);
-        if (a.kind == PK_ONEWAY) oneway<T>(a, smem, t, 0);
-        else sandwich_r2r<T>(a, smem, t, 0);
+        if (a.kind == PK_ONEWAY) oneway<T, BIG>(a, smem, t, 0);
+        else sandwich_r2r<T, BIG>(a, smem, t, 0);
         __syncthreads();  // LDS reuse by the next tile
       }
     }
@@ -660,11 +664,15 @@ __global__ void __launch_bounds__(kThreads) k_batched(const PassArgs* passes, co
   }
 }
 
-int batched_blocks_per_cu(int lds, int prec) {
+int batched_blocks_per_cu(int lds, int prec, int big) {
   int n = 0;
-  hipError_t e = prec == 0
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<float>, kThreads, lds)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<double>, kThreads, lds);
+  hipError_t e;
+  if (prec == 0)
+    e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<float, 1>, kThreads, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<float, 0>, kThreads, lds);
+  else
+    e = big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<double, 1>, kThreads, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<double, 0>, kThreads, lds);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 1;
@@ -672,19 +680,25 @@ int batched_blocks_per_cu(int lds, int prec) {
   return n > 0 ? n : 1;
 }
 
+template <typename T, int BIG>
+static void launch_batched_t(const PassArgs* passes, const BatchItem* items, int nitems,
+                             unsigned* counters, int* err, int grid, int lds, hipStream_t s) {
+  allow_lds<k_batched<T, BIG>>();
+  hipLaunchKernelGGL((k_batched<T, BIG>), dim3(grid), dim3(kThreads), lds, s, passes, items, nitems,
+                     counters, err);
+}
+
 hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int nitems,
                           unsigned* counters, int ncounters, int* err, int grid, int lds,
-                          int prec, hipStream_t s) {
+                          int prec, int big, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_counters, dim3(1 + ncounters / 256), dim3(256), 0, s, counters,
                      ncounters, err);
   if (prec == 0) {
-    allow_lds<k_batched<float>>();
-    hipLaunchKernelGGL(k_batched<float>, dim3(grid), dim3(kThreads), lds, s, passes, items, nitems,
-                       counters, err);
+    if (big) launch_batched_t<float, 1>(passes, items, nitems, counters, err, grid, lds, s);
+    else launch_batched_t<float, 0>(passes, items, nitems, counters, err, grid, lds, s);
   } else {
-    allow_lds<k_batched<double>>();
-    hipLaunchKernelGGL(k_batched<double>, dim3(grid), dim3(kThreads), lds, s, passes, items, nitems,
-                       counters, err);
+    if (big) launch_batched_t<double, 1>(passes, items, nitems, counters, err, grid, lds, s);
+    else launch_batched_t<double, 0>(passes, items, nitems, counters, err, grid, lds, s);
   }
   return hipGetLastError();
 }

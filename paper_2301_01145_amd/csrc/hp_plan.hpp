@@ -64,6 +64,7 @@ struct hp_plan_s {
   void* batch_items = nullptr;
   unsigned* batch_counters = nullptr;
   int batch_nitems = 0, batch_ncounters = 0, batch_grid = 0, batch_lds = 0;
+  int batch_big = 0;  // register budget of the persistent kernel (PassArgs.big)
   std::vector<hp::PassRec> batch_passes;
   std::vector<unsigned char> batch_uploaded;  // pass table last copied to the device
   // per-pass timing

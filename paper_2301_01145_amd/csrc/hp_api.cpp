@@ -452,7 +452,27 @@ hp_status setup_problem(hp_plan p, Problem& P) {
       if (P.nder) HP_TRY(upload(p, wavenumbers(P.n[a], P.h[a], P.n[a]), true, &P.kvec[a]));
     }
     const int nf = P.ncomp + P.nder;
-    if (P.nd >= 2) {
+    // 3D power-of-two plans: the wavefront passes of the free-space path on
+    // undoubled pencils (transform lengths M = n)
+    if (!p->batched) {
+      for (int a = 0; a < 3; ++a) P.M[a] = P.n[a];
+      P.fast_periodic = fast_unbounded_ok(p, P);
+      if (!P.fast_periodic)
+        for (int a = 0; a < 3; ++a) P.M[a] = 2 * P.n[a];
+    }
+    if (P.fast_periodic) {
+      const size_t K2 = (size_t)P.n[2] / 2 + 1, K2c = (K2 + 15) / 16 * 16;
+      P.slabs.assign(1, {0, (int)K2});
+      for (int f = 0; f < nf; ++f) {
+        void* b;
+        HP_TRY(dev_alloc(p, (size_t)P.n[0] * K2c * P.n[1] * 2 * es, &b));
+        P.a1.push_back(b);
+        HP_TRY(dev_alloc(p, K2 * P.n[1] * (size_t)P.n[0] * 2 * es, &b));
+        P.b2.push_back(b);
+        HP_TRY(dev_alloc(p, K2 * P.n[1] * (size_t)P.n[0] * 2 * es, &b));
+        P.c2.push_back(b);
+      }
+    } else if (P.nd >= 2) {
       const size_t K = (size_t)P.n[P.nd - 1] / 2 + 1;
       size_t sz = K;
       for (int a = 0; a < P.nd - 1; ++a) sz *= P.n[a];
@@ -1032,8 +1052,10 @@ hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<Pass
 // [64, 1024]).  Layouts (complex): A1 [x][kz][y], B2 [kz][ky][x],
 // C2 [kz][x][ky], C1 [x][y][kz] (C1 reuses the A1 buffers).  Every pass reads
 // contiguous pencils; strided sides are written through LDS tiles.
+// Also used for 3D periodic plans, whose transform lengths M are then n.
 bool fast_unbounded_ok(hp_plan p, const Problem& P) {
-  if (std::getenv("HP_GENERIC")) return false;
+  if (std::getenv("HP_GENERIC") || P.nd != 3) return false;
+  const bool pad = P.d.bc == HP_UNBOUNDED;
   auto pow2 = [](int v) { return v >= 64 && v <= 1024 && (v & (v - 1)) == 0; };
   for (int a = 0; a < 3; ++a)
     if (!pow2(P.M[a])) return false;
@@ -1042,12 +1064,16 @@ bool fast_unbounded_ok(hp_plan p, const Problem& P) {
   const int K2 = P.M[2] / 2 + 1;
   for (int i = 0; i < 5; ++i) {
     const int Pt = fast_tile(kinds[i], axisL[i], p->prec);
-    if (fast_lds_bytes(kinds[i], axisL[i], Pt, K2, p->prec, 0) > 160 * 1024) return false;
+    if (fast_lds_bytes(kinds[i], axisL[i], Pt, K2, p->prec, 0, pad) > 160 * 1024) return false;
   }
   return true;
 }
 
+// Free-space passes, or (periodic) the same five passes on undoubled
+// pencils with the Table 1 eigenvalue multiplier in place of the Green's
+// function.
 hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
+  const bool periodic = P.d.bc == HP_PERIODIC;
   const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
   const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2];
   const int K2 = M2 / 2 + 1;
@@ -1093,9 +1119,10 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     // C1 [x][y][kz]: the backward y pass writes rows y of one x close together
     a.c1_sx = (long long)P.n[1] * a.c1_ld;
     a.c1_sy = a.c1_ld;
+    a.pad = periodic ? 0 : 1;
     a.emit_dbl = fast_emit_dbl(kind);
-    if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl) > 160 * 1024) a.emit_dbl = 0;
-    a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl);
+    if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl, a.pad) > 160 * 1024) a.emit_dbl = 0;
+    a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl, a.pad);
     out.push_back({a, 1});
     return HP_OK;
   };
@@ -1127,15 +1154,21 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
       PassArgs& a = r.a;
       a.kz_base = kb;
       a.kz_count = kc;
-      a.mult = M_GREEN;
-      a.green = P.green;
-      for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+      if (periodic) {
+        a.mult = M_EIGEN;
+        for (int b = 0; b < 3; ++b) a.lam[b] = P.lam[b];
+        a.norm = P.norm;
+      } else {
+        a.mult = M_GREEN;
+        a.green = P.green;
+        for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+      }
       if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
       else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
       for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
       for (int f = 0; f < n_mid; ++f) a.out[f] = P.c2[f];
       r.grid_y = (a.diff == D_NONE || a.diff == D_CURL) ? nc : 1;
-      const double oct = (double)(M0 / 2 + 1) * (M1 / 2 + 1) * kc * es;
+      const double oct = periodic ? 0.0 : (double)(M0 / 2 + 1) * (M1 / 2 + 1) * kc * es;
       r.bytes = (n_live + n_mid) * (double)kc * M1 * n0 * cs + oct;
     }
     // P4: backward C2C along y (with derivative completion) into C1 (= A1 buffers)
@@ -1168,6 +1201,7 @@ hp_status build_passes(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>
     return passes_unbounded(p, P, adjoint, out);
   }
   if (adjoint) return fail(p, HP_E_UNSUPPORTED, "adjoint solve is provided for unbounded plans");
+  if (P.d.bc == HP_PERIODIC && P.fast_periodic) return passes_unbounded_fast(p, P, false, out);
   if (P.d.bc == HP_PERIODIC) return passes_periodic(p, P, out);
   return passes_bounded(p, P, out);
 }

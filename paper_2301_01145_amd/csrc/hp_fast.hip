@@ -39,9 +39,10 @@ struct R2CShape {
   static constexpr int NT = 64 * NW;
 };
 
-template <typename T, int L, int P>
+template <typename T, int L, int P, bool PAD>
 __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
+  constexpr int NIN = PAD ? R0 / 2 : R0;  // elements per lane read from a row
   constexpr int K2 = L / 2 + 1, TS = P + 1;
   constexpr int NW = R2CShape<L, P>::NW, NT = R2CShape<L, P>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -69,12 +70,12 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
 #pragma unroll
     for (int i = 0; i < R0; ++i) {
       v[i] = {(T)0, (T)0};
-      if (i < R0 / 2) {
+      if (i < NIN) {
         if (va) v[i].re = ra[g + G * i];
         if (vb) v[i].im = rb[g + G * i];
       }
     }
-    wave_fft<T, L, false, true>(v, buf, 1, g, tw);
+    wave_fft<T, L, false, PAD>(v, buf, 1, g, tw);
     wave_sync();
 #pragma unroll
     for (int i = 0; i < R0; ++i) buf[padrun<PadA, G>(g, i)] = v[i];
@@ -105,9 +106,10 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
 // ------------------------------------------------------- P2: forward C2C (y)
 // Pencils (x, kz) of A1, y < n1 of L = M1, written to B2[kz][ky][x] through a
 // [L][P] tile whose columns double as the FFT exchange slots.
-template <typename T, int L, int P>
+template <typename T, int L, int P, bool PAD>
 __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
+  constexpr int NIN = PAD ? R0 / 2 : R0;
   constexpr int TS = P + 1, NT = 64 * (P / PPW);
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
@@ -133,10 +135,10 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
 #pragma unroll
     for (int i = 0; i < R0; ++i) {
       v[i] = {(T)0, (T)0};
-      if (i < R0 / 2 && valid) v[i] = src[g + G * i];
+      if (i < NIN && valid) v[i] = src[g + G * i];
     }
     C2<T>* col = tile + (p < P ? p : 0);
-    wave_fft<T, L, false, true>(v, col, TS, g, tw);
+    wave_fft<T, L, false, PAD>(v, col, TS, g, tw);
     wave_sync();
     if (p < P) {
 #pragma unroll
@@ -168,12 +170,13 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
 // FFTs and stores.  Tile order: kz slowest, then pairs of ky tiles
 // (t, ytiles-1-t) whose wavenumbers +-ky share Green's function rows, then the
 // output groups; the XCD-contiguous numbering keeps such tiles behind one L2.
-template <typename T, int L, int P, bool ADJ, bool DBL>
+template <typename T, int L, int P, bool ADJ, bool DBL, bool PAD>
 __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
                                   (sizeof(T) == 4 && P == 8 && L == 512 && !ADJ) ? 4 : 1)
     kf_sandwich(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
-  constexpr int NT = 64 * (P / PPW), TS = P + 1, NX = L / 2;
+  constexpr int NIN = PAD ? R0 / 2 : R0;  // elements per lane on the x < n0 side
+  constexpr int NT = 64 * (P / PPW), TS = P + 1, NX = PAD ? L / 2 : L;
   extern __shared__ __align__(16) unsigned char smem[];
   // DBL: per-pencil exchange slots and two alternating [NX][P] output tiles
   // (one barrier per output field); otherwise one [slot_len(L)][P] tile whose
@@ -217,25 +220,36 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     return (const T*)a.green + (long long)(a.kz_base + t.kzl) * a.g_s[2] +
            (long long)min(ky, M1 - ky) * a.g_s[1];
   };
+  // spectral multiplier of bin k0 along x: the Green's octant (free space) or
+  // norm / (sum of the Table 1 eigenvalues) (periodic; 0 for the zero mode)
+  auto mult_of = [&](const TileIdx& t, const T* gr, int k0) -> T {
+    if constexpr (PAD) {
+      return gr[min(k0, L - k0)];
+    } else {
+      const double lam = a.lam[0][k0] + a.lam[1][t.ky0 + p] + a.lam[2][a.kz_base + t.kzl];
+      if (lam == 0.0) return (T)0;
+      return (T)a.norm / (T)lam;
+    }
+  };
   // single-input groups (D_NONE, forward curl): prefetched input and Green's values
   const bool pref = a.diff == D_NONE || (!ADJ && a.diff == D_CURL);
   auto src_of = [&](const TileIdx& t) { return a.in[a.diff == D_NONE || a.diff == D_CURL ? t.grp : 0]; };
-  C2<T> pf[R0 / 2];
+  C2<T> pf[NIN];
   T pg[R0];
   auto prefetch = [&](const TileIdx& t) {
     // an unbound field (adjoint with a zero upstream gradient) reads as zero
     const void* src = src_of(t);
-    const T* gr = green_ptr(t);
+    const T* gr = PAD ? green_ptr(t) : nullptr;
     if (src) {
       const C2<T>* sp = in_ptr(t, src);
 #pragma unroll
-      for (int i = 0; i < R0 / 2; ++i) pf[i] = sp[g + G * i];
+      for (int i = 0; i < NIN; ++i) pf[i] = sp[g + G * i];
     } else {
 #pragma unroll
-      for (int i = 0; i < R0 / 2; ++i) pf[i] = {(T)0, (T)0};
+      for (int i = 0; i < NIN; ++i) pf[i] = {(T)0, (T)0};
     }
 #pragma unroll
-    for (int i = 0; i < R0; ++i) pg[i] = gr[min(g + G * i, L - g - G * i)];
+    for (int i = 0; i < R0; ++i) pg[i] = mult_of(t, gr, g + G * i);
   };
   TileIdx cur = decode(lt);
   if (pref) prefetch(cur);
@@ -254,7 +268,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     if (pref) {
 #pragma unroll
       for (int i = 0; i < R0; ++i) {
-        v[i] = i < R0 / 2 ? pf[i] : C2<T>{(T)0, (T)0};
+        v[i] = i < NIN ? pf[i] : C2<T>{(T)0, (T)0};
         gv[i] = pg[i];
       }
     }
@@ -268,17 +282,17 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
 #pragma unroll
         for (int i = 0; i < R0; ++i) w[i] = cscale(w[i], gv[i]);
       } else {
-        const T* gr = green_ptr(t);
+        const T* gr = PAD ? green_ptr(t) : nullptr;
 #pragma unroll
-        for (int i = 0; i < R0; ++i) w[i] = cscale(w[i], gr[min(g + G * i, L - g - G * i)]);
+        for (int i = 0; i < R0; ++i) w[i] = cscale(w[i], mult_of(t, gr, g + G * i));
       }
     };
     // forward FFT of the pencil of field `src` (x < n0 nonzero)
     auto load = [&](C2<T> (&w)[R0], const void* src) {
       const C2<T>* sp = in_ptr(t, src);
 #pragma unroll
-      for (int i = 0; i < R0; ++i) w[i] = i < R0 / 2 ? sp[g + G * i] : C2<T>{(T)0, (T)0};
-      wave_fft<T, L, false, true>(w, col, bs, g, tw);
+      for (int i = 0; i < R0; ++i) w[i] = i < NIN ? sp[g + G * i] : C2<T>{(T)0, (T)0};
+      wave_fft<T, L, false, PAD>(w, col, bs, g, tw);
     };
     // backward FFT, x < n0 of every pencil to the tile, stored along ky
     auto emit = [&](C2<T> (&w)[R0], void* dst) {
@@ -287,7 +301,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       C2<T>* tile = DBL ? tiles + tb * NX * TS : tiles;
       auto row = [](int x) { return DBL ? x : padrow(x); };
 #pragma unroll
-      for (int i = 0; i < R0 / 2; ++i) tile[row(g + G * i) * TS + p] = w[i];
+      for (int i = 0; i < NIN; ++i) tile[row(g + G * i) * TS + p] = w[i];
       __syncthreads();
       C2<T>* d = (C2<T>*)dst + obase;
       for (int e = threadIdx.x; e < NX * P; e += NT) {
@@ -299,14 +313,14 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     };
 
     if (a.diff == D_NONE) {
-      wave_fft<T, L, false, true>(v, col, bs, g, tw);
+      wave_fft<T, L, false, PAD>(v, col, bs, g, tw);
       green(v);
       emit(v, a.out[t.grp]);
     } else if (!ADJ && a.diff == D_CURL) {
       // one component per output group: psi_c, plus B = d_x psi_y (c = 1) or
       // A = -d_x psi_z (c = 2)
       const int c = t.grp;
-      wave_fft<T, L, false, true>(v, col, bs, g, tw);
+      wave_fft<T, L, false, PAD>(v, col, bs, g, tw);
       green(v);
       if (c > 0) {
         C2<T> u[R0];
@@ -387,10 +401,11 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
 // psi_z, A, B give psi and u = curl psi (u_x = d_y psi_z - d_z psi_y,
 // u_y = d_z psi_x + A, u_z = B - d_y psi_x); in gradient mode psi, d_x psi give
 // psi and grad psi.  At most two spectra are live per lane.
-template <typename T, int L, int P, bool DBL>
+template <typename T, int L, int P, bool DBL, bool PAD>
 __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
-  constexpr int NT = 64 * (P / PPW), TS = P + 1, NY = L / 2;
+  constexpr int NIN = PAD ? R0 / 2 : R0;  // elements per lane stored (y < n1)
+  constexpr int NT = 64 * (P / PPW), TS = P + 1, NY = PAD ? L / 2 : L;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
   C2<T>* exch = tw + L;
@@ -430,7 +445,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
     C2<T>* tile = DBL ? tiles + tb * NY * TS : tiles;
     auto row = [](int y) { return DBL ? y : padrow(y); };
 #pragma unroll
-    for (int i = 0; i < R0 / 2; ++i) tile[row(g + G * i) * TS + p] = v[i];
+    for (int i = 0; i < NIN; ++i) tile[row(g + G * i) * TS + p] = v[i];
     __syncthreads();
     C2<T>* d = (C2<T>*)dst + obase;
     for (int e = threadIdx.x; e < NY * P; e += NT) {
@@ -490,9 +505,10 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
 // Half spectra C1 (kz < K2 contiguous; [x][y][kz]) of pencils (x, y) and
 // (x, y + 1) form one complex inverse FFT (Hermitian completion); z < n2 of
 // both rows is stored into the real output [x][y][z].
-template <typename T, int L>
+template <typename T, int L, bool PAD>
 __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
+  constexpr int NIN = PAD ? R0 / 2 : R0;  // elements per lane stored (z < n2)
   constexpr int K2 = L / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* tw = (C2<T>*)smem;
@@ -538,7 +554,7 @@ __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
     T* oa = out + ((long long)x * n1 + ya) * n2;
     T* ob = oa + n2;
 #pragma unroll
-    for (int i = 0; i < R0 / 2; ++i) {
+    for (int i = 0; i < NIN; ++i) {
       if (valid) oa[g + G * i] = v[i].re;
       if (vb) ob[g + G * i] = v[i].im;
     }
@@ -571,26 +587,27 @@ int fast_emit_dbl(int fast) {
   return 1;
 }
 
-int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl) {
+int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl, int pad) {
   const int cs = prec == 0 ? 8 : 16;
   const int R0 = L >= 1024 ? 16 : 8;
   const int ppw = 64 / (L / R0);
   const int SL = slot_len(L);
+  const int NX = pad ? L / 2 : L;  // stored rows of the x / backward-y output tiles
   switch (fast) {
     case FAST_R2C: return (L + ((P / 2 + ppw - 1) / ppw) * ppw * SL + K2 * (P + 1)) * cs;
     case FAST_FWD_Y: return (L + SL * (P + 1)) * cs;
     case FAST_SANDWICH:
-      if (dbl) return (L + P * SL + 2 * (L / 2) * (P + 1)) * cs;
+      if (dbl) return (L + P * SL + 2 * NX * (P + 1)) * cs;
       return (L + SL * (P + 1)) * cs;
     case FAST_INV_Y:
-      if (dbl) return (L + P * SL + 2 * (L / 2) * (P + 1)) * cs;
+      if (dbl) return (L + P * SL + 2 * NX * (P + 1)) * cs;
       return (L + slot_len(L, true) * (P + 1)) * cs;
     case FAST_C2R: return (L + 4 * ppw * SL) * cs;
     default: return 0;
   }
 }
 
-template <typename T, int L, int P>
+template <typename T, int L, int P, bool PAD>
 static hipError_t launch_LP(const PassArgs& a0, int grid_y, hipStream_t s) {
   PassArgs a = a0;
   a.ngrp = grid_y;
@@ -599,13 +616,13 @@ static hipError_t launch_LP(const PassArgs& a0, int grid_y, hipStream_t s) {
   switch (a.fast) {
     case FAST_R2C: {
       dim3 grid(((n1 + P - 1) / P) * n0, grid_y);
-      allow_lds<kf_r2c<T, L, P>>();
-      hipLaunchKernelGGL((kf_r2c<T, L, P>), grid, dim3(R2CShape<L, P>::NT), lds, s, a);
+      allow_lds<kf_r2c<T, L, P, PAD>>();
+      hipLaunchKernelGGL((kf_r2c<T, L, P, PAD>), grid, dim3(R2CShape<L, P>::NT), lds, s, a);
     } break;
     case FAST_FWD_Y: {
       dim3 grid(((n0 + P - 1) / P) * a.kz_count, grid_y);
-      allow_lds<kf_fwd_y<T, L, P>>();
-      hipLaunchKernelGGL((kf_fwd_y<T, L, P>), grid, dim3(64 * (P / WF<L>::PPW)), lds, s, a);
+      allow_lds<kf_fwd_y<T, L, P, PAD>>();
+      hipLaunchKernelGGL((kf_fwd_y<T, L, P, PAD>), grid, dim3(64 * (P / WF<L>::PPW)), lds, s, a);
     } break;
     case FAST_SANDWICH: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
@@ -616,24 +633,28 @@ static hipError_t launch_LP(const PassArgs& a0, int grid_y, hipStream_t s) {
         const int nb = persistent_grid<decltype(kern)::value>(NT, lds, ntiles);
         hipLaunchKernelGGL(decltype(kern)::value, dim3(nb), dim3(NT), lds, s, a);
       };
+#define HP_SW(ADJ, DBL) \
+  go(std::integral_constant<decltype(&kf_sandwich<T, L, P, ADJ, DBL, PAD>), \
+                            &kf_sandwich<T, L, P, ADJ, DBL, PAD>>{})
       if (a.emit_dbl) {  // double-buffered output tiles
-        if (adj) go(std::integral_constant<decltype(&kf_sandwich<T, L, P, true, true>), &kf_sandwich<T, L, P, true, true>>{});
-        else go(std::integral_constant<decltype(&kf_sandwich<T, L, P, false, true>), &kf_sandwich<T, L, P, false, true>>{});
+        if (adj) HP_SW(true, true);
+        else HP_SW(false, true);
       } else {
-        if (adj) go(std::integral_constant<decltype(&kf_sandwich<T, L, P, true, false>), &kf_sandwich<T, L, P, true, false>>{});
-        else go(std::integral_constant<decltype(&kf_sandwich<T, L, P, false, false>), &kf_sandwich<T, L, P, false, false>>{});
+        if (adj) HP_SW(true, false);
+        else HP_SW(false, false);
       }
+#undef HP_SW
     } break;
     case FAST_INV_Y: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
       dim3 grid(((a.kz_count + P - 1) / P) * n0, grid_y);
       if (a.P > 64) return hipErrorInvalidValue;
       if (a.emit_dbl) {  // double-buffered output tiles
-        allow_lds<kf_inv_y<T, L, P, true>>();
-        hipLaunchKernelGGL((kf_inv_y<T, L, P, true>), grid, dim3(NT), lds, s, a);
+        allow_lds<kf_inv_y<T, L, P, true, PAD>>();
+        hipLaunchKernelGGL((kf_inv_y<T, L, P, true, PAD>), grid, dim3(NT), lds, s, a);
       } else {
-        allow_lds<kf_inv_y<T, L, P, false>>();
-        hipLaunchKernelGGL((kf_inv_y<T, L, P, false>), grid, dim3(NT), lds, s, a);
+        allow_lds<kf_inv_y<T, L, P, false, PAD>>();
+        hipLaunchKernelGGL((kf_inv_y<T, L, P, false, PAD>), grid, dim3(NT), lds, s, a);
       }
     } break;
     default:
@@ -642,22 +663,29 @@ static hipError_t launch_LP(const PassArgs& a0, int grid_y, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int L>
-static hipError_t launch_L(const PassArgs& a, int grid_y, hipStream_t s) {
+template <typename T, int L, bool PAD>
+static hipError_t launch_LPAD(const PassArgs& a, int grid_y, hipStream_t s) {
   if (a.fast == FAST_C2R) {
     const int n0 = a.un[0], n1 = a.un[1];
     const long long pairs = (long long)n0 * ((n1 + 1) / 2);
     const long long groups = (pairs + WF<L>::PPW - 1) / WF<L>::PPW;
     dim3 grid((unsigned)((groups + 3) / 4), grid_y);
-    allow_lds<kf_c2r<T, L>>();
-    hipLaunchKernelGGL((kf_c2r<T, L>), grid, dim3(kC2RThreads), a.lds_bytes, s, a);
+    allow_lds<kf_c2r<T, L, PAD>>();
+    hipLaunchKernelGGL((kf_c2r<T, L, PAD>), grid, dim3(kC2RThreads), a.lds_bytes, s, a);
     return hipGetLastError();
   }
-  if (a.P == 8) return launch_LP<T, L, 8>(a, grid_y, s);
+  if (a.P == 8) return launch_LP<T, L, 8, PAD>(a, grid_y, s);
   if constexpr (sizeof(T) == 4 && L < 1024) {
-    if (a.P == 16) return launch_LP<T, L, 16>(a, grid_y, s);
+    if (a.P == 16) return launch_LP<T, L, 16, PAD>(a, grid_y, s);
   }
   return hipErrorInvalidValue;
+}
+
+// a.pad: free-space (doubled, half of every pencil physical) or periodic
+template <typename T, int L>
+static hipError_t launch_L(const PassArgs& a, int grid_y, hipStream_t s) {
+  if (a.pad) return launch_LPAD<T, L, true>(a, grid_y, s);
+  return launch_LPAD<T, L, false>(a, grid_y, s);
 }
 
 template <typename T>

@@ -87,6 +87,7 @@ struct PassArgs {
   int c1_ld;               // row length (kz) of C1: K2 rounded up to 16
   long long c1_sx, c1_sy;  // C1 strides (elements) of x and y
   int ngrp;                // x pass: output groups per tile (set at launch)
+  int pad;                 // 1: doubled free-space pencils (physical half), 0: periodic
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
@@ -102,7 +103,7 @@ hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s);
 int r2r_tile(int prec);
 int r2r_lds_bytes(int fast, int L, int n, int prec);
 // Dynamic LDS bytes of a wavefront-FFT pass; 0 if the pass is not available.
-int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl);
+int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl, int pad);
 int fast_emit_dbl(int fast);
 // Pencils per workgroup of the wavefront-FFT passes.
 int fast_tile(int fast, int L, int prec);

@@ -40,6 +40,7 @@ struct Problem {
   long long g_s[3] = {0, 0, 0};  // octant strides of i0, i1, k2
   double norm = 1.0;
   std::vector<std::pair<int, int>> slabs;  // kz (first, count) of the free-space y / x passes
+  bool fast_periodic = false;  // periodic plan on the wavefront passes (M = n)
 };
 
 }  // namespace hp

@@ -109,6 +109,36 @@ def test_periodic_curl(prec, nc):
         check(gd[a], rd[a], prec, f"curl {a}")
 
 
+# 3D periodic plans with power-of-two sizes in [64, 1024]: the wavefront
+# passes of the free-space path on undoubled pencils.
+PERF = [([64, 64, 128], 1, "none"), ([128, 64, 64], 1, "grad"), ([64, 128, 64], 3, "curl"),
+        ([64, 64, 64], 3, "none")]
+
+
+@pytest.mark.parametrize("nc,ncomp,diff", PERF)
+@pytest.mark.parametrize("kernel", ["ps", "fd2"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_periodic_fast(nc, ncomp, diff, kernel, prec):
+    f, _ = case_input("periodic", "staggered", nc, ncomp, False, prec, seed=13)
+    got, gd = gpu_solve("periodic", "staggered", nc, LO, HI, f, kernel, diff, prec, ncomp, None)
+    ref, rd = oracle_solve("periodic", "staggered", nc, LO, HI, f, kernel, diff, None)
+    check(got, ref, prec, "psi")
+    assert len(gd) == len(rd)
+    for a in range(len(rd)):
+        check(gd[a], rd[a], prec, f"deriv {a}")
+
+
+def test_periodic_fast_matches_general(monkeypatch):
+    nc = [64, 128, 64]
+    f, _ = case_input("periodic", "staggered", nc, 3, False, "f64", seed=31)
+    fast, fd = gpu_solve("periodic", "staggered", nc, LO, HI, f, "ps", "curl", "f64", 3, None)
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen, gdr = gpu_solve("periodic", "staggered", nc, LO, HI, f, "ps", "curl", "f64", 3, None)
+    check(fast, gen, "f64", "psi fast vs general")
+    for a in range(3):
+        check(fd[a], gdr[a], "f64", f"curl {a} fast vs general")
+
+
 UNB = [([8, 10, 12], 1, "none"), ([8, 10, 12], 1, "grad"), ([8, 10, 12], 3, "curl"),
        ([20, 18, 24], 3, "curl"), ([20, 18, 24], 3, "none"), ([30, 16, 15], 1, "grad"),
        # power-of-two doubled lengths: wavefront-FFT kernels

@@ -1245,7 +1245,9 @@ double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
 const char* pass_name(const PassArgs& a) {
   static const char* fast_names[] = {"",       "r2c_z",      "fwd_y",       "sandwich_x", "inv_y",
                                      "c2r_z",  "r2r_contig", "r2r_strided", "r2r_sandwich"};
-  if (a.fast) return fast_names[a.fast];
+  constexpr int nfast = (int)(sizeof(fast_names) / sizeof(fast_names[0]));
+  if (a.fast > 0 && a.fast < nfast) return fast_names[a.fast];
+  if (a.fast) return "wavefront";
   if (a.kind == PK_SANDWICH) return "sandwich";
   switch (a.xf) {
     case X_C2C_F: return "c2c_fwd";

@@ -72,15 +72,20 @@ def test_bounded_fast(bc, grid, nc, kernel, inhom, prec):
     check(got, ref, prec, "psi")
 
 
-@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("neumann", "staggered")])
-def test_bounded_fast_matches_general(bc, grid, monkeypatch):
-    """The same power-of-two problem through the wavefront and the general kernels."""
+@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("neumann", "staggered"),
+                                     ("dirichlet", "staggered"), ("neumann", "regular")])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bounded_fast_matches_general(bc, grid, prec, monkeypatch):
+    """The same power-of-two 3D problem on the wavefront and the general kernels."""
     nc = [64, 32, 128]
-    f, faces = case_input(bc, grid, nc, 1, True, "f64", seed=29)
-    fast, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", "f64", 1, faces)
+    f, faces = case_input(bc, grid, nc, 1, True, prec, seed=29)
+    fast, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", prec, 1, faces)
     monkeypatch.setenv("HP_GENERIC", "1")
-    gen, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", "f64", 1, faces)
-    check(fast, gen, "f64", "fast vs general")
+    gen, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", prec, 1, faces)
+    ref, _ = oracle_solve(bc, grid, nc, LO, HI, f, "fd2", "none", faces)
+    check(fast, ref, prec, "wavefront vs oracle")
+    check(gen, ref, prec, "general vs oracle")
+    check(fast, gen, prec, "wavefront vs general")
 
 
 @pytest.mark.parametrize("nd,nc", [(1, [12]), (1, [9]), (2, [12, 10]), (2, [9, 15]), (3, [12, 10, 9]),

@@ -1120,7 +1120,7 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     a.c1_sx = (long long)P.n[1] * a.c1_ld;
     a.c1_sy = a.c1_ld;
     a.pad = periodic ? 0 : 1;
-    a.emit_dbl = fast_emit_dbl(kind);
+    a.emit_dbl = fast_emit_dbl(kind, p->prec);
     if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl, a.pad) > 160 * 1024) a.emit_dbl = 0;
     a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl, a.pad);
     out.push_back({a, 1});

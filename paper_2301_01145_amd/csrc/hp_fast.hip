@@ -580,11 +580,13 @@ int fast_tile(int fast, int L, int prec) {
 
 // Output-tile scheme of the x and backward-y passes: 1 = double-buffered
 // tiles with separate exchange slots, 0 = one tile whose columns are the
-// exchange slots (less LDS, two barriers per output field).
-int fast_emit_dbl(int fast) {
+// exchange slots (less LDS, two barriers per output field).  Measured at 256^3
+// (doubled 512^3): 0 for FP32 (two workgroups per CU in the backward y pass),
+// 1 for FP64.
+int fast_emit_dbl(int fast, int prec) {
   const char* e = std::getenv(fast == FAST_INV_Y ? "HP_EMIT_INVY" : "HP_EMIT_SAND");
   if (e) return std::atoi(e) == 1 ? 1 : 0;
-  return 1;
+  return prec == 0 ? 0 : 1;
 }
 
 int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl, int pad) {

@@ -104,7 +104,7 @@ int r2r_tile(int prec);
 int r2r_lds_bytes(int fast, int L, int n, int prec);
 // Dynamic LDS bytes of a wavefront-FFT pass; 0 if the pass is not available.
 int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl, int pad);
-int fast_emit_dbl(int fast);
+int fast_emit_dbl(int fast, int prec);
 // Pencils per workgroup of the wavefront-FFT passes.
 int fast_tile(int fast, int L, int prec);
 

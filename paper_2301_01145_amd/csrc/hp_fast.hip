@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
 int fast_tile(int fast, int L, int prec) {
   if (fast == FAST_C2R) return 2;
   if (prec != 0) return 8;
-  if ((fast == FAST_SANDWICH || fast == FAST_INV_Y) && L >= 1024) return 8;
+  if (L >= 1024) return 8;  // (16-pencil tiles are instantiated below 1024 only)
   static const char* env[] = {"", "HP_TILE_R2C", "HP_TILE_FWDY", "HP_TILE_SAND", "HP_TILE_INVY"};
   if (const char* t = std::getenv(env[fast])) {
     const int v = std::atoi(t);

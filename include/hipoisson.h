@@ -92,8 +92,13 @@ enum {
   HP_Q_NUM_PASSES = 3,      /* kernel launches of one hp_solve */
   HP_Q_NUM_OUTPUTS = 4,     /* psi components + derivative components */
   HP_Q_NUM_DERIVS = 5,      /* derivative components (gradient or curl) */
-  HP_Q_BATCH_ERROR = 6      /* batched plans: 1 if the last solve hit a dependency-wait
+  HP_Q_BATCH_ERROR = 6,     /* batched plans: 1 if the last solve hit a dependency-wait
                                limit (results invalid), else 0; synchronises */
+  HP_Q_TUNED_PASSES = 7,    /* pass signatures whose configuration hp_autotune changed */
+  HP_Q_TUNE_DEFAULT_MS = 8, /* milliseconds of one solve with the planner's defaults,
+                               measured by the last hp_autotune */
+  HP_Q_TUNE_BEST_MS = 9,    /* the same with the configuration it kept */
+  HP_Q_BATCH_TILES = 10     /* batched plans: tiles per work item of the persistent kernel */
 };
 
 /* Create a plan for one problem (the initialisation of Section 3.2.1): grid
@@ -160,6 +165,27 @@ HP_API hp_status hp_get_gradient(hp_plan plan, int problem, int comp, void* dst,
 HP_API hp_status hp_set_timing(hp_plan plan, int enable);
 HP_API hp_status hp_pass_stats(hp_plan plan, int max, int* npass, double* ms, double* bytes,
                                const char** names);
+
+/* Autotuning of the plan's kernel configurations (not a step of the paper's
+ * method: the paper leaves the FFT plan to its FFT library).  For every
+ * distinct pass geometry of the plan it times, on the plan's stream, `reps`
+ * runs (< 1: 5; at most 100) of each configuration the kernels are built for:
+ * general kernels, every radix order of the length over radices 2, 3, 4, 5, 8
+ * with tile widths of 1/2, 1 and 2 times the planner's choice and both
+ * register budgets; wavefront passes, 8- and 16-pencil tiles and both
+ * output-tile schemes; batched plans, 1, 2, 4 or 8 tiles per work item.  A
+ * configuration replaces the default when it is at least 3% faster, and the
+ * choices are kept only if the whole solve (batched plans: the whole batch,
+ * which also decides the work-item size) is faster with them; later solves of
+ * this plan use them.  Batched plans keep every pass within the register
+ * budget and LDS of the default persistent kernel.  The tuned plan is then run against the default
+ * on the same pseudo-random input and every output must agree to rounding
+ * (relative L2 difference <= 1e-5 FP32, <= 1e-12 FP64); otherwise the tuning
+ * is dropped and HP_E_DEVICE returned.  Works on scratch arrays it allocates
+ * and frees: bound inputs, outputs and workspaces keep their bindings (plan
+ * workspaces are overwritten).  Blocking; HP_E_STATE under stream capture.
+ * A batched plan must run one hp_solve after tuning before it is captured. */
+HP_API hp_status hp_autotune(hp_plan plan, int reps);
 
 /* Numeric plan properties (HP_Q_* keys). */
 HP_API hp_status hp_query(hp_plan plan, int what, double* value);

@@ -9,7 +9,7 @@ from ._lib import (  # noqa: F401  (C-ABI names)
     HipoissonError, hp_bind_gradient, hp_bind_output, hp_desc, hp_get_gradient, hp_get_output,
     hp_input_shape, hp_last_error, hp_output_shape, hp_plan_create, hp_plan_create_batched,
     hp_plan_destroy, hp_query, hp_set_boundary, hp_set_input, hp_solve, hp_solve_adjoint,
-    hp_pass_stats, hp_set_timing, hp_status_string,
+    hp_autotune, hp_pass_stats, hp_set_timing, hp_status_string,
 )
 
 BCS = {"periodic": _lib.HP_PERIODIC, "dirichlet": _lib.HP_DIRICHLET,
@@ -86,6 +86,15 @@ class Solver:
 
     def model_bytes(self):
         return hp_query(self.plan, _lib.HP_Q_MODEL_BYTES)
+
+    def autotune(self, reps=5):
+        """Time the kernel configurations of this plan and keep the fastest
+        (hp_autotune); returns (tuned pass signatures, solve ms with the defaults,
+        solve ms with the kept configuration), as measured while tuning."""
+        hp_autotune(self.plan, reps)
+        return (int(hp_query(self.plan, _lib.HP_Q_TUNED_PASSES)),
+                hp_query(self.plan, _lib.HP_Q_TUNE_DEFAULT_MS),
+                hp_query(self.plan, _lib.HP_Q_TUNE_BEST_MS))
 
     def bind(self, f, faces=None, psi=None, derivs=None):
         """Bind input, boundary and output tensors (no copies)."""

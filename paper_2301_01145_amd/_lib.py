@@ -18,13 +18,14 @@ HP_D_NONE, HP_D_GRAD, HP_D_CURL = 0, 1, 2
 HP_F32, HP_F64 = 0, 1
 HP_Q_MODEL_BYTES, HP_Q_WORKSPACE_BYTES, HP_Q_NUM_PASSES, HP_Q_NUM_OUTPUTS, HP_Q_NUM_DERIVS = 1, 2, 3, 4, 5
 HP_Q_BATCH_ERROR = 6
+HP_Q_TUNED_PASSES, HP_Q_TUNE_DEFAULT_MS, HP_Q_TUNE_BEST_MS, HP_Q_BATCH_TILES = 7, 8, 9, 10
 
 # Every exported function of include/hipoisson.h (checked by the ABI tests).
 EXPORTS = (
     "hp_plan_create", "hp_plan_create_batched", "hp_input_shape", "hp_output_shape",
     "hp_set_input", "hp_set_boundary", "hp_bind_output", "hp_bind_gradient", "hp_solve",
     "hp_solve_adjoint", "hp_get_output", "hp_get_gradient", "hp_query", "hp_plan_destroy",
-    "hp_status_string", "hp_last_error", "hp_set_timing", "hp_pass_stats",
+    "hp_status_string", "hp_last_error", "hp_set_timing", "hp_pass_stats", "hp_autotune",
 )
 
 
@@ -73,6 +74,7 @@ _SIG = {
     "hp_status_string": ([_I], ctypes.c_char_p),
     "hp_last_error": ([_P], ctypes.c_char_p),
     "hp_set_timing": ([_P, _I], _I),
+    "hp_autotune": ([_P, _I], _I),
     "hp_pass_stats": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_char_p)], _I),
 }
@@ -167,6 +169,10 @@ def hp_query(plan, what):
 
 def hp_plan_destroy(plan):
     _check(lib().hp_plan_destroy(plan))
+
+
+def hp_autotune(plan, reps=5):
+    _check(lib().hp_autotune(plan, int(reps)), plan)
 
 
 def hp_set_timing(plan, enable):

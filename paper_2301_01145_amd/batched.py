@@ -1,7 +1,7 @@
 """Many independent bounded solves in one persistent launch (hp_plan_create_batched)."""
 from . import _lib
-from ._lib import (hp_bind_output, hp_input_shape, hp_output_shape, hp_plan_create_batched,
-                   hp_plan_destroy, hp_query, hp_set_input, hp_solve)
+from ._lib import (hp_autotune, hp_bind_output, hp_input_shape, hp_output_shape,
+                   hp_plan_create_batched, hp_plan_destroy, hp_query, hp_set_input, hp_solve)
 
 
 class BatchedSolver:
@@ -45,6 +45,14 @@ class BatchedSolver:
 
     def run(self):
         hp_solve(self.plan)
+
+    def autotune(self, reps=5):
+        """Tune radix orders, tiles and the work-item size (hp_autotune); returns
+        (tuned pass signatures, tiles per work item).  Run one solve before
+        capturing the plan into a graph."""
+        hp_autotune(self.plan, reps)
+        return (int(hp_query(self.plan, _lib.HP_Q_TUNED_PASSES)),
+                int(hp_query(self.plan, _lib.HP_Q_BATCH_TILES)))
 
     def error_flag(self):
         return int(hp_query(self.plan, _lib.HP_Q_BATCH_ERROR))

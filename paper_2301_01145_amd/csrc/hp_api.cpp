@@ -560,21 +560,52 @@ void strides_of(const int* dims, long long* s) {
   s[0] = (long long)dims[1] * dims[2];
 }
 
-// Fill the FFT fields of a pass for length L; P from the LDS model.
-hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_per_P_fixed,
-                      int lds_kind) {
-  if (!factorize(a.L, a.radix, &a.nstage)) return fail(p, HP_E_UNSUPPORTED, "length");
+// FNV-1a over the integers that fix a pass's geometry.
+unsigned long long tune_hash(const long long* v, int n) {
+  unsigned long long h = 1469598103934665603ull;
+  for (int i = 0; i < n; ++i) {
+    unsigned long long x = (unsigned long long)v[i];
+    for (int b = 0; b < 8; ++b) {
+      h ^= (x >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  }
+  return h;
+}
+
+// Signature of a general pass from the fields its builder sets before the
+// tile is chosen.
+unsigned long long general_key(const PassArgs& a, int prec, int want, int minP, int lds_kind) {
+  const long long v[] = {0,        prec,      a.kind,    a.xf,      a.xb,      a.L,
+                         a.n,      a.nin,     a.nout,    a.Np,      a.No,      a.in_jfast,
+                         a.out_jfast, a.in_sj, a.in_sp,  a.in_so,   a.out_sj,  a.out_sp,
+                         a.out_so, a.n_in,    a.n_out,   a.diff,    a.mult,    want,
+                         minP,     lds_kind};
+  return tune_hash(v, (int)(sizeof(v) / sizeof(v[0])));
+}
+
+// Fill the FFT fields of a pass for length L; P from the LDS model.  A tuned
+// configuration (radix order, tile width, register budget) replaces the
+// default when it fits this pass; otherwise the default stands.
+hp_status finish_pass_with(hp_plan p, PassArgs& a, int want, int minP, int lds_kind,
+                           const Tune* tn) {
+  if (tn) {
+    a.nstage = tn->nstage;
+    for (int s = 0; s < tn->nstage; ++s) a.radix[s] = tn->radix[s];
+    want = tn->P;
+  } else if (!factorize(a.L, a.radix, &a.nstage)) {
+    return fail(p, HP_E_UNSUPPORTED, "length");
+  }
   const void* tw;
   HP_TRY(twiddles(p, a.L, &tw));
   a.tw = tw;
-  (void)lds_per_P_fixed;
   const long long cs = 2 * (long long)p->es, es = p->es;
   int lds = 0;
   auto nfft_pair = [](int q) { return q / 2; };
   auto nfft_one = [](int q) { return q; };
   // the smaller register budget first (more resident waves), the larger one
   // when a tile of this length does not fit it
-  for (int big = 0; big < 2; ++big) {
+  for (int big = tn ? tn->big : 0; big < (tn ? tn->big + 1 : 2); ++big) {
     a.big = big;
     switch (lds_kind) {
       case 0:  // one-way complex
@@ -609,8 +640,28 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
     }
     if (a.P > 0) break;
   }
+  if (tn && a.P != tn->P) return HP_E_UNSUPPORTED;  // does not fit: caller takes the default
   if (a.P == 0) return fail(p, HP_E_UNSUPPORTED, "pass of length " + std::to_string(a.L) + " does not fit in LDS");
   a.lds_bytes = lds;
+  return HP_OK;
+}
+
+hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_per_P_fixed,
+                      int lds_kind) {
+  (void)lds_per_P_fixed;
+  const unsigned long long key = general_key(a, p->prec, want, minP, lds_kind);
+  auto it = p->tuned.find(key);
+  if (it != p->tuned.end() && it->second.fast == FAST_NONE &&
+      radix_ok(a.L, it->second.radix, it->second.nstage)) {
+    PassArgs t = a;
+    if (finish_pass_with(p, t, want, minP, lds_kind, &it->second) == HP_OK) {
+      a = t;
+      a.tune_key = key;
+      return HP_OK;
+    }
+  }
+  HP_TRY(finish_pass_with(p, a, want, minP, lds_kind, nullptr));
+  a.tune_key = key;
   return HP_OK;
 }
 
@@ -1122,6 +1173,18 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     a.pad = periodic ? 0 : 1;
     a.emit_dbl = fast_emit_dbl(kind, p->prec);
     if (fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl, a.pad) > 160 * 1024) a.emit_dbl = 0;
+    {
+      const long long v[] = {1,      p->prec, kind,   L,      a.pad,  P.n[0],  P.n[1], P.n[2],
+                             P.M[0], P.M[1],  P.M[2], dk,     adjoint ? 1 : 0, n_src, n_live};
+      a.tune_key = tune_hash(v, (int)(sizeof(v) / sizeof(v[0])));
+      auto it = p->tuned.find(a.tune_key);
+      if (it != p->tuned.end() && it->second.fast == kind &&
+          fast_tile_ok(kind, L, it->second.P, p->prec) &&
+          fast_lds_bytes(kind, L, it->second.P, K2, p->prec, it->second.emit_dbl, a.pad) <= 160 * 1024) {
+        a.P = it->second.P;
+        a.emit_dbl = it->second.emit_dbl;
+      }
+    }
     a.lds_bytes = fast_lds_bytes(kind, L, a.P, K2, p->prec, a.emit_dbl, a.pad);
     out.push_back({a, 1});
     return HP_OK;
@@ -1368,6 +1431,32 @@ hp_status create(const hp_desc* descs, int count, hp_stream stream, hp_plan* out
 namespace hp {
 hp_status plan_fail(hp_plan p, hp_status s, const std::string& msg) { return fail(p, s, msg); }
 hp_status plan_alloc(hp_plan p, size_t bytes, void** out) { return dev_alloc(p, bytes, out); }
+void plan_free(hp_plan p, void* ptr) {
+  if (!ptr) return;
+  auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+  if (it == p->allocs.end()) return;
+  p->allocs.erase(it);
+  (void)hipFree(ptr);
+}
+hp_status plan_outputs(hp_plan p, Problem& P) { return ensure_outputs(p, P); }
+hp_status launch_rec(hp_plan p, const PassRec& r) {
+  hipError_t e = r.a.fast >= FAST_R2R_C ? launch_bounded(r.a, p->prec, p->stream)
+                 : r.a.fast               ? launch_fast(r.a, p->prec, r.grid_y, p->stream)
+                                          : launch_pass(r.a, p->prec, r.grid_y, p->stream);
+  if (e != hipSuccess) return fail(p, HP_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
+  return HP_OK;
+}
+// A radix order the general kernels run: radices 2, 3, 4, 5, 8 whose product is L.
+bool radix_ok(int L, const int* radix, int nstage) {
+  if (nstage < 1 || nstage > kMaxStages) return false;
+  long long prod = 1;
+  for (int s = 0; s < nstage; ++s) {
+    const int r = radix[s];
+    if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return false;
+    prod *= r;
+  }
+  return prod == L;
+}
 hp_status passes_for(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
   return build_passes(p, P, adjoint, out);
 }
@@ -1591,6 +1680,19 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
       *value = err;
       return HP_OK;
     }
+    case HP_Q_TUNED_PASSES:
+      *value = plan->tuned_passes;
+      return HP_OK;
+    case HP_Q_TUNE_DEFAULT_MS:
+      *value = plan->tune_default_ms;
+      return HP_OK;
+    case HP_Q_TUNE_BEST_MS:
+      *value = plan->tune_best_ms;
+      return HP_OK;
+    case HP_Q_BATCH_TILES:
+      if (!plan->batched) return fail(plan, HP_E_ARG, "not a batched plan");
+      *value = batch_tiles_of(plan);
+      return HP_OK;
     case HP_Q_MODEL_BYTES:
     case HP_Q_NUM_PASSES: {
       if (plan->batched) {

@@ -46,6 +46,8 @@ const int kBatchTilesPerItem = batch_tiles_per_item();
 
 }  // namespace
 
+int batch_tiles_of(hp_plan p) { return p->batch_tiles > 0 ? p->batch_tiles : kBatchTilesPerItem; }
+
 hp_status batched_setup(hp_plan p) {
   for (auto& P : p->probs) {
     if (P.d.bc == HP_DIRICHLET && P.d.grid == HP_REGULAR)
@@ -68,6 +70,7 @@ hp_status batched_setup(hp_plan p) {
     }
   }
   p->batch_big = big;
+  const int per_item = batch_tiles_of(p);
   std::vector<BatchItem> items;
   for (int lev = 0; lev < maxlev; ++lev) {
     for (size_t q = 0; q < lists.size(); ++q) {
@@ -78,13 +81,21 @@ hp_status batched_setup(hp_plan p) {
       // consecutive tiles of a pass share one item (one queue step, one
       // dependency check and one release per item)
       const int nt = tiles_of(lists[q][lev].a);
-      for (int t = 0; t < nt; t += kBatchTilesPerItem)
-        items.push_back({gp, t, std::min(kBatchTilesPerItem, nt - t), dep, need});
+      for (int t = 0; t < nt; t += per_item)
+        items.push_back({gp, t, std::min(per_item, nt - t), dep, need});
     }
   }
   p->batch_nitems = (int)items.size();
   p->batch_ncounters = 1 + npass;
   p->batch_lds = lds;
+  // a second setup (after autotuning) replaces the tables of the first
+  (void)hipStreamSynchronize(p->stream);
+  plan_free(p, p->batch_items);
+  plan_free(p, p->batch_counters);
+  plan_free(p, p->batch_probs);
+  p->batch_items = p->batch_probs = nullptr;
+  p->batch_counters = nullptr;
+  p->batch_uploaded.clear();
   void* d;
   s = plan_alloc(p, items.size() * sizeof(BatchItem), &d);
   if (s != HP_OK) return s;

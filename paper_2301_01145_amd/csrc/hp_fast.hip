@@ -578,6 +578,12 @@ int fast_tile(int fast, int L, int prec) {
   return fast == FAST_SANDWICH ? 8 : 16;
 }
 
+bool fast_tile_ok(int fast, int L, int P, int prec) {
+  if (fast == FAST_C2R) return P == 2;
+  if (fast < FAST_R2C || fast > FAST_INV_Y) return false;
+  return P == 8 || (P == 16 && prec == 0 && L < 1024);
+}
+
 // Output-tile scheme of the x and backward-y passes: 1 = double-buffered
 // tiles with separate exchange slots, 0 = one tile whose columns are the
 // exchange slots (less LDS, two barriers per output field).  Measured at 256^3

@@ -88,6 +88,9 @@ struct PassArgs {
   long long c1_sx, c1_sy;  // C1 strides (elements) of x and y
   int ngrp;                // x pass: output groups per tile (set at launch)
   int pad;                 // 1: doubled free-space pencils (physical half), 0: periodic
+  // signature of the pass geometry (host planner): passes with equal keys
+  // share the configuration chosen by the autotuner
+  unsigned long long tune_key;
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
@@ -107,6 +110,8 @@ int fast_lds_bytes(int fast, int L, int P, int K2, int prec, int dbl, int pad);
 int fast_emit_dbl(int fast, int prec);
 // Pencils per workgroup of the wavefront-FFT passes.
 int fast_tile(int fast, int L, int prec);
+// Tile widths a wavefront-FFT pass is built for.
+bool fast_tile_ok(int fast, int L, int P, int prec);
 
 // Launch one pass over `grid_y` independent field groups.
 hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s);

@@ -10,6 +10,16 @@
 
 namespace hp {
 
+// Configuration the autotuner chose for every pass with one signature
+// (PassArgs.tune_key): general kernels take the radix order, tile width and
+// register budget; wavefront passes the tile width and output-tile scheme.
+struct Tune {
+  int fast = 0;  // FastKind of the pass (FAST_NONE: general kernel)
+  int P = 0, big = 0, emit_dbl = 0;
+  int nstage = 0;
+  int radix[kMaxStages] = {};
+};
+
 struct PassRec {
   PassArgs a;
   int grid_y;
@@ -67,6 +77,13 @@ struct hp_plan_s {
   int batch_nitems = 0, batch_ncounters = 0, batch_grid = 0, batch_lds = 0;
   int batch_big = 0;  // register budget of the persistent kernel (PassArgs.big)
   std::vector<hp::PassRec> batch_passes;
+  int batch_tiles = 0;  // tiles per work item (0: the default)
+  // autotuning (hp_autotune): chosen configurations by pass signature, the
+  // number of signatures that left the default, and the summed per-pass
+  // times of the default and chosen configurations measured while tuning
+  std::map<unsigned long long, hp::Tune> tuned;
+  int tuned_passes = 0;
+  double tune_default_ms = 0.0, tune_best_ms = 0.0;
   std::vector<unsigned char> batch_uploaded;  // pass table last copied to the device
   // per-pass timing
   bool timing = false;
@@ -81,9 +98,14 @@ namespace hp {
 // implemented in hp_api.cpp
 hp_status plan_fail(hp_plan p, hp_status s, const std::string& msg);
 hp_status plan_alloc(hp_plan p, size_t bytes, void** out);
+void plan_free(hp_plan p, void* ptr);
+hp_status launch_rec(hp_plan p, const PassRec& r);
+bool radix_ok(int L, const int* radix, int nstage);
+hp_status plan_outputs(hp_plan p, Problem& P);
 hp_status passes_for(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out);
 double passes_model_bytes(hp_plan p, const std::vector<PassRec>& ps);
 // implemented in hp_batched.cpp
 hp_status batched_setup(hp_plan p);
 hp_status batched_solve(hp_plan p);
+int batch_tiles_of(hp_plan p);  // tiles per work item in effect
 }  // namespace hp

@@ -29,7 +29,8 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     grid_type: "regular" | "staggered"
     nc, lo, hi: per-axis cell count and domain bounds (length = ndim)
     f: source on the unknown points (scalar), or (3, ...) for a 3D vector
-    operator: "ps" | "fd2" for bounded BCs (ignored for unbounded: G2)
+    operator: "ps" | "fd2" for bounded BCs; for unbounded, the Green's kernel
+              ("g2", "g4", "g6", "g8", "g10", "spectral"; anything else: "g2")
     diff: "none" | "grad" | "curl"
     faces: {(axis, side): g} boundary values (FD2 Dirichlet / Neumann)
     Returns (psi, derivs) on the output points.
@@ -40,7 +41,8 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     f = np.asarray(f, dtype=np.float64)
     if bc == "unbounded":
         sigma = float(sigma_cells) * max(hs)
-        return unbounded.solve_unbounded(f, hs, sigma, diff)
+        kernel = operator if operator in unbounded.KERNELS else "g2"
+        return unbounded.solve_unbounded(f, hs, sigma, diff, kernel)
     vector = f.ndim == nd + 1
     comps = [f[c] for c in range(f.shape[0])] if vector else [f]
     psi = [bounded.solve_bounded(c, bc, grid_type, operator, lengths, hs, faces if not vector else (faces[i] if faces else None))

@@ -20,13 +20,36 @@ Readings of points the paper leaves open:
     given a zero derivative.
 The curl output solves the curl Poisson problem of Section 4.3
 (eq. poisscurl): psi = G * f first, then u = curl(psi) spectrally.
+
+Higher-order and spectral kernels (Section 2.5.2 names kernels of orders 2 to
+10 and a spectral kernel without printing them).  Reading used here: each is
+defined by its spectrum, G^(k) = -zeta^(k) / k^2, with
+  * Gaussian order 2m: zeta^(k) = exp(-s) sum_{j<m} s^j / j!, s = k^2 sigma^2 / 2
+    (the Gaussian times its own Taylor series truncated after m terms, so
+    1 - zeta^ = O(k^(2m)) and the regularisation error is O(sigma^(2m)));
+  * spectral: zeta^(k) = 1 for |k| <= k_c = pi / H, else 0 (H = max_a H_a).
+Their radial inverse transforms G(r) = -(1 / (2 pi^2 r)) int_0^inf zeta^(k)
+sin(k r) / k dk are, with rho = r / sigma and He_n the probabilists' Hermite
+polynomials,
+  G_2m(r) = -(1 / (4 pi r)) [erf(rho / sqrt2)
+            + sqrt(2 / pi) exp(-rho^2 / 2) sum_{j=1}^{m-1} (-1)^(j-1) He_{2j-1}(rho) / (2^j j!)]
+  (each j term from int_0^inf exp(-u^2/2) u^(2j-1) sin(u rho) du
+   = (-1)^(j-1) sqrt(pi/2) He_{2j-1}(rho) exp(-rho^2/2)), and
+  G_spectral(r) = -Si(k_c r) / (2 pi^2 r).
+At r = 0 the limits are G_2m(0) = -(1 / ((2 pi)^(3/2) sigma)) sum_{j<m} C(2j, j) / 4^j
+and G_spectral(0) = -k_c / (2 pi^2).  The closed forms are checked against the
+spectral integrals by quadrature in the tests.
 """
 import math
 
 import numpy as np
-from scipy.special import erf
+from numpy.polynomial import hermite_e
+from scipy.special import erf, sici
 
 SQRT2 = math.sqrt(2.0)
+
+# Green's kernels of the free-space solve: name -> Gaussian order (0: spectral)
+KERNELS = {"g2": 2, "g4": 4, "g6": 6, "g8": 8, "g10": 10, "spectral": 0}
 
 
 def green_g2(r, sigma):
@@ -40,25 +63,68 @@ def green_g2(r, sigma):
     return out
 
 
+def green_gauss(r, sigma, order):
+    """Gaussian-regularised 3D kernel of even order 2m (reading above)."""
+    m = order // 2
+    if order != 2 * m or m < 1:
+        raise ValueError("order must be 2, 4, ..., 10")
+    r = np.asarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    zero = r == 0.0
+    rr = r[~zero]
+    rho = rr / sigma
+    acc = erf(rho / SQRT2)
+    for j in range(1, m):
+        c = np.zeros(2 * j)
+        c[2 * j - 1] = 1.0  # He_{2j-1}
+        acc = acc + math.sqrt(2.0 / math.pi) * np.exp(-0.5 * rho * rho) * (
+            (-1) ** (j - 1) * hermite_e.hermeval(rho, c) / (2.0 ** j * math.factorial(j)))
+    out[~zero] = -acc / (4.0 * np.pi * rr)
+    out[zero] = -sum(math.comb(2 * j, j) / 4.0 ** j for j in range(m)) / ((2.0 * np.pi) ** 1.5 * sigma)
+    return out
+
+
+def green_spectral(r, h):
+    """Spectrally truncated 3D kernel, cutoff k_c = pi / h (reading above)."""
+    kc = math.pi / h
+    r = np.asarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    zero = r == 0.0
+    rr = r[~zero]
+    out[~zero] = -sici(kc * rr)[0] / (2.0 * np.pi ** 2 * rr)
+    out[zero] = -kc / (2.0 * np.pi ** 2)
+    return out
+
+
+def green(kernel, r, sigma, h):
+    """Kernel `kernel` of KERNELS at distances r (sigma: Gaussian width, h: cutoff spacing)."""
+    order = KERNELS[kernel]
+    if order == 0:
+        return green_spectral(r, h)
+    if order == 2:
+        return green_g2(r, sigma)
+    return green_gauss(r, sigma, order)
+
+
 def mirrored_distance(n, h):
     """Per-axis distances min(m, 2n - m) * H on the doubled grid."""
     m = np.arange(2 * n)
     return np.minimum(m, 2 * n - m).astype(np.float64) * float(h)
 
 
-def green_extended(shape, hs, sigma):
+def green_extended(shape, hs, sigma, kernel="g2"):
     """G_ext on the doubled grid of the given physical shape (3D)."""
     if len(shape) != 3:
-        raise NotImplementedError("the G2 kernel is the 3D kernel")
+        raise NotImplementedError("the free-space kernels are 3D kernels")
     dx = mirrored_distance(shape[0], hs[0])[:, None, None]
     dy = mirrored_distance(shape[1], hs[1])[None, :, None]
     dz = mirrored_distance(shape[2], hs[2])[None, None, :]
-    return green_g2(np.sqrt(dx * dx + dy * dy + dz * dz), sigma)
+    return green(kernel, np.sqrt(dx * dx + dy * dy + dz * dz), sigma, max(hs))
 
 
-def green_spectrum(shape, hs, sigma):
+def green_spectrum(shape, hs, sigma, kernel="g2"):
     """Ghat = DFT(G_ext) * prod(H) on the doubled grid (R2C layout)."""
-    g = green_extended(shape, hs, sigma)
+    g = green_extended(shape, hs, sigma, kernel)
     return np.fft.rfftn(g) * float(np.prod(hs))
 
 
@@ -95,7 +161,7 @@ def _back(spec, shape):
     return full[tuple(slice(0, n) for n in shape)]
 
 
-def solve_unbounded(f, hs, sigma, diff="none"):
+def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
     """Free-space solve of lap(psi) = f for a scalar or a 3-component field.
 
     f has shape (n_x, n_y, n_z) or (3, n_x, n_y, n_z).  Returns
@@ -107,7 +173,7 @@ def solve_unbounded(f, hs, sigma, diff="none"):
     vector = f.ndim == 4
     comps = [f[c] for c in range(3)] if vector else [f]
     shape = comps[0].shape
-    ghat = green_spectrum(shape, hs, sigma)
+    ghat = green_spectrum(shape, hs, sigma, kernel)
     psihat = [ghat * np.fft.rfftn(_pad(c)) for c in comps]
     psi = [_back(p, shape) for p in psihat]
     ks = wavenumbers(shape, hs)
@@ -132,7 +198,7 @@ def solve_unbounded(f, hs, sigma, diff="none"):
     return psi_out, derivs
 
 
-def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none"):
+def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
     """Transpose of the map f -> (psi, derivs) of solve_unbounded.
 
     The forward map is K = R D G P: P pads to the doubled grid, G is the
@@ -151,7 +217,7 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none"):
     else:
         vector = diff == "curl"
         shape = derivs[0].shape
-    ghat = green_spectrum(shape, hs, sigma)
+    ghat = green_spectrum(shape, hs, sigma, kernel)
     ks = wavenumbers(shape, hs)
     ncomp = 3 if vector else 1
     acc = []
@@ -175,7 +241,7 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none"):
     return np.stack(out) if vector else out[0]
 
 
-def psi_at(points, f, hs, sigma):
+def psi_at(points, f, hs, sigma, kernel="g2"):
     """psi at selected output points by the direct sum of the discrete convolution.
 
     psi_i = prod(H) * sum_j G_ext(i - j) f_j, which is what the doubled-domain
@@ -191,5 +257,5 @@ def psi_at(points, f, hs, sigma):
         dy = np.abs(np.arange(shape[1]) - p[1]) * hs[1]
         dz = np.abs(np.arange(shape[2]) - p[2]) * hs[2]
         r = np.sqrt(dx[:, None, None] ** 2 + dy[None, :, None] ** 2 + dz[None, None, :] ** 2)
-        out.append(vol * float(np.sum(green_g2(r, sigma) * f)))
+        out.append(vol * float(np.sum(green(kernel, r, sigma, max(hs)) * f)))
     return np.array(out)

@@ -66,6 +66,6 @@ def gpu_solve(bc, grid, nc, lo, hi, f, kernel, diff, prec, ncomp, faces, sigma_c
 
 
 def oracle_solve(bc, grid, nc, lo, hi, f, kernel, diff, faces, sigma_cells=0.0):
-    op = {"ps": "ps", "fd2": "fd2", "g2": "ps"}[kernel]
+    op = kernel  # bounded: "ps" | "fd2"; free space: the Green's kernel name
     return oracle.solve(bc, grid, nc, lo, hi, f, operator=op, diff=diff, faces=faces,
                         sigma_cells=sigma_cells if sigma_cells > 0 else 2.0)

@@ -132,6 +132,40 @@ def other_workloads(steps, warmup):
                                    "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
                                    "error_flag": bs.error_flag()}
     bs.close()
+    # free-space kernels (Section 2.5.2): plan time (Green's function on the doubled
+    # grid, FP64 transform, octant) and solve time of the 256^3 curl plan, and the
+    # FP64 error against the exact potential of a Gaussian blob at 64^3 and 128^3
+    from scipy.special import erf
+    kern = {}
+    f_rings = [torch.as_tensor(vortex_rings(256, seed=4, count=32)[c].astype(np.float32), device="cuda")
+               for c in range(3)]
+    for kname in ("g2", "g4", "g6", "g8", "g10", "spectral"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = Solver("unbounded", "staggered", [256] * 3, kernel=kname, diff="curl", dtype=torch.float32,
+                   ncomp=3)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        s.bind(f_rings)
+        solve_ms = _time(s.run, max(5, steps // 4), warmup, s.stream)
+        s.close()
+        errs = []
+        for n in (64, 128):
+            h = 1.0 / n
+            x = (np.arange(n) + 0.5) * h
+            c, A, sb = (0.5, 0.47, 0.52), 1.0, 0.06
+            r = np.sqrt((x[:, None, None] - c[0]) ** 2 + (x[None, :, None] - c[1]) ** 2
+                        + (x[None, None, :] - c[2]) ** 2)
+            fb = A * np.exp(-r * r / (2 * sb * sb))
+            exact = -A * (2 * np.pi * sb * sb) ** 1.5 * erf(r / (np.sqrt(2) * sb)) / (4 * np.pi * r)
+            sb_ = Solver("unbounded", "staggered", [n] * 3, kernel=kname, dtype=torch.float64)
+            psi, _ = sb_.solve(torch.as_tensor(fb, device="cuda"))
+            torch.cuda.synchronize()
+            errs.append(float(np.max(np.abs(psi[0].cpu().numpy() - exact)) / np.max(np.abs(exact))))
+            sb_.close()
+        kern[kname] = {"plan_ms": plan_ms, "solve_ms": solve_ms, "blob_rel_max_err_64": errs[0],
+                       "blob_rel_max_err_128": errs[1], "observed_order": float(np.log2(errs[0] / errs[1]))}
+    res["unbounded256_kernels"] = kern
     # differentiable 128^3 curl solve: forward + backward of sum |u - u_t|^2, FP32
     n = 128
     fr = vortex_rings(n, seed=6, count=16, r_range=(0.08, 0.16), core_ratio=0.25).astype(np.float32)

@@ -63,9 +63,21 @@ typedef enum {
 
 typedef enum { HP_PERIODIC = 0, HP_DIRICHLET = 1, HP_NEUMANN = 2, HP_UNBOUNDED = 3 } hp_bc;
 typedef enum { HP_REGULAR = 0, HP_STAGGERED = 1 } hp_grid;
-/* Spectral multiplier: PS / FD2 eigenvalues (Table 1) for bounded BCs, the
- * Gaussian-regularised 3D kernel G2 (Section 2.5.2) for unbounded ones. */
-typedef enum { HP_OP_PS = 0, HP_OP_FD2 = 1, HP_G_GAUSS2 = 2 } hp_kernel;
+/* Spectral multiplier: PS / FD2 eigenvalues (Table 1) for bounded BCs; for
+ * unbounded ones a 3D free-space kernel of Section 2.5.2, which names Gaussian
+ * kernels of orders 2 to 10 and a spectral kernel without printing them.  Each
+ * is read here through its spectrum G^(k) = -zeta^(k) / k^2:
+ *   HP_G_GAUSS<2m>: zeta^ = exp(-s) sum_{j<m} s^j / j!, s = (k sigma)^2 / 2
+ *     (error O(sigma^(2m)); sigma = reg_sigma_cells * max_a H_a); in space
+ *     G(r) = -(1/(4 pi r)) [erf(rho/sqrt2) + sqrt(2/pi) exp(-rho^2/2)
+ *            sum_{j=1}^{m-1} (-1)^(j-1) He_{2j-1}(rho) / (2^j j!)], rho = r / sigma;
+ *   HP_G_SPECTRAL: zeta^ = 1 for |k| <= pi / max_a H_a, else 0; in space
+ *     G(r) = -Si(k_c r) / (2 pi^2 r). */
+typedef enum {
+  HP_OP_PS = 0, HP_OP_FD2 = 1,
+  HP_G_GAUSS2 = 2, HP_G_GAUSS4 = 3, HP_G_GAUSS6 = 4, HP_G_GAUSS8 = 5, HP_G_GAUSS10 = 6,
+  HP_G_SPECTRAL = 7
+} hp_kernel;
 /* Spectral derivative applied after the convolution (Section 2.3.3):
  * GRAD of a scalar (ndim extra outputs), CURL of a 3D vector (3 outputs). */
 typedef enum { HP_D_NONE = 0, HP_D_GRAD = 1, HP_D_CURL = 2 } hp_diff;

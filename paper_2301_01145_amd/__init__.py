@@ -15,7 +15,9 @@ from ._lib import (  # noqa: F401  (C-ABI names)
 BCS = {"periodic": _lib.HP_PERIODIC, "dirichlet": _lib.HP_DIRICHLET,
        "neumann": _lib.HP_NEUMANN, "unbounded": _lib.HP_UNBOUNDED}
 GRIDS = {"regular": _lib.HP_REGULAR, "staggered": _lib.HP_STAGGERED}
-KERNELS = {"ps": _lib.HP_OP_PS, "fd2": _lib.HP_OP_FD2, "g2": _lib.HP_G_GAUSS2}
+KERNELS = {"ps": _lib.HP_OP_PS, "fd2": _lib.HP_OP_FD2, "g2": _lib.HP_G_GAUSS2,
+           "g4": _lib.HP_G_GAUSS4, "g6": _lib.HP_G_GAUSS6, "g8": _lib.HP_G_GAUSS8,
+           "g10": _lib.HP_G_GAUSS10, "spectral": _lib.HP_G_SPECTRAL}
 DIFFS = {"none": _lib.HP_D_NONE, "grad": _lib.HP_D_GRAD, "curl": _lib.HP_D_CURL}
 
 

@@ -139,7 +139,7 @@ hp_status validate(const hp_desc* d) {
   if (d->ncomp == 3 && d->ndim != 3) return fail(nullptr, HP_E_ARG, "vector fields need ndim 3");
   if (d->bc < 0 || d->bc > 3) return fail(nullptr, HP_E_ARG, "bad bc");
   if (d->grid < 0 || d->grid > 1) return fail(nullptr, HP_E_ARG, "bad grid");
-  if (d->kernel < 0 || d->kernel > 2) return fail(nullptr, HP_E_ARG, "bad kernel");
+  if (d->kernel < 0 || d->kernel > HP_G_SPECTRAL) return fail(nullptr, HP_E_ARG, "bad kernel");
   if (d->diff < 0 || d->diff > 2) return fail(nullptr, HP_E_ARG, "bad diff");
   if (d->prec < 0 || d->prec > 1) return fail(nullptr, HP_E_ARG, "bad prec");
   if (d->reg_sigma_cells < 0.0 || !std::isfinite(d->reg_sigma_cells))
@@ -154,9 +154,9 @@ hp_status validate(const hp_desc* d) {
       return fail(nullptr, HP_E_ARG, "too few cells for this BC and grid");
   }
   const bool unb = d->bc == HP_UNBOUNDED;
-  if (unb && d->kernel != HP_G_GAUSS2)
-    return fail(nullptr, HP_E_ARG, "unbounded plans take a Green's kernel (HP_G_GAUSS2)");
-  if (!unb && d->kernel == HP_G_GAUSS2)
+  if (unb && d->kernel < HP_G_GAUSS2)
+    return fail(nullptr, HP_E_ARG, "unbounded plans take a Green's kernel (HP_G_GAUSS2 .. HP_G_SPECTRAL)");
+  if (!unb && d->kernel >= HP_G_GAUSS2)
     return fail(nullptr, HP_E_ARG, "bounded plans take PS or FD2 eigenvalues");
   if (d->inhomogeneous) {
     if (d->bc != HP_DIRICHLET && d->bc != HP_NEUMANN)
@@ -321,6 +321,61 @@ std::vector<double> wavenumbers(int N, double h, int count) {
 }
 
 // ----------------------------------------------------------- Green's spectrum
+// Nodes and weights of 8-point Gauss-Legendre quadrature on [-1, 1]: the roots
+// of the Legendre polynomial P_8 by Newton's method from the Chebyshev-like
+// first guesses cos(pi (i + 3/4) / (8 + 1/2)), weights 2 / ((1 - x^2) P_8'(x)^2).
+void gauss_legendre8(double* x, double* w) {
+  const int n = 8;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;  // P_0, P_1; recurrence (k+1) P_{k+1} = (2k+1) z P_k - k P_{k-1}
+      for (int k = 1; k < n; ++k) {
+        const double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 1; k < n; ++k) {
+      const double p2 = ((2 * k + 1) * z * p1 - k * p0) / (k + 1);
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Si(j step), j < n: the integral of sin(t) / t accumulated interval by
+// interval (four 8-point Gauss-Legendre panels per interval, compensated sum).
+std::vector<double> sine_integral_table(int n, double step, const double* gx, const double* gw) {
+  std::vector<double> tab(n, 0.0);
+  double sum = 0.0, comp = 0.0;
+  for (int j = 1; j < n; ++j) {
+    for (int q = 0; q < 4; ++q) {
+      const double a = (j - 1) * step + q * step / 4, b = a + step / 4;
+      const double mid = 0.5 * (a + b), half = 0.5 * (b - a);
+      double acc = 0.0;
+      for (int i = 0; i < 8; ++i) {
+        const double t = mid + half * gx[i];
+        acc += gw[i] * std::sin(t) / t;
+      }
+      const double y = half * acc - comp;
+      const double t2 = sum + y;
+      comp = (t2 - sum) - y;
+      sum = t2;
+    }
+    tab[j] = sum;
+  }
+  return tab;
+}
+
 hp_status green_spectrum(hp_plan p, Problem& P) {
   const int M[3] = {P.M[0], P.M[1], P.M[2]};
   const int K2 = M[2] / 2 + 1;
@@ -336,8 +391,31 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
     return fail(p, HP_E_NOMEM, "Green's spectrum allocation failed");
   }
   hp_status st = HP_OK;
+  GreenEval ge{};
+  ge.kind = P.d.kernel == HP_G_SPECTRAL ? 0 : 2 * (P.d.kernel - HP_G_GAUSS2 + 1);
+  ge.sigma = sigma;
+  ge.kc = M_PI / hmax;
+  gauss_legendre8(ge.gl_x, ge.gl_w);
+  void* si_dev = nullptr;
+  if (ge.kind == 0) {
+    // Si on a table of step 1/2 up to past k_c times the largest distance
+    double rmax2 = 0.0;
+    for (int a = 0; a < 3; ++a) rmax2 += std::pow(0.5 * M[a] * P.h[a], 2);
+    ge.si_step = 0.5;
+    ge.si_n = (int)std::ceil(ge.kc * std::sqrt(rmax2) / ge.si_step) + 2;
+    const std::vector<double> tab = sine_integral_table(ge.si_n, ge.si_step, ge.gl_x, ge.gl_w);
+    if (hipMalloc(&si_dev, tab.size() * 8) != hipSuccess ||
+        hipMemcpy(si_dev, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      if (si_dev) (void)hipFree(si_dev);
+      (void)hipFree(g);
+      (void)hipFree(spec);
+      return fail(p, HP_E_NOMEM, "sine-integral table allocation failed");
+    }
+    ge.si = (const double*)si_dev;
+  }
   auto run = [&]() -> hp_status {
-    HP_HIP(p, launch_green_eval((double*)g, M, P.h, sigma, P.h[0] * P.h[1] * P.h[2], p->stream));
+    HP_HIP(p, launch_green_eval((double*)g, M, P.h, ge, P.h[0] * P.h[1] * P.h[2], p->stream));
     // FP64 forward transform with the general passes (a temporary FP64 view)
     const int saved_prec = p->prec;
     const size_t saved_es = p->es;
@@ -412,6 +490,7 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
   (void)hipStreamSynchronize(p->stream);
   (void)hipFree(g);
   (void)hipFree(spec);
+  if (si_dev) (void)hipFree(si_dev);
   return st;
 }
 

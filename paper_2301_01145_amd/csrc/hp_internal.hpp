@@ -115,8 +115,22 @@ bool fast_tile_ok(int fast, int L, int P, int prec);
 
 // Launch one pass over `grid_y` independent field groups.
 hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s);
-// Evaluate prod(H) * G2 on the doubled grid (FP64, real, [M0][M1][M2]).
-hipError_t launch_green_eval(double* g, const int M[3], const double h[3], double sigma,
+// Free-space kernel of the plan (Section 2.5.2 readings): Gaussian order
+// `kind` = 2, 4, ..., 10 of width sigma, or `kind` = 0, the spectral cutoff
+// at kc with Si(j si_step) tabulated for j < si_n and an 8-point
+// Gauss-Legendre rule (nodes gl_x, weights gl_w on [-1, 1]) for the rest.
+struct GreenEval {
+  int kind;
+  double sigma;
+  double kc;
+  const double* si;
+  double si_step;
+  int si_n;
+  double gl_x[8], gl_w[8];
+};
+// Evaluate scale * G on the doubled grid (FP64, real, [M0][M1][M2]) at the
+// mirrored distances.
+hipError_t launch_green_eval(double* g, const int M[3], const double h[3], const GreenEval& ge,
                              double scale, hipStream_t s);
 // Keep the real part of an FP64 half spectrum [M0][M1][M2/2+1] (complex) on the
 // octant, scaled, as T, stored [M2/2+1][M1/2+1][M0/2+1] (axis 0 contiguous).

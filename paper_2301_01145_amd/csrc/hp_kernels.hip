@@ -704,8 +704,44 @@ hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int ni
 }
 
 // ------------------------------------------------------ plan-time kernels
+// G(r) of the free-space kernel (GreenEval); see the kernel list in hipoisson.h.
+__device__ double green_value(double r, const GreenEval& e) {
+  if (e.kind == 0) {
+    // spectral cutoff: -Si(kc r) / (2 pi^2 r); Si from the nearest table node
+    // plus the Gauss-Legendre integral of sin(t) / t over the remaining stretch
+    if (r == 0.0) return -e.kc / (2.0 * M_PI * M_PI);
+    const double x = e.kc * r;
+    int j = (int)(x / e.si_step + 0.5);
+    j = min(j, e.si_n - 1);
+    const double a = j * e.si_step;
+    const double mid = 0.5 * (x + a), half = 0.5 * (x - a);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double t = mid + half * e.gl_x[q];
+      acc += e.gl_w[q] * sin(t) / t;
+    }
+    return -(e.si[j] + half * acc) / (2.0 * M_PI * M_PI * r);
+  }
+  // Gaussian order 2m: -(1 / (4 pi sigma)) [erf(rho / sqrt2) / rho
+  //                    + sqrt(2 / pi) exp(-rho^2 / 2) S_m(rho^2)], with the
+  // Hermite sum S_m expanded in t = rho^2
+  const double rho = r / e.sigma, t = rho * rho;
+  const double s2pi = 0.79788456080286535587989211986876;  // sqrt(2 / pi)
+  const double E = rho == 0.0 ? s2pi : erf(rho / M_SQRT2) / rho;
+  double S = 0.0;
+  switch (e.kind) {
+    case 4: S = 0.5; break;
+    case 6: S = (7.0 - t) / 8.0; break;
+    case 8: S = ((t - 16.0) * t + 57.0) / 48.0; break;
+    case 10: S = (((29.0 - t) * t - 233.0) * t + 561.0) / 384.0; break;
+    default: break;
+  }
+  return -(E + s2pi * exp(-0.5 * t) * S) / (4.0 * M_PI * e.sigma);
+}
+
 __global__ void k_green_eval(double* g, int M0, int M1, int M2, double h0, double h1,
-                             double h2, double sigma, double scale) {
+                             double h2, const GreenEval e, double scale) {
   const long long total = (long long)M0 * M1 * M2;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
@@ -713,21 +749,15 @@ __global__ void k_green_eval(double* g, int M0, int M1, int M2, double h0, doubl
     const int y = (int)((i / M2) % M1);
     const int x = (int)(i / ((long long)M1 * M2));
     const double dx = min(x, M0 - x) * h0, dy = min(y, M1 - y) * h1, dz = min(z, M2 - z) * h2;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    double v;
-    if (r == 0.0) {
-      v = -1.0 / (pow(2.0 * M_PI, 1.5) * sigma);
-    } else {
-      v = -erf(r / (M_SQRT2 * sigma)) / (4.0 * M_PI * r);
-    }
-    g[i] = v * scale;
+    g[i] = green_value(sqrt(dx * dx + dy * dy + dz * dz), e) * scale;
   }
 }
 
-hipError_t launch_green_eval(double* g, const int M[3], const double h[3], double sigma,
+hipError_t launch_green_eval(double* g, const int M[3], const double h[3], const GreenEval& ge,
                              double scale, hipStream_t s) {
+  if (ge.kind == 0 && (!ge.si || ge.si_n < 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_green_eval, dim3(4096), dim3(256), 0, s, g, M[0], M[1], M[2], h[0], h[1],
-                     h[2], sigma, scale);
+                     h[2], ge, scale);
   return hipGetLastError();
 }
 

@@ -9,7 +9,8 @@
   tests/golden/make_unbounded_samples.py from oracle/), full-field L2 norms,
   and psi at 8 points by the oracle's direct sum (independent of the file).
 * The Gaussian-blob twin at 256^3: psi and curl against the closed form.
-* 3D free-space 128^3 (doubled 256^3) curl: every element against the oracle.
+* 3D free-space 128^3 (doubled 256^3) curl with the G2, G6, G10 and spectral
+  kernels: every element against the oracle.
 """
 import math
 import os
@@ -147,8 +148,9 @@ def test_unbounded_256_gaussian_closed_form():
     s.close()
 
 
+@pytest.mark.parametrize("kernel", ["g2", "g6", "g10", "spectral"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_unbounded_128_curl_full(prec):
+def test_unbounded_128_curl_full(prec, kernel):
     import torch
     import oracle
     from paper_2301_01145_amd import Solver
@@ -157,10 +159,11 @@ def test_unbounded_128_curl_full(prec):
     dtype = torch.float32 if prec == "f32" else torch.float64
     rnd = np.float32 if prec == "f32" else np.float64
     f = vortex_rings(n, seed=6, count=16, r_range=(0.08, 0.16), core_ratio=0.25).astype(rnd).astype(np.float64)
-    s = Solver("unbounded", "staggered", [n] * 3, diff="curl", dtype=dtype, ncomp=3)
+    s = Solver("unbounded", "staggered", [n] * 3, kernel=kernel, diff="curl", dtype=dtype, ncomp=3)
     psi, u = s.solve([torch.as_tensor(f[c], dtype=dtype, device="cuda") for c in range(3)])
     torch.cuda.synchronize()
-    ref_psi, ref_u = oracle.solve("unbounded", "staggered", [n] * 3, [0, 0, 0], [1, 1, 1], f, diff="curl")
+    ref_psi, ref_u = oracle.solve("unbounded", "staggered", [n] * 3, [0, 0, 0], [1, 1, 1], f,
+                                  operator=kernel, diff="curl")
     l2, mx = TOL[prec]
     for c in range(3):
         assert rel_l2(psi[c].double().cpu().numpy(), ref_psi[c]) <= l2

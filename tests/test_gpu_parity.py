@@ -175,6 +175,47 @@ def test_unbounded(nc, ncomp, diff, prec, grid):
         check(gd[a], rd[a], prec, f"deriv {a}")
 
 
+NEW_KERNELS = ["g4", "g6", "g8", "g10", "spectral"]
+
+
+@pytest.mark.parametrize("kernel", NEW_KERNELS)
+@pytest.mark.parametrize("nc,ncomp,diff", [([10, 12, 8], 1, "none"), ([24, 20, 16], 1, "grad"),
+                                           ([32, 32, 64], 3, "curl"), ([9, 15, 10], 1, "none")])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unbounded_kernels(kernel, nc, ncomp, diff, prec):
+    # higher-order Gaussian and spectral kernels (anisotropic cells: the
+    # spectral cutoff uses the largest spacing); general and wavefront passes
+    f, _ = case_input("unbounded", "staggered", nc, ncomp, False, prec, seed=23)
+    got, gd = gpu_solve("unbounded", "staggered", nc, LO, HI, f, kernel, diff, prec, ncomp, None)
+    ref, rd = oracle_solve("unbounded", "staggered", nc, LO, HI, f, kernel, diff, None)
+    check(got, ref, prec, "psi")
+    for a in range(len(rd)):
+        check(gd[a], rd[a], prec, f"deriv {a}")
+
+
+@pytest.mark.parametrize("kernel", ["g6", "spectral"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unbounded_kernels_adjoint(kernel, prec):
+    import torch
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd import Solver
+    nc = [16, 12, 20]
+    rng = np.random.default_rng(29)
+    rnd = np.float32 if prec == "f32" else np.float64
+    gpsi = rng.normal(size=(3,) + tuple(nc)).astype(rnd).astype(np.float64)
+    gder = [rng.normal(size=tuple(nc)).astype(rnd).astype(np.float64) for _ in range(3)]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver("unbounded", "staggered", nc, LO, HI, kernel=kernel, diff="curl", dtype=dtype, ncomp=3)
+    dev = lambda x: torch.as_tensor(x, dtype=dtype, device="cuda")
+    out = s.adjoint([dev(gpsi[c]) for c in range(3)], [dev(g) for g in gder])
+    torch.cuda.synchronize()
+    got = np.stack([o.double().cpu().numpy() for o in out])
+    hs = [(HI[a] - LO[a]) / nc[a] for a in range(3)]
+    ref = ub.adjoint_unbounded(gpsi, gder, hs, 2.0 * max(hs), "curl", kernel=kernel)
+    s.close()
+    check(got, ref, prec, "adjoint")
+
+
 @pytest.mark.parametrize("generic", [False, True])
 def test_unbounded_generic_matches_fast(generic, monkeypatch):
     """The same power-of-two problem through the general passes and the wavefront kernels."""

@@ -31,7 +31,9 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     f: source on the unknown points (scalar), or (3, ...) for a 3D vector
     operator: "ps" | "fd2" for bounded BCs; for unbounded, the Green's kernel
               ("g2", "g4", "g6", "g8", "g10", "spectral"; anything else: "g2")
-    diff: "none" | "grad" | "curl"
+    diff: "none" | "grad" | "curl" | "div" | "nabla" (Section 2.3.3's operators,
+          applied to psi: gradient of a scalar, curl or divergence of a 3D
+          vector, Laplacian of every component)
     faces: {(axis, side): g} boundary values (FD2 Dirichlet / Neumann)
     Returns (psi, derivs) on the output points.
     """
@@ -57,6 +59,16 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
             raise NotImplementedError("bounded curl: periodic 3D vector only")
         g = [bounded.periodic_gradient(p, lengths) for p in psi]
         derivs = [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+    elif diff == "div":
+        if bc != "periodic" or not vector or nd != 3:
+            raise NotImplementedError("bounded divergence: periodic 3D vector only")
+        derivs = [sum(bounded.periodic_gradient(psi[c], lengths)[c] for c in range(3))]
+    elif diff == "nabla":
+        if bc != "periodic":
+            raise NotImplementedError("bounded Laplacian: periodic only")
+        # the spectral first derivative (Nyquist zeroed) applied twice per axis
+        derivs = [sum(bounded.periodic_gradient(bounded.periodic_gradient(p, lengths)[a], lengths)[a]
+                      for a in range(nd)) for p in psi]
     elif diff != "none":
         raise ValueError(diff)
     return (np.stack(psi) if vector else psi[0]), derivs

@@ -167,7 +167,9 @@ def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
     f has shape (n_x, n_y, n_z) or (3, n_x, n_y, n_z).  Returns
     (psi, derivs): psi like f; derivs is [] for diff="none", the gradient
     components of a scalar psi for "grad", the curl of a 3-component psi for
-    "curl".
+    "curl", its divergence for "div" and the Laplacian of every component for
+    "nabla" (the spectral first derivative, Nyquist zeroed, applied twice per
+    axis).  `kernel` names the Green's kernel (KERNELS).
     """
     f = np.asarray(f, dtype=np.float64)
     vector = f.ndim == 4
@@ -192,6 +194,13 @@ def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
             _back(1j * (kz * px - kx * pz), shape),
             _back(1j * (kx * py - ky * px), shape),
         ]
+    elif diff == "div":
+        if not vector:
+            raise ValueError("div needs a 3-component field")
+        derivs = [_back(sum(1j * ks[a] * psihat[a] for a in range(3)), shape)]
+    elif diff == "nabla":
+        # sum over axes of the spectral first derivative applied twice
+        derivs = [_back(sum((1j * ks[a]) ** 2 for a in range(3)) * p, shape) for p in psihat]
     elif diff != "none":
         raise ValueError(diff)
     psi_out = np.stack(psi) if vector else psi[0]
@@ -215,7 +224,7 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
         vector = g_psi.ndim == 4
         shape = g_psi.shape[1:] if vector else g_psi.shape
     else:
-        vector = diff == "curl"
+        vector = diff in ("curl", "div") or (diff == "nabla" and len(derivs) == 3)
         shape = derivs[0].shape
     ghat = green_spectrum(shape, hs, sigma, kernel)
     ks = wavenumbers(shape, hs)
@@ -235,6 +244,16 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
     elif diff == "grad":
         for a in range(3):
             acc[0] = acc[0] - 1j * ks[a] * np.fft.rfftn(_pad(derivs[a]))
+    elif diff == "div":
+        # the divergence's transpose is minus the gradient
+        gd = np.fft.rfftn(_pad(derivs[0]))
+        for c in range(3):
+            acc[c] = acc[c] - 1j * ks[c] * gd
+    elif diff == "nabla":
+        # the Laplacian (a real even multiplier) is its own transpose
+        lap = sum((1j * ks[a]) ** 2 for a in range(3))
+        for c in range(ncomp):
+            acc[c] = acc[c] + lap * np.fft.rfftn(_pad(derivs[c]))
     elif diff != "none":
         raise ValueError(diff)
     out = [_back(ghat * s, shape) for s in acc]

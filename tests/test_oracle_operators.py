@@ -1,0 +1,113 @@
+"""Pins of the oracle's DIV and NABLA operators (Section 2.3.3 lists DIV, GRAD,
+CURL and NABLA; they act on psi after the convolution, as in Section 4.3).
+
+NABLA is read as the spectral first derivative (Nyquist mode zeroed) applied
+twice per axis and summed; DIV as the sum of the components' own derivatives.
+  * periodic PS: for a source of Fourier modes below the Nyquist index the
+    Laplacian of psi is the source itself, and the divergence of psi is a
+    closed form per mode;
+  * free space, spectral kernel: the Laplacian of psi of a resolved Gaussian
+    blob is the blob itself;
+  * free space, G2 kernel: the divergence of psi of the field (blob, 0, 0) is
+    the closed-form x-derivative of the blob's potential;
+  * the transposes used by the adjoint: <K a, b> = <a, K^T b>.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import oracle
+from oracle import unbounded as ub
+
+
+def _modes(rng, n, lengths, count):
+    out = []
+    for _ in range(count):
+        m = [int(rng.integers(-(na // 2) + 1, na // 2)) for na in n]
+        if all(v == 0 for v in m):
+            m[0] = 1
+        out.append((m, rng.normal(), rng.uniform(0, 2 * np.pi)))
+    return out
+
+
+def _grid(n, lo, hi):
+    xs = [lo[a] + (np.arange(n[a]) + 0.5) * (hi[a] - lo[a]) / n[a] for a in range(len(n))]
+    return np.meshgrid(*xs, indexing="ij")
+
+
+def test_periodic_nabla_returns_source():
+    rng = np.random.default_rng(31)
+    n, lo, hi = (12, 10, 8), [0.0, -0.5, 1.0], [1.0, 1.3, 2.5]
+    L = [hi[a] - lo[a] for a in range(3)]
+    X = _grid(n, lo, hi)
+    f = np.zeros(n)
+    for m, A, ph in _modes(rng, n, L, 6):
+        f += A * np.cos(sum(2 * np.pi * m[a] * (X[a] - lo[a]) / L[a] for a in range(3)) + ph)
+    psi, (lap,) = oracle.solve("periodic", "staggered", list(n), lo, hi, f, operator="ps", diff="nabla")
+    assert np.max(np.abs(lap - f)) <= 1e-12 * np.max(np.abs(f))
+
+
+def test_periodic_div_closed_form():
+    rng = np.random.default_rng(32)
+    n, lo, hi = (10, 12, 14), [0.0, 0.0, 0.0], [1.0, 1.5, 0.8]
+    L = [hi[a] - lo[a] for a in range(3)]
+    X = _grid(n, lo, hi)
+    f = np.zeros((3,) + n)
+    ref = np.zeros(n)
+    for c in range(3):
+        for m, A, ph in _modes(rng, n, L, 3):
+            k = [2 * np.pi * m[a] / L[a] for a in range(3)]
+            th = sum(k[a] * (X[a] - lo[a]) for a in range(3)) + ph
+            f[c] += A * np.cos(th)
+            k2 = sum(v * v for v in k)
+            # psi_c = -A cos(th) / |k|^2, d_c psi_c = A k_c sin(th) / |k|^2
+            ref += A * k[c] * np.sin(th) / k2
+    _, (div,) = oracle.solve("periodic", "staggered", list(n), lo, hi, f, operator="ps", diff="div")
+    assert np.max(np.abs(div - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _blob(n, c, A, s):
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    d = (X - c[0], Y - c[1], Z - c[2])
+    r = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+    return h, r, d, A * np.exp(-r * r / (2 * s * s))
+
+
+def test_unbounded_spectral_nabla_returns_source():
+    h, r, _, f = _blob(48, (0.5, 0.47, 0.52), 1.1, 0.06)
+    _, (lap,) = ub.solve_unbounded(f, [h] * 3, 2 * h, "nabla", kernel="spectral")
+    assert np.max(np.abs(lap - f)) <= 1e-11 * np.max(np.abs(f))
+
+
+def test_unbounded_g2_div_closed_form():
+    h, r, d, b = _blob(48, (0.5, 0.5, 0.47), 0.8, 0.05)
+    sigma = 2 * h
+    fv = np.stack([b, 0 * b, 0 * b])
+    _, (div,) = ub.solve_unbounded(fv, [h] * 3, sigma, "div")
+    Q = 0.8 * (2 * np.pi * 0.05 ** 2) ** 1.5
+    se = math.sqrt(0.05 ** 2 + sigma ** 2)
+    dpsi = (Q * erf(r / (math.sqrt(2) * se)) / (4 * np.pi * r ** 2)
+            - Q * math.sqrt(2 / np.pi) / se * np.exp(-r ** 2 / (2 * se * se)) / (4 * np.pi * r))
+    ref = dpsi * d[0] / r
+    assert np.max(np.abs(div - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("diff,vec", [("div", True), ("nabla", False), ("nabla", True)])
+def test_div_nabla_transposes(diff, vec):
+    rng = np.random.default_rng(12)
+    shape = (6, 7, 5)
+    hs = [0.1, 0.12, 0.08]
+    a = rng.normal(size=((3,) + shape) if vec else shape)
+    Ka_psi, Ka_d = ub.solve_unbounded(a, hs, 0.2, diff)
+    b_psi = rng.normal(size=Ka_psi.shape)
+    b_d = [rng.normal(size=shape) for _ in Ka_d]
+    lhs = np.sum(Ka_psi * b_psi) + sum(np.sum(x * y) for x, y in zip(Ka_d, b_d))
+    rhs = np.sum(a * ub.adjoint_unbounded(b_psi, b_d, hs, 0.2, diff))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    lhs2 = sum(np.sum(x * y) for x, y in zip(Ka_d, b_d))
+    rhs2 = np.sum(a * ub.adjoint_unbounded(None, b_d, hs, 0.2, diff))
+    assert abs(lhs2 - rhs2) <= 1e-11 * abs(lhs2)

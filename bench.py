@@ -166,6 +166,14 @@ def other_workloads(steps, warmup):
         kern[kname] = {"plan_ms": plan_ms, "solve_ms": solve_ms, "blob_rel_max_err_64": errs[0],
                        "blob_rel_max_err_128": errs[1], "observed_order": float(np.log2(errs[0] / errs[1]))}
     res["unbounded256_kernels"] = kern
+    # Section 2.3.3's DIV (vector -> scalar) and NABLA on psi at 256^3, FP32 (general passes)
+    for dname, nc_ in (("div", 3), ("nabla", 1)):
+        s = Solver("unbounded", "staggered", [256] * 3, diff=dname, dtype=torch.float32, ncomp=nc_)
+        s.bind(f_rings if nc_ == 3 else f_rings[0])
+        ms = _time(s.run, max(5, steps // 4), warmup, s.stream)
+        res[f"unbounded256_{dname}_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+                                             "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+        s.close()
     # differentiable 128^3 curl solve: forward + backward of sum |u - u_t|^2, FP32
     n = 128
     fr = vortex_rings(n, seed=6, count=16, r_range=(0.08, 0.16), core_ratio=0.25).astype(np.float32)

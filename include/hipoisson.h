@@ -78,9 +78,13 @@ typedef enum {
   HP_G_GAUSS2 = 2, HP_G_GAUSS4 = 3, HP_G_GAUSS6 = 4, HP_G_GAUSS8 = 5, HP_G_GAUSS10 = 6,
   HP_G_SPECTRAL = 7
 } hp_kernel;
-/* Spectral derivative applied after the convolution (Section 2.3.3):
- * GRAD of a scalar (ndim extra outputs), CURL of a 3D vector (3 outputs). */
-typedef enum { HP_D_NONE = 0, HP_D_GRAD = 1, HP_D_CURL = 2 } hp_diff;
+/* Spectral operator applied to psi after the convolution (Section 2.3.3's
+ * list): GRAD of a scalar (ndim extra outputs), CURL of a 3D vector (3
+ * outputs), DIV of a 3D vector (1 output), NABLA, the Laplacian of every
+ * component (ncomp outputs).  Derivatives multiply by i k_a with the Nyquist
+ * mode set to zero; NABLA is that first derivative applied twice per axis and
+ * summed.  DIV and NABLA run on the general passes. */
+typedef enum { HP_D_NONE = 0, HP_D_GRAD = 1, HP_D_CURL = 2, HP_D_DIV = 3, HP_D_NABLA = 4 } hp_diff;
 typedef enum { HP_F32 = 0, HP_F64 = 1 } hp_prec;
 
 typedef struct {

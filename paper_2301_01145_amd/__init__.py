@@ -18,7 +18,8 @@ GRIDS = {"regular": _lib.HP_REGULAR, "staggered": _lib.HP_STAGGERED}
 KERNELS = {"ps": _lib.HP_OP_PS, "fd2": _lib.HP_OP_FD2, "g2": _lib.HP_G_GAUSS2,
            "g4": _lib.HP_G_GAUSS4, "g6": _lib.HP_G_GAUSS6, "g8": _lib.HP_G_GAUSS8,
            "g10": _lib.HP_G_GAUSS10, "spectral": _lib.HP_G_SPECTRAL}
-DIFFS = {"none": _lib.HP_D_NONE, "grad": _lib.HP_D_GRAD, "curl": _lib.HP_D_CURL}
+DIFFS = {"none": _lib.HP_D_NONE, "grad": _lib.HP_D_GRAD, "curl": _lib.HP_D_CURL,
+         "div": _lib.HP_D_DIV, "nabla": _lib.HP_D_NABLA}
 
 
 def make_desc(bc, grid, nc, lo=None, hi=None, kernel=None, diff="none", prec="f32", ncomp=1,

@@ -15,7 +15,7 @@ HP_PERIODIC, HP_DIRICHLET, HP_NEUMANN, HP_UNBOUNDED = 0, 1, 2, 3
 HP_REGULAR, HP_STAGGERED = 0, 1
 HP_OP_PS, HP_OP_FD2, HP_G_GAUSS2 = 0, 1, 2
 HP_G_GAUSS4, HP_G_GAUSS6, HP_G_GAUSS8, HP_G_GAUSS10, HP_G_SPECTRAL = 3, 4, 5, 6, 7
-HP_D_NONE, HP_D_GRAD, HP_D_CURL = 0, 1, 2
+HP_D_NONE, HP_D_GRAD, HP_D_CURL, HP_D_DIV, HP_D_NABLA = 0, 1, 2, 3, 4
 HP_F32, HP_F64 = 0, 1
 HP_Q_MODEL_BYTES, HP_Q_WORKSPACE_BYTES, HP_Q_NUM_PASSES, HP_Q_NUM_OUTPUTS, HP_Q_NUM_DERIVS = 1, 2, 3, 4, 5
 HP_Q_BATCH_ERROR = 6

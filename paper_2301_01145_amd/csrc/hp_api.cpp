@@ -140,7 +140,7 @@ hp_status validate(const hp_desc* d) {
   if (d->bc < 0 || d->bc > 3) return fail(nullptr, HP_E_ARG, "bad bc");
   if (d->grid < 0 || d->grid > 1) return fail(nullptr, HP_E_ARG, "bad grid");
   if (d->kernel < 0 || d->kernel > HP_G_SPECTRAL) return fail(nullptr, HP_E_ARG, "bad kernel");
-  if (d->diff < 0 || d->diff > 2) return fail(nullptr, HP_E_ARG, "bad diff");
+  if (d->diff < 0 || d->diff > HP_D_NABLA) return fail(nullptr, HP_E_ARG, "bad diff");
   if (d->prec < 0 || d->prec > 1) return fail(nullptr, HP_E_ARG, "bad prec");
   if (d->reg_sigma_cells < 0.0 || !std::isfinite(d->reg_sigma_cells))
     return fail(nullptr, HP_E_ARG, "bad reg_sigma_cells");
@@ -166,6 +166,8 @@ hp_status validate(const hp_desc* d) {
   }
   if (d->diff == HP_D_CURL && (d->ncomp != 3 || d->ndim != 3))
     return fail(nullptr, HP_E_ARG, "curl needs a 3-component 3D field");
+  if (d->diff == HP_D_DIV && (d->ncomp != 3 || d->ndim != 3))
+    return fail(nullptr, HP_E_ARG, "div needs a 3-component 3D field");
   if (d->diff == HP_D_GRAD && d->ncomp != 1)
     return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
   if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN))
@@ -501,7 +503,11 @@ hp_status setup_problem(hp_plan p, Problem& P) {
   const hp_desc& d = P.d;
   P.nd = d.ndim;
   P.ncomp = d.ncomp;
-  P.nder = d.diff == HP_D_GRAD ? d.ndim : (d.diff == HP_D_CURL ? 3 : 0);
+  P.nder = d.diff == HP_D_GRAD    ? d.ndim
+           : d.diff == HP_D_CURL  ? 3
+           : d.diff == HP_D_DIV   ? 1
+           : d.diff == HP_D_NABLA ? d.ncomp
+                                  : 0;
   for (int a = 0; a < 3; ++a) {
     P.n[a] = P.nout[a] = P.M[a] = 1;
     P.h[a] = P.len[a] = 1.0;
@@ -639,6 +645,17 @@ void strides_of(const int* dims, long long* s) {
   s[0] = (long long)dims[1] * dims[2];
 }
 
+// Sandwich coupling of the descriptor's operator (forward or transposed).
+int diff_kind(int dk, bool adjoint) {
+  switch (dk) {
+    case HP_D_GRAD: return adjoint ? D_ADJ_GRAD : D_GRAD;
+    case HP_D_CURL: return adjoint ? D_ADJ_CURL : D_CURL;
+    case HP_D_DIV: return adjoint ? D_ADJ_DIV : D_DIV;
+    case HP_D_NABLA: return adjoint ? D_ADJ_NABLA : D_NABLA;
+    default: return D_NONE;
+  }
+}
+
 // FNV-1a over the integers that fix a pass's geometry.
 unsigned long long tune_hash(const long long* v, int n) {
   unsigned long long h = 1469598103934665603ull;
@@ -703,7 +720,7 @@ hp_status finish_pass_with(hp_plan p, PassArgs& a, int want, int minP, int lds_k
                        [&](int q) { return (long long)(q / 2) * a.L * cs + (long long)q * a.nin * es; }, nfft_pair, &lds);
         break;
       case 4: {  // c2c sandwich: (nS + 1) complex tiles
-        const int nS = (a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD) ? a.n_out : a.n_in;
+        const int nS = diff_is_adjoint(a.diff) ? a.n_out : a.n_in;
         a.P = choose_P(want, minP, a.Np, a.L, p->prec, big,
                        [&](int q) { return (long long)(nS + 1) * q * a.L * cs; }, nfft_one, &lds);
       } break;
@@ -959,7 +976,7 @@ hp_status passes_periodic(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     a.mult = M_EIGEN;
     for (int b = 0; b < nd; ++b) { a.lam[b] = P.lam[b]; a.kvec[b] = P.kvec[b]; }
     a.norm = P.norm;
-    a.diff = P.d.diff == HP_D_GRAD ? D_GRAD : (P.d.diff == HP_D_CURL ? D_CURL : D_NONE);
+    a.diff = diff_kind(P.d.diff, false);
     a.n_in = coupled ? nin : 1;
     a.n_out = coupled ? nfo : 1;
   };
@@ -1137,9 +1154,7 @@ hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<Pass
     for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
     a.gM[0] = M0; a.gM[1] = M1; a.gM[2] = M2;
     for (int b = 0; b < 3; ++b) a.kvec[b] = P.kvec[b];
-    const int dk = P.d.diff;
-    if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
-    else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
+    a.diff = diff_kind(P.d.diff, adjoint);
     const bool coupled = a.diff != D_NONE;
     a.n_in = coupled ? n_src : 1;
     a.n_out = coupled ? n_dst : 1;
@@ -1185,6 +1200,8 @@ hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<Pass
 // Also used for 3D periodic plans, whose transform lengths M are then n.
 bool fast_unbounded_ok(hp_plan p, const Problem& P) {
   if (std::getenv("HP_GENERIC") || P.nd != 3) return false;
+  // the wavefront passes provide the gradient and the curl
+  if (P.d.diff == HP_D_DIV || P.d.diff == HP_D_NABLA) return false;
   const bool pad = P.d.bc == HP_UNBOUNDED;
   auto pow2 = [](int v) { return v >= 64 && v <= 1024 && (v & (v - 1)) == 0; };
   for (int a = 0; a < 3; ++a)

@@ -26,8 +26,13 @@ enum Xform : int {
 
 enum PassKind : int { PK_ONEWAY = 0, PK_SANDWICH = 1 };
 enum MultKind : int { M_NONE = 0, M_EIGEN = 1, M_GREEN = 2 };
-// Derivative coupling inside the sandwich pass.
-enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_CURL = 4 };
+// Derivative coupling inside the sandwich pass (D_ADJ_*: the transposes used
+// by the adjoint solve).
+enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_CURL = 4,
+                      D_DIV = 5, D_NABLA = 6, D_ADJ_DIV = 7, D_ADJ_NABLA = 8 };
+__host__ __device__ inline bool diff_is_adjoint(int d) {
+  return d == D_ADJ_GRAD || d == D_ADJ_CURL || d == D_ADJ_DIV || d == D_ADJ_NABLA;
+}
 
 // Threads per workgroup of the general pencil kernels (and the persistent
 // batched kernel); the wavefront-FFT kernels size their own workgroups.

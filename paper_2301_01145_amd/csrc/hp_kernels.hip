@@ -432,7 +432,7 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
   const int nfft = pair ? a.P / 2 : a.P;
   const int L = a.L;
   const int tileC = nfft * L;
-  const bool adj = a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD;
+  const bool adj = diff_is_adjoint(a.diff);
   const int nS = adj ? a.n_out : a.n_in;
   // independent fields (no derivative coupling) take their field from blockIdx.y
   const int fb = (a.diff == D_NONE) ? (int)blockIdx.y : 0;
@@ -460,7 +460,18 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
       __syncthreads();
     }
   }
-  // Transposed derivative inputs: curl (symmetric) or minus the divergence.
+  // spectral Laplacian: the first derivative i k_b (Nyquist zeroed) twice per axis
+  auto lap_of = [&](const int k[3]) -> T {
+    T s = (T)0;
+    for (int b = 0; b < 3; ++b)
+      if (a.kvec[b]) {
+        const T kb = kval<T>(a, b, k);
+        s -= kb * kb;
+      }
+    return s;
+  };
+  // Transposed derivative inputs: curl (symmetric), minus the divergence
+  // (gradient), minus the gradient (divergence) or the Laplacian (symmetric).
   if (adj) {
     const int nextra = a.n_in - nS;
     for (int i = 0; i < nextra; ++i) {
@@ -481,6 +492,12 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
           C2<T> ig = cmuli(g);
           S[(size_t)c1 * tileC + e] = cadd(S[(size_t)c1 * tileC + e], cscale(ig, kc2));
           S[(size_t)c2 * tileC + e] = csub(S[(size_t)c2 * tileC + e], cscale(ig, kc1));
+        } else if (a.diff == D_ADJ_DIV) {
+          const C2<T> ig = cmuli(g);
+          for (int c = 0; c < nS; ++c)
+            S[(size_t)c * tileC + e] = csub(S[(size_t)c * tileC + e], cscale(ig, kval<T>(a, c, k)));
+        } else if (a.diff == D_ADJ_NABLA) {
+          S[(size_t)i * tileC + e] = cadd(S[(size_t)i * tileC + e], cscale(g, lap_of(k)));
         } else {
           const T ka = kval<T>(a, i, k);
           S[e] = csub(S[e], cscale(cmuli(g), ka));
@@ -501,7 +518,7 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
   __syncthreads();
   const int xb = pair ? X_PAIR_B : X_C2C_B;
   // derivative outputs (forward GRAD / CURL) through W, then psi in place
-  if (a.diff == D_GRAD || a.diff == D_CURL) {
+  if (a.diff == D_GRAD || a.diff == D_CURL || a.diff == D_DIV || a.diff == D_NABLA) {
     const int nd = a.n_out - a.n_in;
     for (int d = 0; d < nd; ++d) {
       for (int e = threadIdx.x; e < tileC; e += kThreads) {
@@ -512,6 +529,13 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
         C2<T> v;
         if (a.diff == D_GRAD) {
           v = cscale(cmuli(S[e]), kval<T>(a, d, k));
+        } else if (a.diff == D_DIV) {
+          C2<T> acc = {(T)0, (T)0};
+          for (int c = 0; c < a.n_in; ++c)
+            acc = cadd(acc, cscale(S[(size_t)c * tileC + e], kval<T>(a, c, k)));
+          v = cmuli(acc);
+        } else if (a.diff == D_NABLA) {
+          v = cscale(S[(size_t)d * tileC + e], lap_of(k));
         } else {
           const int c1 = (d + 1) % 3, c2 = (d + 2) % 3;
           v = cmuli(csub(cscale(S[(size_t)c2 * tileC + e], kval<T>(a, c1, k)),

@@ -40,6 +40,11 @@ BAD = [
     (dict(bc="periodic", grid="regular", nc=[8, 8], diff="curl"), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=1), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="regular", nc=[8, 8, 8], diff="grad", ncomp=3), _lib.HP_E_ARG),
+    (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="div", ncomp=1), _lib.HP_E_ARG),
+    (dict(bc="periodic", grid="regular", nc=[8, 8], diff="div"), _lib.HP_E_ARG),
+    (dict(bc="neumann", grid="staggered", nc=[8, 8, 8], diff="nabla"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="spectral"), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8], kernel="g2"), _lib.HP_E_UNSUPPORTED),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="g2"), _lib.HP_E_ARG),
@@ -64,7 +69,7 @@ def test_descriptor_validation(kw, status):
 
 def test_bad_enum_values():
     d = make_desc("periodic", "regular", [8])
-    for field, val in [("bc", 7), ("grid", 5), ("kernel", 9), ("diff", 4), ("prec", 3), ("ndim", 4), ("ncomp", 2)]:
+    for field, val in [("bc", 7), ("grid", 5), ("kernel", 9), ("diff", 5), ("prec", 3), ("ndim", 4), ("ncomp", 2)]:
         old = getattr(d, field)
         setattr(d, field, val)
         assert create_status(d) == _lib.HP_E_ARG, field

@@ -216,6 +216,60 @@ def test_unbounded_kernels_adjoint(kernel, prec):
     check(got, ref, prec, "adjoint")
 
 
+@pytest.mark.parametrize("bc,nc", [("periodic", [12, 10, 8]), ("periodic", [64, 32, 64]),
+                                   ("unbounded", [10, 12, 8]), ("unbounded", [32, 32, 64])])
+@pytest.mark.parametrize("diff,ncomp", [("div", 3), ("nabla", 1), ("nabla", 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_div_nabla(bc, nc, diff, ncomp, prec):
+    # Section 2.3.3's DIV and NABLA on psi (general passes, also at power-of-two sizes)
+    kernel = "ps" if bc == "periodic" else "g2"
+    f, _ = case_input(bc, "staggered", nc, ncomp, False, prec, seed=37)
+    got, gd = gpu_solve(bc, "staggered", nc, LO, HI, f, kernel, diff, prec, ncomp, None)
+    ref, rd = oracle_solve(bc, "staggered", nc, LO, HI, f, kernel, diff, None)
+    check(got, ref, prec, "psi")
+    assert len(gd) == len(rd) == (1 if diff == "div" else ncomp)
+    for a in range(len(rd)):
+        check(gd[a], rd[a], prec, f"{diff} {a}")
+
+
+@pytest.mark.parametrize("nd,nc", [(1, [24]), (2, [12, 20]), (2, [64, 64])])
+@pytest.mark.parametrize("kernel", ["ps", "fd2"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_periodic_nabla_low_dim(nd, nc, kernel, prec):
+    f, _ = case_input("periodic", "staggered", nc, 1, False, prec, seed=38)
+    got, gd = gpu_solve("periodic", "staggered", nc, LO[:nd], HI[:nd], f, kernel, "nabla", prec, 1, None)
+    ref, rd = oracle_solve("periodic", "staggered", nc, LO[:nd], HI[:nd], f, kernel, "nabla", None)
+    check(got, ref, prec, "psi")
+    check(gd[0], rd[0], prec, "nabla")
+
+
+@pytest.mark.parametrize("diff,ncomp", [("div", 3), ("nabla", 1), ("nabla", 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("with_psi", [True, False])
+def test_div_nabla_adjoint(diff, ncomp, prec, with_psi):
+    import torch
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd import Solver
+    nc = [16, 12, 20]
+    rng = np.random.default_rng(41)
+    rnd = np.float32 if prec == "f32" else np.float64
+    shape = tuple(nc)
+    gpsi = rng.normal(size=((ncomp,) + shape) if ncomp == 3 else shape).astype(rnd).astype(np.float64)
+    nder = 1 if diff == "div" else ncomp
+    gder = [rng.normal(size=shape).astype(rnd).astype(np.float64) for _ in range(nder)]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver("unbounded", "staggered", nc, LO, HI, diff=diff, dtype=dtype, ncomp=ncomp)
+    dev = lambda x: torch.as_tensor(x, dtype=dtype, device="cuda")
+    gp = ([dev(gpsi[c]) for c in range(3)] if ncomp == 3 else [dev(gpsi)]) if with_psi else None
+    out = s.adjoint(gp, [dev(g) for g in gder])
+    torch.cuda.synchronize()
+    got = np.stack([o.double().cpu().numpy() for o in out]) if ncomp == 3 else out[0].double().cpu().numpy()
+    hs = [(HI[a] - LO[a]) / nc[a] for a in range(3)]
+    ref = ub.adjoint_unbounded(gpsi if with_psi else None, gder, hs, 2.0 * max(hs), diff)
+    s.close()
+    check(got, ref, prec, "adjoint")
+
+
 @pytest.mark.parametrize("generic", [False, True])
 def test_unbounded_generic_matches_fast(generic, monkeypatch):
     """The same power-of-two problem through the general passes and the wavefront kernels."""

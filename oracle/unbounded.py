@@ -39,14 +39,30 @@ polynomials,
 At r = 0 the limits are G_2m(0) = -(1 / ((2 pi)^(3/2) sigma)) sum_{j<m} C(2j, j) / 4^j
 and G_spectral(0) = -k_c / (2 pi^2).  The closed forms are checked against the
 spectral integrals by quadrature in the tests.
+
+Lower dimensions (Section 2.5.2: spectral kernels in 1D, 2D and 3D, Gaussian
+kernels of orders 2-10 in 2D and 3D), read through the same spectra; the
+additive constant of each is fixed so that G approaches the unregularised
+fundamental solution ((1 / 2 pi) ln r in 2D, |x| / 2 in 1D) at large r:
+  2D, order 2m: G = (1 / 2 pi) [ln r + E1(rho^2 / 2) / 2
+                 - sum_{j=1}^{m-1} exp(-rho^2 / 2) L_{j-1}(rho^2 / 2) / (2 j)]
+     (L_n Laguerre polynomials; each j term from int_0^inf exp(-u^2/2)
+      u^(2j-1) J0(u rho) du = 2^(j-1) (j-1)! exp(-rho^2/2) L_{j-1}(rho^2/2));
+  2D, spectral:  G = (1 / 2 pi) [F(k_c r) - ln(k_c / 2) - gamma],
+     F(x) = int_0^x (1 - J0(t)) / t dt;
+  1D, order 2:   G = (x / 2) erf(x / (sqrt2 sigma)) + sigma exp(-x^2 / (2 sigma^2)) / sqrt(2 pi);
+  1D, spectral:  G = (|x| Si(k_c |x|) + cos(k_c x) / k_c) / pi.
 """
+import functools
 import math
 
 import numpy as np
 from numpy.polynomial import hermite_e
-from scipy.special import erf, sici
+from scipy import integrate
+from scipy.special import erf, eval_laguerre, exp1, j0, sici
 
 SQRT2 = math.sqrt(2.0)
+EULER_GAMMA = 0.57721566490153286060651209008240243
 
 # Green's kernels of the free-space solve: name -> Gaussian order (0: spectral)
 KERNELS = {"g2": 2, "g4": 4, "g6": 6, "g8": 8, "g10": 10, "spectral": 0}
@@ -96,9 +112,67 @@ def green_spectral(r, h):
     return out
 
 
-def green(kernel, r, sigma, h):
-    """Kernel `kernel` of KERNELS at distances r (sigma: Gaussian width, h: cutoff spacing)."""
+def green_gauss_2d(r, sigma, order):
+    """2D Gaussian-regularised kernel of order 2m (reading above)."""
+    m = order // 2
+    r = np.asarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    zero = r == 0.0
+    t = 0.5 * (r[~zero] / sigma) ** 2
+    acc = np.log(r[~zero]) + 0.5 * exp1(t)
+    for j in range(1, m):
+        acc = acc - np.exp(-t) * eval_laguerre(j - 1, t) / (2.0 * j)
+    out[~zero] = acc / (2.0 * np.pi)
+    # r -> 0: ln r + E1(t)/2 -> (ln(2 sigma^2) - gamma) / 2, L_{j-1}(0) = 1
+    out[zero] = (0.5 * (math.log(2.0 * sigma * sigma) - EULER_GAMMA)
+                 - sum(1.0 / (2.0 * j) for j in range(1, m))) / (2.0 * np.pi)
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _one_minus_j0_integral(x):
+    """F(x) = int_0^x (1 - J0(t)) / t dt by adaptive quadrature."""
+    if x == 0.0:
+        return 0.0
+    pts = [j * math.pi for j in range(1, int(x / math.pi) + 1)][:500] or None
+    val, _ = integrate.quad(lambda t: (1.0 - j0(t)) / t if t > 0 else 0.0, 0.0, x, limit=2000,
+                            points=pts, epsabs=1e-15, epsrel=1e-14)
+    return val
+
+
+def green_spectral_2d(r, h):
+    """2D spectrally truncated kernel, cutoff k_c = pi / h (reading above)."""
+    kc = math.pi / h
+    r = np.asarray(r, dtype=np.float64)
+    F = np.vectorize(lambda x: _one_minus_j0_integral(float(x)))(kc * r)
+    return (F - math.log(0.5 * kc) - EULER_GAMMA) / (2.0 * np.pi)
+
+
+def green_g2_1d(x, sigma):
+    """1D Gaussian-regularised kernel (reading above)."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    return 0.5 * x * erf(x / (SQRT2 * sigma)) + sigma * np.exp(-0.5 * (x / sigma) ** 2) / math.sqrt(2.0 * np.pi)
+
+
+def green_spectral_1d(x, h):
+    """1D spectrally truncated kernel, cutoff k_c = pi / h (reading above)."""
+    kc = math.pi / h
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    return (x * sici(kc * x)[0] + np.cos(kc * x) / kc) / np.pi
+
+
+def green(kernel, r, sigma, h, dim=3):
+    """Kernel `kernel` of KERNELS in `dim` dimensions at distances r (sigma:
+    Gaussian width, h: cutoff spacing)."""
     order = KERNELS[kernel]
+    if dim == 2:
+        return green_spectral_2d(r, h) if order == 0 else green_gauss_2d(r, sigma, order)
+    if dim == 1:
+        if order == 0:
+            return green_spectral_1d(r, h)
+        if order == 2:
+            return green_g2_1d(r, sigma)
+        raise NotImplementedError("1D free space: kernels g2 and spectral")
     if order == 0:
         return green_spectral(r, h)
     if order == 2:
@@ -113,13 +187,15 @@ def mirrored_distance(n, h):
 
 
 def green_extended(shape, hs, sigma, kernel="g2"):
-    """G_ext on the doubled grid of the given physical shape (3D)."""
-    if len(shape) != 3:
-        raise NotImplementedError("the free-space kernels are 3D kernels")
-    dx = mirrored_distance(shape[0], hs[0])[:, None, None]
-    dy = mirrored_distance(shape[1], hs[1])[None, :, None]
-    dz = mirrored_distance(shape[2], hs[2])[None, None, :]
-    return green(kernel, np.sqrt(dx * dx + dy * dy + dz * dz), sigma, max(hs))
+    """G_ext on the doubled grid of the given physical shape (1D, 2D or 3D)."""
+    nd = len(shape)
+    r2 = 0.0
+    for a in range(nd):
+        view = [1] * nd
+        view[a] = 2 * shape[a]
+        d = mirrored_distance(shape[a], hs[a]).reshape(view)
+        r2 = r2 + d * d
+    return green(kernel, np.sqrt(r2), sigma, max(hs), nd)
 
 
 def green_spectrum(shape, hs, sigma, kernel="g2"):
@@ -164,7 +240,7 @@ def _back(spec, shape):
 def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
     """Free-space solve of lap(psi) = f for a scalar or a 3-component field.
 
-    f has shape (n_x, n_y, n_z) or (3, n_x, n_y, n_z).  Returns
+    f has shape (n_x,), (n_x, n_y), (n_x, n_y, n_z) or (3, n_x, n_y, n_z).  Returns
     (psi, derivs): psi like f; derivs is [] for diff="none", the gradient
     components of a scalar psi for "grad", the curl of a 3-component psi for
     "curl", its divergence for "div" and the Laplacian of every component for
@@ -183,7 +259,7 @@ def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
     if diff == "grad":
         if vector:
             raise ValueError("grad is defined here for a scalar field")
-        derivs = [_back(1j * ks[a] * psihat[0], shape) for a in range(3)]
+        derivs = [_back(1j * ks[a] * psihat[0], shape) for a in range(len(shape))]
     elif diff == "curl":
         if not vector:
             raise ValueError("curl needs a 3-component field")
@@ -200,7 +276,7 @@ def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
         derivs = [_back(sum(1j * ks[a] * psihat[a] for a in range(3)), shape)]
     elif diff == "nabla":
         # sum over axes of the spectral first derivative applied twice
-        derivs = [_back(sum((1j * ks[a]) ** 2 for a in range(3)) * p, shape) for p in psihat]
+        derivs = [_back(sum((1j * ks[a]) ** 2 for a in range(len(shape))) * p, shape) for p in psihat]
     elif diff != "none":
         raise ValueError(diff)
     psi_out = np.stack(psi) if vector else psi[0]
@@ -242,7 +318,7 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
         acc[1] = acc[1] + 1j * (kz * gu[0] - kx * gu[2])
         acc[2] = acc[2] + 1j * (kx * gu[1] - ky * gu[0])
     elif diff == "grad":
-        for a in range(3):
+        for a in range(len(shape)):
             acc[0] = acc[0] - 1j * ks[a] * np.fft.rfftn(_pad(derivs[a]))
     elif diff == "div":
         # the divergence's transpose is minus the gradient
@@ -251,7 +327,7 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
             acc[c] = acc[c] - 1j * ks[c] * gd
     elif diff == "nabla":
         # the Laplacian (a real even multiplier) is its own transpose
-        lap = sum((1j * ks[a]) ** 2 for a in range(3))
+        lap = sum((1j * ks[a]) ** 2 for a in range(len(shape)))
         for c in range(ncomp):
             acc[c] = acc[c] + lap * np.fft.rfftn(_pad(derivs[c]))
     elif diff != "none":
@@ -270,11 +346,13 @@ def psi_at(points, f, hs, sigma, kernel="g2"):
     f = np.asarray(f, dtype=np.float64)
     shape = f.shape
     vol = float(np.prod(hs))
+    nd = f.ndim
     out = []
     for p in points:
-        dx = np.abs(np.arange(shape[0]) - p[0]) * hs[0]
-        dy = np.abs(np.arange(shape[1]) - p[1]) * hs[1]
-        dz = np.abs(np.arange(shape[2]) - p[2]) * hs[2]
-        r = np.sqrt(dx[:, None, None] ** 2 + dy[None, :, None] ** 2 + dz[None, None, :] ** 2)
-        out.append(vol * float(np.sum(green(kernel, r, sigma, max(hs)) * f)))
+        r2 = 0.0
+        for a in range(nd):
+            view = [1] * nd
+            view[a] = shape[a]
+            r2 = r2 + ((np.arange(shape[a]) - p[a]) * hs[a]).reshape(view) ** 2
+        out.append(vol * float(np.sum(green(kernel, np.sqrt(r2), sigma, max(hs), nd) * f)))
     return np.array(out)

@@ -1,4 +1,5 @@
-"""Pins of the oracle's higher-order Gaussian and spectral free-space kernels.
+"""Pins of the oracle's higher-order Gaussian and spectral free-space kernels
+(3D, and the 2D / 1D kernels).
 
 Each kernel is defined by its spectrum G^(k) = -zeta^(k) / k^2 (the reading of
 Section 2.5.2 stated in oracle/unbounded.py).  The checks here do not reuse
@@ -140,4 +141,99 @@ def test_new_kernels_direct_sum(kernel):
     hs = [0.1, 0.13, 0.09]
     psi, _ = ub.solve_unbounded(f, hs, 0.2, kernel=kernel)
     pts = [(0, 0, 0), (5, 4, 6), (2, 3, 1), (4, 0, 5)]
+    assert np.allclose(ub.psi_at(pts, f, hs, 0.2, kernel=kernel), [psi[p] for p in pts], rtol=1e-13, atol=0)
+
+
+# ------------------------------------------------------------------ 1D and 2D
+from scipy.special import exp1, j0 as bessel_j0
+
+
+def radial_inverse_2d_diff(zh, r, r0, kmax):
+    """G(r) - G(r0) = -(1 / 2 pi) int_0^kmax zh(k) (J0(k r) - J0(k r0)) / k dk."""
+    pts = sorted(set([j * math.pi / r for j in range(1, int(kmax * r / math.pi) + 1)][:300]
+                     + [j * math.pi / r0 for j in range(1, int(kmax * r0 / math.pi) + 1)][:300])) or None
+    val, _ = integrate.quad(lambda k: zh(k) * (bessel_j0(k * r) - bessel_j0(k * r0)) / k if k > 0 else 0.0,
+                            0.0, kmax, limit=4000, points=pts, epsabs=1e-15, epsrel=1e-13)
+    return -val / (2 * math.pi)
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_gauss_2d_kernel_is_its_spectral_integral(order):
+    sigma = 0.1
+    r0 = 0.5 * sigma
+    g0 = ub.green(f"g{order}", np.array([r0]), sigma, 1.0, dim=2)[0]
+    for r in np.array([0.0, 0.05, 1.0, 2.5, 6.0]) * sigma:
+        g = ub.green(f"g{order}", np.array([r]), sigma, 1.0, dim=2)[0]
+        ref = radial_inverse_2d_diff(lambda k: zeta_hat(k, sigma, order), r, r0, 40.0 / sigma)
+        assert abs((g - g0) - ref) <= 1e-10 * max(abs(ref), 1e-3), (order, r, g - g0, ref)
+    far = np.array([40.0, 80.0]) * sigma
+    assert np.allclose(ub.green(f"g{order}", far, sigma, 1.0, dim=2), np.log(far) / (2 * np.pi),
+                       rtol=1e-13, atol=0)
+
+
+def test_spectral_2d_kernel_is_its_spectral_integral():
+    h = 0.05
+    kc = math.pi / h
+    r0 = 0.7 * h
+    g0 = ub.green("spectral", np.array([r0]), 0.1, h, dim=2)[0]
+    for r in np.array([0.0, 0.3, 1.0, 4.0, 11.0]) * h:
+        g = ub.green("spectral", np.array([r]), 0.1, h, dim=2)[0]
+        ref = radial_inverse_2d_diff(lambda k: 1.0, r, r0, kc)
+        assert abs((g - g0) - ref) <= 1e-10 * max(abs(ref), 1e-3), (r, g - g0, ref)
+    # large r: the unregularised (1 / 2 pi) ln r, up to an O(1 / (k_c r)^(3/2)) oscillation
+    far = np.array([3000.0, 7000.0]) * h
+    assert np.allclose(ub.green("spectral", far, 0.1, h, dim=2), np.log(far) / (2 * np.pi), rtol=0,
+                       atol=2e-4)
+
+
+@pytest.mark.parametrize("kernel", ["g2", "spectral"])
+def test_1d_kernels_are_their_spectral_integrals(kernel):
+    sigma, h = 0.1, 0.05
+    kc = math.pi / h
+    zh = (lambda k: math.exp(-0.5 * (k * sigma) ** 2)) if kernel == "g2" else (lambda k: 1.0)
+    kmax = 40.0 / sigma if kernel == "g2" else kc
+    g0 = ub.green(kernel, np.array([0.0]), sigma, h, dim=1)[0]
+    for x in [0.02, 0.1, 0.37, 1.3]:
+        g = ub.green(kernel, np.array([x]), sigma, h, dim=1)[0]
+        # G(x) - G(0) = -(1 / pi) int zh(k) (cos(k x) - 1) / k^2 dk
+        pts = [j * math.pi / x for j in range(1, int(kmax * x / math.pi) + 1)][:300] or None
+        val, _ = integrate.quad(lambda k: zh(k) * (math.cos(k * x) - 1) / (k * k) if k > 0 else -0.5 * x * x,
+                                0.0, kmax, limit=2000, points=pts, epsabs=1e-15, epsrel=1e-13)
+        ref = -val / math.pi  # (the spectral kernel's spectrum stops at k_c)
+        assert abs((g - g0) - ref) <= 1e-10 * abs(ref), (kernel, x, g - g0, ref)
+    assert np.allclose(ub.green(kernel, np.array([50.0, 80.0]), sigma, h, dim=1), [25.0, 40.0], rtol=0,
+                       atol=1e-3)
+
+
+@pytest.mark.parametrize("kernel", ["g2", "g4", "g6", "spectral"])
+def test_2d_blob_solve(kernel):
+    n = 64
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    c, A, s = (0.5, 0.47), 1.2, 0.06
+    r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2)
+    f = A * np.exp(-r * r / (2 * s * s))
+    sigma = 2 * h
+    psi, _ = ub.solve_unbounded(f, [h, h], sigma, kernel=kernel)
+    Q = A * 2 * np.pi * s * s
+    S = s if kernel == "spectral" else math.sqrt(s * s + sigma * sigma)
+    t = 0.5 * (r / S) ** 2
+    ref = np.log(r) + 0.5 * exp1(t)
+    if kernel != "spectral":
+        from scipy.special import eval_laguerre
+        for j in range(1, int(kernel[1:]) // 2):
+            ref = ref - (sigma / S) ** (2 * j) * np.exp(-t) * eval_laguerre(j - 1, t) / (2 * j)
+    ref = Q * ref / (2 * np.pi)
+    assert np.max(np.abs(psi - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("kernel,dim", [("g4", 2), ("spectral", 2), ("g2", 1), ("spectral", 1)])
+def test_low_dim_direct_sum(kernel, dim):
+    rng = np.random.default_rng(22)
+    shape = (7, 5)[:dim] if dim == 2 else (9,)
+    f = rng.normal(size=shape)
+    hs = [0.1, 0.13][:dim]
+    psi, _ = ub.solve_unbounded(f, hs, 0.2, kernel=kernel)
+    pts = [(0, 0), (6, 4), (3, 2)] if dim == 2 else [(0,), (8,), (4,)]
     assert np.allclose(ub.psi_at(pts, f, hs, 0.2, kernel=kernel), [psi[p] for p in pts], rtol=1e-13, atol=0)

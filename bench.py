@@ -166,6 +166,32 @@ def other_workloads(steps, warmup):
         kern[kname] = {"plan_ms": plan_ms, "solve_ms": solve_ms, "blob_rel_max_err_64": errs[0],
                        "blob_rel_max_err_128": errs[1], "observed_order": float(np.log2(errs[0] / errs[1]))}
     res["unbounded256_kernels"] = kern
+    # 2D free space: FP64 error against the exact potential of a Gaussian blob at
+    # 128^2 and 256^2 per kernel, and the FP32 solve time with the gradient at 2048^2
+    from scipy.special import exp1
+    k2d = {}
+    for kname in ("g2", "g4", "g6", "g8", "g10", "spectral"):
+        errs = []
+        for n in (128, 256):
+            h = 1.0 / n
+            x = (np.arange(n) + 0.5) * h
+            c, A, sb = (0.5, 0.47), 1.0, 0.06
+            r = np.sqrt((x[:, None] - c[0]) ** 2 + (x[None, :] - c[1]) ** 2)
+            fb = A * np.exp(-r * r / (2 * sb * sb))
+            exact = A * sb * sb * (np.log(r) + 0.5 * exp1(0.5 * (r / sb) ** 2))
+            s2 = Solver("unbounded", "staggered", [n, n], kernel=kname, dtype=torch.float64)
+            psi, _ = s2.solve(torch.as_tensor(fb, device="cuda"))
+            torch.cuda.synchronize()
+            errs.append(float(np.max(np.abs(psi[0].cpu().numpy() - exact)) / np.max(np.abs(exact))))
+            s2.close()
+        k2d[kname] = {"blob_rel_max_err_128": errs[0], "blob_rel_max_err_256": errs[1],
+                      "observed_order": float(np.log2(errs[0] / errs[1]))}
+    s2 = Solver("unbounded", "staggered", [2048, 2048], kernel="g2", diff="grad", dtype=torch.float32)
+    s2.bind(torch.randn(2048, 2048, device="cuda"))
+    ms = _time(s2.run, max(5, steps // 4), warmup, s2.stream)
+    res["unbounded2d"] = {"kernels": k2d, "grad_2048_fp32_ms": ms,
+                          "grad_2048_fp32_model_gbs": s2.model_bytes() / (ms * 1e-3) / 1e9}
+    s2.close()
     # Section 2.3.3's DIV (vector -> scalar) and NABLA on psi at 256^3, FP32 (general passes)
     for dname, nc_ in (("div", 3), ("nabla", 1)):
         s = Solver("unbounded", "staggered", [256] * 3, diff=dname, dtype=torch.float32, ncomp=nc_)

@@ -172,8 +172,8 @@ hp_status validate(const hp_desc* d) {
     return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
   if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN))
     return fail(nullptr, HP_E_UNSUPPORTED, "spectral derivatives on Dirichlet/Neumann grids");
-  if (unb && d->ndim != 3)
-    return fail(nullptr, HP_E_UNSUPPORTED, "unbounded solves are 3D (G2 is the 3D kernel)");
+  if (unb && d->ndim == 1 && d->kernel != HP_G_GAUSS2 && d->kernel != HP_G_SPECTRAL)
+    return fail(nullptr, HP_E_UNSUPPORTED, "1D free space takes the G2 or the spectral kernel");
   // transform lengths must be 2^a 3^b 5^c
   for (int a = 0; a < d->ndim; ++a) {
     const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);
@@ -354,9 +354,11 @@ void gauss_legendre8(double* x, double* w) {
   }
 }
 
-// Si(j step), j < n: the integral of sin(t) / t accumulated interval by
+// int_0^(j step) g(t) dt, j < n, for a smooth g: accumulated interval by
 // interval (four 8-point Gauss-Legendre panels per interval, compensated sum).
-std::vector<double> sine_integral_table(int n, double step, const double* gx, const double* gw) {
+// g(t) = sin(t) / t gives Si; g(t) = (1 - J0(t)) / t the 2D spectral kernel's F.
+template <class G>
+std::vector<double> integral_table(int n, double step, const double* gx, const double* gw, G g) {
   std::vector<double> tab(n, 0.0);
   double sum = 0.0, comp = 0.0;
   for (int j = 1; j < n; ++j) {
@@ -365,8 +367,7 @@ std::vector<double> sine_integral_table(int n, double step, const double* gx, co
       const double mid = 0.5 * (a + b), half = 0.5 * (b - a);
       double acc = 0.0;
       for (int i = 0; i < 8; ++i) {
-        const double t = mid + half * gx[i];
-        acc += gw[i] * std::sin(t) / t;
+        acc += gw[i] * g(mid + half * gx[i]);
       }
       const double y = half * acc - comp;
       const double t2 = sum + y;
@@ -381,7 +382,9 @@ std::vector<double> sine_integral_table(int n, double step, const double* gx, co
 hp_status green_spectrum(hp_plan p, Problem& P) {
   const int M[3] = {P.M[0], P.M[1], P.M[2]};
   const int K2 = M[2] / 2 + 1;
-  const double hmax = std::max(P.h[0], std::max(P.h[1], P.h[2]));
+  // (axes beyond the problem's dimension are unit placeholders)
+  double hmax = 0.0;
+  for (int a = 0; a < P.nd; ++a) hmax = std::max(hmax, P.h[a]);
   const double sigma = (P.d.reg_sigma_cells > 0 ? P.d.reg_sigma_cells : 2.0) * hmax;
   const size_t nreal = (size_t)M[0] * M[1] * M[2];
   const size_t ncplx = (size_t)M[0] * M[1] * K2;
@@ -395,17 +398,23 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
   hp_status st = HP_OK;
   GreenEval ge{};
   ge.kind = P.d.kernel == HP_G_SPECTRAL ? 0 : 2 * (P.d.kernel - HP_G_GAUSS2 + 1);
+  ge.dim = P.nd;
   ge.sigma = sigma;
   ge.kc = M_PI / hmax;
   gauss_legendre8(ge.gl_x, ge.gl_w);
   void* si_dev = nullptr;
   if (ge.kind == 0) {
-    // Si on a table of step 1/2 up to past k_c times the largest distance
+    // Si (1D, 3D) or F (2D) on a table of step 1/2 up to past k_c times the
+    // largest distance
     double rmax2 = 0.0;
     for (int a = 0; a < 3; ++a) rmax2 += std::pow(0.5 * M[a] * P.h[a], 2);
     ge.si_step = 0.5;
     ge.si_n = (int)std::ceil(ge.kc * std::sqrt(rmax2) / ge.si_step) + 2;
-    const std::vector<double> tab = sine_integral_table(ge.si_n, ge.si_step, ge.gl_x, ge.gl_w);
+    const std::vector<double> tab =
+        ge.dim == 2 ? integral_table(ge.si_n, ge.si_step, ge.gl_x, ge.gl_w,
+                                     [](double t) { return (1.0 - ::j0(t)) / t; })
+                    : integral_table(ge.si_n, ge.si_step, ge.gl_x, ge.gl_w,
+                                     [](double t) { return std::sin(t) / t; });
     if (hipMalloc(&si_dev, tab.size() * 8) != hipSuccess ||
         hipMemcpy(si_dev, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipGetLastError();

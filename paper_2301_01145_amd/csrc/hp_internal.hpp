@@ -120,12 +120,15 @@ bool fast_tile_ok(int fast, int L, int P, int prec);
 
 // Launch one pass over `grid_y` independent field groups.
 hipError_t launch_pass(const PassArgs& a, int prec, int grid_y, hipStream_t s);
-// Free-space kernel of the plan (Section 2.5.2 readings): Gaussian order
-// `kind` = 2, 4, ..., 10 of width sigma, or `kind` = 0, the spectral cutoff
-// at kc with Si(j si_step) tabulated for j < si_n and an 8-point
-// Gauss-Legendre rule (nodes gl_x, weights gl_w on [-1, 1]) for the rest.
+// Free-space kernel of the plan (Section 2.5.2 readings) in `dim` = 1, 2 or
+// 3 dimensions: Gaussian order `kind` = 2, 4, ..., 10 of width sigma, or
+// `kind` = 0, the spectral cutoff at kc with its integral (Si in 1D / 3D,
+// F(x) = int_0^x (1 - J0(t)) / t dt in 2D) tabulated at j si_step, j < si_n,
+// and an 8-point Gauss-Legendre rule (nodes gl_x, weights gl_w on [-1, 1])
+// for the rest.
 struct GreenEval {
   int kind;
+  int dim;
   double sigma;
   double kc;
   const double* si;

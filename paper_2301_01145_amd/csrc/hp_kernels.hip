@@ -728,8 +728,87 @@ hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int ni
 }
 
 // ------------------------------------------------------ plan-time kernels
+// Tabulated integral of the spectral kernel at x >= 0: the nearest table node
+// plus the Gauss-Legendre integral of the integrand over the rest (<= step/2).
+template <class F>
+__device__ double table_integral(double x, const GreenEval& e, F g) {
+  int j = (int)(x / e.si_step + 0.5);
+  j = min(j, e.si_n - 1);
+  const double a = j * e.si_step;
+  const double mid = 0.5 * (x + a), half = 0.5 * (x - a);
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc += e.gl_w[q] * g(mid + half * e.gl_x[q]);
+  return e.si[j] + half * acc;
+}
+
+// ln(t) + E1(t), t >= 0 (the ln t singularities cancel): the power series
+// -gamma - sum_k (-t)^k / (k k!) for t <= 2, else ln t + E1(t) with E1 from its
+// continued fraction e^-t / (t + 1 - 1^2 / (t + 3 - 2^2 / (t + 5 - ...)))
+// evaluated by the modified Lentz method.
+__device__ double log_plus_e1(double t) {
+  const double euler = 0.57721566490153286060651209008240243;
+  if (t <= 2.0) {
+    double term = 1.0, sum = 0.0;
+    for (int k = 1; k <= 40; ++k) {
+      term *= -t / k;  // (-t)^k / k!
+      const double add = term / k;
+      sum += add;
+      if (fabs(add) < 1e-18 * fabs(sum)) break;
+    }
+    return -euler - sum;
+  }
+  const double tiny = 1e-300;
+  double b = t + 1.0, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i <= 200; ++i) {
+    const double an = -(double)i * i;
+    b += 2.0;
+    d = 1.0 / (an * d + b);
+    c = b + an / c;
+    const double del = c * d;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  return log(t) + h * exp(-t);
+}
+
+// G(r) of a 2D or 1D free-space kernel (the readings beside the 3D ones).
+__device__ double green_value_low(double r, const GreenEval& e) {
+  const double pi = M_PI;
+  if (e.dim == 2) {
+    if (e.kind == 0) {
+      const double euler = 0.57721566490153286060651209008240243;
+      const double F = r == 0.0 ? 0.0 : table_integral(e.kc * r, e, [](double t) { return (1.0 - j0(t)) / t; });
+      return (F - log(0.5 * e.kc) - euler) / (2.0 * pi);
+    }
+    // (1 / 2 pi) [ln sigma + (ln 2 + ln t + E1(t)) / 2 - e^-t sum_j L_{j-1}(t) / (2 j)], t = rho^2 / 2
+    const double t = 0.5 * (r / e.sigma) * (r / e.sigma);
+    double S = 0.0;
+    switch (e.kind) {  // sum_{j=1}^{m-1} L_{j-1}(t) / (2 j), expanded
+      case 4: S = 0.5; break;
+      case 6: S = 0.5 + (1.0 - t) / 4.0; break;
+      case 8: S = 0.5 + (1.0 - t) / 4.0 + ((0.5 * t - 2.0) * t + 1.0) / 6.0; break;
+      case 10:
+        S = 0.5 + (1.0 - t) / 4.0 + ((0.5 * t - 2.0) * t + 1.0) / 6.0 +
+            (((-t / 6.0 + 1.5) * t - 3.0) * t + 1.0) / 8.0;
+        break;
+      default: break;
+    }
+    return (log(e.sigma) + 0.5 * (M_LN2 + log_plus_e1(t)) - exp(-t) * S) / (2.0 * pi);
+  }
+  // 1D: G2 or the spectral cutoff
+  const double x = fabs(r);
+  if (e.kind == 0) {
+    const double si = x == 0.0 ? 0.0 : table_integral(e.kc * x, e, [](double t) { return sin(t) / t; });
+    return (x * si + cos(e.kc * x) / e.kc) / pi;
+  }
+  return 0.5 * x * erf(x / (M_SQRT2 * e.sigma)) +
+         e.sigma * exp(-0.5 * (x / e.sigma) * (x / e.sigma)) / sqrt(2.0 * pi);
+}
+
 // G(r) of the free-space kernel (GreenEval); see the kernel list in hipoisson.h.
 __device__ double green_value(double r, const GreenEval& e) {
+  if (e.dim != 3) return green_value_low(r, e);
   if (e.kind == 0) {
     // spectral cutoff: -Si(kc r) / (2 pi^2 r); Si from the nearest table node
     // plus the Gauss-Legendre integral of sin(t) / t over the remaining stretch

@@ -45,7 +45,8 @@ BAD = [
     (dict(bc="neumann", grid="staggered", nc=[8, 8, 8], diff="nabla"), _lib.HP_E_UNSUPPORTED),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="spectral"), _lib.HP_E_ARG),
-    (dict(bc="unbounded", grid="staggered", nc=[8, 8], kernel="g2"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="unbounded", grid="staggered", nc=[8], kernel="g6"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="unbounded", grid="staggered", nc=[8, 8], diff="curl"), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="g2"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="grad"), _lib.HP_E_UNSUPPORTED),

@@ -270,6 +270,56 @@ def test_div_nabla_adjoint(diff, ncomp, prec, with_psi):
     check(got, ref, prec, "adjoint")
 
 
+LOW_DIM = [(2, k) for k in ["g2", "g4", "g6", "g8", "g10", "spectral"]] + [(1, "g2"), (1, "spectral")]
+
+
+@pytest.mark.parametrize("nd,kernel", LOW_DIM)
+@pytest.mark.parametrize("diff", ["none", "grad", "nabla"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unbounded_low_dim(nd, kernel, diff, prec):
+    # 2D / 1D free space (run as 3D plans with unit, undoubled trailing axes)
+    for nc in ([[24, 20], [64, 48]] if nd == 2 else [[40], [256]]):
+        f, _ = case_input("unbounded", "staggered", nc, 1, False, prec, seed=43)
+        got, gd = gpu_solve("unbounded", "staggered", nc, LO[:nd], HI[:nd], f, kernel, diff, prec, 1, None)
+        ref, rd = oracle_solve("unbounded", "staggered", nc, LO[:nd], HI[:nd], f, kernel, diff, None)
+        check(got, ref, prec, f"psi {nc}")
+        assert len(gd) == len(rd)
+        for a in range(len(rd)):
+            if diff == "nabla" and prec == "f64":
+                # the Laplacian multiplies the spectrum by k^2 <= (pi / H)^2: the FP64
+                # rounding of the transform of the slowly decaying 1D / 2D kernel (set by
+                # its largest values) grows by up to (n / 128)^2 against the O(1) output
+                tol = 1e-12 * max(1.0, (max(nc) / 128.0) ** 2)
+                e2 = rel_l2(gd[a], rd[a])
+                assert e2 <= tol and rel_max(gd[a], rd[a]) <= 10 * tol, (nc, e2)
+            else:
+                check(gd[a], rd[a], prec, f"{diff} {a} {nc}")
+
+
+@pytest.mark.parametrize("nd", [1, 2])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unbounded_low_dim_adjoint(nd, prec):
+    import torch
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd import Solver
+    nc = [36, 20][:nd] if nd == 2 else [50]
+    rng = np.random.default_rng(44)
+    rnd = np.float32 if prec == "f32" else np.float64
+    gpsi = rng.normal(size=tuple(nc)).astype(rnd).astype(np.float64)
+    gder = [rng.normal(size=tuple(nc)).astype(rnd).astype(np.float64) for _ in range(nd)]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    kernel = "g4" if nd == 2 else "spectral"
+    s = Solver("unbounded", "staggered", nc, LO[:nd], HI[:nd], kernel=kernel, diff="grad", dtype=dtype)
+    dev = lambda x: torch.as_tensor(x, dtype=dtype, device="cuda")
+    out = s.adjoint([dev(gpsi)], [dev(g) for g in gder])
+    torch.cuda.synchronize()
+    got = out[0].double().cpu().numpy()
+    hs = [(HI[a] - LO[a]) / nc[a] for a in range(nd)]
+    ref = ub.adjoint_unbounded(gpsi, gder, hs, 2.0 * max(hs), "grad", kernel=kernel)
+    s.close()
+    check(got, ref, prec, "adjoint")
+
+
 @pytest.mark.parametrize("generic", [False, True])
 def test_unbounded_generic_matches_fast(generic, monkeypatch):
     """The same power-of-two problem through the general passes and the wavefront kernels."""

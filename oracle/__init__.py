@@ -33,7 +33,8 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
               ("g2", "g4", "g6", "g8", "g10", "spectral"; anything else: "g2")
     diff: "none" | "grad" | "curl" | "div" | "nabla" (Section 2.3.3's operators,
           applied to psi: gradient of a scalar, curl or divergence of a 3D
-          vector, Laplacian of every component)
+          vector, Laplacian of every component; in 2D the curl of a scalar
+          is (d_y psi, -d_x psi))
     faces: {(axis, side): g} boundary values (FD2 Dirichlet / Neumann)
     Returns (psi, derivs) on the output points.
     """
@@ -54,6 +55,12 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
         if bc != "periodic" or vector:
             raise NotImplementedError("bounded gradient: periodic scalar only")
         derivs = bounded.periodic_gradient(psi[0], lengths)
+    elif diff == "curl" and nd == 2 and not vector:
+        if bc != "periodic":
+            raise NotImplementedError("bounded curl: periodic only")
+        # 2D curl of a scalar (stream function): (d_y psi, -d_x psi)
+        g = bounded.periodic_gradient(psi[0], lengths)
+        derivs = [g[1], -g[0]]
     elif diff == "curl":
         if bc != "periodic" or not vector or nd != 3:
             raise NotImplementedError("bounded curl: periodic 3D vector only")

@@ -260,6 +260,9 @@ def solve_unbounded(f, hs, sigma, diff="none", kernel="g2"):
         if vector:
             raise ValueError("grad is defined here for a scalar field")
         derivs = [_back(1j * ks[a] * psihat[0], shape) for a in range(len(shape))]
+    elif diff == "curl" and len(shape) == 2 and not vector:
+        # 2D curl of a scalar (stream function): (d_y psi, -d_x psi)
+        derivs = [_back(1j * ks[1] * psihat[0], shape), _back(-1j * ks[0] * psihat[0], shape)]
     elif diff == "curl":
         if not vector:
             raise ValueError("curl needs a 3-component field")
@@ -300,8 +303,8 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
         vector = g_psi.ndim == 4
         shape = g_psi.shape[1:] if vector else g_psi.shape
     else:
-        vector = diff in ("curl", "div") or (diff == "nabla" and len(derivs) == 3)
         shape = derivs[0].shape
+        vector = (diff == "curl" and len(shape) == 3) or diff == "div" or (diff == "nabla" and len(derivs) == 3)
     ghat = green_spectrum(shape, hs, sigma, kernel)
     ks = wavenumbers(shape, hs)
     ncomp = 3 if vector else 1
@@ -311,7 +314,10 @@ def adjoint_unbounded(g_psi, g_derivs, hs, sigma, diff="none", kernel="g2"):
             acc.append(np.zeros(ghat.shape, dtype=np.complex128))
         else:
             acc.append(np.fft.rfftn(_pad(g_psi[c] if vector else g_psi)))
-    if diff == "curl":
+    if diff == "curl" and len(shape) == 2:
+        # transpose of (d_y, -d_x): -d_y g_0 + d_x g_1
+        acc[0] = acc[0] - 1j * ks[1] * np.fft.rfftn(_pad(derivs[0])) + 1j * ks[0] * np.fft.rfftn(_pad(derivs[1]))
+    elif diff == "curl":
         gu = [np.fft.rfftn(_pad(d)) for d in derivs]
         kx, ky, kz = ks
         acc[0] = acc[0] + 1j * (ky * gu[2] - kz * gu[1])

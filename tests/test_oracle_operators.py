@@ -111,3 +111,46 @@ def test_div_nabla_transposes(diff, vec):
     lhs2 = sum(np.sum(x * y) for x, y in zip(Ka_d, b_d))
     rhs2 = np.sum(a * ub.adjoint_unbounded(None, b_d, hs, 0.2, diff))
     assert abs(lhs2 - rhs2) <= 1e-11 * abs(lhs2)
+
+
+def test_unbounded_2d_curl_closed_form():
+    # spectral kernel: psi is the exact potential of the resolved blob
+    n = 64
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    c, A, s = (0.5, 0.47), 1.0, 0.06
+    r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2)
+    f = A * np.exp(-r * r / (2 * s * s))
+    _, (u0, u1) = ub.solve_unbounded(f, [h, h], 2 * h, "curl", kernel="spectral")
+    Q = A * 2 * np.pi * s * s
+    dpsi = Q * (1 - np.exp(-r * r / (2 * s * s))) / (2 * np.pi * r)  # d psi / d r
+    ref0, ref1 = dpsi * (Y - c[1]) / r, -dpsi * (X - c[0]) / r
+    scale = np.max(np.abs(ref0))
+    assert np.max(np.abs(u0 - ref0)) <= 1e-11 * scale and np.max(np.abs(u1 - ref1)) <= 1e-11 * scale
+
+
+def test_periodic_2d_curl_closed_form():
+    n, lo, hi = (12, 10), [0.0, 0.0], [1.0, 1.5]
+    L = [1.0, 1.5]
+    x = [(np.arange(n[a]) + 0.5) * L[a] / n[a] for a in range(2)]
+    X, Y = np.meshgrid(*x, indexing="ij")
+    kx, ky = 2 * np.pi * 2 / L[0], 2 * np.pi * 3 / L[1]
+    f = np.cos(kx * X + ky * Y + 0.3)
+    _, (u0, u1) = oracle.solve("periodic", "staggered", list(n), lo, hi, f, operator="ps", diff="curl")
+    k2 = kx * kx + ky * ky
+    # psi = -cos(th) / k2: d_y psi = ky sin(th) / k2, -d_x psi = -kx sin(th) / k2
+    th = kx * X + ky * Y + 0.3
+    assert np.max(np.abs(u0 - ky * np.sin(th) / k2)) <= 1e-13 and np.max(np.abs(u1 + kx * np.sin(th) / k2)) <= 1e-13
+
+
+def test_unbounded_2d_curl_transpose():
+    rng = np.random.default_rng(14)
+    shape, hs = (7, 9), [0.1, 0.12]
+    a = rng.normal(size=shape)
+    Ka_psi, Ka_d = ub.solve_unbounded(a, hs, 0.2, "curl")
+    b_psi = rng.normal(size=shape)
+    b_d = [rng.normal(size=shape) for _ in Ka_d]
+    lhs = np.sum(Ka_psi * b_psi) + sum(np.sum(x * y) for x, y in zip(Ka_d, b_d))
+    rhs = np.sum(a * ub.adjoint_unbounded(b_psi, b_d, hs, 0.2, "curl"))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)

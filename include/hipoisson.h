@@ -80,7 +80,9 @@ typedef enum {
 } hp_kernel;
 /* Spectral operator applied to psi after the convolution (Section 2.3.3's
  * list): GRAD of a scalar (ndim extra outputs), CURL of a 3D vector (3
- * outputs), DIV of a 3D vector (1 output), NABLA, the Laplacian of every
+ * outputs) or of a 2D scalar ((d_y psi, -d_x psi), 2 outputs, the form
+ * Section 4.3 treats as the gradient's 2D counterpart), DIV of a 3D vector
+ * (1 output), NABLA, the Laplacian of every
  * component (ncomp outputs).  Derivatives multiply by i k_a with the Nyquist
  * mode set to zero; NABLA is that first derivative applied twice per axis and
  * summed.  DIV and NABLA run on the general passes. */

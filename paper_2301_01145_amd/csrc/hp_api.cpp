@@ -164,8 +164,8 @@ hp_status validate(const hp_desc* d) {
     if (d->kernel != HP_OP_FD2)
       return fail(nullptr, HP_E_UNSUPPORTED, "inhomogeneous BCs need FD2 eigenvalues");
   }
-  if (d->diff == HP_D_CURL && (d->ncomp != 3 || d->ndim != 3))
-    return fail(nullptr, HP_E_ARG, "curl needs a 3-component 3D field");
+  if (d->diff == HP_D_CURL && !((d->ncomp == 3 && d->ndim == 3) || (d->ncomp == 1 && d->ndim == 2)))
+    return fail(nullptr, HP_E_ARG, "curl needs a 3-component 3D field or a 2D scalar");
   if (d->diff == HP_D_DIV && (d->ncomp != 3 || d->ndim != 3))
     return fail(nullptr, HP_E_ARG, "div needs a 3-component 3D field");
   if (d->diff == HP_D_GRAD && d->ncomp != 1)
@@ -513,7 +513,7 @@ hp_status setup_problem(hp_plan p, Problem& P) {
   P.nd = d.ndim;
   P.ncomp = d.ncomp;
   P.nder = d.diff == HP_D_GRAD    ? d.ndim
-           : d.diff == HP_D_CURL  ? 3
+           : d.diff == HP_D_CURL  ? (d.ndim == 2 ? 2 : 3)
            : d.diff == HP_D_DIV   ? 1
            : d.diff == HP_D_NABLA ? d.ncomp
                                   : 0;

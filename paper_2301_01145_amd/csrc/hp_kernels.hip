@@ -484,7 +484,11 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
         int k[3];
         spectral_index(a, m, t.p0 + f, t.o, k);
         const C2<T> g = W[e];
-        if (a.diff == D_ADJ_CURL) {
+        if (a.diff == D_ADJ_CURL && nS == 1) {
+          // 2D curl of a scalar, (d_y, -d_x): its transpose is -d_y g_0 + d_x g_1
+          const T kk = i == 0 ? -kval<T>(a, 1, k) : kval<T>(a, 0, k);
+          S[e] = cadd(S[e], cscale(cmuli(g), kk));
+        } else if (a.diff == D_ADJ_CURL) {
           // (C g)_c = i(k_{c+1} g_{c+2} - k_{c+2} g_{c+1}): g_i enters
           // component i+1 with +i k_{i+2} and component i+2 with -i k_{i+1}
           const int c1 = (i + 1) % 3, c2 = (i + 2) % 3;
@@ -536,6 +540,9 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
           v = cmuli(acc);
         } else if (a.diff == D_NABLA) {
           v = cscale(S[(size_t)d * tileC + e], lap_of(k));
+        } else if (a.n_in == 1) {
+          // 2D curl of a scalar: (d_y psi, -d_x psi)
+          v = cscale(cmuli(S[e]), d == 0 ? kval<T>(a, 1, k) : -kval<T>(a, 0, k));
         } else {
           const int c1 = (d + 1) % 3, c2 = (d + 2) % 3;
           v = cmuli(csub(cscale(S[(size_t)c2 * tileC + e], kval<T>(a, c1, k)),

@@ -37,7 +37,7 @@ def create_status(desc):
 BAD = [
     (dict(bc="dirichlet", grid="regular", nc=[8], kernel="ps", inhomogeneous=True), _lib.HP_E_UNSUPPORTED),
     (dict(bc="periodic", grid="regular", nc=[8], inhomogeneous=True, kernel="fd2"), _lib.HP_E_ARG),
-    (dict(bc="periodic", grid="regular", nc=[8, 8], diff="curl"), _lib.HP_E_ARG),
+    (dict(bc="periodic", grid="regular", nc=[8], diff="curl"), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=1), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="regular", nc=[8, 8, 8], diff="grad", ncomp=3), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="div", ncomp=1), _lib.HP_E_ARG),
@@ -46,7 +46,7 @@ BAD = [
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="spectral"), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8], kernel="g6"), _lib.HP_E_UNSUPPORTED),
-    (dict(bc="unbounded", grid="staggered", nc=[8, 8], diff="curl"), _lib.HP_E_ARG),
+    (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=1), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="g2"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="grad"), _lib.HP_E_UNSUPPORTED),

@@ -296,6 +296,42 @@ def test_unbounded_low_dim(nd, kernel, diff, prec):
                 check(gd[a], rd[a], prec, f"{diff} {a} {nc}")
 
 
+@pytest.mark.parametrize("bc,kernel", [("periodic", "ps"), ("periodic", "fd2"), ("unbounded", "g2"),
+                                       ("unbounded", "g6"), ("unbounded", "spectral")])
+@pytest.mark.parametrize("nc", [[24, 20], [64, 48]])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_curl_2d(bc, kernel, nc, prec):
+    # 2D curl of a scalar: (d_y psi, -d_x psi)
+    f, _ = case_input(bc, "staggered", nc, 1, False, prec, seed=47)
+    got, gd = gpu_solve(bc, "staggered", nc, LO[:2], HI[:2], f, kernel, "curl", prec, 1, None)
+    ref, rd = oracle_solve(bc, "staggered", nc, LO[:2], HI[:2], f, kernel, "curl", None)
+    check(got, ref, prec, "psi")
+    assert len(gd) == len(rd) == 2
+    for a in range(2):
+        check(gd[a], rd[a], prec, f"curl {a}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_curl_2d_adjoint(prec):
+    import torch
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd import Solver
+    nc = [30, 24]
+    rng = np.random.default_rng(48)
+    rnd = np.float32 if prec == "f32" else np.float64
+    gpsi = rng.normal(size=tuple(nc)).astype(rnd).astype(np.float64)
+    gder = [rng.normal(size=tuple(nc)).astype(rnd).astype(np.float64) for _ in range(2)]
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver("unbounded", "staggered", nc, LO[:2], HI[:2], kernel="g4", diff="curl", dtype=dtype)
+    dev = lambda x: torch.as_tensor(x, dtype=dtype, device="cuda")
+    out = s.adjoint([dev(gpsi)], [dev(g) for g in gder])
+    torch.cuda.synchronize()
+    hs = [(HI[a] - LO[a]) / nc[a] for a in range(2)]
+    ref = ub.adjoint_unbounded(gpsi, gder, hs, 2.0 * max(hs), "curl", kernel="g4")
+    s.close()
+    check(out[0].double().cpu().numpy(), ref, prec, "adjoint")
+
+
 @pytest.mark.parametrize("nd", [1, 2])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_unbounded_low_dim_adjoint(nd, prec):

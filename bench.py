@@ -288,6 +288,54 @@ def cpu_baseline(n_sample, n_full):
     }
 
 
+def cpu_fft_context(n, threads):
+    """Context beside the oracle baseline, in the role of the paper's CPU (FFTW)
+    runs: the same pruned-free doubled-domain curl solve (R2C of the padded
+    fields, Green's spectrum, curl, C2R) with scipy.fft on `threads` host
+    threads, FP64 and FP32.  Not the oracle; labelled context only."""
+    import numpy as np
+    import scipy.fft as sfft
+    from scipy.special import erf
+
+    from workloads import vortex_rings
+    h = 1.0 / n
+    M = 2 * n
+    sigma = 2 * h
+    m = np.minimum(np.arange(M), M - np.arange(M)) * h
+    out = {}
+    f64 = vortex_rings(n, seed=4, count=32).astype(np.float64)
+    for dt in (np.float64, np.float32):
+        f = f64.astype(dt)
+        t0 = time.perf_counter()
+        r = np.sqrt(m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            g = np.where(r > 0, -erf(r / (np.sqrt(2) * sigma)) / (4 * np.pi * np.where(r > 0, r, 1)),
+                         -1 / ((2 * np.pi) ** 1.5 * sigma))
+        ghat = (sfft.rfftn(g.astype(dt), workers=threads) * h ** 3).real.astype(dt)
+        del g, r
+        t1 = time.perf_counter()
+        k = 2 * np.pi * np.fft.fftfreq(M, d=h)
+        k[M // 2] = 0
+        kz = k[: M // 2 + 1].copy()
+        kz[-1] = 0
+        kx, ky, kzz = k[:, None, None].astype(dt), k[None, :, None].astype(dt), kz[None, None, :].astype(dt)
+        ps = []
+        for c in range(3):
+            big = np.zeros((M, M, M), dtype=dt)
+            big[:n, :n, :n] = f[c]
+            ps.append(sfft.rfftn(big, workers=threads) * ghat)
+        outs = [sfft.irfftn(p_, s=(M, M, M), workers=threads)[:n, :n, :n] for p_ in ps]
+        curl = [1j * (ky * ps[2] - kzz * ps[1]), 1j * (kzz * ps[0] - kx * ps[2]), 1j * (kx * ps[1] - ky * ps[0])]
+        outs += [sfft.irfftn(u, s=(M, M, M), workers=threads)[:n, :n, :n] for u in curl]
+        t2 = time.perf_counter()
+        out["fp64" if dt == np.float64 else "fp32"] = {"solve_s": t2 - t1, "green_setup_s": t1 - t0,
+                                                        "solves_per_s": 1.0 / (t2 - t1)}
+        del ps, outs, curl
+    out.update({"kind": "context: scipy.fft (pocketfft) unpruned doubled-domain solve, not the oracle",
+                "threads": threads, "grid": n})
+    return out
+
+
 def main():
     args = parse()
     if args.copy_ref:
@@ -364,6 +412,8 @@ def main():
         out["other_workloads"] = other_workloads(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        out["cpu_fft_context"] = cpu_fft_context(n, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -91,6 +91,30 @@ def _time(fn, steps, warmup, stream):
     return a.elapsed_time(b) / steps
 
 
+def _time_graph(run, stream, steps, warmup):
+    """Mean ms of `steps` replays of one solve captured into a hipGraph on
+    `stream` (the plan's own stream, which must not be the default stream)."""
+    import torch
+    with torch.cuda.stream(stream):
+        run()  # settles uploads of bound pointers before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        run()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        for _ in range(steps):
+            g.replay()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
 def other_workloads(steps, warmup):
     """Secondary workloads: solves/s and model GB/s each (same timing method)."""
     import numpy as np
@@ -118,17 +142,24 @@ def other_workloads(steps, warmup):
     res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
                                        "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
     s.close()
-    # 64 batched Neumann problems, one persistent launch, FP32
+    # 64 batched Neumann problems: one persistent launch replayed from a captured
+    # hipGraph (the plan lives on a side stream so that it can be captured), FP32
     probs = neumann_batch(64, seed=5)
-    bs = BatchedSolver("neumann", "staggered", [{"nc": list(p["shape"])} for p in probs], kernel="ps")
-    bs.bind([torch.as_tensor(p["f"].astype(np.float32), device="cuda") for p in probs])
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        bs = BatchedSolver("neumann", "staggered", [{"nc": list(p["shape"])} for p in probs], kernel="ps")
+        bs.bind([torch.as_tensor(p["f"].astype(np.float32), device="cuda") for p in probs])
+    torch.cuda.synchronize()
     ms_default = _time(bs.run, steps, warmup, bs.stream)
     # plan-time autotuning (radix orders, tiles, work-item size), outside the timed region
-    ntuned, tiles = bs.autotune(reps=5)
-    ms = _time(bs.run, steps, warmup, bs.stream)
+    with torch.cuda.stream(side):
+        ntuned, tiles = bs.autotune(reps=5)
+    ms_eager = _time(bs.run, steps, warmup, bs.stream)
+    ms = _time_graph(bs.run, side, steps, warmup)
     res["neumann_batch64_fp32"] = {"batches_per_s": 1000 / ms, "problems_per_s": 64000 / ms, "ms": ms,
-                                   "ms_untuned": ms_default, "tuned_pass_signatures": ntuned,
-                                   "tiles_per_item": tiles,
+                                   "timing": "hipGraph replays of the one persistent launch",
+                                   "ms_eager": ms_eager, "ms_untuned_eager": ms_default,
+                                   "tuned_pass_signatures": ntuned, "tiles_per_item": tiles,
                                    "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
                                    "error_flag": bs.error_flag()}
     bs.close()
@@ -408,6 +439,16 @@ def main():
         out["fp64"] = {"value": 1000.0 / r64["ms"], "ms_per_step": r64["ms"],
                        "model_gbs": r64["model_bytes"] / (r64["ms"] * 1e-3) / 1e9}
         out["fp32_error_vs_fp64"] = {"rel_l2": (num / den) ** 0.5, "rel_max": mx / mref}
+    # the same FP32 solve replayed from a captured hipGraph (extra field; `value`
+    # stays the eager HIP-event time above)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = Solver("unbounded", "staggered", [n, n, n], diff="curl", dtype=torch.float32, ncomp=3,
+                   device=dev)
+        s.bind([torch.as_tensor(f32[c], device=dev).contiguous() for c in range(3)])
+    torch.cuda.synchronize()
+    out["graph_ms_per_step"] = _time_graph(s.run, side, args.steps, args.warmup)
+    s.close()
     if not args.no_others:
         out["other_workloads"] = other_workloads(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu:

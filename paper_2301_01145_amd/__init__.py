@@ -123,6 +123,11 @@ class Solver:
         for c, t in enumerate(derivs):
             self._check_tensor(t, self.out_shape, "deriv")
             hp_bind_gradient(self.plan, 0, c, t.data_ptr())
+        # the plan holds raw device pointers: keep every bound tensor alive for
+        # as long as the binding stands (a freed block can be returned to the
+        # driver, e.g. by torch.cuda.empty_cache, and a later solve would then
+        # touch unmapped memory)
+        self._keep = (comps, faces, psi, list(derivs))
         return psi, list(derivs)
 
     def run(self):
@@ -156,8 +161,8 @@ class Solver:
             if t is not None:
                 self._check_tensor(t, self.out_shape, "g_deriv")
             hp_bind_gradient(self.plan, 0, c, t.data_ptr() if t is not None else None)
+        self._keep = (grad_f, gp, gd)  # bound before the launch reads them
         hp_solve_adjoint(self.plan)
-        self._keep = (grad_f, g_psi, g_derivs)
         return grad_f
 
     def close(self):

@@ -6,7 +6,7 @@ bounded with boundary values)."""
 import numpy as np
 import pytest
 
-from gpu_util import case_input, to_dev
+from gpu_util import case_input, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -53,4 +53,43 @@ def test_graph_replay(bc, grid, nc, kernel, diff, ncomp, inhom, prec):
         for i, o in enumerate(outs):
             assert torch.equal(o, eager[i]), (rep, i)
         del junk
+    s.close()
+
+
+def test_bind_keeps_bound_tensors_alive():
+    """bind() hands raw device pointers to the plan, so the solver must keep the
+    bound tensors alive: temporaries passed to bind() and outputs the caller
+    drops stay valid across torch.cuda.empty_cache() (which graph capture
+    calls) and across graph replays."""
+    import torch
+    from gpu_util import oracle_solve
+    from paper_2301_01145_amd import Solver
+    nc = [32, 32, 64]
+    f, _ = case_input("unbounded", "staggered", nc, 3, False, "f32", seed=51)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = Solver("unbounded", "staggered", nc, LO, HI, kernel="g2", diff="curl", dtype=torch.float32,
+                   ncomp=3)
+        s.bind([to_dev(f[c], torch.float32, torch) for c in range(3)])  # temporaries, outputs dropped
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ref, rd = oracle_solve("unbounded", "staggered", nc, LO, HI, f, "g2", "curl", None)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        s.run()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        s.run()
+    psi, der = s._keep[2], s._keep[3]
+    for rep in range(2):
+        for o in psi + der:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = np.stack([p.double().cpu().numpy() for p in psi])
+        assert rel_l2(got, ref) <= 1e-5, rep
+        for a in range(3):
+            assert rel_l2(der[a].double().cpu().numpy(), rd[a]) <= 1e-5, (rep, a)
+    del g
     s.close()

@@ -287,6 +287,9 @@ def timed_solves(solver, steps, warmup):
     return ms, hp_pass_stats(solver.plan)
 
 
+_ORACLE_FIELDS = None  # (grid, [psi_x, psi_y, psi_z, u_x, u_y, u_z]) of the last oracle run
+
+
 def cpu_baseline(n_sample, n_full):
     """Time the FP64 oracle on the same workload recipe at a smaller grid."""
     import math
@@ -297,8 +300,10 @@ def cpu_baseline(n_sample, n_full):
     from workloads import vortex_rings
     f = vortex_rings(n_sample, seed=4, count=32).astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
-    oracle.solve("unbounded", "staggered", [n_sample] * 3, [0, 0, 0], [1, 1, 1], f, diff="curl")
+    psi, curl = oracle.solve("unbounded", "staggered", [n_sample] * 3, [0, 0, 0], [1, 1, 1], f, diff="curl")
     t = time.perf_counter() - t0
+    global _ORACLE_FIELDS
+    _ORACLE_FIELDS = (n_sample, [psi[c] for c in range(3)] + list(curl))
     # work of the dense FFT pipeline ~ M log M with M the doubled grid
     Ms, Mf = (2 * n_sample) ** 3, (2 * n_full) ** 3
     frac = (Ms * math.log2(Ms)) / (Mf * math.log2(Mf))
@@ -453,6 +458,25 @@ def main():
         out["other_workloads"] = other_workloads(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
+        # the GPU results against that FP64 oracle solve (same input, every element)
+        if _ORACLE_FIELDS is not None and _ORACLE_FIELDS[0] == n:
+            err = {}
+            ref = _ORACLE_FIELDS[1]
+            for prec, r in results.items():
+                num = den = 0.0
+                mx = mref = 0.0
+                per = []
+                for a, b in zip(r["fields"], ref):
+                    g = a.cpu().numpy()
+                    d2 = float(np.sum((g - b) ** 2))
+                    b2 = float(np.sum(b * b))
+                    num, den = num + d2, den + b2
+                    mx = max(mx, float(np.max(np.abs(g - b))))
+                    mref = max(mref, float(np.max(np.abs(b))))
+                    per.append((d2 / b2) ** 0.5)
+                err[prec] = {"rel_l2": (num / den) ** 0.5, "rel_max": mx / mref,
+                             "rel_l2_per_field": per}
+            out["error_vs_oracle"] = err
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
         out["cpu_fft_context"] = cpu_fft_context(n, threads)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,122 @@
+"""The oracle's pins catch plausible mistakes: each test plants one mistake in
+the oracle (on the CPU, through monkeypatch) and checks that a pin written
+against the paper or the mathematics now fails.  Together with the pins
+passing on the unmodified oracle, this shows the pins are not vacuous."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bounded, transforms
+from oracle import unbounded as ub
+
+import test_oracle_bounded as pb
+import test_oracle_kernels as pk
+import test_oracle_operators as po
+import test_oracle_transforms as pt
+import test_oracle_unbounded as pu
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_eigenvalue_index_shift_is_caught(monkeypatch):
+    # Table 1, FD2 Dirichlet regular, with k in place of k + 1
+    orig = bounded.eigenvalues
+
+    def wrong(bc, grid, operator, n, length, h):
+        lam = orig(bc, grid, operator, n, length, h)
+        if bc == "dirichlet" and grid == "regular" and operator == "fd2":
+            k = np.arange(n, dtype=np.float64)
+            lam = -4.0 / (h * h) * np.sin(np.pi * k / (2.0 * (n + 1))) ** 2
+        return lam
+
+    monkeypatch.setattr(bounded, "eigenvalues", wrong)
+    _fails(pb.test_fd2_matches_dense_solve, "dirichlet", "regular", 2, False)
+
+
+def test_boundary_weight_sign_is_caught(monkeypatch):
+    # Neumann staggered face terms with the sides swapped
+    orig = bounded.apply_boundary_values
+
+    def wrong(f, bc, grid, hs, faces):
+        if bc == "neumann" and grid == "staggered":
+            faces = {(a, 1 - s): g for (a, s), g in faces.items()}
+        return orig(f, bc, grid, hs, faces)
+
+    monkeypatch.setattr(bounded, "apply_boundary_values", wrong)
+    _fails(pb.test_fd2_matches_dense_solve, "neumann", "staggered", 2, True)
+
+
+def test_sine_transform_index_is_caught(monkeypatch):
+    # DST-II with (j + 1) in place of (2 j + 1) / 2
+    def wrong(n):
+        k = np.arange(n)[:, None]
+        j = np.arange(n)[None, :]
+        return 2.0 * np.sin(np.pi * (j + 1) * (k + 1) / n)
+
+    monkeypatch.setitem(transforms.MATRICES, "dst2", wrong)
+    _fails(pt.test_matrix_matches_library, "dst2", 8)
+
+
+def test_missing_cell_volume_is_caught(monkeypatch):
+    # the discrete convolution without the quadrature weight prod(H)
+    def wrong(shape, hs, sigma, kernel="g2"):
+        return np.fft.rfftn(ub.green_extended(shape, hs, sigma, kernel))
+
+    monkeypatch.setattr(ub, "green_spectrum", wrong)
+    _fails(pu.test_gaussian_closed_form, 32)
+
+
+def test_unmirrored_green_function_is_caught(monkeypatch):
+    # G laid out as G(m H) on the doubled grid instead of G(min(m, 2n - m) H)
+    monkeypatch.setattr(ub, "mirrored_distance", lambda n, h: np.arange(2 * n, dtype=np.float64) * float(h))
+    _fails(pu.test_doubling_equals_direct_sum)
+
+
+def test_wavenumber_sign_is_caught(monkeypatch):
+    # negative wavenumbers folded to positive ones (m in place of m - M)
+    orig = ub.wavenumbers
+
+    def wrong(shape, hs):
+        return [np.abs(k) for k in orig(shape, hs)]
+
+    monkeypatch.setattr(ub, "wavenumbers", wrong)
+    _fails(pu.test_gradient_and_curl_closed_form)
+
+
+def test_hermite_sign_is_caught(monkeypatch):
+    # order-4 kernel with the Hermite correction subtracted instead of added
+    def wrong(r, sigma, order):
+        r = np.asarray(r, dtype=np.float64)
+        rho = r / sigma
+        from scipy.special import erf
+        acc = erf(rho / math.sqrt(2)) - math.sqrt(2 / math.pi) * np.exp(-0.5 * rho * rho) * rho / 2
+        return -acc / (4 * np.pi * r)
+
+    monkeypatch.setattr(ub, "green_gauss", wrong)
+    _fails(pk.test_gauss_kernel_is_its_spectral_integral, 4)
+
+
+def test_spectral_cutoff_is_caught(monkeypatch):
+    # cutoff at the half-grid wavenumber pi / (2 H)
+    orig = ub.green_spectral
+    monkeypatch.setattr(ub, "green_spectral", lambda r, h: orig(r, 2 * h))
+    _fails(pk.test_spectral_kernel_is_its_spectral_integral)
+
+
+def test_laplacian_sign_is_caught(monkeypatch):
+    # NABLA with the sign of (i k)^2 dropped: negate the outer of the two
+    # first-derivative applications
+    orig = bounded.periodic_gradient
+    calls = {"n": 0}
+
+    def wrong(psi, lengths):
+        calls["n"] += 1
+        g = orig(psi, lengths)
+        return [-x for x in g] if calls["n"] % 2 == 0 else g
+
+    monkeypatch.setattr(bounded, "periodic_gradient", wrong)
+    _fails(po.test_periodic_nabla_returns_source)

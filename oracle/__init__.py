@@ -18,7 +18,31 @@ import numpy as np
 
 from . import bounded, grid, transforms, unbounded
 
-__all__ = ["bounded", "grid", "transforms", "unbounded", "solve"]
+__all__ = ["bounded", "grid", "transforms", "unbounded", "solve", "zero_mode"]
+
+
+def zero_mode(bc, grid_type, nc, lo, hi, f, faces=None):
+    """The part of the source that the k = 0 projection removes (Section 2.2,
+    the zero eigenvalue of periodic and Neumann problems): the k = 0
+    coefficient of the forward transform of the right-hand side (boundary
+    terms included, FD2) divided by the k = 0 coefficient of a field of ones.
+    Zero for Dirichlet and free-space problems, and for compatible sources."""
+    if bc not in ("periodic", "neumann"):
+        return 0.0
+    nd = len(nc)
+    hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
+    f = np.asarray(f, dtype=np.float64)
+    if faces:
+        f = bounded.apply_boundary_values(f, bc, grid_type, hs, faces)
+    one = np.ones_like(f)
+    if bc == "periodic":
+        return float(np.fft.fftn(f).flat[0].real / np.fft.fftn(one).flat[0].real)
+    fwd = bounded.TRANSFORM_PAIRS[(bc, grid_type)][0]
+    a_hat, o_hat = f, one
+    for a in range(nd):
+        a_hat = transforms.apply(fwd, a_hat, a)
+        o_hat = transforms.apply(fwd, o_hat, a)
+    return float(a_hat.flat[0] / o_hat.flat[0])
 
 
 def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",

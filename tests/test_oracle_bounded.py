@@ -28,8 +28,10 @@ CASES = [("dirichlet", "regular"), ("dirichlet", "staggered"),
 
 
 # --------------------------------------------------------------- dense FD model
-def dense_fd_solve(f, bc, gtype, hs, faces):
-    """Solve the FD2 equations directly on an extended grid (test-side model)."""
+def dense_fd_solve(f, bc, gtype, hs, faces, return_constant=False):
+    """Solve the FD2 equations directly on an extended grid (test-side model).
+    Periodic and Neumann systems carry one more unknown, the constant removed
+    from the source (returned as well with return_constant=True)."""
     shape = f.shape
     nd = len(shape)
     periodic = bc == "periodic"
@@ -119,15 +121,19 @@ def dense_fd_solve(f, bc, gtype, hs, faces):
                         if p[a] in (off, off + shape[a] - 1):
                             w *= 0.5
                 A[nvar, i] = w
-    sol = np.linalg.solve(A, b)[:nvar]
+    sol_all = np.linalg.solve(A, b)
+    sol = sol_all[:nvar]
+    const = float(sol_all[nvar]) if singular else 0.0
     full = np.zeros(ext)
     for p, i in idx.items():
         full[p] = sol[i]
     if bc == "dirichlet" and gtype == "regular":
-        return full
-    if periodic:
-        return full
-    return full[tuple(slice(1, 1 + n) for n in shape)]
+        out = full
+    elif periodic:
+        out = full
+    else:
+        out = full[tuple(slice(1, 1 + n) for n in shape)]
+    return (out, const) if return_constant else out
 
 
 def random_faces(bc, gtype, nc, nd, rng):
@@ -348,3 +354,34 @@ def test_ps_inhomogeneous_rejected():
     with pytest.raises(ValueError):
         oracle.solve("dirichlet", "regular", [4], [0], [1], np.zeros(3), operator="ps",
                      faces={(0, 0): np.array(1.0)})
+
+
+@pytest.mark.parametrize("bc,gtype", [("neumann", "regular"), ("neumann", "staggered"),
+                                      ("periodic", "staggered"), ("periodic", "regular")])
+@pytest.mark.parametrize("nd", [1, 2, 3])
+@pytest.mark.parametrize("inhom", [False, True])
+def test_zero_mode_is_the_removed_constant(bc, gtype, nd, inhom):
+    """oracle.zero_mode equals the constant c of the dense FD2 model
+    L_h psi + c = f (with the boundary values), the part of the source that no
+    solution can match."""
+    if inhom and bc == "periodic":
+        pytest.skip("periodic has no boundary values")
+    rng = np.random.default_rng(nd * 10 + inhom + 5)
+    nc = [7, 6, 5][:nd]
+    lo = [0.0, -0.5, 1.0][:nd]
+    hi = [1.0, 1.3, 2.5][:nd]
+    hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
+    shape = tuple(grid.unknowns(bc, gtype, nc[a]) for a in range(nd))
+    f = rng.normal(size=shape) + 0.7  # incompatible on purpose
+    faces = random_faces(bc, gtype, nc, nd, rng) if inhom else None
+    _, c = dense_fd_solve(f, bc, gtype, hs, faces or {}, return_constant=True)
+    got = oracle.zero_mode(bc, gtype, nc, lo, hi, f, faces)
+    assert abs(got - c) <= 1e-11 * max(1.0, abs(c)), (got, c)
+    # a compatible source (the constant removed) has no zero mode
+    assert abs(oracle.zero_mode(bc, gtype, nc, lo, hi, f - c, faces)) <= 1e-11 * max(1.0, abs(c))
+
+
+def test_zero_mode_zero_without_a_zero_eigenvalue():
+    f = np.ones((4, 5))
+    assert oracle.zero_mode("dirichlet", "staggered", [4, 5], [0, 0], [1, 1], f) == 0.0
+    assert oracle.zero_mode("unbounded", "staggered", [4, 5], [0, 0], [1, 1], f) == 0.0

@@ -116,7 +116,13 @@ enum {
   HP_Q_TUNE_DEFAULT_MS = 8, /* milliseconds of one solve with the planner's defaults,
                                measured by the last hp_autotune */
   HP_Q_TUNE_BEST_MS = 9,    /* the same with the configuration it kept */
-  HP_Q_BATCH_TILES = 10     /* batched plans: tiles per work item of the persistent kernel */
+  HP_Q_BATCH_TILES = 10,    /* batched plans: tiles per work item of the persistent kernel */
+  HP_Q_ZERO_MODE = 11       /* periodic / Neumann plans: the part of the bound source (with its
+                               FD2 boundary terms) that the k = 0 projection removes, i.e. the
+                               k = 0 coefficient of its forward transform over that of a field
+                               of ones (the weighted mean, DCT-I ends weighted 1/2); 0 for a
+                               compatible source and for other BCs; 3-component plans give
+                               the component of largest magnitude; synchronises */
 };
 
 /* Create a plan for one problem (the initialisation of Section 3.2.1): grid

@@ -90,6 +90,11 @@ class Solver:
     def model_bytes(self):
         return hp_query(self.plan, _lib.HP_Q_MODEL_BYTES)
 
+    def zero_mode(self):
+        """Part of the bound source that the k = 0 projection removes (periodic and
+        Neumann plans; 0 for a compatible source and for other BCs)."""
+        return hp_query(self.plan, _lib.HP_Q_ZERO_MODE)
+
     def autotune(self, reps=5):
         """Time the kernel configurations of this plan and keep the fastest
         (hp_autotune); returns (tuned pass signatures, solve ms with the defaults,

@@ -654,6 +654,33 @@ void strides_of(const int* dims, long long* s) {
   s[0] = (long long)dims[1] * dims[2];
 }
 
+// Boundary terms of component `comp` of an inhomogeneous FD2 problem
+// (Section 2.4.2 reading): face arrays, their strides over the remaining axes
+// (output layout) and the weights added to the unknowns next to each face.
+void fill_face_terms(const Problem& P, int comp, PassArgs& a) {
+  const hp_desc& d = P.d;
+  if (!d.inhomogeneous) return;
+  const int nd = P.nd;
+  a.face_off = (d.bc == HP_DIRICHLET && d.grid == HP_REGULAR) ? 1 : 0;
+  for (int ax = 0; ax < nd; ++ax) {
+    int rem[2], nr = 0;
+    for (int b = 0; b < nd; ++b)
+      if (b != ax) rem[nr++] = b;
+    a.face_s[ax][0] = a.face_s[ax][1] = 0;
+    if (nr == 2) { a.face_s[ax][1] = 1; a.face_s[ax][0] = P.nout[rem[1]]; }
+    else if (nr == 1) { a.face_s[ax][0] = 1; }
+    const double h = P.h[ax];
+    for (int side = 0; side < 2; ++side) {
+      a.face[ax][side] = P.face[ax][side][comp];
+      double w;
+      if (d.bc == HP_DIRICHLET) w = (d.grid == HP_REGULAR ? -1.0 : -2.0) / (h * h);
+      else if (d.grid == HP_REGULAR) w = (side == 0 ? 2.0 : -2.0) / h;
+      else w = (side == 0 ? 1.0 : -1.0) / h;
+      a.face_w[ax][side] = w;
+    }
+  }
+}
+
 // Sandwich coupling of the descriptor's operator (forward or transposed).
 int diff_kind(int dk, bool adjoint) {
   switch (dk) {
@@ -833,30 +860,8 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? P.n[b] : 0;
     return a;
   };
-  auto set_faces = [&](PassArgs& a, int comp) {
-    if (!d.inhomogeneous) return;
-    a.face_off = dreg ? 1 : 0;
-    for (int ax = 0; ax < nd; ++ax) {
-      // strides of the face array over the remaining axes (output layout)
-      int rem[2], nr = 0;
-      for (int b = 0; b < nd; ++b)
-        if (b != ax) rem[nr++] = b;
-      long long s1 = 1;
-      a.face_s[ax][0] = a.face_s[ax][1] = 0;
-      if (nr == 2) { a.face_s[ax][1] = 1; a.face_s[ax][0] = P.nout[rem[1]]; }
-      else if (nr == 1) { a.face_s[ax][0] = 1; }
-      (void)s1;
-      const double h = P.h[ax];
-      for (int side = 0; side < 2; ++side) {
-        a.face[ax][side] = P.face[ax][side][comp];
-        double w;
-        if (d.bc == HP_DIRICHLET) w = (d.grid == HP_REGULAR ? -1.0 : -2.0) / (h * h);
-        else if (d.grid == HP_REGULAR) w = (side == 0 ? 2.0 : -2.0) / h;
-        else w = (side == 0 ? 1.0 : -1.0) / h;
-        a.face_w[ax][side] = w;
-      }
-    }
-  };
+  auto set_faces = [&](PassArgs& a, int comp) { fill_face_terms(P, comp, a); };
+  (void)dreg;
   // one pass per component (faces differ per component)
   for (int comp = 0; comp < P.ncomp; ++comp) {
     if (nd == 1) {
@@ -1794,6 +1799,37 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
     case HP_Q_TUNE_BEST_MS:
       *value = plan->tune_best_ms;
       return HP_OK;
+    case HP_Q_ZERO_MODE: {
+      if (plan->batched) return fail(plan, HP_E_ARG, "zero mode: single-problem plans");
+      *value = 0.0;
+      if (P.d.bc != HP_PERIODIC && P.d.bc != HP_NEUMANN) return HP_OK;
+      const int nb = 256;
+      if (!plan->zm_partial) HP_TRY(dev_alloc(plan, nb * sizeof(double), (void**)&plan->zm_partial));
+      double best = 0.0;
+      for (int c = 0; c < P.ncomp; ++c) {
+        if (!P.in[c]) return fail(plan, HP_E_STATE, "input component " + std::to_string(c) + " not set");
+        PassArgs a{};
+        a.ax_j = 0; a.ax_p = 1; a.ax_o = 2;
+        for (int b = 0; b < 3; ++b) a.nunk[b] = b < P.nd ? P.n[b] : 0;
+        fill_face_terms(P, c, a);
+        int trap[3] = {0, 0, 0};
+        double W = 1.0;
+        for (int b = 0; b < P.nd; ++b) {
+          trap[b] = (P.d.bc == HP_NEUMANN && P.d.grid == HP_REGULAR) ? 1 : 0;
+          W *= trap[b] ? (double)(P.n[b] - 1) : (double)P.n[b];
+        }
+        HP_HIP(plan, launch_zero_mode(a, P.in[c], P.n, trap, plan->zm_partial, nb, plan->prec, plan->stream));
+        double part[nb];
+        HP_HIP(plan, hipMemcpyAsync(part, plan->zm_partial, sizeof part, hipMemcpyDeviceToHost, plan->stream));
+        HP_HIP(plan, hipStreamSynchronize(plan->stream));
+        double sum = 0.0;
+        for (int i = 0; i < nb; ++i) sum += part[i];
+        const double m = sum / W;
+        if (c == 0 || std::fabs(m) > std::fabs(best)) best = m;
+      }
+      *value = best;
+      return HP_OK;
+    }
     case HP_Q_BATCH_TILES:
       if (!plan->batched) return fail(plan, HP_E_ARG, "not a batched plan");
       *value = batch_tiles_of(plan);

@@ -159,6 +159,12 @@ struct BatchItem {
   int need;   // tile count of that pass
 };
 
+// Zero mode of a periodic / Neumann source: per-block partial sums (nb blocks,
+// FP64) of prod_a w_a(i_a) (f(i) + boundary terms of `a`) over the unknowns
+// n[0] x n[1] x n[2] (row-major), w_a = 1/2 at the two ends of an axis with
+// trap[a] set (DCT-I), else 1.
+hipError_t launch_zero_mode(const PassArgs& a, const void* f, const int n[3], const int trap[3],
+                            double* partial, int nb, int prec, hipStream_t s);
 // Persistent batched solve: counters[0] is the work-queue head, counters[1 + i]
 // the completed tiles of pass i (zeroed by the launch itself); err[0] is set
 // to 1 if a dependency wait exceeds its spin limit (the item is then skipped).

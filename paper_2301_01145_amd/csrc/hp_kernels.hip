@@ -871,6 +871,43 @@ hipError_t launch_green_eval(double* g, const int M[3], const double h[3], const
   return hipGetLastError();
 }
 
+// Weighted sum of the boundary-augmented source (zero-mode query): grid-stride
+// accumulation in FP64, one partial per block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_mode(const PassArgs a, const T* f, int n0, int n1,
+                                                   int n2, int t0, int t1, int t2, double* partial) {
+  __shared__ double red[256];
+  const long long total = (long long)n0 * n1 * n2;
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int i2 = (int)(i % n2), i1 = (int)((i / n2) % n1), i0 = (int)(i / ((long long)n1 * n2));
+    double w = 1.0;
+    if (t0 && (i0 == 0 || i0 == n0 - 1)) w *= 0.5;
+    if (t1 && (i1 == 0 || i1 == n1 - 1)) w *= 0.5;
+    if (t2 && (i2 == 0 || i2 == n2 - 1)) w *= 0.5;
+    acc += w * ((double)f[i] + face_terms<T>(a, i0, i1, i2));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_zero_mode(const PassArgs& a, const void* f, const int n[3], const int trap[3],
+                            double* partial, int nb, int prec, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_zero_mode<float>, dim3(nb), dim3(256), 0, s, a, (const float*)f, n[0], n[1],
+                       n[2], trap[0], trap[1], trap[2], partial);
+  else
+    hipLaunchKernelGGL(k_zero_mode<double>, dim3(nb), dim3(256), 0, s, a, (const double*)f, n[0],
+                       n[1], n[2], trap[0], trap[1], trap[2], partial);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void k_octant(const double* spec, int M0, int M1, int K2, double scale, T* out) {
   const int O0 = M0 / 2 + 1, O1 = M1 / 2 + 1;

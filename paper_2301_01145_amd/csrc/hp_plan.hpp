@@ -78,6 +78,7 @@ struct hp_plan_s {
   int batch_big = 0;  // register budget of the persistent kernel (PassArgs.big)
   std::vector<hp::PassRec> batch_passes;
   int batch_tiles = 0;  // tiles per work item (0: the default)
+  double* zm_partial = nullptr;  // per-block partial sums of the zero-mode query
   // autotuning (hp_autotune): chosen configurations by pass signature, the
   // number of signatures that left the default, and the summed per-pass
   // times of the default and chosen configurations measured while tuning

@@ -11,7 +11,7 @@ import itertools
 import numpy as np
 import pytest
 
-from gpu_util import TOL, case_input, gpu_solve, oracle_solve, rel_l2, rel_max
+from gpu_util import TOL, case_input, gpu_solve, oracle_solve, rel_l2, rel_max, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -354,6 +354,36 @@ def test_unbounded_low_dim_adjoint(nd, prec):
     ref = ub.adjoint_unbounded(gpsi, gder, hs, 2.0 * max(hs), "grad", kernel=kernel)
     s.close()
     check(got, ref, prec, "adjoint")
+
+
+@pytest.mark.parametrize("bc,grid,nc,inhom,ncomp", [
+    ("periodic", "staggered", [40], False, 1), ("periodic", "regular", [12, 20], False, 1),
+    ("periodic", "staggered", [16, 12, 10], False, 3), ("neumann", "regular", [30], True, 1),
+    ("neumann", "staggered", [24, 18], True, 1), ("neumann", "regular", [12, 10, 15], True, 1),
+    ("neumann", "staggered", [64, 32, 64], False, 1), ("dirichlet", "staggered", [8, 8], False, 1)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zero_mode_query(bc, grid, nc, inhom, ncomp, prec):
+    import torch
+    import oracle
+    from paper_2301_01145_amd import Solver
+    nd = len(nc)
+    f, faces = case_input(bc, grid, nc, ncomp, inhom, prec, seed=53)
+    f = f + 0.37  # incompatible source
+    rnd = np.float32 if prec == "f32" else np.float64
+    f = f.astype(rnd).astype(np.float64)
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    kernel = "fd2" if inhom else "ps"
+    s = Solver(bc, grid, nc, LO[:nd], HI[:nd], kernel=kernel, dtype=dtype, ncomp=ncomp, inhomogeneous=inhom,
+               diff="curl" if ncomp == 3 else "none")
+    fin = [to_dev(f[c], dtype, torch) for c in range(3)] if ncomp == 3 else to_dev(f, dtype, torch)
+    fd = {k: to_dev(v, dtype, torch) for k, v in faces.items()} if faces else None
+    s.bind(fin, fd)
+    got = s.zero_mode()
+    comps = [f[c] for c in range(3)] if ncomp == 3 else [f]
+    refs = [oracle.zero_mode(bc, grid, nc, LO[:nd], HI[:nd], c, faces) for c in comps]
+    ref = max(refs, key=abs)
+    assert abs(got - ref) <= 1e-12 * max(1.0, float(np.max(np.abs(f)))), (got, ref)
+    s.close()
 
 
 @pytest.mark.parametrize("generic", [False, True])

@@ -23,6 +23,11 @@ CASES = [
     ("periodic", "staggered", [64, 64, 128], "ps", "curl", 3, False),
     # wavefront bounded passes (fixed configuration: nothing to tune)
     ("dirichlet", "staggered", [64, 32, 64], "fd2", "none", 1, True),
+    # general passes of the operators and lower dimensions (unit placeholder axes)
+    ("unbounded", "staggered", [24, 20, 30], "g6", "div", 3, False),
+    ("periodic", "staggered", [36, 40, 30], "fd2", "nabla", 1, False),
+    ("unbounded", "staggered", [48, 60], "spectral", "curl", 1, False),
+    ("unbounded", "staggered", [90], "g2", "grad", 1, False),
 ]
 
 

@@ -18,6 +18,11 @@ CASES = [
     ("periodic", "staggered", [64, 64, 128], "ps", "grad", 1, False),
     ("dirichlet", "regular", [64, 32, 128], "fd2", "none", 1, True),
     ("neumann", "staggered", [32, 64, 64], "fd2", "none", 1, True),
+    # general passes: operators, kernels, lower dimensions
+    ("unbounded", "staggered", [24, 20, 30], "g4", "div", 3, False),
+    ("periodic", "staggered", [30, 24, 20], "ps", "nabla", 3, False),
+    ("unbounded", "staggered", [40, 36], "spectral", "curl", 1, False),
+    ("unbounded", "staggered", [120], "g2", "grad", 1, False),
 ]
 
 
@@ -31,7 +36,7 @@ def test_graph_replay(bc, grid, nc, kernel, diff, ncomp, inhom, prec):
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         # the plan records the stream that is current when it is created
-        s = Solver(bc, grid, nc, LO, HI, kernel=kernel, diff=diff, dtype=dtype, ncomp=ncomp,
+        s = Solver(bc, grid, nc, LO[:len(nc)], HI[:len(nc)], kernel=kernel, diff=diff, dtype=dtype, ncomp=ncomp,
                    inhomogeneous=inhom)
         fin = [to_dev(f[c], dtype, torch) for c in range(3)] if ncomp == 3 else to_dev(f, dtype, torch)
         fd = {k: to_dev(v, dtype, torch) for k, v in faces.items()} if faces else None

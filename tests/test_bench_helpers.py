@@ -1,0 +1,39 @@
+"""CPU checks of bench.py's bookkeeping: the HBM traffic it reports comes from
+the committed rocprofv3 summary only while that summary was measured on the
+current library sources (sha256 over csrc), and the JSON contract refuses more
+than one GPU."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_traffic_follows_the_source_digest(monkeypatch, tmp_path):
+    d = tmp_path / "profiles"
+    d.mkdir()
+    (d / "unbounded256_curl_fp32_hbm_counters.md").write_text(
+        "# x\n\n    source_sha256: %s\n    traffic_bytes: sandwich_x 100 23\n    traffic_bytes: inv_y 7 8\n"
+        % bench.kernel_source_digest())
+    monkeypatch.setattr(bench, "PROFILES", str(d))
+    assert bench.measured_traffic("sandwich_x", 256) == 123.0
+    assert bench.measured_traffic("inv_y", 256) == 15.0
+    assert bench.measured_traffic("c2r_z", 256) is None
+    assert bench.measured_traffic("sandwich_x", 128) is None  # no file for that size
+    (d / "unbounded256_curl_fp32_hbm_counters.md").write_text(
+        "    source_sha256: %s\n    traffic_bytes: sandwich_x 100 23\n" % ("0" * 64))
+    assert bench.measured_traffic("sandwich_x", 256) is None  # other sources
+
+
+def test_committed_profile_parses():
+    path = os.path.join(ROOT, "profiles", "unbounded256_curl_fp32_hbm_counters.md")
+    text = open(path).read()
+    assert "source_sha256:" in text and "traffic_bytes: sandwich_x" in text
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr

@@ -13,6 +13,7 @@ Prints one JSON line (rank 0).  Usage: python bench.py [--steps K] [--warmup W]
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -36,6 +37,22 @@ def kernel_source_digest():
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()
+
+
+# FP32 vector peak without packed math (the library is built with packed FP32
+# disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def sandwich_flops(n):
+    """Algorithmic flops of one launch of the x pass of the n^3 curl solve:
+    (M/2 + 1) M pencils of length M = 2n, each with 3 forward and 5 backward
+    complex FFTs at 5 M log2 M flops, the real Green's multiply of 3 spectra
+    (2 flops per element) and the two x derivatives (2 flops per element)."""
+    M = 2 * n
+    fft = 5.0 * M * math.log2(M)
+    per_pencil = 8 * fft + 3 * 2 * M + 2 * 2 * M
+    return (M // 2 + 1) * M * per_pencil
 
 
 def measured_traffic(pass_name, n):
@@ -431,7 +448,13 @@ def main():
         "model_bytes_per_solve": r32["model_bytes"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n),
-                     "kernel": name, "kernel_ms": pms, "kernel_bytes": pbytes},
+                     "kernel": name, "kernel_ms": pms, "kernel_bytes": pbytes,
+                     # the same pass against the vector ALU (it issues VALU instructions
+                     # about three quarters of its cycles; profiles/ SQ counters)
+                     "alu_view": ({"bound": "alu", "achieved": sandwich_flops(n) / (pms * 1e-3) / 1e12,
+                                   "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": sandwich_flops(n) / (pms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS,
+                                   "flops": sandwich_flops(n)} if name == "sandwich_x" else None)},
         "passes": [{"name": a, "ms": b, "model_gbs": c / (b * 1e-3) / 1e9 if b > 0 else None}
                    for a, b, c in r32["passes"]],
     })

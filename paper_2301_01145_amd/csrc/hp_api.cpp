@@ -1368,8 +1368,118 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
   return HP_OK;
 }
 
+// 1D / 2D free space (the problem lifted to 3D with unit trailing axes, whose
+// Green's table is the 1D / 2D kernel): the real transform runs along the
+// last physical axis, so the x pass works on the half spectrum only.
+//   2D: f [x][y] -R2C y (y < n1 of M1)-> B2 [ky][x] -sandwich x (Ghat,
+//       derivative)-> B2 -C2R y (keep y < n1)-> out [x][y]
+//   1D: one paired real sandwich along x (x < n0 of M0 in and out)
+hp_status passes_unbounded_low(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
+  const int n0 = P.n[0], n1 = P.n[1];
+  const int M0 = P.M[0], M1 = P.M[1];
+  const int nc = P.ncomp, nder = P.nder, nslot = nc + nder;
+  const void* src[kMaxFields] = {};
+  void* dst[kMaxFields] = {};
+  int n_src, n_dst;
+  if (!adjoint) {
+    n_src = nc;
+    n_dst = nslot;
+    for (int c = 0; c < nc; ++c) src[c] = P.in[c];
+    for (int f = 0; f < nslot; ++f) dst[f] = f < nc ? P.out[f] : P.der[f - nc];
+  } else {
+    n_src = nslot;
+    n_dst = nc;
+    for (int f = 0; f < nslot; ++f) src[f] = f < nc ? P.out[f] : P.der[f - nc];
+    for (int c = 0; c < nc; ++c) dst[c] = (void*)P.in[c];
+  }
+  auto sandwich_common = [&](PassArgs& a) {
+    a.kind = PK_SANDWICH;
+    a.mult = M_GREEN;
+    a.green = P.green;
+    for (int b = 0; b < 3; ++b) {
+      a.g_s[b] = P.g_s[b];
+      a.gM[b] = P.M[b];
+      a.kvec[b] = P.kvec[b];
+    }
+    a.diff = diff_kind(P.d.diff, adjoint);
+    const bool coupled = a.diff != D_NONE;
+    a.n_in = coupled ? n_src : 1;
+    a.n_out = coupled ? n_dst : 1;
+    return coupled;
+  };
+  if (P.nd == 1) {
+    PassArgs a{};
+    a.ax_j = 0; a.ax_p = a.ax_o = -1;
+    a.Np = a.No = 1;
+    const bool coupled = sandwich_common(a);
+    a.xf = X_PAIR_F; a.xb = X_PAIR_B;
+    a.L = M0; a.n = M0; a.nin = n0; a.nout = n0;
+    for (int f = 0; f < n_src; ++f) a.in[f] = src[f];
+    for (int f = 0; f < n_dst; ++f) a.out[f] = dst[f];
+    a.in_sj = a.out_sj = 1;
+    a.in_jfast = a.out_jfast = 1;
+    HP_TRY(finish_pass(p, a, 2, 2, 0, 5));
+    out.push_back({a, coupled ? 1 : nc});
+    return HP_OK;
+  }
+  const int K1 = M1 / 2 + 1;
+  // P1: R2C along y (pruned input y < n1), transposing to [ky][x]
+  {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.n_in = a.n_out = 1;
+    a.No = 1;
+    a.kind = PK_ONEWAY;
+    a.xf = X_R2C;
+    a.L = M1; a.n = M1; a.nin = n1; a.nout = K1;
+    for (int f = 0; f < n_src; ++f) { a.in[f] = src[f]; a.out[f] = P.b2[f]; }
+    a.in_sj = 1; a.in_sp = n1;
+    a.out_sj = n0; a.out_sp = 1;
+    a.Np = n0;
+    a.in_jfast = 1; a.out_jfast = 0;
+    HP_TRY(finish_pass(p, a, p->prec == 0 ? 32 : 16, 2, 0, 1));
+    out.push_back({a, n_src});
+  }
+  // P2: sandwich along x on the half spectrum ky < K1
+  {
+    PassArgs a{};
+    a.ax_j = 0; a.ax_p = 1; a.ax_o = 2;
+    a.No = 1;
+    const bool coupled = sandwich_common(a);
+    a.xf = X_C2C_F; a.xb = X_C2C_B;
+    a.L = M0; a.n = M0; a.nin = n0; a.nout = n0;
+    for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
+    for (int f = 0; f < n_dst; ++f) a.out[f] = P.b2[f];
+    a.in_sj = a.out_sj = 1;
+    a.in_sp = a.out_sp = n0;
+    a.Np = K1;
+    a.in_jfast = a.out_jfast = 1;
+    HP_TRY(finish_pass(p, a, 16, 1, 0, 4));
+    out.push_back({a, coupled ? 1 : nc});
+  }
+  // P3: C2R along y, keep y < n1, into the destination arrays [x][y]
+  {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.n_in = a.n_out = 1;
+    a.No = 1;
+    a.kind = PK_ONEWAY;
+    a.xf = X_C2R;
+    a.L = M1; a.n = M1; a.nin = K1; a.nout = n1;
+    for (int f = 0; f < n_dst; ++f) { a.in[f] = P.b2[f]; a.out[f] = dst[f]; }
+    a.in_sj = n0; a.in_sp = 1;
+    a.out_sj = 1; a.out_sp = n1;
+    a.Np = n0;
+    a.in_jfast = 0; a.out_jfast = 1;
+    HP_TRY(finish_pass(p, a, p->prec == 0 ? 32 : 16, 2, 0, 2));
+    out.push_back({a, n_dst});
+  }
+  return HP_OK;
+}
+
 hp_status build_passes(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
   if (P.d.bc == HP_UNBOUNDED) {
+    if (P.nd < 3) return passes_unbounded_low(p, P, adjoint, out);
     if (fast_unbounded_ok(p, P)) return passes_unbounded_fast(p, P, adjoint, out);
     return passes_unbounded(p, P, adjoint, out);
   }

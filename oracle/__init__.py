@@ -58,7 +58,8 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     diff: "none" | "grad" | "curl" | "div" | "nabla" (Section 2.3.3's operators,
           applied to psi: gradient of a scalar, curl or divergence of a 3D
           vector, Laplacian of every component; in 2D the curl of a scalar
-          is (d_y psi, -d_x psi))
+          is (d_y psi, -d_x psi)).  Dirichlet / Neumann take "grad" only,
+          with homogeneous boundary values (bounded.bounded_gradient)
     faces: {(axis, side): g} boundary values (FD2 Dirichlet / Neumann)
     Returns (psi, derivs) on the output points.
     """
@@ -75,9 +76,13 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     psi = [bounded.solve_bounded(c, bc, grid_type, operator, lengths, hs, faces if not vector else (faces[i] if faces else None))
            for i, c in enumerate(comps)]
     derivs = []
-    if diff == "grad":
-        if bc != "periodic" or vector:
-            raise NotImplementedError("bounded gradient: periodic scalar only")
+    if diff == "grad" and bc != "periodic":
+        if vector or faces:
+            raise NotImplementedError("Dirichlet / Neumann gradient: homogeneous scalar only")
+        derivs = bounded.bounded_gradient(psi[0], bc, grid_type, nc, lengths)
+    elif diff == "grad":
+        if vector:
+            raise NotImplementedError("periodic gradient: scalar only")
         derivs = bounded.periodic_gradient(psi[0], lengths)
     elif diff == "curl" and nd == 2 and not vector:
         if bc != "periodic":

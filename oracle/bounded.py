@@ -190,3 +190,46 @@ def periodic_gradient(psi, lengths):
         view[a] = n
         out.append(np.fft.ifftn(1j * k.reshape(view) * ph).real)
     return out
+
+
+def eigenfunctions(bc, n, length, x):
+    """The n eigenfunctions of Table 1 along one axis at positions x measured
+    from X_l, and their derivatives: sin(pi (k+1) x / L) for Dirichlet,
+    cos(pi k x / L) for Neumann, k = 0 .. n-1.  Returns (phi, dphi), each of
+    shape (len(x), n)."""
+    x = np.asarray(x, dtype=np.float64)[:, None]
+    k = np.arange(n, dtype=np.float64)[None, :]
+    if bc == "dirichlet":
+        w = np.pi * (k + 1.0) / float(length)
+        return np.sin(w * x), w * np.cos(w * x)
+    if bc == "neumann":
+        w = np.pi * k / float(length)
+        return np.cos(w * x), -w * np.sin(w * x)
+    raise ValueError(bc)
+
+
+def bounded_gradient(psi, bc, grid, nc, lengths):
+    """Spectral gradient of a Dirichlet / Neumann solution with homogeneous
+    boundary values.  Section 2.3.3 defines the spectral derivative for the
+    Fourier basis; for the sine / cosine bases of Table 1 it is read here as
+    the derivative of the eigenfunction series that passes through psi at the
+    unknown points (sine series -> cosine series and back), evaluated at the
+    output points.  Along axis a this is the matrix dphi(x_out) phi(x_unk)^-1
+    applied to every line of psi.  REGULAR Dirichlet output includes the
+    boundary nodes (the normal derivative there; 0 along the faces)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    nd = psi.ndim
+    out = []
+    for a in range(nd):
+        n = _grid.unknowns(bc, grid, nc[a])
+        x_out = _grid.positions(bc, grid, 0.0, lengths[a], nc[a])
+        dreg = bc == "dirichlet" and grid == "regular"
+        x_unk = x_out[1:-1] if dreg else x_out
+        phi, _ = eigenfunctions(bc, n, lengths[a], x_unk)
+        _, dphi = eigenfunctions(bc, n, lengths[a], x_out)
+        dmat = dphi @ np.linalg.inv(phi)
+        vals = np.moveaxis(psi, a, 0)
+        if dreg:
+            vals = vals[1:-1]
+        out.append(np.moveaxis(np.tensordot(dmat, vals, axes=1), 0, a))
+    return out

@@ -13,6 +13,9 @@ What pins what:
   * The quadratic of eq. (tfih1D) is reproduced exactly by FD2 for REGULAR
     Dirichlet and both Neumann grids (Section 4.2).
   * FD2 converges at O(H^2) (Fig. BS / Fig. IH claims).
+  * The Dirichlet / Neumann gradient of a product of eigenfunctions (PS and
+    FD2, one mode per axis, the top modes included) is the analytic
+    derivative of the closed-form psi, boundary nodes included.
 """
 import itertools
 
@@ -385,3 +388,83 @@ def test_zero_mode_zero_without_a_zero_eigenvalue():
     f = np.ones((4, 5))
     assert oracle.zero_mode("dirichlet", "staggered", [4, 5], [0, 0], [1, 1], f) == 0.0
     assert oracle.zero_mode("unbounded", "staggered", [4, 5], [0, 0], [1, 1], f) == 0.0
+
+
+# ------------------------------------------------------- bounded gradient
+def _mode(bc, m, length):
+    """Eigenfunction of mode m (sin(pi m x / L) or cos(pi m x / L)) and its
+    analytic derivative, as functions of x measured from X_l."""
+    w = np.pi * m / length
+    if bc == "dirichlet":
+        return (lambda x: np.sin(w * x)), (lambda x: w * np.cos(w * x)), w
+    return (lambda x: np.cos(w * x)), (lambda x: -w * np.sin(w * x)), w
+
+
+def _mode_product_case(bc, gtype, nc, lo, hi, modes, operator):
+    """Source = product of one eigenfunction per axis at the unknown points.
+    psi is the same product over the eigenvalue sum (PS: -w^2; FD2: the
+    three-point stencil applied to a sampled sinusoid, -(4/H^2) sin^2(w H/2)),
+    and d psi / d x_a replaces the factor of axis a by its derivative."""
+    nd = len(nc)
+    xs_out, xs_unk, fns = [], [], []
+    lam = 0.0
+    for a in range(nd):
+        length = hi[a] - lo[a]
+        h = length / nc[a]
+        x = grid.positions(bc, gtype, lo[a], hi[a], nc[a]) - lo[a]
+        xs_out.append(x)
+        xs_unk.append(x[1:-1] if (bc == "dirichlet" and gtype == "regular") else x)
+        g, dg, w = _mode(bc, modes[a], length)
+        fns.append((g, dg))
+        lam += -w * w if operator == "ps" else -(4.0 / h**2) * np.sin(w * h / 2) ** 2
+
+    def product(xs, deriv_axis=None):
+        out = np.ones([len(x) for x in xs])
+        for a in range(nd):
+            view = [1] * nd
+            view[a] = -1
+            fn = fns[a][1] if a == deriv_axis else fns[a][0]
+            out = out * fn(xs[a]).reshape(view)
+        return out
+
+    f = product(xs_unk)
+    psi_a = product(xs_out) / lam
+    grad_a = [product(xs_out, a) / lam for a in range(nd)]
+    return f, psi_a, grad_a
+
+
+@pytest.mark.parametrize("bc,gtype", CASES[:4])
+@pytest.mark.parametrize("nd", [1, 2, 3])
+@pytest.mark.parametrize("operator", ["ps", "fd2"])
+def test_bounded_gradient_of_eigenmodes(bc, gtype, nd, operator):
+    nc = [12, 10, 8][:nd]
+    lo = [0.0, 1.0, -2.0][:nd]
+    hi = [1.0, 3.0, 1.0][:nd]
+    f, psi_a, grad_a = _mode_product_case(bc, gtype, nc, lo, hi, [3, 2, 5][:nd], operator)
+    psi, grad = oracle.solve(bc, gtype, nc, lo, hi, f, operator=operator, diff="grad")
+    scale = max(np.max(np.abs(g)) for g in grad_a)
+    assert np.max(np.abs(psi - psi_a)) <= 1e-13 * np.max(np.abs(psi_a))
+    assert len(grad) == nd
+    for a in range(nd):
+        assert np.max(np.abs(grad[a] - grad_a[a])) <= 1e-12 * scale, a
+
+
+@pytest.mark.parametrize("bc,gtype,top", [("dirichlet", "regular", 9), ("dirichlet", "staggered", 10),
+                                          ("neumann", "regular", 10), ("neumann", "staggered", 9)])
+def test_bounded_gradient_top_mode(bc, gtype, top):
+    """The highest eigenfunction of each basis (10 cells): staggered sine and
+    regular cosine tops alternate in sign on the points, where their derivative
+    is exactly zero; the other two are ordinary modes."""
+    f, psi_a, grad_a = _mode_product_case(bc, gtype, [10], [0.0], [2.0], [top], "ps")
+    _, grad = oracle.solve(bc, gtype, [10], [0.0], [2.0], f, operator="ps", diff="grad")
+    scale = max(1.0, np.max(np.abs(grad_a[0])))
+    assert np.max(np.abs(grad[0] - grad_a[0])) <= 1e-12 * scale
+    if (bc, gtype) in (("dirichlet", "staggered"), ("neumann", "regular")):
+        assert np.max(np.abs(grad_a[0])) < 1e-12 * np.pi * top / 2.0
+
+
+def test_bounded_gradient_inhomogeneous_rejected():
+    f = np.zeros((6,))
+    with pytest.raises(NotImplementedError):
+        oracle.solve("dirichlet", "staggered", [6], [0.0], [1.0], f, operator="fd2", diff="grad",
+                     faces={(0, 0): np.array(1.0)})

@@ -120,3 +120,30 @@ def test_laplacian_sign_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "periodic_gradient", wrong)
     _fails(po.test_periodic_nabla_returns_source)
+
+
+def test_bounded_derivative_sign_is_caught(monkeypatch):
+    # Neumann: d/dx cos taken as +w sin
+    orig = bounded.eigenfunctions
+
+    def wrong(bc, n, length, x):
+        phi, dphi = orig(bc, n, length, x)
+        return (phi, -dphi) if bc == "neumann" else (phi, dphi)
+
+    monkeypatch.setattr(bounded, "eigenfunctions", wrong)
+    _fails(pb.test_bounded_gradient_of_eigenmodes, "neumann", "staggered", 2, "ps")
+
+
+def test_bounded_derivative_chain_factor_is_caught(monkeypatch):
+    # Dirichlet: the factor pi (k + 1) / L of the chain rule dropped
+    orig = bounded.eigenfunctions
+
+    def wrong(bc, n, length, x):
+        phi, dphi = orig(bc, n, length, x)
+        if bc == "dirichlet":
+            w = np.pi * (np.arange(n) + 1.0) / float(length)
+            dphi = dphi / w[None, :]
+        return phi, dphi
+
+    monkeypatch.setattr(bounded, "eigenfunctions", wrong)
+    _fails(pb.test_bounded_gradient_of_eigenmodes, "dirichlet", "regular", 3, "fd2")

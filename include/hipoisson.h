@@ -85,7 +85,12 @@ typedef enum {
  * (1 output), NABLA, the Laplacian of every
  * component (ncomp outputs).  Derivatives multiply by i k_a with the Nyquist
  * mode set to zero; NABLA is that first derivative applied twice per axis and
- * summed.  DIV and NABLA run on the general passes. */
+ * summed.  DIV and NABLA run on the general passes.  Periodic and free-space
+ * plans take every operator; Dirichlet / Neumann plans take GRAD only, with
+ * homogeneous boundary values (HP_E_UNSUPPORTED otherwise): the derivative of
+ * the Table 1 sine (cosine) series through psi, evaluated as a cosine (sine)
+ * series at the output points (REGULAR Dirichlet: every node, the normal
+ * derivative on the boundary nodes).  Batched plans take HP_D_NONE only. */
 typedef enum { HP_D_NONE = 0, HP_D_GRAD = 1, HP_D_CURL = 2, HP_D_DIV = 3, HP_D_NABLA = 4 } hp_diff;
 typedef enum { HP_F32 = 0, HP_F64 = 1 } hp_prec;
 

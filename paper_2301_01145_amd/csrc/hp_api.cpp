@@ -170,8 +170,15 @@ hp_status validate(const hp_desc* d) {
     return fail(nullptr, HP_E_ARG, "div needs a 3-component 3D field");
   if (d->diff == HP_D_GRAD && d->ncomp != 1)
     return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
-  if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN))
-    return fail(nullptr, HP_E_UNSUPPORTED, "spectral derivatives on Dirichlet/Neumann grids");
+  if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN)) {
+    if (d->diff != HP_D_GRAD)
+      return fail(nullptr, HP_E_UNSUPPORTED, "Dirichlet/Neumann grids take the gradient only");
+    if (d->inhomogeneous)
+      return fail(nullptr, HP_E_UNSUPPORTED, "the Dirichlet/Neumann gradient needs homogeneous boundary values");
+    for (int a = 0; a < d->ndim; ++a)
+      if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
+        return fail(nullptr, HP_E_ARG, "the Neumann regular gradient needs 2 cells per axis");
+  }
   if (unb && d->ndim == 1 && d->kernel != HP_G_GAUSS2 && d->kernel != HP_G_SPECTRAL)
     return fail(nullptr, HP_E_UNSUPPORTED, "1D free space takes the G2 or the spectral kernel");
   // transform lengths must be 2^a 3^b 5^c
@@ -507,6 +514,7 @@ hp_status green_spectrum(hp_plan p, Problem& P) {
 
 // ----------------------------------------------------------- plan setup
 bool fast_unbounded_ok(hp_plan p, const Problem& P);
+size_t count_elems(const int* dims, int nd);
 
 hp_status setup_problem(hp_plan p, Problem& P) {
   const hp_desc& d = P.d;
@@ -538,6 +546,7 @@ hp_status setup_problem(hp_plan p, Problem& P) {
       P.norm /= c;
       HP_TRY(upload(p, eigen(d.bc, d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false, (void**)&P.lam[a]));
     }
+    if (P.nder) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.grad_s));
   } else if (d.bc == HP_PERIODIC) {
     P.norm = 1.0;
     for (int a = 0; a < P.nd; ++a) {
@@ -812,11 +821,15 @@ bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
 
 // Switch a general bounded pass (same descriptor) to its wavefront kernel.
 hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
+  if (a.fast == FAST_GRAD_PREP) return HP_OK;
   const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
   bool faces = false;
   for (int ax = 0; ax < 3; ++ax) faces |= a.face[ax][0] != nullptr || a.face[ax][1] != nullptr;
   if (faces && !contig) return HP_OK;  // boundary terms: contiguous passes only
-  a.fast = a.kind == PK_SANDWICH ? FAST_R2R_SW : (contig ? FAST_R2R_C : FAST_R2R_S);
+  const int kind = a.kind == PK_SANDWICH ? FAST_R2R_SW : (contig ? FAST_R2R_C : FAST_R2R_S);
+  const int lds = r2r_lds_bytes(kind, a.L, a.n, p->prec);
+  if (lds <= 0 || lds > 160 * 1024) return HP_OK;  // stays on the general kernel
+  a.fast = kind;
   const void* tw;
   HP_TRY(fast_twiddles(p, a.L, &tw));
   a.tw = tw;
@@ -862,9 +875,110 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   };
   auto set_faces = [&](PassArgs& a, int comp) { fill_face_terms(P, comp, a); };
   (void)dreg;
+  const int last = nd - 1;
+  // Gradient (homogeneous Dirichlet / Neumann): the source transformed along
+  // every axis goes to grad_s (the forward pass along axis 0 is done once
+  // more, out of place); per derivative axis g a prep pass writes the
+  // coefficients of the derivative series into that derivative's output, and
+  // backward passes along every axis evaluate it, with the transform of the
+  // other parity along g.  The passes of psi are unchanged.
+  auto grad_chain = [&](int comp) -> hp_status {
+    void* S = (void*)((char*)P.grad_s + woff * es);
+    {
+      PassArgs a = base();
+      a.kind = PK_ONEWAY;
+      a.xf = xf[0];
+      a.L = L[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
+      a.in[0] = nd == 1 ? P.in[comp] : work(comp);
+      a.out[0] = S;
+      a.ax_j = 0;
+      if (nd == 1) {
+        a.in_sj = a.out_sj = 1;
+        a.in_jfast = a.out_jfast = 1;
+      } else {
+        a.in_sj = a.out_sj = ws[0];
+        a.in_sp = a.out_sp = ws[last];
+        a.Np = P.n[last]; a.ax_p = last;
+        if (nd == 3) { a.in_so = a.out_so = ws[1]; a.No = P.n[1]; a.ax_o = 1; }
+      }
+      HP_TRY(finish_pass(p, a, nd == 1 ? 2 : 32, 2, 0, 1));
+      const void* q;
+      HP_TRY(quarter(p, a.n, &q));
+      a.qtw = q;
+      out.push_back({a, 1});
+    }
+    const bool dir = d.bc == HP_DIRICHLET, reg = d.grid == HP_REGULAR;
+    for (int g = 0; g < nd; ++g) {
+      // active view of the derivative output: extent len[b] from off[b]
+      int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
+      for (int b = 0; b < nd; ++b) { off[b] = dreg ? 1 : 0; len[b] = P.n[b]; }
+      int xd;
+      if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
+      else if (dir) xd = X_DCT3;
+      else if (reg) { xd = X_DST1; len[g] = P.n[g] - 2; off[g] = 1; }   // interior nodes
+      else xd = X_DST3;
+      {
+        PassArgs a = base();
+        a.fast = FAST_GRAD_PREP;
+        a.ax_j = g;
+        a.in[0] = S;
+        a.out[0] = P.der[g];
+        double cnt_in = 1.0, cnt_out = 1.0;
+        for (int b = 0; b < 3; ++b) {
+          a.gp_ext[b] = b < nd ? P.nout[b] : 1;
+          a.gp_off[b] = off[b];
+          a.gp_len[b] = len[b];
+          a.gp_is[b] = a.gp_os[b] = b < nd ? ws[b] : 0;
+          a.nunk[b] = b < nd ? P.n[b] : 1;
+          a.lam[b] = b < nd ? P.lam[b] : nullptr;
+          if (b < nd) { cnt_in *= P.n[b]; cnt_out *= P.nout[b]; }
+        }
+        a.gp_shift = dir ? -1 : 1;  // sine index k carries wavenumber k + 1
+        a.gp_kadd = dir ? 1 : 0;
+        a.gp_scale = (dir ? 1.0 : -1.0) * M_PI / P.len[g];
+        a.norm = P.norm;
+        PassRec r{a, 1};
+        r.bytes = (cnt_in + cnt_out) * (double)es;
+        out.push_back(r);
+      }
+      long long vo = 0;
+      for (int b = 0; b < nd; ++b) vo += (long long)off[b] * ws[b];
+      void* view = (void*)((char*)P.der[g] + vo * (long long)es);
+      for (int c = last; c >= 0; --c) {
+        PassArgs a = base();
+        a.kind = PK_ONEWAY;
+        a.xf = c == g ? xd : xb[c];
+        a.L = L[c]; a.n = len[c]; a.nin = a.nout = len[c];
+        a.in[0] = view; a.out[0] = view;
+        a.in_sj = a.out_sj = ws[c];
+        a.ax_j = c;
+        if (nd == 1) {
+          a.in_jfast = a.out_jfast = 1;
+        } else if (c == last) {
+          a.in_sp = a.out_sp = ws[last - 1]; a.Np = len[last - 1]; a.ax_p = last - 1;
+          if (nd == 3) { a.in_so = a.out_so = ws[0]; a.No = len[0]; a.ax_o = 0; }
+          a.in_jfast = a.out_jfast = 1;
+        } else {
+          a.in_sp = a.out_sp = ws[last]; a.Np = len[last]; a.ax_p = last;
+          if (nd == 3) {
+            const int o = c == 0 ? 1 : 0;
+            a.in_so = a.out_so = ws[o]; a.No = len[o]; a.ax_o = o;
+          }
+        }
+        for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? len[b] : 0;
+        HP_TRY(finish_pass(p, a, nd == 1 ? 2 : (c == last ? 16 : 32), 2, 0, 1));
+        const void* q;
+        HP_TRY(quarter(p, a.n, &q));
+        a.qtw = q;
+        out.push_back({a, 1});
+      }
+    }
+    return HP_OK;
+  };
   // one pass per component (faces differ per component)
   for (int comp = 0; comp < P.ncomp; ++comp) {
     if (nd == 1) {
+      if (P.nder) HP_TRY(grad_chain(comp));
       PassArgs a = base();
       a.kind = PK_SANDWICH;
       a.xf = xf[0]; a.xb = xb[0];
@@ -881,7 +995,6 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
       continue;
     }
-    const int last = nd - 1;
     // P1: forward along the last (contiguous) axis, source + boundary terms
     {
       PassArgs a = base();
@@ -903,6 +1016,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
     }
     // P2 (3D): forward along axis 1, in place, tile across the last axis
+    PassArgs p2{};
     if (nd == 3) {
       PassArgs a = base();
       a.kind = PK_ONEWAY;
@@ -919,7 +1033,9 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       HP_TRY(quarter(p, a.n, &q));
       a.qtw = q;
       out.push_back({a, 1});
+      p2 = a;
     }
+    if (P.nder) HP_TRY(grad_chain(comp));
     // P3: sandwich along axis 0
     {
       PassArgs a = base();
@@ -943,7 +1059,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     }
     // P4 (3D): backward along axis 1
     if (nd == 3) {
-      PassArgs a = out[out.size() - 2].a;  // same geometry as P2
+      PassArgs a = p2;  // same geometry as P2
       a.xf = xb[1];
       out.push_back({a, 1});
     }
@@ -1527,7 +1643,8 @@ double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
 
 const char* pass_name(const PassArgs& a) {
   static const char* fast_names[] = {"",       "r2c_z",      "fwd_y",       "sandwich_x", "inv_y",
-                                     "c2r_z",  "r2r_contig", "r2r_strided", "r2r_sandwich"};
+                                     "c2r_z",  "r2r_contig", "r2r_strided", "r2r_sandwich",
+                                     "grad_prep"};
   constexpr int nfast = (int)(sizeof(fast_names) / sizeof(fast_names[0]));
   if (a.fast > 0 && a.fast < nfast) return fast_names[a.fast];
   if (a.fast) return "wavefront";
@@ -1617,6 +1734,8 @@ hp_status create(const hp_desc* descs, int count, hp_stream stream, hp_plan* out
       return fail(nullptr, HP_E_UNSUPPORTED, "batched plans take homogeneous problems");
     if (d0.ndim != 3)
       return fail(nullptr, HP_E_UNSUPPORTED, "batched plans take 3D problems");
+    if (d0.diff != HP_D_NONE)
+      return fail(nullptr, HP_E_UNSUPPORTED, "batched plans take no derivatives");
   }
   hp_plan p = new (std::nothrow) hp_plan_s();
   if (!p) return fail(nullptr, HP_E_NOMEM, "host allocation failed");

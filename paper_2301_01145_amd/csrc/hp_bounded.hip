@@ -395,9 +395,66 @@ hipError_t launch_bounded_T(const PassArgs& a, hipStream_t s) {
   }
 }
 
+// Coefficients of the derivative along ax_j of a Dirichlet / Neumann solve.
+// The source holds the forward-transformed right-hand side (every axis);
+// dividing by the eigenvalue sum gives the coefficients u of psi, and d/dx of
+// the sine (cosine) series is the cosine (sine) series with coefficients
+// +-(pi kappa / L) u, one index over.  Written so that the backward transform
+// along ax_j of the other type (DST-I -> DCT-I on the n + 2 nodes, DST-III ->
+// DCT-III, DCT-III -> DST-III, DCT-I -> DST-I on the n - 2 interior nodes)
+// and the usual backward transforms along the other axes evaluate it.
+// One thread per output element; consecutive threads take consecutive
+// elements of the last logical axis.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad_prep(PassArgs a) {
+  const long long total = (long long)a.gp_ext[0] * a.gp_ext[1] * a.gp_ext[2];
+  const T* src = (const T*)a.in[0];
+  T* dst = (T*)a.out[0];
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += step) {
+    long long r = e;
+    int i[3];
+    i[2] = (int)(r % a.gp_ext[2]);
+    r /= a.gp_ext[2];
+    i[1] = (int)(r % a.gp_ext[1]);
+    i[0] = (int)(r / a.gp_ext[1]);
+    bool ok = true;
+    long long so = 0, dof = 0;
+    double lam = 0.0;
+    int kap = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      dof += (long long)i[b] * a.gp_os[b];
+      const int sb = i[b] - a.gp_off[b];
+      const int k = b == a.ax_j ? sb + a.gp_shift : sb;
+      ok = ok && sb >= 0 && sb < a.gp_len[b] && k >= 0 && k < a.nunk[b];
+      if (ok) {
+        so += (long long)k * a.gp_is[b];
+        if (a.lam[b]) lam += a.lam[b][k];
+        if (b == a.ax_j) kap = k + a.gp_kadd;
+      }
+    }
+    T v = (T)0;
+    if (ok && lam != 0.0) v = (T)(a.norm / lam * a.gp_scale * (double)kap) * src[so];
+    dst[dof] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_grad_prep(const PassArgs& a, hipStream_t s) {
+  const long long total = (long long)a.gp_ext[0] * a.gp_ext[1] * a.gp_ext[2];
+  if (total <= 0) return hipSuccess;
+  const long long blocks = (total + 255) / 256;
+  const int grid = (int)(blocks < 8192 ? blocks : 8192);
+  hipLaunchKernelGGL(k_grad_prep<T>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s) {
+  if (a.fast == FAST_GRAD_PREP)
+    return prec == 0 ? launch_grad_prep<float>(a, s) : launch_grad_prep<double>(a, s);
   if (prec == 0) return launch_bounded_T<float>(a, s);
   return launch_bounded_T<double>(a, s);
 }

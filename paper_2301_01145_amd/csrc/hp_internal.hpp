@@ -96,12 +96,24 @@ struct PassArgs {
   // signature of the pass geometry (host planner): passes with equal keys
   // share the configuration chosen by the autotuner
   unsigned long long tune_key;
+  // FAST_GRAD_PREP (Dirichlet / Neumann gradient along ax_j): output element
+  // i (logical axes, extents gp_ext, strides gp_os) is active where
+  // s = i - gp_off lies in [0, gp_len) on every axis; it reads the source
+  // coefficient src = s (+ gp_shift along ax_j; strides gp_is, extents nunk)
+  // times gp_scale (src + gp_kadd) norm / sum_b lam[b][src_b].  Elements that
+  // are not active, or whose source lies outside, are written as 0.
+  int gp_ext[3], gp_off[3], gp_len[3];
+  int gp_shift, gp_kadd;
+  double gp_scale;
+  long long gp_is[3], gp_os[3];
 };
 
 enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH = 3,
                       FAST_INV_Y = 4, FAST_C2R = 5,
                       // bounded real-to-real passes (hp_bounded.hip)
-                      FAST_R2R_C = 6, FAST_R2R_S = 7, FAST_R2R_SW = 8 };
+                      FAST_R2R_C = 6, FAST_R2R_S = 7, FAST_R2R_SW = 8,
+                      // elementwise: spectral derivative coefficients (hp_bounded.hip)
+                      FAST_GRAD_PREP = 9 };
 // Derivative completion in the backward y pass of the free-space path.
 enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 

@@ -49,7 +49,11 @@ BAD = [
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=1), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="g2"), _lib.HP_E_ARG),
-    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="grad"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="grad"), None),  # homogeneous: valid
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=3), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8], diff="grad", kernel="fd2", inhomogeneous=True),
+     _lib.HP_E_UNSUPPORTED),
+    (dict(bc="neumann", grid="regular", nc=[1], diff="grad"), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[7, 8]), _lib.HP_E_UNSUPPORTED),
     (dict(bc="periodic", grid="staggered", nc=[0, 8]), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="regular", nc=[1]), _lib.HP_E_ARG),

@@ -2,7 +2,7 @@
 replayed: every replay, with eager work and synchronisations in between and
 the outputs poisoned before it, equals the eager solve bit for bit.  Covers
 the wavefront-FFT paths (free space with curl, periodic with gradient,
-bounded with boundary values)."""
+bounded with boundary values or with the gradient)."""
 import numpy as np
 import pytest
 
@@ -23,6 +23,9 @@ CASES = [
     ("periodic", "staggered", [30, 24, 20], "ps", "nabla", 3, False),
     ("unbounded", "staggered", [40, 36], "spectral", "curl", 1, False),
     ("unbounded", "staggered", [120], "g2", "grad", 1, False),
+    # Dirichlet / Neumann gradient: wavefront and general passes
+    ("dirichlet", "regular", [64, 32, 128], "ps", "grad", 1, False),
+    ("neumann", "regular", [12, 10, 9], "fd2", "grad", 1, False),
 ]
 
 

@@ -88,6 +88,36 @@ def test_bounded_fast_matches_general(bc, grid, prec, monkeypatch):
     check(fast, gen, prec, "wavefront vs general")
 
 
+# Dirichlet / Neumann gradient: small ragged sizes on the general passes, and
+# power-of-two transform lengths on the wavefront passes (also checked against
+# the general ones).  psi is the same with and without the gradient.
+BGRAD = [[12], [9], [12, 10], [9, 15], [12, 10, 9], [64, 32, 128], [128, 64]]
+
+
+@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("dirichlet", "staggered"),
+                                     ("neumann", "regular"), ("neumann", "staggered")])
+@pytest.mark.parametrize("nc", BGRAD)
+@pytest.mark.parametrize("kernel", ["ps", "fd2"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bounded_grad(bc, grid, nc, kernel, prec, monkeypatch):
+    nd = len(nc)
+    f, _ = case_input(bc, grid, nc, 1, False, prec, seed=5 + nd)
+    got, gd = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "grad", prec, 1, None)
+    ref, rd = oracle_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "grad", None)
+    check(got, ref, prec, "psi")
+    assert len(gd) == len(rd) == nd
+    for a in range(nd):
+        assert gd[a].shape == rd[a].shape
+        check(gd[a], rd[a], prec, f"d/dx{a}")
+    plain, _ = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "none", prec, 1, None)
+    assert np.array_equal(plain, got)
+    if max(nc) >= 64:
+        monkeypatch.setenv("HP_GENERIC", "1")
+        _, gen = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, "grad", prec, 1, None)
+        for a in range(nd):
+            check(gd[a], gen[a], prec, f"wavefront vs general d/dx{a}")
+
+
 @pytest.mark.parametrize("nd,nc", [(1, [12]), (1, [9]), (2, [12, 10]), (2, [9, 15]), (3, [12, 10, 9]),
                                    (3, [20, 24, 30])])
 @pytest.mark.parametrize("kernel", ["ps", "fd2"])
@@ -294,6 +324,22 @@ def test_unbounded_low_dim(nd, kernel, diff, prec):
                 assert e2 <= tol and rel_max(gd[a], rd[a]) <= 10 * tol, (nc, e2)
             else:
                 check(gd[a], rd[a], prec, f"{diff} {a} {nc}")
+
+
+@pytest.mark.parametrize("nd,kernel", [(2, "g2"), (2, "spectral"), (1, "g2"), (1, "spectral")])
+@pytest.mark.parametrize("diff", ["none", "grad"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unbounded_low_dim_regular(nd, kernel, diff, prec):
+    # node-centred 2D / 1D free space: N_c + 1 nodes doubled to 2 (N_c + 1)
+    for nc in ([[23, 19], [63, 47]] if nd == 2 else [[39], [255]]):
+        f, _ = case_input("unbounded", "regular", nc, 1, False, prec, seed=47)
+        got, gd = gpu_solve("unbounded", "regular", nc, LO[:nd], HI[:nd], f, kernel, diff, prec, 1, None)
+        ref, rd = oracle_solve("unbounded", "regular", nc, LO[:nd], HI[:nd], f, kernel, diff, None)
+        assert got.shape == tuple(n + 1 for n in nc)
+        check(got, ref, prec, f"psi {nc}")
+        assert len(gd) == len(rd)
+        for a in range(len(rd)):
+            check(gd[a], rd[a], prec, f"{diff} {a} {nc}")
 
 
 @pytest.mark.parametrize("bc,kernel", [("periodic", "ps"), ("periodic", "fd2"), ("unbounded", "g2"),

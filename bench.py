@@ -159,6 +159,13 @@ def other_workloads(steps, warmup):
     res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
                                        "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
     s.close()
+    # the same source, homogeneous PS, psi and its gradient (sine -> cosine series)
+    s = Solver("dirichlet", "regular", [128] * 3, kernel="ps", diff="grad", dtype=torch.float32)
+    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"))
+    ms = _time(s.run, steps, warmup, s.stream)
+    res["dirichlet3d_128_ps_grad_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+                                           "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+    s.close()
     # 64 batched Neumann problems: one persistent launch replayed from a captured
     # hipGraph (the plan lives on a side stream so that it can be captured), FP32
     probs = neumann_batch(64, seed=5)

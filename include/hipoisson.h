@@ -85,7 +85,7 @@ typedef enum {
  * (1 output), NABLA, the Laplacian of every
  * component (ncomp outputs).  Derivatives multiply by i k_a with the Nyquist
  * mode set to zero; NABLA is that first derivative applied twice per axis and
- * summed.  DIV and NABLA run on the general passes.  Periodic and free-space
+ * summed.  Periodic and free-space
  * plans take every operator; Dirichlet / Neumann plans take GRAD only, with
  * homogeneous boundary values (HP_E_UNSUPPORTED otherwise): the derivative of
  * the Table 1 sine (cosine) series through psi, evaluated as a cosine (sine)

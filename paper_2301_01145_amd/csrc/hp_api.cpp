@@ -1330,8 +1330,6 @@ hp_status passes_unbounded(hp_plan p, Problem& P, bool adjoint, std::vector<Pass
 // Also used for 3D periodic plans, whose transform lengths M are then n.
 bool fast_unbounded_ok(hp_plan p, const Problem& P) {
   if (std::getenv("HP_GENERIC") || P.nd != 3) return false;
-  // the wavefront passes provide the gradient and the curl
-  if (P.d.diff == HP_D_DIV || P.d.diff == HP_D_NABLA) return false;
   const bool pad = P.d.bc == HP_UNBOUNDED;
   auto pow2 = [](int v) { return v >= 64 && v <= 1024 && (v & (v - 1)) == 0; };
   for (int a = 0; a < 3; ++a)
@@ -1365,7 +1363,10 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
     n_dst = nc + nder;
     for (int c = 0; c < nc; ++c) src[c] = P.in[c];
     for (int f = 0; f < n_dst; ++f) dst[f] = f < nc ? P.out[f] : P.der[f - nc];
-    n_mid = dk == HP_D_CURL ? 5 : (dk == HP_D_GRAD ? 2 : nc);
+    // spectra between the x and the backward y pass: the curl completes its
+    // y / z derivatives there (5), the gradient its y / z (2); psi, the
+    // divergence and the Laplacian leave the x pass complete
+    n_mid = dk == HP_D_CURL ? 5 : (dk == HP_D_GRAD ? 2 : n_dst);
     iy_mode = dk == HP_D_CURL ? IY_CURL5 : (dk == HP_D_GRAD ? IY_GRAD2 : IY_PLAIN);
   } else {
     n_src = nc + nder;
@@ -1452,11 +1453,12 @@ hp_status passes_unbounded_fast(hp_plan p, Problem& P, bool adjoint, std::vector
         a.green = P.green;
         for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
       }
-      if (!adjoint) a.diff = dk == HP_D_GRAD ? D_GRAD : (dk == HP_D_CURL ? D_CURL : D_NONE);
-      else a.diff = dk == HP_D_GRAD ? D_ADJ_GRAD : (dk == HP_D_CURL ? D_ADJ_CURL : D_NONE);
+      a.diff = diff_kind(dk, adjoint);
       for (int f = 0; f < n_src; ++f) a.in[f] = src[f] ? P.b2[f] : nullptr;
       for (int f = 0; f < n_mid; ++f) a.out[f] = P.c2[f];
-      r.grid_y = (a.diff == D_NONE || a.diff == D_CURL) ? nc : 1;
+      // one output group per component, or one coupled group
+      r.grid_y = (a.diff == D_NONE || a.diff == D_CURL || a.diff == D_NABLA || a.diff == D_ADJ_NABLA)
+                     ? nc : 1;
       const double oct = periodic ? 0.0 : (double)(M0 / 2 + 1) * (M1 / 2 + 1) * kc * es;
       r.bytes = (n_live + n_mid) * (double)kc * M1 * n0 * cs + oct;
     }

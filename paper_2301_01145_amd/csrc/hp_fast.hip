@@ -170,9 +170,12 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
 // FFTs and stores.  Tile order: kz slowest, then pairs of ky tiles
 // (t, ytiles-1-t) whose wavenumbers +-ky share Green's function rows, then the
 // output groups; the XCD-contiguous numbering keeps such tiles behind one L2.
-template <typename T, int L, int P, bool ADJ, bool DBL, bool PAD>
+// EXT: the divergence and the Laplacian (D_DIV, D_NABLA and their
+// transposes) in instances of their own; the other instances keep the code
+// of psi, the gradient and the curl only.
+template <typename T, int L, int P, bool ADJ, bool DBL, bool PAD, bool EXT>
 __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
-                                  (sizeof(T) == 4 && P == 8 && L == 512 && !ADJ) ? 4 : 1)
+                                  (sizeof(T) == 4 && P == 8 && L == 512 && !ADJ && !EXT) ? 4 : 1)
     kf_sandwich(const PassArgs a) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   constexpr int NIN = PAD ? R0 / 2 : R0;  // elements per lane on the x < n0 side
@@ -231,9 +234,13 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       return (T)a.norm / (T)lam;
     }
   };
-  // single-input groups (D_NONE, forward curl): prefetched input and Green's values
-  const bool pref = a.diff == D_NONE || (!ADJ && a.diff == D_CURL);
-  auto src_of = [&](const TileIdx& t) { return a.in[a.diff == D_NONE || a.diff == D_CURL ? t.grp : 0]; };
+  // single-input groups (D_NONE, forward curl, forward Laplacian): prefetched
+  // input and Green's values
+  const bool pref = EXT ? (!ADJ && a.diff == D_NABLA) : (a.diff == D_NONE || (!ADJ && a.diff == D_CURL));
+  auto src_of = [&](const TileIdx& t) {
+    if constexpr (EXT) return a.in[t.grp];
+    else return a.in[a.diff == D_NONE || a.diff == D_CURL ? t.grp : 0];
+  };
   C2<T> pf[NIN];
   T pg[R0];
   auto prefetch = [&](const TileIdx& t) {
@@ -312,7 +319,73 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       else __syncthreads();
     };
 
-    if (a.diff == D_NONE) {
+    // |k|^2 of bin i (every wavenumber with its Nyquist value zeroed)
+    auto ksq = [&](int i) -> T { return kx(i) * kx(i) + kyv * kyv + kzv * kzv; };
+    auto zero = [](C2<T> (&w)[R0]) {
+#pragma unroll
+      for (int i = 0; i < R0; ++i) w[i] = {(T)0, (T)0};
+    };
+    if constexpr (EXT) {
+      const int nc = ngrp;  // components (Laplacian groups)
+      if (!ADJ && a.diff == D_NABLA) {
+        // psi_c and its Laplacian -|k|^2 psi_c (output nc + c)
+        const int c = t.grp;
+        wave_fft<T, L, false, PAD>(v, col, bs, g, tw);
+        green(v);
+        C2<T> u[R0];
+#pragma unroll
+        for (int i = 0; i < R0; ++i) u[i] = cscale(v[i], -ksq(i));
+        emit(u, a.out[nc + c]);
+        emit(v, a.out[c]);
+      } else if (!ADJ) {
+        // D_DIV: psi_0..2 and sum_c i k_c psi_c (output 3)
+        C2<T> D[R0];
+        zero(D);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          C2<T> w[R0];
+          load(w, a.in[c]);
+          green(w);
+#pragma unroll
+          for (int i = 0; i < R0; ++i) D[i] = cadd(D[i], cscale(cmuli(w[i]), kcomp(c, i)));
+          emit(w, a.out[c]);
+        }
+        emit(D, a.out[3]);
+      } else if (a.diff == D_ADJ_NABLA) {
+        // the Laplacian is symmetric: S_c = g_psi_c - |k|^2 g_lap_c
+        const int c = t.grp;
+        C2<T> S[R0];
+        if (a.in[c]) load(S, a.in[c]);
+        else zero(S);
+        if (a.in[nc + c]) {
+          C2<T> w[R0];
+          load(w, a.in[nc + c]);
+#pragma unroll
+          for (int i = 0; i < R0; ++i) S[i] = csub(S[i], cscale(w[i], ksq(i)));
+        }
+        green(S);
+        emit(S, a.out[c]);
+      } else {
+        // D_ADJ_DIV, the transpose of the divergence (minus the gradient):
+        // S_c = g_psi_c - i k_c g_div
+        const bool hd = a.in[3] != nullptr;
+        C2<T> Dv[R0];
+        if (hd) load(Dv, a.in[3]);
+        else zero(Dv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          C2<T> S[R0];
+          if (a.in[c]) load(S, a.in[c]);
+          else zero(S);
+          if (hd) {
+#pragma unroll
+            for (int i = 0; i < R0; ++i) S[i] = csub(S[i], cscale(cmuli(Dv[i]), kcomp(c, i)));
+          }
+          green(S);
+          emit(S, a.out[c]);
+        }
+      }
+    } else if (a.diff == D_NONE) {
       wave_fft<T, L, false, PAD>(v, col, bs, g, tw);
       green(v);
       emit(v, a.out[t.grp]);
@@ -635,22 +708,30 @@ static hipError_t launch_LP(const PassArgs& a0, int grid_y, hipStream_t s) {
     case FAST_SANDWICH: {
       constexpr int NT = 64 * (P / WF<L>::PPW);
       const int ntiles = (a.gM[1] / P) * a.kz_count * grid_y;
-      const bool adj = a.diff == D_ADJ_CURL || a.diff == D_ADJ_GRAD;
+      const bool adj = diff_is_adjoint(a.diff);
+      const bool ext = a.diff == D_DIV || a.diff == D_NABLA || a.diff == D_ADJ_DIV ||
+                       a.diff == D_ADJ_NABLA;
       auto go = [&](auto kern) {
         allow_lds<decltype(kern)::value>();
         const int nb = persistent_grid<decltype(kern)::value>(NT, lds, ntiles);
         hipLaunchKernelGGL(decltype(kern)::value, dim3(nb), dim3(NT), lds, s, a);
       };
-#define HP_SW(ADJ, DBL) \
-  go(std::integral_constant<decltype(&kf_sandwich<T, L, P, ADJ, DBL, PAD>), \
-                            &kf_sandwich<T, L, P, ADJ, DBL, PAD>>{})
+#define HP_SW(ADJ, DBL, EXT) \
+  go(std::integral_constant<decltype(&kf_sandwich<T, L, P, ADJ, DBL, PAD, EXT>), \
+                            &kf_sandwich<T, L, P, ADJ, DBL, PAD, EXT>>{})
+#define HP_SW2(DBL, EXT) \
+  do {                   \
+    if (adj) HP_SW(true, DBL, EXT); \
+    else HP_SW(false, DBL, EXT);    \
+  } while (0)
       if (a.emit_dbl) {  // double-buffered output tiles
-        if (adj) HP_SW(true, true);
-        else HP_SW(false, true);
+        if (ext) HP_SW2(true, true);
+        else HP_SW2(true, false);
       } else {
-        if (adj) HP_SW(true, false);
-        else HP_SW(false, false);
+        if (ext) HP_SW2(false, true);
+        else HP_SW2(false, false);
       }
+#undef HP_SW2
 #undef HP_SW
     } break;
     case FAST_INV_Y: {

@@ -20,6 +20,8 @@ CASES = [
     ("neumann", "staggered", [32, 64, 64], "fd2", "none", 1, True),
     # general passes: operators, kernels, lower dimensions
     ("unbounded", "staggered", [24, 20, 30], "g4", "div", 3, False),
+    ("unbounded", "staggered", [32, 64, 32], "g2", "div", 3, False),
+    ("periodic", "staggered", [64, 64, 64], "fd2", "nabla", 3, False),
     ("periodic", "staggered", [30, 24, 20], "ps", "nabla", 3, False),
     ("unbounded", "staggered", [40, 36], "spectral", "curl", 1, False),
     ("unbounded", "staggered", [120], "g2", "grad", 1, False),

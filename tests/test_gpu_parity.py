@@ -247,11 +247,13 @@ def test_unbounded_kernels_adjoint(kernel, prec):
 
 
 @pytest.mark.parametrize("bc,nc", [("periodic", [12, 10, 8]), ("periodic", [64, 32, 64]),
-                                   ("unbounded", [10, 12, 8]), ("unbounded", [32, 32, 64])])
+                                   ("periodic", [64, 64, 128]), ("unbounded", [10, 12, 8]),
+                                   ("unbounded", [32, 32, 64])])
 @pytest.mark.parametrize("diff,ncomp", [("div", 3), ("nabla", 1), ("nabla", 3)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_div_nabla(bc, nc, diff, ncomp, prec):
-    # Section 2.3.3's DIV and NABLA on psi (general passes, also at power-of-two sizes)
+    # Section 2.3.3's DIV and NABLA on psi: general passes at ragged sizes,
+    # wavefront passes where every transform length is a power of two >= 64
     kernel = "ps" if bc == "periodic" else "g2"
     f, _ = case_input(bc, "staggered", nc, ncomp, False, prec, seed=37)
     got, gd = gpu_solve(bc, "staggered", nc, LO, HI, f, kernel, diff, prec, ncomp, None)
@@ -276,11 +278,11 @@ def test_periodic_nabla_low_dim(nd, nc, kernel, prec):
 @pytest.mark.parametrize("diff,ncomp", [("div", 3), ("nabla", 1), ("nabla", 3)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("with_psi", [True, False])
-def test_div_nabla_adjoint(diff, ncomp, prec, with_psi):
+@pytest.mark.parametrize("nc", [[16, 12, 20], [32, 64, 32]])
+def test_div_nabla_adjoint(diff, ncomp, prec, with_psi, nc):
     import torch
     from oracle import unbounded as ub
     from paper_2301_01145_amd import Solver
-    nc = [16, 12, 20]
     rng = np.random.default_rng(41)
     rnd = np.float32 if prec == "f32" else np.float64
     shape = tuple(nc)
@@ -298,6 +300,21 @@ def test_div_nabla_adjoint(diff, ncomp, prec, with_psi):
     ref = ub.adjoint_unbounded(gpsi if with_psi else None, gder, hs, 2.0 * max(hs), diff)
     s.close()
     check(got, ref, prec, "adjoint")
+
+
+@pytest.mark.parametrize("bc,nc", [("unbounded", [32, 64, 32]), ("periodic", [64, 128, 64])])
+@pytest.mark.parametrize("diff,ncomp", [("div", 3), ("nabla", 1), ("nabla", 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_div_nabla_fast_matches_general(bc, nc, diff, ncomp, prec, monkeypatch):
+    """DIV / NABLA on the wavefront passes against the general passes (same input)."""
+    kernel = "ps" if bc == "periodic" else "g2"
+    f, _ = case_input(bc, "staggered", nc, ncomp, False, prec, seed=53)
+    fast, fd = gpu_solve(bc, "staggered", nc, LO, HI, f, kernel, diff, prec, ncomp, None)
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen, gd = gpu_solve(bc, "staggered", nc, LO, HI, f, kernel, diff, prec, ncomp, None)
+    check(fast, gen, prec, "psi")
+    for a in range(len(gd)):
+        check(fd[a], gd[a], prec, f"{diff} {a}")
 
 
 LOW_DIM = [(2, k) for k in ["g2", "g4", "g6", "g8", "g10", "spectral"]] + [(1, "g2"), (1, "spectral")]

@@ -69,3 +69,15 @@ def oracle_solve(bc, grid, nc, lo, hi, f, kernel, diff, faces, sigma_cells=0.0):
     op = kernel  # bounded: "ps" | "fd2"; free space: the Green's kernel name
     return oracle.solve(bc, grid, nc, lo, hi, f, operator=op, diff=diff, faces=faces,
                         sigma_cells=sigma_cells if sigma_cells > 0 else 2.0)
+
+
+def laplacian_rounding_tol(psi, lap, hs, doubled):
+    """Rounding bound for a Laplacian taken in spectral space from FP64 data:
+    an FFT of N points rounds psi-hat by at most about eps log2(N) relative
+    (once on each side compared: the GPU and the oracle), and multiplying by
+    |k|^2 <= sum_a (pi / H_a)^2 amplifies that against the output by
+    A = k_max^2 ||psi|| / ||lap psi||.  Returns the rel-L2 bound 2 eps log2(N) A."""
+    eps = np.finfo(np.float64).eps
+    k2 = sum((np.pi / h) ** 2 for h in hs)
+    amp = k2 * np.linalg.norm(psi) / np.linalg.norm(lap)
+    return 2.0 * eps * np.log2(float(np.prod(doubled))) * amp

@@ -28,6 +28,12 @@ CASES = [
     ("periodic", "staggered", [36, 40, 30], "fd2", "nabla", 1, False),
     ("unbounded", "staggered", [48, 60], "spectral", "curl", 1, False),
     ("unbounded", "staggered", [90], "g2", "grad", 1, False),
+    # Dirichlet / Neumann gradient (elementwise prep passes stay untuned), and
+    # DIV / NABLA on the wavefront passes
+    ("neumann", "regular", [24, 20, 30], "ps", "grad", 1, False),
+    ("dirichlet", "staggered", [64, 32, 64], "fd2", "grad", 1, False),
+    ("unbounded", "staggered", [32, 64, 32], "g2", "div", 3, False),
+    ("periodic", "staggered", [64, 64, 64], "ps", "nabla", 3, False),
 ]
 
 

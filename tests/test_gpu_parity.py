@@ -11,7 +11,8 @@ import itertools
 import numpy as np
 import pytest
 
-from gpu_util import TOL, case_input, gpu_solve, oracle_solve, rel_l2, rel_max, to_dev
+from gpu_util import (TOL, case_input, gpu_solve, laplacian_rounding_tol, oracle_solve, rel_l2, rel_max,
+                      to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -335,8 +336,11 @@ def test_unbounded_low_dim(nd, kernel, diff, prec):
             if diff == "nabla" and prec == "f64":
                 # the Laplacian multiplies the spectrum by k^2 <= (pi / H)^2: the FP64
                 # rounding of the transform of the slowly decaying 1D / 2D kernel (set by
-                # its largest values) grows by up to (n / 128)^2 against the O(1) output
-                tol = 1e-12 * max(1.0, (max(nc) / 128.0) ** 2)
+                # its largest values) grows by up to (n / 128)^2 against the O(1) output,
+                # and in general by the amplification of laplacian_rounding_tol
+                hs = [(HI[b] - LO[b]) / nc[b] for b in range(nd)]
+                tol = max(1e-12 * max(1.0, (max(nc) / 128.0) ** 2),
+                          laplacian_rounding_tol(ref, rd[a], hs, [2 * n for n in nc]))
                 e2 = rel_l2(gd[a], rd[a])
                 assert e2 <= tol and rel_max(gd[a], rd[a]) <= 10 * tol, (nc, e2)
             else:

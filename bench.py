@@ -290,6 +290,28 @@ def copy_reference():
     print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 3}), flush=True)
 
 
+def copy_ceiling(warmup=3, reps=20):
+    """Measured HBM ceiling of a plain device-to-device copy (torch copy_ of
+    1 GiB): bytes read + written per copy over its mean HIP-event time."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * 4 * n / (ms * 1e-3) / 1e9
+
+
 def timed_solves(solver, steps, warmup):
     import torch
     from paper_2301_01145_amd import hp_pass_stats, hp_set_timing
@@ -484,6 +506,10 @@ def main():
     torch.cuda.synchronize()
     out["graph_ms_per_step"] = _time_graph(s.run, side, args.steps, args.warmup)
     s.close()
+    # the same bytes against what a plain copy reaches on this device
+    cgbs = copy_ceiling()
+    out["copy_ceiling"] = {"copy_gbs": cgbs, "model_gbs_frac": out["model_gbs"] / cgbs,
+                           "dominant_kernel_frac": out["roofline"]["achieved"] / cgbs}
     if not args.no_others:
         out["other_workloads"] = other_workloads(max(5, args.steps // 2), args.warmup)
     if not args.no_cpu:

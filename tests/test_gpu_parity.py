@@ -206,6 +206,33 @@ def test_unbounded(nc, ncomp, diff, prec, grid):
         check(gd[a], rd[a], prec, f"deriv {a}")
 
 
+@pytest.mark.parametrize("diff,ncomp", [("curl", 3), ("grad", 1), ("nabla", 1)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unbounded_regular_wavefront(diff, ncomp, prec):
+    # node-centred free space with N_c + 1 = 32, 64, 32 nodes: doubled lengths
+    # 64, 128, 64, so the wavefront passes run
+    from paper_2301_01145_amd import hp_pass_stats, hp_set_timing
+    import torch
+    from paper_2301_01145_amd import Solver
+    nc = [31, 63, 31]
+    f, _ = case_input("unbounded", "regular", nc, ncomp, False, prec, seed=59)
+    got, gd = gpu_solve("unbounded", "regular", nc, LO, HI, f, "g2", diff, prec, ncomp, None)
+    ref, rd = oracle_solve("unbounded", "regular", nc, LO, HI, f, "g2", diff, None)
+    check(got, ref, prec, "psi")
+    for a in range(len(rd)):
+        check(gd[a], rd[a], prec, f"{diff} {a}")
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver("unbounded", "regular", nc, LO, HI, diff=diff, dtype=dtype, ncomp=ncomp)
+    s.bind([to_dev(f[c], dtype, torch) for c in range(3)] if ncomp == 3 else to_dev(f, dtype, torch))
+    hp_set_timing(s.plan, True)
+    s.run()
+    torch.cuda.synchronize()
+    hp_set_timing(s.plan, False)
+    names = [p[0] for p in hp_pass_stats(s.plan)]
+    s.close()
+    assert names == ["r2c_z", "fwd_y", "sandwich_x", "inv_y", "c2r_z"], names
+
+
 NEW_KERNELS = ["g4", "g6", "g8", "g10", "spectral"]
 
 

@@ -424,7 +424,7 @@ def main():
         copy_reference()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

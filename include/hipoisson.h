@@ -72,7 +72,11 @@ typedef enum { HP_REGULAR = 0, HP_STAGGERED = 1 } hp_grid;
  *     G(r) = -(1/(4 pi r)) [erf(rho/sqrt2) + sqrt(2/pi) exp(-rho^2/2)
  *            sum_{j=1}^{m-1} (-1)^(j-1) He_{2j-1}(rho) / (2^j j!)], rho = r / sigma;
  *   HP_G_SPECTRAL: zeta^ = 1 for |k| <= pi / max_a H_a, else 0; in space
- *     G(r) = -Si(k_c r) / (2 pi^2 r). */
+ *     G(r) = -Si(k_c r) / (2 pi^2 r).
+ * 2D and 1D plans use the same spectra, whose kernels grow as ln(r) / (2 pi)
+ * and |x| / 2; every kernel is available in every dimension.  1D order 2m:
+ * G(x) = (x/2) erf(rho/sqrt2) + (sigma / sqrt(2 pi)) exp(-rho^2/2)
+ *        [1 + sum_{j=1}^{m-1} (-1)^j He_{2j-2}(rho) / (2^j j!)]. */
 typedef enum {
   HP_OP_PS = 0, HP_OP_FD2 = 1,
   HP_G_GAUSS2 = 2, HP_G_GAUSS4 = 3, HP_G_GAUSS6 = 4, HP_G_GAUSS8 = 5, HP_G_GAUSS10 = 6,

@@ -41,7 +41,8 @@ and G_spectral(0) = -k_c / (2 pi^2).  The closed forms are checked against the
 spectral integrals by quadrature in the tests.
 
 Lower dimensions (Section 2.5.2: spectral kernels in 1D, 2D and 3D, Gaussian
-kernels of orders 2-10 in 2D and 3D), read through the same spectra; the
+kernels of orders 2-10; in 1D the paper has only the spectral one, and the
+Gaussian orders are added here), read through the same spectra; the
 additive constant of each is fixed so that G approaches the unregularised
 fundamental solution ((1 / 2 pi) ln r in 2D, |x| / 2 in 1D) at large r:
   2D, order 2m: G = (1 / 2 pi) [ln r + E1(rho^2 / 2) / 2
@@ -51,6 +52,7 @@ fundamental solution ((1 / 2 pi) ln r in 2D, |x| / 2 in 1D) at large r:
   2D, spectral:  G = (1 / 2 pi) [F(k_c r) - ln(k_c / 2) - gamma],
      F(x) = int_0^x (1 - J0(t)) / t dt;
   1D, order 2:   G = (x / 2) erf(x / (sqrt2 sigma)) + sigma exp(-x^2 / (2 sigma^2)) / sqrt(2 pi);
+  1D, order 2m:  G2 + (sigma / sqrt(2 pi)) e^{-rho^2/2} sum_{j=1}^{m-1} (-1)^j He_{2j-2}(rho) / (2^j j!);
   1D, spectral:  G = (|x| Si(k_c |x|) + cos(k_c x) / k_c) / pi.
 """
 import functools
@@ -59,7 +61,7 @@ import math
 import numpy as np
 from numpy.polynomial import hermite_e
 from scipy import integrate
-from scipy.special import erf, eval_laguerre, exp1, j0, sici
+from scipy.special import erf, eval_hermitenorm, eval_laguerre, exp1, j0, sici
 
 SQRT2 = math.sqrt(2.0)
 EULER_GAMMA = 0.57721566490153286060651209008240243
@@ -154,6 +156,21 @@ def green_g2_1d(x, sigma):
     return 0.5 * x * erf(x / (SQRT2 * sigma)) + sigma * np.exp(-0.5 * (x / sigma) ** 2) / math.sqrt(2.0 * np.pi)
 
 
+def green_gauss_1d(x, sigma, order):
+    """1D Gaussian-regularised kernel of order 2m (reading above): the order-2m
+    source is the Gaussian times sum_{j<m} (-1)^j He_{2j}(rho) / (2^j j!), and
+    since d^2/d rho^2 [e^{-rho^2/2} He_n] = e^{-rho^2/2} He_{n+2}, integrating
+    twice adds (sigma / sqrt(2 pi)) e^{-rho^2/2} sum_{j=1}^{m-1} (-1)^j
+    He_{2j-2}(rho) / (2^j j!) to the G2 kernel (no linear term: G stays even
+    and keeps the far field |x| / 2)."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    rho = x / sigma
+    corr = np.zeros_like(x)
+    for j in range(1, order // 2):
+        corr = corr + (-1.0) ** j * eval_hermitenorm(2 * j - 2, rho) / (2.0 ** j * math.factorial(j))
+    return green_g2_1d(x, sigma) + sigma * np.exp(-0.5 * rho * rho) / math.sqrt(2.0 * np.pi) * corr
+
+
 def green_spectral_1d(x, h):
     """1D spectrally truncated kernel, cutoff k_c = pi / h (reading above)."""
     kc = math.pi / h
@@ -172,7 +189,7 @@ def green(kernel, r, sigma, h, dim=3):
             return green_spectral_1d(r, h)
         if order == 2:
             return green_g2_1d(r, sigma)
-        raise NotImplementedError("1D free space: kernels g2 and spectral")
+        return green_gauss_1d(r, sigma, order)
     if order == 0:
         return green_spectral(r, h)
     if order == 2:

@@ -179,8 +179,6 @@ hp_status validate(const hp_desc* d) {
       if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
         return fail(nullptr, HP_E_ARG, "the Neumann regular gradient needs 2 cells per axis");
   }
-  if (unb && d->ndim == 1 && d->kernel != HP_G_GAUSS2 && d->kernel != HP_G_SPECTRAL)
-    return fail(nullptr, HP_E_UNSUPPORTED, "1D free space takes the G2 or the spectral kernel");
   // transform lengths must be 2^a 3^b 5^c
   for (int a = 0; a < d->ndim; ++a) {
     const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);

@@ -803,14 +803,24 @@ __device__ double green_value_low(double r, const GreenEval& e) {
     }
     return (log(e.sigma) + 0.5 * (M_LN2 + log_plus_e1(t)) - exp(-t) * S) / (2.0 * pi);
   }
-  // 1D: G2 or the spectral cutoff
+  // 1D: the spectral cutoff, or Gaussian order 2m: G2 plus
+  // (sigma / sqrt(2 pi)) e^{-rho^2/2} sum_{j=1}^{m-1} (-1)^j He_{2j-2}(rho) / (2^j j!)
+  // (the twice-integrated Hermite terms of the order-2m source), in t = rho^2
   const double x = fabs(r);
   if (e.kind == 0) {
     const double si = x == 0.0 ? 0.0 : table_integral(e.kc * x, e, [](double t) { return sin(t) / t; });
     return (x * si + cos(e.kc * x) / e.kc) / pi;
   }
-  return 0.5 * x * erf(x / (M_SQRT2 * e.sigma)) +
-         e.sigma * exp(-0.5 * (x / e.sigma) * (x / e.sigma)) / sqrt(2.0 * pi);
+  const double t = (x / e.sigma) * (x / e.sigma);
+  double C = 1.0;
+  switch (e.kind) {
+    case 10: C += (((t - 15.0) * t + 45.0) * t - 15.0) / 384.0; [[fallthrough]];
+    case 8: C -= ((t - 6.0) * t + 3.0) / 48.0; [[fallthrough]];
+    case 6: C += (t - 1.0) / 8.0; [[fallthrough]];
+    case 4: C -= 0.5; break;
+    default: break;
+  }
+  return 0.5 * x * erf(x / (M_SQRT2 * e.sigma)) + e.sigma * exp(-0.5 * t) / sqrt(2.0 * pi) * C;
 }
 
 // G(r) of the free-space kernel (GreenEval); see the kernel list in hipoisson.h.

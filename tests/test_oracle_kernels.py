@@ -186,23 +186,41 @@ def test_spectral_2d_kernel_is_its_spectral_integral():
                        atol=2e-4)
 
 
-@pytest.mark.parametrize("kernel", ["g2", "spectral"])
+@pytest.mark.parametrize("kernel", ["g2", "g4", "g6", "g8", "g10", "spectral"])
 def test_1d_kernels_are_their_spectral_integrals(kernel):
     sigma, h = 0.1, 0.05
     kc = math.pi / h
-    zh = (lambda k: math.exp(-0.5 * (k * sigma) ** 2)) if kernel == "g2" else (lambda k: 1.0)
-    kmax = 40.0 / sigma if kernel == "g2" else kc
+    zh = (lambda k: zeta_hat(k, sigma, int(kernel[1:]))) if kernel != "spectral" else (lambda k: 1.0)
+    kmax = kc if kernel == "spectral" else 40.0 / sigma
     g0 = ub.green(kernel, np.array([0.0]), sigma, h, dim=1)[0]
     for x in [0.02, 0.1, 0.37, 1.3]:
         g = ub.green(kernel, np.array([x]), sigma, h, dim=1)[0]
-        # G(x) - G(0) = -(1 / pi) int zh(k) (cos(k x) - 1) / k^2 dk
-        pts = [j * math.pi / x for j in range(1, int(kmax * x / math.pi) + 1)][:300] or None
+        # G(x) - G(0) = -(1 / pi) int zh(k) (cos(k x) - 1) / k^2 dk (break points at the
+        # zeros of cos(k x) - 1 for the cutoff spectrum; the Gaussian spectra are smooth)
+        pts = ([j * math.pi / x for j in range(1, int(kmax * x / math.pi) + 1)][:300] or None
+               if kernel == "spectral" else None)
         val, _ = integrate.quad(lambda k: zh(k) * (math.cos(k * x) - 1) / (k * k) if k > 0 else -0.5 * x * x,
-                                0.0, kmax, limit=2000, points=pts, epsabs=1e-15, epsrel=1e-13)
+                                0.0, kmax, limit=4000, points=pts, epsabs=1e-16, epsrel=1e-14)
         ref = -val / math.pi  # (the spectral kernel's spectrum stops at k_c)
         assert abs((g - g0) - ref) <= 1e-10 * abs(ref), (kernel, x, g - g0, ref)
     assert np.allclose(ub.green(kernel, np.array([50.0, 80.0]), sigma, h, dim=1), [25.0, 40.0], rtol=0,
                        atol=1e-3)
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10])
+def test_1d_gauss_kernel_second_derivative_is_its_source(order):
+    """G'' = zeta_2m, the Gaussian times sum_{j<m} (-1)^j He_2j(rho) / (2^j j!) (the
+    inverse transform of zeta^ = exp(-s) sum_{j<m} s^j / j!), by central differences."""
+    from scipy.special import eval_hermitenorm
+    sigma = 0.1
+    d = 1e-3 * sigma
+    for x in (0.0, 0.07, 0.19, 0.33):
+        G = lambda y: ub.green(f"g{order}", np.array([y]), sigma, 1.0, dim=1)[0]
+        gpp = (G(x + d) - 2 * G(x) + G(x - d)) / d ** 2
+        rho = x / sigma
+        zeta = math.exp(-0.5 * rho * rho) / (math.sqrt(2 * math.pi) * sigma) * sum(
+            (-1) ** j * eval_hermitenorm(2 * j, rho) / (2 ** j * math.factorial(j)) for j in range(order // 2))
+        assert abs(gpp - zeta) <= 1e-5 * max(abs(zeta), 1.0 / sigma), (order, x, gpp, zeta)
 
 
 @pytest.mark.parametrize("kernel", ["g2", "g4", "g6", "spectral"])
@@ -228,7 +246,7 @@ def test_2d_blob_solve(kernel):
     assert np.max(np.abs(psi - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("kernel,dim", [("g4", 2), ("spectral", 2), ("g2", 1), ("spectral", 1)])
+@pytest.mark.parametrize("kernel,dim", [("g4", 2), ("spectral", 2), ("g2", 1), ("g8", 1), ("spectral", 1)])
 def test_low_dim_direct_sum(kernel, dim):
     rng = np.random.default_rng(22)
     shape = (7, 5)[:dim] if dim == 2 else (9,)

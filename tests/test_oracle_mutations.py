@@ -147,3 +147,14 @@ def test_bounded_derivative_chain_factor_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "eigenfunctions", wrong)
     _fails(pb.test_bounded_gradient_of_eigenmodes, "dirichlet", "regular", 3, "fd2")
+
+
+def test_1d_hermite_correction_sign_is_caught(monkeypatch):
+    # 1D order-4 kernel with the Hermite correction subtracted instead of added
+    orig = ub.green_gauss_1d
+
+    def wrong(x, sigma, order):
+        return 2.0 * ub.green_g2_1d(x, sigma) - orig(x, sigma, order)
+
+    monkeypatch.setattr(ub, "green_gauss_1d", wrong)
+    _fails(pk.test_1d_gauss_kernel_second_derivative_is_its_source, 4)

@@ -110,3 +110,8 @@ def test_batched_validation():
     arr = (_lib.hp_desc * 1)(c)
     assert _lib.lib().hp_plan_create_batched(arr, 1, None, ctypes.byref(out)) == _lib.HP_E_UNSUPPORTED
     assert _lib.lib().hp_plan_create_batched(arr, 0, None, ctypes.byref(out)) == _lib.HP_E_ARG
+    # a Dirichlet / Neumann gradient is valid for a single plan, not for a batch
+    d = make_desc("neumann", "staggered", [8, 8, 8], diff="grad")
+    arr = (_lib.hp_desc * 1)(d)
+    assert _lib.lib().hp_plan_create_batched(arr, 1, None, ctypes.byref(out)) == _lib.HP_E_UNSUPPORTED
+    assert "derivatives" in _lib.hp_last_error(None)

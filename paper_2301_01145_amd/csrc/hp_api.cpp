@@ -874,104 +874,115 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   auto set_faces = [&](PassArgs& a, int comp) { fill_face_terms(P, comp, a); };
   (void)dreg;
   const int last = nd - 1;
-  // Gradient (homogeneous Dirichlet / Neumann): the source transformed along
-  // every axis goes to grad_s (the forward pass along axis 0 is done once
-  // more, out of place); per derivative axis g a prep pass writes the
-  // coefficients of the derivative series into that derivative's output, and
-  // backward passes along every axis evaluate it, with the transform of the
-  // other parity along g.  The passes of psi are unchanged.
-  auto grad_chain = [&](int comp) -> hp_status {
-    void* S = (void*)((char*)P.grad_s + woff * es);
+  // Gradient (homogeneous Dirichlet / Neumann).  The passes of psi are
+  // unchanged.  d/dx_0: the forward pass along axis 0 is done once more, out
+  // of place, so that grad_s holds the source transformed along every axis;
+  // a prep pass writes the coefficients of the derivative series (divided by
+  // the eigenvalue sum) into the output of d/dx_0, and backward passes along
+  // every axis evaluate it, with the transform of the other parity along
+  // axis 0.  d/dx_g, g > 0: psi's own array after the sandwich already holds
+  // the divided coefficients along axes 1.. (axis 0 physical), so the prep
+  // reads it and only the axes 1.. are transformed back.
+  auto grad_forward_x = [&](int comp) -> hp_status {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = xf[0];
+    a.L = L[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
+    a.in[0] = nd == 1 ? P.in[comp] : work(comp);
+    a.out[0] = (void*)((char*)P.grad_s + woff * es);
+    a.ax_j = 0;
+    if (nd == 1) {
+      a.in_sj = a.out_sj = 1;
+      a.in_jfast = a.out_jfast = 1;
+    } else {
+      a.in_sj = a.out_sj = ws[0];
+      a.in_sp = a.out_sp = ws[last];
+      a.Np = P.n[last]; a.ax_p = last;
+      if (nd == 3) { a.in_so = a.out_so = ws[1]; a.No = P.n[1]; a.ax_o = 1; }
+    }
+    HP_TRY(finish_pass(p, a, nd == 1 ? 2 : 32, 2, 0, 1));
+    const void* q;
+    HP_TRY(quarter(p, a.n, &q));
+    a.qtw = q;
+    out.push_back({a, 1});
+    return HP_OK;
+  };
+  // derivative g from coefficients `src` (the work-view layout); `eigen`: the
+  // eigenvalue sum still has to be divided out (source transformed along every
+  // axis), else src is psi's array after the sandwich
+  auto grad_deriv = [&](int g, const void* src, bool eigen) -> hp_status {
+    const bool dir = d.bc == HP_DIRICHLET, reg = d.grid == HP_REGULAR;
+    // active view of the derivative output: extent len[b] from off[b]
+    int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
+    for (int b = 0; b < nd; ++b) { off[b] = dreg ? 1 : 0; len[b] = P.n[b]; }
+    int xd;
+    if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
+    else if (dir) xd = X_DCT3;
+    else if (reg) { xd = X_DST1; len[g] = P.n[g] - 2; off[g] = 1; }   // interior nodes
+    else xd = X_DST3;
     {
       PassArgs a = base();
+      a.fast = FAST_GRAD_PREP;
+      a.ax_j = g;
+      a.in[0] = src;
+      a.out[0] = P.der[g];
+      double cnt_in = 1.0, cnt_out = 1.0;
+      for (int b = 0; b < 3; ++b) {
+        a.gp_ext[b] = b < nd ? P.nout[b] : 1;
+        a.gp_off[b] = off[b];
+        a.gp_len[b] = len[b];
+        a.gp_is[b] = a.gp_os[b] = b < nd ? ws[b] : 0;
+        a.nunk[b] = b < nd ? P.n[b] : 1;
+        a.lam[b] = eigen && b < nd ? P.lam[b] : nullptr;
+        if (b < nd) { cnt_in *= P.n[b]; cnt_out *= P.nout[b]; }
+      }
+      a.gp_eigen = eigen ? 1 : 0;
+      a.gp_shift = dir ? -1 : 1;  // sine index k carries wavenumber k + 1
+      a.gp_kadd = dir ? 1 : 0;
+      a.gp_scale = (dir ? 1.0 : -1.0) * M_PI / P.len[g];
+      a.norm = P.norm;
+      PassRec r{a, 1};
+      r.bytes = (cnt_in + cnt_out) * (double)es;
+      out.push_back(r);
+    }
+    long long vo = 0;
+    for (int b = 0; b < nd; ++b) vo += (long long)off[b] * ws[b];
+    void* view = (void*)((char*)P.der[g] + vo * (long long)es);
+    // axis 0 is already physical when the coefficients come from psi's array
+    for (int c = last; c >= (eigen ? 0 : 1); --c) {
+      PassArgs a = base();
       a.kind = PK_ONEWAY;
-      a.xf = xf[0];
-      a.L = L[0]; a.n = P.n[0]; a.nin = a.nout = P.n[0];
-      a.in[0] = nd == 1 ? P.in[comp] : work(comp);
-      a.out[0] = S;
-      a.ax_j = 0;
+      a.xf = c == g ? xd : xb[c];
+      a.L = L[c]; a.n = len[c]; a.nin = a.nout = len[c];
+      a.in[0] = view; a.out[0] = view;
+      a.in_sj = a.out_sj = ws[c];
+      a.ax_j = c;
       if (nd == 1) {
-        a.in_sj = a.out_sj = 1;
+        a.in_jfast = a.out_jfast = 1;
+      } else if (c == last) {
+        a.in_sp = a.out_sp = ws[last - 1]; a.Np = len[last - 1]; a.ax_p = last - 1;
+        if (nd == 3) { a.in_so = a.out_so = ws[0]; a.No = len[0]; a.ax_o = 0; }
         a.in_jfast = a.out_jfast = 1;
       } else {
-        a.in_sj = a.out_sj = ws[0];
-        a.in_sp = a.out_sp = ws[last];
-        a.Np = P.n[last]; a.ax_p = last;
-        if (nd == 3) { a.in_so = a.out_so = ws[1]; a.No = P.n[1]; a.ax_o = 1; }
+        a.in_sp = a.out_sp = ws[last]; a.Np = len[last]; a.ax_p = last;
+        if (nd == 3) {
+          const int o = c == 0 ? 1 : 0;
+          a.in_so = a.out_so = ws[o]; a.No = len[o]; a.ax_o = o;
+        }
       }
-      HP_TRY(finish_pass(p, a, nd == 1 ? 2 : 32, 2, 0, 1));
+      for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? len[b] : 0;
+      HP_TRY(finish_pass(p, a, nd == 1 ? 2 : (c == last ? 16 : 32), 2, 0, 1));
       const void* q;
       HP_TRY(quarter(p, a.n, &q));
       a.qtw = q;
       out.push_back({a, 1});
     }
-    const bool dir = d.bc == HP_DIRICHLET, reg = d.grid == HP_REGULAR;
-    for (int g = 0; g < nd; ++g) {
-      // active view of the derivative output: extent len[b] from off[b]
-      int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
-      for (int b = 0; b < nd; ++b) { off[b] = dreg ? 1 : 0; len[b] = P.n[b]; }
-      int xd;
-      if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
-      else if (dir) xd = X_DCT3;
-      else if (reg) { xd = X_DST1; len[g] = P.n[g] - 2; off[g] = 1; }   // interior nodes
-      else xd = X_DST3;
-      {
-        PassArgs a = base();
-        a.fast = FAST_GRAD_PREP;
-        a.ax_j = g;
-        a.in[0] = S;
-        a.out[0] = P.der[g];
-        double cnt_in = 1.0, cnt_out = 1.0;
-        for (int b = 0; b < 3; ++b) {
-          a.gp_ext[b] = b < nd ? P.nout[b] : 1;
-          a.gp_off[b] = off[b];
-          a.gp_len[b] = len[b];
-          a.gp_is[b] = a.gp_os[b] = b < nd ? ws[b] : 0;
-          a.nunk[b] = b < nd ? P.n[b] : 1;
-          a.lam[b] = b < nd ? P.lam[b] : nullptr;
-          if (b < nd) { cnt_in *= P.n[b]; cnt_out *= P.nout[b]; }
-        }
-        a.gp_shift = dir ? -1 : 1;  // sine index k carries wavenumber k + 1
-        a.gp_kadd = dir ? 1 : 0;
-        a.gp_scale = (dir ? 1.0 : -1.0) * M_PI / P.len[g];
-        a.norm = P.norm;
-        PassRec r{a, 1};
-        r.bytes = (cnt_in + cnt_out) * (double)es;
-        out.push_back(r);
-      }
-      long long vo = 0;
-      for (int b = 0; b < nd; ++b) vo += (long long)off[b] * ws[b];
-      void* view = (void*)((char*)P.der[g] + vo * (long long)es);
-      for (int c = last; c >= 0; --c) {
-        PassArgs a = base();
-        a.kind = PK_ONEWAY;
-        a.xf = c == g ? xd : xb[c];
-        a.L = L[c]; a.n = len[c]; a.nin = a.nout = len[c];
-        a.in[0] = view; a.out[0] = view;
-        a.in_sj = a.out_sj = ws[c];
-        a.ax_j = c;
-        if (nd == 1) {
-          a.in_jfast = a.out_jfast = 1;
-        } else if (c == last) {
-          a.in_sp = a.out_sp = ws[last - 1]; a.Np = len[last - 1]; a.ax_p = last - 1;
-          if (nd == 3) { a.in_so = a.out_so = ws[0]; a.No = len[0]; a.ax_o = 0; }
-          a.in_jfast = a.out_jfast = 1;
-        } else {
-          a.in_sp = a.out_sp = ws[last]; a.Np = len[last]; a.ax_p = last;
-          if (nd == 3) {
-            const int o = c == 0 ? 1 : 0;
-            a.in_so = a.out_so = ws[o]; a.No = len[o]; a.ax_o = o;
-          }
-        }
-        for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? len[b] : 0;
-        HP_TRY(finish_pass(p, a, nd == 1 ? 2 : (c == last ? 16 : 32), 2, 0, 1));
-        const void* q;
-        HP_TRY(quarter(p, a.n, &q));
-        a.qtw = q;
-        out.push_back({a, 1});
-      }
-    }
     return HP_OK;
+  };
+  // before the sandwich: d/dx_0
+  auto grad_chain = [&](int comp) -> hp_status {
+    HP_TRY(grad_forward_x(comp));
+    return grad_deriv(0, (const void*)((char*)P.grad_s + woff * es), true);
   };
   // one pass per component (faces differ per component)
   for (int comp = 0; comp < P.ncomp; ++comp) {
@@ -1055,6 +1066,9 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       a.qtw = q;
       out.push_back({a, 1});
     }
+    // after the sandwich: d/dx_g, g > 0, from psi's array (before P4 changes it)
+    if (P.nder)
+      for (int g = 1; g < nd; ++g) HP_TRY(grad_deriv(g, work(comp), false));
     // P4 (3D): backward along axis 1
     if (nd == 3) {
       PassArgs a = p2;  // same geometry as P2

@@ -396,8 +396,9 @@ hipError_t launch_bounded_T(const PassArgs& a, hipStream_t s) {
 }
 
 // Coefficients of the derivative along ax_j of a Dirichlet / Neumann solve.
-// The source holds the forward-transformed right-hand side (every axis);
-// dividing by the eigenvalue sum gives the coefficients u of psi, and d/dx of
+// The source holds the forward-transformed right-hand side (every axis; with
+// gp_eigen, dividing by the eigenvalue sum gives the coefficients u of psi)
+// or already the coefficients u (axis 0 physical); d/dx of
 // the sine (cosine) series is the cosine (sine) series with coefficients
 // +-(pi kappa / L) u, one index over.  Written so that the backward transform
 // along ax_j of the other type (DST-I -> DCT-I on the n + 2 nodes, DST-III ->
@@ -435,7 +436,11 @@ __global__ void __launch_bounds__(256) k_grad_prep(PassArgs a) {
       }
     }
     T v = (T)0;
-    if (ok && lam != 0.0) v = (T)(a.norm / lam * a.gp_scale * (double)kap) * src[so];
+    if (ok) {
+      double m = a.gp_scale * (double)kap;
+      if (a.gp_eigen) m = lam == 0.0 ? 0.0 : m * a.norm / lam;
+      v = (T)m * src[so];
+    }
     dst[dof] = v;
   }
 }

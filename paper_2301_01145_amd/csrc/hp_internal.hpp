@@ -100,10 +100,11 @@ struct PassArgs {
   // i (logical axes, extents gp_ext, strides gp_os) is active where
   // s = i - gp_off lies in [0, gp_len) on every axis; it reads the source
   // coefficient src = s (+ gp_shift along ax_j; strides gp_is, extents nunk)
-  // times gp_scale (src + gp_kadd) norm / sum_b lam[b][src_b].  Elements that
-  // are not active, or whose source lies outside, are written as 0.
+  // times gp_scale (src + gp_kadd), and with gp_eigen by norm / sum_b
+  // lam[b][src_b] (0 where that sum is 0).  Elements that are not active, or
+  // whose source lies outside, are written as 0.
   int gp_ext[3], gp_off[3], gp_len[3];
-  int gp_shift, gp_kadd;
+  int gp_shift, gp_kadd, gp_eigen;
   double gp_scale;
   long long gp_is[3], gp_os[3];
 };

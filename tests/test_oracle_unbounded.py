@@ -166,3 +166,28 @@ def test_curl_operator_symmetric():
     lhs = sum(np.sum(Ka[c] * b[c]) for c in range(3))
     rhs = sum(np.sum(a[c] * Kb[c]) for c in range(3))
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_regular_grid_is_the_node_convolution():
+    """REGULAR free space (reading of the node count): N_c + 1 nodes per axis at
+    spacing L / N_c, doubled to 2 (N_c + 1); the solve equals the direct sum of
+    the discrete convolution over those nodes (3D brute force, 2D / 1D direct sums)."""
+    import oracle
+    rng = np.random.default_rng(3)
+    nc = [5, 4, 6]
+    hs = [0.1, 0.13, 0.09]
+    lo = [0.0, -0.2, 0.5]
+    hi = [lo[a] + hs[a] * nc[a] for a in range(3)]
+    f = rng.normal(size=tuple(n + 1 for n in nc))
+    psi, _ = oracle.solve("unbounded", "regular", nc, lo, hi, f, operator="g2", sigma_cells=2.0)
+    assert psi.shape == f.shape
+    ref = brute_force(f, hs, 2.0 * max(hs))
+    assert np.max(np.abs(psi - ref)) <= 1e-13 * np.max(np.abs(ref))
+    for nd, kernel in ((2, "g4"), (1, "spectral")):
+        f = rng.normal(size=tuple(n + 1 for n in nc[:nd]))
+        psi, _ = oracle.solve("unbounded", "regular", nc[:nd], lo[:nd], hi[:nd], f, operator=kernel,
+                              sigma_cells=2.0)
+        pts = [(0, 0), (5, 4), (2, 3)] if nd == 2 else [(0,), (5,), (3,)]
+        got = [psi[p] for p in pts]
+        want = ub.psi_at(pts, f, hs[:nd], 2.0 * max(hs[:nd]), kernel=kernel)
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-14), (nd, got, want)

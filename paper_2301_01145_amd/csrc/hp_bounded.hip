@@ -121,6 +121,25 @@ __device__ __forceinline__ void r2r_fft(C2<T> (&v)[WF<L>::R0], int x, int n, C2<
   else wave_fft<T, L, false>(v, slot, 1, g, tw);
 }
 
+// Runs f with the transform type as a compile-time constant: one branch per
+// FFT (uniform per wavefront) instead of a switch per element.
+template <class F>
+__device__ __forceinline__ void with_xform(int x, F&& f) {
+  switch (x) {
+    case X_DST1: f(std::integral_constant<int, X_DST1>{}); break;
+    case X_DST2: f(std::integral_constant<int, X_DST2>{}); break;
+    case X_DST3: f(std::integral_constant<int, X_DST3>{}); break;
+    case X_DCT1: f(std::integral_constant<int, X_DCT1>{}); break;
+    case X_DCT2: f(std::integral_constant<int, X_DCT2>{}); break;
+    default: f(std::integral_constant<int, X_DCT3>{}); break;
+  }
+}
+
+// Backward transform of the Table 1 pair that starts with forward type x.
+__host__ __device__ constexpr int r2r_partner(int x) {
+  return x == X_DST2 ? X_DST3 : (x == X_DCT2 ? X_DCT3 : x);
+}
+
 // Multiplier norm / (sum of the eigenvalues) at spectral index k along the
 // pencil axis, given the eigenvalue sum `rest` of the other axes.
 // (the eigenvalue sum is formed in FP64; an FP32 plan divides in FP32)
@@ -185,18 +204,21 @@ __global__ void __launch_bounds__(64 * kR2RContigWaves) kb_contig(const PassArgs
     R[n + j] = vb_;
   }
   wave_sync();
-  C2<T> v[R0];
-  r2r_fft<T, L>(v, a.xf, n, slot, g, tw, q, [&](int s, int w) { return R[w * n + s]; });
   T* out = (T*)a.out[0];
   const long long ob = (long long)o * a.out_so + (long long)pa * a.out_sp;
+  with_xform(a.xf, [&](auto XF) {
+    constexpr int X = decltype(XF)::value;
+    C2<T> v[R0];
+    r2r_fft<T, L>(v, X, n, slot, g, tw, q, [&](int s, int w) { return R[w * n + s]; });
 #pragma unroll
-  for (int i = 0; i < R0; ++i) {
-    T oa, obv;
-    const int k = r2r_extract<T>(a.xf, g + G * i, n, v[i], q, oa, obv);
-    if (k < 0) continue;
-    if (valid) out[ob + (long long)k * a.out_sj] = oa;
-    if (vb) out[ob + a.out_sp + (long long)k * a.out_sj] = obv;
-  }
+    for (int i = 0; i < R0; ++i) {
+      T oa, obv;
+      const int k = r2r_extract<T>(X, g + G * i, n, v[i], q, oa, obv);
+      if (k < 0) continue;
+      if (valid) out[ob + (long long)k * a.out_sj] = oa;
+      if (vb) out[ob + a.out_sp + (long long)k * a.out_sj] = obv;
+    }
+  });
 }
 
 // ------------------------------------------- strided one-way and sandwich
@@ -281,34 +303,38 @@ __global__ void __launch_bounds__(64 * W) kb_strided(const PassArgs a) {
       const int f = wave * PPW + qq;  // pair: columns 2f, 2f + 1
       T* ca = tile + 2 * f;
       auto get = [&](int s, int w) { return ca[s * TS + w]; };
-      C2<T> v[R0];
-      r2r_fft<T, L>(v, a.xf, n, slot, g, tw, q, get);
-      int x_out = a.xf;
-      if (SW) {
-        // spectra times the multiplier, back into the pair's columns
-        const int pa = min(p0 + 2 * f, a.Np - 1), pb = min(p0 + 2 * f + 1, a.Np - 1);
-        const double ra = eigen_rest(a, pa, o), rb = eigen_rest(a, pb, o);
+      // the sandwich's backward type is the Table 1 partner of its forward
+      // type (checked at launch)
+      with_xform(a.xf, [&](auto XF) {
+        constexpr int XFc = decltype(XF)::value;
+        constexpr int XO = SW ? r2r_partner(XFc) : XFc;
+        C2<T> v[R0];
+        r2r_fft<T, L>(v, XFc, n, slot, g, tw, q, get);
+        if constexpr (SW) {
+          // spectra times the multiplier, back into the pair's columns
+          const int pa = min(p0 + 2 * f, a.Np - 1), pb = min(p0 + 2 * f + 1, a.Np - 1);
+          const double ra = eigen_rest(a, pa, o), rb = eigen_rest(a, pb, o);
+#pragma unroll
+          for (int i = 0; i < R0; ++i) {
+            T sa, sb;
+            const int k = r2r_extract<T>(XFc, g + G * i, n, v[i], q, sa, sb);
+            if (k < 0) continue;
+            ca[k * TS] = sa * eigen_mult<T>(a, k, ra);
+            ca[k * TS + 1] = sb * eigen_mult<T>(a, k, rb);
+          }
+          wave_sync();
+          r2r_fft<T, L>(v, XO, n, slot, g, tw, q, get);
+        }
+        // outputs into the pair's columns (the inputs were consumed above)
 #pragma unroll
         for (int i = 0; i < R0; ++i) {
-          T sa, sb;
-          const int k = r2r_extract<T>(a.xf, g + G * i, n, v[i], q, sa, sb);
+          T oa, obv;
+          const int k = r2r_extract<T>(XO, g + G * i, n, v[i], q, oa, obv);
           if (k < 0) continue;
-          ca[k * TS] = sa * eigen_mult<T>(a, k, ra);
-          ca[k * TS + 1] = sb * eigen_mult<T>(a, k, rb);
+          ca[k * TS] = oa;
+          ca[k * TS + 1] = obv;
         }
-        wave_sync();
-        r2r_fft<T, L>(v, a.xb, n, slot, g, tw, q, get);
-        x_out = a.xb;
-      }
-      // outputs into the pair's columns (the inputs were consumed above)
-#pragma unroll
-      for (int i = 0; i < R0; ++i) {
-        T oa, obv;
-        const int k = r2r_extract<T>(x_out, g + G * i, n, v[i], q, oa, obv);
-        if (k < 0) continue;
-        ca[k * TS] = oa;
-        ca[k * TS + 1] = obv;
-      }
+      });
       wave_sync();  // the slot is reused by the next pair
     }
     __syncthreads();
@@ -362,6 +388,7 @@ hipError_t launch_bounded_L(const PassArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(((a.Np + P - 1) / P) * a.No));
   const int ntiles = (int)grid.x;
   if (a.fast == FAST_R2R_SW) {
+    if (a.xb != r2r_partner(a.xf)) return hipErrorInvalidValue;
     allow_lds<kb_strided<T, L, P, W, true, true>>();
     const int nb = persistent_grid<kb_strided<T, L, P, W, true, true>>(64 * W, lds, ntiles);
     if (ntiles > 4 * nb && !std::getenv("HP_R2R_NOPERS")) {

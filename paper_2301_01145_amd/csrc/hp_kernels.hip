@@ -191,8 +191,11 @@ __device__ void load_half(C2<T>* R, const void* src, const PassArgs& a, const Ti
 }
 
 // Build the complex FFT input Z[f][m] (f = pencil pair) from real pencils R.
-template <typename T>
-__device__ void build_from_real(C2<T>* Z, const T* R, int x, const PassArgs& a, int nfft) {
+// (XC: the transform type as a compile-time constant; build_from_real below
+// branches once per call instead of once per element)
+template <typename T, int XC>
+__device__ void build_from_real_x(C2<T>* Z, const T* R, const PassArgs& a, int nfft) {
+  constexpr int x = XC;
   const int L = a.L, n = a.n, cnt = a.nin;
   const C2<T>* q = (const C2<T>*)a.qtw;
   for (int e = threadIdx.x; e < nfft * L; e += kThreads) {
@@ -234,6 +237,21 @@ __device__ void build_from_real(C2<T>* Z, const T* R, int x, const PassArgs& a, 
         break;
     }
     Z[e] = z;
+  }
+}
+
+template <typename T>
+__device__ void build_from_real(C2<T>* Z, const T* R, int x, const PassArgs& a, int nfft) {
+  switch (x) {
+    case X_R2C: build_from_real_x<T, X_R2C>(Z, R, a, nfft); break;
+    case X_PAIR_F: build_from_real_x<T, X_PAIR_F>(Z, R, a, nfft); break;
+    case X_DST1: build_from_real_x<T, X_DST1>(Z, R, a, nfft); break;
+    case X_DST2: build_from_real_x<T, X_DST2>(Z, R, a, nfft); break;
+    case X_DST3: build_from_real_x<T, X_DST3>(Z, R, a, nfft); break;
+    case X_DCT1: build_from_real_x<T, X_DCT1>(Z, R, a, nfft); break;
+    case X_DCT2: build_from_real_x<T, X_DCT2>(Z, R, a, nfft); break;
+    case X_DCT3: build_from_real_x<T, X_DCT3>(Z, R, a, nfft); break;
+    default: build_from_real_x<T, -1>(Z, R, a, nfft); break;
   }
 }
 
@@ -311,8 +329,9 @@ __device__ __forceinline__ C2<T> half_out(const C2<T>* Z, const PassArgs& a, int
   return {s.re * (T)0.5, s.im * (T)0.5};
 }
 
-template <typename T>
-__device__ void store_out(const C2<T>* Z, int x, void* dst, const PassArgs& a, const Tile& t) {
+template <typename T, int XC>
+__device__ void store_out_x(const C2<T>* Z, void* dst, const PassArgs& a, const Tile& t) {
+  constexpr int x = XC;
   const int cnt = a.nout;
   const int total = a.P * cnt;
   const long long obase = (long long)t.o * a.out_so + (long long)t.p0 * a.out_sp;
@@ -328,6 +347,24 @@ __device__ void store_out(const C2<T>* Z, int x, void* dst, const PassArgs& a, c
     } else {
       ((T*)dst)[off] = real_out(Z, x, a, p, k);
     }
+  }
+}
+
+template <typename T>
+__device__ void store_out(const C2<T>* Z, int x, void* dst, const PassArgs& a, const Tile& t) {
+  switch (x) {
+    case X_C2C_F: store_out_x<T, X_C2C_F>(Z, dst, a, t); break;
+    case X_C2C_B: store_out_x<T, X_C2C_B>(Z, dst, a, t); break;
+    case X_R2C: store_out_x<T, X_R2C>(Z, dst, a, t); break;
+    case X_C2R: store_out_x<T, X_C2R>(Z, dst, a, t); break;
+    case X_PAIR_B: store_out_x<T, X_PAIR_B>(Z, dst, a, t); break;
+    case X_DST1: store_out_x<T, X_DST1>(Z, dst, a, t); break;
+    case X_DST2: store_out_x<T, X_DST2>(Z, dst, a, t); break;
+    case X_DST3: store_out_x<T, X_DST3>(Z, dst, a, t); break;
+    case X_DCT1: store_out_x<T, X_DCT1>(Z, dst, a, t); break;
+    case X_DCT2: store_out_x<T, X_DCT2>(Z, dst, a, t); break;
+    case X_DCT3: store_out_x<T, X_DCT3>(Z, dst, a, t); break;
+    default: store_out_x<T, -1>(Z, dst, a, t); break;
   }
 }
 

@@ -93,8 +93,7 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     elif diff == "curl":
         if bc != "periodic" or not vector or nd != 3:
             raise NotImplementedError("bounded curl: periodic 3D vector only")
-        g = [bounded.periodic_gradient(p, lengths) for p in psi]
-        derivs = [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+        derivs = bounded.periodic_curl(psi, lengths)
     elif diff == "div":
         if bc != "periodic" or not vector or nd != 3:
             raise NotImplementedError("bounded divergence: periodic 3D vector only")

@@ -192,6 +192,15 @@ def periodic_gradient(psi, lengths):
     return out
 
 
+def periodic_curl(psi, lengths):
+    """Spectral curl u = i k x psi^ of a periodic 3D vector field (Section
+    2.3.3, eq. ft_sd; the curl output of Section 4.3, eq. poisscurl):
+    u_x = d_y psi_z - d_z psi_y, u_y = d_z psi_x - d_x psi_z,
+    u_z = d_x psi_y - d_y psi_x, each derivative from periodic_gradient."""
+    g = [periodic_gradient(p, lengths) for p in psi]
+    return [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+
+
 def eigenfunctions(bc, n, length, x):
     """The n eigenfunctions of Table 1 along one axis at positions x measured
     from X_l, and their derivatives: sin(pi (k+1) x / L) for Dirichlet,

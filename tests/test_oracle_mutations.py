@@ -158,3 +158,38 @@ def test_1d_hermite_correction_sign_is_caught(monkeypatch):
 
     monkeypatch.setattr(ub, "green_gauss_1d", wrong)
     _fails(pk.test_1d_gauss_kernel_second_derivative_is_its_source, 4)
+
+
+def test_periodic_curl_component_swap_is_caught(monkeypatch):
+    # u_y and u_z exchanged in the periodic 3D curl
+    orig = bounded.periodic_curl
+
+    def wrong(psi, lengths):
+        u = orig(psi, lengths)
+        return [u[0], u[2], u[1]]
+
+    monkeypatch.setattr(bounded, "periodic_curl", wrong)
+    _fails(po.test_periodic_3d_curl_closed_form)
+
+
+def test_periodic_curl_sign_is_caught(monkeypatch):
+    # u_x = d_z psi_y - d_y psi_z (one component with its sign flipped)
+    orig = bounded.periodic_curl
+
+    def wrong(psi, lengths):
+        u = orig(psi, lengths)
+        return [-u[0], u[1], u[2]]
+
+    monkeypatch.setattr(bounded, "periodic_curl", wrong)
+    _fails(po.test_periodic_3d_curl_closed_form)
+
+
+def test_periodic_gradient_axis_is_caught(monkeypatch):
+    # the wavenumber of axis 1 used for axis 2 (anisotropic box)
+    orig = bounded.periodic_gradient
+
+    def wrong(psi, lengths):
+        return orig(psi, [lengths[0], lengths[1], lengths[1]] if len(lengths) == 3 else lengths)
+
+    monkeypatch.setattr(bounded, "periodic_gradient", wrong)
+    _fails(po.test_periodic_3d_gradient_closed_form)

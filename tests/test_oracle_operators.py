@@ -154,3 +154,50 @@ def test_unbounded_2d_curl_transpose():
     lhs = np.sum(Ka_psi * b_psi) + sum(np.sum(x * y) for x, y in zip(Ka_d, b_d))
     rhs = np.sum(a * ub.adjoint_unbounded(b_psi, b_d, hs, 0.2, "curl"))
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def _vector_modes_3d(seed, n, lo, hi, per_comp):
+    """A 3-component source of Fourier modes below the Nyquist index on an
+    anisotropic periodic box, with the closed forms of the PS solution per
+    mode: f_c = A cos(th), th = k.(x - lo) + phase; psi_c = -A cos(th) / |k|^2
+    and d_a psi_c = A k_a sin(th) / |k|^2 (Section 2.2, eq. spect_sol with the
+    PS multiplier -|k|^2; eq. ft_sd for the derivative)."""
+    rng = np.random.default_rng(seed)
+    L = [hi[a] - lo[a] for a in range(3)]
+    X = _grid(n, lo, hi)
+    f = np.zeros((3,) + tuple(n))
+    psi = np.zeros_like(f)
+    dpsi = np.zeros((3, 3) + tuple(n))  # [component][axis]
+    for c in range(3):
+        for m, A, ph in _modes(rng, n, L, per_comp):
+            k = [2 * np.pi * m[a] / L[a] for a in range(3)]
+            th = sum(k[a] * (X[a] - lo[a]) for a in range(3)) + ph
+            k2 = sum(v * v for v in k)
+            f[c] += A * np.cos(th)
+            psi[c] -= A * np.cos(th) / k2
+            for a in range(3):
+                dpsi[c, a] += A * k[a] * np.sin(th) / k2
+    return f, psi, dpsi
+
+
+def test_periodic_3d_curl_closed_form():
+    # u = curl psi per mode: u_x = d_y psi_z - d_z psi_y, u_y = d_z psi_x -
+    # d_x psi_z, u_z = d_x psi_y - d_y psi_x (Section 4.3, eq. poisscurl)
+    n, lo, hi = (12, 10, 14), [0.0, -0.4, 0.3], [1.0, 1.1, 1.1]
+    f, psi_ref, d = _vector_modes_3d(41, n, lo, hi, 4)
+    psi, u = oracle.solve("periodic", "staggered", list(n), lo, hi, f, operator="ps", diff="curl")
+    ref = [d[2, 1] - d[1, 2], d[0, 2] - d[2, 0], d[1, 0] - d[0, 1]]
+    assert np.max(np.abs(psi - psi_ref)) <= 1e-12 * np.max(np.abs(psi_ref))
+    for c in range(3):
+        scale = max(np.max(np.abs(r)) for r in ref)
+        assert np.max(np.abs(u[c] - ref[c])) <= 1e-12 * scale, c
+
+
+def test_periodic_3d_gradient_closed_form():
+    n, lo, hi = (10, 12, 8), [0.2, 0.0, -1.0], [1.0, 1.7, 0.5]
+    f, psi_ref, d = _vector_modes_3d(42, n, lo, hi, 5)
+    psi, g = oracle.solve("periodic", "staggered", list(n), lo, hi, f[0], operator="ps", diff="grad")
+    assert np.max(np.abs(psi - psi_ref[0])) <= 1e-12 * np.max(np.abs(psi_ref[0]))
+    scale = np.max(np.abs(d[0]))
+    for a in range(3):
+        assert np.max(np.abs(g[a] - d[0, a])) <= 1e-12 * scale, a

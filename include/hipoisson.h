@@ -223,6 +223,24 @@ HP_API hp_status hp_autotune(hp_plan plan, int reps);
 /* Numeric plan properties (HP_Q_* keys). */
 HP_API hp_status hp_query(hp_plan plan, int what, double* value);
 
+/* The zero mode of HP_Q_ZERO_MODE without allocation or host
+ * synchronisation, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Writes out[c], c < ncomp, for every component of the bound source (device
+ * memory owned by the caller, ncomp doubles): the k = 0 coefficient of its
+ * forward transform over that of a field of ones, 0 for BCs without a zero
+ * eigenvalue; out[] holds the same values as the per-component results of
+ * HP_Q_ZERO_MODE, which returns the one of largest magnitude.  Runs
+ * asynchronously on the plan's stream (two small kernels per component, no
+ * memset, so it can be captured).  Its partial sums (256 FP64 values per
+ * component, 3 components at most: 6 KiB) live in a static device array of
+ * the library, one per GPU, held until the process ends; this call allocates
+ * nothing.  Calls that overlap on one GPU (other streams, other threads) share
+ * that array and race.  HP_E_ARG for a NULL plan or out or a batched plan,
+ * HP_E_STATE if an input is not set, HP_E_UNSUPPORTED above 3 components,
+ * HP_E_DEVICE if a launch fails. */
+HP_API hp_status hp_zero_mode_noalloc(hp_plan plan, double* out);
+
 /* Release the plan and everything it owns (synchronises its stream). */
 HP_API hp_status hp_plan_destroy(hp_plan plan);
 

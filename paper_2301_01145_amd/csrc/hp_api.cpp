@@ -1710,6 +1710,22 @@ hp_status run_passes(hp_plan p, const std::vector<PassRec>& ps) {
   return HP_OK;
 }
 
+// Arguments of the zero-mode reduction of component c: the boundary terms of
+// the first pass, DCT-I end weights (trap) and the total weight W, the k = 0
+// coefficient of the forward transform of a field of ones.
+void zero_mode_setup(const Problem& P, int c, PassArgs& a, int trap[3], double* W) {
+  a = PassArgs{};
+  a.ax_j = 0; a.ax_p = 1; a.ax_o = 2;
+  for (int b = 0; b < 3; ++b) a.nunk[b] = b < P.nd ? P.n[b] : 0;
+  fill_face_terms(P, c, a);
+  trap[0] = trap[1] = trap[2] = 0;
+  *W = 1.0;
+  for (int b = 0; b < P.nd; ++b) {
+    trap[b] = (P.d.bc == HP_NEUMANN && P.d.grid == HP_REGULAR) ? 1 : 0;
+    *W *= trap[b] ? (double)(P.n[b] - 1) : (double)P.n[b];
+  }
+}
+
 Problem* get_problem(hp_plan p, int problem) {
   if (!p || problem < 0 || problem >= (int)p->probs.size()) return nullptr;
   return &p->probs[problem];
@@ -2046,21 +2062,15 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
       if (plan->batched) return fail(plan, HP_E_ARG, "zero mode: single-problem plans");
       *value = 0.0;
       if (P.d.bc != HP_PERIODIC && P.d.bc != HP_NEUMANN) return HP_OK;
-      const int nb = 256;
+      const int nb = kZeroModeBlocks;
       if (!plan->zm_partial) HP_TRY(dev_alloc(plan, nb * sizeof(double), (void**)&plan->zm_partial));
       double best = 0.0;
       for (int c = 0; c < P.ncomp; ++c) {
         if (!P.in[c]) return fail(plan, HP_E_STATE, "input component " + std::to_string(c) + " not set");
-        PassArgs a{};
-        a.ax_j = 0; a.ax_p = 1; a.ax_o = 2;
-        for (int b = 0; b < 3; ++b) a.nunk[b] = b < P.nd ? P.n[b] : 0;
-        fill_face_terms(P, c, a);
-        int trap[3] = {0, 0, 0};
-        double W = 1.0;
-        for (int b = 0; b < P.nd; ++b) {
-          trap[b] = (P.d.bc == HP_NEUMANN && P.d.grid == HP_REGULAR) ? 1 : 0;
-          W *= trap[b] ? (double)(P.n[b] - 1) : (double)P.n[b];
-        }
+        PassArgs a;
+        int trap[3];
+        double W;
+        zero_mode_setup(P, c, a, trap, &W);
         HP_HIP(plan, launch_zero_mode(a, P.in[c], P.n, trap, plan->zm_partial, nb, plan->prec, plan->stream));
         double part[nb];
         HP_HIP(plan, hipMemcpyAsync(part, plan->zm_partial, sizeof part, hipMemcpyDeviceToHost, plan->stream));
@@ -2098,6 +2108,28 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
     default:
       return fail(plan, HP_E_ARG, "unknown query");
   }
+}
+
+hp_status hp_zero_mode_noalloc(hp_plan plan, double* out) {
+  if (!plan || !out) return HP_E_ARG;
+  if (plan->batched) return fail(plan, HP_E_ARG, "zero mode: single-problem plans");
+  Problem& P = plan->probs[0];
+  if (P.ncomp > kZeroModeMaxComp)
+    return fail(plan, HP_E_UNSUPPORTED, "zero mode without allocation: at most " +
+                                            std::to_string(kZeroModeMaxComp) + " components");
+  PassArgs a[kZeroModeMaxComp];
+  const void* f[kZeroModeMaxComp] = {};
+  double W[kZeroModeMaxComp] = {0.0, 0.0, 0.0};
+  int trap[3] = {0, 0, 0};
+  const bool has_zero = P.d.bc == HP_PERIODIC || P.d.bc == HP_NEUMANN;
+  for (int c = 0; c < P.ncomp; ++c) {
+    if (!P.in[c]) return fail(plan, HP_E_STATE, "input component " + std::to_string(c) + " not set");
+    f[c] = P.in[c];
+    if (has_zero) zero_mode_setup(P, c, a[c], trap, &W[c]);
+    else a[c] = PassArgs{};  // W = 0: only zeros are written
+  }
+  HP_HIP(plan, launch_zero_mode_noalloc(a, f, P.ncomp, P.n, trap, W, out, plan->prec, plan->stream));
+  return HP_OK;
 }
 
 hp_status hp_plan_destroy(hp_plan plan) {

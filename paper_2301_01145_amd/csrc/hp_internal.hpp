@@ -178,6 +178,17 @@ struct BatchItem {
 // trap[a] set (DCT-I), else 1.
 hipError_t launch_zero_mode(const PassArgs& a, const void* f, const int n[3], const int trap[3],
                             double* partial, int nb, int prec, hipStream_t s);
+// Allocation-free form of the same query: the partial sums of component c
+// (kZeroModeBlocks of them) go to a static per-device scratch array, and a
+// second kernel writes out[c] = (their sum in block order) / W[c] (0 where
+// W[c] = 0) to caller-owned device memory.  Stream-ordered, no host
+// synchronisation, no allocation; concurrent calls on one device share the
+// scratch array and race.
+constexpr int kZeroModeBlocks = 256;
+constexpr int kZeroModeMaxComp = 3;
+hipError_t launch_zero_mode_noalloc(const PassArgs* a, const void* const* f, int ncomp,
+                                    const int n[3], const int trap[3], const double* W,
+                                    double* out, int prec, hipStream_t s);
 // Persistent batched solve: counters[0] is the work-queue head, counters[1 + i]
 // the completed tiles of pass i (zeroed by the launch itself); err[0] is set
 // to 1 if a dependency wait exceeds its spin limit (the item is then skipped).

@@ -13,6 +13,8 @@
 // spectrum, Section 2.2 step 2), applies the spectral derivative (step 3,
 // eq. ft_sd), transforms back and stores, so the spectrum of that axis never
 // leaves LDS.
+#include <mutex>
+
 #include "hp_device.hpp"
 #include "hp_faces.hpp"
 #include "hp_internal.hpp"
@@ -952,6 +954,77 @@ hipError_t launch_zero_mode(const PassArgs& a, const void* f, const int n[3], co
   else
     hipLaunchKernelGGL(k_zero_mode<double>, dim3(nb), dim3(256), 0, s, a, (const double*)f, n[0],
                        n[1], n[2], trap[0], trap[1], trap[2], partial);
+  return hipGetLastError();
+}
+
+// ------------------------------------------ allocation-free zero-mode query
+// The per-block partial sums of every component live in this file-scope
+// device array instead of plan memory.  Each device holds its own copy (at
+// its own address) until the process ends; in host code the name is only a
+// stand-in, so host code uses the address that hipGetSymbolAddress returns
+// for the device, never the name itself.
+static __device__ __align__(256) double scratch[kZeroModeMaxComp * kZeroModeBlocks];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t zero_mode_scratch(hipStream_t s, double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipStreamGetDevice(s, &dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (double*)g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// out[c] = (partials of component c summed in block order) / W[c]; one
+// thread per component, so the sum is the same as a host loop over them.
+__global__ void k_zero_mode_finish(const double* partial, int nb, int ncomp, double W0, double W1,
+                                   double W2, double* out) {
+  const int c = threadIdx.x;
+  if (c >= ncomp) return;
+  const double W = c == 0 ? W0 : (c == 1 ? W1 : W2);
+  double sum = 0.0;
+  if (W != 0.0) {
+    for (int i = 0; i < nb; ++i) sum += partial[(long long)c * nb + i];
+    sum /= W;
+  }
+  out[c] = sum;
+}
+
+hipError_t launch_zero_mode_noalloc(const PassArgs* a, const void* const* f, int ncomp,
+                                    const int n[3], const int trap[3], const double* W,
+                                    double* out, int prec, hipStream_t s) {
+  if (ncomp < 1 || ncomp > kZeroModeMaxComp) return hipErrorInvalidValue;
+  double* partial = nullptr;
+  hipError_t e = zero_mode_scratch(s, &partial);
+  if (e != hipSuccess) return e;
+  for (int c = 0; c < ncomp; ++c) {
+    if (W[c] == 0.0) continue;  // no zero eigenvalue: the finish kernel writes 0
+    e = launch_zero_mode(a[c], f[c], n, trap, partial + (long long)c * kZeroModeBlocks,
+                         kZeroModeBlocks, prec, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_zero_mode_finish, dim3(1), dim3(64), 0, s, partial, kZeroModeBlocks, ncomp,
+                     W[0], ncomp > 1 ? W[1] : 0.0, ncomp > 2 ? W[2] : 0.0, out);
   return hipGetLastError();
 }
 

@@ -78,3 +78,33 @@ def test_gradient_vs_oracle_transpose():
     ref = ub.adjoint_unbounded(None, list(gu), [h] * 3, 2 * h, "curl")
     assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-5
     s.close()
+
+
+def test_gradient_128_vs_oracle_every_element():
+    """The 128^3 FP32 gradient of L = sum |curl psi(f) - u_t|^2 (16 rings,
+    seeds 6 and 7), every element against the oracle's transposed map applied
+    to the oracle's own upstream gradient 2 (u(f) - u_t), all in FP64."""
+    import torch
+    import oracle
+    from oracle import unbounded as ub
+    from paper_2301_01145_amd.autograd import poisson_solve
+    n = 128
+    s, f, ft, dtype = _setup(n, "f32", 6, 7, 16)
+    f = f.astype(np.float32).astype(np.float64)
+    _, ut = oracle.solve("unbounded", "staggered", [n] * 3, [0, 0, 0], [1, 1, 1], ft, diff="curl")
+    _, uf = oracle.solve("unbounded", "staggered", [n] * 3, [0, 0, 0], [1, 1, 1], f, diff="curl")
+    fin = [torch.as_tensor(f[c], dtype=dtype, device="cuda").requires_grad_(True) for c in range(3)]
+    _, u = poisson_solve(s, fin)
+    loss = sum(torch.sum((u[c] - torch.as_tensor(ut[c], dtype=dtype, device="cuda")) ** 2)
+               for c in range(3))
+    loss.backward()
+    g = np.stack([x.grad.double().cpu().numpy() for x in fin])
+    h = 1.0 / n
+    gu = [2.0 * (uf[c] - ut[c]) for c in range(3)]
+    ref = ub.adjoint_unbounded(None, gu, [h] * 3, 2 * h, "curl")
+    for c in range(3):
+        err = np.linalg.norm(g[c] - ref[c]) / np.linalg.norm(ref[c])
+        emax = np.max(np.abs(g[c] - ref[c])) / np.max(np.abs(ref[c]))
+        print(f"128^3 gradient comp {c}: rel-L2 {err:.2e} rel-max {emax:.2e}", flush=True)
+        assert err <= 1e-5 and emax <= 1e-4, c
+    s.close()

@@ -8,6 +8,8 @@
   (tests/golden/unbounded256_curl_samples.npz, written by
   tests/golden/make_unbounded_samples.py from oracle/), full-field L2 norms,
   and psi at 8 points by the oracle's direct sum (independent of the file).
+* The same 256^3 curl solve, FP32 and FP64: every element of psi and the curl
+  against one FP64 oracle solve (computed once per session).
 * The Gaussian-blob twin at 256^3: psi and curl against the closed form.
 * 3D free-space 128^3 (doubled 256^3) curl with the G2, G6, G10 and spectral
   kernels: every element against the oracle.
@@ -105,6 +107,29 @@ def test_unbounded_256_curl_samples(prec):
         ref = ub.psi_at(pts, f[c].astype(np.float64), [h] * 3, 2 * h)
         got = np.array([float(psi[c][p]) for p in pts])
         assert np.max(np.abs(got - ref)) <= l2 * 10 * g["psi_absmax"][c], c
+
+
+@pytest.fixture(scope="module")
+def oracle256():
+    """One FP64 oracle solve of the 256^3 ring workload (psi and curl)."""
+    import oracle
+    from workloads import vortex_rings
+    f = vortex_rings(256, seed=4, count=32).astype(np.float32).astype(np.float64)
+    return oracle.solve("unbounded", "staggered", [256] * 3, [0, 0, 0], [1, 1, 1], f, diff="curl")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_unbounded_256_curl_every_element(prec, oracle256):
+    ref_psi, ref_u = oracle256
+    f, psi, u = _unbounded256(prec)
+    l2, mx = TOL[prec]
+    for c in range(3):
+        gp = psi[c].double().cpu().numpy()
+        gu = u[c].double().cpu().numpy()
+        print(f"256^3 {prec} comp {c}: psi rel-L2 {rel_l2(gp, ref_psi[c]):.2e} "
+              f"curl rel-L2 {rel_l2(gu, ref_u[c]):.2e}", flush=True)
+        assert rel_l2(gp, ref_psi[c]) <= l2 and rel_max(gp, ref_psi[c]) <= mx, ("psi", c)
+        assert rel_l2(gu, ref_u[c]) <= l2 and rel_max(gu, ref_u[c]) <= mx, ("curl", c)
 
 
 def _blob_fields(n, s_blob, sigma, params, x):

@@ -192,8 +192,6 @@ UNB = [([8, 10, 12], 1, "none"), ([8, 10, 12], 1, "grad"), ([8, 10, 12], 3, "cur
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("grid", ["staggered", "regular"])
 def test_unbounded(nc, ncomp, diff, prec, grid):
-    if prec == "f64" and max(nc) == 512:
-        pytest.skip("FP64 at doubled length 1024 runs on the general passes (LDS)")
     if grid == "regular" and nc[0] != 8:
         pytest.skip("regular grid: one size")
     if grid == "regular":

@@ -55,24 +55,65 @@ def sandwich_flops(n):
     return (M // 2 + 1) * M * per_pencil
 
 
-def measured_traffic(pass_name, n):
-    """HBM bytes per launch of `pass_name` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy-kernel
-    factors), or None when there is none for these sources."""
-    path = os.path.join(PROFILES, f"unbounded{n}_curl_fp32_hbm_counters.md")
+def _profile_lines(path):
+    """(source digest, {key: [values]}) of the machine-readable lines of a
+    committed profile summary: `source_sha256: <hex>` and `<key>: <pass> <v>...`."""
+    digest, rows = None, {}
     if not os.path.exists(path):
-        return None
-    digest, traffic = None, {}
+        return None, rows
     with open(path) as fh:
         for line in fh:
             t = line.strip().strip("`").split()
             if len(t) == 2 and t[0] == "source_sha256:":
                 digest = t[1]
-            elif len(t) == 4 and t[0] == "traffic_bytes:":
-                traffic[t[1]] = float(t[2]) + float(t[3])
+            elif len(t) >= 3 and t[0] in ("traffic_bytes:", "kernel_avg_us:"):
+                rows.setdefault(t[0][:-1], {})[t[1]] = [float(v) for v in t[2:]]
+    return digest, rows
+
+
+def measured_traffic(pass_name, n):
+    """HBM bytes per launch of `pass_name` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy-kernel
+    factors), or None when there is none for these sources."""
+    digest, rows = _profile_lines(os.path.join(PROFILES, f"unbounded{n}_curl_fp32_hbm_counters.md"))
     if digest != kernel_source_digest():
         return None
-    return traffic.get(pass_name)
+    v = rows.get("traffic_bytes", {}).get(pass_name)
+    return None if v is None else v[0] + v[1]
+
+
+def profiled_kernel_us(pass_name, n):
+    """Average duration (us) of `pass_name`'s kernel in the committed
+    rocprofv3 --kernel-trace --stats summary of this benchmark, or None when
+    there is none for these sources."""
+    digest, rows = _profile_lines(os.path.join(PROFILES, f"unbounded{n}_curl_fp32_kernel_trace.md"))
+    if digest != kernel_source_digest():
+        return None
+    v = rows.get("kernel_avg_us", {}).get(pass_name)
+    return None if v is None else v[0]
+
+
+def survey_model_bytes(n, es=4):
+    """The pruned five-pass byte model with six stored spectral fields between
+    the x pass and the backward y pass and the Green's octant in FP64: per
+    component, A = (n+1) n n complex half-spectrum rows (P1 out), B = (n+1)
+    2n n complex (P2 out); P1 3 (n^3 + A), P2 3 (A + B), P3 (3 + 6) B + octant,
+    P4 6 (B + A), P5 6 (A + n^3)."""
+    K = n + 1
+    real = n ** 3 * es
+    A = K * n * n * 2 * es
+    B = K * 2 * n * n * 2 * es
+    octant = K ** 3 * 8
+    return 3 * (real + A) + 3 * (A + B) + 9 * B + octant + 6 * (B + A) + 6 * (A + real)
+
+
+def _profile_view(name, n, pbytes):
+    us = profiled_kernel_us(name, n)
+    if us is None:
+        return None
+    gbs = pbytes / (us * 1e-6) / 1e9
+    return {"kernel_avg_us": us, "achieved": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "source": f"profiles/unbounded{n}_curl_fp32_kernel_trace.md"}
 
 
 def parse():
@@ -277,39 +318,48 @@ def other_workloads(steps, warmup):
     return res
 
 
+def _device_copy(src, dst):
+    from paper_2301_01145_amd import _lib
+    import torch
+    _lib.hp_device_copy(src.data_ptr(), dst.data_ptr(), src.numel() * src.element_size(),
+                        torch.cuda.current_stream().cuda_stream)
+
+
 def copy_reference():
-    """A plain device-to-device copy of known size, to calibrate FETCH_SIZE /
-    WRITE_SIZE counters against bytes actually moved."""
+    """A plain device copy of known size (the library's 16-byte streaming copy
+    kernel, k_copy16), to calibrate FETCH_SIZE / WRITE_SIZE counters against
+    bytes actually moved."""
     import torch
     n = 1 << 28  # 2^28 floats = 1 GiB
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
-        dst.copy_(src)
+        _device_copy(src, dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 3}), flush=True)
 
 
 def copy_ceiling(warmup=3, reps=20):
-    """Measured HBM ceiling of a plain device-to-device copy (torch copy_ of
-    1 GiB): bytes read + written per copy over its mean HIP-event time."""
+    """Measured HBM ceiling of a plain streaming copy (the library's k_copy16,
+    1 GiB each way): bytes read + written per copy over its mean HIP-event time."""
     import torch
     n = 1 << 28
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(warmup):
-        dst.copy_(src)
+        _device_copy(src, dst)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        _device_copy(src, dst)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(src, dst))
     del src, dst
-    return 2.0 * 4 * n / (ms * 1e-3) / 1e9
+    return 2.0 * 4 * n / (ms * 1e-3) / 1e9, ok
 
 
 def timed_solves(solver, steps, warmup):
@@ -475,9 +525,18 @@ def main():
                    "grid": n, "components": 3, "outputs": 6},
         "model_gbs": r32["model_bytes"] / (r32["ms"] * 1e-3) / 1e9,
         "model_bytes_per_solve": r32["model_bytes"],
+        # the same solve priced with six stored spectral fields between the x and
+        # backward-y passes and an FP64 Green's octant (this library stores five,
+        # and the octant in the solve precision)
+        "model_bytes_six_field_fp64_green": survey_model_bytes(n),
+        "model_gbs_six_field_fp64_green": survey_model_bytes(n) / (r32["ms"] * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n),
                      "kernel": name, "kernel_ms": pms, "kernel_bytes": pbytes,
+                     # the same bytes over the kernel's average in the committed
+                     # rocprofv3 kernel trace of this benchmark (null: none for
+                     # these sources)
+                     "profile": _profile_view(name, n, pbytes),
                      # the same pass against the vector ALU (it issues VALU instructions
                      # about three quarters of its cycles; profiles/ SQ counters)
                      "alu_view": ({"bound": "alu", "achieved": sandwich_flops(n) / (pms * 1e-3) / 1e12,
@@ -507,8 +566,9 @@ def main():
     out["graph_ms_per_step"] = _time_graph(s.run, side, args.steps, args.warmup)
     s.close()
     # the same bytes against what a plain copy reaches on this device
-    cgbs = copy_ceiling()
-    out["copy_ceiling"] = {"copy_gbs": cgbs, "model_gbs_frac": out["model_gbs"] / cgbs,
+    cgbs, cok = copy_ceiling()
+    out["copy_ceiling"] = {"copy_gbs": cgbs, "kernel": "k_copy16 (16-byte loads/stores, 1 GiB each way)",
+                           "copy_correct": cok, "model_gbs_frac": out["model_gbs"] / cgbs,
                            "dominant_kernel_frac": out["roofline"]["achieved"] / cgbs}
     if not args.no_others:
         out["other_workloads"] = other_workloads(max(5, args.steps // 2), args.warmup)

@@ -37,6 +37,7 @@
 #ifndef HIPOISSON_H
 #define HIPOISSON_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #if defined(__GNUC__) || defined(__clang__)
@@ -222,6 +223,13 @@ HP_API hp_status hp_autotune(hp_plan plan, int reps);
 
 /* Numeric plan properties (HP_Q_* keys). */
 HP_API hp_status hp_query(hp_plan plan, int what, double* value);
+
+/* Measurement utility (not a step of the method): copy `bytes` of device
+ * memory from src to dst on `stream` with a plain streaming kernel (16-byte
+ * loads and stores), the reference rate of a kernel that only moves data,
+ * for stating the solve's bandwidth against what the device reaches.  Both
+ * pointers 16-byte aligned and not overlapping; HP_E_ARG otherwise. */
+HP_API hp_status hp_device_copy(const void* src, void* dst, size_t bytes, hp_stream stream);
 
 /* The zero mode of HP_Q_ZERO_MODE without allocation or host
  * synchronisation, for callers that cannot allocate device memory: code under

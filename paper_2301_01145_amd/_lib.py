@@ -28,7 +28,7 @@ EXPORTS = (
     "hp_set_input", "hp_set_boundary", "hp_bind_output", "hp_bind_gradient", "hp_solve",
     "hp_solve_adjoint", "hp_get_output", "hp_get_gradient", "hp_query", "hp_plan_destroy",
     "hp_status_string", "hp_last_error", "hp_set_timing", "hp_pass_stats", "hp_autotune",
-    "hp_zero_mode_noalloc",
+    "hp_zero_mode_noalloc", "hp_device_copy",
 )
 
 
@@ -79,6 +79,7 @@ _SIG = {
     "hp_set_timing": ([_P, _I], _I),
     "hp_autotune": ([_P, _I], _I),
     "hp_zero_mode_noalloc": ([_P, _P], _I),
+    "hp_device_copy": ([_P, _P, ctypes.c_size_t, _P], _I),
     "hp_pass_stats": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double),
                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_char_p)], _I),
 }
@@ -204,3 +205,8 @@ def hp_last_error(plan=None):
 def hp_zero_mode_noalloc(plan, out_ptr):
     """Per-component zero modes into the caller's device buffer (ncomp doubles)."""
     _check(lib().hp_zero_mode_noalloc(plan, out_ptr), plan)
+
+
+def hp_device_copy(src_ptr, dst_ptr, nbytes, stream=None):
+    """Plain streaming device copy (the measured bandwidth ceiling of bench.py)."""
+    _check(lib().hp_device_copy(src_ptr, dst_ptr, int(nbytes), stream))

@@ -2110,6 +2110,13 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
   }
 }
 
+hp_status hp_device_copy(const void* src, void* dst, size_t bytes, hp_stream stream) {
+  if (bytes == 0) return HP_OK;
+  if (!src || !dst || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) return HP_E_ARG;
+  if (launch_copy(src, dst, bytes, (hipStream_t)stream) != hipSuccess) return HP_E_DEVICE;
+  return HP_OK;
+}
+
 hp_status hp_zero_mode_noalloc(hp_plan plan, double* out) {
   if (!plan || !out) return HP_E_ARG;
   if (plan->batched) return fail(plan, HP_E_ARG, "zero mode: single-problem plans");

@@ -178,6 +178,8 @@ struct BatchItem {
 // trap[a] set (DCT-I), else 1.
 hipError_t launch_zero_mode(const PassArgs& a, const void* f, const int n[3], const int trap[3],
                             double* partial, int nb, int prec, hipStream_t s);
+// Plain streaming copy of `bytes` (16-byte accesses; src and dst 16-byte aligned).
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // Allocation-free form of the same query: the partial sums of component c
 // (kZeroModeBlocks of them) go to a static per-device scratch array, and a
 // second kernel writes out[c] = (their sum in block order) / W[c] (0 where

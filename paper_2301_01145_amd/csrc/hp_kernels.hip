@@ -13,6 +13,7 @@
 // spectrum, Section 2.2 step 2), applies the spectral derivative (step 3,
 // eq. ft_sd), transforms back and stores, so the spectrum of that axis never
 // leaves LDS.
+#include <algorithm>
 #include <mutex>
 
 #include "hp_device.hpp"
@@ -954,6 +955,49 @@ hipError_t launch_zero_mode(const PassArgs& a, const void* f, const int n[3], co
   else
     hipLaunchKernelGGL(k_zero_mode<double>, dim3(nb), dim3(256), 0, s, a, (const double*)f, n[0],
                        n[1], n[2], trap[0], trap[1], trap[2], partial);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- reference streaming copy
+// A plain copy with 16-byte loads and stores, four in flight per thread: the
+// bandwidth that a kernel doing nothing but streaming reaches on the device,
+// the measured ceiling beside the HBM specification.
+__global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, long long n16) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_copy_tail(const unsigned char* src, unsigned char* dst, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const long long n16 = (long long)(bytes / 16);
+  if (n16 > 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      cus = 256;
+    }
+    const long long want = (n16 + 4LL * 256 - 1) / (4LL * 256);
+    const int grid = (int)std::max(1LL, std::min<long long>(want, (long long)cus * 16));
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+  }
+  const long long tail = (long long)(bytes - (size_t)n16 * 16);
+  if (tail > 0)
+    hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, (const unsigned char*)src + n16 * 16,
+                       (unsigned char*)dst + n16 * 16, tail);
   return hipGetLastError();
 }
 

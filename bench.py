@@ -215,15 +215,25 @@ def other_workloads(steps, warmup):
         bs = BatchedSolver("neumann", "staggered", [{"nc": list(p["shape"])} for p in probs], kernel="ps")
         bs.bind([torch.as_tensor(p["f"].astype(np.float32), device="cuda") for p in probs])
     torch.cuda.synchronize()
+    mode_default = bs.kernel_mode()
     ms_default = _time(bs.run, steps, warmup, bs.stream)
-    # plan-time autotuning (radix orders, tiles, work-item size), outside the timed region
+    ms_default_graph = _time_graph(bs.run, side, steps, warmup)
+    # plan-time autotuning (kernel form, radix orders, tiles, work-item size),
+    # outside the timed region
     with torch.cuda.stream(side):
         ntuned, tiles = bs.autotune(reps=5)
     ms_eager = _time(bs.run, steps, warmup, bs.stream)
     ms = _time_graph(bs.run, side, steps, warmup)
+    forms = {0: "one persistent launch, general passes",
+             1: "one persistent launch, wavefront tile bodies",
+             2: "one launch per pass level (5), wavefront tile bodies"}
     res["neumann_batch64_fp32"] = {"batches_per_s": 1000 / ms, "problems_per_s": 64000 / ms, "ms": ms,
-                                   "timing": "hipGraph replays of the one persistent launch",
-                                   "ms_eager": ms_eager, "ms_untuned_eager": ms_default,
+                                   "timing": "hipGraph replays of the tuned batch",
+                                   "kernel_form": forms[bs.kernel_mode()],
+                                   "ms_eager": ms_eager,
+                                   "default_form": forms[mode_default],
+                                   "ms_default_graph": ms_default_graph,
+                                   "ms_default_eager": ms_default,
                                    "tuned_pass_signatures": ntuned, "tiles_per_item": tiles,
                                    "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
                                    "error_flag": bs.error_flag()}

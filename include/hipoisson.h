@@ -127,12 +127,17 @@ enum {
                                measured by the last hp_autotune */
   HP_Q_TUNE_BEST_MS = 9,    /* the same with the configuration it kept */
   HP_Q_BATCH_TILES = 10,    /* batched plans: tiles per work item of the persistent kernel */
-  HP_Q_ZERO_MODE = 11       /* periodic / Neumann plans: the part of the bound source (with its
+  HP_Q_ZERO_MODE = 11,      /* periodic / Neumann plans: the part of the bound source (with its
                                FD2 boundary terms) that the k = 0 projection removes, i.e. the
                                k = 0 coefficient of its forward transform over that of a field
                                of ones (the weighted mean, DCT-I ends weighted 1/2); 0 for a
                                compatible source and for other BCs; 3-component plans give
                                the component of largest magnitude; synchronises */
+  HP_Q_BATCH_KERNEL = 12    /* batched plans: 0 = one persistent launch of the general passes,
+                               1 = one persistent launch of the wavefront-FFT tile bodies (FP32,
+                               every transform length 64, 96, 128, 192 or 256), 2 = the same
+                               tile bodies as one launch per pass level (chosen by hp_autotune
+                               only) */
 };
 
 /* Create a plan for one problem (the initialisation of Section 3.2.1): grid
@@ -144,7 +149,10 @@ HP_API hp_status hp_plan_create(const hp_desc* desc, hp_stream stream, hp_plan* 
 /* A plan over `count` independent problems (descs[0..count-1]); they must
  * share bc, grid, kernel, diff, prec and ndim and may differ in size.  One
  * hp_solve launches a single persistent kernel that runs every pass of every
- * problem.  Supported for bounded, non-periodic, homogeneous problems. */
+ * problem.  Supported for bounded, non-periodic, homogeneous problems.  When
+ * every transform length of every problem is 64, 96, 128, 192 or 256 (FP32)
+ * the launch runs one FFT per wavefront, otherwise the general LDS-staged
+ * passes (HP_Q_BATCH_KERNEL; hp_autotune may choose either). */
 HP_API hp_status hp_plan_create_batched(const hp_desc* descs, int count, hp_stream stream, hp_plan* out);
 
 /* Unknown (input) and output point counts per axis of problem `problem`;

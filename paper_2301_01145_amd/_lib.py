@@ -21,6 +21,7 @@ HP_Q_MODEL_BYTES, HP_Q_WORKSPACE_BYTES, HP_Q_NUM_PASSES, HP_Q_NUM_OUTPUTS, HP_Q_
 HP_Q_BATCH_ERROR = 6
 HP_Q_TUNED_PASSES, HP_Q_TUNE_DEFAULT_MS, HP_Q_TUNE_BEST_MS, HP_Q_BATCH_TILES = 7, 8, 9, 10
 HP_Q_ZERO_MODE = 11
+HP_Q_BATCH_KERNEL = 12
 
 # Every exported function of include/hipoisson.h (checked by the ABI tests).
 EXPORTS = (

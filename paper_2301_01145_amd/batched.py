@@ -54,6 +54,15 @@ class BatchedSolver:
         return (int(hp_query(self.plan, _lib.HP_Q_TUNED_PASSES)),
                 int(hp_query(self.plan, _lib.HP_Q_BATCH_TILES)))
 
+    def wavefront_kernel(self):
+        """True when the batch runs the wavefront-FFT tile bodies."""
+        return bool(hp_query(self.plan, _lib.HP_Q_BATCH_KERNEL))
+
+    def kernel_mode(self):
+        """0: general passes in one persistent launch; 1: wavefront tile bodies in
+        one persistent launch; 2: wavefront tile bodies, one launch per pass level."""
+        return int(hp_query(self.plan, _lib.HP_Q_BATCH_KERNEL))
+
     def error_flag(self):
         return int(hp_query(self.plan, _lib.HP_Q_BATCH_ERROR))
 

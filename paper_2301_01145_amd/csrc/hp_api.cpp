@@ -218,15 +218,18 @@ hp_status twiddles(hp_plan p, int L, const void** out) {
   return HP_OK;
 }
 
-// Twiddles of the wavefront FFT of length L (power of two, 64..1024), per
-// stage after the first: stage 1 (radix 8 after R0) then stage 2 (radix
-// G/8 after 8 R0), each stored [t - 1][k] = W_{NS R}^{t k}, so that the lanes
-// of a wavefront read consecutive entries.  L entries are allocated (the
+// Twiddles of the wavefront FFT of length L (wf_r0), per stage after the
+// first: stage 1 (radix G <= 8 after R0, the last one; after R0 = 12 radix
+// 4; else radix 8) then stage 2 (radix G/4 after 4 R0, or G/8 after 8 R0),
+// each stored [t - 1][k] = W_{NS R}^{t k}, so that the lanes of a wavefront
+// read consecutive entries.  L entries are allocated (the
 // kernels copy L entries to LDS); unused ones are zero.
 hp_status fast_twiddles(hp_plan p, int L, const void** out) {
   auto it = p->ftw.find(L);
   if (it != p->ftw.end()) { *out = it->second; return HP_OK; }
-  const int R0 = L >= 1024 ? 16 : 8, G = L / R0;
+  const int R0 = wf_r0(L);
+  if (R0 <= 0) return fail(p, HP_E_UNSUPPORTED, "no wavefront FFT of length " + std::to_string(L));
+  const int G = L / R0;
   std::vector<double> w(2 * (size_t)L, 0.0);
   size_t off = 0;
   auto stage = [&](int NS, int R) {
@@ -239,8 +242,15 @@ hp_status fast_twiddles(hp_plan p, int L, const void** out) {
       }
     off += (size_t)(R - 1) * NS;
   };
-  stage(R0, 8);
-  if (G > 8) stage(8 * R0, G / 8);
+  if (G <= 8 && R0 % G == 0) {
+    stage(R0, G);
+  } else if (R0 % 3 == 0) {
+    stage(R0, 4);
+    stage(4 * R0, G / 4);
+  } else {
+    stage(R0, 8);
+    stage(8 * R0, G / 8);
+  }
   if (off > (size_t)L) return fail(p, HP_E_UNSUPPORTED, "wavefront FFT twiddle table overflow");
   void* d;
   HP_TRY(dev_alloc(p, (size_t)L * 2 * p->es, &d));
@@ -806,13 +816,16 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
 
 // --------------------------------------------------------- pass lists
 // Wavefront-FFT kernels for the bounded passes (hp_bounded.hip): 2D / 3D
-// single plans whose every transform length is a power of two in [64, 512].
+// single plans whose every transform length is a power of two in [64, 512],
+// or 96 or 192.
 bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
   if (std::getenv("HP_GENERIC") || p->batched || P.nd < 2) return false;
   for (int a = 0; a < P.nd; ++a) {
-    if (L[a] < 64 || L[a] > 512 || (L[a] & (L[a] - 1))) return false;
-    for (int k = FAST_R2R_C; k <= FAST_R2R_SW; ++k)
-      if (r2r_lds_bytes(k, L[a], P.n[a], p->prec) > 160 * 1024) return false;
+    if (L[a] < 64 || L[a] > 512 || wf_r0(L[a]) <= 0) return false;
+    for (int k = FAST_R2R_C; k <= FAST_R2R_SW; ++k) {
+      const int lds = r2r_lds_bytes(k, L[a], P.n[a], p->prec);
+      if (lds <= 0 || lds > 160 * 1024) return false;
+    }
   }
   return true;
 }
@@ -1808,6 +1821,7 @@ void plan_free(hp_plan p, void* ptr) {
   (void)hipFree(ptr);
 }
 hp_status plan_outputs(hp_plan p, Problem& P) { return ensure_outputs(p, P); }
+hp_status plan_fast_twiddles(hp_plan p, int L, const void** out) { return fast_twiddles(p, L, out); }
 hp_status launch_rec(hp_plan p, const PassRec& r) {
   hipError_t e = r.a.fast >= FAST_R2R_C ? launch_bounded(r.a, p->prec, p->stream)
                  : r.a.fast               ? launch_fast(r.a, p->prec, r.grid_y, p->stream)
@@ -2086,6 +2100,10 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
     case HP_Q_BATCH_TILES:
       if (!plan->batched) return fail(plan, HP_E_ARG, "not a batched plan");
       *value = batch_tiles_of(plan);
+      return HP_OK;
+    case HP_Q_BATCH_KERNEL:
+      if (!plan->batched) return fail(plan, HP_E_ARG, "not a batched plan");
+      *value = (double)plan->batch_wf;
       return HP_OK;
     case HP_Q_MODEL_BYTES:
     case HP_Q_NUM_PASSES: {

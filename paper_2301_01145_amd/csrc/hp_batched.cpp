@@ -1,9 +1,12 @@
 // Batched persistent solve: many independent bounded problems of different
 // sizes in one launch.  The pass list of every problem is the one of the
 // single-problem path (all passes in place in the problem's output array); the
-// persistent kernel walks a global item list (one item = one tile of one pass)
-// ordered pass level by pass level, with per-pass completion counters as the
-// only dependencies between workgroups.
+// persistent kernel walks a global item list (one item = consecutive tiles of
+// one pass) ordered pass level by pass level, with per-pass completion
+// counters as the only dependencies between workgroups.  Where every pass of
+// every problem has a wavefront FFT (FP32, lengths 64, 96, 128, 192, 256) the
+// kernel runs the wavefront tile bodies (k_batched_wf); otherwise the general
+// pass code (k_batched).
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -35,6 +38,44 @@ hp_status build_all(hp_plan p, bool placeholders, std::vector<std::vector<PassRe
 
 int tiles_of(const PassArgs& a) { return ((a.Np + a.P - 1) / a.P) * a.No; }
 
+// Transform pair of a batch on the wavefront kernels: every pass a
+// real-to-real one-way or sandwich pass of the pair (xf, Table 1 partner) with
+// a length of batched_wf_length, FP32, no boundary terms.  Returns xf, or 0.
+int wf_family(hp_plan p, const std::vector<std::vector<PassRec>>& lists) {
+  if (p->prec != 0 || std::getenv("HP_GENERIC")) return 0;
+  int xf = 0;
+  for (auto& l : lists)
+    for (auto& r : l)
+      if (r.a.kind == PK_SANDWICH) xf = r.a.xf;
+  const int xb = xf == X_DCT2 ? X_DCT3 : (xf == X_DST2 ? X_DST3 : xf);
+  if (xf != X_DCT2 && xf != X_DST2 && xf != X_DCT1) return 0;
+  for (auto& l : lists)
+    for (auto& r : l) {
+      const PassArgs& a = r.a;
+      if (a.fast != FAST_NONE || !batched_wf_length(a.L) || a.n > a.L / 2 + 1) return 0;
+      if (a.kind == PK_SANDWICH ? (a.xf != xf || a.xb != xb) : (a.xf != xf && a.xf != xb)) return 0;
+      for (int ax = 0; ax < 3; ++ax)
+        if (a.face[ax][0] || a.face[ax][1]) return 0;
+    }
+  return xf;
+}
+
+// The pass on the wavefront tile bodies of k_batched_wf (same descriptor).
+hp_status to_wf(hp_plan p, PassArgs& a) {
+  const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
+  a.fast = a.kind == PK_SANDWICH ? FAST_R2R_SW : (contig ? FAST_R2R_C : FAST_R2R_S);
+  const void* tw;
+  hp_status s = plan_fast_twiddles(p, a.L, &tw);
+  if (s != HP_OK) return s;
+  a.tw = tw;
+  a.P = 32;
+  a.lds_bytes = batched_wf_lds(a.fast, a.L);
+  return HP_OK;
+}
+
+// Tiles of a pass in the kernel of the plan's mode.
+int mode_tiles(hp_plan p, const PassArgs& a) { return p->batch_wf ? batched_wf_tiles(a) : tiles_of(a); }
+
 int batch_tiles_per_item() {
   if (const char* e = std::getenv("HP_BATCH_TILES")) {
     const int v = std::atoi(e);
@@ -57,6 +98,22 @@ hp_status batched_setup(hp_plan p) {
   std::vector<std::vector<PassRec>> lists;
   hp_status s = build_all(p, true, lists);
   if (s != HP_OK) return s;
+  // wavefront tile bodies where every pass allows them (unless the autotuner
+  // chose the general passes)
+  const int xf = p->batch_mode == 0 ? 0 : wf_family(p, lists);
+  // HP_BATCH_LEVELS=1: the level-launch form by default (as the autotuner may choose)
+  const char* lv = std::getenv("HP_BATCH_LEVELS");
+  const bool levels = p->batch_mode == 2 || (p->batch_mode < 0 && lv && std::atoi(lv) == 1);
+  p->batch_wf = xf == 0 ? 0 : (levels ? 2 : 1);
+  p->batch_xf = xf;
+  if (p->batch_wf) {
+    p->tuned.clear();  // per-pass configurations are those of the general kernels
+    for (auto& l : lists)
+      for (auto& r : l) {
+        s = to_wf(p, r.a);
+        if (s != HP_OK) return s;
+      }
+  }
   // items: pass level by pass level, problems in order, tiles in order
   std::vector<int> first(lists.size(), 0);
   int npass = 0, maxlev = 0, lds = 0, big = 0;
@@ -72,19 +129,25 @@ hp_status batched_setup(hp_plan p) {
   p->batch_big = big;
   const int per_item = batch_tiles_of(p);
   std::vector<BatchItem> items;
+  p->batch_level_first.clear();
   for (int lev = 0; lev < maxlev; ++lev) {
+    p->batch_level_first.push_back((int)items.size());
     for (size_t q = 0; q < lists.size(); ++q) {
       if (lev >= (int)lists[q].size()) continue;
       const int gp = first[q] + lev;
       const int dep = lev > 0 ? gp - 1 : -1;
-      const int need = lev > 0 ? tiles_of(lists[q][lev - 1].a) : 0;
+      const int need = lev > 0 ? mode_tiles(p, lists[q][lev - 1].a) : 0;
       // consecutive tiles of a pass share one item (one queue step, one
-      // dependency check and one release per item)
-      const int nt = tiles_of(lists[q][lev].a);
-      for (int t = 0; t < nt; t += per_item)
-        items.push_back({gp, t, std::min(per_item, nt - t), dep, need});
+      // dependency check and one release per item); a wavefront strided item
+      // holds one tile per group of wavefronts for every step
+      const PassArgs& a = lists[q][lev].a;
+      const int nt = mode_tiles(p, a);
+      const int step = per_item * (p->batch_wf ? batched_wf_group(a) : 1);
+      for (int t = 0; t < nt; t += step)
+        items.push_back({gp, t, std::min(step, nt - t), dep, need});
     }
   }
+  p->batch_level_first.push_back((int)items.size());
   p->batch_nitems = (int)items.size();
   p->batch_ncounters = 1 + npass;
   p->batch_lds = lds;
@@ -112,7 +175,7 @@ hp_status batched_setup(hp_plan p) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return plan_fail(p, HP_E_DEVICE, "device query failed");
-  const int per_cu = batched_blocks_per_cu(lds, p->prec, big);
+  const int per_cu = p->batch_wf ? batched_wf_blocks_per_cu(xf, lds) : batched_blocks_per_cu(lds, p->prec, big);
   p->batch_grid = std::max(1, std::min(p->batch_nitems, per_cu * cus));
   // keep the pass list (placeholder pointers) for the byte model
   p->batch_passes.clear();
@@ -140,7 +203,13 @@ hp_status batched_solve(hp_plan p) {
   if (s != HP_OK) return s;
   std::vector<PassArgs> flat;
   for (auto& l : lists)
-    for (auto& r : l) flat.push_back(r.a);
+    for (auto& r : l) {
+      if (p->batch_wf) {
+        s = to_wf(p, r.a);
+        if (s != HP_OK) return s;
+      }
+      flat.push_back(r.a);
+    }
   // the pass table holds the bound pointers: upload when they changed
   const size_t bytes = flat.size() * sizeof(PassArgs);
   std::vector<unsigned char> img(bytes);
@@ -155,10 +224,22 @@ hp_status batched_solve(hp_plan p) {
       return plan_fail(p, HP_E_DEVICE, "upload of the batched pass table failed");
     p->batch_uploaded = img;
   }
-  hipError_t e = launch_batched((const PassArgs*)p->batch_probs, (const BatchItem*)p->batch_items,
-                                p->batch_nitems, p->batch_counters, p->batch_ncounters,
-                                (int*)(p->batch_counters + p->batch_ncounters), p->batch_grid,
-                                p->batch_lds, p->prec, p->batch_big, p->stream);
+  hipError_t e =
+      p->batch_wf == 2
+          ? launch_batched_levels(p->batch_xf, (const PassArgs*)p->batch_probs,
+                                  (const BatchItem*)p->batch_items, p->batch_level_first.data(),
+                                  (int)p->batch_level_first.size() - 1,
+                                  (int*)(p->batch_counters + p->batch_ncounters), p->batch_lds,
+                                  p->stream)
+      : p->batch_wf
+          ? launch_batched_wf(p->batch_xf, (const PassArgs*)p->batch_probs,
+                              (const BatchItem*)p->batch_items, p->batch_nitems, p->batch_counters,
+                              p->batch_ncounters, (int*)(p->batch_counters + p->batch_ncounters),
+                              p->batch_grid, p->batch_lds, p->stream)
+          : launch_batched((const PassArgs*)p->batch_probs, (const BatchItem*)p->batch_items,
+                           p->batch_nitems, p->batch_counters, p->batch_ncounters,
+                           (int*)(p->batch_counters + p->batch_ncounters), p->batch_grid,
+                           p->batch_lds, p->prec, p->batch_big, p->stream);
   if (e != hipSuccess)
     return plan_fail(p, HP_E_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
   p->solved = true;

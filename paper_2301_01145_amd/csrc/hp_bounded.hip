@@ -1,5 +1,6 @@
 // Bounded (Dirichlet / Neumann) passes with one FFT per wavefront, for
-// power-of-two transform lengths L = 64 .. 1024 (hp_wavefft.hpp).
+// transform lengths L = 64 .. 1024 (powers of two), 96 and 192
+// (hp_wavefft.hpp).
 //
 // The real-to-real transforms of Table 1 (DST-I/II/III, DCT-I/II/III) run as
 // one complex FFT of length L on a pair of real pencils packed as a + ib,
@@ -351,6 +352,477 @@ __global__ void __launch_bounds__(64 * W) kb_strided(const PassArgs a) {
   }
 }
 
+// ------------------------------------------ batched persistent solve
+// Every pass of every problem of a batched plan, one persistent launch: a
+// workgroup of kBatchWaves wavefronts takes work items (consecutive tiles of
+// one pass of one problem) from a queue ordered pass level by pass level and
+// waits for the pass it depends on (per-pass completion counters, agent-scope
+// acquire / release), as the general batched kernel does.  The tile bodies
+// are those of kb_contig / kb_strided with the transform length and type as
+// compile-time constants:
+//   contiguous pass: a tile is kBatchWaves * PPW pencil pairs (one per lane
+//     group) taken in (o, pair) order;
+//   strided pass / sandwich: a tile is P = 32 pencils adjacent along the
+//     contiguous axis (16 pairs), transformed by W = min(P / (2 PPW),
+//     kBatchWaves) wavefronts, each lane group taking P / (2 W PPW) pairs in
+//     turn; the workgroup holds S = kBatchWaves / W tiles at once (one per
+//     group of W wavefronts).
+// LDS: twiddles [L] | quarter twists [L/2 + 1] | exchange slots | S tiles.
+// Four wavefronts per workgroup keep the exchange slots small enough for
+// three or four workgroups per CU at every length.
+constexpr int kBatchWaves = 4;
+
+namespace {
+
+template <int L>
+struct BW {
+  static constexpr int PPW = WF<L>::PPW;
+  static constexpr int P = 32;  // FP32 pencils per strided tile (128-byte runs)
+  static constexpr int W = (P / 2) / PPW < kBatchWaves ? (P / 2) / PPW : kBatchWaves;
+  static constexpr int PPL = (P / 2) / (W * PPW);  // pairs per lane group
+  static constexpr int S = kBatchWaves / W;
+  static constexpr int MAXN = L / 2 + 1;
+  static constexpr int TS = P + 1;
+  static_assert(W >= 1 && kBatchWaves % W == 0 && PPL * W * PPW == P / 2, "batched strided tile");
+};
+
+// The fields of a pass that the tile bodies read, as wavefront-uniform
+// values.  The pass table is read with vector loads (the kernel also writes
+// global memory, so the compiler cannot use scalar loads for it); passing
+// each field through readfirstlane lets it live in scalar registers instead
+// of vector registers for the whole item.
+struct BwArgs {
+  int L, fast, xf, n, Np, No;
+  long long in_sj, in_sp, in_so, out_sj, out_sp, out_so;
+  const float* in;
+  float* out;
+  const C2<float>* tw;
+  const C2<float>* qtw;
+  const double* lam_j;  // eigenvalues along the pencil axis (sandwich)
+  const double* lam_p;  // along the tile axis (null: none)
+  const double* lam_o;  // along the outer axis (null: none)
+  double norm;
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni(long long v) {
+  const unsigned lo = (unsigned)uni((int)(v & 0xffffffffLL)), hi = (unsigned)uni((int)(v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) { return (P*)uni((long long)p); }
+__device__ __forceinline__ double uni(double d) { return __longlong_as_double(uni(__double_as_longlong(d))); }
+
+__device__ __forceinline__ BwArgs bw_args(const PassArgs& a) {
+  BwArgs b;
+  b.L = uni(a.L);
+  b.fast = uni(a.fast);
+  b.xf = uni(a.xf);
+  b.n = uni(a.n);
+  b.Np = uni(a.Np);
+  b.No = uni(a.No);
+  b.in_sj = uni(a.in_sj);
+  b.in_sp = uni(a.in_sp);
+  b.in_so = uni(a.in_so);
+  b.out_sj = uni(a.out_sj);
+  b.out_sp = uni(a.out_sp);
+  b.out_so = uni(a.out_so);
+  b.in = uni((const float*)a.in[0]);
+  b.out = uni((float*)a.out[0]);
+  b.tw = uni((const C2<float>*)a.tw);
+  b.qtw = uni((const C2<float>*)a.qtw);
+  const int aj = uni(a.ax_j), ap = uni(a.ax_p), ao = uni(a.ax_o);
+  b.lam_j = aj >= 0 ? uni(a.lam[aj]) : nullptr;
+  b.lam_p = ap >= 0 ? uni(a.lam[ap]) : nullptr;
+  b.lam_o = ao >= 0 ? uni(a.lam[ao]) : nullptr;
+  b.norm = uni(a.norm);
+  return b;
+}
+
+__device__ __forceinline__ BwArgs bw_uniform(const BwArgs& a) {
+  BwArgs b;
+  b.L = uni(a.L);
+  b.fast = uni(a.fast);
+  b.xf = uni(a.xf);
+  b.n = uni(a.n);
+  b.Np = uni(a.Np);
+  b.No = uni(a.No);
+  b.in_sj = uni(a.in_sj);
+  b.in_sp = uni(a.in_sp);
+  b.in_so = uni(a.in_so);
+  b.out_sj = uni(a.out_sj);
+  b.out_sp = uni(a.out_sp);
+  b.out_so = uni(a.out_so);
+  b.in = uni(a.in);
+  b.out = uni(a.out);
+  b.tw = uni(a.tw);
+  b.qtw = uni(a.qtw);
+  b.lam_j = uni(a.lam_j);
+  b.lam_p = uni(a.lam_p);
+  b.lam_o = uni(a.lam_o);
+  b.norm = uni(a.norm);
+  return b;
+}
+
+// The thread index, opaque to the optimiser: everything a tile body derives
+// from it (lane splits, LDS slot addresses) is then computed inside the body
+// instead of being hoisted out of the persistent loop, where the values of
+// every (length, kind) body would stay live together and spill.
+__device__ __forceinline__ int bw_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Load the twiddles of the pass (and the quarter-wave twists) into LDS.
+template <int L>
+__device__ __forceinline__ void bw_tables(const BwArgs& a, C2<float>* tw, C2<float>* q, int tid) {
+  constexpr int NT = 64 * kBatchWaves;
+  for (int m = tid; m < L; m += NT) tw[m] = a.tw[m];
+  if (a.qtw)
+    for (int m = tid; m < a.n; m += NT) q[m] = a.qtw[m];
+}
+
+// Each tile body is a function of its own (not inlined into the kernel), so
+// that it is register-allocated like a kernel of its own; its arguments are
+// copied into scalar registers on entry (bw_uniform).
+template <int L, int X>
+__device__ __attribute__((noinline)) void bw_contig(const BwArgs* ap, unsigned char* smem, int tile,
+                                                    int ntile) {
+  const BwArgs a = bw_uniform(*ap);
+  constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
+  using T = float;
+  const int n = a.n;
+  C2<T>* tw = (C2<T>*)smem;
+  C2<T>* q = tw + L;
+  C2<T>* slots = q + BW<L>::MAXN;
+  const int tid = bw_tid();
+  bw_tables<L>(a, tw, q, tid);
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int qq = lane / G, g = lane % G;
+  C2<T>* slot = slots + (wave * PPW + qq) * slot_len(L);
+  T* R = (T*)slot;
+  const int pairs_p = (a.Np + 1) / 2;
+  const long long total = (long long)pairs_p * a.No;
+  for (int k = 0; k < ntile; ++k) {
+    const long long pr = ((long long)(tile + k) * kBatchWaves + wave) * PPW + qq;
+    const bool valid = pr < total;
+    const int o = valid ? (int)(pr / pairs_p) : 0;
+    const int pa = valid ? 2 * (int)(pr % pairs_p) : 0;
+    const bool vb = valid && pa + 1 < a.Np;
+    const long long ib = (long long)o * a.in_so + (long long)pa * a.in_sp;
+    for (int j = g; j < n; j += G) {
+      R[j] = valid ? a.in[ib + (long long)j * a.in_sj] : (T)0;
+      R[n + j] = vb ? a.in[ib + a.in_sp + (long long)j * a.in_sj] : (T)0;
+    }
+    wave_sync();
+    const long long ob = (long long)o * a.out_so + (long long)pa * a.out_sp;
+    C2<T> v[R0];
+    r2r_fft<T, L>(v, X, n, slot, g, tw, q, [&](int s, int w) { return R[w * n + s]; });
+#pragma unroll
+    for (int i = 0; i < R0; ++i) {
+      T oa, obv;
+      const int kk = r2r_extract<T>(X, g + G * i, n, v[i], q, oa, obv);
+      if (kk < 0) continue;
+      if (valid) a.out[ob + (long long)kk * a.out_sj] = oa;
+      if (vb) a.out[ob + a.out_sp + (long long)kk * a.out_sj] = obv;
+    }
+    wave_sync();  // the slot is reused by the next pair
+  }
+}
+
+template <int L, int XF, int XO, bool SW>
+__device__ __attribute__((noinline)) void bw_strided(const BwArgs* ap, unsigned char* smem, int tile,
+                                                     int ntile) {
+  const BwArgs a = bw_uniform(*ap);
+  constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
+  constexpr int P = BW<L>::P, W = BW<L>::W, S = BW<L>::S, TS = BW<L>::TS, PPL = BW<L>::PPL;
+  constexpr int MAXN = BW<L>::MAXN, NTS = 64 * W;
+  using T = float;
+  const int n = a.n;
+  C2<T>* tw = (C2<T>*)smem;
+  C2<T>* q = tw + L;
+  C2<T>* slots = q + MAXN;
+  T* tiles = (T*)(slots + kBatchWaves * PPW * slot_len(L));
+  const int tid = bw_tid();
+  bw_tables<L>(a, tw, q, tid);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int sub = wave / W, wv = wave - sub * W;  // tile group and wavefront in it
+  const int ts = tid - sub * NTS;                  // thread in the group
+  const int qq = lane / G, g = lane % G;
+  C2<T>* slot = slots + (wave * PPW + qq) * slot_len(L);
+  T* tile_s = tiles + sub * MAXN * TS;
+  const int tiles_p = (a.Np + P - 1) / P;
+  for (int base = 0; base < ntile; base += S) {
+    const bool active = base + sub < ntile;
+    const int t = tile + base + sub;
+    const int o = active ? t / tiles_p : 0, p0 = active ? (t % tiles_p) * P : 0;
+    const int np = active ? min(P, a.Np - p0) : 0;
+    const long long ib = (long long)o * a.in_so + (long long)p0 * a.in_sp;
+    for (int e = ts; e < n * P; e += NTS) {
+      const int j = e / P, c = e - (e / P) * P;
+      tile_s[j * TS + c] = c < np ? a.in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
+    }
+    __syncthreads();
+    for (int r = 0; r < PPL && active; ++r) {
+      const int f = (r * W + wv) * PPW + qq;  // pair: columns 2f, 2f + 1
+      T* ca = tile_s + 2 * f;
+      auto get = [&](int s, int w) { return ca[s * TS + w]; };
+      C2<T> v[R0];
+      r2r_fft<T, L>(v, XF, n, slot, g, tw, q, get);
+      if constexpr (SW) {
+        // multiplier norm / (sum of the eigenvalues), FP64 sum (Table 1)
+        const int pa = min(p0 + 2 * f, a.Np - 1), pb = min(p0 + 2 * f + 1, a.Np - 1);
+        const double ro = a.lam_o ? a.lam_o[o] : 0.0;
+        const double ra = ro + (a.lam_p ? a.lam_p[pa] : 0.0), rb = ro + (a.lam_p ? a.lam_p[pb] : 0.0);
+#pragma unroll
+        for (int i = 0; i < R0; ++i) {
+          T sa, sb;
+          const int k = r2r_extract<T>(XF, g + G * i, n, v[i], q, sa, sb);
+          if (k < 0) continue;
+          const double la = a.lam_j[k] + ra, lb = a.lam_j[k] + rb;
+          ca[k * TS] = la == 0.0 ? (T)0 : sa * ((T)a.norm / (T)la);
+          ca[k * TS + 1] = lb == 0.0 ? (T)0 : sb * ((T)a.norm / (T)lb);
+        }
+        wave_sync();
+        r2r_fft<T, L>(v, XO, n, slot, g, tw, q, get);
+      }
+#pragma unroll
+      for (int i = 0; i < R0; ++i) {
+        T oa, obv;
+        const int k = r2r_extract<T>(XO, g + G * i, n, v[i], q, oa, obv);
+        if (k < 0) continue;
+        ca[k * TS] = oa;
+        ca[k * TS + 1] = obv;
+      }
+      wave_sync();  // the slot is reused by the next pair
+    }
+    __syncthreads();
+    const long long ob = (long long)o * a.out_so + (long long)p0 * a.out_sp;
+    for (int e = ts; e < n * P; e += NTS) {
+      const int j = e / P, c = e - (e / P) * P;
+      if (c < np) a.out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp] = tile_s[j * TS + c];
+    }
+    __syncthreads();  // the tiles are reloaded by the next step
+  }
+}
+
+// One item: ntile tiles of pass a, for the transform pair (XF, XB) of the batch.
+template <int L, int XF, int XB>
+__device__ void bw_item_L(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
+  if (a.fast == FAST_R2R_C) {
+    if (a.xf == XF) bw_contig<L, XF>(&a, smem, tile, ntile);
+    else bw_contig<L, XB>(&a, smem, tile, ntile);
+  } else if (a.fast == FAST_R2R_S) {
+    if (a.xf == XF) bw_strided<L, XF, XF, false>(&a, smem, tile, ntile);
+    else bw_strided<L, XB, XB, false>(&a, smem, tile, ntile);
+  } else {
+    bw_strided<L, XF, XB, true>(&a, smem, tile, ntile);
+  }
+}
+
+template <int XF, int XB>
+__device__ void bw_item(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
+  switch (a.L) {
+    case 64: bw_item_L<64, XF, XB>(a, smem, tile, ntile); break;
+    case 96: bw_item_L<96, XF, XB>(a, smem, tile, ntile); break;
+    case 128: bw_item_L<128, XF, XB>(a, smem, tile, ntile); break;
+    case 192: bw_item_L<192, XF, XB>(a, smem, tile, ntile); break;
+    default: bw_item_L<256, XF, XB>(a, smem, tile, ntile); break;
+  }
+}
+
+__global__ void k_bw_zero(unsigned* c, int n, int* err) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) err[0] = 0;
+}
+
+// Four wavefronts per SIMD: at most 128 VGPRs.
+template <int XF, int XB>
+__global__ void __launch_bounds__(64 * kBatchWaves, 4)
+    k_batched_wf(const PassArgs* passes, const BatchItem* items, int nitems, unsigned* counters,
+                 int* err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item, s_ok;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= nitems) break;
+    BatchItem bi = items[it];
+    bi.pass = uni(bi.pass);
+    bi.tile = uni(bi.tile);
+    bi.ntile = uni(bi.ntile);
+    bi.dep = uni(bi.dep);
+    bi.need = uni(bi.need);
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      if (bi.dep >= 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(&counters[1 + bi.dep], __ATOMIC_ACQUIRE,
+                                 __HIP_MEMORY_SCOPE_AGENT) < (unsigned)bi.need) {
+          __builtin_amdgcn_s_sleep(2);
+          // bounded wait: report and skip (also stop at once if another wait failed)
+          if (++spins > (1u << 22) ||
+              __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = 0;
+            atomicExch(err, 1);
+            break;
+          }
+        }
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    const int ok = __builtin_amdgcn_readfirstlane(s_ok);
+    // acquire: the tiles written by the workgroups that completed the pass
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ok) {
+      const BwArgs args = bw_args(passes[bi.pass]);
+      bw_item<XF, XB>(args, smem, bi.tile, bi.ntile);
+    }
+    // release: this item's stores before its tiles are counted
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(&counters[1 + bi.pass], (unsigned)bi.ntile, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+  }
+}
+
+// One pass level of the batch (the passes of every problem that have no
+// dependency left): one workgroup per item, no queue, no waiting; the launch
+// boundary orders the levels.
+template <int XF, int XB>
+__global__ void __launch_bounds__(64 * kBatchWaves, 4)
+    k_batched_level(const PassArgs* passes, const BatchItem* items, int* err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && err) err[0] = 0;  // no waits: never set
+  BatchItem bi = items[blockIdx.x];
+  bi.pass = uni(bi.pass);
+  bi.tile = uni(bi.tile);
+  bi.ntile = uni(bi.ntile);
+  const BwArgs args = bw_args(passes[bi.pass]);
+  bw_item<XF, XB>(args, smem, bi.tile, bi.ntile);
+}
+
+template <int XF, int XB>
+hipError_t bw_launch_levels(const PassArgs* passes, const BatchItem* items, const int* level_first,
+                            int nlevels, int* err, int lds, hipStream_t s) {
+  allow_lds<k_batched_level<XF, XB>>();
+  for (int l = 0; l < nlevels; ++l) {
+    const int n = level_first[l + 1] - level_first[l];
+    if (n <= 0) continue;
+    hipLaunchKernelGGL((k_batched_level<XF, XB>), dim3(n), dim3(64 * kBatchWaves), lds, s, passes,
+                       items + level_first[l], l == 0 ? err : nullptr);
+  }
+  return hipGetLastError();
+}
+
+template <int XF, int XB>
+int bw_blocks_per_cu(int lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched_wf<XF, XB>, 64 * kBatchWaves, lds) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n > 0 ? n : 1;
+}
+
+template <int XF, int XB>
+hipError_t bw_launch(const PassArgs* passes, const BatchItem* items, int nitems, unsigned* counters,
+                     int ncounters, int* err, int grid, int lds, hipStream_t s) {
+  allow_lds<k_batched_wf<XF, XB>>();
+  hipLaunchKernelGGL(k_bw_zero, dim3(1 + ncounters / 256), dim3(256), 0, s, counters, ncounters, err);
+  hipLaunchKernelGGL((k_batched_wf<XF, XB>), dim3(grid), dim3(64 * kBatchWaves), lds, s, passes, items,
+                     nitems, counters, err);
+  return hipGetLastError();
+}
+
+template <int L>
+int bw_lds_L(int fast) {
+  using B = BW<L>;
+  const int base = (L + B::MAXN + kBatchWaves * B::PPW * slot_len(L)) * 8;
+  return fast == FAST_R2R_C ? base : base + B::S * B::MAXN * B::TS * 4;
+}
+
+}  // namespace
+
+bool batched_wf_length(int L) { return L == 64 || L == 96 || L == 128 || L == 192 || L == 256; }
+
+int batched_wf_lds(int fast, int L) {
+  switch (L) {
+    case 64: return bw_lds_L<64>(fast);
+    case 96: return bw_lds_L<96>(fast);
+    case 128: return bw_lds_L<128>(fast);
+    case 192: return bw_lds_L<192>(fast);
+    case 256: return bw_lds_L<256>(fast);
+    default: return -1;
+  }
+}
+
+int batched_wf_tiles(const PassArgs& a) {
+  int ppw = 0, P = 32;
+  switch (a.L) {
+    case 64: ppw = WF<64>::PPW; break;
+    case 96: ppw = WF<96>::PPW; break;
+    case 128: ppw = WF<128>::PPW; break;
+    case 192: ppw = WF<192>::PPW; break;
+    case 256: ppw = WF<256>::PPW; break;
+    default: return 0;
+  }
+  if (a.fast == FAST_R2R_C) {
+    const long long pairs = (long long)((a.Np + 1) / 2) * a.No;
+    const long long per = (long long)kBatchWaves * ppw;
+    return (int)((pairs + per - 1) / per);
+  }
+  return ((a.Np + P - 1) / P) * a.No;
+}
+
+int batched_wf_group(const PassArgs& a) {
+  if (a.fast == FAST_R2R_C) return 1;
+  switch (a.L) {
+    case 64: return BW<64>::S;
+    case 96: return BW<96>::S;
+    case 128: return BW<128>::S;
+    case 192: return BW<192>::S;
+    default: return BW<256>::S;
+  }
+}
+
+int batched_wf_blocks_per_cu(int xf, int lds) {
+  if (xf == X_DCT2) return bw_blocks_per_cu<X_DCT2, X_DCT3>(lds);
+  if (xf == X_DST2) return bw_blocks_per_cu<X_DST2, X_DST3>(lds);
+  return bw_blocks_per_cu<X_DCT1, X_DCT1>(lds);
+}
+
+hipError_t launch_batched_levels(int xf, const PassArgs* passes, const BatchItem* items,
+                                 const int* level_first, int nlevels, int* err, int lds,
+                                 hipStream_t s) {
+  if (xf == X_DCT2)
+    return bw_launch_levels<X_DCT2, X_DCT3>(passes, items, level_first, nlevels, err, lds, s);
+  if (xf == X_DST2)
+    return bw_launch_levels<X_DST2, X_DST3>(passes, items, level_first, nlevels, err, lds, s);
+  if (xf == X_DCT1)
+    return bw_launch_levels<X_DCT1, X_DCT1>(passes, items, level_first, nlevels, err, lds, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_wf(int xf, const PassArgs* passes, const BatchItem* items, int nitems,
+                             unsigned* counters, int ncounters, int* err, int grid, int lds,
+                             hipStream_t s) {
+  if (xf == X_DCT2)
+    return bw_launch<X_DCT2, X_DCT3>(passes, items, nitems, counters, ncounters, err, grid, lds, s);
+  if (xf == X_DST2)
+    return bw_launch<X_DST2, X_DST3>(passes, items, nitems, counters, ncounters, err, grid, lds, s);
+  if (xf == X_DCT1)
+    return bw_launch<X_DCT1, X_DCT1>(passes, items, nitems, counters, ncounters, err, grid, lds, s);
+  return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------- launch
 // Pencils per tile of the strided passes: runs of 128 bytes.
 int r2r_tile(int prec) { return prec == 0 ? 32 : 16; }
@@ -361,10 +833,14 @@ constexpr int r2r_waves(int P, int ppw) { return (P / 2) / ppw; }
 
 int r2r_lds_bytes(int fast, int L, int n, int prec) {
   const int cs = prec == 0 ? 8 : 16, es = cs / 2;
-  const int R0 = L >= 1024 ? 16 : 8, ppw = 64 / (L / R0);
+  const int R0 = wf_r0(L);
+  if (R0 <= 0 || (R0 % 3 == 0 && prec != 0)) return -1;  // 3 x 2^k: FP32 only
+  const int ppw = 64 / (L / R0);
   const int SL = slot_len(L);
   if (fast == FAST_R2R_C) return (L + n + kR2RContigWaves * ppw * SL) * cs;
   const int P = r2r_tile(prec);
+  // one pencil pair per lane group: the tile's pairs must fill whole wavefronts
+  if ((P / 2) % ppw != 0) return -1;
   return (L + n + r2r_waves(P, ppw) * ppw * SL) * cs + n * (P + 1) * es;
 }
 
@@ -385,35 +861,54 @@ hipError_t launch_bounded_L(const PassArgs& a, hipStream_t s) {
   constexpr int P = sizeof(T) == 4 ? 32 : 16;
   constexpr int W = r2r_waves(P, PPW);
   if (a.P != P) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(((a.Np + P - 1) / P) * a.No));
-  const int ntiles = (int)grid.x;
-  if (a.fast == FAST_R2R_SW) {
-    if (a.xb != r2r_partner(a.xf)) return hipErrorInvalidValue;
-    allow_lds<kb_strided<T, L, P, W, true, true>>();
-    const int nb = persistent_grid<kb_strided<T, L, P, W, true, true>>(64 * W, lds, ntiles);
-    if (ntiles > 4 * nb && !std::getenv("HP_R2R_NOPERS")) {
-      hipLaunchKernelGGL((kb_strided<T, L, P, W, true, true>), dim3(nb), dim3(64 * W), lds, s, a);
-    } else {
+  if constexpr (W < 1 || (P / 2) % PPW != 0) {
+    return hipErrorInvalidValue;  // the planner keeps such passes on the general kernels
+  } else {
+    const dim3 grid((unsigned)(((a.Np + P - 1) / P) * a.No));
+    const int ntiles = (int)grid.x;
+    // radix-12 lengths: the register prefetch of the persistent form would
+    // cost occupancy, so their tiles are one workgroup each
+    constexpr bool kPers = WF<L>::R0 % 3 != 0;
+    if (a.fast == FAST_R2R_SW) {
+      if (a.xb != r2r_partner(a.xf)) return hipErrorInvalidValue;
+      if constexpr (kPers) {
+        allow_lds<kb_strided<T, L, P, W, true, true>>();
+        const int nb = persistent_grid<kb_strided<T, L, P, W, true, true>>(64 * W, lds, ntiles);
+        if (ntiles > 4 * nb && !std::getenv("HP_R2R_NOPERS")) {
+          hipLaunchKernelGGL((kb_strided<T, L, P, W, true, true>), dim3(nb), dim3(64 * W), lds, s, a);
+          return hipGetLastError();
+        }
+      }
       allow_lds<kb_strided<T, L, P, W, true, false>>();
       hipLaunchKernelGGL((kb_strided<T, L, P, W, true, false>), grid, dim3(64 * W), lds, s, a);
-    }
-  } else {
-    allow_lds<kb_strided<T, L, P, W, false, true>>();
-    const int nb = persistent_grid<kb_strided<T, L, P, W, false, true>>(64 * W, lds, ntiles);
-    if (ntiles > 4 * nb) {
-      hipLaunchKernelGGL((kb_strided<T, L, P, W, false, true>), dim3(nb), dim3(64 * W), lds, s, a);
     } else {
+      if constexpr (kPers) {
+        allow_lds<kb_strided<T, L, P, W, false, true>>();
+        const int nb = persistent_grid<kb_strided<T, L, P, W, false, true>>(64 * W, lds, ntiles);
+        if (ntiles > 4 * nb) {
+          hipLaunchKernelGGL((kb_strided<T, L, P, W, false, true>), dim3(nb), dim3(64 * W), lds, s, a);
+          return hipGetLastError();
+        }
+      }
       allow_lds<kb_strided<T, L, P, W, false, false>>();
       hipLaunchKernelGGL((kb_strided<T, L, P, W, false, false>), grid, dim3(64 * W), lds, s, a);
     }
+    return hipGetLastError();
   }
-  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_bounded_T(const PassArgs& a, hipStream_t s) {
   switch (a.L) {
     case 64: return launch_bounded_L<T, 64>(a, s);
+    // 3 x 2^k lengths: FP32 only (radix-12 first stage; FP64 stays on the
+    // general kernels, see r2r_lds_bytes)
+    case 96:
+      if constexpr (sizeof(T) == 4) return launch_bounded_L<T, 96>(a, s);
+      else return hipErrorInvalidValue;
+    case 192:
+      if constexpr (sizeof(T) == 4) return launch_bounded_L<T, 192>(a, s);
+      else return hipErrorInvalidValue;
     case 128: return launch_bounded_L<T, 128>(a, s);
     case 256: return launch_bounded_L<T, 256>(a, s);
     case 512: return launch_bounded_L<T, 512>(a, s);

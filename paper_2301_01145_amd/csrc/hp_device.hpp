@@ -170,9 +170,61 @@ __device__ __forceinline__ void dft16(C2<T>* v) {
   }
 }
 
+// cos(pi m / 12) for any integer m, from the exact first-quadrant values
+// (m = 0..6: 1, cos 15, cos 30, cos 45, 1/2, cos 75 degrees, 0).
+__host__ __device__ constexpr double cospi12(int m) {
+  m %= 24;
+  if (m < 0) m += 24;
+  const int r = m <= 6 ? m : (m <= 12 ? 12 - m : (m <= 18 ? m - 12 : 24 - m));
+  const double c = r == 0 ? 1.0
+                 : r == 1 ? 0.96592582628906828674974319972890
+                 : r == 2 ? 0.86602540378443864676372317075294
+                 : r == 3 ? 0.70710678118654752440084436210485
+                 : r == 4 ? 0.5
+                 : r == 5 ? 0.25881904510252076234889883762405
+                          : 0.0;
+  return (m > 6 && m < 18) ? -c : c;
+}
+
+// N = N1 N2 point DFT (N divides 24) by one Cooley-Tukey split: with
+// x[N2 n1 + n2], N1-point DFTs over n1 for every n2, the twiddles
+// W_N^(n2 k1), then N2-point DFTs over n2, giving X[k1 + N1 k2].
+template <typename T, int N1, int N2, bool INV>
+__device__ __forceinline__ void dft_split(C2<T>* v) {
+  constexpr int N = N1 * N2;
+  static_assert(24 % N == 0, "split DFT for lengths dividing 24");
+  C2<T> a[N2][N1];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n2][n1] = v[N2 * n1 + n2];
+    dftR<T, N1, INV>(a[n2]);
+  }
+#pragma unroll
+  for (int n2 = 1; n2 < N2; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) {
+      const int m = (n2 * k1 * (24 / N)) % 24;  // W_N^(n2 k1) = exp(-+ i pi m / 12)
+      const T c = (T)cospi12(m), sn = (T)cospi12(m - 6);
+      a[n2][k1] = cmul(a[n2][k1], C2<T>{c, INV ? sn : -sn});
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) {
+    C2<T> b[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) b[n2] = a[n2][k1];
+    dftR<T, N2, INV>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) v[k1 + N1 * k2] = b[k2];
+  }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftN(C2<T>* v) {
   if constexpr (R == 16) dft16<T, INV>(v);
+  else if constexpr (R == 24) dft_split<T, 8, 3, INV>(v);
+  else if constexpr (R == 12) dft_split<T, 4, 3, INV>(v);
   else dftR<T, R, INV>(v);
 }
 

@@ -118,6 +118,14 @@ enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH
 // Derivative completion in the backward y pass of the free-space path.
 enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 
+// Elements per lane of the wavefront FFT of length L (0: no such FFT):
+// powers of two 64 .. 1024 (8, 16 from 1024) and 48, 96, 192 (12).
+__host__ __device__ constexpr int wf_r0(int L) {
+  return (L == 48 || L == 96 || L == 192) ? 12
+         : (L >= 64 && L <= 1024 && (L & (L - 1)) == 0) ? (L >= 1024 ? 16 : 8)
+                                                         : 0;
+}
+
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s);
@@ -197,6 +205,27 @@ hipError_t launch_zero_mode_noalloc(const PassArgs* a, const void* const* f, int
 hipError_t launch_batched(const PassArgs* passes, const BatchItem* items, int nitems,
                           unsigned* counters, int ncounters, int* err, int grid, int lds,
                           int prec, int big, hipStream_t s);
+// Batched persistent solve on the wavefront kernels (FP32, transform lengths
+// 64, 96, 128, 192, 256; hp_bounded.hip).  Passes carry fast = FAST_R2R_C /
+// FAST_R2R_S / FAST_R2R_SW, the wavefront twiddles and P = 32; xf is the
+// forward type of the batch (DCT-II, DST-II or DCT-I; the backward type is
+// its Table 1 partner).  Tiles: batched_wf_tiles per pass; a strided item
+// should hold a multiple of batched_wf_group tiles (one per group of
+// wavefronts of the workgroup).  LDS: the largest batched_wf_lds of its passes.
+bool batched_wf_length(int L);
+int batched_wf_lds(int fast, int L);
+int batched_wf_tiles(const PassArgs& a);
+int batched_wf_group(const PassArgs& a);
+int batched_wf_blocks_per_cu(int xf, int lds);
+hipError_t launch_batched_wf(int xf, const PassArgs* passes, const BatchItem* items, int nitems,
+                             unsigned* counters, int ncounters, int* err, int grid, int lds,
+                             hipStream_t s);
+// The same tile bodies as one launch per pass level (no queue, no waits):
+// level l runs items [level_first[l], level_first[l + 1]), one workgroup each;
+// err[0] is cleared (there is no wait to fail).
+hipError_t launch_batched_levels(int xf, const PassArgs* passes, const BatchItem* items,
+                                 const int* level_first, int nlevels, int* err, int lds,
+                                 hipStream_t s);
 // Resident workgroups per CU of the persistent kernel with `lds` bytes of LDS.
 int batched_blocks_per_cu(int lds, int prec, int big);
 }  // namespace hp

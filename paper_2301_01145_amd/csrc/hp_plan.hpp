@@ -77,6 +77,14 @@ struct hp_plan_s {
   unsigned* batch_counters = nullptr;
   int batch_nitems = 0, batch_ncounters = 0, batch_grid = 0, batch_lds = 0;
   int batch_big = 0;  // register budget of the persistent kernel (PassArgs.big)
+  // kernels of the batched solve: 0 = general passes in one persistent launch
+  // (k_batched); 1 = wavefront tile bodies in one persistent launch
+  // (k_batched_wf, forward type batch_xf); 2 = the wavefront tile bodies as
+  // one launch per pass level (k_batched_level).  batch_mode -1 = the
+  // planner's choice (1 where every pass allows it, else 0); 0, 1, 2 chosen
+  // by the autotuner (1 and 2 fall back to 0 where not allowed)
+  int batch_wf = 0, batch_xf = 0, batch_mode = -1;
+  std::vector<int> batch_level_first;  // mode 2: first item of every level, then the item count
   std::vector<hp::PassRec> batch_passes;
   int batch_tiles = 0;  // tiles per work item (0: the default)
   double* zm_partial = nullptr;  // per-block partial sums of the zero-mode query
@@ -104,6 +112,7 @@ void plan_free(hp_plan p, void* ptr);
 hp_status launch_rec(hp_plan p, const PassRec& r);
 bool radix_ok(int L, const int* radix, int nstage);
 hp_status plan_outputs(hp_plan p, Problem& P);
+hp_status plan_fast_twiddles(hp_plan p, int L, const void** out);
 hp_status passes_for(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out);
 double passes_model_bytes(hp_plan p, const std::vector<PassRec>& ps);
 // implemented in hp_batched.cpp

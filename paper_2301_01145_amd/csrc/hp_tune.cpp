@@ -10,7 +10,8 @@
 //     and both register budgets;
 //   * wavefront passes: tile widths of 8 and 16 pencils and, for the x and
 //     backward-y passes, both output-tile schemes;
-//   * batched plans: 1, 2, 4 or 8 tiles per work item of the persistent kernel.
+//   * batched plans: the persistent kernel's tile bodies (wavefront or general
+//     passes) and 1, 2, 4 or 8 tiles per work item.
 // A configuration replaces the planner's default only when it is at least 3%
 // faster, and the choices are kept only when the whole solve is faster with
 // them (batched plans: the combination of pass configurations and work-item
@@ -263,6 +264,7 @@ struct Tuner {
     p->tuned_passes = 0;
     p->tune_default_ms = p->tune_best_ms = 0.0;
     p->batch_tiles = 0;
+    p->batch_mode = -1;
     // scratch bindings: pseudo-random sources, zeroed outputs; the caller's
     // bindings are restored on every exit path
     struct Saved {
@@ -291,6 +293,7 @@ struct Tuner {
       p->tuned.clear();
       p->tuned_passes = 0;
       p->batch_tiles = 0;
+      p->batch_mode = -1;
       if (p->batched) (void)batched_setup(p);
     }
     return s;
@@ -320,25 +323,37 @@ struct Tuner {
     std::set<unsigned long long> done;
     for (auto& P : p->probs) HP_TRY_T(tune_list(P, done));
     if (p->batched) {
-      // whole-batch timing decides between the default and tuned pass
-      // configurations and the work-item size of the persistent kernel
+      // whole-batch timing decides between the kernels of the persistent
+      // launch (wavefront tile bodies where the batch allows them; the general
+      // passes with default or tuned configurations) and its work-item size
       const std::map<unsigned long long, Tune> per_pass = p->tuned;
       const int npass = p->tuned_passes;
+      const int def_mode = p->batch_wf;
       double best = t_def;
-      int best_tiles = 0, best_use = 0;
-      for (int use = 0; use < (per_pass.empty() ? 1 : 2); ++use) {
-        p->tuned = use ? per_pass : std::map<unsigned long long, Tune>{};
-        for (int tiles : {1, 2, 4, 8}) {
-          p->batch_tiles = tiles;
-          HP_TRY_T(batched_setup(p));
-          const double ms = time([&] { return batched_solve(p); });
-          if (ms >= 0.0 && ms < 0.97 * best) {
-            best = ms;
-            best_tiles = tiles;
-            best_use = use;
+      int best_tiles = 0, best_use = 0, best_mode = -1;
+      for (int mode : {1, 2, 0}) {
+        p->batch_mode = mode;
+        p->tuned.clear();
+        HP_TRY_T(batched_setup(p));
+        if (mode != 0 && !p->batch_wf) continue;  // no wavefront form of this batch
+        const int uses = (mode != 0 || per_pass.empty()) ? 1 : 2;
+        for (int use = 0; use < uses; ++use) {
+          p->tuned = use ? per_pass : std::map<unsigned long long, Tune>{};
+          for (int tiles : {1, 2, 4, 8}) {
+            p->batch_tiles = tiles;
+            HP_TRY_T(batched_setup(p));
+            const double ms = time([&] { return batched_solve(p); });
+            if (ms >= 0.0 && ms < 0.97 * best) {
+              best = ms;
+              best_tiles = tiles;
+              best_use = use;
+              best_mode = mode;
+            }
           }
         }
       }
+      // nothing 3% faster: the planner's default kernel and work-item size
+      p->batch_mode = best_mode < 0 ? (def_mode ? -1 : 0) : best_mode;
       p->tuned = best_use ? per_pass : std::map<unsigned long long, Tune>{};
       p->tuned_passes = best_use ? npass : 0;
       p->batch_tiles = best_tiles;

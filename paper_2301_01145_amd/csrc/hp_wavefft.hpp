@@ -1,11 +1,13 @@
-// Wavefront-level FFT of power-of-two length L = 64 .. 1024 (gfx950).
+// Wavefront-level FFT of length L = 64 .. 1024 (powers of two) and
+// L = 48, 96, 192 (3 times a power of two) (gfx950).
 //
 // A pencil of length L is held by G = L / R0 lanes, R0 elements per lane:
-// lane g holds x[g + G i], i < R0.  The first Stockham stage (radix R0) works
-// on those registers directly; the following radix-8 (and a final radix-2/4)
-// stages exchange data through a wavefront-private LDS slot, so no workgroup
-// barrier is needed inside the FFT.  After the last stage lane g holds
-// X[g + G i] again.
+// lane g holds x[g + G i], i < R0.  The first Stockham stage (radix R0: 8 or
+// 16 for powers of two, 12 = 4 x 3 otherwise) works on those registers
+// directly; the following radix-8 (and a final radix-2/4) stages (after
+// radix 12: radix 4, then 2 or 4) exchange data through a wavefront-private
+// LDS slot, so no workgroup barrier is needed inside the FFT.  After the last
+// stage lane g holds X[g + G i] again.
 #pragma once
 
 #include <algorithm>
@@ -19,9 +21,10 @@ namespace hp {
 
 template <int L>
 struct WF {
-  static constexpr int R0 = L >= 1024 ? 16 : 8;  // elements per lane
-  static constexpr int G = L / R0;               // lanes per pencil
-  static constexpr int PPW = 64 / G;             // pencils per wavefront
+  static constexpr int R0 = wf_r0(L);  // elements per lane
+  static constexpr int G = L / R0;     // lanes per pencil
+  static constexpr int PPW = 64 / G;   // pencils per wavefront
+  static_assert(R0 > 0 && G * R0 == L && 64 % G == 0, "wavefront FFT length");
 };
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
@@ -98,6 +101,7 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
         // NS >= 2^S the step is constant; for NS < 2^S, k < NS keeps
         // k + NS t within the same 2^S block as NS t
         if constexpr (NS % (1 << PW::S_) == 0) row = PW::row(m0 + k) + t * PW::row(NS);
+        else if constexpr ((NS & (NS - 1)) != 0) row = PW::row(m0 + k + NS * t);  // NS = 12
         else row = PW::row(m0) + k + NS * t + ((NS * t) >> PW::S_) * PW::K_;
         buf[row * bs] = v[b * R + t];
       }
@@ -119,14 +123,25 @@ __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int 
   if constexpr (HALF) dftN_half<T, R0, INV>(x);
   else dftN<T, R0, INV>(x);
   wave_sync();
-  // element g R0 + t, t < R0 in {8, 16}: never crosses a multiple of 16
-  const int r0 = PadA::row(g * R0);
+  if constexpr (R0 % 16 == 0 || 16 % R0 == 0) {
+    // element g R0 + t, t < R0 in {8, 16}: never crosses a multiple of 16
+    const int r0 = PadA::row(g * R0);
 #pragma unroll
-  for (int t = 0; t < R0; ++t) buf[(r0 + t) * bs] = x[t];
-  wave_sync();
-  if constexpr (G == 8) {
-    wstage<T, L, 8, R0, true, INV, PadA, PadA>(x, buf, bs, g, tw);
+    for (int t = 0; t < R0; ++t) buf[(r0 + t) * bs] = x[t];
   } else {
+#pragma unroll
+    for (int t = 0; t < R0; ++t) buf[PadA::row(g * R0 + t) * bs] = x[t];
+  }
+  wave_sync();
+  if constexpr (G <= 8 && R0 % G == 0) {
+    // one more stage, of radix G (R0 = 8, G = 8; R0 = 12, G = 4)
+    wstage<T, L, G, R0, true, INV, PadA, PadA>(x, buf, bs, g, tw);
+  } else if constexpr (R0 % 3 == 0) {
+    // R0 = 12: a radix-4 stage, then radix G / 4 (2 or 4)
+    wstage<T, L, 4, R0, false, INV, PadA, PadA>(x, buf, bs, g, tw);
+    wstage<T, L, G / 4, 4 * R0, true, INV, PadA, PadA>(x, buf, bs, g, tw + 3 * R0);
+  } else {
+    static_assert((R0 & (R0 - 1)) == 0, "three stages: power-of-two lengths only");
     wstage<T, L, 8, R0, false, INV, PadA, PB>(x, buf, bs, g, tw);
     wstage<T, L, G / 8, 8 * R0, true, INV, PB, PB>(x, buf, bs, g, tw + 7 * R0);
   }

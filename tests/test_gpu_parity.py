@@ -58,7 +58,9 @@ def test_bounded_tiles(bc, grid, prec):
 # bounded kernels (ragged 32-pencil tiles where an axis has N_c - 1 or
 # N_c + 1 unknowns).
 FASTB = [([64, 32, 128], "fd2", True), ([32, 64, 32], "ps", False), ([64, 128], "fd2", True),
-         ([128, 32], "ps", False), ([256, 32, 32], "fd2", True), ([32, 32, 256], "ps", False)]
+         ([128, 32], "ps", False), ([256, 32, 32], "fd2", True), ([32, 32, 256], "ps", False),
+         # lengths 96 and 192 (radix-12 first stage; FP32 on the wavefront kernels)
+         ([48, 96, 64], "fd2", True), ([96, 48], "ps", False), ([32, 48, 96], "ps", False)]
 
 
 @pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("dirichlet", "staggered"),
@@ -76,9 +78,10 @@ def test_bounded_fast(bc, grid, nc, kernel, inhom, prec):
 @pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("neumann", "staggered"),
                                      ("dirichlet", "staggered"), ("neumann", "regular")])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_bounded_fast_matches_general(bc, grid, prec, monkeypatch):
-    """The same power-of-two 3D problem on the wavefront and the general kernels."""
-    nc = [64, 32, 128]
+@pytest.mark.parametrize("nc", [[64, 32, 128], [96, 48, 64]])
+def test_bounded_fast_matches_general(bc, grid, prec, nc, monkeypatch):
+    """The same 3D problem (transform lengths 2^k, 96, 192) on the wavefront
+    and the general kernels."""
     f, faces = case_input(bc, grid, nc, 1, True, prec, seed=29)
     fast, _ = gpu_solve(bc, grid, nc, LO, HI, f, "fd2", "none", prec, 1, faces)
     monkeypatch.setenv("HP_GENERIC", "1")

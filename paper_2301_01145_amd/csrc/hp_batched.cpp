@@ -73,6 +73,15 @@ hp_status to_wf(hp_plan p, PassArgs& a) {
   return HP_OK;
 }
 
+// Kind of a wavefront pass in the level launches (BatchGroup.kind); general
+// passes are all kind 0 (they are never launched by level).
+int pass_kind(const PassArgs& a, int xf) {
+  if (a.fast == FAST_R2R_SW) return 4;
+  if (a.fast == FAST_R2R_C) return a.xf == xf ? 0 : 1;
+  if (a.fast == FAST_R2R_S) return a.xf == xf ? 2 : 3;
+  return 0;
+}
+
 // Tiles of a pass in the kernel of the plan's mode.
 int mode_tiles(hp_plan p, const PassArgs& a) { return p->batch_wf ? batched_wf_tiles(a) : tiles_of(a); }
 
@@ -129,25 +138,39 @@ hp_status batched_setup(hp_plan p) {
   p->batch_big = big;
   const int per_item = batch_tiles_of(p);
   std::vector<BatchItem> items;
-  p->batch_level_first.clear();
+  p->batch_groups.clear();
   for (int lev = 0; lev < maxlev; ++lev) {
-    p->batch_level_first.push_back((int)items.size());
-    for (size_t q = 0; q < lists.size(); ++q) {
-      if (lev >= (int)lists[q].size()) continue;
-      const int gp = first[q] + lev;
-      const int dep = lev > 0 ? gp - 1 : -1;
-      const int need = lev > 0 ? mode_tiles(p, lists[q][lev - 1].a) : 0;
-      // consecutive tiles of a pass share one item (one queue step, one
-      // dependency check and one release per item); a wavefront strided item
-      // holds one tile per group of wavefronts for every step
-      const PassArgs& a = lists[q][lev].a;
-      const int nt = mode_tiles(p, a);
-      const int step = per_item * (p->batch_wf ? batched_wf_group(a) : 1);
-      for (int t = 0; t < nt; t += step)
-        items.push_back({gp, t, std::min(step, nt - t), dep, need});
+    // within a level, the problems' passes grouped by transform length and
+    // kind (the level launches run one kernel instance per group; the
+    // persistent kernels take any order within a level)
+    std::vector<std::pair<int, int>> keys;
+    for (size_t q = 0; q < lists.size(); ++q)
+      if (lev < (int)lists[q].size()) keys.push_back({lists[q][lev].a.L, pass_kind(lists[q][lev].a, xf)});
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    for (auto key : keys) {
+      BatchGroup grp{(int)items.size(), 0, key.first, key.second, 0};
+      for (size_t q = 0; q < lists.size(); ++q) {
+        if (lev >= (int)lists[q].size() || lists[q][lev].a.L != key.first ||
+            pass_kind(lists[q][lev].a, xf) != key.second)
+          continue;
+        grp.lds = std::max(grp.lds, lists[q][lev].a.lds_bytes);
+        const int gp = first[q] + lev;
+        const int dep = lev > 0 ? gp - 1 : -1;
+        const int need = lev > 0 ? mode_tiles(p, lists[q][lev - 1].a) : 0;
+        // consecutive tiles of a pass share one item (one queue step, one
+        // dependency check and one release per item); a wavefront strided item
+        // holds one tile per group of wavefronts for every step
+        const PassArgs& a = lists[q][lev].a;
+        const int nt = mode_tiles(p, a);
+        const int step = per_item * (p->batch_wf ? batched_wf_group(a) : 1);
+        for (int t = 0; t < nt; t += step)
+          items.push_back({gp, t, std::min(step, nt - t), dep, need});
+      }
+      grp.count = (int)items.size() - grp.first;
+      p->batch_groups.push_back(grp);
     }
   }
-  p->batch_level_first.push_back((int)items.size());
   p->batch_nitems = (int)items.size();
   p->batch_ncounters = 1 + npass;
   p->batch_lds = lds;
@@ -227,10 +250,9 @@ hp_status batched_solve(hp_plan p) {
   hipError_t e =
       p->batch_wf == 2
           ? launch_batched_levels(p->batch_xf, (const PassArgs*)p->batch_probs,
-                                  (const BatchItem*)p->batch_items, p->batch_level_first.data(),
-                                  (int)p->batch_level_first.size() - 1,
-                                  (int*)(p->batch_counters + p->batch_ncounters), p->batch_lds,
-                                  p->stream)
+                                  (const BatchItem*)p->batch_items, p->batch_groups.data(),
+                                  (int)p->batch_groups.size(),
+                                  (int*)(p->batch_counters + p->batch_ncounters), p->stream)
       : p->batch_wf
           ? launch_batched_wf(p->batch_xf, (const PassArgs*)p->batch_probs,
                               (const BatchItem*)p->batch_items, p->batch_nitems, p->batch_counters,

@@ -483,13 +483,8 @@ __device__ __forceinline__ void bw_tables(const BwArgs& a, C2<float>* tw, C2<flo
     for (int m = tid; m < a.n; m += NT) q[m] = a.qtw[m];
 }
 
-// Each tile body is a function of its own (not inlined into the kernel), so
-// that it is register-allocated like a kernel of its own; its arguments are
-// copied into scalar registers on entry (bw_uniform).
 template <int L, int X>
-__device__ __attribute__((noinline)) void bw_contig(const BwArgs* ap, unsigned char* smem, int tile,
-                                                    int ntile) {
-  const BwArgs a = bw_uniform(*ap);
+__device__ __forceinline__ void bw_contig(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   using T = float;
   const int n = a.n;
@@ -512,9 +507,22 @@ __device__ __attribute__((noinline)) void bw_contig(const BwArgs* ap, unsigned c
     const int pa = valid ? 2 * (int)(pr % pairs_p) : 0;
     const bool vb = valid && pa + 1 < a.Np;
     const long long ib = (long long)o * a.in_so + (long long)pa * a.in_sp;
-    for (int j = g; j < n; j += G) {
-      R[j] = valid ? a.in[ib + (long long)j * a.in_sj] : (T)0;
-      R[n + j] = vb ? a.in[ib + a.in_sp + (long long)j * a.in_sj] : (T)0;
+    // every load of the pair in flight at once (compile-time trip count)
+    constexpr int NJ = (BW<L>::MAXN + G - 1) / G;
+    T va[NJ], vbv[NJ];
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      const int j = g + r * G;
+      va[r] = (valid && j < n) ? a.in[ib + (long long)j * a.in_sj] : (T)0;
+      vbv[r] = (vb && j < n) ? a.in[ib + a.in_sp + (long long)j * a.in_sj] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      const int j = g + r * G;
+      if (j < n) {
+        R[j] = va[r];
+        R[n + j] = vbv[r];
+      }
     }
     wave_sync();
     const long long ob = (long long)o * a.out_so + (long long)pa * a.out_sp;
@@ -533,9 +541,7 @@ __device__ __attribute__((noinline)) void bw_contig(const BwArgs* ap, unsigned c
 }
 
 template <int L, int XF, int XO, bool SW>
-__device__ __attribute__((noinline)) void bw_strided(const BwArgs* ap, unsigned char* smem, int tile,
-                                                     int ntile) {
-  const BwArgs a = bw_uniform(*ap);
+__device__ __forceinline__ void bw_strided(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, PPW = WF<L>::PPW;
   constexpr int P = BW<L>::P, W = BW<L>::W, S = BW<L>::S, TS = BW<L>::TS, PPL = BW<L>::PPL;
   constexpr int MAXN = BW<L>::MAXN, NTS = 64 * W;
@@ -560,9 +566,23 @@ __device__ __attribute__((noinline)) void bw_strided(const BwArgs* ap, unsigned 
     const int o = active ? t / tiles_p : 0, p0 = active ? (t % tiles_p) * P : 0;
     const int np = active ? min(P, a.Np - p0) : 0;
     const long long ib = (long long)o * a.in_so + (long long)p0 * a.in_sp;
-    for (int e = ts; e < n * P; e += NTS) {
-      const int j = e / P, c = e - (e / P) * P;
-      tile_s[j * TS + c] = c < np ? a.in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
+    // eight loads in flight per thread before their LDS stores: one load at a
+    // time waits out the memory latency once per element (a register copy of
+    // the whole tile spilled)
+    constexpr int U = 8;
+    for (int e0 = ts; e0 < n * P; e0 += U * NTS) {
+      T v8[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NTS;
+        const int j = e / P, c = e % P;
+        v8[u] = (j < n && c < np) ? a.in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NTS;
+        if (e < n * P) tile_s[(e / P) * TS + e % P] = v8[u];
+      }
     }
     __syncthreads();
     for (int r = 0; r < PPL && active; ++r) {
@@ -608,28 +628,55 @@ __device__ __attribute__((noinline)) void bw_strided(const BwArgs* ap, unsigned 
   }
 }
 
+// The persistent kernel calls every tile body as a function of its own (not
+// inlined), so that each is register-allocated on its own: inlined into the
+// loop over items their values stayed live together and spilled.  The
+// arguments are copied into scalar registers on entry (bw_uniform).  The
+// level launches have no loop over items and inline the bodies.
+template <int L, int X>
+__device__ __attribute__((noinline)) void bw_contig_call(const BwArgs* ap, unsigned char* smem,
+                                                         int tile, int ntile) {
+  bw_contig<L, X>(bw_uniform(*ap), smem, tile, ntile);
+}
+template <int L, int XF, int XO, bool SW>
+__device__ __attribute__((noinline)) void bw_strided_call(const BwArgs* ap, unsigned char* smem,
+                                                          int tile, int ntile) {
+  bw_strided<L, XF, XO, SW>(bw_uniform(*ap), smem, tile, ntile);
+}
+
 // One item: ntile tiles of pass a, for the transform pair (XF, XB) of the batch.
-template <int L, int XF, int XB>
-__device__ void bw_item_L(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
+template <int L, int XF, int XB, bool CALL>
+__device__ __forceinline__ void bw_item_L(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
   if (a.fast == FAST_R2R_C) {
-    if (a.xf == XF) bw_contig<L, XF>(&a, smem, tile, ntile);
-    else bw_contig<L, XB>(&a, smem, tile, ntile);
+    if constexpr (CALL) {
+      if (a.xf == XF) bw_contig_call<L, XF>(&a, smem, tile, ntile);
+      else bw_contig_call<L, XB>(&a, smem, tile, ntile);
+    } else {
+      if (a.xf == XF) bw_contig<L, XF>(a, smem, tile, ntile);
+      else bw_contig<L, XB>(a, smem, tile, ntile);
+    }
   } else if (a.fast == FAST_R2R_S) {
-    if (a.xf == XF) bw_strided<L, XF, XF, false>(&a, smem, tile, ntile);
-    else bw_strided<L, XB, XB, false>(&a, smem, tile, ntile);
+    if constexpr (CALL) {
+      if (a.xf == XF) bw_strided_call<L, XF, XF, false>(&a, smem, tile, ntile);
+      else bw_strided_call<L, XB, XB, false>(&a, smem, tile, ntile);
+    } else {
+      if (a.xf == XF) bw_strided<L, XF, XF, false>(a, smem, tile, ntile);
+      else bw_strided<L, XB, XB, false>(a, smem, tile, ntile);
+    }
   } else {
-    bw_strided<L, XF, XB, true>(&a, smem, tile, ntile);
+    if constexpr (CALL) bw_strided_call<L, XF, XB, true>(&a, smem, tile, ntile);
+    else bw_strided<L, XF, XB, true>(a, smem, tile, ntile);
   }
 }
 
-template <int XF, int XB>
-__device__ void bw_item(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
+template <int XF, int XB, bool CALL>
+__device__ __forceinline__ void bw_item(const BwArgs& a, unsigned char* smem, int tile, int ntile) {
   switch (a.L) {
-    case 64: bw_item_L<64, XF, XB>(a, smem, tile, ntile); break;
-    case 96: bw_item_L<96, XF, XB>(a, smem, tile, ntile); break;
-    case 128: bw_item_L<128, XF, XB>(a, smem, tile, ntile); break;
-    case 192: bw_item_L<192, XF, XB>(a, smem, tile, ntile); break;
-    default: bw_item_L<256, XF, XB>(a, smem, tile, ntile); break;
+    case 64: bw_item_L<64, XF, XB, CALL>(a, smem, tile, ntile); break;
+    case 96: bw_item_L<96, XF, XB, CALL>(a, smem, tile, ntile); break;
+    case 128: bw_item_L<128, XF, XB, CALL>(a, smem, tile, ntile); break;
+    case 192: bw_item_L<192, XF, XB, CALL>(a, smem, tile, ntile); break;
+    default: bw_item_L<256, XF, XB, CALL>(a, smem, tile, ntile); break;
   }
 }
 
@@ -680,7 +727,7 @@ __global__ void __launch_bounds__(64 * kBatchWaves, 4)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (ok) {
       const BwArgs args = bw_args(passes[bi.pass]);
-      bw_item<XF, XB>(args, smem, bi.tile, bi.ntile);
+      bw_item<XF, XB, true>(args, smem, bi.tile, bi.ntile);
     }
     // release: this item's stores before its tiles are counted
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -692,10 +739,15 @@ __global__ void __launch_bounds__(64 * kBatchWaves, 4)
   }
 }
 
-// One pass level of the batch (the passes of every problem that have no
-// dependency left): one workgroup per item, no queue, no waiting; the launch
-// boundary orders the levels.
-template <int XF, int XB>
+// One pass level of the batch for one transform length L and one pass kind
+// (the passes of every problem that have no dependency left, transform along
+// L and are of that kind): one workgroup per item, no queue, no waiting; the
+// launch boundaries order the levels.  One instance per (L, kind) holds a
+// single tile body, register-allocated like the single-plan kernels (all
+// lengths and kinds in one kernel did not fit in 128 VGPRs).
+// KIND: 0 / 1 contiguous pass of type XF / XB, 2 / 3 strided pass of type
+// XF / XB, 4 sandwich (XF, multiplier, XB).
+template <int XF, int XB, int L, int KIND>
 __global__ void __launch_bounds__(64 * kBatchWaves, 4)
     k_batched_level(const PassArgs* passes, const BatchItem* items, int* err) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -704,21 +756,56 @@ __global__ void __launch_bounds__(64 * kBatchWaves, 4)
   bi.pass = uni(bi.pass);
   bi.tile = uni(bi.tile);
   bi.ntile = uni(bi.ntile);
-  const BwArgs args = bw_args(passes[bi.pass]);
-  bw_item<XF, XB>(args, smem, bi.tile, bi.ntile);
+  const BwArgs a = bw_args(passes[bi.pass]);
+  if constexpr (KIND == 0) bw_contig<L, XF>(a, smem, bi.tile, bi.ntile);
+  else if constexpr (KIND == 1) bw_contig<L, XB>(a, smem, bi.tile, bi.ntile);
+  else if constexpr (KIND == 2) bw_strided<L, XF, XF, false>(a, smem, bi.tile, bi.ntile);
+  else if constexpr (KIND == 3) bw_strided<L, XB, XB, false>(a, smem, bi.tile, bi.ntile);
+  else bw_strided<L, XF, XB, true>(a, smem, bi.tile, bi.ntile);
+}
+
+template <int XF, int XB, int L, int KIND>
+hipError_t bw_launch_group(const PassArgs* passes, const BatchItem* items, int n, int* err, int lds,
+                           hipStream_t s) {
+  allow_lds<k_batched_level<XF, XB, L, KIND>>();
+  hipLaunchKernelGGL((k_batched_level<XF, XB, L, KIND>), dim3(n), dim3(64 * kBatchWaves), lds, s,
+                     passes, items, err);
+  return hipGetLastError();
+}
+
+template <int XF, int XB, int L>
+hipError_t bw_launch_kind(const BatchGroup& g, const PassArgs* passes, const BatchItem* it, int* e,
+                          hipStream_t s) {
+  switch (g.kind) {
+    case 0: return bw_launch_group<XF, XB, L, 0>(passes, it, g.count, e, g.lds, s);
+    case 1: return bw_launch_group<XF, XB, L, 1>(passes, it, g.count, e, g.lds, s);
+    case 2: return bw_launch_group<XF, XB, L, 2>(passes, it, g.count, e, g.lds, s);
+    case 3: return bw_launch_group<XF, XB, L, 3>(passes, it, g.count, e, g.lds, s);
+    case 4: return bw_launch_group<XF, XB, L, 4>(passes, it, g.count, e, g.lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int XF, int XB>
-hipError_t bw_launch_levels(const PassArgs* passes, const BatchItem* items, const int* level_first,
-                            int nlevels, int* err, int lds, hipStream_t s) {
-  allow_lds<k_batched_level<XF, XB>>();
-  for (int l = 0; l < nlevels; ++l) {
-    const int n = level_first[l + 1] - level_first[l];
-    if (n <= 0) continue;
-    hipLaunchKernelGGL((k_batched_level<XF, XB>), dim3(n), dim3(64 * kBatchWaves), lds, s, passes,
-                       items + level_first[l], l == 0 ? err : nullptr);
+hipError_t bw_launch_levels(const PassArgs* passes, const BatchItem* items, const BatchGroup* groups,
+                            int ngroups, int* err, hipStream_t s) {
+  for (int k = 0; k < ngroups; ++k) {
+    const BatchGroup& g = groups[k];
+    if (g.count <= 0) continue;
+    int* e = k == 0 ? err : nullptr;
+    const BatchItem* it = items + g.first;
+    hipError_t r;
+    switch (g.L) {
+      case 64: r = bw_launch_kind<XF, XB, 64>(g, passes, it, e, s); break;
+      case 96: r = bw_launch_kind<XF, XB, 96>(g, passes, it, e, s); break;
+      case 128: r = bw_launch_kind<XF, XB, 128>(g, passes, it, e, s); break;
+      case 192: r = bw_launch_kind<XF, XB, 192>(g, passes, it, e, s); break;
+      case 256: r = bw_launch_kind<XF, XB, 256>(g, passes, it, e, s); break;
+      default: r = hipErrorInvalidValue;
+    }
+    if (r != hipSuccess) return r;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 template <int XF, int XB>
@@ -800,14 +887,10 @@ int batched_wf_blocks_per_cu(int xf, int lds) {
 }
 
 hipError_t launch_batched_levels(int xf, const PassArgs* passes, const BatchItem* items,
-                                 const int* level_first, int nlevels, int* err, int lds,
-                                 hipStream_t s) {
-  if (xf == X_DCT2)
-    return bw_launch_levels<X_DCT2, X_DCT3>(passes, items, level_first, nlevels, err, lds, s);
-  if (xf == X_DST2)
-    return bw_launch_levels<X_DST2, X_DST3>(passes, items, level_first, nlevels, err, lds, s);
-  if (xf == X_DCT1)
-    return bw_launch_levels<X_DCT1, X_DCT1>(passes, items, level_first, nlevels, err, lds, s);
+                                 const BatchGroup* groups, int ngroups, int* err, hipStream_t s) {
+  if (xf == X_DCT2) return bw_launch_levels<X_DCT2, X_DCT3>(passes, items, groups, ngroups, err, s);
+  if (xf == X_DST2) return bw_launch_levels<X_DST2, X_DST3>(passes, items, groups, ngroups, err, s);
+  if (xf == X_DCT1) return bw_launch_levels<X_DCT1, X_DCT1>(passes, items, groups, ngroups, err, s);
   return hipErrorInvalidValue;
 }
 

@@ -220,12 +220,17 @@ int batched_wf_blocks_per_cu(int xf, int lds);
 hipError_t launch_batched_wf(int xf, const PassArgs* passes, const BatchItem* items, int nitems,
                              unsigned* counters, int ncounters, int* err, int grid, int lds,
                              hipStream_t s);
-// The same tile bodies as one launch per pass level (no queue, no waits):
-// level l runs items [level_first[l], level_first[l + 1]), one workgroup each;
+// The same tile bodies as one launch per pass level, transform length and
+// pass kind (no queue, no waits): group k runs items [first, first + count),
+// all of one level, one length L and one kind (0 / 1 contiguous pass of the
+// forward / backward type, 2 / 3 strided pass of the forward / backward type,
+// 4 sandwich), one workgroup each with lds bytes of LDS, in group order;
 // err[0] is cleared (there is no wait to fail).
+struct BatchGroup {
+  int first, count, L, kind, lds;
+};
 hipError_t launch_batched_levels(int xf, const PassArgs* passes, const BatchItem* items,
-                                 const int* level_first, int nlevels, int* err, int lds,
-                                 hipStream_t s);
+                                 const BatchGroup* groups, int ngroups, int* err, hipStream_t s);
 // Resident workgroups per CU of the persistent kernel with `lds` bytes of LDS.
 int batched_blocks_per_cu(int lds, int prec, int big);
 }  // namespace hp

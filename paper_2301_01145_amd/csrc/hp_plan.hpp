@@ -84,7 +84,7 @@ struct hp_plan_s {
   // planner's choice (1 where every pass allows it, else 0); 0, 1, 2 chosen
   // by the autotuner (1 and 2 fall back to 0 where not allowed)
   int batch_wf = 0, batch_xf = 0, batch_mode = -1;
-  std::vector<int> batch_level_first;  // mode 2: first item of every level, then the item count
+  std::vector<hp::BatchGroup> batch_groups;  // mode 2: launches (level, length) in order
   std::vector<hp::PassRec> batch_passes;
   int batch_tiles = 0;  // tiles per work item (0: the default)
   double* zm_partial = nullptr;  // per-block partial sums of the zero-mode query

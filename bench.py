@@ -26,16 +26,31 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_digest():
-    """sha256 over the library sources (name + bytes, sorted): HBM counters
-    recorded for one digest do not describe kernels built from another."""
+# Sources of the free-space / periodic wavefront kernels (the headline's
+# passes): their code, the wavefront FFT and the radix DFTs, plus the pass
+# descriptor struct (PassArgs in hp_internal.hpp).  Changes elsewhere in the
+# library do not change these kernels.
+HEADLINE_SOURCES = ("hp_fast.hip", "hp_wavefft.hpp", "hp_device.hpp")
+
+
+def _pass_args_text():
+    with open(os.path.join(ROOT, "paper_2301_01145_amd", "csrc", "hp_internal.hpp"), "rb") as fh:
+        t = fh.read()
+    a = t.index(b"struct PassArgs {")
+    return t[a:t.index(b"};", a) + 2]
+
+
+def kernel_source_digest(files=HEADLINE_SOURCES):
+    """sha256 over the named library sources (name + bytes, in the order
+    given) and the PassArgs struct: counters recorded for one digest do not
+    describe kernels built from another."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2301_01145_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".cpp", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    h.update(_pass_args_text())
     return h.hexdigest()
 
 
@@ -128,6 +143,8 @@ def parse():
                     help="grid of the oracle sample (default: the benchmark's own 256^3)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 64-problem batched Neumann workload (prints its JSON object)")
     ap.add_argument("--no-others", action="store_true",
                     help="skip the secondary workloads (2D periodic, 3D Dirichlet, batched Neumann, "
                          "differentiable 128^3)")
@@ -173,42 +190,16 @@ def _time_graph(run, stream, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def other_workloads(steps, warmup):
-    """Secondary workloads: solves/s and model GB/s each (same timing method)."""
+def neumann_batch64(steps, warmup):
+    """64 batched Neumann problems (sizes from {32, 48, 64, 96, 128} per axis,
+    seed 5), FP32: the default form and the autotuned one, replayed from a
+    captured hipGraph (the plan lives on a side stream so that it can be
+    captured)."""
     import numpy as np
     import torch
 
-    from paper_2301_01145_amd import Solver
-    from paper_2301_01145_amd.autograd import poisson_solve
     from paper_2301_01145_amd.batched import BatchedSolver
-    from workloads import dirichlet_3d, neumann_batch, periodic_modes_2d, vortex_rings
-    res = {}
-    # 2D periodic 64^2 FP64 PS
-    f, _ = periodic_modes_2d(64, seed=1)
-    s = Solver("periodic", "staggered", [64, 64], kernel="ps", dtype=torch.float64)
-    s.bind(torch.as_tensor(f, device="cuda"))
-    ms = _time(s.run, steps, warmup, s.stream)
-    res["periodic2d_64_fp64"] = {"solves_per_s": 1000 / ms, "ms": ms,
-                                 "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
-    s.close()
-    # 3D Dirichlet 128^3 regular FD2 inhomogeneous FP32
-    f, faces = dirichlet_3d(128)
-    s = Solver("dirichlet", "regular", [128] * 3, kernel="fd2", dtype=torch.float32, inhomogeneous=True)
-    fd = {k: torch.as_tensor(v.astype(np.float32), device="cuda") for k, v in faces.items()}
-    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"), fd)
-    ms = _time(s.run, steps, warmup, s.stream)
-    res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
-                                       "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
-    s.close()
-    # the same source, homogeneous PS, psi and its gradient (sine -> cosine series)
-    s = Solver("dirichlet", "regular", [128] * 3, kernel="ps", diff="grad", dtype=torch.float32)
-    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"))
-    ms = _time(s.run, steps, warmup, s.stream)
-    res["dirichlet3d_128_ps_grad_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
-                                           "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
-    s.close()
-    # 64 batched Neumann problems: one persistent launch replayed from a captured
-    # hipGraph (the plan lives on a side stream so that it can be captured), FP32
+    from workloads import neumann_batch
     probs = neumann_batch(64, seed=5)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
@@ -226,18 +217,60 @@ def other_workloads(steps, warmup):
     ms = _time_graph(bs.run, side, steps, warmup)
     forms = {0: "one persistent launch, general passes",
              1: "one persistent launch, wavefront tile bodies",
-             2: "one launch per pass level (5), wavefront tile bodies"}
-    res["neumann_batch64_fp32"] = {"batches_per_s": 1000 / ms, "problems_per_s": 64000 / ms, "ms": ms,
-                                   "timing": "hipGraph replays of the tuned batch",
-                                   "kernel_form": forms[bs.kernel_mode()],
-                                   "ms_eager": ms_eager,
-                                   "default_form": forms[mode_default],
-                                   "ms_default_graph": ms_default_graph,
-                                   "ms_default_eager": ms_default,
-                                   "tuned_pass_signatures": ntuned, "tiles_per_item": tiles,
-                                   "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
-                                   "error_flag": bs.error_flag()}
+             2: "one launch per pass level, transform length and pass kind, wavefront tile bodies"}
+    out = {"batches_per_s": 1000 / ms, "problems_per_s": 64000 / ms, "ms": ms,
+           "timing": "hipGraph replays of the tuned batch",
+           "kernel_form": forms[bs.kernel_mode()], "ms_eager": ms_eager,
+           "default_form": forms[mode_default], "ms_default_graph": ms_default_graph,
+           "ms_default_eager": ms_default,
+           "tuned_pass_signatures": ntuned, "tiles_per_item": tiles,
+           "model_bytes": bs.model_bytes(),
+           "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
+           "error_flag": bs.error_flag()}
     bs.close()
+    return out
+
+
+def other_workloads(steps, warmup):
+    """Secondary workloads: solves/s and model GB/s each (same timing method)."""
+    import numpy as np
+    import torch
+
+    from paper_2301_01145_amd import Solver
+    from paper_2301_01145_amd.autograd import poisson_solve
+    from paper_2301_01145_amd.batched import BatchedSolver
+    from workloads import dirichlet_3d, neumann_batch, periodic_modes_2d, vortex_rings
+    res = {}
+    # 2D periodic 64^2 FP64 PS
+    # (three launches), eager and replayed from a captured graph
+    f, _ = periodic_modes_2d(64, seed=1)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = Solver("periodic", "staggered", [64, 64], kernel="ps", dtype=torch.float64)
+        s.bind(torch.as_tensor(f, device="cuda"))
+    torch.cuda.synchronize()
+    ms = _time(s.run, steps, warmup, s.stream)
+    ms_graph = _time_graph(s.run, side, steps, warmup)
+    res["periodic2d_64_fp64"] = {"solves_per_s": 1000 / ms_graph, "ms_graph": ms_graph, "ms_eager": ms,
+                                 "launches": int(s.passes()), "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+    s.close()
+    # 3D Dirichlet 128^3 regular FD2 inhomogeneous FP32
+    f, faces = dirichlet_3d(128)
+    s = Solver("dirichlet", "regular", [128] * 3, kernel="fd2", dtype=torch.float32, inhomogeneous=True)
+    fd = {k: torch.as_tensor(v.astype(np.float32), device="cuda") for k, v in faces.items()}
+    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"), fd)
+    ms = _time(s.run, steps, warmup, s.stream)
+    res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+                                       "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+    s.close()
+    # the same source, homogeneous PS, psi and its gradient (sine -> cosine series)
+    s = Solver("dirichlet", "regular", [128] * 3, kernel="ps", diff="grad", dtype=torch.float32)
+    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"))
+    ms = _time(s.run, steps, warmup, s.stream)
+    res["dirichlet3d_128_ps_grad_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+                                           "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+    s.close()
+    res["neumann_batch64_fp32"] = neumann_batch64(steps, warmup)
     # free-space kernels (Section 2.5.2): plan time (Green's function on the doubled
     # grid, FP64 transform, octant) and solve time of the 256^3 curl plan, and the
     # FP64 error against the exact potential of a Gaussian blob at 64^3 and 128^3
@@ -482,6 +515,11 @@ def main():
     args = parse()
     if args.copy_ref:
         copy_reference()
+        return
+    if args.batch_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"neumann_batch64_fp32": neumann_batch64(args.steps, args.warmup)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the library has no multi-GPU path); use --gpus 1",

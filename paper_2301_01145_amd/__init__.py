@@ -90,6 +90,10 @@ class Solver:
     def model_bytes(self):
         return hp_query(self.plan, _lib.HP_Q_MODEL_BYTES)
 
+    def passes(self):
+        """Kernel launches of one solve."""
+        return hp_query(self.plan, _lib.HP_Q_NUM_PASSES)
+
     def zero_mode(self):
         """Part of the bound source that the k = 0 projection removes (periodic and
         Neumann plans; 0 for a compatible source and for other BCs)."""

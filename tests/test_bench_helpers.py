@@ -31,6 +31,15 @@ def test_committed_profile_parses():
     path = os.path.join(ROOT, "profiles", "unbounded256_curl_fp32_hbm_counters.md")
     text = open(path).read()
     assert "source_sha256:" in text and "traffic_bytes: sandwich_x" in text
+    text = open(os.path.join(ROOT, "profiles", "unbounded256_curl_fp32_kernel_trace.md")).read()
+    assert "source_sha256:" in text and "kernel_avg_us: sandwich_x" in text
+
+
+def test_committed_profiles_match_the_kernel_sources():
+    # the committed counters describe the kernels built from these sources
+    for name in ("unbounded256_curl_fp32_hbm_counters.md", "unbounded256_curl_fp32_kernel_trace.md"):
+        digest, _ = bench._profile_lines(os.path.join(ROOT, "profiles", name))
+        assert digest == bench.kernel_source_digest(), name
 
 
 def test_more_than_one_gpu_is_refused():

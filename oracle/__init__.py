@@ -58,8 +58,9 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     diff: "none" | "grad" | "curl" | "div" | "nabla" (Section 2.3.3's operators,
           applied to psi: gradient of a scalar, curl or divergence of a 3D
           vector, Laplacian of every component; in 2D the curl of a scalar
-          is (d_y psi, -d_x psi)).  Dirichlet / Neumann take "grad" only,
-          with homogeneous boundary values (bounded.bounded_gradient)
+          is (d_y psi, -d_x psi)).  Dirichlet / Neumann plans take every
+          operator with homogeneous boundary values, as derivatives of the
+          eigenfunction series (bounded.bounded_derivative)
     faces: {(axis, side): g} boundary values (FD2 Dirichlet / Neumann)
     Returns (psi, derivs) on the output points.
     """
@@ -76,31 +77,46 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     psi = [bounded.solve_bounded(c, bc, grid_type, operator, lengths, hs, faces if not vector else (faces[i] if faces else None))
            for i, c in enumerate(comps)]
     derivs = []
-    if diff == "grad" and bc != "periodic":
-        if vector or faces:
-            raise NotImplementedError("Dirichlet / Neumann gradient: homogeneous scalar only")
-        derivs = bounded.bounded_gradient(psi[0], bc, grid_type, nc, lengths)
+    if diff != "none" and bc != "periodic":
+        if faces:
+            raise NotImplementedError("Dirichlet / Neumann operators: homogeneous boundary values only")
+        if diff == "grad":
+            if vector:
+                raise NotImplementedError("gradient: scalar only")
+            derivs = bounded.bounded_gradient(psi[0], bc, grid_type, nc, lengths)
+        elif diff == "nabla":
+            derivs = [bounded.bounded_laplacian(p, bc, grid_type, nc, lengths) for p in psi]
+        elif diff == "div":
+            if not vector or nd != 3:
+                raise NotImplementedError("divergence: 3D vector only")
+            derivs = [sum(bounded.bounded_derivative(psi[c], bc, grid_type, nc, lengths, c, 1)
+                          for c in range(3))]
+        elif diff == "curl" and nd == 2 and not vector:
+            g = bounded.bounded_gradient(psi[0], bc, grid_type, nc, lengths)
+            derivs = [g[1], -g[0]]
+        elif diff == "curl":
+            if not vector or nd != 3:
+                raise NotImplementedError("curl: 3D vector or 2D scalar")
+            derivs = bounded.bounded_curl(psi, bc, grid_type, nc, lengths)
+        else:
+            raise ValueError(diff)
     elif diff == "grad":
         if vector:
             raise NotImplementedError("periodic gradient: scalar only")
         derivs = bounded.periodic_gradient(psi[0], lengths)
     elif diff == "curl" and nd == 2 and not vector:
-        if bc != "periodic":
-            raise NotImplementedError("bounded curl: periodic only")
         # 2D curl of a scalar (stream function): (d_y psi, -d_x psi)
         g = bounded.periodic_gradient(psi[0], lengths)
         derivs = [g[1], -g[0]]
     elif diff == "curl":
-        if bc != "periodic" or not vector or nd != 3:
-            raise NotImplementedError("bounded curl: periodic 3D vector only")
+        if not vector or nd != 3:
+            raise NotImplementedError("curl: 3D vector or 2D scalar")
         derivs = bounded.periodic_curl(psi, lengths)
     elif diff == "div":
-        if bc != "periodic" or not vector or nd != 3:
-            raise NotImplementedError("bounded divergence: periodic 3D vector only")
+        if not vector or nd != 3:
+            raise NotImplementedError("divergence: 3D vector only")
         derivs = [sum(bounded.periodic_gradient(psi[c], lengths)[c] for c in range(3))]
     elif diff == "nabla":
-        if bc != "periodic":
-            raise NotImplementedError("bounded Laplacian: periodic only")
         # the spectral first derivative (Nyquist zeroed) applied twice per axis
         derivs = [sum(bounded.periodic_gradient(bounded.periodic_gradient(p, lengths)[a], lengths)[a]
                       for a in range(nd)) for p in psi]

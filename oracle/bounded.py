@@ -217,28 +217,58 @@ def eigenfunctions(bc, n, length, x):
     raise ValueError(bc)
 
 
+def bounded_derivative(psi, bc, grid, nc, lengths, axis, order=1):
+    """Derivative of order 1 or 2 along `axis` of a Dirichlet / Neumann
+    solution with homogeneous boundary values.  Section 2.3.3 defines the
+    spectral derivative for the Fourier basis; for the sine / cosine bases of
+    Table 1 it is read here as the derivative of the eigenfunction series that
+    passes through psi at the unknown points, evaluated at the output points:
+    along `axis` the matrix d^m phi(x_out) phi(x_unk)^-1 applied to every line
+    of psi, the other axes untouched.  The first derivative turns a sine series
+    into a cosine series and back; the second keeps the basis, each
+    eigenfunction times -w^2.  REGULAR Dirichlet output includes the boundary
+    nodes (the normal derivative there; 0 along the faces)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    a = axis
+    n = _grid.unknowns(bc, grid, nc[a])
+    x_out = _grid.positions(bc, grid, 0.0, lengths[a], nc[a])
+    dreg = bc == "dirichlet" and grid == "regular"
+    x_unk = x_out[1:-1] if dreg else x_out
+    phi, _ = eigenfunctions(bc, n, lengths[a], x_unk)
+    phi_out, dphi = eigenfunctions(bc, n, lengths[a], x_out)
+    if order == 1:
+        deriv = dphi
+    elif order == 2:
+        w = np.pi * (np.arange(n) + (1.0 if bc == "dirichlet" else 0.0)) / float(lengths[a])
+        deriv = phi_out * (-w * w)[None, :]
+    else:
+        raise ValueError(order)
+    dmat = deriv @ np.linalg.inv(phi)
+    vals = np.moveaxis(psi, a, 0)
+    if dreg:
+        vals = vals[1:-1]
+    return np.moveaxis(np.tensordot(dmat, vals, axes=1), 0, a)
+
+
 def bounded_gradient(psi, bc, grid, nc, lengths):
     """Spectral gradient of a Dirichlet / Neumann solution with homogeneous
-    boundary values.  Section 2.3.3 defines the spectral derivative for the
-    Fourier basis; for the sine / cosine bases of Table 1 it is read here as
-    the derivative of the eigenfunction series that passes through psi at the
-    unknown points (sine series -> cosine series and back), evaluated at the
-    output points.  Along axis a this is the matrix dphi(x_out) phi(x_unk)^-1
-    applied to every line of psi.  REGULAR Dirichlet output includes the
-    boundary nodes (the normal derivative there; 0 along the faces)."""
+    boundary values: the first derivative of the eigenfunction series along
+    every axis (bounded_derivative)."""
     psi = np.asarray(psi, dtype=np.float64)
-    nd = psi.ndim
-    out = []
-    for a in range(nd):
-        n = _grid.unknowns(bc, grid, nc[a])
-        x_out = _grid.positions(bc, grid, 0.0, lengths[a], nc[a])
-        dreg = bc == "dirichlet" and grid == "regular"
-        x_unk = x_out[1:-1] if dreg else x_out
-        phi, _ = eigenfunctions(bc, n, lengths[a], x_unk)
-        _, dphi = eigenfunctions(bc, n, lengths[a], x_out)
-        dmat = dphi @ np.linalg.inv(phi)
-        vals = np.moveaxis(psi, a, 0)
-        if dreg:
-            vals = vals[1:-1]
-        out.append(np.moveaxis(np.tensordot(dmat, vals, axes=1), 0, a))
-    return out
+    return [bounded_derivative(psi, bc, grid, nc, lengths, a, 1) for a in range(psi.ndim)]
+
+
+def bounded_laplacian(psi, bc, grid, nc, lengths):
+    """NABLA of Section 2.3.3 on a Dirichlet / Neumann solution: the sum over
+    the axes of the second derivative of the eigenfunction series."""
+    psi = np.asarray(psi, dtype=np.float64)
+    return sum(bounded_derivative(psi, bc, grid, nc, lengths, a, 2) for a in range(psi.ndim))
+
+
+def bounded_curl(psi, bc, grid, nc, lengths):
+    """Curl of a 3D vector Dirichlet / Neumann solution (component c of psi on
+    its own sine / cosine series): u_x = d_y psi_z - d_z psi_y,
+    u_y = d_z psi_x - d_x psi_z, u_z = d_x psi_y - d_y psi_x, each derivative
+    from bounded_derivative."""
+    d = lambda c, a: bounded_derivative(psi[c], bc, grid, nc, lengths, a, 1)
+    return [d(2, 1) - d(1, 2), d(0, 2) - d(2, 0), d(1, 0) - d(0, 1)]

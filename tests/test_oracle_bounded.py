@@ -463,6 +463,74 @@ def test_bounded_gradient_top_mode(bc, gtype, top):
         assert np.max(np.abs(grad_a[0])) < 1e-12 * np.pi * top / 2.0
 
 
+@pytest.mark.parametrize("bc,gtype", CASES[:4])
+@pytest.mark.parametrize("nd", [1, 2, 3])
+@pytest.mark.parametrize("operator", ["ps", "fd2"])
+def test_bounded_laplacian_of_eigenmodes(bc, gtype, nd, operator):
+    """NABLA of a product of eigenfunctions: every second derivative brings
+    -w_a^2, so NABLA psi = sum_a (-w_a^2) x the product / the eigenvalue sum
+    at the output points (boundary nodes included).  With PS that sum is the
+    eigenvalue itself and NABLA psi is the source."""
+    nc = [12, 10, 8][:nd]
+    lo = [0.0, 1.0, -2.0][:nd]
+    hi = [1.0, 3.0, 1.0][:nd]
+    modes = [3, 2, 5][:nd]
+    f, psi_a, _ = _mode_product_case(bc, gtype, nc, lo, hi, modes, operator)
+    w2 = sum((np.pi * modes[a] / (hi[a] - lo[a])) ** 2 for a in range(nd))
+    lap_a = -w2 * psi_a  # psi_a = product / eigenvalue sum at the output points
+    psi, lap = oracle.solve(bc, gtype, nc, lo, hi, f, operator=operator, diff="nabla")
+    assert len(lap) == 1
+    assert np.max(np.abs(lap[0] - lap_a)) <= 1e-11 * np.max(np.abs(lap_a))
+    if operator == "ps":
+        # the eigenfunction product itself: the source, now at the output points
+        _, prod, _ = _mode_product_case(bc, gtype, nc, lo, hi, modes, "ps")
+        prod = -w2 * prod
+        assert np.max(np.abs(lap[0] - prod)) <= 1e-11 * np.max(np.abs(prod))
+
+
+def _vector_mode_case(bc, gtype, nc, lo, hi, operator):
+    """A 3D vector whose component c is a product of eigenfunctions with its
+    own modes: sources, potentials and every first derivative in closed form."""
+    modes = [[3, 2, 1], [1, 3, 2], [2, 1, 4]]
+    f, psi, grads = [], [], []
+    for c in range(3):
+        fc, pc, gc = _mode_product_case(bc, gtype, nc, lo, hi, modes[c], operator)
+        f.append(fc)
+        psi.append(pc)
+        grads.append(gc)
+    return np.stack(f), psi, grads
+
+
+@pytest.mark.parametrize("bc,gtype", CASES[:4])
+@pytest.mark.parametrize("operator", ["ps", "fd2"])
+def test_bounded_curl_and_div_of_eigenmodes(bc, gtype, operator):
+    """CURL and DIV of a 3D vector of eigenfunction products, from the closed
+    forms of every d psi_c / d x_a (the curl's components and signs, the
+    divergence's diagonal terms)."""
+    nc, lo, hi = [10, 8, 12], [0.0, 1.0, -2.0], [1.0, 3.0, 1.0]
+    f, psi_a, g = _vector_mode_case(bc, gtype, nc, lo, hi, operator)
+    psi, curl = oracle.solve(bc, gtype, nc, lo, hi, f, operator=operator, diff="curl")
+    curl_a = [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+    scale = max(np.max(np.abs(c)) for c in curl_a)
+    for c in range(3):
+        assert np.max(np.abs(psi[c] - psi_a[c])) <= 1e-12 * np.max(np.abs(psi_a[c]))
+        assert np.max(np.abs(curl[c] - curl_a[c])) <= 1e-11 * scale, c
+    _, div = oracle.solve(bc, gtype, nc, lo, hi, f, operator=operator, diff="div")
+    div_a = g[0][0] + g[1][1] + g[2][2]
+    assert len(div) == 1
+    assert np.max(np.abs(div[0] - div_a)) <= 1e-11 * max(np.max(np.abs(x[i])) for i, x in enumerate(g))
+
+
+@pytest.mark.parametrize("bc,gtype", CASES[:4])
+def test_bounded_curl_2d_of_eigenmodes(bc, gtype):
+    nc, lo, hi = [12, 10], [0.0, 1.0], [1.0, 3.0]
+    f, psi_a, g = _mode_product_case(bc, gtype, nc, lo, hi, [3, 2], "ps")
+    _, curl = oracle.solve(bc, gtype, nc, lo, hi, f, operator="ps", diff="curl")
+    scale = max(np.max(np.abs(x)) for x in g)
+    assert np.max(np.abs(curl[0] - g[1])) <= 1e-12 * scale
+    assert np.max(np.abs(curl[1] + g[0])) <= 1e-12 * scale
+
+
 def test_bounded_gradient_inhomogeneous_rejected():
     f = np.zeros((6,))
     with pytest.raises(NotImplementedError):

@@ -193,3 +193,54 @@ def test_periodic_gradient_axis_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "periodic_gradient", wrong)
     _fails(po.test_periodic_3d_gradient_closed_form)
+
+
+def test_bounded_curl_component_swap_is_caught(monkeypatch):
+    # Dirichlet / Neumann curl with u_x and u_y exchanged
+    orig = bounded.bounded_curl
+
+    def wrong(psi, bc, grid, nc, lengths):
+        u = orig(psi, bc, grid, nc, lengths)
+        return [u[1], u[0], u[2]]
+
+    monkeypatch.setattr(bounded, "bounded_curl", wrong)
+    _fails(pb.test_bounded_curl_and_div_of_eigenmodes, "neumann", "staggered", "ps")
+
+
+def test_bounded_curl_sign_is_caught(monkeypatch):
+    # u_z = d_y psi_x - d_x psi_y (sign of one component flipped)
+    orig = bounded.bounded_curl
+
+    def wrong(psi, bc, grid, nc, lengths):
+        u = orig(psi, bc, grid, nc, lengths)
+        return [u[0], u[1], -u[2]]
+
+    monkeypatch.setattr(bounded, "bounded_curl", wrong)
+    _fails(pb.test_bounded_curl_and_div_of_eigenmodes, "dirichlet", "regular", "fd2")
+
+
+def test_bounded_second_derivative_factor_is_caught(monkeypatch):
+    # second derivative of the series with -w in place of -w^2
+    orig = bounded.bounded_derivative
+
+    def wrong(psi, bc, grid, nc, lengths, axis, order=1):
+        if order != 2:
+            return orig(psi, bc, grid, nc, lengths, axis, order)
+        d1 = orig(psi, bc, grid, nc, lengths, axis, 2)
+        w = np.pi / float(lengths[axis])
+        return d1 / w
+
+    monkeypatch.setattr(bounded, "bounded_derivative", wrong)
+    _fails(pb.test_bounded_laplacian_of_eigenmodes, "dirichlet", "staggered", 2, "ps")
+
+
+def test_bounded_divergence_axis_is_caught(monkeypatch):
+    # divergence built from d psi_c / d x_(c+1) instead of d psi_c / d x_c
+    import oracle
+    orig = bounded.bounded_derivative
+
+    def wrong(psi, bc, grid, nc, lengths, axis, order=1):
+        return orig(psi, bc, grid, nc, lengths, (axis + 1) % np.ndim(psi), order)
+
+    monkeypatch.setattr(bounded, "bounded_derivative", wrong)
+    _fails(pb.test_bounded_curl_and_div_of_eigenmodes, "neumann", "regular", "fd2")

@@ -91,11 +91,14 @@ typedef enum {
  * component (ncomp outputs).  Derivatives multiply by i k_a with the Nyquist
  * mode set to zero; NABLA is that first derivative applied twice per axis and
  * summed.  Periodic and free-space
- * plans take every operator; Dirichlet / Neumann plans take GRAD only, with
- * homogeneous boundary values (HP_E_UNSUPPORTED otherwise): the derivative of
- * the Table 1 sine (cosine) series through psi, evaluated as a cosine (sine)
- * series at the output points (REGULAR Dirichlet: every node, the normal
- * derivative on the boundary nodes).  Batched plans take HP_D_NONE only. */
+ * plans take every operator; Dirichlet / Neumann plans take every operator
+ * with homogeneous boundary values (HP_E_UNSUPPORTED otherwise), as
+ * derivatives of the Table 1 sine (cosine) series through psi evaluated at the
+ * output points: a first derivative along an axis turns that axis's series
+ * into a cosine (sine) series (REGULAR Dirichlet: every node, the normal
+ * derivative on the boundary nodes); NABLA keeps each series, every
+ * eigenfunction times -(pi kappa / L)^2 per axis.  Batched plans take
+ * HP_D_NONE only. */
 typedef enum { HP_D_NONE = 0, HP_D_GRAD = 1, HP_D_CURL = 2, HP_D_DIV = 3, HP_D_NABLA = 4 } hp_diff;
 typedef enum { HP_F32 = 0, HP_F64 = 1 } hp_prec;
 

@@ -171,13 +171,12 @@ hp_status validate(const hp_desc* d) {
   if (d->diff == HP_D_GRAD && d->ncomp != 1)
     return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
   if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN)) {
-    if (d->diff != HP_D_GRAD)
-      return fail(nullptr, HP_E_UNSUPPORTED, "Dirichlet/Neumann grids take the gradient only");
     if (d->inhomogeneous)
-      return fail(nullptr, HP_E_UNSUPPORTED, "the Dirichlet/Neumann gradient needs homogeneous boundary values");
+      return fail(nullptr, HP_E_UNSUPPORTED,
+                  "Dirichlet/Neumann derivatives need homogeneous boundary values");
     for (int a = 0; a < d->ndim; ++a)
       if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
-        return fail(nullptr, HP_E_ARG, "the Neumann regular gradient needs 2 cells per axis");
+        return fail(nullptr, HP_E_ARG, "Neumann regular derivatives need 2 cells per axis");
   }
   // transform lengths must be 2^a 3^b 5^c
   for (int a = 0; a < d->ndim; ++a) {
@@ -555,6 +554,10 @@ hp_status setup_problem(hp_plan p, Problem& P) {
       HP_TRY(upload(p, eigen(d.bc, d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false, (void**)&P.lam[a]));
     }
     if (P.nder) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.grad_s));
+    // second terms of DIV (d_y psi_y, d_z psi_z) and of the 3D curl, added
+    // into the outputs at the end of the solve
+    const int ntmp = d.diff == HP_D_DIV ? 2 : (d.diff == HP_D_CURL && P.nd == 3 ? 3 : 0);
+    for (int t = 0; t < ntmp; ++t) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.dtmp[t]));
   } else if (d.bc == HP_PERIODIC) {
     P.norm = 1.0;
     for (int a = 0; a < P.nd; ++a) {
@@ -832,7 +835,7 @@ bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
 
 // Switch a general bounded pass (same descriptor) to its wavefront kernel.
 hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
-  if (a.fast == FAST_GRAD_PREP) return HP_OK;
+  if (a.fast == FAST_GRAD_PREP || a.fast == FAST_ADD) return HP_OK;
   const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
   bool faces = false;
   for (int ax = 0; ax < 3; ++ax) faces |= a.face[ax][0] != nullptr || a.face[ax][1] != nullptr;
@@ -920,25 +923,30 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     out.push_back({a, 1});
     return HP_OK;
   };
-  // derivative g from coefficients `src` (the work-view layout); `eigen`: the
-  // eigenvalue sum still has to be divided out (source transformed along every
-  // axis), else src is psi's array after the sandwich
-  auto grad_deriv = [&](int g, const void* src, bool eigen) -> hp_status {
+  // derivative g from coefficients `src` (the work-view layout) into `dst`,
+  // times `sign`; `eigen`: the eigenvalue sum still has to be divided out
+  // (source transformed along every axis), else src is psi's array after the
+  // sandwich.  `lap`: NABLA instead, the sum over the axes of the second
+  // derivatives, which keeps every axis's basis (-w_b^2 per eigenfunction),
+  // from the transformed source.
+  auto grad_deriv = [&](int g, const void* src, bool eigen, void* dst, double sign,
+                        bool lap) -> hp_status {
     const bool dir = d.bc == HP_DIRICHLET, reg = d.grid == HP_REGULAR;
     // active view of the derivative output: extent len[b] from off[b]
     int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
     for (int b = 0; b < nd; ++b) { off[b] = dreg ? 1 : 0; len[b] = P.n[b]; }
-    int xd;
-    if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
+    int xd = 0;
+    if (lap) xd = xb[0];
+    else if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
     else if (dir) xd = X_DCT3;
     else if (reg) { xd = X_DST1; len[g] = P.n[g] - 2; off[g] = 1; }   // interior nodes
     else xd = X_DST3;
     {
       PassArgs a = base();
       a.fast = FAST_GRAD_PREP;
-      a.ax_j = g;
+      a.ax_j = lap ? -1 : g;
       a.in[0] = src;
-      a.out[0] = P.der[g];
+      a.out[0] = dst;
       double cnt_in = 1.0, cnt_out = 1.0;
       for (int b = 0; b < 3; ++b) {
         a.gp_ext[b] = b < nd ? P.nout[b] : 1;
@@ -947,12 +955,19 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
         a.gp_is[b] = a.gp_os[b] = b < nd ? ws[b] : 0;
         a.nunk[b] = b < nd ? P.n[b] : 1;
         a.lam[b] = eigen && b < nd ? P.lam[b] : nullptr;
+        a.kc[b] = lap && b < nd ? M_PI / P.len[b] : 0.0;
         if (b < nd) { cnt_in *= P.n[b]; cnt_out *= P.nout[b]; }
       }
       a.gp_eigen = eigen ? 1 : 0;
-      a.gp_shift = dir ? -1 : 1;  // sine index k carries wavenumber k + 1
-      a.gp_kadd = dir ? 1 : 0;
-      a.gp_scale = (dir ? 1.0 : -1.0) * M_PI / P.len[g];
+      a.gp_kadd = dir ? 1 : 0;  // sine index k carries wavenumber k + 1
+      if (lap) {
+        a.diff = D_NABLA;
+        a.gp_shift = 0;
+        a.gp_scale = sign;
+      } else {
+        a.gp_shift = dir ? -1 : 1;
+        a.gp_scale = sign * (dir ? 1.0 : -1.0) * M_PI / P.len[g];
+      }
       a.norm = P.norm;
       PassRec r{a, 1};
       r.bytes = (cnt_in + cnt_out) * (double)es;
@@ -960,12 +975,12 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     }
     long long vo = 0;
     for (int b = 0; b < nd; ++b) vo += (long long)off[b] * ws[b];
-    void* view = (void*)((char*)P.der[g] + vo * (long long)es);
+    void* view = (void*)((char*)dst + vo * (long long)es);
     // axis 0 is already physical when the coefficients come from psi's array
     for (int c = last; c >= (eigen ? 0 : 1); --c) {
       PassArgs a = base();
       a.kind = PK_ONEWAY;
-      a.xf = c == g ? xd : xb[c];
+      a.xf = (!lap && c == g) ? xd : xb[c];
       a.L = L[c]; a.n = len[c]; a.nin = a.nout = len[c];
       a.in[0] = view; a.out[0] = view;
       a.in_sj = a.out_sj = ws[c];
@@ -992,15 +1007,68 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     }
     return HP_OK;
   };
-  // before the sandwich: d/dx_0
-  auto grad_chain = [&](int comp) -> hp_status {
+  // The derivative terms of every operator: component `comp` contributes
+  // d psi_comp / d x_axis (axis -1: NABLA) times `sign` to slot `dst` (an
+  // output, or a temporary added into an output at the end).  Axis 0 and
+  // NABLA terms are taken before the sandwich from the transformed source,
+  // the other axes after it from psi's array.
+  struct Term {
+    int comp, axis;
+    void* dst;
+    double sign;
+  };
+  std::vector<Term> terms;
+  switch (d.diff) {
+    case HP_D_GRAD:
+      for (int g = 0; g < nd; ++g) terms.push_back({0, g, P.der[g], 1.0});
+      break;
+    case HP_D_NABLA:
+      for (int c = 0; c < P.ncomp; ++c) terms.push_back({c, -1, P.der[c], 1.0});
+      break;
+    case HP_D_DIV:  // d_x psi_x into the output, d_y psi_y and d_z psi_z added
+      terms.push_back({0, 0, P.der[0], 1.0});
+      terms.push_back({1, 1, P.dtmp[0], 1.0});
+      terms.push_back({2, 2, P.dtmp[1], 1.0});
+      break;
+    case HP_D_CURL:
+      if (nd == 2) {  // (d_y psi, -d_x psi)
+        terms.push_back({0, 1, P.der[0], 1.0});
+        terms.push_back({0, 0, P.der[1], -1.0});
+      } else {  // u_x = d_y psi_z - d_z psi_y, u_y = d_z psi_x - d_x psi_z, u_z = d_x psi_y - d_y psi_x
+        terms.push_back({0, 1, P.dtmp[2], -1.0});
+        terms.push_back({0, 2, P.der[1], 1.0});
+        terms.push_back({1, 0, P.der[2], 1.0});
+        terms.push_back({1, 2, P.dtmp[0], -1.0});
+        terms.push_back({2, 0, P.dtmp[1], -1.0});
+        terms.push_back({2, 1, P.der[0], 1.0});
+      }
+      break;
+    default:
+      break;
+  }
+  // before the sandwich: the terms along axis 0 and NABLA, from the source
+  // transformed along every axis (one more forward pass along axis 0, out of place)
+  auto pre_terms = [&](int comp) -> hp_status {
+    bool any = false;
+    for (auto& t : terms) any |= t.comp == comp && t.axis <= 0;
+    if (!any) return HP_OK;
     HP_TRY(grad_forward_x(comp));
-    return grad_deriv(0, (const void*)((char*)P.grad_s + woff * es), true);
+    const void* src = (const void*)((char*)P.grad_s + woff * es);
+    for (auto& t : terms)
+      if (t.comp == comp && t.axis <= 0) HP_TRY(grad_deriv(0, src, true, t.dst, t.sign, t.axis < 0));
+    return HP_OK;
+  };
+  // after the sandwich: the terms along axes 1.., from psi's array (before
+  // the backward passes change it)
+  auto post_terms = [&](int comp) -> hp_status {
+    for (auto& t : terms)
+      if (t.comp == comp && t.axis > 0) HP_TRY(grad_deriv(t.axis, work(comp), false, t.dst, t.sign, false));
+    return HP_OK;
   };
   // one pass per component (faces differ per component)
   for (int comp = 0; comp < P.ncomp; ++comp) {
     if (nd == 1) {
-      if (P.nder) HP_TRY(grad_chain(comp));
+      HP_TRY(pre_terms(comp));
       PassArgs a = base();
       a.kind = PK_SANDWICH;
       a.xf = xf[0]; a.xb = xb[0];
@@ -1057,7 +1125,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
       p2 = a;
     }
-    if (P.nder) HP_TRY(grad_chain(comp));
+    HP_TRY(pre_terms(comp));
     // P3: sandwich along axis 0
     {
       PassArgs a = base();
@@ -1080,8 +1148,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
     }
     // after the sandwich: d/dx_g, g > 0, from psi's array (before P4 changes it)
-    if (P.nder)
-      for (int g = 1; g < nd; ++g) HP_TRY(grad_deriv(g, work(comp), false));
+    HP_TRY(post_terms(comp));
     // P4 (3D): backward along axis 1
     if (nd == 3) {
       PassArgs a = p2;  // same geometry as P2
@@ -1108,6 +1175,24 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
     }
   }
+  // DIV / 3D CURL: the second terms added into the outputs (elementwise)
+  auto add_into = [&](void* dst, const void* t0, const void* t1) {
+    PassArgs a = base();
+    a.fast = FAST_ADD;
+    a.out[0] = dst;
+    a.in[0] = t0;
+    a.in[1] = t1;
+    long long cnt = 1;
+    for (int b = 0; b < nd; ++b) cnt *= P.nout[b];
+    a.gp_ext[0] = (int)cnt;
+    a.gp_ext[1] = a.gp_ext[2] = 1;
+    PassRec r{a, 1};
+    r.bytes = (double)cnt * (double)es * (t1 ? 4.0 : 3.0);
+    out.push_back(r);
+  };
+  if (d.diff == HP_D_DIV) add_into(P.der[0], P.dtmp[0], P.dtmp[1]);
+  if (d.diff == HP_D_CURL && nd == 3)
+    for (int c = 0; c < 3; ++c) add_into(P.der[c], P.dtmp[c], nullptr);
   if (bounded_fast_ok(p, P, L))
     for (size_t i = first_pass; i < out.size(); ++i) HP_TRY(to_fast_r2r(p, out[i].a));
   return HP_OK;
@@ -1671,7 +1756,7 @@ double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
 const char* pass_name(const PassArgs& a) {
   static const char* fast_names[] = {"",       "r2c_z",      "fwd_y",       "sandwich_x", "inv_y",
                                      "c2r_z",  "r2r_contig", "r2r_strided", "r2r_sandwich",
-                                     "grad_prep"};
+                                     "grad_prep", "add"};
   constexpr int nfast = (int)(sizeof(fast_names) / sizeof(fast_names[0]));
   if (a.fast > 0 && a.fast < nfast) return fast_names[a.fast];
   if (a.fast) return "wavefront";

@@ -1026,7 +1026,7 @@ __global__ void __launch_bounds__(256) k_grad_prep(PassArgs a) {
     i[0] = (int)(r / a.gp_ext[1]);
     bool ok = true;
     long long so = 0, dof = 0;
-    double lam = 0.0;
+    double lam = 0.0, w2 = 0.0;
     int kap = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -1038,11 +1038,15 @@ __global__ void __launch_bounds__(256) k_grad_prep(PassArgs a) {
         so += (long long)k * a.gp_is[b];
         if (a.lam[b]) lam += a.lam[b][k];
         if (b == a.ax_j) kap = k + a.gp_kadd;
+        const double w = a.kc[b] * (double)(k + a.gp_kadd);  // NABLA: pi kappa_b / L_b
+        w2 += w * w;
       }
     }
     T v = (T)0;
     if (ok) {
-      double m = a.gp_scale * (double)kap;
+      // gradient: +-(pi kappa / L) one index over; NABLA (diff = D_NABLA):
+      // -sum_b (pi kappa_b / L_b)^2 on the same index
+      double m = a.diff == D_NABLA ? -a.gp_scale * w2 : a.gp_scale * (double)kap;
       if (a.gp_eigen) m = lam == 0.0 ? 0.0 : m * a.norm / lam;
       v = (T)m * src[so];
     }
@@ -1060,11 +1064,38 @@ hipError_t launch_grad_prep(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// out[0][i] += in[0][i] (+ in[1][i]), i < gp_ext[0]: the second terms of the
+// Dirichlet / Neumann divergence and curl.
+template <typename T>
+__global__ void __launch_bounds__(256) k_add(PassArgs a) {
+  const long long total = a.gp_ext[0];
+  T* dst = (T*)a.out[0];
+  const T* x = (const T*)a.in[0];
+  const T* y = (const T*)a.in[1];
+  const long long step = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += step) {
+    T v = dst[e] + x[e];
+    if (y) v += y[e];
+    dst[e] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_add(const PassArgs& a, hipStream_t s) {
+  const long long total = a.gp_ext[0];
+  if (total <= 0) return hipSuccess;
+  const long long blocks = (total + 255) / 256;
+  const int grid = (int)(blocks < 8192 ? blocks : 8192);
+  hipLaunchKernelGGL(k_add<T>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s) {
   if (a.fast == FAST_GRAD_PREP)
     return prec == 0 ? launch_grad_prep<float>(a, s) : launch_grad_prep<double>(a, s);
+  if (a.fast == FAST_ADD) return prec == 0 ? launch_add<float>(a, s) : launch_add<double>(a, s);
   if (prec == 0) return launch_bounded_T<float>(a, s);
   return launch_bounded_T<double>(a, s);
 }

@@ -114,7 +114,9 @@ enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH
                       // bounded real-to-real passes (hp_bounded.hip)
                       FAST_R2R_C = 6, FAST_R2R_S = 7, FAST_R2R_SW = 8,
                       // elementwise: spectral derivative coefficients (hp_bounded.hip)
-                      FAST_GRAD_PREP = 9 };
+                      FAST_GRAD_PREP = 9,
+                      // elementwise: out[0] += in[0] (+ in[1]) over gp_ext[0] elements
+                      FAST_ADD = 10 };
 // Derivative completion in the backward y pass of the free-space path.
 enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 

@@ -43,6 +43,7 @@ struct Problem {
   void* own_out[3] = {};
   void* own_der[3] = {};
   void* grad_s = nullptr;  // Dirichlet / Neumann gradient: transformed source
+  void* dtmp[3] = {};      // Dirichlet / Neumann DIV / CURL: second derivative terms
   void* own_face[3][2][3] = {};
   std::vector<void*> a1, b2, c2, c1;  // unbounded / periodic workspaces
   double* lam[3] = {};        // eigenvalue tables (bounded)

@@ -42,7 +42,10 @@ BAD = [
     (dict(bc="periodic", grid="regular", nc=[8, 8, 8], diff="grad", ncomp=3), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], diff="div", ncomp=1), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="regular", nc=[8, 8], diff="div"), _lib.HP_E_ARG),
-    (dict(bc="neumann", grid="staggered", nc=[8, 8, 8], diff="nabla"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="neumann", grid="staggered", nc=[8, 8, 8], diff="nabla"), None),  # valid
+    (dict(bc="neumann", grid="staggered", nc=[8, 8], diff="nabla", kernel="fd2", inhomogeneous=True),
+     _lib.HP_E_UNSUPPORTED),
+    (dict(bc="dirichlet", grid="regular", nc=[8, 8, 8], diff="div", ncomp=1), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="spectral"), _lib.HP_E_ARG),
     (dict(bc="unbounded", grid="staggered", nc=[8], kernel="g6"), None),  # 1D order 6: valid
@@ -50,7 +53,9 @@ BAD = [
     (dict(bc="unbounded", grid="staggered", nc=[8, 8, 8], kernel="ps"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], kernel="g2"), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="grad"), None),  # homogeneous: valid
-    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=3), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=3), None),  # valid
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=3, kernel="fd2",
+          inhomogeneous=True), _lib.HP_E_UNSUPPORTED),
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8], diff="grad", kernel="fd2", inhomogeneous=True),
      _lib.HP_E_UNSUPPORTED),
     (dict(bc="neumann", grid="regular", nc=[1], diff="grad"), _lib.HP_E_ARG),

@@ -591,3 +591,36 @@ def test_unbounded_kz_slabs(slab, prec, monkeypatch):
     check(got, ref, prec, "psi")
     for a in range(3):
         check(gd[a], rd[a], prec, f"curl {a}")
+
+
+# NABLA, DIV and CURL on Dirichlet / Neumann plans (homogeneous): small ragged
+# sizes on the general passes and power-of-two / 96 transform lengths on the
+# wavefront passes, against the oracle's derivatives of the eigenfunction series.
+BOPS = [([12, 10, 9], "nabla", 1), ([10, 12, 8], "nabla", 3), ([9, 12, 10], "div", 3),
+        ([10, 9, 12], "curl", 3), ([12, 10], "curl", 1), ([16], "nabla", 1), ([12, 15], "nabla", 1),
+        ([64, 32, 32], "div", 3), ([32, 64, 32], "curl", 3), ([64, 32], "curl", 1),
+        ([32, 32, 64], "nabla", 3), ([48, 32, 64], "curl", 3)]
+
+
+@pytest.mark.parametrize("bc,grid", [("dirichlet", "regular"), ("dirichlet", "staggered"),
+                                     ("neumann", "regular"), ("neumann", "staggered")])
+@pytest.mark.parametrize("nc,diff,ncomp", BOPS)
+@pytest.mark.parametrize("kernel", ["ps", "fd2"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bounded_operators(bc, grid, nc, diff, ncomp, kernel, prec):
+    nd = len(nc)
+    f, _ = case_input(bc, grid, nc, ncomp, False, prec, seed=71 + nd)
+    got, gd = gpu_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, diff, prec, ncomp, None)
+    ref, rd = oracle_solve(bc, grid, nc, LO[:nd], HI[:nd], f, kernel, diff, None)
+    check(got, ref, prec, "psi")
+    assert len(gd) == len(rd)
+    for a in range(len(rd)):
+        if diff == "nabla":
+            # the Laplacian amplifies the transform rounding by up to k_max^2
+            hs = [(HI[b] - LO[b]) / nc[b] for b in range(nd)]
+            psi_c = ref[a] if ncomp == 3 else ref
+            l2 = TOL[prec][0] if prec == "f32" else max(
+                TOL[prec][0], laplacian_rounding_tol(psi_c, rd[a], hs, [2 * n for n in nc]))
+            assert rel_l2(gd[a], rd[a]) <= l2, (a, rel_l2(gd[a], rd[a]), l2)
+        else:
+            check(gd[a], rd[a], prec, f"{diff} {a}")

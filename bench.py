@@ -615,7 +615,7 @@ def main():
     s.close()
     # the same bytes against what a plain copy reaches on this device
     cgbs, cok = copy_ceiling()
-    out["copy_ceiling"] = {"copy_gbs": cgbs, "kernel": "k_copy16 (16-byte loads/stores, 1 GiB each way)",
+    out["copy_ceiling"] = {"copy_gbs": cgbs, "kernel": "k_copy16 (16-byte nontemporal loads and stores, 1 GiB each way)",
                            "copy_correct": cok, "model_gbs_frac": out["model_gbs"] / cgbs,
                            "dominant_kernel_frac": out["roofline"]["achieved"] / cgbs}
     if not args.no_others:

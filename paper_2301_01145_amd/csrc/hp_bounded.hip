@@ -216,8 +216,8 @@ __global__ void __launch_bounds__(64 * kR2RContigWaves) kb_contig(const PassArgs
       T oa, obv;
       const int k = r2r_extract<T>(X, g + G * i, n, v[i], q, oa, obv);
       if (k < 0) continue;
-      if (valid) out[ob + (long long)k * a.out_sj] = oa;
-      if (vb) out[ob + a.out_sp + (long long)k * a.out_sj] = obv;
+      if (valid) st_stream(&out[ob + (long long)k * a.out_sj], oa);
+      if (vb) st_stream(&out[ob + a.out_sp + (long long)k * a.out_sj], obv);
     }
   });
 }
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(64 * W) kb_strided(const PassArgs a) {
     const long long ob = (long long)o * a.out_so + (long long)p0 * a.out_sp;
     for (int e = threadIdx.x; e < n * P; e += NT) {
       const int j = e / P, c = e - (e / P) * P;
-      if (c < np) out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp] = tile[j * TS + c];
+      if (c < np) st_stream(&out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp], tile[j * TS + c]);
     }
     t = nxt;
     if (!PERS || t >= ntiles) break;
@@ -533,8 +533,8 @@ __device__ __forceinline__ void bw_contig(const BwArgs& a, unsigned char* smem, 
       T oa, obv;
       const int kk = r2r_extract<T>(X, g + G * i, n, v[i], q, oa, obv);
       if (kk < 0) continue;
-      if (valid) a.out[ob + (long long)kk * a.out_sj] = oa;
-      if (vb) a.out[ob + a.out_sp + (long long)kk * a.out_sj] = obv;
+      if (valid) st_stream(&a.out[ob + (long long)kk * a.out_sj], oa);
+      if (vb) st_stream(&a.out[ob + a.out_sp + (long long)kk * a.out_sj], obv);
     }
     wave_sync();  // the slot is reused by the next pair
   }
@@ -622,7 +622,7 @@ __device__ __forceinline__ void bw_strided(const BwArgs& a, unsigned char* smem,
     const long long ob = (long long)o * a.out_so + (long long)p0 * a.out_sp;
     for (int e = ts; e < n * P; e += NTS) {
       const int j = e / P, c = e - (e / P) * P;
-      if (c < np) a.out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp] = tile_s[j * TS + c];
+      if (c < np) st_stream(&a.out[ob + (long long)j * a.out_sj + (long long)c * a.out_sp], tile_s[j * TS + c]);
     }
     __syncthreads();  // the tiles are reloaded by the next step
   }

@@ -31,6 +31,32 @@ __device__ __forceinline__ C2<T> rot(C2<T> a) {
   return INV ? C2<T>{-a.im, a.re} : C2<T>{a.im, -a.re};
 }
 
+// Streaming (nontemporal) global stores: data written once per pass and not
+// read again before it is evicted, so it is kept from displacing cache lines.
+template <typename T>
+__device__ __forceinline__ void st_stream(C2<T>* p, const C2<T>& v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.re;
+  w.y = v.im;
+  __builtin_nontemporal_store(w, (v2*)p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+// Streaming (nontemporal) global loads: data read once per pass.
+template <typename T>
+__device__ __forceinline__ C2<T> ld_stream(const C2<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 w = __builtin_nontemporal_load((const v2*)p);
+  return {w.x, w.y};
+}
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // ---------------------------------------------------------------- radix DFTs
 template <typename T, bool INV>
 __device__ __forceinline__ void dft2(C2<T>* v) {

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
   const long long obase = (long long)x * K2 * n1 + y0;
   for (int e = threadIdx.x; e < K2 * P; e += NT) {
     const int k = e / P, c = e - (e / P) * P;
-    if (y0 + c < n1) out[obase + (long long)k * n1 + c] = tile[k * TS + c];
+    if (y0 + c < n1) st_stream(&out[obase + (long long)k * n1 + c], tile[k * TS + c]);
   }
   (void)n0;
 }
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
   const long long obase = (long long)kzl * L * n0 + x0;
   for (int e = threadIdx.x; e < L * P; e += NT) {
     const int ky = e / P, c = e - (e / P) * P;
-    if (x0 + c < n0) out[obase + (long long)ky * n0 + c] = tile[padrow(ky) * TS + c];
+    if (x0 + c < n0) st_stream(&out[obase + (long long)ky * n0 + c], tile[padrow(ky) * TS + c]);
   }
 }
 
@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       C2<T>* d = (C2<T>*)dst + obase;
       for (int e = threadIdx.x; e < NX * P; e += NT) {
         const int x = e / P, c = e - (e / P) * P;
-        d[(long long)x * M1 + c] = tile[row(x) * TS + c];
+        st_stream(&d[(long long)x * M1 + c], tile[row(x) * TS + c]);
       }
       if (DBL) tb ^= 1;
       else __syncthreads();
@@ -509,7 +509,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   auto load = [&](C2<T> (&v)[R0], const void* src) {
     const C2<T>* sp = (const C2<T>*)src + ibase;
 #pragma unroll
-    for (int i = 0; i < R0; ++i) v[i] = valid ? sp[g + G * i] : C2<T>{(T)0, (T)0};
+    // streaming loads here only: measured faster in this pass, slower in the others
+    for (int i = 0; i < R0; ++i) v[i] = valid ? ld_stream(&sp[g + G * i]) : C2<T>{(T)0, (T)0};
   };
   int tb = 0;
   auto emit = [&](C2<T> (&v)[R0], void* dst) {
@@ -523,7 +524,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
     C2<T>* d = (C2<T>*)dst + obase;
     for (int e = threadIdx.x; e < NY * P; e += NT) {
       const int y = e / P, c = e - (e / P) * P;
-      if (c < nvalid) d[(long long)y * a.c1_sy + c] = tile[row(y) * TS + c];
+      if (c < nvalid) st_stream(&d[(long long)y * a.c1_sy + c], tile[row(y) * TS + c]);
     }
     if (DBL) tb ^= 1;
     else __syncthreads();
@@ -628,8 +629,8 @@ __global__ void __launch_bounds__(kC2RThreads) kf_c2r(const PassArgs a) {
     T* ob = oa + n2;
 #pragma unroll
     for (int i = 0; i < NIN; ++i) {
-      if (valid) oa[g + G * i] = v[i].re;
-      if (vb) ob[g + G * i] = v[i].im;
+      if (valid) st_stream(&oa[g + G * i], v[i].re);
+      if (vb) st_stream(&ob[g + G * i], v[i].im);
     }
   }
 }

@@ -242,7 +242,7 @@ def other_workloads(steps, warmup):
     from workloads import dirichlet_3d, neumann_batch, periodic_modes_2d, vortex_rings
     res = {}
     # 2D periodic 64^2 FP64 PS
-    # (three launches), eager and replayed from a captured graph
+    # (one launch: its half spectrum fits one workgroup), eager and replayed from a captured graph
     f, _ = periodic_modes_2d(64, seed=1)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):

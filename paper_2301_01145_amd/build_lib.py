@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhipoisson.so")
 
 SOURCES = ["hp_api.cpp", "hp_batched.cpp", "hp_tune.cpp", "hp_kernels.hip", "hp_fast.hip",
-           "hp_bounded.hip"]
+           "hp_bounded.hip", "hp_small.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

@@ -1234,6 +1234,35 @@ hp_status passes_periodic(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     out.push_back({a, coupled ? 1 : nin});
     return HP_OK;
   }
+  // 2D grids whose half spectrum fits one workgroup's LDS: the whole solve
+  // in one launch (HP_SMALL2D=0 keeps the three general passes)
+  if (nd == 2) {
+    const int dk = diff_kind(P.d.diff, false);
+    const char* e = std::getenv("HP_SMALL2D");
+    const bool ok_diff = dk == D_NONE || dk == D_GRAD || dk == D_NABLA || (dk == D_CURL && nin == 1);
+    const int nbuf = dk == D_NONE ? nin : nin + 1;
+    const int lds = small2d_lds_bytes(P.n[0], P.n[1], p->prec, nbuf);
+    bool bound = true;
+    for (int f = 0; f < nin; ++f) bound = bound && P.in[f];
+    if (ok_diff && bound && lds > 0 && lds <= 160 * 1024 && !(e && std::atoi(e) == 0)) {
+      PassArgs a = base();
+      sandwich_common(a);
+      a.fast = FAST_SMALL2D;
+      a.gM[0] = P.n[0];
+      a.gM[1] = P.n[1];
+      HP_TRY(fast_twiddles(p, P.n[0], &a.tw));
+      HP_TRY(fast_twiddles(p, P.n[1], &a.qtw));
+      a.n_in = nin;
+      a.n_out = nfo;
+      for (int f = 0; f < nin; ++f) a.in[f] = P.in[f];
+      for (int f = 0; f < nfo; ++f) a.out[f] = outptr(f);
+      a.lds_bytes = lds;
+      PassRec r{a, 1};
+      r.bytes = (double)(nin + nfo) * P.n[0] * P.n[1] * p->es;
+      out.push_back(r);
+      return HP_OK;
+    }
+  }
   const int last = nd - 1;
   const int n_last = P.n[last];
   const int K = n_last / 2 + 1;
@@ -1756,7 +1785,7 @@ double model_bytes(hp_plan p, const std::vector<PassRec>& ps) {
 const char* pass_name(const PassArgs& a) {
   static const char* fast_names[] = {"",       "r2c_z",      "fwd_y",       "sandwich_x", "inv_y",
                                      "c2r_z",  "r2r_contig", "r2r_strided", "r2r_sandwich",
-                                     "grad_prep", "add"};
+                                     "grad_prep", "add", "small2d"};
   constexpr int nfast = (int)(sizeof(fast_names) / sizeof(fast_names[0]));
   if (a.fast > 0 && a.fast < nfast) return fast_names[a.fast];
   if (a.fast) return "wavefront";

@@ -1096,6 +1096,7 @@ hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s) {
   if (a.fast == FAST_GRAD_PREP)
     return prec == 0 ? launch_grad_prep<float>(a, s) : launch_grad_prep<double>(a, s);
   if (a.fast == FAST_ADD) return prec == 0 ? launch_add<float>(a, s) : launch_add<double>(a, s);
+  if (a.fast == FAST_SMALL2D) return launch_small2d(a, prec, s);
   if (prec == 0) return launch_bounded_T<float>(a, s);
   return launch_bounded_T<double>(a, s);
 }

@@ -116,7 +116,11 @@ enum FastKind : int { FAST_NONE = 0, FAST_R2C = 1, FAST_FWD_Y = 2, FAST_SANDWICH
                       // elementwise: spectral derivative coefficients (hp_bounded.hip)
                       FAST_GRAD_PREP = 9,
                       // elementwise: out[0] += in[0] (+ in[1]) over gp_ext[0] elements
-                      FAST_ADD = 10 };
+                      FAST_ADD = 10,
+                      // the whole 2D periodic solve in one workgroup (hp_small.hip):
+                      // lengths gM[0] x gM[1], twiddles of the x FFT in tw and of
+                      // the y FFT in qtw, n_in inputs, n_out outputs
+                      FAST_SMALL2D = 11 };
 // Derivative completion in the backward y pass of the free-space path.
 enum InvYMode : int { IY_PLAIN = 0, IY_CURL5 = 1, IY_GRAD2 = 2 };
 
@@ -131,6 +135,10 @@ __host__ __device__ constexpr int wf_r0(int L) {
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s);
+// single-launch 2D periodic solve (hp_small.hip): LDS bytes with nbuf
+// spectral buffers (-1: no kernel for these lengths) and the launch
+int small2d_lds_bytes(int L0, int L1, int prec, int nbuf);
+hipError_t launch_small2d(const PassArgs& a, int prec, hipStream_t s);
 int r2r_tile(int prec);
 int r2r_lds_bytes(int fast, int L, int n, int prec);
 // Dynamic LDS bytes of a wavefront-FFT pass; 0 if the pass is not available.

@@ -99,7 +99,12 @@ bool factorize(int L, int* radix, int* nstage) {
     else if (r % 2 == 0) f = 2;
     else if (r % 3 == 0) f = 3;
     else if (r % 5 == 0) f = 5;
-    else return false;
+    else {
+      // the smallest prime factor (> 5): a direct prime-radix stage
+      f = 7;
+      while (r % f != 0 && (long long)f * f <= r) f += 2;
+      if (r % f != 0) f = r;
+    }
     if (s >= kMaxStages) return false;
     radix[s++] = f;
     r /= f;
@@ -178,7 +183,8 @@ hp_status validate(const hp_desc* d) {
       if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
         return fail(nullptr, HP_E_ARG, "Neumann regular derivatives need 2 cells per axis");
   }
-  // transform lengths must be 2^a 3^b 5^c
+  // any transform length whose radix stages (2, 3, 4, 5, 8 and primes) number at
+  // most kMaxStages, up to the largest tile of one pencil
   for (int a = 0; a < d->ndim; ++a) {
     const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);
     int L = n, xf, xb, rad[kMaxStages], ns;
@@ -187,7 +193,7 @@ hp_status validate(const hp_desc* d) {
     if (unb) L = 2 * n;
     if (!factorize(L, rad, &ns))
       return fail(nullptr, HP_E_UNSUPPORTED,
-                  "transform length " + std::to_string(L) + " is not a product of 2, 3 and 5");
+                  "transform length " + std::to_string(L) + " needs too many radix stages");
     if ((long long)L > (long long)(d->prec == 0 ? 32 : 16) * kMaxLenThreads)
       return fail(nullptr, HP_E_UNSUPPORTED, "transform length too large");
   }

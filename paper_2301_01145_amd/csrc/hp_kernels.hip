@@ -4,7 +4,8 @@
 // workgroup of 256 threads takes a tile of P pencils: it loads the tile from
 // HBM with unit-stride runs (along the pencil when the pencil is contiguous,
 // across pencils otherwise), builds the complex FFT input in LDS, runs a
-// mixed-radix (2/3/4/5/8) Stockham FFT in LDS and writes the result with
+// mixed-radix (2/3/4/5/8, and any larger prime as a direct stage) Stockham
+// FFT in LDS and writes the result with
 // unit-stride runs again.  The strides of the input and output sides are
 // independent, so a pass can also transpose.
 //
@@ -70,6 +71,53 @@ __device__ __attribute__((noinline)) void fft_stage(C2<T>* Z, int L, int nfft, i
   __syncthreads();
 }
 
+// One stage of a prime radix R > 5 (lengths with a prime factor that the fixed
+// radices do not cover).  Output t' of butterfly j (k = j mod Ns) is the
+// R-term sum  sum_t x[j + t L/R] W_{Ns R}^{t (k + t' Ns)}: the stage twiddle
+// W_{Ns R}^{t k} and the R-point DFT factor W_R^{t t'} in one table entry.
+// It costs R multiply-adds per output instead of O(log R), which is what a
+// direct DFT of a prime length costs.  One output per thread slot (the tile
+// holds at most kThreads * MAXE elements); all reads finish (barrier) before
+// any write, so the stage is in place like the fixed-radix ones.
+template <typename T, int MAXE, bool INV>
+__device__ __attribute__((noinline)) void fft_stage_prime(C2<T>* Z, int L, int nfft, int R, int Ns,
+                                                          int twstep, const C2<T>* __restrict__ tw) {
+  const int nbl = L / R;
+  const int total = nfft * L;
+  C2<T> v[MAXE];
+  int ob[MAXE];
+#pragma unroll
+  for (int b = 0; b < MAXE; ++b) {
+    const int idx = threadIdx.x + b * kThreads;
+    ob[b] = -1;
+    if (idx < total) {
+      const int f = idx / L;
+      const int r = idx - f * L;
+      const int j = r / R, tp = r - j * R;  // butterfly j, output t'
+      const int k = j % Ns;
+      const C2<T>* src = Z + f * L + j;
+      // exponent of W_L for term t: t (k + t' Ns) twstep mod L, stepped by e1 < L
+      const int e1 = (k + tp * Ns) * twstep;
+      int e = 0;
+      C2<T> acc = {(T)0, (T)0};
+      for (int t = 0; t < R; ++t) {
+        C2<T> w = tw[e];
+        if (INV) w.im = -w.im;
+        acc = cadd(acc, cmul(src[t * nbl], w));
+        e += e1;
+        if (e >= L) e -= L;
+      }
+      v[b] = acc;
+      ob[b] = f * L + (j - k) * R + k + tp * Ns;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXE; ++b)
+    if (ob[b] >= 0) Z[ob[b]] = v[b];
+  __syncthreads();
+}
+
 // Complex elements per thread of one stage: BIG = 0 holds 16 (FP32) / 8
 // (FP64), fewer registers and more resident waves; BIG = 1 holds 32 / 16 for
 // tiles of long transforms.
@@ -93,7 +141,8 @@ __device__ void fft_lds(C2<T>* Z, int nfft, const PassArgs& a) {
       case 4: fft_stage<T, 4, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
       case 2: fft_stage<T, 2, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
       case 3: fft_stage<T, 3, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
-      default: fft_stage<T, 5, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+      case 5: fft_stage<T, 5, ME, INV>(Z, L, nfft, Ns, twstep, tw); break;
+      default: fft_stage_prime<T, ME, INV>(Z, L, nfft, R, Ns, twstep, tw); break;
     }
     Ns *= R;
   }

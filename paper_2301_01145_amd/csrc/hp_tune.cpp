@@ -48,7 +48,8 @@ size_t elems(const int* n, int nd) {
   return c;
 }
 
-// Radix orders of L = 2^a 3^b 5^c that the general kernels run.
+// Radix orders of L = 2^a 3^b 5^c that the general kernels run (none for
+// lengths with a larger prime factor: those keep the planner's order).
 std::vector<std::vector<int>> radix_orders(int L) {
   int a = 0, b = 0, c = 0, r = L;
   while (r % 2 == 0) { r /= 2; ++a; }

@@ -59,7 +59,9 @@ BAD = [
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8], diff="grad", kernel="fd2", inhomogeneous=True),
      _lib.HP_E_UNSUPPORTED),
     (dict(bc="neumann", grid="regular", nc=[1], diff="grad"), _lib.HP_E_ARG),
-    (dict(bc="periodic", grid="staggered", nc=[7, 8]), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="periodic", grid="staggered", nc=[7, 8]), None),  # prime length: a direct radix-7 stage
+    (dict(bc="periodic", grid="staggered", nc=[8193], prec="f32"), _lib.HP_E_UNSUPPORTED),  # longer than a tile
+    (dict(bc="periodic", grid="staggered", nc=[4097], prec="f64"), _lib.HP_E_UNSUPPORTED),
     (dict(bc="periodic", grid="staggered", nc=[0, 8]), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="regular", nc=[1]), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[8], lo=[1.0], hi=[1.0]), _lib.HP_E_ARG),

@@ -27,9 +27,25 @@ def zero_mode(bc, grid_type, nc, lo, hi, f, faces=None):
     coefficient of the forward transform of the right-hand side (boundary
     terms included, FD2) divided by the k = 0 coefficient of a field of ones.
     Zero for Dirichlet and free-space problems, and for compatible sources."""
+    nd = len(nc)
+    if isinstance(bc, (list, tuple)):
+        # a condition per axis: a zero eigenvalue sum only without Dirichlet axes
+        if any(b not in ("periodic", "neumann") for b in bc):
+            return 0.0
+        hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
+        f = np.asarray(f, dtype=np.float64)
+        if faces:
+            f = bounded.apply_boundary_values_mixed(f, list(bc), grid_type, hs, faces)
+        a_hat, o_hat = f, np.ones_like(f)
+        for a in range(nd):
+            if bc[a] == "periodic":
+                a_hat, o_hat = np.fft.fft(a_hat, axis=a).real, np.fft.fft(o_hat, axis=a).real
+            else:
+                fwd = bounded.TRANSFORM_PAIRS[(bc[a], grid_type)][0]
+                a_hat, o_hat = transforms.apply(fwd, a_hat, a), transforms.apply(fwd, o_hat, a)
+        return float(a_hat.flat[0] / o_hat.flat[0])
     if bc not in ("periodic", "neumann"):
         return 0.0
-    nd = len(nc)
     hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
     f = np.asarray(f, dtype=np.float64)
     if faces:
@@ -49,7 +65,8 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
           faces=None, sigma_cells=2.0):
     """One solve described like the library's plan descriptor.
 
-    bc: "periodic" | "dirichlet" | "neumann" | "unbounded"
+    bc: "periodic" | "dirichlet" | "neumann" | "unbounded", or one of the first
+        three per axis (a list) for a mixed-boundary solve
     grid_type: "regular" | "staggered"
     nc, lo, hi: per-axis cell count and domain bounds (length = ndim)
     f: source on the unknown points (scalar), or (3, ...) for a 3D vector
@@ -68,6 +85,16 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
     lengths = [float(hi[a]) - float(lo[a]) for a in range(nd)]
     f = np.asarray(f, dtype=np.float64)
+    if isinstance(bc, (list, tuple)):
+        # a condition per axis (bounded.solve_mixed); psi only
+        if diff != "none":
+            raise NotImplementedError("mixed-boundary solves: psi only")
+        vector = f.ndim == nd + 1
+        comps = [f[c] for c in range(f.shape[0])] if vector else [f]
+        psi = [bounded.solve_mixed(c, list(bc), grid_type, operator, lengths, hs,
+                                   (faces[i] if (faces and vector) else faces))
+               for i, c in enumerate(comps)]
+        return (np.stack(psi) if vector else psi[0]), []
     if bc == "unbounded":
         sigma = float(sigma_cells) * max(hs)
         kernel = operator if operator in unbounded.KERNELS else "g2"

@@ -272,3 +272,100 @@ def bounded_curl(psi, bc, grid, nc, lengths):
     from bounded_derivative."""
     d = lambda c, a: bounded_derivative(psi[c], bc, grid, nc, lengths, a, 1)
     return [d(2, 1) - d(1, 2), d(0, 2) - d(2, 0), d(1, 0) - d(0, 1)]
+
+
+# ------------------------------------------------------------------ mixed BCs
+# Section 2.6 describes building a solve from 1D transforms per axis, a DFT,
+# DST or DCT chosen per direction, so that each axis can carry its own
+# boundary condition.  The paper plans this without implementing it; the
+# oracle writes it out directly: every axis takes the forward transform of its
+# own condition (the complex DFT for a periodic axis, the Table 1 pair
+# otherwise), the spectrum is divided by the sum of the per-axis Table 1
+# eigenvalues (eq. pois_spec), and every axis takes its backward transform.
+
+def _apply_real_pair(kind, x, axis):
+    """A real-to-real transform applied to the real and imaginary parts."""
+    x = np.asarray(x)
+    if np.iscomplexobj(x):
+        return _tr.apply(kind, x.real, axis) + 1j * _tr.apply(kind, x.imag, axis)
+    return _tr.apply(kind, x, axis)
+
+
+def apply_boundary_values_mixed(f, bcs, grid, hs, faces):
+    """apply_boundary_values with a condition per axis: each face takes the
+    weight of its own axis's condition; the face arrays span the output points
+    of the other axes, so their boundary nodes are dropped along REGULAR
+    Dirichlet axes only."""
+    f = np.array(f, dtype=np.float64, copy=True)
+    nd = f.ndim
+    for (axis, side), g in faces.items():
+        bc = bcs[axis]
+        if bc == "periodic":
+            raise ValueError("a periodic axis has no faces")
+        g = np.asarray(g, dtype=np.float64)
+        rest = [b for b in range(nd) if b != axis]
+        g = g[tuple(slice(1, -1) if (bcs[b] == "dirichlet" and grid == "regular") else slice(None)
+                    for b in rest)]
+        h = hs[axis]
+        if bc == "dirichlet" and grid == "regular":
+            term = -g / h**2
+        elif bc == "dirichlet":
+            term = -2.0 * g / h**2
+        elif grid == "regular":
+            term = (2.0 * g / h) if side == 0 else (-2.0 * g / h)
+        else:
+            term = (g / h) if side == 0 else (-g / h)
+        idx = [slice(None)] * nd
+        idx[axis] = 0 if side == 0 else f.shape[axis] - 1
+        f[tuple(idx)] += term
+    return f
+
+
+def mixed_output(psi_inner, bcs, grid, faces):
+    """Embed the unknowns into the output points: REGULAR Dirichlet axes gain
+    their two boundary nodes, which take their face's value (a node on several
+    faces: the face of the highest axis index; missing faces are 0)."""
+    nd = psi_inner.ndim
+    dreg = [bcs[a] == "dirichlet" and grid == "regular" for a in range(nd)]
+    out = np.zeros(tuple(n + 2 if dreg[a] else n for a, n in enumerate(psi_inner.shape)))
+    out[tuple(slice(1, -1) if dreg[a] else slice(None) for a in range(nd))] = psi_inner
+    for axis in range(nd):
+        if not dreg[axis]:
+            continue
+        for side in (0, 1):
+            g = faces.get((axis, side)) if faces else None
+            idx = [slice(None)] * nd
+            idx[axis] = 0 if side == 0 else out.shape[axis] - 1
+            out[tuple(idx)] = 0.0 if g is None else np.asarray(g, dtype=np.float64)
+    return out
+
+
+def solve_mixed(f, bcs, grid, operator, lengths, hs, faces=None):
+    """Solve lap(psi) = f with condition bcs[a] ("periodic", "dirichlet" or
+    "neumann") on axis a.  f has the unknown shape; returns psi on the output
+    points."""
+    f = np.asarray(f, dtype=np.float64)
+    nd = f.ndim
+    if faces:
+        if operator != "fd2":
+            raise ValueError("inhomogeneous boundary values need the FD2 operator")
+        f = apply_boundary_values_mixed(f, bcs, grid, hs, faces)
+    lam = np.zeros(f.shape)
+    for a in range(nd):
+        view = [1] * nd
+        view[a] = f.shape[a]
+        lam = lam + eigenvalues(bcs[a], grid, operator, f.shape[a], lengths[a], hs[a]).reshape(view)
+    fhat = f.astype(np.complex128)
+    for a in range(nd):
+        if bcs[a] == "periodic":
+            fhat = np.fft.fft(fhat, axis=a)
+        else:
+            fhat = _apply_real_pair(TRANSFORM_PAIRS[(bcs[a], grid)][0], fhat, a)
+    psi = _divide(fhat, lam)
+    for a in reversed(range(nd)):
+        if bcs[a] == "periodic":
+            psi = np.fft.ifft(psi, axis=a)
+        else:
+            _, bwd, norm = TRANSFORM_PAIRS[(bcs[a], grid)]
+            psi = _apply_real_pair(bwd, psi, a) / norm(f.shape[a])
+    return mixed_output(psi.real, bcs, grid, faces or {})

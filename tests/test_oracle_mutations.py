@@ -244,3 +244,46 @@ def test_bounded_divergence_axis_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "bounded_derivative", wrong)
     _fails(pb.test_bounded_curl_and_div_of_eigenmodes, "neumann", "regular", "fd2")
+
+
+def test_mixed_face_weight_axis_is_caught(monkeypatch):
+    # every face weighted by the condition of axis 0
+    import test_oracle_mixed as pm
+    orig = bounded.apply_boundary_values_mixed
+
+    def wrong(f, bcs, grid, hs, faces):
+        return orig(f, [bcs[0]] * len(bcs), grid, hs, faces)
+
+    monkeypatch.setattr(bounded, "apply_boundary_values_mixed", wrong)
+    _fails(pm.test_mixed_fd2_matches_dense_solve, ["dirichlet", "neumann"], "staggered", True)
+
+
+def test_mixed_periodic_eigenvalue_is_caught(monkeypatch):
+    # a periodic axis given the Neumann eigenvalues (pi k / L instead of 2 pi k~ / L)
+    import test_oracle_mixed as pm
+    orig = bounded.eigenvalues
+
+    def wrong(bc, grid, operator, n, length, h):
+        return orig("neumann" if bc == "periodic" else bc, grid, operator, n, length, h)
+
+    monkeypatch.setattr(bounded, "eigenvalues", wrong)
+    _fails(pm.test_mixed_ps_closed_form, ["periodic", "dirichlet"], "staggered")
+
+
+def test_mixed_boundary_node_side_is_caught(monkeypatch):
+    # the lower boundary nodes of a REGULAR Dirichlet axis given the upper face
+    import test_oracle_mixed as pm
+    orig = bounded.mixed_output
+
+    def wrong(psi_inner, bcs, grid, faces):
+        out = orig(psi_inner, bcs, grid, faces)
+        nd = psi_inner.ndim
+        for a in range(nd):
+            if bcs[a] == "dirichlet" and grid == "regular" and faces and (a, 1) in faces:
+                idx = [slice(None)] * nd
+                idx[a] = 0
+                out[tuple(idx)] = np.asarray(faces[(a, 1)])
+        return out
+
+    monkeypatch.setattr(bounded, "mixed_output", wrong)
+    _fails(pm.test_mixed_fd2_matches_dense_solve, ["dirichlet", "neumann", "periodic"], "regular", True)

@@ -62,7 +62,17 @@ typedef enum {
   HP_E_STATE = -5        /* call out of order (e.g. output before a solve) */
 } hp_status;
 
-typedef enum { HP_PERIODIC = 0, HP_DIRICHLET = 1, HP_NEUMANN = 2, HP_UNBOUNDED = 3 } hp_bc;
+/* HP_MIXED: a different condition per axis, each periodic, Dirichlet or
+ * Neumann (bc_axis of the descriptor; both faces of an axis alike).  The
+ * paper builds its solves from 1D transforms per axis (Section 2.6 names
+ * mixed conditions through combinations of DST, DCT and DFT); here a periodic
+ * axis runs the discrete Hartley transform (real to real, its own inverse up
+ * to n, diagonal for the periodic Laplacian) beside the Table 1 sine and
+ * cosine transforms, with the eigenvalue sum of eq. (pois_spec) over the
+ * axes.  PS or FD2; boundary values (FD2) on the Dirichlet / Neumann faces;
+ * no derivative outputs (HP_E_UNSUPPORTED). */
+typedef enum { HP_PERIODIC = 0, HP_DIRICHLET = 1, HP_NEUMANN = 2, HP_UNBOUNDED = 3,
+               HP_MIXED = 4 } hp_bc;
 typedef enum { HP_REGULAR = 0, HP_STAGGERED = 1 } hp_grid;
 /* Spectral multiplier: PS / FD2 eigenvalues (Table 1) for bounded BCs; for
  * unbounded ones a 3D free-space kernel of Section 2.5.2, which names Gaussian
@@ -107,13 +117,15 @@ typedef struct {
   int ncomp;            /* 1 (scalar) or 3 (3D vector, component-wise) */
   int64_t nc[3];        /* cells per axis N_c (entries >= ndim ignored) */
   double lo[3], hi[3];  /* domain bounds X_l < X_u per axis */
-  int bc;               /* hp_bc, the same on every face */
+  int bc;               /* hp_bc, the same on every face (HP_MIXED: per axis) */
   int grid;             /* hp_grid */
   int kernel;           /* hp_kernel */
   int diff;             /* hp_diff */
   int prec;             /* hp_prec: data and FFT precision; tables are FP64-built */
   int inhomogeneous;    /* 1: boundary values from hp_set_boundary (FD2 only) */
   double reg_sigma_cells; /* G2 width sigma in units of max_a H_a; 0 -> 2.0 */
+  int bc_axis[3];       /* bc == HP_MIXED: hp_bc of each axis (HP_PERIODIC,
+                           HP_DIRICHLET or HP_NEUMANN); ignored otherwise */
 } hp_desc;
 
 /* Query keys for hp_query. */
@@ -174,7 +186,8 @@ HP_API hp_status hp_set_input(hp_plan plan, int problem, int comp, const void* f
 /* Boundary values of face (axis, side) (side 0 = lower, 1 = upper) for
  * inhomogeneous FD2 Dirichlet / Neumann plans (Section 2.4.2): an array with
  * the output shape of the other axes (ascending axis order).  Dirichlet: psi
- * on the face; Neumann: d(psi)/dx_axis on the face.  NULL = homogeneous. */
+ * on the face; Neumann: d(psi)/dx_axis on the face.  NULL = homogeneous.  A
+ * periodic axis of an HP_MIXED plan has no faces (HP_E_ARG unless g is NULL). */
 HP_API hp_status hp_set_boundary(hp_plan plan, int problem, int axis, int side, int comp,
                           const void* g, int on_device);
 

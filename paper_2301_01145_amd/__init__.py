@@ -24,7 +24,9 @@ DIFFS = {"none": _lib.HP_D_NONE, "grad": _lib.HP_D_GRAD, "curl": _lib.HP_D_CURL,
 
 def make_desc(bc, grid, nc, lo=None, hi=None, kernel=None, diff="none", prec="f32", ncomp=1,
               inhomogeneous=False, sigma_cells=0.0):
-    """Build an hp_desc from readable options (see include/hipoisson.h)."""
+    """Build an hp_desc from readable options (see include/hipoisson.h).  bc is
+    one name for every face, or one name per axis ("periodic", "dirichlet",
+    "neumann") for a mixed-boundary plan."""
     nd = len(nc)
     lo = list(lo) if lo is not None else [0.0] * nd
     hi = list(hi) if hi is not None else [1.0] * nd
@@ -37,7 +39,14 @@ def make_desc(bc, grid, nc, lo=None, hi=None, kernel=None, diff="none", prec="f3
         d.nc[a] = int(nc[a]) if a < nd else 1
         d.lo[a] = float(lo[a]) if a < nd else 0.0
         d.hi[a] = float(hi[a]) if a < nd else 1.0
-    d.bc = BCS[bc]
+    if isinstance(bc, (list, tuple)):
+        if len(bc) != nd:
+            raise ValueError("one boundary condition per axis")
+        d.bc = _lib.HP_MIXED
+        for a in range(nd):
+            d.bc_axis[a] = BCS[bc[a]]
+    else:
+        d.bc = BCS[bc]
     d.grid = GRIDS[grid]
     d.kernel = KERNELS[kernel]
     d.diff = DIFFS[diff]

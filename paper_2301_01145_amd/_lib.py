@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhipoisson.so")
 
 HP_OK, HP_E_ARG, HP_E_UNSUPPORTED, HP_E_NOMEM, HP_E_DEVICE, HP_E_STATE = 0, -1, -2, -3, -4, -5
-HP_PERIODIC, HP_DIRICHLET, HP_NEUMANN, HP_UNBOUNDED = 0, 1, 2, 3
+HP_PERIODIC, HP_DIRICHLET, HP_NEUMANN, HP_UNBOUNDED, HP_MIXED = 0, 1, 2, 3, 4
 HP_REGULAR, HP_STAGGERED = 0, 1
 HP_OP_PS, HP_OP_FD2, HP_G_GAUSS2 = 0, 1, 2
 HP_G_GAUSS4, HP_G_GAUSS6, HP_G_GAUSS8, HP_G_GAUSS10, HP_G_SPECTRAL = 3, 4, 5, 6, 7
@@ -47,6 +47,7 @@ class hp_desc(ctypes.Structure):
         ("prec", ctypes.c_int),
         ("inhomogeneous", ctypes.c_int),
         ("reg_sigma_cells", ctypes.c_double),
+        ("bc_axis", ctypes.c_int * 3),
     ]
 
 

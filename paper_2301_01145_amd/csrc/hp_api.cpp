@@ -81,9 +81,31 @@ int outputs(int bc, int grid, int nc) {
   return unknowns(bc, grid, nc);
 }
 
-// Forward / backward transform of Table 1 and the FFT length they need.
+// Condition of axis a (the descriptor's, or its per-axis entry for HP_MIXED).
+int axis_bc(const hp_desc& d, int a) { return d.bc == HP_MIXED ? d.bc_axis[a] : d.bc; }
+// Plans solved by the real-to-real passes: Dirichlet, Neumann and mixed.
+bool r2r_plan(const hp_desc& d) {
+  return d.bc == HP_DIRICHLET || d.bc == HP_NEUMANN || d.bc == HP_MIXED;
+}
+// A k = 0 eigenvalue sum of zero (periodic and Neumann on every axis).
+bool has_zero_mode(const hp_desc& d) {
+  for (int a = 0; a < d.ndim; ++a)
+    if (axis_bc(d, a) != HP_PERIODIC && axis_bc(d, a) != HP_NEUMANN) return false;
+  return true;
+}
+// Bit a set: axis a is a REGULAR Dirichlet axis (output carries its boundary nodes).
+int dreg_axes(const hp_desc& d) {
+  int m = 0;
+  for (int a = 0; a < d.ndim; ++a)
+    if (axis_bc(d, a) == HP_DIRICHLET && d.grid == HP_REGULAR) m |= 1 << a;
+  return m;
+}
+
+// Forward / backward transform of Table 1 and the FFT length they need (a
+// periodic axis of a mixed plan: the Hartley transform, its own inverse up to n).
 void r2r_ops(int bc, int grid, int n, int* xf, int* xb, int* L, double* c) {
-  if (bc == HP_DIRICHLET && grid == HP_REGULAR) { *xf = X_DST1; *xb = X_DST1; *L = 2 * (n + 1); *c = 2.0 * (n + 1); }
+  if (bc == HP_PERIODIC) { *xf = X_DHT; *xb = X_DHT; *L = n; *c = (double)n; }
+  else if (bc == HP_DIRICHLET && grid == HP_REGULAR) { *xf = X_DST1; *xb = X_DST1; *L = 2 * (n + 1); *c = 2.0 * (n + 1); }
   else if (bc == HP_DIRICHLET) { *xf = X_DST2; *xb = X_DST3; *L = 2 * n; *c = 2.0 * n; }
   else if (grid == HP_REGULAR) { *xf = X_DCT1; *xb = X_DCT1; *L = 2 * (n - 1); *c = 2.0 * (n - 1); }
   else { *xf = X_DCT2; *xb = X_DCT3; *L = 2 * n; *c = 2.0 * n; }
@@ -142,7 +164,14 @@ hp_status validate(const hp_desc* d) {
   if (d->ndim < 1 || d->ndim > 3) return fail(nullptr, HP_E_ARG, "ndim must be 1, 2 or 3");
   if (d->ncomp != 1 && d->ncomp != 3) return fail(nullptr, HP_E_ARG, "ncomp must be 1 or 3");
   if (d->ncomp == 3 && d->ndim != 3) return fail(nullptr, HP_E_ARG, "vector fields need ndim 3");
-  if (d->bc < 0 || d->bc > 3) return fail(nullptr, HP_E_ARG, "bad bc");
+  if (d->bc < 0 || d->bc > 4) return fail(nullptr, HP_E_ARG, "bad bc");
+  if (d->bc == HP_MIXED) {
+    for (int a = 0; a < d->ndim; ++a)
+      if (d->bc_axis[a] != HP_PERIODIC && d->bc_axis[a] != HP_DIRICHLET && d->bc_axis[a] != HP_NEUMANN)
+        return fail(nullptr, HP_E_ARG, "mixed plans take a periodic, Dirichlet or Neumann axis each");
+    if (d->diff != HP_D_NONE)
+      return fail(nullptr, HP_E_UNSUPPORTED, "mixed-boundary plans take no derivative outputs");
+  }
   if (d->grid < 0 || d->grid > 1) return fail(nullptr, HP_E_ARG, "bad grid");
   if (d->kernel < 0 || d->kernel > HP_G_SPECTRAL) return fail(nullptr, HP_E_ARG, "bad kernel");
   if (d->diff < 0 || d->diff > HP_D_NABLA) return fail(nullptr, HP_E_ARG, "bad diff");
@@ -153,9 +182,9 @@ hp_status validate(const hp_desc* d) {
     if (d->nc[a] < 1 || d->nc[a] > (1 << 20)) return fail(nullptr, HP_E_ARG, "nc out of range");
     if (!(d->hi[a] > d->lo[a]) || !std::isfinite(d->lo[a]) || !std::isfinite(d->hi[a]))
       return fail(nullptr, HP_E_ARG, "need lo < hi on every axis");
-    const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);
+    const int n = unknowns(axis_bc(*d, a), d->grid, (int)d->nc[a]);
     if (n < 1) return fail(nullptr, HP_E_ARG, "too few cells for this BC and grid");
-    if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && n < 2)
+    if (axis_bc(*d, a) == HP_NEUMANN && d->grid == HP_REGULAR && n < 2)
       return fail(nullptr, HP_E_ARG, "too few cells for this BC and grid");
   }
   const bool unb = d->bc == HP_UNBOUNDED;
@@ -164,7 +193,10 @@ hp_status validate(const hp_desc* d) {
   if (!unb && d->kernel >= HP_G_GAUSS2)
     return fail(nullptr, HP_E_ARG, "bounded plans take PS or FD2 eigenvalues");
   if (d->inhomogeneous) {
-    if (d->bc != HP_DIRICHLET && d->bc != HP_NEUMANN)
+    bool faces = false;
+    for (int a = 0; a < d->ndim; ++a)
+      faces = faces || axis_bc(*d, a) == HP_DIRICHLET || axis_bc(*d, a) == HP_NEUMANN;
+    if (!r2r_plan(*d) || !faces)
       return fail(nullptr, HP_E_ARG, "boundary values need a Dirichlet or Neumann BC");
     if (d->kernel != HP_OP_FD2)
       return fail(nullptr, HP_E_UNSUPPORTED, "inhomogeneous BCs need FD2 eigenvalues");
@@ -186,10 +218,10 @@ hp_status validate(const hp_desc* d) {
   // any transform length whose radix stages (2, 3, 4, 5, 8 and primes) number at
   // most kMaxStages, up to the largest tile of one pencil
   for (int a = 0; a < d->ndim; ++a) {
-    const int n = unknowns(d->bc, d->grid, (int)d->nc[a]);
+    const int n = unknowns(axis_bc(*d, a), d->grid, (int)d->nc[a]);
     int L = n, xf, xb, rad[kMaxStages], ns;
     double c;
-    if (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN) r2r_ops(d->bc, d->grid, n, &xf, &xb, &L, &c);
+    if (r2r_plan(*d)) r2r_ops(axis_bc(*d, a), d->grid, n, &xf, &xb, &L, &c);
     if (unb) L = 2 * n;
     if (!factorize(L, rad, &ns))
       return fail(nullptr, HP_E_UNSUPPORTED,
@@ -545,19 +577,20 @@ hp_status setup_problem(hp_plan p, Problem& P) {
   for (int a = 0; a < P.nd; ++a) {
     P.len[a] = d.hi[a] - d.lo[a];
     P.h[a] = P.len[a] / (double)d.nc[a];
-    P.n[a] = unknowns(d.bc, d.grid, (int)d.nc[a]);
-    P.nout[a] = outputs(d.bc, d.grid, (int)d.nc[a]);
+    P.n[a] = unknowns(axis_bc(d, a), d.grid, (int)d.nc[a]);
+    P.nout[a] = outputs(axis_bc(d, a), d.grid, (int)d.nc[a]);
     P.M[a] = 2 * P.n[a];
   }
   const size_t es = p->es;
-  if (d.bc == HP_DIRICHLET || d.bc == HP_NEUMANN) {
+  if (r2r_plan(d)) {
     P.norm = 1.0;
     for (int a = 0; a < P.nd; ++a) {
       int xf, xb, L;
       double c;
-      r2r_ops(d.bc, d.grid, P.n[a], &xf, &xb, &L, &c);
+      r2r_ops(axis_bc(d, a), d.grid, P.n[a], &xf, &xb, &L, &c);
       P.norm /= c;
-      HP_TRY(upload(p, eigen(d.bc, d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false, (void**)&P.lam[a]));
+      HP_TRY(upload(p, eigen(axis_bc(d, a), d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false,
+                    (void**)&P.lam[a]));
     }
     if (P.nder) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.grad_s));
     // second terms of DIV (d_y psi_y, d_z psi_z) and of the 3D curl, added
@@ -687,7 +720,7 @@ void fill_face_terms(const Problem& P, int comp, PassArgs& a) {
   const hp_desc& d = P.d;
   if (!d.inhomogeneous) return;
   const int nd = P.nd;
-  a.face_off = (d.bc == HP_DIRICHLET && d.grid == HP_REGULAR) ? 1 : 0;
+  a.face_off = dreg_axes(d);
   for (int ax = 0; ax < nd; ++ax) {
     int rem[2], nr = 0;
     for (int b = 0; b < nd; ++b)
@@ -696,10 +729,11 @@ void fill_face_terms(const Problem& P, int comp, PassArgs& a) {
     if (nr == 2) { a.face_s[ax][1] = 1; a.face_s[ax][0] = P.nout[rem[1]]; }
     else if (nr == 1) { a.face_s[ax][0] = 1; }
     const double h = P.h[ax];
+    const int bc = axis_bc(d, ax);
     for (int side = 0; side < 2; ++side) {
-      a.face[ax][side] = P.face[ax][side][comp];
+      a.face[ax][side] = bc == HP_PERIODIC ? nullptr : P.face[ax][side][comp];
       double w;
-      if (d.bc == HP_DIRICHLET) w = (d.grid == HP_REGULAR ? -1.0 : -2.0) / (h * h);
+      if (bc == HP_DIRICHLET) w = (d.grid == HP_REGULAR ? -1.0 : -2.0) / (h * h);
       else if (d.grid == HP_REGULAR) w = (side == 0 ? 2.0 : -2.0) / h;
       else w = (side == 0 ? 1.0 : -1.0) / h;
       a.face_w[ax][side] = w;
@@ -830,6 +864,7 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
 bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
   if (std::getenv("HP_GENERIC") || p->batched || P.nd < 2) return false;
   for (int a = 0; a < P.nd; ++a) {
+    if (axis_bc(P.d, a) == HP_PERIODIC) return false;  // Hartley axes: general kernels
     if (L[a] < 64 || L[a] > 512 || wf_r0(L[a]) <= 0) return false;
     for (int k = FAST_R2R_C; k <= FAST_R2R_SW; ++k) {
       const int lds = r2r_lds_bytes(k, L[a], P.n[a], p->prec);
@@ -863,7 +898,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   const int nd = P.nd;
   int xf[3], xb[3], L[3];
   double c[3];
-  for (int a = 0; a < nd; ++a) r2r_ops(d.bc, d.grid, P.n[a], &xf[a], &xb[a], &L[a], &c[a]);
+  for (int a = 0; a < nd; ++a) r2r_ops(axis_bc(d, a), d.grid, P.n[a], &xf[a], &xb[a], &L[a], &c[a]);
   const size_t first_pass = out.size();
   // work view = the output array (interior for REGULAR Dirichlet)
   int od[3] = {1, 1, 1}, idims[3] = {1, 1, 1};
@@ -878,9 +913,10 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   for (int a = 0; a < 3; ++a) ws[a] = fs[a] = 0;
   for (int a = 0; a < nd; ++a) { ws[a] = os3[3 - nd + a]; fs[a] = is3[3 - nd + a]; }
   const bool dreg = d.bc == HP_DIRICHLET && d.grid == HP_REGULAR;
+  const int dmask = dreg_axes(d);
   long long woff = 0;
-  if (dreg)
-    for (int a = 0; a < nd; ++a) woff += ws[a];
+  for (int a = 0; a < nd; ++a)
+    if ((dmask >> a) & 1) woff += ws[a];
   const size_t es = p->es;
   auto work = [&](int comp) { return (void*)((char*)P.out[comp] + woff * es); };
 
@@ -1854,7 +1890,7 @@ void zero_mode_setup(const Problem& P, int c, PassArgs& a, int trap[3], double* 
   trap[0] = trap[1] = trap[2] = 0;
   *W = 1.0;
   for (int b = 0; b < P.nd; ++b) {
-    trap[b] = (P.d.bc == HP_NEUMANN && P.d.grid == HP_REGULAR) ? 1 : 0;
+    trap[b] = (axis_bc(P.d, b) == HP_NEUMANN && P.d.grid == HP_REGULAR) ? 1 : 0;
     *W *= trap[b] ? (double)(P.n[b] - 1) : (double)P.n[b];
   }
 }
@@ -2020,6 +2056,7 @@ hp_status hp_set_boundary(hp_plan plan, int problem, int axis, int side, int com
     P->face[axis][side][comp] = nullptr;
     return HP_OK;
   }
+  if (axis_bc(P->d, axis) == HP_PERIODIC) return fail(plan, HP_E_ARG, "a periodic axis has no faces");
   size_t cnt = 1;
   for (int b = 0; b < P->nd; ++b)
     if (b != axis) cnt *= (size_t)P->nout[b];
@@ -2053,7 +2090,7 @@ hp_status hp_solve(hp_plan plan) {
   std::vector<PassRec> ps;
   HP_TRY(build_passes(plan, P, false, ps));
   HP_TRY(run_passes(plan, ps));
-  if (P.d.bc == HP_DIRICHLET && P.d.grid == HP_REGULAR) {
+  if (dreg_axes(P.d)) {
     for (int c = 0; c < P.ncomp; ++c) {
       const void* faces[3][2] = {};
       for (int a = 0; a < P.nd; ++a)
@@ -2063,7 +2100,8 @@ hp_status hp_solve(hp_plan plan) {
       // the fill kernel indexes logical axes; pass dims in logical order
       int Nl[3] = {P.nout[0], P.nd > 1 ? P.nout[1] : 1, P.nd > 2 ? P.nout[2] : 1};
       (void)N;
-      HP_HIP(plan, launch_dirichlet_fill(P.out[c], Nl, P.nd, faces, plan->prec, plan->stream));
+      HP_HIP(plan, launch_dirichlet_fill(P.out[c], Nl, P.nd, dreg_axes(P.d), faces, plan->prec,
+                                         plan->stream));
     }
   }
   plan->solved = true;
@@ -2195,7 +2233,7 @@ hp_status hp_query(hp_plan plan, int what, double* value) {
     case HP_Q_ZERO_MODE: {
       if (plan->batched) return fail(plan, HP_E_ARG, "zero mode: single-problem plans");
       *value = 0.0;
-      if (P.d.bc != HP_PERIODIC && P.d.bc != HP_NEUMANN) return HP_OK;
+      if (!has_zero_mode(P.d)) return HP_OK;
       const int nb = kZeroModeBlocks;
       if (!plan->zm_partial) HP_TRY(dev_alloc(plan, nb * sizeof(double), (void**)&plan->zm_partial));
       double best = 0.0;
@@ -2266,7 +2304,7 @@ hp_status hp_zero_mode_noalloc(hp_plan plan, double* out) {
   const void* f[kZeroModeMaxComp] = {};
   double W[kZeroModeMaxComp] = {0.0, 0.0, 0.0};
   int trap[3] = {0, 0, 0};
-  const bool has_zero = P.d.bc == HP_PERIODIC || P.d.bc == HP_NEUMANN;
+  const bool has_zero = has_zero_mode(P.d);
   for (int c = 0; c < P.ncomp; ++c) {
     if (!P.in[c]) return fail(plan, HP_E_STATE, "input component " + std::to_string(c) + " not set");
     f[c] = P.in[c];

@@ -29,7 +29,7 @@ __device__ __forceinline__ double face_terms(const PassArgs& a, int j, int p, in
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         if (b == ax || a.nunk[b] <= 0) continue;
-        if (r < 2) off += (long long)(c[b] + a.face_off) * a.face_s[ax][r];
+        if (r < 2) off += (long long)(c[b] + ((a.face_off >> b) & 1)) * a.face_s[ax][r];
         ++r;
       }
       add += a.face_w[ax][side] * (double)g[off];

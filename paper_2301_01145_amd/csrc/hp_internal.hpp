@@ -21,7 +21,10 @@ enum Xform : int {
   X_DST3 = 8,   // via DCT-III of the reversed input, (-1)^k output
   X_DCT1 = 9,   // L = 2 (n - 1), even extension
   X_DCT2 = 10,  // L = 2 n, symmetric extension and e^{-i pi k / 2n}
-  X_DCT3 = 11   // L = 2 n, e^{+i pi j / 2n} Hermitian input, inverse DFT
+  X_DCT3 = 11,  // L = 2 n, e^{+i pi j / 2n} Hermitian input, inverse DFT
+  X_DHT = 12    // discrete Hartley transform, L = n: H_k = Re X_k - Im X_k of the
+                // DFT X; real to real and its own inverse up to n (periodic axes
+                // of mixed-boundary plans)
 };
 
 enum PassKind : int { PK_ONEWAY = 0, PK_SANDWICH = 1 };
@@ -77,7 +80,8 @@ struct PassArgs {
   // boundary terms added while loading the first pass (FD2 inhomogeneous)
   const void* face[3][2];
   long long face_s[3][2];  // strides of the two remaining axes (ascending)
-  int face_off;            // 1 when faces include boundary nodes (REGULAR Dirichlet)
+  int face_off;            // bit b: face arrays include the boundary nodes of axis b
+                           // (REGULAR Dirichlet axes)
   double face_w[3][2];     // weight applied to g
   int nunk[3];             // unknown counts per logical axis
   int lds_bytes;
@@ -175,9 +179,10 @@ hipError_t launch_green_eval(double* g, const int M[3], const double h[3], const
 // octant, scaled, as T, stored [M2/2+1][M1/2+1][M0/2+1] (axis 0 contiguous).
 hipError_t launch_octant(const double* spec, const int M[3], double scale, void* out,
                          int prec, hipStream_t s);
-// Write the boundary nodes of a REGULAR Dirichlet output [N0][N1][N2] from
-// face arrays (node with several faces: highest axis wins).
-hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, const void* face[3][2],
+// Write the boundary nodes of the REGULAR Dirichlet axes (bit a of `axes`)
+// of an output [N0][N1][N2] from face arrays (node with several faces:
+// highest axis wins).
+hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, int axes, const void* face[3][2],
                                  int prec, hipStream_t s);
 // Consecutive tiles of one pass of the batched persistent solve.  `dep` is the global
 // index of the pass that must be complete first (-1: none) and `need` its tile

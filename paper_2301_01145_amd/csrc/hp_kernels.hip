@@ -153,11 +153,11 @@ __device__ __forceinline__ bool xform_inverse_fft(int x) {
 }
 __device__ __forceinline__ bool xform_real_in(int x) {
   return x == X_R2C || x == X_PAIR_F || x == X_DST1 || x == X_DST2 || x == X_DST3 ||
-         x == X_DCT1 || x == X_DCT2 || x == X_DCT3;
+         x == X_DCT1 || x == X_DCT2 || x == X_DCT3 || x == X_DHT;
 }
 __device__ __forceinline__ bool xform_real_out(int x) {
   return x == X_C2R || x == X_PAIR_B || x == X_DST1 || x == X_DST2 || x == X_DST3 ||
-         x == X_DCT1 || x == X_DCT2 || x == X_DCT3;
+         x == X_DCT1 || x == X_DCT2 || x == X_DCT3 || x == X_DHT;
 }
 
 // ----------------------------------------------------------- tile addressing
@@ -259,6 +259,7 @@ __device__ void build_from_real_x(C2<T>* Z, const T* R, const PassArgs& a, int n
     switch (x) {
       case X_R2C:
       case X_PAIR_F:
+      case X_DHT:
         if (m < cnt) z = {ra[m], rb[m]};
         break;
       case X_DST1:  // [0, x_0..x_{n-1}, 0, -x_{n-1}..-x_0]
@@ -303,6 +304,7 @@ __device__ void build_from_real(C2<T>* Z, const T* R, int x, const PassArgs& a, 
     case X_DCT1: build_from_real_x<T, X_DCT1>(Z, R, a, nfft); break;
     case X_DCT2: build_from_real_x<T, X_DCT2>(Z, R, a, nfft); break;
     case X_DCT3: build_from_real_x<T, X_DCT3>(Z, R, a, nfft); break;
+    case X_DHT: build_from_real_x<T, X_DHT>(Z, R, a, nfft); break;
     default: build_from_real_x<T, -1>(Z, R, a, nfft); break;
   }
 }
@@ -362,6 +364,12 @@ __device__ __forceinline__ T real_out(const C2<T>* Z, int x, const PassArgs& a, 
       C2<T> v = cmul(z[kk], ((const C2<T>*)a.qtw)[kk]);
       return second ? v.im : v.re;
     }
+    case X_DHT: {
+      // Z = X_a + i X_b with X_a, X_b Hermitian; H = Re X - Im X per pencil
+      const C2<T> u = z[k], w = z[k == 0 ? 0 : a.L - k];
+      return second ? (T)0.5 * ((u.im + w.im) + (u.re - w.re))
+                    : (T)0.5 * ((u.re + w.re) - (u.im - w.im));
+    }
     default:
       return (T)0;
   }
@@ -416,6 +424,7 @@ __device__ void store_out(const C2<T>* Z, int x, void* dst, const PassArgs& a, c
     case X_DCT1: store_out_x<T, X_DCT1>(Z, dst, a, t); break;
     case X_DCT2: store_out_x<T, X_DCT2>(Z, dst, a, t); break;
     case X_DCT3: store_out_x<T, X_DCT3>(Z, dst, a, t); break;
+    case X_DHT: store_out_x<T, X_DHT>(Z, dst, a, t); break;
     default: store_out_x<T, -1>(Z, dst, a, t); break;
   }
 }
@@ -1156,7 +1165,7 @@ struct FacePtrs {
 };
 
 template <typename T>
-__global__ void k_dirichlet_fill(T* out, int N0, int N1, int N2, int ndim, FacePtrs fp) {
+__global__ void k_dirichlet_fill(T* out, int N0, int N1, int N2, int ndim, int axes, FacePtrs fp) {
   const int N[3] = {N0, N1, N2};
   const long long total = (long long)N0 * N1 * N2;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -1167,6 +1176,7 @@ __global__ void k_dirichlet_fill(T* out, int N0, int N1, int N2, int ndim, FaceP
     c[0] = (int)(i / ((long long)N1 * N2));
     int axis = -1, side = 0;
     for (int a = 0; a < ndim; ++a) {
+      if (!((axes >> a) & 1)) continue;  // axis without boundary nodes
       if (c[a] == 0) { axis = a; side = 0; }
       else if (c[a] == N[a] - 1) { axis = a; side = 1; }
     }
@@ -1185,17 +1195,17 @@ __global__ void k_dirichlet_fill(T* out, int N0, int N1, int N2, int ndim, FaceP
   }
 }
 
-hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, const void* face[3][2],
+hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, int axes, const void* face[3][2],
                                  int prec, hipStream_t s) {
   FacePtrs fp;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 2; ++b) fp.f[a][b] = face[a][b];
   if (prec == 0)
     hipLaunchKernelGGL(k_dirichlet_fill<float>, dim3(1024), dim3(256), 0, s, (float*)out, N[0],
-                       N[1], N[2], ndim, fp);
+                       N[1], N[2], ndim, axes, fp);
   else
     hipLaunchKernelGGL(k_dirichlet_fill<double>, dim3(1024), dim3(256), 0, s, (double*)out, N[0],
-                       N[1], N[2], ndim, fp);
+                       N[1], N[2], ndim, axes, fp);
   return hipGetLastError();
 }
 

@@ -60,6 +60,15 @@ BAD = [
      _lib.HP_E_UNSUPPORTED),
     (dict(bc="neumann", grid="regular", nc=[1], diff="grad"), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[7, 8]), None),  # prime length: a direct radix-7 stage
+    # a condition per axis (HP_MIXED)
+    (dict(bc=["periodic", "dirichlet"], grid="staggered", nc=[8, 8]), None),
+    (dict(bc=["periodic", "unbounded"], grid="staggered", nc=[8, 8]), _lib.HP_E_ARG),
+    (dict(bc=["periodic", "neumann"], grid="staggered", nc=[8, 8], diff="grad"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc=["dirichlet", "neumann"], grid="staggered", nc=[8, 8], kernel="ps", inhomogeneous=True),
+     _lib.HP_E_UNSUPPORTED),
+    (dict(bc=["periodic", "periodic"], grid="staggered", nc=[8, 8], kernel="fd2", inhomogeneous=True),
+     _lib.HP_E_ARG),  # no face takes boundary values
+    (dict(bc=["neumann", "periodic"], grid="regular", nc=[8, 8], kernel="g2"), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[8193], prec="f32"), _lib.HP_E_UNSUPPORTED),  # longer than a tile
     (dict(bc="periodic", grid="staggered", nc=[4097], prec="f64"), _lib.HP_E_UNSUPPORTED),
     (dict(bc="periodic", grid="staggered", nc=[0, 8]), _lib.HP_E_ARG),

@@ -1,0 +1,162 @@
+"""Mixed-boundary plans (a periodic, Dirichlet or Neumann condition per axis)
+on the GPU against the oracle, element by element.
+
+* every ordered pair of distinct conditions in 2D and four triples in 3D, both
+  grids, PS and FD2, homogeneous and inhomogeneous (FD2), FP32 and FP64;
+* lengths with prime factors (periodic axes run the Hartley transform on the
+  general kernels at any length);
+* Dirichlet / Neumann mixes at power-of-two transform lengths run the bounded
+  wavefront kernels, also checked against the general ones;
+* the zero mode of periodic / Neumann mixes; a 3-component field;
+* descriptor rules (derivatives refused, faces of periodic axes).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+LO = [0.0, -0.5, 1.0]
+HI = [1.0, 1.3, 2.5]
+PAIRS = [["periodic", "dirichlet"], ["dirichlet", "periodic"], ["periodic", "neumann"],
+         ["neumann", "periodic"], ["dirichlet", "neumann"], ["neumann", "dirichlet"]]
+TRIPLES = [["periodic", "dirichlet", "neumann"], ["neumann", "periodic", "dirichlet"],
+           ["dirichlet", "neumann", "periodic"], ["periodic", "neumann", "neumann"]]
+
+
+def mixed_input(bcs, gtype, nc, ncomp, inhom, prec, seed):
+    from oracle import grid as og
+    rng = np.random.default_rng(seed)
+    nd = len(nc)
+    shape = tuple(og.unknowns(bcs[a], gtype, nc[a]) for a in range(nd))
+    f = rng.normal(size=((ncomp,) + shape) if ncomp == 3 else shape)
+    faces = None
+    if inhom:
+        faces = {}
+        for a in range(nd):
+            if bcs[a] == "periodic":
+                continue
+            shp = tuple(og.output_points(bcs[b], gtype, nc[b]) for b in range(nd) if b != a)
+            for s in (0, 1):
+                faces[(a, s)] = rng.normal(size=shp)
+    rnd = np.float32 if prec == "f32" else np.float64
+    f = f.astype(rnd).astype(np.float64)
+    if faces:
+        faces = {k: v.astype(rnd).astype(np.float64) for k, v in faces.items()}
+    return f, faces
+
+
+def gpu_mixed(bcs, gtype, nc, f, kernel, prec, ncomp, faces):
+    import torch
+    from paper_2301_01145_amd import Solver
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    nd = len(nc)
+    s = Solver(list(bcs), gtype, nc, LO[:nd], HI[:nd], kernel=kernel, dtype=dtype, ncomp=ncomp,
+               inhomogeneous=faces is not None)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+    fin = [dev(f[c]) for c in range(3)] if ncomp == 3 else dev(f)
+    fd = {k: dev(v) for k, v in faces.items()} if faces else None
+    psi, _ = s.solve(fin, fd)
+    torch.cuda.synchronize()
+    out = np.stack([p.double().cpu().numpy() for p in psi]) if ncomp == 3 else psi[0].double().cpu().numpy()
+    zm = s.zero_mode()
+    npass = s.passes()
+    s.close()
+    return out, zm, npass
+
+
+def check(got, ref, prec, what):
+    l2, mx = TOL[prec]
+    e2, em = rel_l2(got, ref), rel_max(got, ref)
+    assert e2 <= l2 and em <= mx, f"{what}: rel-L2 {e2:.3e} rel-max {em:.3e}"
+
+
+def run_case(bcs, gtype, nc, kernel, inhom, prec, seed, ncomp=1):
+    import oracle
+    nd = len(nc)
+    print(f"mixed {bcs} {gtype} {nc} {kernel} inhom={inhom} {prec} ncomp={ncomp}", flush=True)
+    f, faces = mixed_input(bcs, gtype, nc, ncomp, inhom, prec, seed)
+    got, zm, npass = gpu_mixed(bcs, gtype, nc, f, kernel, prec, ncomp, faces)
+    ref, _ = oracle.solve(list(bcs), gtype, nc, LO[:nd], HI[:nd], f, operator=kernel,
+                          faces=([faces] * 3 if (faces and ncomp == 3) else faces))
+    assert got.shape == ref.shape
+    check(got, ref, prec, "psi")
+    if ncomp == 1:
+        zr = oracle.zero_mode(list(bcs), gtype, nc, LO[:nd], HI[:nd], f, faces)
+        assert abs(zm - zr) <= (1e-10 if prec == "f64" else 1e-4) * max(1.0, float(np.max(np.abs(f)))), (zm, zr)
+    return got, npass
+
+
+CASES = []
+for bcs in PAIRS:
+    for gtype in ("regular", "staggered"):
+        for kernel, inhom in (("ps", False), ("fd2", False), ("fd2", True)):
+            for prec in ("f64", "f32"):
+                CASES.append((bcs, gtype, [12, 10], kernel, inhom, prec))
+for bcs in TRIPLES:
+    for gtype in ("regular", "staggered"):
+        for kernel, inhom in (("ps", False), ("fd2", True)):
+            for prec in ("f64", "f32"):
+                CASES.append((bcs, gtype, [12, 10, 9], kernel, inhom, prec))
+
+
+@pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,prec", CASES)
+def test_mixed_matches_oracle(bcs, gtype, nc, kernel, inhom, prec):
+    run_case(bcs, gtype, nc, kernel, inhom, prec, seed=101 + len(nc))
+
+
+@pytest.mark.parametrize("bcs,nc", [(["periodic", "dirichlet"], [7, 13]), (["neumann", "periodic"], [11, 127]),
+                                    (["periodic", "neumann", "dirichlet"], [13, 7, 11])])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mixed_prime_lengths(bcs, nc, prec):
+    run_case(bcs, "staggered", nc, "fd2", True, prec, seed=103)
+
+
+@pytest.mark.parametrize("bcs", [["dirichlet", "neumann", "dirichlet"], ["neumann", "dirichlet", "neumann"]])
+@pytest.mark.parametrize("gtype", ["regular", "staggered"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mixed_wavefront_matches_general(bcs, gtype, prec, monkeypatch):
+    # transform lengths 64 / 128 on every axis: the bounded wavefront kernels
+    if gtype == "staggered":
+        nc = [32, 64, 32]
+    else:  # DST-I 2 N_c, DCT-I 2 N_c
+        nc = [32, 64, 32]
+    fast, npass = run_case(bcs, gtype, nc, "fd2", True, prec, seed=107)
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen, _ = run_case(bcs, gtype, nc, "fd2", True, prec, seed=107)
+    check(fast, gen, prec, "wavefront vs general")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mixed_vector(prec):
+    run_case(["periodic", "dirichlet", "neumann"], "staggered", [16, 12, 10], "ps", False, prec, seed=109,
+             ncomp=3)
+
+
+def test_mixed_constant_source_zero_mode():
+    import torch
+    from paper_2301_01145_amd import Solver
+    s = Solver(["periodic", "neumann"], "regular", [12, 10], LO[:2], HI[:2], kernel="fd2", dtype=torch.float64)
+    f = torch.full(s.in_shape, 2.5, dtype=torch.float64, device="cuda")
+    psi, _ = s.solve(f)
+    torch.cuda.synchronize()
+    assert abs(s.zero_mode() - 2.5) <= 1e-12
+    assert float(psi[0].abs().max()) <= 1e-12
+    s.close()
+
+
+def test_mixed_descriptor_rules():
+    import ctypes
+    import torch
+    from paper_2301_01145_amd import HipoissonError, Solver, _lib, make_desc
+    d = make_desc(["periodic", "dirichlet"], "staggered", [8, 8], diff="grad")
+    out = ctypes.c_void_p()
+    assert _lib.lib().hp_plan_create(ctypes.byref(d), None, ctypes.byref(out)) == _lib.HP_E_UNSUPPORTED
+    s = Solver(["periodic", "dirichlet"], "staggered", [8, 8], kernel="fd2", dtype=torch.float64,
+               inhomogeneous=True)
+    g = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(HipoissonError):
+        _lib.hp_set_boundary(s.plan, 0, 0, 0, 0, g.data_ptr(), 1)  # axis 0 is periodic
+    _lib.hp_set_boundary(s.plan, 0, 1, 0, 0, g.data_ptr(), 1)     # axis 1 is Dirichlet
+    s.close()

@@ -29,7 +29,8 @@ def zero_mode(bc, grid_type, nc, lo, hi, f, faces=None):
     Zero for Dirichlet and free-space problems, and for compatible sources."""
     nd = len(nc)
     if isinstance(bc, (list, tuple)):
-        # a condition per axis: a zero eigenvalue sum only without Dirichlet axes
+        # a condition per axis: a zero eigenvalue sum only without Dirichlet
+        # (or free) axes
         if any(b not in ("periodic", "neumann") for b in bc):
             return 0.0
         hs = [grid.spacing(lo[a], hi[a], nc[a]) for a in range(nd)]
@@ -65,8 +66,9 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
           faces=None, sigma_cells=2.0):
     """One solve described like the library's plan descriptor.
 
-    bc: "periodic" | "dirichlet" | "neumann" | "unbounded", or one of the first
-        three per axis (a list) for a mixed-boundary solve
+    bc: "periodic" | "dirichlet" | "neumann" | "unbounded", or one condition
+        per axis (a list) for a mixed-boundary solve, at most one of them
+        "unbounded" (a semi-unbounded solve, bounded.solve_semi)
     grid_type: "regular" | "staggered"
     nc, lo, hi: per-axis cell count and domain bounds (length = ndim)
     f: source on the unknown points (scalar), or (3, ...) for a 3D vector
@@ -91,8 +93,9 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
             raise NotImplementedError("mixed-boundary solves: psi only")
         vector = f.ndim == nd + 1
         comps = [f[c] for c in range(f.shape[0])] if vector else [f]
-        psi = [bounded.solve_mixed(c, list(bc), grid_type, operator, lengths, hs,
-                                   (faces[i] if (faces and vector) else faces))
+        solver = bounded.solve_semi if "unbounded" in bc else bounded.solve_mixed
+        psi = [solver(c, list(bc), grid_type, operator, lengths, hs,
+                      (faces[i] if (faces and vector) else faces))
                for i, c in enumerate(comps)]
         return (np.stack(psi) if vector else psi[0]), []
     if bc == "unbounded":

@@ -369,3 +369,71 @@ def solve_mixed(f, bcs, grid, operator, lengths, hs, faces=None):
             _, bwd, norm = TRANSFORM_PAIRS[(bcs[a], grid)]
             psi = _apply_real_pair(bwd, psi, a) / norm(f.shape[a])
     return mixed_output(psi.real, bcs, grid, faces or {})
+
+
+# ------------------------------------------------------- semi-unbounded axes
+# Section 2.6: transforming the bounded directions splits the Laplacian, and
+# what remains along the free directions is a Helmholtz equation per mode.
+# With one free axis u and bounded-mode eigenvalue sum Lambda <= 0, the mode
+# solves psi'' - kappa^2 psi = f along u, kappa^2 = -Lambda, whose free-space
+# Green's function is G(x) = -exp(-kappa |x|) / (2 kappa) (|x| / 2 for
+# kappa = 0).  The oracle convolves with it by the Hockney-Eastwood doubling of
+# Section 2.5 along u: M = 2 n points, G sampled at min(m, M - m) H_u, times
+# the cell length H_u.
+
+def helmholtz_kernel_1d(kappa, x):
+    """Free-space Green's function of d^2/dx^2 - kappa^2 in 1D."""
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    kappa = np.asarray(kappa, dtype=np.float64)
+    safe = np.where(kappa > 0.0, kappa, 1.0)
+    return np.where(kappa > 0.0, -np.exp(-safe * x) / (2.0 * safe), 0.5 * x)
+
+
+def solve_semi(f, bcs, grid, operator, lengths, hs, faces=None):
+    """solve_mixed with one axis "unbounded": that axis is convolved with the
+    1D Helmholtz Green's function of each bounded mode (doubled to M = 2 n)."""
+    f = np.asarray(f, dtype=np.float64)
+    nd = f.ndim
+    u = bcs.index("unbounded")
+    if faces:
+        if operator != "fd2":
+            raise ValueError("inhomogeneous boundary values need the FD2 operator")
+        if any(a == u for (a, _) in faces):
+            raise ValueError("a free axis has no faces")
+        f = apply_boundary_values_mixed(f, bcs, grid, hs, faces)
+    lam = np.zeros([1 if a == u else f.shape[a] for a in range(nd)])
+    for a in range(nd):
+        if a == u:
+            continue
+        view = [1] * nd
+        view[a] = f.shape[a]
+        lam = lam + eigenvalues(bcs[a], grid, operator, f.shape[a], lengths[a], hs[a]).reshape(view)
+    fhat = f.astype(np.complex128)
+    for a in range(nd):
+        if a == u:
+            continue
+        if bcs[a] == "periodic":
+            fhat = np.fft.fft(fhat, axis=a)
+        else:
+            fhat = _apply_real_pair(TRANSFORM_PAIRS[(bcs[a], grid)][0], fhat, a)
+    n = f.shape[u]
+    M = 2 * n
+    m = np.arange(M)
+    dist = np.minimum(m, M - m) * hs[u]
+    kappa = np.sqrt(np.maximum(-lam, 0.0))
+    gshape = [1] * nd
+    gshape[u] = M
+    g_ext = helmholtz_kernel_1d(kappa, dist.reshape(gshape))  # broadcast over the bounded modes
+    pad = [(0, 0)] * nd
+    pad[u] = (0, M - n)
+    conv = np.fft.ifft(np.fft.fft(np.pad(fhat, pad), axis=u) * np.fft.fft(g_ext, axis=u), axis=u)
+    psi = np.take(conv, np.arange(n), axis=u) * hs[u]
+    for a in reversed(range(nd)):
+        if a == u:
+            continue
+        if bcs[a] == "periodic":
+            psi = np.fft.ifft(psi, axis=a)
+        else:
+            _, bwd, norm = TRANSFORM_PAIRS[(bcs[a], grid)]
+            psi = _apply_real_pair(bwd, psi, a) / norm(f.shape[a])
+    return mixed_output(psi.real, bcs, grid, faces or {})

@@ -287,3 +287,19 @@ def test_mixed_boundary_node_side_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "mixed_output", wrong)
     _fails(pm.test_mixed_fd2_matches_dense_solve, ["dirichlet", "neumann", "periodic"], "regular", True)
+
+
+def test_semi_kernel_sign_is_caught(monkeypatch):
+    # the 1D Helmholtz Green's function with the wrong sign
+    import test_oracle_semi as ps
+    orig = bounded.helmholtz_kernel_1d
+    monkeypatch.setattr(bounded, "helmholtz_kernel_1d", lambda kappa, x: -orig(kappa, x))
+    _fails(ps.test_semi_fd2_matches_dense_matrix_function, ["unbounded", "periodic"], "staggered")
+
+
+def test_semi_kernel_decay_is_caught(monkeypatch):
+    # exp(-kappa |x| / 2): a decay rate off by a factor of two
+    import test_oracle_semi as ps
+    orig = bounded.helmholtz_kernel_1d
+    monkeypatch.setattr(bounded, "helmholtz_kernel_1d", lambda kappa, x: orig(np.asarray(kappa) / 2.0, x) / 2.0)
+    _fails(ps.test_semi_fd2_matches_dense_matrix_function, ["dirichlet", "unbounded"], "regular")

@@ -70,7 +70,13 @@ typedef enum {
  * to n, diagonal for the periodic Laplacian) beside the Table 1 sine and
  * cosine transforms, with the eigenvalue sum of eq. (pois_spec) over the
  * axes.  PS or FD2; boundary values (FD2) on the Dirichlet / Neumann faces;
- * no derivative outputs (HP_E_UNSUPPORTED). */
+ * no derivative outputs (HP_E_UNSUPPORTED).
+ * Semi-unbounded: one axis (of 2 or 3) may be HP_UNBOUNDED.  Each bounded
+ * mode, eigenvalue sum Lambda, then solves psi'' - kappa^2 psi = f along the
+ * free axis (kappa^2 = -Lambda, Section 2.6's Helmholtz split), convolved by
+ * the Hockney-Eastwood doubling (M = 2 n, Section 2.5) with the exact 1D
+ * Green's function -exp(-kappa |x|) / (2 kappa) (|x| / 2 for kappa = 0) times
+ * the cell length.  The free axis has no faces. */
 typedef enum { HP_PERIODIC = 0, HP_DIRICHLET = 1, HP_NEUMANN = 2, HP_UNBOUNDED = 3,
                HP_MIXED = 4 } hp_bc;
 typedef enum { HP_REGULAR = 0, HP_STAGGERED = 1 } hp_grid;
@@ -125,7 +131,8 @@ typedef struct {
   int inhomogeneous;    /* 1: boundary values from hp_set_boundary (FD2 only) */
   double reg_sigma_cells; /* G2 width sigma in units of max_a H_a; 0 -> 2.0 */
   int bc_axis[3];       /* bc == HP_MIXED: hp_bc of each axis (HP_PERIODIC,
-                           HP_DIRICHLET or HP_NEUMANN); ignored otherwise */
+                           HP_DIRICHLET, HP_NEUMANN, or HP_UNBOUNDED on at
+                           most one axis); ignored otherwise */
 } hp_desc;
 
 /* Query keys for hp_query. */
@@ -187,7 +194,8 @@ HP_API hp_status hp_set_input(hp_plan plan, int problem, int comp, const void* f
  * inhomogeneous FD2 Dirichlet / Neumann plans (Section 2.4.2): an array with
  * the output shape of the other axes (ascending axis order).  Dirichlet: psi
  * on the face; Neumann: d(psi)/dx_axis on the face.  NULL = homogeneous.  A
- * periodic axis of an HP_MIXED plan has no faces (HP_E_ARG unless g is NULL). */
+ * periodic or free axis of an HP_MIXED plan has no faces (HP_E_ARG unless g
+ * is NULL). */
 HP_API hp_status hp_set_boundary(hp_plan plan, int problem, int axis, int side, int comp,
                           const void* g, int on_device);
 

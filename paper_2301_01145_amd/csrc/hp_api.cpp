@@ -166,9 +166,14 @@ hp_status validate(const hp_desc* d) {
   if (d->ncomp == 3 && d->ndim != 3) return fail(nullptr, HP_E_ARG, "vector fields need ndim 3");
   if (d->bc < 0 || d->bc > 4) return fail(nullptr, HP_E_ARG, "bad bc");
   if (d->bc == HP_MIXED) {
-    for (int a = 0; a < d->ndim; ++a)
+    int nfree = 0;
+    for (int a = 0; a < d->ndim; ++a) {
+      if (d->bc_axis[a] == HP_UNBOUNDED) { ++nfree; continue; }
       if (d->bc_axis[a] != HP_PERIODIC && d->bc_axis[a] != HP_DIRICHLET && d->bc_axis[a] != HP_NEUMANN)
-        return fail(nullptr, HP_E_ARG, "mixed plans take a periodic, Dirichlet or Neumann axis each");
+        return fail(nullptr, HP_E_ARG, "mixed plans take a periodic, Dirichlet, Neumann or free axis each");
+    }
+    if (nfree == d->ndim) return fail(nullptr, HP_E_ARG, "a plan that is free on every axis is HP_UNBOUNDED");
+    if (nfree > 1) return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded plans take one free axis");
     if (d->diff != HP_D_NONE)
       return fail(nullptr, HP_E_UNSUPPORTED, "mixed-boundary plans take no derivative outputs");
   }
@@ -222,7 +227,7 @@ hp_status validate(const hp_desc* d) {
     int L = n, xf, xb, rad[kMaxStages], ns;
     double c;
     if (r2r_plan(*d)) r2r_ops(axis_bc(*d, a), d->grid, n, &xf, &xb, &L, &c);
-    if (unb) L = 2 * n;
+    if (unb || axis_bc(*d, a) == HP_UNBOUNDED) L = 2 * n;
     if (!factorize(L, rad, &ns))
       return fail(nullptr, HP_E_UNSUPPORTED,
                   "transform length " + std::to_string(L) + " needs too many radix stages");
@@ -585,12 +590,34 @@ hp_status setup_problem(hp_plan p, Problem& P) {
   if (r2r_plan(d)) {
     P.norm = 1.0;
     for (int a = 0; a < P.nd; ++a) {
+      if (axis_bc(d, a) == HP_UNBOUNDED) {
+        P.free_axis = a;
+        P.M[a] = 2 * P.n[a];
+        continue;
+      }
       int xf, xb, L;
       double c;
       r2r_ops(axis_bc(d, a), d.grid, P.n[a], &xf, &xb, &L, &c);
       P.norm /= c;
       HP_TRY(upload(p, eigen(axis_bc(d, a), d.grid, d.kernel, P.n[a], P.len[a], P.h[a]), false,
                     (void**)&P.lam[a]));
+    }
+    if (P.free_axis >= 0) {
+      // rows of the free axis's Helmholtz Green's spectrum per bounded mode,
+      // scaled by the bounded inverse normalisation, 1 / M of the free axis's
+      // inverse FFT and its cell length; logical-axis strides g_s
+      const int u = P.free_axis, M = P.M[u], K = M / 2 + 1;
+      int b[2] = {-1, -1}, nb = 0;
+      for (int a = 0; a < P.nd; ++a)
+        if (a != u) b[nb++] = a;
+      const int n1 = P.n[b[0]], n2 = nb > 1 ? P.n[b[1]] : 1;
+      for (int a = 0; a < 3; ++a) P.g_s[a] = 0;
+      P.g_s[u] = 1;
+      P.g_s[b[0]] = K;
+      if (nb > 1) P.g_s[b[1]] = (long long)K * n1;
+      HP_TRY(dev_alloc(p, (size_t)K * n1 * n2 * es, &P.green));
+      HP_HIP(p, launch_semi_green(P.green, P.lam[b[0]], n1, nb > 1 ? P.lam[b[1]] : nullptr, n2, M,
+                                  P.h[u], P.norm * P.h[u] / (double)M, p->prec, p->stream));
     }
     if (P.nder) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.grad_s));
     // second terms of DIV (d_y psi_y, d_z psi_z) and of the 3D curl, added
@@ -731,7 +758,7 @@ void fill_face_terms(const Problem& P, int comp, PassArgs& a) {
     const double h = P.h[ax];
     const int bc = axis_bc(d, ax);
     for (int side = 0; side < 2; ++side) {
-      a.face[ax][side] = bc == HP_PERIODIC ? nullptr : P.face[ax][side][comp];
+      a.face[ax][side] = (bc == HP_PERIODIC || bc == HP_UNBOUNDED) ? nullptr : P.face[ax][side][comp];
       double w;
       if (bc == HP_DIRICHLET) w = (d.grid == HP_REGULAR ? -1.0 : -2.0) / (h * h);
       else if (d.grid == HP_REGULAR) w = (side == 0 ? 2.0 : -2.0) / h;
@@ -1776,6 +1803,117 @@ hp_status passes_unbounded_low(hp_plan p, Problem& P, bool adjoint, std::vector<
   return HP_OK;
 }
 
+// Semi-unbounded plans (Section 2.6): one free axis u beside periodic,
+// Dirichlet and Neumann axes.  Forward transforms along the bounded axes (the
+// contiguous one first, boundary terms added on the first load), then the free
+// axis as a doubled paired-real sandwich whose multiplier is the row of the
+// Helmholtz Green's spectrum of each pencil's bounded mode (M_GREEN_ROWS),
+// then the backward transforms.  In place in the output array, as on the
+// Dirichlet / Neumann path; one pass list per component.
+hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
+  const hp_desc& d = P.d;
+  const int nd = P.nd, u = P.free_axis;
+  int xf[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, L[3] = {1, 1, 1};
+  double c[3] = {1, 1, 1};
+  for (int a = 0; a < nd; ++a) {
+    if (a == u) L[a] = P.M[u];
+    else r2r_ops(axis_bc(d, a), d.grid, P.n[a], &xf[a], &xb[a], &L[a], &c[a]);
+  }
+  // strides of the input array and of the work view (the output array, its
+  // interior along REGULAR Dirichlet axes), logical axis a -> storage dim 3 - nd + a
+  int sod[3] = {1, 1, 1}, sid[3] = {1, 1, 1};
+  for (int a = 0; a < nd; ++a) { sod[3 - nd + a] = P.nout[a]; sid[3 - nd + a] = P.n[a]; }
+  long long os3[3], is3[3];
+  strides_of(sod, os3);
+  strides_of(sid, is3);
+  long long ws[3] = {0, 0, 0}, fs[3] = {0, 0, 0};
+  for (int a = 0; a < nd; ++a) { ws[a] = os3[3 - nd + a]; fs[a] = is3[3 - nd + a]; }
+  const int dmask = dreg_axes(d);
+  long long woff = 0;
+  for (int a = 0; a < nd; ++a)
+    if ((dmask >> a) & 1) woff += ws[a];
+  const size_t es = p->es;
+  auto work = [&](int comp) { return (void*)((char*)P.out[comp] + woff * es); };
+  auto base = [&]() {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.No = 1;
+    a.Np = 1;
+    a.n_in = a.n_out = 1;
+    for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? P.n[b] : 0;
+    return a;
+  };
+  // pencils along axis j: the tile runs along the last of the other axes
+  // (contiguous unless j is the last axis, whose pencils are contiguous)
+  auto geom = [&](PassArgs& a, int j, bool from_input) {
+    const long long* is = from_input ? fs : ws;
+    int others[2], no = 0;
+    for (int b = 0; b < nd; ++b)
+      if (b != j) others[no++] = b;
+    a.ax_j = j;
+    a.in_sj = is[j];
+    a.out_sj = ws[j];
+    const int pa = others[no - 1];
+    a.ax_p = pa;
+    a.Np = P.n[pa];
+    a.in_sp = is[pa];
+    a.out_sp = ws[pa];
+    if (no == 2) {
+      const int oa = others[0];
+      a.ax_o = oa;
+      a.No = P.n[oa];
+      a.in_so = is[oa];
+      a.out_so = ws[oa];
+    }
+    a.in_jfast = a.out_jfast = j == nd - 1 ? 1 : 0;
+  };
+  auto oneway = [&](int comp, int j, int x, bool first) -> hp_status {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = x;
+    a.L = L[j]; a.n = P.n[j]; a.nin = a.nout = P.n[j];
+    a.in[0] = first ? P.in[comp] : work(comp);
+    a.out[0] = work(comp);
+    geom(a, j, first);
+    if (first) fill_face_terms(P, comp, a);
+    HP_TRY(finish_pass(p, a, j == nd - 1 ? 16 : 32, 2, 0, 1));
+    const void* q;
+    HP_TRY(quarter(p, a.n, &q));
+    a.qtw = q;
+    out.push_back({a, 1});
+    return HP_OK;
+  };
+  for (int comp = 0; comp < P.ncomp; ++comp) {
+    bool first = true;
+    for (int j = nd - 1; j >= 0; --j) {
+      if (j == u) continue;
+      HP_TRY(oneway(comp, j, xf[j], first));
+      first = false;
+    }
+    {
+      PassArgs a = base();
+      a.kind = PK_SANDWICH;
+      a.xf = X_PAIR_F;
+      a.xb = X_PAIR_B;
+      a.L = L[u]; a.n = P.n[u]; a.nin = a.nout = P.n[u];
+      a.in[0] = work(comp);
+      a.out[0] = work(comp);
+      geom(a, u, false);
+      a.mult = M_GREEN_ROWS;
+      a.green = P.green;
+      for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+      a.diff = D_NONE;
+      HP_TRY(finish_pass(p, a, 16, 2, 0, 5));
+      out.push_back({a, 1});
+    }
+    for (int j = 0; j < nd; ++j) {
+      if (j == u) continue;
+      HP_TRY(oneway(comp, j, xb[j], false));
+    }
+  }
+  return HP_OK;
+}
+
 hp_status build_passes(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>& out) {
   if (P.d.bc == HP_UNBOUNDED) {
     if (P.nd < 3) return passes_unbounded_low(p, P, adjoint, out);
@@ -1785,6 +1923,7 @@ hp_status build_passes(hp_plan p, Problem& P, bool adjoint, std::vector<PassRec>
   if (adjoint) return fail(p, HP_E_UNSUPPORTED, "adjoint solve is provided for unbounded plans");
   if (P.d.bc == HP_PERIODIC && P.fast_periodic) return passes_unbounded_fast(p, P, false, out);
   if (P.d.bc == HP_PERIODIC) return passes_periodic(p, P, out);
+  if (P.free_axis >= 0) return passes_semi(p, P, out);
   return passes_bounded(p, P, out);
 }
 
@@ -2056,7 +2195,8 @@ hp_status hp_set_boundary(hp_plan plan, int problem, int axis, int side, int com
     P->face[axis][side][comp] = nullptr;
     return HP_OK;
   }
-  if (axis_bc(P->d, axis) == HP_PERIODIC) return fail(plan, HP_E_ARG, "a periodic axis has no faces");
+  if (axis_bc(P->d, axis) == HP_PERIODIC || axis_bc(P->d, axis) == HP_UNBOUNDED)
+    return fail(plan, HP_E_ARG, "a periodic or free axis has no faces");
   size_t cnt = 1;
   for (int b = 0; b < P->nd; ++b)
     if (b != axis) cnt *= (size_t)P->nout[b];

@@ -28,7 +28,12 @@ enum Xform : int {
 };
 
 enum PassKind : int { PK_ONEWAY = 0, PK_SANDWICH = 1 };
-enum MultKind : int { M_NONE = 0, M_EIGEN = 1, M_GREEN = 2 };
+enum MultKind : int { M_NONE = 0, M_EIGEN = 1, M_GREEN = 2,
+                      // semi-unbounded free axis: one real-even row of the
+                      // Helmholtz Green's spectrum per bounded mode of the
+                      // pencil (green[m g_s[ax_j] + p g_s[ax_p] + o g_s[ax_o]],
+                      // m <= L / 2), paired real pencils
+                      M_GREEN_ROWS = 3 };
 // Derivative coupling inside the sandwich pass (D_ADJ_*: the transposes used
 // by the adjoint solve).
 enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_CURL = 4,
@@ -177,6 +182,12 @@ hipError_t launch_green_eval(double* g, const int M[3], const double h[3], const
                              double scale, hipStream_t s);
 // Keep the real part of an FP64 half spectrum [M0][M1][M2/2+1] (complex) on the
 // octant, scaled, as T, stored [M2/2+1][M1/2+1][M0/2+1] (axis 0 contiguous).
+// Rows of the free-axis Green's spectrum of a semi-unbounded plan: out[m + K
+// (i1 + n1 i2)], K = M / 2 + 1, is scale times the DFT bin m of the 1D
+// Helmholtz kernel sampled on the doubled axis (spacing h, M points, mirrored)
+// for kappa^2 = -(lam1[i1] + lam2[i2]) (lam2 may be null, n2 = 1).
+hipError_t launch_semi_green(void* out, const double* lam1, int n1, const double* lam2, int n2,
+                             int M, double h, double scale, int prec, hipStream_t s);
 hipError_t launch_octant(const double* spec, const int M[3], double scale, void* out,
                          int prec, hipStream_t s);
 // Write the boundary nodes of the REGULAR Dirichlet axes (bit a of `axes`)

@@ -608,14 +608,41 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
       __syncthreads();
     }
   }
-  // multiply by the spectral multiplier
-  for (int e = threadIdx.x; e < tileC; e += kThreads) {
-    const int f = e / L;
-    const int m = e - f * L;
-    int k[3];
-    spectral_index(a, m, t.p0 + f, t.o, k);
-    const T mu = multiplier<T>(a, k);
-    for (int c = 0; c < nS; ++c) S[(size_t)c * tileC + e] = cscale(S[(size_t)c * tileC + e], mu);
+  if (a.mult == M_GREEN_ROWS) {
+    // Paired real pencils 2f, 2f + 1 of the tile belong to different bounded
+    // modes, so they take different real-even Green's rows G_a, G_b.  The FFT
+    // Z of a + ib holds the Hermitian spectra X_a = (Z_m + conj Z_-m) / 2 and
+    // X_b = (Z_m - conj Z_-m) / 2i; G_a X_a + i G_b X_b recombines to
+    // Z'_m = A Z_m + B conj Z_-m with A = (G_a + G_b) / 2, B = (G_a - G_b) / 2,
+    // the same A, B at -m.  One thread per bin pair (m, L - m).
+    const int half = L / 2;
+    auto row = [&](int p, int m) -> T {
+      p = min(p, a.Np - 1);
+      long long off = (long long)m * a.g_s[a.ax_j] + (long long)p * a.g_s[a.ax_p];
+      if (a.ax_o >= 0) off += (long long)t.o * a.g_s[a.ax_o];
+      return ((const T*)a.green)[off];
+    };
+    for (int e = threadIdx.x; e < nfft * (half + 1); e += kThreads) {
+      const int f = e / (half + 1);
+      const int m = e - f * (half + 1);
+      const int mm = m == 0 ? 0 : L - m;
+      const T ga = row(t.p0 + 2 * f, m), gb = row(t.p0 + 2 * f + 1, m);
+      const T A = (T)0.5 * (ga + gb), B = (T)0.5 * (ga - gb);
+      C2<T>* z = S + (size_t)f * L;
+      const C2<T> zm = z[m], zmm = z[mm];
+      z[m] = cadd(cscale(zm, A), cscale(cconj(zmm), B));
+      if (mm != m) z[mm] = cadd(cscale(zmm, A), cscale(cconj(zm), B));
+    }
+  } else {
+    // multiply by the spectral multiplier
+    for (int e = threadIdx.x; e < tileC; e += kThreads) {
+      const int f = e / L;
+      const int m = e - f * L;
+      int k[3];
+      spectral_index(a, m, t.p0 + f, t.o, k);
+      const T mu = multiplier<T>(a, k);
+      for (int c = 0; c < nS; ++c) S[(size_t)c * tileC + e] = cscale(S[(size_t)c * tileC + e], mu);
+    }
   }
   __syncthreads();
   const int xb = pair ? X_PAIR_B : X_C2C_B;
@@ -1157,6 +1184,54 @@ hipError_t launch_octant(const double* spec, const int M[3], double scale, void*
   else
     hipLaunchKernelGGL(k_octant<double>, dim3(2048), dim3(256), 0, s, spec, M[0], M[1], K2, scale,
                        (double*)out);
+  return hipGetLastError();
+}
+
+// Green's spectrum rows of the free axis (see launch_semi_green).  The DFT of
+// the mirrored samples of G = -exp(-kappa x) / (2 kappa) sums two geometric
+// series in q = exp(-kappa h); with s = (-1)^m q^n (n = M / 2) and
+// theta = 2 pi m / M it is
+//   -(1 - s)(1 - q^2) / (2 kappa ((1 - q)^2 + 4 q sin^2(theta / 2))),
+// a sum of positive terms in the denominator (no cancellation).  kappa = 0
+// (G = |x| / 2): h n^2 / 2 at m = 0, else -h (1 - (-1)^m) / (4 sin^2(theta / 2)).
+template <typename T>
+__global__ void k_semi_green(T* out, const double* lam1, int n1, const double* lam2, int n2, int M,
+                             double h, double scale) {
+  const int K = M / 2 + 1, n = M / 2;
+  const long long total = (long long)K * n1 * n2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(i % K);
+    const long long r = i / K;
+    const int i1 = (int)(r % n1), i2 = (int)(r / n1);
+    const double lam = lam1[i1] + (lam2 ? lam2[i2] : 0.0);
+    const double sh = sinpi((double)m / (double)M);  // sin(theta / 2)
+    const double sgn = (m & 1) ? -1.0 : 1.0;
+    double v;
+    if (lam < 0.0) {
+      const double kappa = sqrt(-lam);
+      const double q = exp(-kappa * h);
+      const double omq = -expm1(-kappa * h);       // 1 - q
+      const double omq2 = -expm1(-2.0 * kappa * h);  // 1 - q^2
+      const double s = sgn * exp(-kappa * h * n);
+      v = -(1.0 - s) * omq2 / (2.0 * kappa * (omq * omq + 4.0 * q * sh * sh));
+    } else if (m == 0) {
+      v = 0.5 * h * (double)n * (double)n;
+    } else {
+      v = -h * (1.0 - sgn) / (4.0 * sh * sh);
+    }
+    out[i] = (T)(scale * v);
+  }
+}
+
+hipError_t launch_semi_green(void* out, const double* lam1, int n1, const double* lam2, int n2,
+                             int M, double h, double scale, int prec, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_semi_green<float>, dim3(1024), dim3(256), 0, s, (float*)out, lam1, n1, lam2,
+                       n2, M, h, scale);
+  else
+    hipLaunchKernelGGL(k_semi_green<double>, dim3(1024), dim3(256), 0, s, (double*)out, lam1, n1,
+                       lam2, n2, M, h, scale);
   return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct Problem {
   double norm = 1.0;
   std::vector<std::pair<int, int>> slabs;  // kz (first, count) of the free-space y / x passes
   bool fast_periodic = false;  // periodic plan on the wavefront passes (M = n)
+  int free_axis = -1;          // semi-unbounded plan: the free axis (M[free_axis] = 2 n)
 };
 
 }  // namespace hp

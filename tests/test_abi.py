@@ -62,7 +62,9 @@ BAD = [
     (dict(bc="periodic", grid="staggered", nc=[7, 8]), None),  # prime length: a direct radix-7 stage
     # a condition per axis (HP_MIXED)
     (dict(bc=["periodic", "dirichlet"], grid="staggered", nc=[8, 8]), None),
-    (dict(bc=["periodic", "unbounded"], grid="staggered", nc=[8, 8]), _lib.HP_E_ARG),
+    (dict(bc=["periodic", "unbounded"], grid="staggered", nc=[8, 8]), None),  # semi-unbounded
+    (dict(bc=["unbounded", "unbounded"], grid="staggered", nc=[8, 8]), _lib.HP_E_ARG),
+    (dict(bc=["unbounded", "unbounded", "neumann"], grid="staggered", nc=[8, 8, 8]), _lib.HP_E_UNSUPPORTED),
     (dict(bc=["periodic", "neumann"], grid="staggered", nc=[8, 8], diff="grad"), _lib.HP_E_UNSUPPORTED),
     (dict(bc=["dirichlet", "neumann"], grid="staggered", nc=[8, 8], kernel="ps", inhomogeneous=True),
      _lib.HP_E_UNSUPPORTED),

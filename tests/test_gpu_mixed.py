@@ -1,5 +1,6 @@
 """Mixed-boundary plans (a periodic, Dirichlet or Neumann condition per axis)
-on the GPU against the oracle, element by element.
+and semi-unbounded plans (one free axis beside them) on the GPU against the
+oracle, element by element.
 
 * every ordered pair of distinct conditions in 2D and four triples in 3D, both
   grids, PS and FD2, homogeneous and inhomogeneous (FD2), FP32 and FP64;
@@ -8,7 +9,10 @@ on the GPU against the oracle, element by element.
 * Dirichlet / Neumann mixes at power-of-two transform lengths run the bounded
   wavefront kernels, also checked against the general ones;
 * the zero mode of periodic / Neumann mixes; a 3-component field;
-* descriptor rules (derivatives refused, faces of periodic axes).
+* descriptor rules (derivatives refused, faces of periodic axes);
+* semi-unbounded: three 2D and three 3D axis layouts, both grids, PS and FD2,
+  boundary values, prime and power-of-two lengths, the kappa = 0 row, a
+  3-component field, descriptor rules.
 """
 import numpy as np
 import pytest
@@ -35,7 +39,7 @@ def mixed_input(bcs, gtype, nc, ncomp, inhom, prec, seed):
     if inhom:
         faces = {}
         for a in range(nd):
-            if bcs[a] == "periodic":
+            if bcs[a] in ("periodic", "unbounded"):
                 continue
             shp = tuple(og.output_points(bcs[b], gtype, nc[b]) for b in range(nd) if b != a)
             for s in (0, 1):
@@ -159,4 +163,82 @@ def test_mixed_descriptor_rules():
     with pytest.raises(HipoissonError):
         _lib.hp_set_boundary(s.plan, 0, 0, 0, 0, g.data_ptr(), 1)  # axis 0 is periodic
     _lib.hp_set_boundary(s.plan, 0, 1, 0, 0, g.data_ptr(), 1)     # axis 1 is Dirichlet
+    s.close()
+
+
+# ----------------------------------------------------------- semi-unbounded
+SEMI2 = [["unbounded", "periodic"], ["dirichlet", "unbounded"], ["unbounded", "neumann"]]
+SEMI3 = [["periodic", "unbounded", "dirichlet"], ["unbounded", "neumann", "periodic"],
+         ["neumann", "dirichlet", "unbounded"]]
+SEMI_CASES = []
+for bcs in SEMI2:
+    for gtype in ("regular", "staggered"):
+        for kernel, inhom in (("ps", False), ("fd2", False), ("fd2", True)):
+            if inhom and bcs == ["unbounded", "periodic"]:
+                continue  # no face takes boundary values
+            for prec in ("f64", "f32"):
+                SEMI_CASES.append((bcs, gtype, [12, 10], kernel, inhom, prec))
+for bcs in SEMI3:
+    for gtype in ("regular", "staggered"):
+        for kernel, inhom in (("ps", False), ("fd2", True)):
+            for prec in ("f64", "f32"):
+                SEMI_CASES.append((bcs, gtype, [12, 10, 9], kernel, inhom, prec))
+
+
+@pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,prec", SEMI_CASES)
+def test_semi_matches_oracle(bcs, gtype, nc, kernel, inhom, prec):
+    run_case(bcs, gtype, nc, kernel, inhom, prec, seed=113 + len(nc))
+
+
+@pytest.mark.parametrize("bcs,nc", [(["unbounded", "dirichlet"], [7, 13]), (["periodic", "unbounded"], [11, 127]),
+                                    (["unbounded", "neumann", "dirichlet"], [13, 7, 11]),
+                                    (["neumann", "periodic", "unbounded"], [32, 16, 64])])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_semi_lengths(bcs, nc, prec):
+    run_case(bcs, "staggered", nc, "fd2", "dirichlet" in bcs or "neumann" in bcs, prec, seed=127)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_semi_zero_eigenvalue_row(prec):
+    # a source constant along the periodic / Neumann axes: only the kappa = 0
+    # row (G = |x| / 2) acts
+    import oracle
+    import torch
+    from paper_2301_01145_amd import Solver
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    nc = [16, 6, 5]
+    bcs = ["unbounded", "periodic", "neumann"]
+    x = np.random.default_rng(131).normal(size=16)
+    f = np.broadcast_to(x[:, None, None], (16, 6, 5)).copy()
+    f = f.astype(np.float32 if prec == "f32" else np.float64).astype(np.float64)
+    s = Solver(bcs, "staggered", nc, LO, HI, kernel="fd2", dtype=dtype)
+    psi, _ = s.solve(torch.as_tensor(f, dtype=dtype, device="cuda"))
+    torch.cuda.synchronize()
+    got = psi[0].double().cpu().numpy()
+    ref, _ = oracle.solve(bcs, "staggered", nc, LO, HI, f, operator="fd2")
+    check(got, ref, prec, "psi")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_semi_vector(prec):
+    run_case(["dirichlet", "periodic", "unbounded"], "staggered", [10, 12, 16], "ps", False, prec, seed=137,
+             ncomp=3)
+
+
+def test_semi_descriptor_rules():
+    import ctypes
+    import torch
+    from paper_2301_01145_amd import HipoissonError, Solver, _lib, make_desc
+    out = ctypes.c_void_p()
+    for kw, st in ((dict(bc=["unbounded", "unbounded"], grid="staggered", nc=[8, 8]), _lib.HP_E_ARG),
+                   (dict(bc=["unbounded", "unbounded", "periodic"], grid="staggered", nc=[8, 8, 8]),
+                    _lib.HP_E_UNSUPPORTED)):
+        d = make_desc(**kw)
+        assert _lib.lib().hp_plan_create(ctypes.byref(d), None, ctypes.byref(out)) == st
+    s = Solver(["unbounded", "dirichlet"], "staggered", [8, 8], kernel="fd2", dtype=torch.float64,
+               inhomogeneous=True)
+    g = torch.zeros(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(HipoissonError):
+        _lib.hp_set_boundary(s.plan, 0, 0, 0, 0, g.data_ptr(), 1)  # the free axis
     s.close()

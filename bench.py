@@ -204,7 +204,7 @@ def neumann_batch64(steps, warmup):
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         bs = BatchedSolver("neumann", "staggered", [{"nc": list(p["shape"])} for p in probs], kernel="ps")
-        bs.bind([torch.as_tensor(p["f"].astype(np.float32), device="cuda") for p in probs])
+        psis32 = bs.bind([torch.as_tensor(p["f"].astype(np.float32), device="cuda") for p in probs])
     torch.cuda.synchronize()
     mode_default = bs.kernel_mode()
     ms_default = _time(bs.run, steps, warmup, bs.stream)
@@ -227,8 +227,70 @@ def neumann_batch64(steps, warmup):
            "model_bytes": bs.model_bytes(),
            "model_gbs": bs.model_bytes() / (ms * 1e-3) / 1e9,
            "error_flag": bs.error_flag()}
+    with torch.cuda.stream(side):
+        bs.run()
+    torch.cuda.synchronize()
+    got32 = [t.double() for t in psis32]
     bs.close()
+    out["vs_fp64"] = _batch_vs_fp64(probs, got32, steps, warmup)
     return out
+
+
+def _batch_vs_fp64(probs, got32, steps, warmup):
+    """The same 64 problems as a batched FP64 plan and as 64 plain FP64 single
+    plans on the same GPU: their times, and the error of the FP32 batch (and
+    of the FP64 batch) against the plain FP64 solves."""
+    import numpy as np
+    import torch
+
+    from paper_2301_01145_amd import Solver
+    from paper_2301_01145_amd.batched import BatchedSolver
+    side = torch.cuda.Stream()
+    fs = [torch.as_tensor(p["f"].astype(np.float32).astype(np.float64), device="cuda") for p in probs]
+    with torch.cuda.stream(side):
+        b64 = BatchedSolver("neumann", "staggered", [{"nc": list(p["shape"])} for p in probs], kernel="ps",
+                            dtype=torch.float64)
+        psis64 = b64.bind(fs)
+        b64.autotune(reps=3)  # FP64 batches run the general passes: tiles per item, radix orders
+    torch.cuda.synchronize()
+    ms_b64 = _time_graph(b64.run, side, steps, warmup)
+    with torch.cuda.stream(side):
+        b64.run()
+    singles, outs = [], []
+    with torch.cuda.stream(side):
+        for i, p in enumerate(probs):
+            s = Solver("neumann", "staggered", list(p["shape"]), kernel="ps", dtype=torch.float64)
+            psi, _ = s.bind(fs[i])
+            singles.append(s)
+            outs.append(psi[0])
+
+    def run_singles():
+        for s in singles:
+            s.run()
+    torch.cuda.synchronize()
+    ms_single = _time_graph(run_singles, side, steps, warmup)
+    with torch.cuda.stream(side):
+        run_singles()
+    torch.cuda.synchronize()
+    num32 = den = num64 = 0.0
+    worst32 = 0.0
+    for i in range(len(probs)):
+        ref = outs[i]
+        d32 = float(torch.sum((got32[i] - ref) ** 2))
+        d64 = float(torch.sum((psis64[i] - ref) ** 2))
+        r2 = float(torch.sum(ref ** 2))
+        num32, num64, den = num32 + d32, num64 + d64, den + r2
+        worst32 = max(worst32, (d32 / r2) ** 0.5 if r2 > 0 else 0.0)
+    res = {"fp64_batched_ms": ms_b64, "fp64_single_plans_ms": ms_single,
+           "timing": "hipGraph replays (FP64 batch: one tuned plan; single plans: 64 plans in one graph)",
+           "fp32_batch_rel_l2_vs_fp64": (num32 / den) ** 0.5,
+           "fp32_batch_worst_problem_rel_l2": worst32,
+           "fp64_batch_rel_l2_vs_fp64_singles": (num64 / den) ** 0.5,
+           "fp64_batch_error_flag": b64.error_flag()}
+    for s in singles:
+        s.close()
+    b64.close()
+    return res
 
 
 def other_workloads(steps, warmup):

@@ -107,9 +107,23 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     psi = [bounded.solve_bounded(c, bc, grid_type, operator, lengths, hs, faces if not vector else (faces[i] if faces else None))
            for i, c in enumerate(comps)]
     derivs = []
-    if diff != "none" and bc != "periodic":
-        if faces:
-            raise NotImplementedError("Dirichlet / Neumann operators: homogeneous boundary values only")
+    if diff != "none" and bc != "periodic" and faces:
+        # boundary values: centred FD2 differences closed by the ghost rules
+        # (bounded.fd_derivative); first-derivative operators only
+        face_c = (lambda c: faces[c]) if vector else (lambda c: faces)
+        grads = [bounded.fd_gradient(psi[c], bc, grid_type, hs, face_c(c)) for c in range(len(psi))]
+        if diff == "grad" and not vector:
+            derivs = grads[0]
+        elif diff == "curl" and nd == 2 and not vector:
+            derivs = [grads[0][1], -grads[0][0]]
+        elif diff == "curl" and vector and nd == 3:
+            g = grads
+            derivs = [g[2][1] - g[1][2], g[0][2] - g[2][0], g[1][0] - g[0][1]]
+        elif diff == "div" and vector and nd == 3:
+            derivs = [grads[0][0] + grads[1][1] + grads[2][2]]
+        else:
+            raise NotImplementedError("boundary values: GRAD, CURL and DIV")
+    elif diff != "none" and bc != "periodic":
         if diff == "grad":
             if vector:
                 raise NotImplementedError("gradient: scalar only")

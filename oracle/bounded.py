@@ -437,3 +437,59 @@ def solve_semi(f, bcs, grid, operator, lengths, hs, faces=None):
             _, bwd, norm = TRANSFORM_PAIRS[(bcs[a], grid)]
             psi = _apply_real_pair(bwd, psi, a) / norm(f.shape[a])
     return mixed_output(psi.real, bcs, grid, faces or {})
+
+
+# ------------------------------------------- derivatives with boundary values
+# With inhomogeneous FD2 boundary values the unknowns' sine / cosine series does
+# not carry g (bounded_derivative needs homogeneous values).  The derivative is
+# then taken the way the FD2 eigenvalues discretise the operator: the centred
+# second-order difference (psi_{i+1} - psi_{i-1}) / (2 H) at every output point,
+# closed at the faces by the Neumann ghost rules that also weight the boundary
+# terms:
+#   Neumann  REGULAR     ghost = psi_1 -+ 2 H g        (centred derivative = g)
+#   Neumann  STAGGERED   ghost = psi_0 -+ H g          (face difference = g)
+# and by one-sided second-order differences next to Dirichlet faces: on
+# REGULAR boundary nodes (where no FD2 equation holds) -+(3 psi_0 - 4 psi_1 +
+# psi_2) / (2 H); at the first STAGGERED centre the derivative of the
+# quadratic through the face value g and the two nearest centres,
+# -+(4 g / 3 - psi_0 - psi_1 / 3) / H (the linear ghost 2 g - psi_0 of the
+# solve would make that point first order only).
+
+def fd_derivative(psi, bc, grid, h, axis, g_lo=None, g_hi=None):
+    """d psi / d x_axis at the output points of a bounded FD2 solve (psi on the
+    output points; g_lo, g_hi the face values of this axis, None = 0)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    x = np.moveaxis(psi, axis, 0)
+    n = x.shape[0]
+    lo = 0.0 if g_lo is None else np.asarray(g_lo, dtype=np.float64)
+    hi = 0.0 if g_hi is None else np.asarray(g_hi, dtype=np.float64)
+    out = np.empty_like(x)
+    if bc == "dirichlet" and grid == "regular":
+        out[1:-1] = (x[2:] - x[:-2]) / (2.0 * h)
+        out[0] = (-3.0 * x[0] + 4.0 * x[1] - x[2]) / (2.0 * h)
+        out[-1] = (3.0 * x[-1] - 4.0 * x[-2] + x[-3]) / (2.0 * h)
+        return np.moveaxis(out, 0, axis)
+    if bc == "dirichlet":
+        if n == 1:
+            out[0] = (hi - lo) / h
+            return np.moveaxis(out, 0, axis)
+        out[1:-1] = (x[2:] - x[:-2]) / (2.0 * h)
+        out[0] = (x[1] / 3.0 + x[0] - 4.0 * lo / 3.0) / h
+        out[-1] = (4.0 * hi / 3.0 - x[-1] - x[-2] / 3.0) / h
+        return np.moveaxis(out, 0, axis)
+    if grid == "regular":
+        below, above = x[1] - 2.0 * h * lo, x[n - 2] + 2.0 * h * hi
+    else:
+        below, above = x[0] - h * lo, x[-1] + h * hi
+    ext = np.concatenate([below[None] if np.ndim(below) else np.full((1,) + x.shape[1:], below), x,
+                          above[None] if np.ndim(above) else np.full((1,) + x.shape[1:], above)], axis=0)
+    out[:] = (ext[2:] - ext[:-2]) / (2.0 * h)
+    return np.moveaxis(out, 0, axis)
+
+
+def fd_gradient(psi, bc, grid, hs, faces):
+    """fd_derivative along every axis; faces {(axis, side): g} (output points
+    of the other axes)."""
+    faces = faces or {}
+    return [fd_derivative(psi, bc, grid, hs[a], a, faces.get((a, 0)), faces.get((a, 1)))
+            for a in range(np.ndim(psi))]

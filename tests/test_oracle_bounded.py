@@ -531,8 +531,9 @@ def test_bounded_curl_2d_of_eigenmodes(bc, gtype):
     assert np.max(np.abs(curl[1] + g[0])) <= 1e-12 * scale
 
 
-def test_bounded_gradient_inhomogeneous_rejected():
+def test_bounded_laplacian_inhomogeneous_rejected():
+    # with boundary values only first derivatives are defined (FD2 differences)
     f = np.zeros((6,))
     with pytest.raises(NotImplementedError):
-        oracle.solve("dirichlet", "staggered", [6], [0.0], [1.0], f, operator="fd2", diff="grad",
+        oracle.solve("dirichlet", "staggered", [6], [0.0], [1.0], f, operator="fd2", diff="nabla",
                      faces={(0, 0): np.array(1.0)})

@@ -303,3 +303,34 @@ def test_semi_kernel_decay_is_caught(monkeypatch):
     orig = bounded.helmholtz_kernel_1d
     monkeypatch.setattr(bounded, "helmholtz_kernel_1d", lambda kappa, x: orig(np.asarray(kappa) / 2.0, x) / 2.0)
     _fails(ps.test_semi_fd2_matches_dense_matrix_function, ["dirichlet", "unbounded"], "regular")
+
+
+def test_fd_neumann_ghost_sign_is_caught(monkeypatch):
+    # the STAGGERED Neumann ghost taken as psi_0 + H g below the lower face
+    import test_oracle_fdgrad as pf
+    orig = bounded.fd_derivative
+
+    def wrong(psi, bc, grid, h, axis, g_lo=None, g_hi=None):
+        if bc == "neumann" and grid == "staggered" and g_lo is not None:
+            g_lo = -np.asarray(g_lo)
+        return orig(psi, bc, grid, h, axis, g_lo, g_hi)
+
+    monkeypatch.setattr(bounded, "fd_derivative", wrong)
+    _fails(pf.test_paraboloid_gradient_is_tfih1dgrad, "neumann", "staggered", 2)
+
+
+def test_fd_one_sided_coefficient_is_caught(monkeypatch):
+    # a first-order one-sided difference on REGULAR Dirichlet boundary nodes
+    import test_oracle_fdgrad as pf
+    orig = bounded.fd_derivative
+
+    def wrong(psi, bc, grid, h, axis, g_lo=None, g_hi=None):
+        out = orig(psi, bc, grid, h, axis, g_lo, g_hi)
+        if bc == "dirichlet" and grid == "regular":
+            x = np.moveaxis(np.asarray(psi), axis, 0)
+            o = np.moveaxis(out, axis, 0)
+            o[0] = (x[1] - x[0]) / h
+        return out
+
+    monkeypatch.setattr(bounded, "fd_derivative", wrong)
+    _fails(pf.test_paraboloid_gradient_is_tfih1dgrad, "dirichlet", "regular", 2)

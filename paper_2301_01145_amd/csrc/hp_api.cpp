@@ -213,9 +213,11 @@ hp_status validate(const hp_desc* d) {
   if (d->diff == HP_D_GRAD && d->ncomp != 1)
     return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
   if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN)) {
-    if (d->inhomogeneous)
+    // with boundary values the first derivatives are FD2 differences (the
+    // series of the unknowns does not carry g); no second derivatives
+    if (d->inhomogeneous && d->diff == HP_D_NABLA)
       return fail(nullptr, HP_E_UNSUPPORTED,
-                  "Dirichlet/Neumann derivatives need homogeneous boundary values");
+                  "Dirichlet/Neumann NABLA needs homogeneous boundary values");
     for (int a = 0; a < d->ndim; ++a)
       if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
         return fail(nullptr, HP_E_ARG, "Neumann regular derivatives need 2 cells per axis");
@@ -1087,7 +1089,9 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     double sign;
   };
   std::vector<Term> terms;
-  switch (d.diff) {
+  // with boundary values the derivatives are differences of psi taken after
+  // the solve (hp_solve, launch_fd_deriv), not series terms
+  switch (d.inhomogeneous ? HP_D_NONE : d.diff) {
     case HP_D_GRAD:
       for (int g = 0; g < nd; ++g) terms.push_back({0, g, P.der[g], 1.0});
       break;
@@ -2034,6 +2038,58 @@ void zero_mode_setup(const Problem& P, int c, PassArgs& a, int trap[3], double* 
   }
 }
 
+// GRAD / CURL / DIV of a Dirichlet / Neumann solve with boundary values: FD2
+// differences of psi on the output points (after the boundary-node fill),
+// closed at the faces by the boundary rules (launch_fd_deriv).
+hp_status fd_derivatives(hp_plan p, const Problem& P) {
+  const int nd = P.nd;
+  FdArgs base{};
+  base.nd = nd;
+  for (int a = 0; a < 3; ++a) {
+    base.N[a] = a < nd ? P.nout[a] : 1;
+    base.h[a] = P.h[a];
+  }
+  base.dirichlet = P.d.bc == HP_DIRICHLET;
+  base.regular = P.d.grid == HP_REGULAR;
+  auto term = [&](int comp, int axis, double sign) {
+    FdTerm t{};
+    t.psi = P.out[comp];
+    t.g_lo = P.face[axis][0][comp];
+    t.g_hi = P.face[axis][1][comp];
+    t.axis = axis;
+    t.sign = sign;
+    return t;
+  };
+  auto launch = [&](int slot, std::initializer_list<FdTerm> ts) -> hp_status {
+    FdArgs a = base;
+    a.out = P.der[slot];
+    for (const FdTerm& t : ts) a.t[a.nterm++] = t;
+    HP_HIP(p, launch_fd_deriv(a, p->prec, p->stream));
+    return HP_OK;
+  };
+  switch (P.d.diff) {
+    case HP_D_GRAD:
+      for (int g = 0; g < nd; ++g) HP_TRY(launch(g, {term(0, g, 1.0)}));
+      break;
+    case HP_D_CURL:
+      if (nd == 2) {  // (d_y psi, -d_x psi)
+        HP_TRY(launch(0, {term(0, 1, 1.0)}));
+        HP_TRY(launch(1, {term(0, 0, -1.0)}));
+      } else {
+        HP_TRY(launch(0, {term(2, 1, 1.0), term(1, 2, -1.0)}));
+        HP_TRY(launch(1, {term(0, 2, 1.0), term(2, 0, -1.0)}));
+        HP_TRY(launch(2, {term(1, 0, 1.0), term(0, 1, -1.0)}));
+      }
+      break;
+    case HP_D_DIV:
+      HP_TRY(launch(0, {term(0, 0, 1.0), term(1, 1, 1.0), term(2, 2, 1.0)}));
+      break;
+    default:
+      return fail(p, HP_E_UNSUPPORTED, "derivative with boundary values");
+  }
+  return HP_OK;
+}
+
 Problem* get_problem(hp_plan p, int problem) {
   if (!p || problem < 0 || problem >= (int)p->probs.size()) return nullptr;
   return &p->probs[problem];
@@ -2244,6 +2300,7 @@ hp_status hp_solve(hp_plan plan) {
                                          plan->stream));
     }
   }
+  if (P.d.inhomogeneous && P.nder > 0) HP_TRY(fd_derivatives(plan, P));
   plan->solved = true;
   return HP_OK;
 }

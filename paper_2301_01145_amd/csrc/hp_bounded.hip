@@ -1092,6 +1092,64 @@ hipError_t launch_add(const PassArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// One thread per output point; every term reads the three points around it
+// along its axis (the faces' values or the one-sided stencils at the ends).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fd_deriv(FdArgs a) {
+  long long total = 1;
+  for (int b = 0; b < a.nd; ++b) total *= a.N[b];
+  T* out = (T*)a.out;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int c[3] = {0, 0, 0};
+    long long r = e;
+    for (int b = a.nd - 1; b >= 0; --b) {
+      c[b] = (int)(r % a.N[b]);
+      r /= a.N[b];
+    }
+    double acc = 0.0;
+    for (int k = 0; k < a.nterm; ++k) {
+      const FdTerm& t = a.t[k];
+      const int ax = t.axis, n = a.N[ax], j = c[ax];
+      long long s = 1;
+      for (int b = ax + 1; b < a.nd; ++b) s *= a.N[b];
+      const T* p = (const T*)t.psi;
+      auto v = [&](int i) -> double { return (double)p[e + (long long)(i - j) * s]; };
+      // face values at this point's position on the other axes
+      long long fo = 0;
+      for (int b = 0; b < a.nd; ++b)
+        if (b != ax) fo = fo * a.N[b] + c[b];
+      const double glo = (t.g_lo && j == 0) ? (double)((const T*)t.g_lo)[fo] : 0.0;
+      const double ghi = (t.g_hi && j == n - 1) ? (double)((const T*)t.g_hi)[fo] : 0.0;
+      const double h = a.h[ax];
+      double d;
+      if (a.dirichlet && a.regular) {  // boundary nodes hold g; n >= 3
+        if (j == 0) d = (-3.0 * v(0) + 4.0 * v(1) - v(2)) / (2.0 * h);
+        else if (j == n - 1) d = (3.0 * v(n - 1) - 4.0 * v(n - 2) + v(n - 3)) / (2.0 * h);
+        else d = (v(j + 1) - v(j - 1)) / (2.0 * h);
+      } else if (a.dirichlet) {  // quadratic through the face value and two centres
+        if (n == 1) d = (ghi - glo) / h;  // (both faces at this one point)
+        else if (j == 0) d = (v(1) / 3.0 + v(0) - 4.0 * glo / 3.0) / h;
+        else if (j == n - 1) d = (4.0 * ghi / 3.0 - v(n - 1) - v(n - 2) / 3.0) / h;
+        else d = (v(j + 1) - v(j - 1)) / (2.0 * h);
+      } else {  // Neumann ghosts: centred difference = g (REGULAR), face difference = g
+        const double left = j > 0 ? v(j - 1) : (a.regular ? v(1) - 2.0 * h * glo : v(0) - h * glo);
+        const double right =
+            j < n - 1 ? v(j + 1) : (a.regular ? v(n - 2) + 2.0 * h * ghi : v(n - 1) + h * ghi);
+        d = (right - left) / (2.0 * h);
+      }
+      acc += t.sign * d;
+    }
+    out[e] = (T)acc;
+  }
+}
+
+hipError_t launch_fd_deriv(const FdArgs& a, int prec, hipStream_t s) {
+  if (prec == 0) hipLaunchKernelGGL(k_fd_deriv<float>, dim3(1024), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_fd_deriv<double>, dim3(1024), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s) {
   if (a.fast == FAST_GRAD_PREP)
     return prec == 0 ? launch_grad_prep<float>(a, s) : launch_grad_prep<double>(a, s);

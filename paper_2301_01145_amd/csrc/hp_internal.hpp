@@ -144,6 +144,29 @@ __host__ __device__ constexpr int wf_r0(int L) {
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s);
+// Derivatives of a Dirichlet / Neumann FD2 solve with boundary values
+// (hp_bounded.hip): out = sum of up to three terms sign * d psi_c / d x_axis,
+// centred second-order differences at every output point, closed by the
+// Neumann ghost rules and one-sided second-order differences at Dirichlet
+// faces.  Arrays are C-contiguous over the output points N[0..nd).
+struct FdTerm {
+  const void* psi;                // component on the output points
+  const void* g_lo;               // face values of `axis` (lower, upper side;
+  const void* g_hi;               //  null = 0), over the other axes' output points
+  int axis;
+  double sign;
+};
+struct FdArgs {
+  void* out;
+  int nd;
+  int N[3];
+  double h[3];
+  int dirichlet, regular;
+  int nterm;
+  FdTerm t[3];
+};
+hipError_t launch_fd_deriv(const FdArgs& a, int prec, hipStream_t s);
+
 // single-launch 2D periodic solve (hp_small.hip): LDS bytes with nbuf
 // spectral buffers (-1: no kernel for these lengths) and the launch
 int small2d_lds_bytes(int L0, int L1, int prec, int nbuf);

@@ -55,8 +55,9 @@ BAD = [
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="grad"), None),  # homogeneous: valid
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=3), None),  # valid
     (dict(bc="dirichlet", grid="staggered", nc=[8, 8, 8], diff="curl", ncomp=3, kernel="fd2",
-          inhomogeneous=True), _lib.HP_E_UNSUPPORTED),
-    (dict(bc="dirichlet", grid="staggered", nc=[8, 8], diff="grad", kernel="fd2", inhomogeneous=True),
+          inhomogeneous=True), None),  # FD2 differences with boundary values
+    (dict(bc="dirichlet", grid="staggered", nc=[8, 8], diff="grad", kernel="fd2", inhomogeneous=True), None),
+    (dict(bc="neumann", grid="regular", nc=[8, 8], diff="nabla", kernel="fd2", inhomogeneous=True),
      _lib.HP_E_UNSUPPORTED),
     (dict(bc="neumann", grid="regular", nc=[1], diff="grad"), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[7, 8]), None),  # prime length: a direct radix-7 stage

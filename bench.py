@@ -313,7 +313,11 @@ def other_workloads(steps, warmup):
     torch.cuda.synchronize()
     ms = _time(s.run, steps, warmup, s.stream)
     ms_graph = _time_graph(s.run, side, steps, warmup)
-    res["periodic2d_64_fp64"] = {"solves_per_s": 1000 / ms_graph, "ms_graph": ms_graph, "ms_eager": ms,
+    # back-to-back launches on the stream are the faster form of this one-kernel
+    # solve (a graph replay costs more host time than one kernel launch here)
+    res["periodic2d_64_fp64"] = {"solves_per_s": 1000 / min(ms, ms_graph),
+                                 "timing": "eager" if ms <= ms_graph else "graph",
+                                 "ms_graph": ms_graph, "ms_eager": ms,
                                  "launches": int(s.passes()), "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
     s.close()
     # 3D Dirichlet 128^3 regular FD2 inhomogeneous FP32

@@ -108,7 +108,7 @@ def profiled_kernel_us(pass_name, n):
     return None if v is None else v[0]
 
 
-def survey_model_bytes(n, es=4):
+def six_field_model_bytes(n, es=4):
     """The pruned five-pass byte model with six stored spectral fields between
     the x pass and the backward y pass and the Green's octant in FP64: per
     component, A = (n+1) n n complex half-spectrum rows (P1 out), B = (n+1)
@@ -642,8 +642,8 @@ def main():
         # the same solve priced with six stored spectral fields between the x and
         # backward-y passes and an FP64 Green's octant (this library stores five,
         # and the octant in the solve precision)
-        "model_bytes_six_field_fp64_green": survey_model_bytes(n),
-        "model_gbs_six_field_fp64_green": survey_model_bytes(n) / (r32["ms"] * 1e-3) / 1e9,
+        "model_bytes_six_field_fp64_green": six_field_model_bytes(n),
+        "model_gbs_six_field_fp64_green": six_field_model_bytes(n) / (r32["ms"] * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, n),
                      "kernel": name, "kernel_ms": pms, "kernel_bytes": pbytes,

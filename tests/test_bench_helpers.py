@@ -68,7 +68,7 @@ def test_profiled_kernel_time_follows_the_source_digest(monkeypatch, tmp_path):
 def test_six_field_model_bytes():
     # 256^3, FP32: P1 0.60 + P2 1.21 + P3 2.56 (nine spectral fields and the
     # FP64 octant of 257^3) + P4 2.43 + P5 1.19 GB
-    b = bench.survey_model_bytes(256)
+    b = bench.six_field_model_bytes(256)
     K = 257
     A = K * 256 * 256 * 8
     B = K * 512 * 256 * 8

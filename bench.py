@@ -336,6 +336,29 @@ def other_workloads(steps, warmup):
     res["dirichlet3d_128_ps_grad_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
                                            "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
     s.close()
+    # a condition per axis, and one free axis (FD2, FP32, seeded normal sources;
+    # boundary values on the Dirichlet / Neumann faces), and a prime length
+    rng = np.random.default_rng(12)
+    for key, bcs, nc, inhom in (("mixed3d_128_pdn_fd2_fp32", ["periodic", "dirichlet", "neumann"],
+                                 [128, 128, 128], True),
+                                ("semi3d_128_free_pp_fd2_fp32", ["unbounded", "periodic", "periodic"],
+                                 [128, 128, 128], False),
+                                ("periodic3d_127_fp32", "periodic", [127, 127, 127], False)):
+        s = Solver(bcs, "staggered", nc, kernel="fd2", dtype=torch.float32, inhomogeneous=inhom)
+        src = torch.as_tensor(rng.normal(size=s.in_shape).astype(np.float32), device="cuda")
+        fd = None
+        if inhom:
+            fd = {}
+            for a in range(3):
+                if bcs[a] in ("dirichlet", "neumann"):
+                    shp = tuple(s.out_shape[b] for b in range(3) if b != a)
+                    for side in (0, 1):
+                        fd[(a, side)] = torch.as_tensor(rng.normal(size=shp).astype(np.float32), device="cuda")
+        s.bind(src, fd)
+        ms = _time(s.run, steps, warmup, s.stream)
+        res[key] = {"solves_per_s": 1000 / ms, "ms": ms, "launches": int(s.passes()),
+                    "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
+        s.close()
     res["neumann_batch64_fp32"] = neumann_batch64(steps, warmup)
     # free-space kernels (Section 2.5.2): plan time (Green's function on the doubled
     # grid, FP64 transform, octant) and solve time of the 256^3 curl plan, and the

@@ -167,8 +167,9 @@ enum {
  * the GPU for unbounded problems), twiddle tables, workspaces.  Any cell count
  * is accepted (Section 2.3.2): transform lengths with prime factors above 5
  * run a direct stage per such prime (R multiply-adds per output), so they are
- * slower than 2^a 3^b 5^c lengths; a length above 8192 (FP32) or 4096 (FP64)
- * returns HP_E_UNSUPPORTED.  Returns HP_E_ARG / HP_E_UNSUPPORTED for
+ * slower than 2^a 3^b 5^c lengths; a length above 8192 (FP32) or 4096 (FP64),
+ * or a doubled free-space length above 4096 (the Green's function is
+ * transformed in FP64), returns HP_E_UNSUPPORTED.  Returns HP_E_ARG / HP_E_UNSUPPORTED for
  * descriptors it cannot serve.  Blocking. */
 HP_API hp_status hp_plan_create(const hp_desc* desc, hp_stream stream, hp_plan* out);
 

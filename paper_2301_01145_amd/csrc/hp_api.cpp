@@ -235,6 +235,9 @@ hp_status validate(const hp_desc* d) {
                   "transform length " + std::to_string(L) + " needs too many radix stages");
     if ((long long)L > (long long)(d->prec == 0 ? 32 : 16) * kMaxLenThreads)
       return fail(nullptr, HP_E_UNSUPPORTED, "transform length too large");
+    // the Green's function of free space is transformed in FP64 at plan time
+    if (unb && (long long)L > 16LL * kMaxLenThreads)
+      return fail(nullptr, HP_E_UNSUPPORTED, "doubled free-space length above 4096");
   }
   return HP_OK;
 }

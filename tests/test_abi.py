@@ -74,6 +74,7 @@ BAD = [
     (dict(bc=["neumann", "periodic"], grid="regular", nc=[8, 8], kernel="g2"), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[8193], prec="f32"), _lib.HP_E_UNSUPPORTED),  # longer than a tile
     (dict(bc="periodic", grid="staggered", nc=[4097], prec="f64"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc="unbounded", grid="staggered", nc=[2049, 8], prec="f32"), _lib.HP_E_UNSUPPORTED),  # FP64 Green's
     (dict(bc="periodic", grid="staggered", nc=[0, 8]), _lib.HP_E_ARG),
     (dict(bc="dirichlet", grid="regular", nc=[1]), _lib.HP_E_ARG),
     (dict(bc="periodic", grid="staggered", nc=[8], lo=[1.0], hi=[1.0]), _lib.HP_E_ARG),

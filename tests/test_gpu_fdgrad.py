@@ -105,3 +105,36 @@ def test_paraboloid_gradient_on_gpu(bc, grid):
     scale = max(np.max(np.abs(g)) for g in grads)
     for a in range(3):
         assert np.max(np.abs(gd[a] - grads[a])) <= 1e-10 * scale, a
+
+
+def test_inhomogeneous_gradient_graph_replay():
+    """The solve with its derivative launches, replayed from a captured graph."""
+    import torch
+    from paper_2301_01145_amd import Solver
+    nc = [12, 10, 9]
+    f, faces = case_input("neumann", "staggered", nc, 1, True, "f64", seed=167)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = Solver("neumann", "staggered", nc, LO, HI, kernel="fd2", diff="grad", dtype=torch.float64,
+                   inhomogeneous=True)
+        dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+        psi, der = s.bind(dev(f), {k: dev(v) for k, v in faces.items()})
+        s.run()
+    torch.cuda.synchronize()
+    outs = list(psi) + list(der)
+    eager = [t.cpu().numpy().copy() for t in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        s.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in outs:
+            t.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda") * 2.0
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, t in enumerate(outs):
+            assert np.array_equal(t.cpu().numpy(), eager[i]), (rep, i)
+        del junk
+    s.close()

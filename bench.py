@@ -322,18 +322,27 @@ def other_workloads(steps, warmup):
     s.close()
     # 3D Dirichlet 128^3 regular FD2 inhomogeneous FP32
     f, faces = dirichlet_3d(128)
-    s = Solver("dirichlet", "regular", [128] * 3, kernel="fd2", dtype=torch.float32, inhomogeneous=True)
-    fd = {k: torch.as_tensor(v.astype(np.float32), device="cuda") for k, v in faces.items()}
-    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"), fd)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = Solver("dirichlet", "regular", [128] * 3, kernel="fd2", dtype=torch.float32, inhomogeneous=True)
+        fd = {k: torch.as_tensor(v.astype(np.float32), device="cuda") for k, v in faces.items()}
+        s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"), fd)
+    torch.cuda.synchronize()
     ms = _time(s.run, steps, warmup, s.stream)
-    res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+    ms_graph = _time_graph(s.run, side, steps, warmup)
+    res["dirichlet3d_128_fd2_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms, "ms_graph": ms_graph,
+                                       "launches": int(s.passes()),
                                        "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
     s.close()
     # the same source, homogeneous PS, psi and its gradient (sine -> cosine series)
-    s = Solver("dirichlet", "regular", [128] * 3, kernel="ps", diff="grad", dtype=torch.float32)
-    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"))
+    with torch.cuda.stream(side):
+        s = Solver("dirichlet", "regular", [128] * 3, kernel="ps", diff="grad", dtype=torch.float32)
+        s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"))
+    torch.cuda.synchronize()
     ms = _time(s.run, steps, warmup, s.stream)
-    res["dirichlet3d_128_ps_grad_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms,
+    ms_graph = _time_graph(s.run, side, steps, warmup)
+    res["dirichlet3d_128_ps_grad_fp32"] = {"solves_per_s": 1000 / ms, "ms": ms, "ms_graph": ms_graph,
+                                           "launches": int(s.passes()),
                                            "model_gbs": s.model_bytes() / (ms * 1e-3) / 1e9}
     s.close()
     # a condition per axis, and one free axis (FD2, FP32, seeded normal sources;

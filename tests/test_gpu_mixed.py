@@ -274,3 +274,39 @@ def test_mixed_and_semi_graph_replay(bcs, kernel, inhom):
         assert np.array_equal(psi[0].cpu().numpy(), eager), rep
         del junk
     s.close()
+
+
+def _sweep_cases(count, seed):
+    """Seeded random mixed / semi-unbounded cases: conditions per axis, grid,
+    operator, boundary values, precision and sizes of any factorization."""
+    from oracle import grid as og
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        nd = int(rng.integers(2, 4))
+        bcs = [str(rng.choice(["periodic", "dirichlet", "neumann"])) for _ in range(nd)]
+        if rng.random() < 0.35:
+            bcs[int(rng.integers(0, nd))] = "unbounded"
+        if len(set(bcs)) == 1:
+            continue  # a uniform plan: covered by the main sweep
+        gtype = str(rng.choice(["regular", "staggered"]))
+        kernel = str(rng.choice(["ps", "fd2"]))
+        faces_ok = any(b in ("dirichlet", "neumann") for b in bcs)
+        inhom = kernel == "fd2" and faces_ok and bool(rng.random() < 0.5)
+        prec = str(rng.choice(["f32", "f64"]))
+        hi_n = 64 if nd == 2 else 20
+        nc = []
+        for b in bcs:
+            while True:
+                n = int(rng.integers(2, hi_n + 1))
+                if og.unknowns(b, gtype, n) >= (2 if (b == "neumann" and gtype == "regular") else 1):
+                    break
+            nc.append(n)
+        ncomp = 3 if (nd == 3 and rng.random() < 0.2) else 1
+        out.append((bcs, gtype, nc, kernel, inhom and ncomp == 1, prec, ncomp, int(rng.integers(0, 1 << 20))))
+    return out
+
+
+@pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,prec,ncomp,seed", _sweep_cases(60, seed=2301))
+def test_mixed_sweep(bcs, gtype, nc, kernel, inhom, prec, ncomp, seed):
+    run_case(bcs, gtype, nc, kernel, inhom, prec, seed=seed, ncomp=ncomp)

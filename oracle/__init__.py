@@ -88,16 +88,36 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     lengths = [float(hi[a]) - float(lo[a]) for a in range(nd)]
     f = np.asarray(f, dtype=np.float64)
     if isinstance(bc, (list, tuple)):
-        # a condition per axis (bounded.solve_mixed); psi only
-        if diff != "none":
-            raise NotImplementedError("mixed-boundary solves: psi only")
+        # a condition per axis (bounded.solve_mixed); derivatives of
+        # homogeneous solves without a free axis, per axis by its own series
+        # (bounded.mixed_derivative)
+        bcs = list(bc)
+        if diff != "none" and ("unbounded" in bcs or faces):
+            raise NotImplementedError("mixed-boundary derivatives: homogeneous, no free axis")
         vector = f.ndim == nd + 1
         comps = [f[c] for c in range(f.shape[0])] if vector else [f]
-        solver = bounded.solve_semi if "unbounded" in bc else bounded.solve_mixed
-        psi = [solver(c, list(bc), grid_type, operator, lengths, hs,
+        solver = bounded.solve_semi if "unbounded" in bcs else bounded.solve_mixed
+        psi = [solver(c, bcs, grid_type, operator, lengths, hs,
                       (faces[i] if (faces and vector) else faces))
                for i, c in enumerate(comps)]
-        return (np.stack(psi) if vector else psi[0]), []
+        d1 = lambda p, a: bounded.mixed_derivative(p, bcs, grid_type, nc, lengths, a, 1)
+        if diff == "none":
+            derivs = []
+        elif diff == "grad" and not vector:
+            derivs = [d1(psi[0], a) for a in range(nd)]
+        elif diff == "curl" and nd == 2 and not vector:
+            derivs = [d1(psi[0], 1), -d1(psi[0], 0)]
+        elif diff == "curl" and vector and nd == 3:
+            derivs = [d1(psi[2], 1) - d1(psi[1], 2), d1(psi[0], 2) - d1(psi[2], 0),
+                      d1(psi[1], 0) - d1(psi[0], 1)]
+        elif diff == "div" and vector and nd == 3:
+            derivs = [d1(psi[0], 0) + d1(psi[1], 1) + d1(psi[2], 2)]
+        elif diff == "nabla":
+            derivs = [sum(bounded.mixed_derivative(p, bcs, grid_type, nc, lengths, a, 2) for a in range(nd))
+                      for p in psi]
+        else:
+            raise ValueError(diff)
+        return (np.stack(psi) if vector else psi[0]), derivs
     if bc == "unbounded":
         sigma = float(sigma_cells) * max(hs)
         kernel = operator if operator in unbounded.KERNELS else "g2"

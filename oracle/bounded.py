@@ -493,3 +493,28 @@ def fd_gradient(psi, bc, grid, hs, faces):
     faces = faces or {}
     return [fd_derivative(psi, bc, grid, hs[a], a, faces.get((a, 0)), faces.get((a, 1)))
             for a in range(np.ndim(psi))]
+
+
+def periodic_derivative(psi, length, axis, order=1):
+    """Spectral derivative of order 1 or 2 along one periodic axis (Section
+    2.3.3, eq. ft_sd; the Nyquist wavenumber zeroed, as in periodic_gradient)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    n = psi.shape[axis]
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    if n % 2 == 0:
+        m[n // 2] = 0.0
+    k = 2.0 * np.pi * m / float(length)
+    view = [1] * psi.ndim
+    view[axis] = n
+    factor = (1j * k) ** order
+    return np.fft.ifft(factor.reshape(view) * np.fft.fft(psi, axis=axis), axis=axis).real
+
+
+def mixed_derivative(psi, bcs, grid, nc, lengths, axis, order=1):
+    """Derivative along `axis` of a mixed-boundary solution with homogeneous
+    values: the eigenfunction series of that axis's own condition
+    (bounded_derivative for Dirichlet / Neumann, periodic_derivative for a
+    periodic axis), the other axes untouched."""
+    if bcs[axis] == "periodic":
+        return periodic_derivative(psi, lengths[axis], axis, order)
+    return bounded_derivative(psi, bcs[axis], grid, nc, lengths, axis, order)

@@ -14,6 +14,11 @@ What pins what:
   * A mixed solve whose axes all carry the same condition is the uniform solve.
   * The zero mode: a constant source on an all periodic / Neumann mix is
     removed entirely; with a Dirichlet axis nothing is removed.
+  * Derivatives (bounded.mixed_derivative): GRAD and NABLA of a product of
+    per-axis eigenfunctions (PS and FD2) are the analytic derivatives of the
+    product over the eigenvalue sum at the output points; CURL and DIV of a
+    3D vector with a different mode triple per component are their closed
+    forms.
 """
 import itertools
 
@@ -244,3 +249,93 @@ def test_periodic_axis_has_no_faces():
     with pytest.raises(ValueError):
         bounded.solve_mixed(f, ["periodic", "dirichlet"], "staggered", "fd2", [1.0, 1.0], [1 / 6, 1 / 5],
                             {(0, 0): np.zeros(5)})
+
+
+# ------------------------------------------------ derivatives of mixed plans
+def _mode_and_derivs(bc, m, x, lo, length):
+    """Eigenfunction of one axis, its first and second derivative, eigenvalue."""
+    t = (x - lo) / length
+    if bc == "dirichlet":
+        w = np.pi * m / length
+        return np.sin(w * (x - lo)), w * np.cos(w * (x - lo)), -w * w * np.sin(w * (x - lo)), -w * w
+    if bc == "neumann":
+        w = np.pi * m / length
+        return np.cos(w * (x - lo)), -w * np.sin(w * (x - lo)), -w * w * np.cos(w * (x - lo)), -w * w
+    w = 2 * np.pi * m / length
+    return (np.cos(w * (x - lo) + 0.4), -w * np.sin(w * (x - lo) + 0.4), -w * w * np.cos(w * (x - lo) + 0.4),
+            -w * w)
+
+
+@pytest.mark.parametrize("bcs", COMBOS)
+@pytest.mark.parametrize("gtype", ["regular", "staggered"])
+@pytest.mark.parametrize("operator", ["ps", "fd2"])
+def test_mixed_gradient_and_laplacian_of_eigenmodes(bcs, gtype, operator):
+    # psi of one product of per-axis eigenfunctions is that product over the
+    # eigenvalue sum; its gradient and Laplacian are the analytic ones (the
+    # FD2 eigenvalues enter only through the sum)
+    nd = len(bcs)
+    nc, lo, hi = [12, 10, 9][:nd], LO[:nd], HI[:nd]
+    xs_out = [grid.positions(bcs[a], gtype, lo[a], hi[a], nc[a]) for a in range(nd)]
+    xs_in = [x[1:-1] if (bcs[a] == "dirichlet" and gtype == "regular") else x for a, x in enumerate(xs_out)]
+    ms = [1 + (a % 2) for a in range(nd)]
+    lam = 0.0
+    fin = np.ones([len(x) for x in xs_in])
+    parts = []
+    for a in range(nd):
+        view = [1] * nd
+        view[a] = -1
+        v, _, _, la = _mode_and_derivs(bcs[a], ms[a], xs_in[a], lo[a], hi[a] - lo[a])
+        fin = fin * v.reshape(view)
+        parts.append([p.reshape(view) for p in _mode_and_derivs(bcs[a], ms[a], xs_out[a], lo[a], hi[a] - lo[a])[:3]])
+        if operator == "ps":
+            lam += la
+    if operator == "fd2":
+        lam = sum(bounded.eigenvalues(bcs[a], gtype, "fd2", len(xs_in[a]), hi[a] - lo[a],
+                                      grid.spacing(lo[a], hi[a], nc[a]))[ms[a] - (1 if bcs[a] == "dirichlet" else 0)
+                                                                       if bcs[a] != "periodic" else ms[a]]
+                  for a in range(nd))
+    psi, grads = oracle.solve(bcs, gtype, nc, lo, hi, fin, operator=operator, diff="grad")
+    _, lap = oracle.solve(bcs, gtype, nc, lo, hi, fin, operator=operator, diff="nabla")
+
+    def prod(sel):
+        out = 1.0
+        for a in range(nd):
+            out = out * parts[a][sel[a]]
+        return out
+
+    ref_psi = prod([0] * nd) / lam
+    assert np.max(np.abs(psi - ref_psi)) <= 1e-11 * np.max(np.abs(ref_psi))
+    for g in range(nd):
+        ref = prod([1 if a == g else 0 for a in range(nd)]) / lam
+        assert np.max(np.abs(grads[g] - ref)) <= 1e-10 * np.max(np.abs(ref)), g
+    ref_lap = sum(prod([2 if a == g else 0 for a in range(nd)]) for g in range(nd)) / lam
+    assert np.max(np.abs(lap[0] - ref_lap)) <= 1e-10 * np.max(np.abs(ref_lap))
+
+
+def test_mixed_curl_and_div_closed_form():
+    bcs = ["periodic", "dirichlet", "neumann"]
+    gtype = "staggered"
+    nc, lo, hi = [12, 10, 9], LO, HI
+    xs = [grid.positions(bcs[a], gtype, lo[a], hi[a], nc[a]) for a in range(3)]
+    comps, psis, dps = [], [], []
+    for c, ms in enumerate([(1, 2, 1), (2, 1, 3), (1, 3, 2)]):
+        fin, lam, parts = 1.0, 0.0, []
+        for a in range(3):
+            view = [1, 1, 1]
+            view[a] = -1
+            v, dv, _, la = _mode_and_derivs(bcs[a], ms[a], xs[a], lo[a], hi[a] - lo[a])
+            fin = fin * v.reshape(view)
+            parts.append((v.reshape(view), dv.reshape(view)))
+            lam += la
+        comps.append(fin)
+        psis.append(fin / lam)
+        dps.append([parts[0][g == 0] * parts[1][g == 1] * parts[2][g == 2] / lam for g in range(3)])
+    f = np.stack(comps)
+    _, curl = oracle.solve(bcs, gtype, nc, lo, hi, f, operator="ps", diff="curl")
+    _, div = oracle.solve(bcs, gtype, nc, lo, hi, f, operator="ps", diff="div")
+    d = dps
+    ref_curl = [d[2][1] - d[1][2], d[0][2] - d[2][0], d[1][0] - d[0][1]]
+    for c in range(3):
+        assert np.max(np.abs(curl[c] - ref_curl[c])) <= 1e-10 * np.max(np.abs(ref_curl[c])), c
+    ref_div = d[0][0] + d[1][1] + d[2][2]
+    assert np.max(np.abs(div[0] - ref_div)) <= 1e-10 * np.max(np.abs(ref_div))

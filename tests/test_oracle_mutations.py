@@ -334,3 +334,16 @@ def test_fd_one_sided_coefficient_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "fd_derivative", wrong)
     _fails(pf.test_paraboloid_gradient_is_tfih1dgrad, "dirichlet", "regular", 2)
+
+
+def test_mixed_periodic_derivative_sign_is_caught(monkeypatch):
+    # the periodic axis's first derivative with -i k in place of i k
+    import test_oracle_mixed as pm
+    orig = bounded.periodic_derivative
+
+    def wrong(psi, length, axis, order=1):
+        d = orig(psi, length, axis, order)
+        return -d if order == 1 else d
+
+    monkeypatch.setattr(bounded, "periodic_derivative", wrong)
+    _fails(pm.test_mixed_gradient_and_laplacian_of_eigenmodes, ["periodic", "dirichlet"], "staggered", "ps")

@@ -92,26 +92,31 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
         # homogeneous solves without a free axis, per axis by its own series
         # (bounded.mixed_derivative)
         bcs = list(bc)
-        if diff != "none" and ("unbounded" in bcs or faces):
-            raise NotImplementedError("mixed-boundary derivatives: homogeneous, no free axis")
+        if diff != "none" and ("unbounded" in bcs or (faces and diff == "nabla")):
+            raise NotImplementedError("mixed-boundary derivatives: no free axis; no NABLA with boundary values")
         vector = f.ndim == nd + 1
         comps = [f[c] for c in range(f.shape[0])] if vector else [f]
         solver = bounded.solve_semi if "unbounded" in bcs else bounded.solve_mixed
         psi = [solver(c, bcs, grid_type, operator, lengths, hs,
                       (faces[i] if (faces and vector) else faces))
                for i, c in enumerate(comps)]
-        d1 = lambda p, a: bounded.mixed_derivative(p, bcs, grid_type, nc, lengths, a, 1)
+        if faces and diff != "none":
+            # boundary values: FD2 differences per axis (bounded.fd_gradient_mixed)
+            face_c = (lambda c: faces[c]) if vector else (lambda c: faces)
+            grads = [bounded.fd_gradient_mixed(psi[c], bcs, grid_type, hs, face_c(c)) for c in range(len(psi))]
+            d1 = lambda c, a: grads[c][a]
+        else:
+            d1 = lambda c, a: bounded.mixed_derivative(psi[c], bcs, grid_type, nc, lengths, a, 1)
         if diff == "none":
             derivs = []
         elif diff == "grad" and not vector:
-            derivs = [d1(psi[0], a) for a in range(nd)]
+            derivs = [d1(0, a) for a in range(nd)]
         elif diff == "curl" and nd == 2 and not vector:
-            derivs = [d1(psi[0], 1), -d1(psi[0], 0)]
+            derivs = [d1(0, 1), -d1(0, 0)]
         elif diff == "curl" and vector and nd == 3:
-            derivs = [d1(psi[2], 1) - d1(psi[1], 2), d1(psi[0], 2) - d1(psi[2], 0),
-                      d1(psi[1], 0) - d1(psi[0], 1)]
+            derivs = [d1(2, 1) - d1(1, 2), d1(0, 2) - d1(2, 0), d1(1, 0) - d1(0, 1)]
         elif diff == "div" and vector and nd == 3:
-            derivs = [d1(psi[0], 0) + d1(psi[1], 1) + d1(psi[2], 2)]
+            derivs = [d1(0, 0) + d1(1, 1) + d1(2, 2)]
         elif diff == "nabla":
             derivs = [sum(bounded.mixed_derivative(p, bcs, grid_type, nc, lengths, a, 2) for a in range(nd))
                       for p in psi]

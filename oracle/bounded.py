@@ -459,6 +459,8 @@ def fd_derivative(psi, bc, grid, h, axis, g_lo=None, g_hi=None):
     """d psi / d x_axis at the output points of a bounded FD2 solve (psi on the
     output points; g_lo, g_hi the face values of this axis, None = 0)."""
     psi = np.asarray(psi, dtype=np.float64)
+    if bc == "periodic":  # a periodic axis of a mixed plan: the grid wraps
+        return (np.roll(psi, -1, axis=axis) - np.roll(psi, 1, axis=axis)) / (2.0 * h)
     x = np.moveaxis(psi, axis, 0)
     n = x.shape[0]
     lo = 0.0 if g_lo is None else np.asarray(g_lo, dtype=np.float64)
@@ -518,3 +520,11 @@ def mixed_derivative(psi, bcs, grid, nc, lengths, axis, order=1):
     if bcs[axis] == "periodic":
         return periodic_derivative(psi, lengths[axis], axis, order)
     return bounded_derivative(psi, bcs[axis], grid, nc, lengths, axis, order)
+
+
+def fd_gradient_mixed(psi, bcs, grid, hs, faces):
+    """fd_derivative along every axis of a mixed-boundary solve, each axis
+    closed by its own condition."""
+    faces = faces or {}
+    return [fd_derivative(psi, bcs[a], grid, hs[a], a, faces.get((a, 0)), faces.get((a, 1)))
+            for a in range(np.ndim(psi))]

@@ -169,3 +169,44 @@ def test_solve_gradient_second_order(bc, gtype):
     # norm; the other grids are second order to the faces
     rate = 1.8 if (bc == "dirichlet" and gtype == "staggered") else 3.3
     assert errs[0] / errs[1] > rate and errs[1] / errs[2] > rate, errs
+
+
+def test_periodic_axis_difference_closed_form():
+    # the wrapped centred difference of sin(k x) is k cos(k x) sin(k H) / (k H)
+    L, n = 1.7, 24
+    h = L / n
+    x = np.arange(n) * h
+    k = 2 * np.pi * 3 / L
+    d = bounded.fd_derivative(np.sin(k * x), "periodic", "regular", h, 0)
+    assert np.max(np.abs(d - k * np.cos(k * x) * np.sin(k * h) / (k * h))) <= 1e-12
+
+
+def test_mixed_boundary_values_gradient_second_order():
+    # a periodic x axis beside a Neumann y axis with boundary values: GRAD of the
+    # FD2 solve of psi = cos(2 pi x + 0.2) * (y^2 - y / 3) + sin(4 pi x) converges at O(H^2)
+    def psi_f(x, y):
+        return np.cos(2 * np.pi * x + 0.2) * (y * y - y / 3) + np.sin(4 * np.pi * x)
+
+    def grad_f(x, y):
+        return (-2 * np.pi * np.sin(2 * np.pi * x + 0.2) * (y * y - y / 3) + 4 * np.pi * np.cos(4 * np.pi * x),
+                np.cos(2 * np.pi * x + 0.2) * (2 * y - 1 / 3))
+
+    def lap_f(x, y):
+        return (-(2 * np.pi) ** 2 * np.cos(2 * np.pi * x + 0.2) * (y * y - y / 3) + 2 * np.cos(2 * np.pi * x + 0.2)
+                - (4 * np.pi) ** 2 * np.sin(4 * np.pi * x))
+
+    errs = []
+    bcs = ["periodic", "neumann"]
+    for n in (16, 32, 64):
+        nc, lo, hi = [n, n], [0.0, 0.0], [1.0, 1.0]
+        xo = [grid.positions(bcs[a], "staggered", lo[a], hi[a], nc[a]) for a in range(2)]
+        X, Y = np.meshgrid(*xo, indexing="ij")
+        faces = {}
+        for side in (0, 1):
+            yv = np.array([lo[1] if side == 0 else hi[1]])
+            PX, PY = np.meshgrid(xo[0], yv, indexing="ij")
+            faces[(1, side)] = grad_f(PX, PY)[1].squeeze(axis=1)
+        _, der = oracle.solve(bcs, "staggered", nc, lo, hi, lap_f(X, Y), operator="fd2", diff="grad", faces=faces)
+        ref = grad_f(X, Y)
+        errs.append(max(np.max(np.abs(der[a] - ref[a])) for a in range(2)))
+    assert errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs

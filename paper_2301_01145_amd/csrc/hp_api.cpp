@@ -174,8 +174,8 @@ hp_status validate(const hp_desc* d) {
     }
     if (nfree == d->ndim) return fail(nullptr, HP_E_ARG, "a plan that is free on every axis is HP_UNBOUNDED");
     if (nfree > 1) return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded plans take one free axis");
-    if (d->diff != HP_D_NONE)
-      return fail(nullptr, HP_E_UNSUPPORTED, "mixed-boundary plans take no derivative outputs");
+    if (nfree && d->diff != HP_D_NONE)
+      return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded plans take no derivative outputs");
   }
   if (d->grid < 0 || d->grid > 1) return fail(nullptr, HP_E_ARG, "bad grid");
   if (d->kernel < 0 || d->kernel > HP_G_SPECTRAL) return fail(nullptr, HP_E_ARG, "bad kernel");
@@ -212,14 +212,14 @@ hp_status validate(const hp_desc* d) {
     return fail(nullptr, HP_E_ARG, "div needs a 3-component 3D field");
   if (d->diff == HP_D_GRAD && d->ncomp != 1)
     return fail(nullptr, HP_E_ARG, "grad is for scalar fields");
-  if (d->diff != HP_D_NONE && (d->bc == HP_DIRICHLET || d->bc == HP_NEUMANN)) {
+  if (d->diff != HP_D_NONE && r2r_plan(*d)) {
     // with boundary values the first derivatives are FD2 differences (the
     // series of the unknowns does not carry g); no second derivatives
     if (d->inhomogeneous && d->diff == HP_D_NABLA)
       return fail(nullptr, HP_E_UNSUPPORTED,
                   "Dirichlet/Neumann NABLA needs homogeneous boundary values");
     for (int a = 0; a < d->ndim; ++a)
-      if (d->bc == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
+      if (axis_bc(*d, a) == HP_NEUMANN && d->grid == HP_REGULAR && d->nc[a] < 2)
         return fail(nullptr, HP_E_ARG, "Neumann regular derivatives need 2 cells per axis");
   }
   // any transform length whose radix stages (2, 3, 4, 5, 8 and primes) number at
@@ -1005,12 +1005,14 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   // from the transformed source.
   auto grad_deriv = [&](int g, const void* src, bool eigen, void* dst, double sign,
                         bool lap) -> hp_status {
-    const bool dir = d.bc == HP_DIRICHLET, reg = d.grid == HP_REGULAR;
+    const int bcg = axis_bc(d, g);
+    const bool dir = bcg == HP_DIRICHLET, reg = d.grid == HP_REGULAR, per = bcg == HP_PERIODIC;
     // active view of the derivative output: extent len[b] from off[b]
     int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
-    for (int b = 0; b < nd; ++b) { off[b] = dreg ? 1 : 0; len[b] = P.n[b]; }
+    for (int b = 0; b < nd; ++b) { off[b] = (dmask >> b) & 1; len[b] = P.n[b]; }
     int xd = 0;
     if (lap) xd = xb[0];
+    else if (per) xd = X_DHT;  // a Hartley series stays one (index mirrored)
     else if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
     else if (dir) xd = X_DCT3;
     else if (reg) { xd = X_DST1; len[g] = P.n[g] - 2; off[g] = 1; }   // interior nodes
@@ -1029,15 +1031,19 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
         a.gp_is[b] = a.gp_os[b] = b < nd ? ws[b] : 0;
         a.nunk[b] = b < nd ? P.n[b] : 1;
         a.lam[b] = eigen && b < nd ? P.lam[b] : nullptr;
-        a.kc[b] = lap && b < nd ? M_PI / P.len[b] : 0.0;
+        const int bb = b < nd ? axis_bc(d, b) : HP_NEUMANN;
+        a.gp_basis[b] = bb == HP_PERIODIC ? 2 : (bb == HP_DIRICHLET ? 0 : 1);
+        a.kc[b] = lap && b < nd ? (bb == HP_PERIODIC ? 2.0 : 1.0) * M_PI / P.len[b] : 0.0;
         if (b < nd) { cnt_in *= P.n[b]; cnt_out *= P.nout[b]; }
       }
       a.gp_eigen = eigen ? 1 : 0;
-      a.gp_kadd = dir ? 1 : 0;  // sine index k carries wavenumber k + 1
       if (lap) {
         a.diff = D_NABLA;
         a.gp_shift = 0;
         a.gp_scale = sign;
+      } else if (per) {
+        a.gp_shift = 0;
+        a.gp_scale = sign * 2.0 * M_PI / P.len[g];
       } else {
         a.gp_shift = dir ? -1 : 1;
         a.gp_scale = sign * (dir ? 1.0 : -1.0) * M_PI / P.len[g];
@@ -2052,13 +2058,17 @@ hp_status fd_derivatives(hp_plan p, const Problem& P) {
     base.N[a] = a < nd ? P.nout[a] : 1;
     base.h[a] = P.h[a];
   }
-  base.dirichlet = P.d.bc == HP_DIRICHLET;
+  for (int a = 0; a < 3; ++a) {
+    const int b = a < nd ? axis_bc(P.d, a) : HP_NEUMANN;
+    base.bc[a] = b == HP_PERIODIC ? FD_PERIODIC : (b == HP_DIRICHLET ? FD_DIRICHLET : FD_NEUMANN);
+  }
   base.regular = P.d.grid == HP_REGULAR;
   auto term = [&](int comp, int axis, double sign) {
     FdTerm t{};
     t.psi = P.out[comp];
-    t.g_lo = P.face[axis][0][comp];
-    t.g_hi = P.face[axis][1][comp];
+    const bool faces = axis_bc(P.d, axis) != HP_PERIODIC;
+    t.g_lo = faces ? P.face[axis][0][comp] : nullptr;
+    t.g_hi = faces ? P.face[axis][1][comp] : nullptr;
     t.axis = axis;
     t.sign = sign;
     return t;

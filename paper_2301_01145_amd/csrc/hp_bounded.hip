@@ -1026,27 +1026,31 @@ __global__ void __launch_bounds__(256) k_grad_prep(PassArgs a) {
     i[0] = (int)(r / a.gp_ext[1]);
     bool ok = true;
     long long so = 0, dof = 0;
-    double lam = 0.0, w2 = 0.0;
-    int kap = 0;
+    double lam = 0.0, w2 = 0.0, kap = 0.0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       dof += (long long)i[b] * a.gp_os[b];
       const int sb = i[b] - a.gp_off[b];
-      const int k = b == a.ax_j ? sb + a.gp_shift : sb;
+      const int basis = a.gp_basis[b];
+      int k = sb;
+      if (b == a.ax_j) k = basis == 2 ? (sb == 0 ? 0 : a.nunk[b] - sb) : sb + a.gp_shift;
       ok = ok && sb >= 0 && sb < a.gp_len[b] && k >= 0 && k < a.nunk[b];
       if (ok) {
         so += (long long)k * a.gp_is[b];
         if (a.lam[b]) lam += a.lam[b][k];
-        if (b == a.ax_j) kap = k + a.gp_kadd;
-        const double w = a.kc[b] * (double)(k + a.gp_kadd);  // NABLA: pi kappa_b / L_b
+        // wavenumber index of coefficient k: k + 1 (sine), k (cosine), signed k (Hartley)
+        const double kk = basis == 2 ? (double)signed_index(k, a.nunk[b]) : (double)(k + (basis == 0 ? 1 : 0));
+        if (b == a.ax_j) kap = basis == 2 ? -(double)signed_index(sb, a.nunk[b]) : kk;
+        const double w = a.kc[b] * kk;  // NABLA: the wavenumber of axis b
         w2 += w * w;
       }
     }
     T v = (T)0;
     if (ok) {
-      // gradient: +-(pi kappa / L) one index over; NABLA (diff = D_NABLA):
-      // -sum_b (pi kappa_b / L_b)^2 on the same index
-      double m = a.diff == D_NABLA ? -a.gp_scale * w2 : a.gp_scale * (double)kap;
+      // gradient: +-(pi kappa / L) one index over (Hartley: -(2 pi k~ / L)
+      // from the mirrored index); NABLA (diff = D_NABLA): -sum_b w_b^2 on the
+      // same index
+      double m = a.diff == D_NABLA ? -a.gp_scale * w2 : a.gp_scale * kap;
       if (a.gp_eigen) m = lam == 0.0 ? 0.0 : m * a.norm / lam;
       v = (T)m * src[so];
     }
@@ -1122,12 +1126,15 @@ __global__ void __launch_bounds__(256) k_fd_deriv(FdArgs a) {
       const double glo = (t.g_lo && j == 0) ? (double)((const T*)t.g_lo)[fo] : 0.0;
       const double ghi = (t.g_hi && j == n - 1) ? (double)((const T*)t.g_hi)[fo] : 0.0;
       const double h = a.h[ax];
+      const int bc = a.bc[ax];
       double d;
-      if (a.dirichlet && a.regular) {  // boundary nodes hold g; n >= 3
+      if (bc == FD_PERIODIC) {  // the grid wraps
+        d = (v(j + 1 < n ? j + 1 : 0) - v(j > 0 ? j - 1 : n - 1)) / (2.0 * h);
+      } else if (bc == FD_DIRICHLET && a.regular) {  // boundary nodes hold g; n >= 3
         if (j == 0) d = (-3.0 * v(0) + 4.0 * v(1) - v(2)) / (2.0 * h);
         else if (j == n - 1) d = (3.0 * v(n - 1) - 4.0 * v(n - 2) + v(n - 3)) / (2.0 * h);
         else d = (v(j + 1) - v(j - 1)) / (2.0 * h);
-      } else if (a.dirichlet) {  // quadratic through the face value and two centres
+      } else if (bc == FD_DIRICHLET) {  // quadratic through the face value and two centres
         if (n == 1) d = (ghi - glo) / h;  // (both faces at this one point)
         else if (j == 0) d = (v(1) / 3.0 + v(0) - 4.0 * glo / 3.0) / h;
         else if (j == n - 1) d = (4.0 * ghi / 3.0 - v(n - 1) - v(n - 2) / 3.0) / h;

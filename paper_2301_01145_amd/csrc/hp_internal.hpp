@@ -105,15 +105,18 @@ struct PassArgs {
   // signature of the pass geometry (host planner): passes with equal keys
   // share the configuration chosen by the autotuner
   unsigned long long tune_key;
-  // FAST_GRAD_PREP (Dirichlet / Neumann gradient along ax_j): output element
-  // i (logical axes, extents gp_ext, strides gp_os) is active where
-  // s = i - gp_off lies in [0, gp_len) on every axis; it reads the source
-  // coefficient src = s (+ gp_shift along ax_j; strides gp_is, extents nunk)
-  // times gp_scale (src + gp_kadd), and with gp_eigen by norm / sum_b
-  // lam[b][src_b] (0 where that sum is 0).  Elements that are not active, or
-  // whose source lies outside, are written as 0.
+  // FAST_GRAD_PREP (series derivative along ax_j): output element i (logical
+  // axes, extents gp_ext, strides gp_os) is active where s = i - gp_off lies
+  // in [0, gp_len) on every axis.  gp_basis[b] names axis b's series: 0 sine
+  // (index k carries wavenumber k + 1), 1 cosine (k), 2 Hartley (signed k,
+  // Nyquist 0).  Along ax_j a sine / cosine source is read at src = s +
+  // gp_shift and scaled by gp_scale times src's wavenumber; a Hartley source
+  // at -s (mod nunk), scaled by -gp_scale times s's signed wavenumber.  Other
+  // axes read src = s (strides gp_is, extents nunk).  With gp_eigen the value
+  // is divided by sum_b lam[b][src_b] / norm (0 where that sum is 0).
+  // Elements that are not active, or whose source lies outside, are 0.
   int gp_ext[3], gp_off[3], gp_len[3];
-  int gp_shift, gp_kadd, gp_eigen;
+  int gp_shift, gp_basis[3], gp_eigen;
   double gp_scale;
   long long gp_is[3], gp_os[3];
 };
@@ -144,11 +147,13 @@ __host__ __device__ constexpr int wf_r0(int L) {
 // Launch one wavefront-FFT pass (power-of-two L in [64, 1024]).
 hipError_t launch_fast(const PassArgs& a, int prec, int grid_y, hipStream_t s);
 hipError_t launch_bounded(const PassArgs& a, int prec, hipStream_t s);
-// Derivatives of a Dirichlet / Neumann FD2 solve with boundary values
-// (hp_bounded.hip): out = sum of up to three terms sign * d psi_c / d x_axis,
-// centred second-order differences at every output point, closed by the
-// Neumann ghost rules and one-sided second-order differences at Dirichlet
-// faces.  Arrays are C-contiguous over the output points N[0..nd).
+// Derivatives of a Dirichlet / Neumann (or mixed) FD2 solve with boundary
+// values (hp_bounded.hip): out = sum of up to three terms sign * d psi_c /
+// d x_axis, centred second-order differences at every output point, closed by
+// the Neumann ghost rules and one-sided second-order differences at Dirichlet
+// faces, wrapped along periodic axes.  Arrays are C-contiguous over the output
+// points N[0..nd).
+enum FdBc : int { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
 struct FdTerm {
   const void* psi;                // component on the output points
   const void* g_lo;               // face values of `axis` (lower, upper side;
@@ -161,7 +166,8 @@ struct FdArgs {
   int nd;
   int N[3];
   double h[3];
-  int dirichlet, regular;
+  int bc[3];  // FdBc of each axis
+  int regular;
   int nterm;
   FdTerm t[3];
 };

@@ -9,7 +9,10 @@ oracle, element by element.
 * Dirichlet / Neumann mixes at power-of-two transform lengths run the bounded
   wavefront kernels, also checked against the general ones;
 * the zero mode of periodic / Neumann mixes; a 3-component field;
-* descriptor rules (derivatives refused, faces of periodic axes);
+* GRAD, CURL, DIV and NABLA of mixed plans (series per axis; FD2 differences
+  with boundary values), also on the wavefront passes;
+* descriptor rules (derivatives of semi-unbounded plans refused, faces of
+  periodic axes);
 * semi-unbounded: three 2D and three 3D axis layouts, both grids, PS and FD2,
   boundary values, prime and power-of-two lengths, the kappa = 0 row, a
   3-component field, descriptor rules.
@@ -154,7 +157,7 @@ def test_mixed_descriptor_rules():
     import ctypes
     import torch
     from paper_2301_01145_amd import HipoissonError, Solver, _lib, make_desc
-    d = make_desc(["periodic", "dirichlet"], "staggered", [8, 8], diff="grad")
+    d = make_desc(["periodic", "unbounded"], "staggered", [8, 8], diff="grad")
     out = ctypes.c_void_p()
     assert _lib.lib().hp_plan_create(ctypes.byref(d), None, ctypes.byref(out)) == _lib.HP_E_UNSUPPORTED
     s = Solver(["periodic", "dirichlet"], "staggered", [8, 8], kernel="fd2", dtype=torch.float64,
@@ -310,3 +313,70 @@ def _sweep_cases(count, seed):
 @pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,prec,ncomp,seed", _sweep_cases(60, seed=2301))
 def test_mixed_sweep(bcs, gtype, nc, kernel, inhom, prec, ncomp, seed):
     run_case(bcs, gtype, nc, kernel, inhom, prec, seed=seed, ncomp=ncomp)
+
+
+# ------------------------------------------------ derivatives of mixed plans
+DERIV_CASES = []
+for bcs in PAIRS:
+    for gtype in ("regular", "staggered"):
+        for kernel, inhom, diff in (("ps", False, "grad"), ("fd2", False, "nabla"), ("fd2", True, "grad"),
+                                    ("ps", False, "curl")):
+            for prec in ("f64", "f32"):
+                DERIV_CASES.append((bcs, gtype, [12, 10], kernel, inhom, diff, prec, 1))
+for bcs in TRIPLES:
+    for gtype in ("regular", "staggered"):
+        for kernel, inhom, diff, ncomp in (("ps", False, "grad", 1), ("fd2", False, "curl", 3),
+                                           ("ps", False, "div", 3), ("ps", False, "nabla", 3),
+                                           ("fd2", True, "grad", 1)):
+            for prec in ("f64", "f32"):
+                DERIV_CASES.append((bcs, gtype, [12, 10, 9], kernel, inhom, diff, prec, ncomp))
+
+
+@pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,diff,prec,ncomp", DERIV_CASES)
+def test_mixed_derivatives(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp):
+    import oracle
+    import torch
+    from paper_2301_01145_amd import Solver
+    nd = len(nc)
+    print(f"mixed deriv {bcs} {gtype} {nc} {kernel} inhom={inhom} {diff} {prec} ncomp={ncomp}", flush=True)
+    f, faces = mixed_input(bcs, gtype, nc, ncomp, inhom, prec, seed=173 + nd)
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    s = Solver(list(bcs), gtype, nc, LO[:nd], HI[:nd], kernel=kernel, diff=diff, dtype=dtype, ncomp=ncomp,
+               inhomogeneous=inhom)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+    fin = [dev(f[c]) for c in range(3)] if ncomp == 3 else dev(f)
+    psi, der = s.solve(fin, {k: dev(v) for k, v in faces.items()} if faces else None)
+    torch.cuda.synchronize()
+    got = np.stack([p.double().cpu().numpy() for p in psi]) if ncomp == 3 else psi[0].double().cpu().numpy()
+    ref, rd = oracle.solve(list(bcs), gtype, nc, LO[:nd], HI[:nd], f, operator=kernel, diff=diff, faces=faces)
+    check(got, ref, prec, "psi")
+    assert len(der) == len(rd)
+    for a in range(len(rd)):
+        check(der[a].double().cpu().numpy(), rd[a], prec, f"{diff} {a}")
+    s.close()
+
+
+@pytest.mark.parametrize("bcs", [["dirichlet", "neumann", "dirichlet"], ["neumann", "dirichlet", "neumann"]])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mixed_derivatives_wavefront_matches_general(bcs, prec, monkeypatch):
+    # Dirichlet / Neumann mixes at power-of-two transform lengths: the series
+    # derivative passes on the wavefront kernels against the general ones
+    import torch
+    from paper_2301_01145_amd import Solver
+    nc = [32, 64, 32]
+    f, _ = mixed_input(bcs, "staggered", nc, 1, False, prec, seed=179)
+    dtype = torch.float32 if prec == "f32" else torch.float64
+
+    def run():
+        s = Solver(bcs, "staggered", nc, LO, HI, kernel="ps", diff="grad", dtype=dtype)
+        psi, der = s.solve(torch.as_tensor(f, dtype=dtype, device="cuda"))
+        torch.cuda.synchronize()
+        out = [d.double().cpu().numpy() for d in der]
+        s.close()
+        return out
+
+    fast = run()
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen = run()
+    for a in range(3):
+        check(fast[a], gen[a], prec, f"d/dx{a}")

@@ -88,19 +88,30 @@ def solve(bc, grid_type, nc, lo, hi, f, operator="ps", diff="none",
     lengths = [float(hi[a]) - float(lo[a]) for a in range(nd)]
     f = np.asarray(f, dtype=np.float64)
     if isinstance(bc, (list, tuple)):
-        # a condition per axis (bounded.solve_mixed); derivatives of
-        # homogeneous solves without a free axis, per axis by its own series
-        # (bounded.mixed_derivative)
+        # a condition per axis (bounded.solve_mixed, bounded.solve_semi);
+        # derivatives of homogeneous solves per bounded axis by its own series
+        # (bounded.mixed_derivative), along a free axis by the kernel's
+        # derivative; with boundary values by FD2 differences
         bcs = list(bc)
-        if diff != "none" and ("unbounded" in bcs or (faces and diff == "nabla")):
-            raise NotImplementedError("mixed-boundary derivatives: no free axis; no NABLA with boundary values")
+        free = "unbounded" in bcs
+        if diff != "none" and ((free and (faces or diff == "nabla")) or (faces and diff == "nabla")):
+            raise NotImplementedError("mixed-boundary derivatives: no NABLA with boundary values or a free "
+                                      "axis; free-axis plans homogeneous")
         vector = f.ndim == nd + 1
         comps = [f[c] for c in range(f.shape[0])] if vector else [f]
         solver = bounded.solve_semi if "unbounded" in bcs else bounded.solve_mixed
         psi = [solver(c, bcs, grid_type, operator, lengths, hs,
                       (faces[i] if (faces and vector) else faces))
                for i, c in enumerate(comps)]
-        if faces and diff != "none":
+        if free and diff != "none":
+            # semi-unbounded: bounded axes by their series, the free axis by the
+            # convolution with the kernel's derivative (bounded.solve_semi)
+            u = bcs.index("unbounded")
+            dfree = [bounded.solve_semi(c, bcs, grid_type, operator, lengths, hs, None, free_derivative=True)
+                     for c in comps]
+            d1 = lambda c, a: (dfree[c] if a == u else
+                               bounded.mixed_derivative(psi[c], bcs, grid_type, nc, lengths, a, 1))
+        elif faces and diff != "none":
             # boundary values: FD2 differences per axis (bounded.fd_gradient_mixed)
             face_c = (lambda c: faces[c]) if vector else (lambda c: faces)
             grads = [bounded.fd_gradient_mixed(psi[c], bcs, grid_type, hs, face_c(c)) for c in range(len(psi))]

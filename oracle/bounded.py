@@ -389,9 +389,21 @@ def helmholtz_kernel_1d(kappa, x):
     return np.where(kappa > 0.0, -np.exp(-safe * x) / (2.0 * safe), 0.5 * x)
 
 
-def solve_semi(f, bcs, grid, operator, lengths, hs, faces=None):
+def helmholtz_kernel_1d_derivative(kappa, x):
+    """d/dx of helmholtz_kernel_1d: sign(x) exp(-kappa |x|) / 2 (sign(x) / 2
+    for kappa = 0), 0 at x = 0 (the mean of its one-sided limits, so that the
+    sampled convolution stays second order across the jump)."""
+    x = np.asarray(x, dtype=np.float64)
+    kappa = np.asarray(kappa, dtype=np.float64)
+    return 0.5 * np.sign(x) * np.exp(-kappa * np.abs(x))
+
+
+def solve_semi(f, bcs, grid, operator, lengths, hs, faces=None, free_derivative=False):
     """solve_mixed with one axis "unbounded": that axis is convolved with the
-    1D Helmholtz Green's function of each bounded mode (doubled to M = 2 n)."""
+    1D Helmholtz Green's function of each bounded mode (doubled to M = 2 n).
+    free_derivative: d psi / d x_u instead, the convolution with the kernel's
+    derivative (odd: sampled as sign(m) G'(|m| H) on the doubled axis, with
+    the entry m = n, which no output in the window reads, set to 0)."""
     f = np.asarray(f, dtype=np.float64)
     nd = f.ndim
     u = bcs.index("unbounded")
@@ -423,7 +435,12 @@ def solve_semi(f, bcs, grid, operator, lengths, hs, faces=None):
     kappa = np.sqrt(np.maximum(-lam, 0.0))
     gshape = [1] * nd
     gshape[u] = M
-    g_ext = helmholtz_kernel_1d(kappa, dist.reshape(gshape))  # broadcast over the bounded modes
+    if free_derivative:
+        signed = np.where(m < n, m, m - M) * hs[u]
+        signed[n] = 0.0
+        g_ext = helmholtz_kernel_1d_derivative(kappa, signed.reshape(gshape))
+    else:
+        g_ext = helmholtz_kernel_1d(kappa, dist.reshape(gshape))  # broadcast over the bounded modes
     pad = [(0, 0)] * nd
     pad[u] = (0, M - n)
     conv = np.fft.ifft(np.fft.fft(np.pad(fhat, pad), axis=u) * np.fft.fft(g_ext, axis=u), axis=u)

@@ -347,3 +347,12 @@ def test_mixed_periodic_derivative_sign_is_caught(monkeypatch):
 
     monkeypatch.setattr(bounded, "periodic_derivative", wrong)
     _fails(pm.test_mixed_gradient_and_laplacian_of_eigenmodes, ["periodic", "dirichlet"], "staggered", "ps")
+
+
+def test_semi_derivative_kernel_sign_is_caught(monkeypatch):
+    # the odd kernel G' of the free-axis derivative with the wrong sign
+    import test_oracle_semi as ps
+    orig = bounded.helmholtz_kernel_1d_derivative
+    monkeypatch.setattr(bounded, "helmholtz_kernel_1d_derivative", lambda kappa, x: -orig(kappa, x))
+    _fails(ps.test_semi_gradient_eigenfunction_times_direct_sums, ["unbounded", "periodic"], "staggered")
+    _fails(ps.test_semi_free_derivative_second_order, "dirichlet")

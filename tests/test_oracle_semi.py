@@ -191,3 +191,81 @@ def test_semi_second_order_along_the_free_axis(other):
         errs.append(np.max(np.abs(psi - ref)) / np.max(np.abs(ref)))
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
     assert errs[2] < 5e-3
+
+
+@pytest.mark.parametrize("bcs", SEMI)
+@pytest.mark.parametrize("gtype", ["regular", "staggered"])
+def test_semi_gradient_eigenfunction_times_direct_sums(bcs, gtype):
+    # psi = phi_B(x_B) conv(x_u): d/dx_b psi = phi_B' conv, d/dx_u psi = phi_B conv'
+    # with conv' the direct sum of the profile against G' (0 at distance 0);
+    # every eigenvalue here is nonzero, so kappa > 0
+    nd = len(bcs)
+    u = bcs.index("unbounded")
+    nc = [12, 10, 9][:nd]
+    lo, hi = LO[:nd], HI[:nd]
+    xs_out = [grid.positions(bcs[a], gtype, lo[a], hi[a], nc[a]) for a in range(nd)]
+    xs_in = [x[1:-1] if (bcs[a] == "dirichlet" and gtype == "regular") else x for a, x in enumerate(xs_out)]
+    prof = np.random.default_rng(19).normal(size=len(xs_in[u]))
+    f_in = np.ones([len(x) for x in xs_in])
+    facs, dfacs = [], []
+    lam = 0.0
+    for a in range(nd):
+        view = [1] * nd
+        view[a] = -1
+        if a == u:
+            f_in = f_in * prof.reshape(view)
+            facs.append(None)
+            dfacs.append(None)
+            continue
+        m = 1 + a % 2
+        vi, la = _eigenfunction(bcs[a], m, xs_in[a], lo[a], hi[a] - lo[a])
+        f_in = f_in * vi.reshape(view)
+        t = (xs_out[a] - lo[a]) / (hi[a] - lo[a])
+        L = hi[a] - lo[a]
+        if bcs[a] == "dirichlet":
+            v, dv = np.sin(np.pi * m * t), np.pi * m / L * np.cos(np.pi * m * t)
+        elif bcs[a] == "neumann":
+            v, dv = np.cos(np.pi * m * t), -np.pi * m / L * np.sin(np.pi * m * t)
+        else:
+            v, dv = np.cos(2 * np.pi * m * t + 0.7), -2 * np.pi * m / L * np.sin(2 * np.pi * m * t + 0.7)
+        facs.append(v.reshape(view))
+        dfacs.append(dv.reshape(view))
+        lam += la
+    kappa = math.sqrt(-lam)
+    xu = xs_in[u]
+    hu = grid.spacing(lo[u], hi[u], nc[u])
+    conv = np.array([hu * np.sum(bounded.helmholtz_kernel_1d(kappa, xu[i] - xu) * prof) for i in range(len(xu))])
+    # G'(x) = -kappa sign(x) G(x) for kappa > 0, from the pinned kernel itself
+    dconv = np.array([hu * np.sum(-kappa * np.sign(xu[i] - xu) * bounded.helmholtz_kernel_1d(kappa, xu[i] - xu) * prof)
+                      for i in range(len(xu))])
+    view = [1] * nd
+    view[u] = -1
+    _, der = oracle.solve(bcs, gtype, nc, lo, hi, f_in, operator="ps", diff="grad")
+    for g in range(nd):
+        ref = (dconv if g == u else conv).reshape(view) * 1.0
+        for a in range(nd):
+            if a != u:
+                ref = ref * (dfacs[a] if a == g else facs[a])
+        assert der[g].shape == ref.shape
+        assert np.max(np.abs(der[g] - ref)) <= 1e-11 * np.max(np.abs(ref)), g
+
+
+@pytest.mark.parametrize("other", ["dirichlet", "periodic"])
+def test_semi_free_derivative_second_order(other):
+    # d/dx of the Gaussian-profile solution, against quadrature of G' * g
+    s = 0.12
+    errs = []
+    for n in (32, 64, 128):
+        nc = [n, 8]
+        lo, hi = [-1.0, 0.0], [1.0, 1.0]
+        x = grid.positions("unbounded", "staggered", lo[0], hi[0], n)
+        y = grid.positions(other, "staggered", lo[1], hi[1], 8)
+        fy, lam = _eigenfunction(other, 1, y, 0.0, 1.0)
+        kappa = math.sqrt(-lam)
+        f = np.exp(-x[:, None] ** 2 / (2 * s * s)) * fy[None, :]
+        _, der = oracle.solve(["unbounded", other], "staggered", nc, lo, hi, f, operator="ps", diff="grad")
+        ref = np.array([integrate.quad(lambda t: 0.5 * math.copysign(1.0, xi - t) * math.exp(-kappa * abs(xi - t))
+                                       * math.exp(-t * t / (2 * s * s)), -1.5, 1.5, points=[xi], limit=200)[0]
+                        for xi in x])[:, None] * fy[None, :]
+        errs.append(np.max(np.abs(der[0] - ref)) / np.max(np.abs(ref)))
+    assert errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs

@@ -174,8 +174,13 @@ hp_status validate(const hp_desc* d) {
     }
     if (nfree == d->ndim) return fail(nullptr, HP_E_ARG, "a plan that is free on every axis is HP_UNBOUNDED");
     if (nfree > 1) return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded plans take one free axis");
-    if (nfree && d->diff != HP_D_NONE)
-      return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded plans take no derivative outputs");
+    // derivatives of a semi-unbounded solve: first derivatives of homogeneous
+    // problems (the free axis's closure for boundary-value differences and
+    // a second-derivative series are not defined here)
+    if (nfree && d->diff == HP_D_NABLA)
+      return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded plans take no NABLA output");
+    if (nfree && d->diff != HP_D_NONE && d->inhomogeneous)
+      return fail(nullptr, HP_E_UNSUPPORTED, "semi-unbounded derivatives need homogeneous boundary values");
   }
   if (d->grid < 0 || d->grid > 1) return fail(nullptr, HP_E_ARG, "bad grid");
   if (d->kernel < 0 || d->kernel > HP_G_SPECTRAL) return fail(nullptr, HP_E_ARG, "bad kernel");
@@ -622,9 +627,14 @@ hp_status setup_problem(hp_plan p, Problem& P) {
       if (nb > 1) P.g_s[b[1]] = (long long)K * n1;
       HP_TRY(dev_alloc(p, (size_t)K * n1 * n2 * es, &P.green));
       HP_HIP(p, launch_semi_green(P.green, P.lam[b[0]], n1, nb > 1 ? P.lam[b[1]] : nullptr, n2, M,
-                                  P.h[u], P.norm * P.h[u] / (double)M, p->prec, p->stream));
+                                  P.h[u], P.norm * P.h[u] / (double)M, 0, p->prec, p->stream));
+      if (P.nder) {  // rows of the kernel's derivative, same layout and scale
+        HP_TRY(dev_alloc(p, (size_t)K * n1 * n2 * es, &P.green_odd));
+        HP_HIP(p, launch_semi_green(P.green_odd, P.lam[b[0]], n1, nb > 1 ? P.lam[b[1]] : nullptr, n2,
+                                    M, P.h[u], P.norm * P.h[u] / (double)M, 1, p->prec, p->stream));
+      }
     }
-    if (P.nder) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.grad_s));
+    if (P.nder && P.free_axis < 0) HP_TRY(dev_alloc(p, count_elems(P.nout, P.nd) * es, &P.grad_s));
     // second terms of DIV (d_y psi_y, d_z psi_z) and of the 3D curl, added
     // into the outputs at the end of the solve
     const int ntmp = d.diff == HP_D_DIV ? 2 : (d.diff == HP_D_CURL && P.nd == 3 ? 3 : 0);
@@ -925,6 +935,77 @@ hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
   return HP_OK;
 }
 
+// The derivative terms of every operator on the real-to-real paths: component
+// `comp` contributes d psi_comp / d x_axis (axis -1: NABLA) times `sign` to
+// slot `dst` (an output, or a temporary added into an output at the end).
+// With boundary values the derivatives are differences of psi taken after the
+// solve (hp_solve, launch_fd_deriv), not series terms: no terms.
+struct DerivTerm {
+  int comp, axis;
+  void* dst;
+  double sign;
+};
+
+std::vector<DerivTerm> derivative_terms(const Problem& P) {
+  const hp_desc& d = P.d;
+  const int nd = P.nd;
+  std::vector<DerivTerm> terms;
+  switch (d.inhomogeneous ? HP_D_NONE : d.diff) {
+    case HP_D_GRAD:
+      for (int g = 0; g < nd; ++g) terms.push_back({0, g, P.der[g], 1.0});
+      break;
+    case HP_D_NABLA:
+      for (int c = 0; c < P.ncomp; ++c) terms.push_back({c, -1, P.der[c], 1.0});
+      break;
+    case HP_D_DIV:  // d_x psi_x into the output, d_y psi_y and d_z psi_z added
+      terms.push_back({0, 0, P.der[0], 1.0});
+      terms.push_back({1, 1, P.dtmp[0], 1.0});
+      terms.push_back({2, 2, P.dtmp[1], 1.0});
+      break;
+    case HP_D_CURL:
+      if (nd == 2) {  // (d_y psi, -d_x psi)
+        terms.push_back({0, 1, P.der[0], 1.0});
+        terms.push_back({0, 0, P.der[1], -1.0});
+      } else {  // u_x = d_y psi_z - d_z psi_y, u_y = d_z psi_x - d_x psi_z, u_z = d_x psi_y - d_y psi_x
+        terms.push_back({0, 1, P.dtmp[2], -1.0});
+        terms.push_back({0, 2, P.der[1], 1.0});
+        terms.push_back({1, 0, P.der[2], 1.0});
+        terms.push_back({1, 2, P.dtmp[0], -1.0});
+        terms.push_back({2, 0, P.dtmp[1], -1.0});
+        terms.push_back({2, 1, P.der[0], 1.0});
+      }
+      break;
+    default:
+      break;
+  }
+  return terms;
+}
+
+// DIV / 3D CURL: the second terms added into the outputs (elementwise)
+void add_second_terms(const Problem& P, size_t es, std::vector<PassRec>& out) {
+  if (P.d.inhomogeneous) return;
+  auto add_into = [&](void* dst, const void* t0, const void* t1) {
+    PassArgs a{};
+    a.ax_j = a.ax_p = a.ax_o = -1;
+    a.No = a.Np = 1;
+    a.n_in = a.n_out = 1;
+    a.fast = FAST_ADD;
+    a.out[0] = dst;
+    a.in[0] = t0;
+    a.in[1] = t1;
+    long long cnt = 1;
+    for (int b = 0; b < P.nd; ++b) cnt *= P.nout[b];
+    a.gp_ext[0] = (int)cnt;
+    a.gp_ext[1] = a.gp_ext[2] = 1;
+    PassRec r{a, 1};
+    r.bytes = (double)cnt * (double)es * (t1 ? 4.0 : 3.0);
+    out.push_back(r);
+  };
+  if (P.d.diff == HP_D_DIV) add_into(P.der[0], P.dtmp[0], P.dtmp[1]);
+  if (P.d.diff == HP_D_CURL && P.nd == 3)
+    for (int c = 0; c < 3; ++c) add_into(P.der[c], P.dtmp[c], nullptr);
+}
+
 hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   const hp_desc& d = P.d;
   const int nd = P.nd;
@@ -1087,47 +1168,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     }
     return HP_OK;
   };
-  // The derivative terms of every operator: component `comp` contributes
-  // d psi_comp / d x_axis (axis -1: NABLA) times `sign` to slot `dst` (an
-  // output, or a temporary added into an output at the end).  Axis 0 and
-  // NABLA terms are taken before the sandwich from the transformed source,
-  // the other axes after it from psi's array.
-  struct Term {
-    int comp, axis;
-    void* dst;
-    double sign;
-  };
-  std::vector<Term> terms;
-  // with boundary values the derivatives are differences of psi taken after
-  // the solve (hp_solve, launch_fd_deriv), not series terms
-  switch (d.inhomogeneous ? HP_D_NONE : d.diff) {
-    case HP_D_GRAD:
-      for (int g = 0; g < nd; ++g) terms.push_back({0, g, P.der[g], 1.0});
-      break;
-    case HP_D_NABLA:
-      for (int c = 0; c < P.ncomp; ++c) terms.push_back({c, -1, P.der[c], 1.0});
-      break;
-    case HP_D_DIV:  // d_x psi_x into the output, d_y psi_y and d_z psi_z added
-      terms.push_back({0, 0, P.der[0], 1.0});
-      terms.push_back({1, 1, P.dtmp[0], 1.0});
-      terms.push_back({2, 2, P.dtmp[1], 1.0});
-      break;
-    case HP_D_CURL:
-      if (nd == 2) {  // (d_y psi, -d_x psi)
-        terms.push_back({0, 1, P.der[0], 1.0});
-        terms.push_back({0, 0, P.der[1], -1.0});
-      } else {  // u_x = d_y psi_z - d_z psi_y, u_y = d_z psi_x - d_x psi_z, u_z = d_x psi_y - d_y psi_x
-        terms.push_back({0, 1, P.dtmp[2], -1.0});
-        terms.push_back({0, 2, P.der[1], 1.0});
-        terms.push_back({1, 0, P.der[2], 1.0});
-        terms.push_back({1, 2, P.dtmp[0], -1.0});
-        terms.push_back({2, 0, P.dtmp[1], -1.0});
-        terms.push_back({2, 1, P.der[0], 1.0});
-      }
-      break;
-    default:
-      break;
-  }
+  const std::vector<DerivTerm> terms = derivative_terms(P);
   // before the sandwich: the terms along axis 0 and NABLA, from the source
   // transformed along every axis (one more forward pass along axis 0, out of place)
   auto pre_terms = [&](int comp) -> hp_status {
@@ -1257,24 +1298,7 @@ hp_status passes_bounded(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       out.push_back({a, 1});
     }
   }
-  // DIV / 3D CURL: the second terms added into the outputs (elementwise)
-  auto add_into = [&](void* dst, const void* t0, const void* t1) {
-    PassArgs a = base();
-    a.fast = FAST_ADD;
-    a.out[0] = dst;
-    a.in[0] = t0;
-    a.in[1] = t1;
-    long long cnt = 1;
-    for (int b = 0; b < nd; ++b) cnt *= P.nout[b];
-    a.gp_ext[0] = (int)cnt;
-    a.gp_ext[1] = a.gp_ext[2] = 1;
-    PassRec r{a, 1};
-    r.bytes = (double)cnt * (double)es * (t1 ? 4.0 : 3.0);
-    out.push_back(r);
-  };
-  if (d.diff == HP_D_DIV) add_into(P.der[0], P.dtmp[0], P.dtmp[1]);
-  if (d.diff == HP_D_CURL && nd == 3)
-    for (int c = 0; c < 3; ++c) add_into(P.der[c], P.dtmp[c], nullptr);
+  add_second_terms(P, es, out);
   if (bounded_fast_ok(p, P, L))
     for (size_t i = first_pass; i < out.size(); ++i) HP_TRY(to_fast_r2r(p, out[i].a));
   return HP_OK;
@@ -1857,8 +1881,10 @@ hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     return a;
   };
   // pencils along axis j: the tile runs along the last of the other axes
-  // (contiguous unless j is the last axis, whose pencils are contiguous)
-  auto geom = [&](PassArgs& a, int j, bool from_input) {
+  // (contiguous unless j is the last axis, whose pencils are contiguous);
+  // extents ext (default: the unknowns)
+  auto geom = [&](PassArgs& a, int j, bool from_input, const int* ext = nullptr) {
+    if (!ext) ext = P.n;
     const long long* is = from_input ? fs : ws;
     int others[2], no = 0;
     for (int b = 0; b < nd; ++b)
@@ -1868,13 +1894,13 @@ hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     a.out_sj = ws[j];
     const int pa = others[no - 1];
     a.ax_p = pa;
-    a.Np = P.n[pa];
+    a.Np = ext[pa];
     a.in_sp = is[pa];
     a.out_sp = ws[pa];
     if (no == 2) {
       const int oa = others[0];
       a.ax_o = oa;
-      a.No = P.n[oa];
+      a.No = ext[oa];
       a.in_so = is[oa];
       a.out_so = ws[oa];
     }
@@ -1896,6 +1922,125 @@ hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
     out.push_back({a, 1});
     return HP_OK;
   };
+  // one real-to-real pass along j, in place on the view at `view` (extents ext)
+  auto oneway_view = [&](void* view, int j, int x, const int* ext) -> hp_status {
+    PassArgs a = base();
+    a.kind = PK_ONEWAY;
+    a.xf = x;
+    a.L = L[j]; a.n = ext[j]; a.nin = a.nout = ext[j];
+    a.in[0] = view;
+    a.out[0] = view;
+    geom(a, j, false, ext);
+    for (int b = 0; b < 3; ++b) a.nunk[b] = b < nd ? ext[b] : 0;
+    HP_TRY(finish_pass(p, a, j == nd - 1 ? 16 : 32, 2, 0, 1));
+    const void* q;
+    HP_TRY(quarter(p, a.n, &q));
+    a.qtw = q;
+    out.push_back({a, 1});
+    return HP_OK;
+  };
+  // the free-axis sandwich on the view at `v`: Green's rows, or the rows of
+  // the kernel's derivative
+  auto sandwich = [&](void* v, bool odd) -> hp_status {
+    PassArgs a = base();
+    a.kind = PK_SANDWICH;
+    a.xf = X_PAIR_F;
+    a.xb = X_PAIR_B;
+    a.L = L[u]; a.n = P.n[u]; a.nin = a.nout = P.n[u];
+    a.in[0] = v;
+    a.out[0] = v;
+    geom(a, u, false);
+    a.mult = odd ? M_GREEN_ROWS_ODD : M_GREEN_ROWS;
+    a.green = odd ? P.green_odd : P.green;
+    for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
+    a.diff = D_NONE;
+    HP_TRY(finish_pass(p, a, 16, 2, 0, 5));
+    out.push_back({a, 1});
+    return HP_OK;
+  };
+  // elementwise prep into the whole output array `dst` (zero outside the
+  // active view off / len): along a bounded axis g the series derivative of
+  // psi's coefficients src (the derivative's basis and index shift, times
+  // sign), or with g < 0 a copy of src times sign
+  auto prep = [&](const void* src, const long long* is, void* dst, int g, const int* off, const int* len,
+                  double sign) {
+    PassArgs a = base();
+    a.fast = FAST_GRAD_PREP;
+    a.ax_j = g;
+    a.diff = D_NONE;
+    a.in[0] = src;
+    a.out[0] = dst;
+    double cnt_in = 1.0, cnt_out = 1.0;
+    for (int b = 0; b < 3; ++b) {
+      a.gp_ext[b] = b < nd ? P.nout[b] : 1;
+      a.gp_off[b] = off[b];
+      a.gp_len[b] = len[b];
+      a.gp_is[b] = b < nd ? is[b] : 0;
+      a.gp_os[b] = b < nd ? ws[b] : 0;
+      a.nunk[b] = b < nd ? P.n[b] : 1;
+      a.lam[b] = nullptr;
+      const int bb = b < nd ? axis_bc(d, b) : HP_NEUMANN;
+      a.gp_basis[b] = bb == HP_PERIODIC ? 2 : (bb == HP_DIRICHLET ? 0 : 1);
+      a.kc[b] = 0.0;
+      if (b < nd) { cnt_in *= P.n[b]; cnt_out *= P.nout[b]; }
+    }
+    a.gp_eigen = 0;
+    a.gp_shift = 0;
+    a.gp_scale = sign;
+    if (g >= 0) {
+      const int bcg = axis_bc(d, g);
+      if (bcg == HP_PERIODIC) {
+        a.gp_scale = sign * 2.0 * M_PI / P.len[g];
+      } else {
+        const bool dir = bcg == HP_DIRICHLET;
+        a.gp_shift = dir ? -1 : 1;
+        a.gp_scale = sign * (dir ? 1.0 : -1.0) * M_PI / P.len[g];
+      }
+    }
+    a.norm = P.norm;
+    PassRec r{a, 1};
+    r.bytes = (cnt_in + cnt_out) * (double)es;
+    out.push_back(r);
+  };
+  // Derivatives of homogeneous solves.  Along a bounded axis g: after the
+  // sandwich psi's array holds the bounded coefficients (the free axis
+  // physical); the prep writes the derivative series along g and backward
+  // transforms along the bounded axes (the other parity's along g) evaluate
+  // it.  Along the free axis: the source copied into the output (times the
+  // term's sign), forward bounded transforms, the sandwich with the odd
+  // kernel's rows and the backward transforms.
+  const std::vector<DerivTerm> terms = derivative_terms(P);
+  auto bounded_term = [&](int comp, int g, void* dst, double sign) -> hp_status {
+    const int bcg = axis_bc(d, g);
+    const bool dir = bcg == HP_DIRICHLET, reg = d.grid == HP_REGULAR;
+    int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
+    for (int b = 0; b < nd; ++b) { off[b] = (dmask >> b) & 1; len[b] = P.n[b]; }
+    int xd;
+    if (bcg == HP_PERIODIC) xd = X_DHT;
+    else if (dir && reg) { xd = X_DCT1; len[g] = P.n[g] + 2; off[g] = 0; }  // n + 2 nodes
+    else if (dir) xd = X_DCT3;
+    else if (reg) { xd = X_DST1; len[g] = P.n[g] - 2; off[g] = 1; }   // interior nodes
+    else xd = X_DST3;
+    prep(work(comp), ws, dst, g, off, len, sign);
+    long long vo = 0;
+    for (int b = 0; b < nd; ++b) vo += (long long)off[b] * ws[b];
+    void* view = (void*)((char*)dst + vo * (long long)es);
+    for (int c = nd - 1; c >= 0; --c)
+      if (c != u) HP_TRY(oneway_view(view, c, c == g ? xd : xb[c], len));
+    return HP_OK;
+  };
+  auto free_term = [&](int comp, void* dst, double sign) -> hp_status {
+    int off[3] = {0, 0, 0}, len[3] = {1, 1, 1};
+    for (int b = 0; b < nd; ++b) { off[b] = (dmask >> b) & 1; len[b] = P.n[b]; }
+    prep(P.in[comp], fs, dst, -1, off, len, sign);
+    void* view = (void*)((char*)dst + woff * es);
+    for (int j = nd - 1; j >= 0; --j)
+      if (j != u) HP_TRY(oneway_view(view, j, xf[j], P.n));
+    HP_TRY(sandwich(view, true));
+    for (int j = 0; j < nd; ++j)
+      if (j != u) HP_TRY(oneway_view(view, j, xb[j], P.n));
+    return HP_OK;
+  };
   for (int comp = 0; comp < P.ncomp; ++comp) {
     bool first = true;
     for (int j = nd - 1; j >= 0; --j) {
@@ -1903,27 +2048,18 @@ hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       HP_TRY(oneway(comp, j, xf[j], first));
       first = false;
     }
-    {
-      PassArgs a = base();
-      a.kind = PK_SANDWICH;
-      a.xf = X_PAIR_F;
-      a.xb = X_PAIR_B;
-      a.L = L[u]; a.n = P.n[u]; a.nin = a.nout = P.n[u];
-      a.in[0] = work(comp);
-      a.out[0] = work(comp);
-      geom(a, u, false);
-      a.mult = M_GREEN_ROWS;
-      a.green = P.green;
-      for (int b = 0; b < 3; ++b) a.g_s[b] = P.g_s[b];
-      a.diff = D_NONE;
-      HP_TRY(finish_pass(p, a, 16, 2, 0, 5));
-      out.push_back({a, 1});
-    }
+    HP_TRY(sandwich(work(comp), false));
+    // bounded-axis terms from psi's array before the backward passes change it
+    for (const DerivTerm& t : terms)
+      if (t.comp == comp && t.axis != u) HP_TRY(bounded_term(comp, t.axis, t.dst, t.sign));
     for (int j = 0; j < nd; ++j) {
       if (j == u) continue;
       HP_TRY(oneway(comp, j, xb[j], false));
     }
+    for (const DerivTerm& t : terms)
+      if (t.comp == comp && t.axis == u) HP_TRY(free_term(comp, t.dst, t.sign));
   }
+  add_second_terms(P, es, out);
   return HP_OK;
 }
 

@@ -1050,7 +1050,8 @@ __global__ void __launch_bounds__(256) k_grad_prep(PassArgs a) {
       // gradient: +-(pi kappa / L) one index over (Hartley: -(2 pi k~ / L)
       // from the mirrored index); NABLA (diff = D_NABLA): -sum_b w_b^2 on the
       // same index
-      double m = a.diff == D_NABLA ? -a.gp_scale * w2 : a.gp_scale * kap;
+      // (ax_j < 0 otherwise: a plain copy times gp_scale)
+      double m = a.diff == D_NABLA ? -a.gp_scale * w2 : (a.ax_j < 0 ? a.gp_scale : a.gp_scale * kap);
       if (a.gp_eigen) m = lam == 0.0 ? 0.0 : m * a.norm / lam;
       v = (T)m * src[so];
     }

@@ -33,7 +33,10 @@ enum MultKind : int { M_NONE = 0, M_EIGEN = 1, M_GREEN = 2,
                       // Helmholtz Green's spectrum per bounded mode of the
                       // pencil (green[m g_s[ax_j] + p g_s[ax_p] + o g_s[ax_o]],
                       // m <= L / 2), paired real pencils
-                      M_GREEN_ROWS = 3 };
+                      M_GREEN_ROWS = 3,
+                      // the same for the free-axis derivative: rows b of the
+                      // odd kernel's spectrum i b(m) (b real, odd in m)
+                      M_GREEN_ROWS_ODD = 4 };
 // Derivative coupling inside the sandwich pass (D_ADJ_*: the transposes used
 // by the adjoint solve).
 enum DiffKind : int { D_NONE = 0, D_GRAD = 1, D_CURL = 2, D_ADJ_GRAD = 3, D_ADJ_CURL = 4,
@@ -114,6 +117,7 @@ struct PassArgs {
   // at -s (mod nunk), scaled by -gp_scale times s's signed wavenumber.  Other
   // axes read src = s (strides gp_is, extents nunk).  With gp_eigen the value
   // is divided by sum_b lam[b][src_b] / norm (0 where that sum is 0).
+  // ax_j < 0 without D_NABLA: a copy, src = s on every axis, times gp_scale.
   // Elements that are not active, or whose source lies outside, are 0.
   int gp_ext[3], gp_off[3], gp_len[3];
   int gp_shift, gp_basis[3], gp_eigen;
@@ -214,9 +218,11 @@ hipError_t launch_green_eval(double* g, const int M[3], const double h[3], const
 // Rows of the free-axis Green's spectrum of a semi-unbounded plan: out[m + K
 // (i1 + n1 i2)], K = M / 2 + 1, is scale times the DFT bin m of the 1D
 // Helmholtz kernel sampled on the doubled axis (spacing h, M points, mirrored)
-// for kappa^2 = -(lam1[i1] + lam2[i2]) (lam2 may be null, n2 = 1).
+// for kappa^2 = -(lam1[i1] + lam2[i2]) (lam2 may be null, n2 = 1).  odd: the
+// kernel's derivative instead (odd samples, 0 at distances 0 and n h), whose
+// bin m is i times the stored value.
 hipError_t launch_semi_green(void* out, const double* lam1, int n1, const double* lam2, int n2,
-                             int M, double h, double scale, int prec, hipStream_t s);
+                             int M, double h, double scale, int odd, int prec, hipStream_t s);
 hipError_t launch_octant(const double* spec, const int M[3], double scale, void* out,
                          int prec, hipStream_t s);
 // Write the boundary nodes of the REGULAR Dirichlet axes (bit a of `axes`)

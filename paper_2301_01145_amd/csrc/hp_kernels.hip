@@ -608,14 +608,17 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
       __syncthreads();
     }
   }
-  if (a.mult == M_GREEN_ROWS) {
+  if (a.mult == M_GREEN_ROWS || a.mult == M_GREEN_ROWS_ODD) {
     // Paired real pencils 2f, 2f + 1 of the tile belong to different bounded
     // modes, so they take different real-even Green's rows G_a, G_b.  The FFT
     // Z of a + ib holds the Hermitian spectra X_a = (Z_m + conj Z_-m) / 2 and
     // X_b = (Z_m - conj Z_-m) / 2i; G_a X_a + i G_b X_b recombines to
     // Z'_m = A Z_m + B conj Z_-m with A = (G_a + G_b) / 2, B = (G_a - G_b) / 2,
-    // the same A, B at -m.  One thread per bin pair (m, L - m).
+    // the same A, B at -m.  One thread per bin pair (m, L - m).  Odd rows
+    // (bins i b_a, i b_b, b odd in m): Z'_m = i (A Z_m + B conj Z_-m) and
+    // Z'_-m = -i (A Z_-m + B conj Z_m), A, B from b_a, b_b at m.
     const int half = L / 2;
+    const bool odd = a.mult == M_GREEN_ROWS_ODD;
     auto row = [&](int p, int m) -> T {
       p = min(p, a.Np - 1);
       long long off = (long long)m * a.g_s[a.ax_j] + (long long)p * a.g_s[a.ax_p];
@@ -630,8 +633,15 @@ __device__ void sandwich_c2c(const PassArgs& a, unsigned char* smem, const Tile&
       const T A = (T)0.5 * (ga + gb), B = (T)0.5 * (ga - gb);
       C2<T>* z = S + (size_t)f * L;
       const C2<T> zm = z[m], zmm = z[mm];
-      z[m] = cadd(cscale(zm, A), cscale(cconj(zmm), B));
-      if (mm != m) z[mm] = cadd(cscale(zmm, A), cscale(cconj(zm), B));
+      const C2<T> ym = cadd(cscale(zm, A), cscale(cconj(zmm), B));
+      const C2<T> ymm = cadd(cscale(zmm, A), cscale(cconj(zm), B));
+      if (odd) {
+        z[m] = cmuli(ym);
+        if (mm != m) z[mm] = cscale(cmuli(ymm), (T)-1);
+      } else {
+        z[m] = ym;
+        if (mm != m) z[mm] = ymm;
+      }
     }
   } else {
     // multiply by the spectral multiplier
@@ -1194,9 +1204,15 @@ hipError_t launch_octant(const double* spec, const int M[3], double scale, void*
 //   -(1 - s)(1 - q^2) / (2 kappa ((1 - q)^2 + 4 q sin^2(theta / 2))),
 // a sum of positive terms in the denominator (no cancellation).  kappa = 0
 // (G = |x| / 2): h n^2 / 2 at m = 0, else -h (1 - (-1)^m) / (4 sin^2(theta / 2)).
+// odd: G' = sign(x) exp(-kappa |x|) / 2 sampled at j = 1 .. n - 1 and with
+// the opposite sign at M - j (0 at j = 0 and n); its bin m is -i times
+// Im sum_{j=1}^{n-1} z^j, z = q e^{i theta}, a geometric series whose sum
+// (z - s) / (1 - z) gives the stored b(m) (bin = i b):
+//   -q sin(theta) (1 - s) / ((1 - q)^2 + 4 q sin^2(theta / 2)),
+// for kappa = 0 (q = 1) -(1 - (-1)^m) cot(theta / 2) / 2, 0 at m = 0.
 template <typename T>
 __global__ void k_semi_green(T* out, const double* lam1, int n1, const double* lam2, int n2, int M,
-                             double h, double scale) {
+                             double h, double scale, int odd) {
   const int K = M / 2 + 1, n = M / 2;
   const long long total = (long long)K * n1 * n2;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -1208,7 +1224,18 @@ __global__ void k_semi_green(T* out, const double* lam1, int n1, const double* l
     const double sh = sinpi((double)m / (double)M);  // sin(theta / 2)
     const double sgn = (m & 1) ? -1.0 : 1.0;
     double v;
-    if (lam < 0.0) {
+    if (odd) {
+      const double st = sinpi(2.0 * (double)m / (double)M);  // sin(theta)
+      if (lam < 0.0) {
+        const double kappa = sqrt(-lam);
+        const double q = exp(-kappa * h);
+        const double omq = -expm1(-kappa * h);
+        const double s = sgn * exp(-kappa * h * n);
+        v = -q * st * (1.0 - s) / (omq * omq + 4.0 * q * sh * sh);
+      } else {
+        v = m == 0 ? 0.0 : -0.5 * (1.0 - sgn) * cospi((double)m / (double)M) / sh;
+      }
+    } else if (lam < 0.0) {
       const double kappa = sqrt(-lam);
       const double q = exp(-kappa * h);
       const double omq = -expm1(-kappa * h);       // 1 - q
@@ -1225,13 +1252,13 @@ __global__ void k_semi_green(T* out, const double* lam1, int n1, const double* l
 }
 
 hipError_t launch_semi_green(void* out, const double* lam1, int n1, const double* lam2, int n2,
-                             int M, double h, double scale, int prec, hipStream_t s) {
+                             int M, double h, double scale, int odd, int prec, hipStream_t s) {
   if (prec == 0)
     hipLaunchKernelGGL(k_semi_green<float>, dim3(1024), dim3(256), 0, s, (float*)out, lam1, n1, lam2,
-                       n2, M, h, scale);
+                       n2, M, h, scale, odd);
   else
     hipLaunchKernelGGL(k_semi_green<double>, dim3(1024), dim3(256), 0, s, (double*)out, lam1, n1,
-                       lam2, n2, M, h, scale);
+                       lam2, n2, M, h, scale, odd);
   return hipGetLastError();
 }
 

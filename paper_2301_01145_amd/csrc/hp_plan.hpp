@@ -49,6 +49,7 @@ struct Problem {
   double* lam[3] = {};        // eigenvalue tables (bounded)
   void* kvec[3] = {};         // wavenumber tables
   void* green = nullptr;      // Ghat octant
+  void* green_odd = nullptr;  // semi-unbounded derivative: odd-kernel rows
   long long g_s[3] = {0, 0, 0};  // octant strides of i0, i1, k2
   double norm = 1.0;
   std::vector<std::pair<int, int>> slabs;  // kz (first, count) of the free-space y / x passes

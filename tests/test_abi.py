@@ -67,7 +67,10 @@ BAD = [
     (dict(bc=["unbounded", "unbounded"], grid="staggered", nc=[8, 8]), _lib.HP_E_ARG),
     (dict(bc=["unbounded", "unbounded", "neumann"], grid="staggered", nc=[8, 8, 8]), _lib.HP_E_UNSUPPORTED),
     (dict(bc=["periodic", "neumann"], grid="staggered", nc=[8, 8], diff="grad"), None),
-    (dict(bc=["periodic", "unbounded"], grid="staggered", nc=[8, 8], diff="grad"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc=["periodic", "unbounded"], grid="staggered", nc=[8, 8], diff="grad"), None),
+    (dict(bc=["periodic", "unbounded"], grid="staggered", nc=[8, 8], diff="nabla"), _lib.HP_E_UNSUPPORTED),
+    (dict(bc=["dirichlet", "unbounded"], grid="staggered", nc=[8, 8], diff="grad", kernel="fd2",
+          inhomogeneous=True), _lib.HP_E_UNSUPPORTED),
     (dict(bc=["dirichlet", "neumann"], grid="staggered", nc=[8, 8], kernel="ps", inhomogeneous=True),
      _lib.HP_E_UNSUPPORTED),
     (dict(bc=["periodic", "periodic"], grid="staggered", nc=[8, 8], kernel="fd2", inhomogeneous=True),

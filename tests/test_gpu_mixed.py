@@ -11,11 +11,13 @@ oracle, element by element.
 * the zero mode of periodic / Neumann mixes; a 3-component field;
 * GRAD, CURL, DIV and NABLA of mixed plans (series per axis; FD2 differences
   with boundary values), also on the wavefront passes;
-* descriptor rules (derivatives of semi-unbounded plans refused, faces of
+* descriptor rules (NABLA of semi-unbounded plans refused, faces of
   periodic axes);
 * semi-unbounded: three 2D and three 3D axis layouts, both grids, PS and FD2,
   boundary values, prime and power-of-two lengths, the kappa = 0 row, a
-  3-component field, descriptor rules.
+  3-component field, descriptor rules;
+* GRAD, CURL and DIV of semi-unbounded plans (series along the bounded axes,
+  the odd kernel's rows along the free one), the kappa = 0 row included.
 """
 import numpy as np
 import pytest
@@ -157,7 +159,7 @@ def test_mixed_descriptor_rules():
     import ctypes
     import torch
     from paper_2301_01145_amd import HipoissonError, Solver, _lib, make_desc
-    d = make_desc(["periodic", "unbounded"], "staggered", [8, 8], diff="grad")
+    d = make_desc(["periodic", "unbounded"], "staggered", [8, 8], diff="nabla")
     out = ctypes.c_void_p()
     assert _lib.lib().hp_plan_create(ctypes.byref(d), None, ctypes.byref(out)) == _lib.HP_E_UNSUPPORTED
     s = Solver(["periodic", "dirichlet"], "staggered", [8, 8], kernel="fd2", dtype=torch.float64,
@@ -334,12 +336,18 @@ for bcs in TRIPLES:
 
 @pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,diff,prec,ncomp", DERIV_CASES)
 def test_mixed_derivatives(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp):
+    run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=173 + len(nc))
+
+
+def run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed, f=None):
     import oracle
     import torch
     from paper_2301_01145_amd import Solver
     nd = len(nc)
     print(f"mixed deriv {bcs} {gtype} {nc} {kernel} inhom={inhom} {diff} {prec} ncomp={ncomp}", flush=True)
-    f, faces = mixed_input(bcs, gtype, nc, ncomp, inhom, prec, seed=173 + nd)
+    faces = None
+    if f is None:
+        f, faces = mixed_input(bcs, gtype, nc, ncomp, inhom, prec, seed=seed)
     dtype = torch.float32 if prec == "f32" else torch.float64
     s = Solver(list(bcs), gtype, nc, LO[:nd], HI[:nd], kernel=kernel, diff=diff, dtype=dtype, ncomp=ncomp,
                inhomogeneous=inhom)
@@ -380,3 +388,57 @@ def test_mixed_derivatives_wavefront_matches_general(bcs, prec, monkeypatch):
     gen = run()
     for a in range(3):
         check(fast[a], gen[a], prec, f"d/dx{a}")
+
+
+# ----------------------------------------- derivatives of semi-unbounded plans
+SEMI_DERIV_CASES = []
+for bcs in SEMI2:
+    for gtype in ("regular", "staggered"):
+        for kernel, diff in (("ps", "grad"), ("fd2", "curl")):
+            for prec in ("f64", "f32"):
+                SEMI_DERIV_CASES.append((bcs, gtype, [12, 10], kernel, diff, prec, 1))
+for bcs in SEMI3:
+    for gtype in ("regular", "staggered"):
+        for kernel, diff, ncomp in (("ps", "grad", 1), ("fd2", "curl", 3), ("ps", "div", 3)):
+            for prec in ("f64", "f32"):
+                SEMI_DERIV_CASES.append((bcs, gtype, [12, 10, 9], kernel, diff, prec, ncomp))
+
+
+@pytest.mark.parametrize("bcs,gtype,nc,kernel,diff,prec,ncomp", SEMI_DERIV_CASES)
+def test_semi_derivatives(bcs, gtype, nc, kernel, diff, prec, ncomp):
+    run_deriv_case(bcs, gtype, nc, kernel, False, diff, prec, ncomp, seed=181 + len(nc))
+
+
+@pytest.mark.parametrize("bcs,nc", [(["unbounded", "dirichlet"], [7, 13]), (["periodic", "unbounded"], [11, 127]),
+                                    (["neumann", "periodic", "unbounded"], [32, 16, 64])])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_semi_derivative_lengths(bcs, nc, prec):
+    run_deriv_case(bcs, "staggered", nc, "fd2", False, "grad", prec, 1, seed=191)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_semi_derivative_zero_eigenvalue_row(prec):
+    # a source constant along the periodic / Neumann axes: the free-axis
+    # derivative takes only the kappa = 0 row (G' = sign(x) / 2); the others
+    # vanish (to rounding, measured against the free-axis derivative's size)
+    import oracle
+    import torch
+    from paper_2301_01145_amd import Solver
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    nc = [16, 6, 5]
+    bcs = ["unbounded", "periodic", "neumann"]
+    x = np.random.default_rng(193).normal(size=16)
+    f = np.broadcast_to(x[:, None, None], (16, 6, 5)).copy()
+    f = f.astype(np.float32 if prec == "f32" else np.float64).astype(np.float64)
+    s = Solver(bcs, "staggered", nc, LO, HI, kernel="fd2", diff="grad", dtype=dtype)
+    psi, der = s.solve(torch.as_tensor(f, dtype=dtype, device="cuda"))
+    torch.cuda.synchronize()
+    ref, rd = oracle.solve(bcs, "staggered", nc, LO, HI, f, operator="fd2", diff="grad")
+    check(psi[0].double().cpu().numpy(), ref, prec, "psi")
+    d0 = der[0].double().cpu().numpy()
+    check(d0, rd[0], prec, "d/dx0")
+    scale = float(np.max(np.abs(rd[0])))
+    for a in (1, 2):
+        assert np.max(np.abs(rd[a])) <= 1e-13 * scale
+        assert np.max(np.abs(der[a].double().cpu().numpy())) <= TOL[prec][1] * scale, a
+    s.close()

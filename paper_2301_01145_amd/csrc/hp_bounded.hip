@@ -191,18 +191,34 @@ __global__ void __launch_bounds__(64 * kR2RContigWaves) kb_contig(const PassArgs
   const bool faces = has_faces(a);
   const T* in = (const T*)a.in[0];
   const long long ib = (long long)o * a.in_so + (long long)pa * a.in_sp;
-  for (int j = g; j < n; j += G) {
-    T va = (T)0, vb_ = (T)0;
-    if (valid) {
-      va = in[ib + (long long)j * a.in_sj];
-      if (faces) va = (T)((double)va + face_terms<T>(a, j, pa, o));
+  // every load of the pair is issued before the first is used (n <= L/2 + 1,
+  // checked at launch): one memory latency per pass, not one per row
+  constexpr int NJ = (L / 2 + 1 + G - 1) / G;
+  T va[NJ], vbv[NJ];
+  // (unconditional loads from clamped addresses: pencil pa + 1 only where it
+  // exists, rows below n; the conditions apply where the values are kept)
+  const long long ibb = ib + (vb ? a.in_sp : 0);
+#pragma unroll
+  for (int r = 0; r < NJ; ++r) {
+    const long long jo = (long long)min(g + G * r, n - 1) * a.in_sj;
+    va[r] = in[ib + jo];
+    vbv[r] = in[ibb + jo];
+  }
+  if (faces) {
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      const int j = g + G * r;
+      if (j < n && valid) va[r] = (T)((double)va[r] + face_terms<T>(a, j, pa, o));
+      if (j < n && vb) vbv[r] = (T)((double)vbv[r] + face_terms<T>(a, j, pa + 1, o));
     }
-    if (vb) {
-      vb_ = in[ib + a.in_sp + (long long)j * a.in_sj];
-      if (faces) vb_ = (T)((double)vb_ + face_terms<T>(a, j, pa + 1, o));
+  }
+#pragma unroll
+  for (int r = 0; r < NJ; ++r) {
+    const int j = g + G * r;
+    if (j < n) {
+      R[j] = valid ? va[r] : (T)0;
+      R[n + j] = vb ? vbv[r] : (T)0;
     }
-    R[j] = va;
-    R[n + j] = vb_;
   }
   wave_sync();
   T* out = (T*)a.out[0];
@@ -259,33 +275,28 @@ __global__ void __launch_bounds__(64 * W) kb_strided(const PassArgs a) {
     const int o = tt / tiles_p, p0 = (tt % tiles_p) * P;
     const int np = min(P, a.Np - p0);
     const long long ib = (long long)o * a.in_so + (long long)p0 * a.in_sp;
+    // unconditional loads from clamped (in-tile) addresses: no branches
+    // between the loads, so all of them are in flight at once; put() drops
+    // the rows beyond n and zeroes the pencils beyond np
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int e = threadIdx.x + r * NT;
       const int j = e / P, c = e - (e / P) * P;
-      pre[r] = (j < n && c < np) ? in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
+      pre[r] = in[ib + (long long)min(j, n - 1) * a.in_sj + (long long)min(c, np - 1) * a.in_sp];
     }
   };
-  auto put = [&]() {
+  auto put = [&](int tt) {
+    const int np = min(P, a.Np - (tt % tiles_p) * P);
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int e = threadIdx.x + r * NT;
       const int j = e / P, c = e - (e / P) * P;
-      if (j < n) tile[j * TS + c] = pre[r];
+      if (j < n) tile[j * TS + c] = c < np ? pre[r] : (T)0;
     }
   };
-  if constexpr (PERS) {
-    fetch(t);
-    put();
-  } else {
-    const int o = t / tiles_p, p0 = (t % tiles_p) * P;
-    const int np = min(P, a.Np - p0);
-    const long long ib = (long long)o * a.in_so + (long long)p0 * a.in_sp;
-    for (int e = threadIdx.x; e < n * P; e += NT) {
-      const int j = e / P, c = e - (e / P) * P;
-      tile[j * TS + c] = c < np ? in[ib + (long long)j * a.in_sj + (long long)c * a.in_sp] : (T)0;
-    }
-  }
+  // the whole tile's loads in flight at once (registers, then LDS)
+  fetch(t);
+  put(t);
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int qq = lane / G, g_lane = lane % G;
@@ -347,7 +358,7 @@ __global__ void __launch_bounds__(64 * W) kb_strided(const PassArgs a) {
     t = nxt;
     if (!PERS || t >= ntiles) break;
     __syncthreads();  // the tile has been read out
-    put();
+    put(t);
     __syncthreads();
   }
 }
@@ -933,6 +944,7 @@ template <typename T, int L>
 hipError_t launch_bounded_L(const PassArgs& a, hipStream_t s) {
   constexpr int PPW = WF<L>::PPW;
   const int lds = a.lds_bytes;
+  if (a.n < 1 || a.n > L / 2 + 1) return hipErrorInvalidValue;  // rows per pencil of every Table 1 type
   if (a.fast == FAST_R2R_C) {
     const long long pairs = (long long)((a.Np + 1) / 2) * a.No;
     const long long per_block = (long long)kR2RContigWaves * PPW;

@@ -186,6 +186,11 @@ __device__ __forceinline__ void tile_pj(int e, int P, int cnt, int jfast, int& p
 }
 
 // ---------------------------------------------------------------- loading
+// Each thread takes kLoadBatch elements per round and issues all their loads
+// before the first is used, so a tile costs one memory latency per round
+// instead of one per element.
+constexpr int kLoadBatch = 4;
+
 // Complex pencils straight into Z[p][m], zero beyond nin.
 template <typename T>
 __device__ void load_c2c(C2<T>* Z, const void* src, const PassArgs& a, const Tile& t) {
@@ -193,12 +198,20 @@ __device__ void load_c2c(C2<T>* Z, const void* src, const PassArgs& a, const Til
   const int cnt = a.nin;
   const int total = a.P * cnt;
   const long long obase = (long long)t.o * a.in_so + (long long)t.p0 * a.in_sp;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    int p, j;
-    tile_pj(e, a.P, cnt, a.in_jfast, p, j);
-    C2<T> v = {(T)0, (T)0};
-    if (p < t.np) v = in[obase + (long long)p * a.in_sp + (long long)j * a.in_sj];
-    Z[p * a.L + j] = v;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kLoadBatch * kThreads) {
+    C2<T> v[kLoadBatch];
+    int pp[kLoadBatch], jj[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = e0 + u * kThreads;
+      tile_pj(min(e, total - 1), a.P, cnt, a.in_jfast, pp[u], jj[u]);
+      // unconditional load from a clamped (in-tile) address; the pencils
+      // beyond np are zeroed where the values are kept
+      v[u] = in[obase + (long long)min(pp[u], t.np - 1) * a.in_sp + (long long)jj[u] * a.in_sj];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (e0 + u * kThreads < total) Z[pp[u] * a.L + jj[u]] = pp[u] < t.np ? v[u] : C2<T>{(T)0, (T)0};
   }
   for (int e = threadIdx.x; e < a.P * (a.L - cnt); e += kThreads) {
     const int p = e / (a.L - cnt);
@@ -214,15 +227,24 @@ __device__ void load_real(T* R, const void* src, const PassArgs& a, const Tile& 
   const int cnt = a.nin;
   const int total = a.P * cnt;
   const long long obase = (long long)t.o * a.in_so + (long long)t.p0 * a.in_sp;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    int p, j;
-    tile_pj(e, a.P, cnt, a.in_jfast, p, j);
-    T v = (T)0;
-    if (p < t.np) {
-      v = in[obase + (long long)p * a.in_sp + (long long)j * a.in_sj];
-      if (faces) v = (T)((double)v + face_terms<T>(a, j, t.p0 + p, t.o));
+  for (int e0 = threadIdx.x; e0 < total; e0 += kLoadBatch * kThreads) {
+    T v[kLoadBatch];
+    int pp[kLoadBatch], jj[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = e0 + u * kThreads;
+      tile_pj(min(e, total - 1), a.P, cnt, a.in_jfast, pp[u], jj[u]);
+      v[u] = in[obase + (long long)min(pp[u], t.np - 1) * a.in_sp + (long long)jj[u] * a.in_sj];
     }
-    R[p * cnt + j] = v;
+    if (faces) {
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u)
+        if (e0 + u * kThreads < total && pp[u] < t.np)
+          v[u] = (T)((double)v[u] + face_terms<T>(a, jj[u], t.p0 + pp[u], t.o));
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (e0 + u * kThreads < total) R[pp[u] * cnt + jj[u]] = pp[u] < t.np ? v[u] : (T)0;
   }
 }
 
@@ -233,12 +255,18 @@ __device__ void load_half(C2<T>* R, const void* src, const PassArgs& a, const Ti
   const int cnt = a.nin;
   const int total = a.P * cnt;
   const long long obase = (long long)t.o * a.in_so + (long long)t.p0 * a.in_sp;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    int p, j;
-    tile_pj(e, a.P, cnt, a.in_jfast, p, j);
-    C2<T> v = {(T)0, (T)0};
-    if (p < t.np) v = in[obase + (long long)p * a.in_sp + (long long)j * a.in_sj];
-    R[p * cnt + j] = v;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kLoadBatch * kThreads) {
+    C2<T> v[kLoadBatch];
+    int pp[kLoadBatch], jj[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = e0 + u * kThreads;
+      tile_pj(min(e, total - 1), a.P, cnt, a.in_jfast, pp[u], jj[u]);
+      v[u] = in[obase + (long long)min(pp[u], t.np - 1) * a.in_sp + (long long)jj[u] * a.in_sj];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (e0 + u * kThreads < total) R[pp[u] * cnt + jj[u]] = pp[u] < t.np ? v[u] : C2<T>{(T)0, (T)0};
   }
 }
 
@@ -1266,34 +1294,31 @@ struct FacePtrs {
   const void* f[3][2];
 };
 
+// Boundary nodes of the REGULAR Dirichlet axes (bit a of `axes`) of an
+// output [N0][N1][N2]: block row blockIdx.y = 2 a + side walks face (a, side)
+// only, one thread per node, the node's other two coordinates row-major (the
+// face array's own index).  A node on several such faces is written once, by
+// the face of its highest axis.  32-bit node indices within a face: the
+// launch refuses faces of 2^30 nodes or more.
 template <typename T>
 __global__ void k_dirichlet_fill(T* out, int N0, int N1, int N2, int ndim, int axes, FacePtrs fp) {
   const int N[3] = {N0, N1, N2};
-  const long long total = (long long)N0 * N1 * N2;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
+  const int a = blockIdx.y >> 1, side = blockIdx.y & 1;
+  if (a >= ndim || !((axes >> a) & 1)) return;
+  const int o0 = a == 0 ? 1 : 0, o1 = a == 2 ? 1 : 2;  // the other axes, in order
+  const int n1 = N[o1], fsize = N[o0] * N[o1];
+  const T* g = (const T*)fp.f[a][side];
+  const long long st[3] = {(long long)N1 * N2, (long long)N2, 1LL};
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < fsize; j += gridDim.x * blockDim.x) {
     int c[3];
-    c[2] = (int)(i % N2);
-    c[1] = (int)((i / N2) % N1);
-    c[0] = (int)(i / ((long long)N1 * N2));
-    int axis = -1, side = 0;
-    for (int a = 0; a < ndim; ++a) {
-      if (!((axes >> a) & 1)) continue;  // axis without boundary nodes
-      if (c[a] == 0) { axis = a; side = 0; }
-      else if (c[a] == N[a] - 1) { axis = a; side = 1; }
-    }
-    if (axis < 0) continue;
-    const T* g = (const T*)fp.f[axis][side];
-    T v = (T)0;
-    if (g) {
-      long long off = 0;
-      for (int b = 0; b < ndim; ++b) {
-        if (b == axis) continue;
-        off = off * N[b] + c[b];
-      }
-      v = g[off];
-    }
-    out[i] = v;
+    c[a] = side ? N[a] - 1 : 0;
+    c[o0] = j / n1;
+    c[o1] = j - c[o0] * n1;
+    bool own = true;
+    for (int b = a + 1; b < ndim; ++b)
+      if (((axes >> b) & 1) && (c[b] == 0 || c[b] == N[b] - 1)) own = false;
+    if (!own) continue;
+    out[c[0] * st[0] + c[1] * st[1] + c[2] * st[2]] = g ? g[j] : (T)0;
   }
 }
 
@@ -1302,11 +1327,15 @@ hipError_t launch_dirichlet_fill(void* out, const int N[3], int ndim, int axes, 
   FacePtrs fp;
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 2; ++b) fp.f[a][b] = face[a][b];
+  long long fmax = 1;
+  for (int a = 0; a < 3; ++a) fmax = std::max(fmax, (long long)N[0] * N[1] * N[2] / std::max(N[a], 1));
+  if (fmax >= (1LL << 30)) return hipErrorInvalidValue;
+  const int bx = (int)std::min<long long>((fmax + 255) / 256, 1024);
   if (prec == 0)
-    hipLaunchKernelGGL(k_dirichlet_fill<float>, dim3(1024), dim3(256), 0, s, (float*)out, N[0],
+    hipLaunchKernelGGL(k_dirichlet_fill<float>, dim3(bx, 6), dim3(256), 0, s, (float*)out, N[0],
                        N[1], N[2], ndim, axes, fp);
   else
-    hipLaunchKernelGGL(k_dirichlet_fill<double>, dim3(1024), dim3(256), 0, s, (double*)out, N[0],
+    hipLaunchKernelGGL(k_dirichlet_fill<double>, dim3(bx, 6), dim3(256), 0, s, (double*)out, N[0],
                        N[1], N[2], ndim, axes, fp);
   return hipGetLastError();
 }

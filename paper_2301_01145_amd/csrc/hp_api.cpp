@@ -2665,6 +2665,9 @@ hp_status hp_plan_destroy(hp_plan plan) {
   if (!plan) return HP_E_ARG;
   (void)hipStreamSynchronize(plan->stream);
   for (hipEvent_t e : plan->ev_pool) (void)hipEventDestroy(e);
+  for (hipStream_t st : plan->batch_aux) (void)hipStreamSynchronize(st);
+  for (hipEvent_t e : plan->batch_ev) (void)hipEventDestroy(e);
+  for (hipStream_t st : plan->batch_aux) (void)hipStreamDestroy(st);
   for (void* a : plan->allocs) (void)hipFree(a);
   delete plan;
   return HP_OK;

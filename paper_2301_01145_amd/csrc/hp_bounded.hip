@@ -798,25 +798,18 @@ hipError_t bw_launch_kind(const BatchGroup& g, const PassArgs* passes, const Bat
 }
 
 template <int XF, int XB>
-hipError_t bw_launch_levels(const PassArgs* passes, const BatchItem* items, const BatchGroup* groups,
-                            int ngroups, int* err, hipStream_t s) {
-  for (int k = 0; k < ngroups; ++k) {
-    const BatchGroup& g = groups[k];
-    if (g.count <= 0) continue;
-    int* e = k == 0 ? err : nullptr;
-    const BatchItem* it = items + g.first;
-    hipError_t r;
-    switch (g.L) {
-      case 64: r = bw_launch_kind<XF, XB, 64>(g, passes, it, e, s); break;
-      case 96: r = bw_launch_kind<XF, XB, 96>(g, passes, it, e, s); break;
-      case 128: r = bw_launch_kind<XF, XB, 128>(g, passes, it, e, s); break;
-      case 192: r = bw_launch_kind<XF, XB, 192>(g, passes, it, e, s); break;
-      case 256: r = bw_launch_kind<XF, XB, 256>(g, passes, it, e, s); break;
-      default: r = hipErrorInvalidValue;
-    }
-    if (r != hipSuccess) return r;
+hipError_t bw_launch_one(const BatchGroup& g, const PassArgs* passes, const BatchItem* items, int* err,
+                         hipStream_t s) {
+  if (g.count <= 0) return hipSuccess;
+  const BatchItem* it = items + g.first;
+  switch (g.L) {
+    case 64: return bw_launch_kind<XF, XB, 64>(g, passes, it, err, s);
+    case 96: return bw_launch_kind<XF, XB, 96>(g, passes, it, err, s);
+    case 128: return bw_launch_kind<XF, XB, 128>(g, passes, it, err, s);
+    case 192: return bw_launch_kind<XF, XB, 192>(g, passes, it, err, s);
+    case 256: return bw_launch_kind<XF, XB, 256>(g, passes, it, err, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipSuccess;
 }
 
 template <int XF, int XB>
@@ -897,11 +890,11 @@ int batched_wf_blocks_per_cu(int xf, int lds) {
   return bw_blocks_per_cu<X_DCT1, X_DCT1>(lds);
 }
 
-hipError_t launch_batched_levels(int xf, const PassArgs* passes, const BatchItem* items,
-                                 const BatchGroup* groups, int ngroups, int* err, hipStream_t s) {
-  if (xf == X_DCT2) return bw_launch_levels<X_DCT2, X_DCT3>(passes, items, groups, ngroups, err, s);
-  if (xf == X_DST2) return bw_launch_levels<X_DST2, X_DST3>(passes, items, groups, ngroups, err, s);
-  if (xf == X_DCT1) return bw_launch_levels<X_DCT1, X_DCT1>(passes, items, groups, ngroups, err, s);
+hipError_t launch_batched_group(int xf, const PassArgs* passes, const BatchItem* items,
+                                const BatchGroup& g, int* err, hipStream_t s) {
+  if (xf == X_DCT2) return bw_launch_one<X_DCT2, X_DCT3>(g, passes, items, err, s);
+  if (xf == X_DST2) return bw_launch_one<X_DST2, X_DST3>(g, passes, items, err, s);
+  if (xf == X_DCT1) return bw_launch_one<X_DCT1, X_DCT1>(g, passes, items, err, s);
   return hipErrorInvalidValue;
 }
 

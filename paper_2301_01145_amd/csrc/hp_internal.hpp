@@ -287,11 +287,14 @@ hipError_t launch_batched_wf(int xf, const PassArgs* passes, const BatchItem* it
 // forward / backward type, 2 / 3 strided pass of the forward / backward type,
 // 4 sandwich), one workgroup each with lds bytes of LDS, in group order;
 // err[0] is cleared (there is no wait to fail).
+// One launch of the level form: items [first, first + count) of one pass
+// level (`level`), all of transform length L and pass kind `kind`.
 struct BatchGroup {
-  int first, count, L, kind, lds;
+  int first, count, L, kind, lds, level;
 };
-hipError_t launch_batched_levels(int xf, const PassArgs* passes, const BatchItem* items,
-                                 const BatchGroup* groups, int ngroups, int* err, hipStream_t s);
+// The launch of one group (its items' err flag: err, may be null).
+hipError_t launch_batched_group(int xf, const PassArgs* passes, const BatchItem* items,
+                                const BatchGroup& g, int* err, hipStream_t s);
 // Resident workgroups per CU of the persistent kernel with `lds` bytes of LDS.
 int batched_blocks_per_cu(int lds, int prec, int big);
 }  // namespace hp

@@ -88,6 +88,12 @@ struct hp_plan_s {
   // by the autotuner (1 and 2 fall back to 0 where not allowed)
   int batch_wf = 0, batch_xf = 0, batch_mode = -1;
   std::vector<hp::BatchGroup> batch_groups;  // mode 2: launches (level, length) in order
+  // mode 2 under stream capture: the groups of one level run on forked
+  // streams (default priority), joined by events before the next level; fork
+  // event and join events per level, created at setup
+  std::vector<hipStream_t> batch_aux;
+  std::vector<hipEvent_t> batch_ev;
+  bool batch_fork = true;
   std::vector<hp::PassRec> batch_passes;
   int batch_tiles = 0;  // tiles per work item (0: the default)
   double* zm_partial = nullptr;  // per-block partial sums of the zero-mode query

@@ -192,3 +192,32 @@ def test_batch_level_launches_match_persistent(monkeypatch):
     lev.close()
     for i in range(len(WF_SHAPES)):
         assert np.array_equal(got_one[i], got_lev[i]), i
+
+
+def test_batch_level_launches_graph_replay(monkeypatch):
+    """The level form captured into a graph (the groups of a level on forked
+    streams, joined before the next level) replays the eager result bit for
+    bit, with eager work between the replays."""
+    import torch
+    monkeypatch.setenv("HP_BATCH_LEVELS", "1")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        bs, fs_np, fs, eager = _run_batch("neumann", "staggered", "ps", WF_SHAPES, "f32", seed=29)
+    assert bs.kernel_mode() == 2
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        bs.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for p in bs._keep[1]:
+            p.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda") * 2.0  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, p in enumerate(bs._keep[1]):
+            assert np.array_equal(p.double().cpu().numpy(), eager[i]), (rep, i)
+        del junk
+    assert bs.error_flag() == 0
+    bs.close()

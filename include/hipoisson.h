@@ -226,13 +226,15 @@ HP_API hp_status hp_solve_adjoint(hp_plan plan);
 HP_API hp_status hp_get_output(hp_plan plan, int problem, int comp, void* dst, int on_device);
 HP_API hp_status hp_get_gradient(hp_plan plan, int problem, int comp, void* dst, int on_device);
 
-/* Per-pass instrumentation for benchmarks.  While enabled, hp_solve records a
- * HIP event pair around every kernel it launches on the plan's stream.
- * hp_pass_stats synchronises the stream and returns, for each of the `*npass`
- * passes of a solve (at most `max`), the mean elapsed milliseconds over the
- * solves recorded since the last call (ms), the algorithmic HBM bytes of the
- * pass (bytes: stored input read once plus stored output written once, plus
- * the Green's octant) and a static name (names); any output may be NULL. */
+/* Per-pass instrumentation for benchmarks.  enable: 0 off; 1: hp_solve
+ * records a HIP event pair around every kernel it launches on the plan's
+ * stream; 2 + k: around pass k only (one pair per solve, so the solve's own
+ * time is barely perturbed); negative: HP_E_ARG.  hp_pass_stats synchronises
+ * the stream and returns, for each of the `*npass` passes of a solve (at most
+ * `max`), the mean elapsed milliseconds over the solves recorded since the
+ * last call (ms; 0 for a pass that was not timed), the algorithmic HBM bytes
+ * of the pass (bytes: stored input read once plus stored output written once,
+ * plus the Green's octant) and a static name (names); any output may be NULL. */
 HP_API hp_status hp_set_timing(hp_plan plan, int enable);
 HP_API hp_status hp_pass_stats(hp_plan plan, int max, int* npass, double* ms, double* bytes,
                                const char** names);

@@ -2140,14 +2140,17 @@ hp_status next_event(hp_plan p, hipEvent_t* e) {
 }
 
 hp_status run_passes(hp_plan p, const std::vector<PassRec>& ps) {
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  std::vector<PassEvents> evs;
   if (p->timing) {
     p->pass_bytes.clear();
     p->pass_names.clear();
   }
-  for (auto& r : ps) {
+  for (size_t i = 0; i < ps.size(); ++i) {
+    const PassRec& r = ps[i];
+    // every pass, or only pass timing_pass (one event pair per solve)
+    const bool rec = p->timing && (p->timing_pass < 0 || p->timing_pass == (int)i);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p->timing) {
+    if (rec) {
       HP_TRY(next_event(p, &e0));
       HP_TRY(next_event(p, &e1));
       HP_HIP(p, hipEventRecord(e0, p->stream));
@@ -2156,9 +2159,11 @@ hp_status run_passes(hp_plan p, const std::vector<PassRec>& ps) {
                    : r.a.fast               ? launch_fast(r.a, p->prec, r.grid_y, p->stream)
                                             : launch_pass(r.a, p->prec, r.grid_y, p->stream);
     if (e != hipSuccess) return fail(p, HP_E_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
-    if (p->timing) {
+    if (rec) {
       HP_HIP(p, hipEventRecord(e1, p->stream));
-      evs.push_back({e0, e1});
+      evs.push_back({(int)i, e0, e1});
+    }
+    if (p->timing) {
       p->pass_bytes.push_back(model_bytes(p, std::vector<PassRec>{r}));
       p->pass_names.push_back(pass_name(r.a));
     }
@@ -2513,8 +2518,9 @@ hp_status hp_get_gradient(hp_plan plan, int problem, int comp, void* dst, int on
 }
 
 hp_status hp_set_timing(hp_plan plan, int enable) {
-  if (!plan) return HP_E_ARG;
+  if (!plan || enable < 0) return HP_E_ARG;
   plan->timing = enable != 0;
+  if (enable) plan->timing_pass = enable == 1 ? -1 : enable - 2;
   return HP_OK;
 }
 
@@ -2525,18 +2531,17 @@ hp_status hp_pass_stats(hp_plan plan, int max, int* npass, double* ms, double* b
   const size_t np = plan->pass_names.size();
   if (npass) *npass = (int)np;
   std::vector<double> acc(np, 0.0);
-  size_t nsolve = 0;
-  for (auto& evs : plan->ev_solves) {
-    if (evs.size() != np) continue;
-    for (size_t i = 0; i < np; ++i) {
+  std::vector<size_t> cnt(np, 0);
+  for (auto& evs : plan->ev_solves)
+    for (const PassEvents& pe : evs) {
+      if (pe.pass < 0 || (size_t)pe.pass >= np) continue;
       float t = 0.f;
-      HP_HIP(plan, hipEventElapsedTime(&t, evs[i].first, evs[i].second));
-      acc[i] += t;
+      HP_HIP(plan, hipEventElapsedTime(&t, pe.e0, pe.e1));
+      acc[pe.pass] += t;
+      ++cnt[pe.pass];
     }
-    ++nsolve;
-  }
   for (size_t i = 0; i < np && (int)i < max; ++i) {
-    if (ms) ms[i] = nsolve ? acc[i] / nsolve : 0.0;
+    if (ms) ms[i] = cnt[i] ? acc[i] / cnt[i] : 0.0;
     if (bytes) bytes[i] = plan->pass_bytes[i];
     if (names) names[i] = plan->pass_names[i];
   }

@@ -96,9 +96,13 @@ __global__ void __launch_bounds__((R2CShape<L, P>::NT)) kf_r2c(const PassArgs a)
   }
   __syncthreads();
   const long long obase = (long long)x * K2 * n1 + y0;
-  for (int e = threadIdx.x; e < K2 * P; e += NT) {
+  // a compile-time count: every LDS read of the thread is issued before the
+  // first store waits for one (a run-time loop reads, waits and stores in turn)
+#pragma unroll
+  for (int r = 0; r < (K2 * P + NT - 1) / NT; ++r) {
+    const int e = threadIdx.x + r * NT;
     const int k = e / P, c = e - (e / P) * P;
-    if (y0 + c < n1) st_stream(&out[obase + (long long)k * n1 + c], tile[k * TS + c]);
+    if (e < K2 * P && y0 + c < n1) st_stream(&out[obase + (long long)k * n1 + c], tile[k * TS + c]);
   }
   (void)n0;
 }
@@ -148,7 +152,10 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_fwd_y(const PassArgs
   }
   __syncthreads();
   const long long obase = (long long)kzl * L * n0 + x0;
-  for (int e = threadIdx.x; e < L * P; e += NT) {
+  static_assert((L * P) % NT == 0, "whole rounds of the tile store");
+#pragma unroll
+  for (int r = 0; r < L * P / NT; ++r) {
+    const int e = threadIdx.x + r * NT;
     const int ky = e / P, c = e - (e / P) * P;
     if (x0 + c < n0) st_stream(&out[obase + (long long)ky * n0 + c], tile[padrow(ky) * TS + c]);
   }
@@ -199,7 +206,10 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
   const int p = wave * PPW + q;
   C2<T>* col = DBL ? exch + p * slot_len(L) : tiles + p;
   constexpr int bs = DBL ? 1 : TS;
-  auto kx = [&](int i) -> T { return (T)(a.kc[0] * signed_index(g + G * i, L)); };
+  // wavenumbers in the solve precision (the FP64 product rounded once was
+  // three conversions and an FP64 multiply per bin)
+  const T kc0 = (T)a.kc[0];
+  auto kx = [&](int i) -> T { return kc0 * (T)signed_index(g + G * i, L); };
 
   struct TileIdx {
     int grp, kzl, ky0;
@@ -311,9 +321,14 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       for (int i = 0; i < NIN; ++i) tile[row(g + G * i) * TS + p] = w[i];
       __syncthreads();
       C2<T>* d = (C2<T>*)dst + obase;
-      for (int e = threadIdx.x; e < NX * P; e += NT) {
+      // compile-time count (all LDS reads before the stores); offsets within
+      // the kz slab, NX * M1 <= 2^20
+      static_assert((NX * P) % NT == 0, "whole rounds of the tile store");
+#pragma unroll
+      for (int r = 0; r < NX * P / NT; ++r) {
+        const int e = threadIdx.x + r * NT;
         const int x = e / P, c = e - (e / P) * P;
-        st_stream(&d[(long long)x * M1 + c], tile[row(x) * TS + c]);
+        st_stream(&d[x * M1 + c], tile[row(x) * TS + c]);
       }
       if (DBL) tb ^= 1;
       else __syncthreads();
@@ -503,7 +518,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
   const long long ibase = ((long long)(valid ? kzl0 + p : 0) * n0 + x) * L;
   const long long obase = (long long)x * a.c1_sx + kz0;
   const int nvalid = min(P, a.kz_count - kzl0);
-  auto kyv = [&](int i) -> T { return (T)(a.kc[1] * signed_index(g + G * i, L)); };
+  const T kc1 = (T)a.kc[1];
+  auto kyv = [&](int i) -> T { return kc1 * (T)signed_index(g + G * i, L); };
   const T kzv = (T)(a.kc[2] * signed_index(kz, M2));
 
   auto load = [&](C2<T> (&v)[R0], const void* src) {
@@ -522,7 +538,10 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW)) kf_inv_y(const PassArgs
     for (int i = 0; i < NIN; ++i) tile[row(g + G * i) * TS + p] = v[i];
     __syncthreads();
     C2<T>* d = (C2<T>*)dst + obase;
-    for (int e = threadIdx.x; e < NY * P; e += NT) {
+    static_assert((NY * P) % NT == 0, "whole rounds of the tile store");
+#pragma unroll
+    for (int r = 0; r < NY * P / NT; ++r) {
+      const int e = threadIdx.x + r * NT;
       const int y = e / P, c = e - (e / P) * P;
       if (c < nvalid) st_stream(&d[(long long)y * a.c1_sy + c], tile[row(y) * TS + c]);
     }

@@ -59,6 +59,14 @@ struct Problem {
 
 }  // namespace hp
 
+namespace hp {
+// the event pair recorded around pass `pass` of one solve (hp_set_timing)
+struct PassEvents {
+  int pass;
+  hipEvent_t e0, e1;
+};
+}  // namespace hp
+
 struct hp_plan_s {
   hipStream_t stream = nullptr;
   int prec = 0;
@@ -107,7 +115,8 @@ struct hp_plan_s {
   // per-pass timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> ev_solves;
+  std::vector<std::vector<hp::PassEvents>> ev_solves;
+  int timing_pass = -1;  // -1: every pass; else only this pass index
   size_t ev_used = 0;
   std::vector<double> pass_bytes;
   std::vector<const char*> pass_names;

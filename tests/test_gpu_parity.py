@@ -234,6 +234,30 @@ def test_unbounded_regular_wavefront(diff, ncomp, prec):
     assert names == ["r2c_z", "fwd_y", "sandwich_x", "inv_y", "c2r_z"], names
 
 
+def test_single_pass_timing():
+    """hp_set_timing(plan, 2 + k) records events around pass k only: every
+    pass keeps its name and bytes, only pass k has a time; a negative mode is
+    refused."""
+    import torch
+    from paper_2301_01145_amd import HipoissonError, Solver, hp_pass_stats, hp_set_timing
+    nc = [32, 32, 32]
+    f, _ = case_input("unbounded", "staggered", nc, 3, False, "f32", seed=61)
+    s = Solver("unbounded", "staggered", nc, LO, HI, diff="curl", dtype=torch.float32, ncomp=3)
+    s.bind([to_dev(f[c], torch.float32, torch) for c in range(3)])
+    hp_pass_stats(s.plan)
+    hp_set_timing(s.plan, 2 + 2)
+    for _ in range(3):
+        s.run()
+    hp_set_timing(s.plan, 0)
+    st = hp_pass_stats(s.plan)
+    assert [p[0] for p in st] == ["r2c_z", "fwd_y", "sandwich_x", "inv_y", "c2r_z"], st
+    assert st[2][1] > 0.0 and all(st[i][1] == 0.0 for i in (0, 1, 3, 4)), st
+    assert all(p[2] > 0.0 for p in st), st
+    with pytest.raises(HipoissonError):
+        hp_set_timing(s.plan, -1)
+    s.close()
+
+
 NEW_KERNELS = ["g4", "g6", "g8", "g10", "spectral"]
 
 

@@ -313,7 +313,9 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     };
     // backward FFT, x < n0 of every pencil to the tile, stored along ky
     auto emit = [&](C2<T> (&w)[R0], void* dst) {
-      wave_fft<T, L, true>(w, col, bs, g, tw);
+      // twiddles read at the multiply: with a second field live (the curl's
+      // derivative output) they would not fit the register budget
+      wave_fft<T, L, true, false, false, false>(w, col, bs, g, tw);
       wave_sync();
       C2<T>* tile = DBL ? tiles + tb * NX * TS : tiles;
       auto row = [](int x) { return DBL ? x : padrow(x); };

@@ -65,10 +65,24 @@ __device__ __forceinline__ int padrun(int a, int t) {
 // One Stockham stage (radix R, NS = product of earlier radices) over the
 // wavefront slot `buf`: reads in layout PR, writes (unless LAST) in layout PW.
 // twS holds this stage's twiddles as twS[(t - 1) NS + k] = W_{NS R}^{t k}.
-template <typename T, int L, int R, int NS, bool LAST, bool INV, typename PR, typename PW>
+// TWPRE: the stage's twiddles are read with the exchange, ahead of the wave
+// barrier, so their LDS latency overlaps it (read at the multiply, each pair
+// of them costs a wait of its own); it holds NB (R - 1) more complex values in
+// registers across the exchange.
+template <typename T, int L, int R, int NS, bool LAST, bool INV, typename PR, typename PW,
+          bool TWPRE = true>
 __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs, int g,
                                        const C2<T>* twS) {
   constexpr int R0 = WF<L>::R0, G = WF<L>::G, NB = R0 / R;
+  C2<T> w[NB * (R - 1)];
+  if constexpr (TWPRE) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = (g + G * b) % NS;
+#pragma unroll
+      for (int t = 1; t < R; ++t) w[b * (R - 1) + t - 1] = twS[(t - 1) * NS + k];
+    }
+  }
   C2<T> v[R0];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -83,9 +97,9 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
     const int k = j % NS;
 #pragma unroll
     for (int t = 1; t < R; ++t) {
-      C2<T> w = twS[(t - 1) * NS + k];
-      if (INV) w.im = -w.im;
-      v[b * R + t] = cmul(v[b * R + t], w);
+      C2<T> tw1 = TWPRE ? w[b * (R - 1) + t - 1] : twS[(t - 1) * NS + k];
+      if (INV) tw1.im = -tw1.im;
+      v[b * R + t] = cmul(v[b * R + t], tw1);
     }
     dftN<T, R, INV>(&v[b * R]);
     if constexpr (LAST) {
@@ -113,7 +127,7 @@ __device__ __forceinline__ void wstage(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs
 // In-place FFT of the pencil held as x[i] = x[g + G i]; on return x[i] = X[g + G i].
 // HALF: x[i] is zero for i >= R0 / 2 (zero-padded input).  tw is the
 // per-stage twiddle table (stage 1 at 0, stage 2 at 7 R0).
-template <typename T, int L, bool INV, bool HALF = false, bool SMALL = false>
+template <typename T, int L, bool INV, bool HALF = false, bool SMALL = false, bool TWPRE = true>
 __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int bs, int g,
                                          const C2<T>* tw) {
   // SMALL: both exchanges in the first layout (a shorter slot, 2x conflicts
@@ -135,15 +149,15 @@ __device__ __forceinline__ void wave_fft(C2<T> (&x)[WF<L>::R0], C2<T>* buf, int 
   wave_sync();
   if constexpr (G <= 8 && R0 % G == 0) {
     // one more stage, of radix G (R0 = 8, G = 8; R0 = 12, G = 4)
-    wstage<T, L, G, R0, true, INV, PadA, PadA>(x, buf, bs, g, tw);
+    wstage<T, L, G, R0, true, INV, PadA, PadA, TWPRE>(x, buf, bs, g, tw);
   } else if constexpr (R0 % 3 == 0) {
     // R0 = 12: a radix-4 stage, then radix G / 4 (2 or 4)
-    wstage<T, L, 4, R0, false, INV, PadA, PadA>(x, buf, bs, g, tw);
-    wstage<T, L, G / 4, 4 * R0, true, INV, PadA, PadA>(x, buf, bs, g, tw + 3 * R0);
+    wstage<T, L, 4, R0, false, INV, PadA, PadA, TWPRE>(x, buf, bs, g, tw);
+    wstage<T, L, G / 4, 4 * R0, true, INV, PadA, PadA, TWPRE>(x, buf, bs, g, tw + 3 * R0);
   } else {
     static_assert((R0 & (R0 - 1)) == 0, "three stages: power-of-two lengths only");
-    wstage<T, L, 8, R0, false, INV, PadA, PB>(x, buf, bs, g, tw);
-    wstage<T, L, G / 8, 8 * R0, true, INV, PB, PB>(x, buf, bs, g, tw + 7 * R0);
+    wstage<T, L, 8, R0, false, INV, PadA, PB, TWPRE>(x, buf, bs, g, tw);
+    wstage<T, L, G / 8, 8 * R0, true, INV, PB, PB, TWPRE>(x, buf, bs, g, tw + 7 * R0);
   }
 }
 

@@ -312,10 +312,11 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       wave_fft<T, L, false, PAD>(w, col, bs, g, tw);
     };
     // backward FFT, x < n0 of every pencil to the tile, stored along ky
-    auto emit = [&](C2<T> (&w)[R0], void* dst) {
-      // twiddles read at the multiply: with a second field live (the curl's
-      // derivative output) they would not fit the register budget
-      wave_fft<T, L, true, false, false, false>(w, col, bs, g, tw);
+    // TW: the inverse transform's twiddles read ahead of each exchange; only
+    // where no second field is live (with the curl's derivative output held
+    // beside psi they do not fit the register budget)
+    auto emit_tw = [&](auto tw_pre, C2<T> (&w)[R0], void* dst) {
+      wave_fft<T, L, true, false, false, decltype(tw_pre)::value>(w, col, bs, g, tw);
       wave_sync();
       C2<T>* tile = DBL ? tiles + tb * NX * TS : tiles;
       auto row = [](int x) { return DBL ? x : padrow(x); };
@@ -335,6 +336,8 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
       if (DBL) tb ^= 1;
       else __syncthreads();
     };
+    auto emit = [&](C2<T> (&w)[R0], void* dst) { emit_tw(std::false_type{}, w, dst); };
+    auto emit_last = [&](C2<T> (&w)[R0], void* dst) { emit_tw(std::true_type{}, w, dst); };
 
     // |k|^2 of bin i (every wavenumber with its Nyquist value zeroed)
     auto ksq = [&](int i) -> T { return kx(i) * kx(i) + kyv * kyv + kzv * kzv; };
@@ -405,7 +408,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     } else if (a.diff == D_NONE) {
       wave_fft<T, L, false, PAD>(v, col, bs, g, tw);
       green(v);
-      emit(v, a.out[t.grp]);
+      emit_last(v, a.out[t.grp]);
     } else if (!ADJ && a.diff == D_CURL) {
       // one component per output group: psi_c, plus B = d_x psi_y (c = 1) or
       // A = -d_x psi_z (c = 2)
@@ -419,7 +422,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
         for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
         emit(u, a.out[c == 1 ? 4 : 3]);
       }
-      emit(v, a.out[c]);
+      emit_last(v, a.out[c]);
     } else if (ADJ && a.diff == D_ADJ_CURL) {
       C2<T> S[3][R0];
 #pragma unroll

@@ -251,8 +251,14 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     if constexpr (EXT) return a.in[t.grp];
     else return a.in[a.diff == D_NONE || a.diff == D_CURL ? t.grp : 0];
   };
+  // GNOW (FP32): the Green's values of a tile are loaded at its start, ahead
+  // of its forward transform, instead of a whole tile ahead with the input;
+  // the eight registers that frees let the first output transform of a curl
+  // group read its twiddles ahead of the exchanges too (A/B on one box:
+  // 1.642 -> 1.636 ms; FP64 was 1.4 % slower that way and keeps the prefetch)
+  constexpr bool GNOW = sizeof(T) == 4;
   C2<T> pf[NIN];
-  T pg[R0];
+  T pg[GNOW ? 1 : R0];
   auto prefetch = [&](const TileIdx& t) {
     // an unbound field (adjoint with a zero upstream gradient) reads as zero
     const void* src = src_of(t);
@@ -265,8 +271,11 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
 #pragma unroll
       for (int i = 0; i < NIN; ++i) pf[i] = {(T)0, (T)0};
     }
+    if constexpr (!GNOW) {
 #pragma unroll
-    for (int i = 0; i < R0; ++i) pg[i] = mult_of(t, gr, g + G * i);
+      for (int i = 0; i < R0; ++i) pg[i] = mult_of(t, gr, g + G * i);
+    }
+    (void)gr;
   };
   TileIdx cur = decode(lt);
   if (pref) prefetch(cur);
@@ -283,10 +292,13 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
     C2<T> v[R0];
     T gv[R0];
     if (pref) {
+      const T* gr = PAD ? green_ptr(t) : nullptr;
+      (void)gr;
 #pragma unroll
       for (int i = 0; i < R0; ++i) {
         v[i] = i < NIN ? pf[i] : C2<T>{(T)0, (T)0};
-        gv[i] = pg[i];
+        if constexpr (GNOW) gv[i] = mult_of(t, gr, g + G * i);
+        else gv[i] = pg[i];
       }
     }
     const int nxt = lt + (int)gridDim.x;
@@ -420,7 +432,7 @@ __global__ void __launch_bounds__(64 * (P / WF<L>::PPW),
         const T sgn = c == 1 ? (T)1 : (T)-1;
 #pragma unroll
         for (int i = 0; i < R0; ++i) u[i] = cscale(cmuli(v[i]), sgn * kx(i));
-        emit(u, a.out[c == 1 ? 4 : 3]);
+        emit_tw(std::integral_constant<bool, GNOW>{}, u, a.out[c == 1 ? 4 : 3]);
       }
       emit_last(v, a.out[c]);
     } else if (ADJ && a.diff == D_ADJ_CURL) {

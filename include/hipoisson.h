@@ -69,14 +69,20 @@ typedef enum {
  * axis runs the discrete Hartley transform (real to real, its own inverse up
  * to n, diagonal for the periodic Laplacian) beside the Table 1 sine and
  * cosine transforms, with the eigenvalue sum of eq. (pois_spec) over the
- * axes.  PS or FD2; boundary values (FD2) on the Dirichlet / Neumann faces;
- * no derivative outputs (HP_E_UNSUPPORTED).
+ * axes.  PS or FD2; boundary values (FD2) on the Dirichlet / Neumann faces.
+ * Derivative outputs (GRAD, CURL, DIV, NABLA) take each axis's own rule: the
+ * sine / cosine series of Table 1's eigenfunctions, the Hartley spectral
+ * derivative along periodic axes; with boundary values second-order
+ * differences of psi instead (NABLA then HP_E_UNSUPPORTED).
  * Semi-unbounded: one axis (of 2 or 3) may be HP_UNBOUNDED.  Each bounded
  * mode, eigenvalue sum Lambda, then solves psi'' - kappa^2 psi = f along the
  * free axis (kappa^2 = -Lambda, Section 2.6's Helmholtz split), convolved by
  * the Hockney-Eastwood doubling (M = 2 n, Section 2.5) with the exact 1D
  * Green's function -exp(-kappa |x|) / (2 kappa) (|x| / 2 for kappa = 0) times
- * the cell length.  The free axis has no faces. */
+ * the cell length.  The free axis has no faces.  GRAD, CURL and DIV of
+ * homogeneous problems: the free axis's derivative is the convolution with
+ * the kernel's derivative sign(x) exp(-kappa |x|) / 2; NABLA, or derivatives
+ * with boundary values, return HP_E_UNSUPPORTED. */
 typedef enum { HP_PERIODIC = 0, HP_DIRICHLET = 1, HP_NEUMANN = 2, HP_UNBOUNDED = 3,
                HP_MIXED = 4 } hp_bc;
 typedef enum { HP_REGULAR = 0, HP_STAGGERED = 1 } hp_grid;

@@ -348,12 +348,16 @@ def other_workloads(steps, warmup):
     # a condition per axis, and one free axis (FD2, FP32, seeded normal sources;
     # boundary values on the Dirichlet / Neumann faces), and a prime length
     rng = np.random.default_rng(12)
-    for key, bcs, nc, inhom in (("mixed3d_128_pdn_fd2_fp32", ["periodic", "dirichlet", "neumann"],
-                                 [128, 128, 128], True),
-                                ("semi3d_128_free_pp_fd2_fp32", ["unbounded", "periodic", "periodic"],
-                                 [128, 128, 128], False),
-                                ("periodic3d_127_fp32", "periodic", [127, 127, 127], False)):
-        s = Solver(bcs, "staggered", nc, kernel="fd2", dtype=torch.float32, inhomogeneous=inhom)
+    for key, bcs, nc, inhom, diff in (("mixed3d_128_pdn_fd2_fp32", ["periodic", "dirichlet", "neumann"],
+                                       [128, 128, 128], True, "none"),
+                                      ("semi3d_128_free_pp_fd2_fp32", ["unbounded", "periodic", "periodic"],
+                                       [128, 128, 128], False, "none"),
+                                      # psi and its gradient: the free axis's derivative by the
+                                      # odd kernel's rows, the periodic ones by the Hartley series
+                                      ("semi3d_128_free_pp_fd2_grad_fp32", ["unbounded", "periodic", "periodic"],
+                                       [128, 128, 128], False, "grad"),
+                                      ("periodic3d_127_fp32", "periodic", [127, 127, 127], False, "none")):
+        s = Solver(bcs, "staggered", nc, kernel="fd2", diff=diff, dtype=torch.float32, inhomogeneous=inhom)
         src = torch.as_tensor(rng.normal(size=s.in_shape).astype(np.float32), device="cuda")
         fd = None
         if inhom:

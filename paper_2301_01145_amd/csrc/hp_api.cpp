@@ -901,24 +901,30 @@ hp_status finish_pass(hp_plan p, PassArgs& a, int want, int minP, long long lds_
 
 // --------------------------------------------------------- pass lists
 // Wavefront-FFT kernels for the bounded passes (hp_bounded.hip): 2D / 3D
-// single plans whose every transform length is a power of two in [64, 512],
-// or 96 or 192.
+// single plans whose every Dirichlet / Neumann transform length is a power of
+// two in [64, 512], or 96 or 192 (the Hartley passes of periodic axes stay on
+// the general kernels).
 bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
   if (std::getenv("HP_GENERIC") || p->batched || P.nd < 2) return false;
+  int bounded = 0;
   for (int a = 0; a < P.nd; ++a) {
-    if (axis_bc(P.d, a) == HP_PERIODIC) return false;  // Hartley axes: general kernels
+    // Hartley (periodic) axes of a mixed plan keep the general kernels; the
+    // passes along the other axes switch one by one (to_fast_r2r)
+    if (axis_bc(P.d, a) == HP_PERIODIC) continue;
+    ++bounded;
     if (L[a] < 64 || L[a] > 512 || wf_r0(L[a]) <= 0) return false;
     for (int k = FAST_R2R_C; k <= FAST_R2R_SW; ++k) {
       const int lds = r2r_lds_bytes(k, L[a], P.n[a], p->prec);
       if (lds <= 0 || lds > 160 * 1024) return false;
     }
   }
-  return true;
+  return bounded > 0;
 }
 
 // Switch a general bounded pass (same descriptor) to its wavefront kernel.
 hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
   if (a.fast == FAST_GRAD_PREP || a.fast == FAST_ADD) return HP_OK;
+  if (a.xf == X_DHT || (a.kind == PK_SANDWICH && a.xb == X_DHT)) return HP_OK;  // general kernels
   const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
   bool faces = false;
   for (int ax = 0; ax < 3; ++ax) faces |= a.face[ax][0] != nullptr || a.face[ax][1] != nullptr;

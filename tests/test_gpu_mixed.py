@@ -359,9 +359,11 @@ def run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed, f=Non
     ref, rd = oracle.solve(list(bcs), gtype, nc, LO[:nd], HI[:nd], f, operator=kernel, diff=diff, faces=faces)
     check(got, ref, prec, "psi")
     assert len(der) == len(rd)
+    dout = [d.double().cpu().numpy() for d in der]
     for a in range(len(rd)):
-        check(der[a].double().cpu().numpy(), rd[a], prec, f"{diff} {a}")
+        check(dout[a], rd[a], prec, f"{diff} {a}")
     s.close()
+    return got, dout
 
 
 @pytest.mark.parametrize("bcs", [["dirichlet", "neumann", "dirichlet"], ["neumann", "dirichlet", "neumann"]])
@@ -442,3 +444,25 @@ def test_semi_derivative_zero_eigenvalue_row(prec):
         assert np.max(np.abs(rd[a])) <= 1e-13 * scale
         assert np.max(np.abs(der[a].double().cpu().numpy())) <= TOL[prec][1] * scale, a
     s.close()
+
+
+# a periodic (Hartley) axis beside Dirichlet / Neumann axes at power-of-two
+# transform lengths: the Dirichlet / Neumann passes run the wavefront kernels,
+# the Hartley passes the general ones
+MIX_WF = [["periodic", "dirichlet", "neumann"], ["neumann", "periodic", "dirichlet"],
+          ["dirichlet", "neumann", "periodic"]]
+
+
+@pytest.mark.parametrize("bcs", MIX_WF)
+@pytest.mark.parametrize("gtype", ["regular", "staggered"])
+@pytest.mark.parametrize("kernel,inhom,diff", [("fd2", True, "none"), ("ps", False, "grad"), ("fd2", False, "curl")])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mixed_periodic_axis_wavefront(bcs, gtype, kernel, inhom, diff, prec, monkeypatch):
+    nc = [32, 64, 32]
+    ncomp = 3 if diff == "curl" else 1
+    got, dout = run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=197)
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen, dgen = run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=197)
+    check(got, gen, prec, "psi wavefront vs general")
+    for a in range(len(dgen)):
+        check(dout[a], dgen[a], prec, f"{diff} {a} wavefront vs general")

@@ -908,9 +908,10 @@ bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
   if (std::getenv("HP_GENERIC") || p->batched || P.nd < 2) return false;
   int bounded = 0;
   for (int a = 0; a < P.nd; ++a) {
-    // Hartley (periodic) axes of a mixed plan keep the general kernels; the
-    // passes along the other axes switch one by one (to_fast_r2r)
-    if (axis_bc(P.d, a) == HP_PERIODIC) continue;
+    // Hartley (periodic) axes and the free axis of a mixed plan keep the
+    // general kernels; the passes along the other axes switch one by one
+    // (to_fast_r2r)
+    if (axis_bc(P.d, a) == HP_PERIODIC || axis_bc(P.d, a) == HP_UNBOUNDED) continue;
     ++bounded;
     if (L[a] < 64 || L[a] > 512 || wf_r0(L[a]) <= 0) return false;
     for (int k = FAST_R2R_C; k <= FAST_R2R_SW; ++k) {
@@ -924,7 +925,9 @@ bool bounded_fast_ok(hp_plan p, const Problem& P, const int* L) {
 // Switch a general bounded pass (same descriptor) to its wavefront kernel.
 hp_status to_fast_r2r(hp_plan p, PassArgs& a) {
   if (a.fast == FAST_GRAD_PREP || a.fast == FAST_ADD) return HP_OK;
-  if (a.xf == X_DHT || (a.kind == PK_SANDWICH && a.xb == X_DHT)) return HP_OK;  // general kernels
+  // Hartley passes and the free axis's Green's-row sandwich: general kernels
+  if (a.xf == X_DHT || (a.kind == PK_SANDWICH && a.xb == X_DHT)) return HP_OK;
+  if (a.mult == M_GREEN_ROWS || a.mult == M_GREEN_ROWS_ODD || a.xf == X_PAIR_F) return HP_OK;
   const bool contig = a.kind == PK_ONEWAY && a.in_jfast && a.out_jfast;
   bool faces = false;
   for (int ax = 0; ax < 3; ++ax) faces |= a.face[ax][0] != nullptr || a.face[ax][1] != nullptr;
@@ -1856,6 +1859,7 @@ hp_status passes_unbounded_low(hp_plan p, Problem& P, bool adjoint, std::vector<
 hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
   const hp_desc& d = P.d;
   const int nd = P.nd, u = P.free_axis;
+  const size_t first_pass = out.size();
   int xf[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, L[3] = {1, 1, 1};
   double c[3] = {1, 1, 1};
   for (int a = 0; a < nd; ++a) {
@@ -2066,6 +2070,10 @@ hp_status passes_semi(hp_plan p, Problem& P, std::vector<PassRec>& out) {
       if (t.comp == comp && t.axis == u) HP_TRY(free_term(comp, t.dst, t.sign));
   }
   add_second_terms(P, es, out);
+  // the passes along Dirichlet / Neumann axes on the wavefront kernels where
+  // their lengths allow (the free axis and Hartley axes stay general)
+  if (bounded_fast_ok(p, P, L))
+    for (size_t i = first_pass; i < out.size(); ++i) HP_TRY(to_fast_r2r(p, out[i].a));
   return HP_OK;
 }
 

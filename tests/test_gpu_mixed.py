@@ -17,7 +17,10 @@ oracle, element by element.
   boundary values, prime and power-of-two lengths, the kappa = 0 row, a
   3-component field, descriptor rules;
 * GRAD, CURL and DIV of semi-unbounded plans (series along the bounded axes,
-  the odd kernel's rows along the free one), the kappa = 0 row included.
+  the odd kernel's rows along the free one), the kappa = 0 row included;
+* mixed and semi-unbounded plans at power-of-two lengths, where the passes
+  along Dirichlet / Neumann axes run the wavefront kernels beside the general
+  Hartley and free-axis passes, against the oracle and the all-general list.
 """
 import numpy as np
 import pytest
@@ -466,3 +469,45 @@ def test_mixed_periodic_axis_wavefront(bcs, gtype, kernel, inhom, diff, prec, mo
     check(got, gen, prec, "psi wavefront vs general")
     for a in range(len(dgen)):
         check(dout[a], dgen[a], prec, f"{diff} {a} wavefront vs general")
+
+
+# semi-unbounded plans with Dirichlet / Neumann axes at power-of-two transform
+# lengths: their passes run the wavefront kernels, the free axis's sandwich
+# the general ones
+SEMI_WF = [["neumann", "dirichlet", "unbounded"], ["unbounded", "dirichlet", "neumann"],
+           ["dirichlet", "unbounded", "neumann"]]
+
+
+@pytest.mark.parametrize("bcs", SEMI_WF)
+@pytest.mark.parametrize("gtype", ["regular", "staggered"])
+@pytest.mark.parametrize("kernel,inhom,diff", [("fd2", True, "none"), ("ps", False, "grad"), ("fd2", False, "curl")])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_semi_bounded_axes_wavefront(bcs, gtype, kernel, inhom, diff, prec, monkeypatch):
+    nc = [32, 64, 32]
+    ncomp = 3 if diff == "curl" else 1
+    got, dout = run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=199)
+    monkeypatch.setenv("HP_GENERIC", "1")
+    gen, dgen = run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=199)
+    check(got, gen, prec, "psi wavefront vs general")
+    for a in range(len(dgen)):
+        check(dout[a], dgen[a], prec, f"{diff} {a} wavefront vs general")
+
+
+@pytest.mark.parametrize("bcs", [["periodic", "dirichlet", "neumann"], ["neumann", "dirichlet", "unbounded"]])
+def test_wavefront_passes_beside_general_ones(bcs):
+    """At power-of-two lengths a mixed plan's Dirichlet / Neumann passes run
+    the wavefront kernels while its Hartley or free-axis passes stay general."""
+    import torch
+    from paper_2301_01145_amd import Solver, hp_pass_stats, hp_set_timing
+    nc = [32, 64, 32]
+    f, _ = mixed_input(bcs, "staggered", nc, 1, False, "f32", seed=201)
+    s = Solver(bcs, "staggered", nc, LO, HI, kernel="fd2", dtype=torch.float32)
+    s.bind(torch.as_tensor(f.astype(np.float32), device="cuda"))
+    hp_pass_stats(s.plan)
+    hp_set_timing(s.plan, 1)
+    s.run()
+    hp_set_timing(s.plan, 0)
+    names = [p[0] for p in hp_pass_stats(s.plan)]
+    s.close()
+    assert any(n.startswith("r2r_") for n in names), names
+    assert any(not n.startswith("r2r_") for n in names), names

@@ -20,8 +20,12 @@ oracle, element by element.
   the odd kernel's rows along the free one), the kappa = 0 row included;
 * mixed and semi-unbounded plans at power-of-two lengths, where the passes
   along Dirichlet / Neumann axes run the wavefront kernels beside the general
-  Hartley and free-axis passes, against the oracle and the all-general list.
+  Hartley and free-axis passes, against the oracle and the all-general list;
+* a seeded random sweep of mixed and semi-unbounded plans with derivative
+  outputs at such lengths (HP_MIXED_SWEEP_CASES cases, 40 by default).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -511,3 +515,42 @@ def test_wavefront_passes_beside_general_ones(bcs):
     s.close()
     assert any(n.startswith("r2r_") for n in names), names
     assert any(not n.startswith("r2r_") for n in names), names
+
+
+
+def _deriv_sweep_cases(count, seed):
+    """Seeded random mixed / semi-unbounded plans with derivative outputs:
+    Dirichlet / Neumann axes of 32 or 64 cells (power-of-two transform
+    lengths: their passes run the wavefront kernels), periodic and free axes of
+    any small size; every operator the plan allows."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        nd = int(rng.integers(2, 4))
+        bcs = [str(rng.choice(["periodic", "dirichlet", "neumann"])) for _ in range(nd)]
+        free = rng.random() < 0.35
+        if free:
+            bcs[int(rng.integers(0, nd))] = "unbounded"
+        if len(set(bcs)) == 1 or not any(b in ("dirichlet", "neumann") for b in bcs):
+            continue
+        gtype = str(rng.choice(["regular", "staggered"]))
+        kernel = str(rng.choice(["ps", "fd2"]))
+        prec = str(rng.choice(["f32", "f64"]))
+        ncomp = 3 if (nd == 3 and rng.random() < 0.4) else 1
+        # boundary values on scalar fields (the binding sets faces of component 0)
+        inhom = kernel == "fd2" and not free and ncomp == 1 and bool(rng.random() < 0.4)
+        if ncomp == 3:
+            choices = ["curl", "div"] + ([] if (free or inhom) else ["nabla"])
+        else:
+            choices = ["grad"] + (["curl"] if nd == 2 else []) + ([] if (free or inhom) else ["nabla"])
+        diff = str(rng.choice(choices))
+        nc = [int(rng.choice([32, 64] if nd == 2 else [32])) if b in ("dirichlet", "neumann")
+              else int(rng.integers(3, 21)) for b in bcs]
+        out.append((bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, int(rng.integers(0, 1 << 20))))
+    return out
+
+
+@pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,diff,prec,ncomp,seed",
+                         _deriv_sweep_cases(int(os.environ.get("HP_MIXED_SWEEP_CASES", "40")), seed=2302))
+def test_mixed_derivative_sweep(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed):
+    run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=seed)

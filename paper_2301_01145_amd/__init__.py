@@ -124,14 +124,19 @@ class Solver:
             self._check_tensor(t, self.in_shape, "f")
             hp_set_input(self.plan, 0, c, t.data_ptr(), 1)
         if self.inhomogeneous:
+            # {(axis, side): g} for every component, or one such dict per component
             faces = faces or {}
-            for a in range(self.nd):
-                shp = tuple(self.out_shape[b] for b in range(self.nd) if b != a)
-                for s in (0, 1):
-                    g = faces.get((a, s))
-                    if g is not None:
-                        self._check_tensor(g, shp, f"face {(a, s)}")
-                    hp_set_boundary(self.plan, 0, a, s, 0, g.data_ptr() if g is not None else None, 1)
+            per = list(faces) if isinstance(faces, (list, tuple)) else [faces] * self.ncomp
+            if len(per) != self.ncomp:
+                raise ValueError(f"faces: one dict per component ({self.ncomp}) or one for all")
+            for c in range(self.ncomp):
+                for a in range(self.nd):
+                    shp = tuple(self.out_shape[b] for b in range(self.nd) if b != a)
+                    for s in (0, 1):
+                        g = (per[c] or {}).get((a, s))
+                        if g is not None:
+                            self._check_tensor(g, shp, f"face {(a, s)} of component {c}")
+                        hp_set_boundary(self.plan, 0, a, s, c, g.data_ptr() if g is not None else None, 1)
         psi = psi if psi is not None else [self.empty_output() for _ in range(self.ncomp)]
         psi = [psi] if not isinstance(psi, (list, tuple)) else list(psi)
         for c, t in enumerate(psi):

@@ -363,7 +363,8 @@ def run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed, f=Non
     psi, der = s.solve(fin, {k: dev(v) for k, v in faces.items()} if faces else None)
     torch.cuda.synchronize()
     got = np.stack([p.double().cpu().numpy() for p in psi]) if ncomp == 3 else psi[0].double().cpu().numpy()
-    ref, rd = oracle.solve(list(bcs), gtype, nc, LO[:nd], HI[:nd], f, operator=kernel, diff=diff, faces=faces)
+    ref, rd = oracle.solve(list(bcs), gtype, nc, LO[:nd], HI[:nd], f, operator=kernel, diff=diff,
+                           faces=([faces] * 3 if (faces and ncomp == 3) else faces))
     check(got, ref, prec, "psi")
     assert len(der) == len(rd)
     dout = [d.double().cpu().numpy() for d in der]
@@ -537,8 +538,7 @@ def _deriv_sweep_cases(count, seed):
         kernel = str(rng.choice(["ps", "fd2"]))
         prec = str(rng.choice(["f32", "f64"]))
         ncomp = 3 if (nd == 3 and rng.random() < 0.4) else 1
-        # boundary values on scalar fields (the binding sets faces of component 0)
-        inhom = kernel == "fd2" and not free and ncomp == 1 and bool(rng.random() < 0.4)
+        inhom = kernel == "fd2" and not free and bool(rng.random() < 0.4)
         if ncomp == 3:
             choices = ["curl", "div"] + ([] if (free or inhom) else ["nabla"])
         else:
@@ -554,3 +554,44 @@ def _deriv_sweep_cases(count, seed):
                          _deriv_sweep_cases(int(os.environ.get("HP_MIXED_SWEEP_CASES", "40")), seed=2302))
 def test_mixed_derivative_sweep(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed):
     run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=seed)
+
+
+
+@pytest.mark.parametrize("bcs", [["dirichlet", "dirichlet", "dirichlet"], ["periodic", "dirichlet", "neumann"],
+                                 ["neumann", "neumann", "dirichlet"]])
+@pytest.mark.parametrize("gtype", ["regular", "staggered"])
+@pytest.mark.parametrize("diff", ["none", "curl", "div"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_vector_boundary_values(bcs, gtype, diff, prec):
+    """A 3-component field with boundary values: the same face arrays bound for
+    every component (FD2; psi, and CURL / DIV by differences)."""
+    run_deriv_case(bcs, gtype, [12, 10, 9], "fd2", True, diff, prec, 3, seed=211)
+
+
+def test_vector_boundary_values_per_component():
+    """One face dict per component: each component solved with its own values,
+    equal to three scalar solves."""
+    import torch
+    from paper_2301_01145_amd import Solver
+    bcs, nc = ["dirichlet", "neumann", "periodic"], [12, 10, 9]
+    fs, fcs = [], []
+    for c in range(3):
+        f, faces = mixed_input(bcs, "staggered", nc, 1, True, "f64", seed=221 + c)
+        fs.append(f)
+        fcs.append(faces)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    s = Solver(bcs, "staggered", nc, LO, HI, kernel="fd2", dtype=torch.float64, ncomp=3, inhomogeneous=True)
+    psi, _ = s.solve([dev(f) for f in fs], [{k: dev(v) for k, v in fc.items()} for fc in fcs])
+    torch.cuda.synchronize()
+    got = [p.double().cpu().numpy() for p in psi]
+    s.close()
+    for c in range(3):
+        ref, _, _ = gpu_mixed(bcs, "staggered", nc, fs[c], "fd2", "f64", 1, fcs[c])
+        check(got[c], ref, "f64", f"component {c}")
+    with pytest.raises(ValueError):
+        s2 = Solver(bcs, "staggered", nc, LO, HI, kernel="fd2", dtype=torch.float64, ncomp=3,
+                    inhomogeneous=True)
+        try:
+            s2.bind([dev(f) for f in fs], [{k: dev(v) for k, v in fcs[0].items()}] * 2)
+        finally:
+            s2.close()

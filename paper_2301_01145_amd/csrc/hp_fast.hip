@@ -683,8 +683,9 @@ int fast_tile(int fast, int L, int prec) {
     const int v = std::atoi(t);
     if (v == 8 || v == 16) return v;
   }
-  // measured on MI355X at 256^3 (doubled 512^3): narrower tiles (more
-  // workgroups per CU) win except in the backward y pass
+  // measured on MI355X at 256^3 (doubled 512^3): 8-pencil tiles in the x
+  // pass (two workgroups per CU within its register budget), 16 elsewhere
+  // (8 there cost 1 % of the solve in R2C and in the forward y pass)
   return fast == FAST_SANDWICH ? 8 : 16;
 }
 

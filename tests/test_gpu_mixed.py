@@ -22,7 +22,8 @@ oracle, element by element.
   along Dirichlet / Neumann axes run the wavefront kernels beside the general
   Hartley and free-axis passes, against the oracle and the all-general list;
 * a seeded random sweep of mixed and semi-unbounded plans with derivative
-  outputs at such lengths (HP_MIXED_SWEEP_CASES cases, 40 by default).
+  outputs at such lengths (HP_MIXED_SWEEP_CASES cases, 40 by default;
+  HP_MIXED_SWEEP_SEED).
 """
 import os
 
@@ -551,7 +552,8 @@ def _deriv_sweep_cases(count, seed):
 
 
 @pytest.mark.parametrize("bcs,gtype,nc,kernel,inhom,diff,prec,ncomp,seed",
-                         _deriv_sweep_cases(int(os.environ.get("HP_MIXED_SWEEP_CASES", "40")), seed=2302))
+                         _deriv_sweep_cases(int(os.environ.get("HP_MIXED_SWEEP_CASES", "40")),
+                                            seed=int(os.environ.get("HP_MIXED_SWEEP_SEED", "2302"))))
 def test_mixed_derivative_sweep(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed):
     run_deriv_case(bcs, gtype, nc, kernel, inhom, diff, prec, ncomp, seed=seed)
 
